@@ -1,0 +1,189 @@
+"""FP64 oracle of the meta-estimator and the optimisers (numpy).
+
+TEST INFRASTRUCTURE ONLY (see oracle/__init__.py).
+
+Follows the paper's Sections 4 (variance estimation) and 5 (optimisation)
+and the supplement's pseudocode, in the paper's order and notation:
+
+  Var[F_i]      zero-centred second moment of <F_i>, bias-corrected EMA with
+                coefficient beta_F                                  (Eq. 9)
+  Var[dF_i]_D   same EMA (beta_D) of <dF_i> / ||dpi_i||_2           (Eq. 13)
+  Var[dF_i]     = Var[dF_i]_D * ||dpi_i||_2^2                       (Eq. 14)
+  alpha_i       = Var[F_i] / (Var[F_i] + Var[F_{i-1}]_M + Var[dF_i])  (Eq. 8)
+                clipped by 1 / (2 - alpha_{i-1})                    (Eq. 17)
+  <F_i>_M       = alpha_i (<F_{i-1}>_M + <dF_i>) + (1 - alpha_i) <F_i>  (Eq. 7)
+  Var[F_i]_M    = alpha_i^2 (Var[F_{i-1}]_M + Var[dF_i])
+                  + (1 - alpha_i)^2 Var[F_i]                        (Eq. 15)
+  dpi_{i+1}     = -eta <F_i>_M / (sqrt(Var[F_i]_M) + eps)          (Eq. 21)
+
+Readings where the paper is silent or ambiguous:
+  * ||dpi_i||_2 is the Euclidean norm over all parameters of one problem of
+    the step actually applied (after projection), pi_i - pi_{i-1}.
+  * At i = 0, and whenever ||dpi_i|| = 0, there is no finite-difference
+    sample: <dF_i> = 0, the Var_D EMA does not step, Var[dF_i] = 0.
+  * The EMAs are the bias-corrected form of the supplement's Moment2
+    (after its first step the moment equals x^2 exactly).
+  * alpha_{-1} = -inf, so alpha_0 = 0 and <F_0>_M = <F_0> (matches Eq. 7's
+    initialisation).
+  * Parameters are stored as float32; pi_{i+1} = clip(f32(pi_i + dpi), lo, hi).
+"""
+from __future__ import annotations
+
+import math
+from typing import Optional
+
+import numpy as np
+
+ALPHA_EPS = 1e-30   # guards the inverse-variance ratio
+STEP_EPS = 1e-8     # epsilon of the stabilised step
+
+
+class Moment2:
+    """Zero-centred second moment, exponential moving average with start-up
+    bias correction: after `count` steps the weights of the samples sum to 1."""
+
+    def __init__(self, shape, decay: float):
+        self.decay = float(decay)
+        self.count = 0
+        self.m2 = np.zeros(shape, np.float64)
+
+    def step(self, x: np.ndarray) -> None:
+        self.count += 1
+        w = 1.0 - self.decay
+        w_sum = 1.0 - self.decay ** self.count
+        self.m2 = self.m2 + (w / w_sum) * (np.asarray(x, np.float64) ** 2 - self.m2)
+
+
+class Meta:
+    """Recurrent meta-estimator <F_i>_M with its variance, and the step of Eq. 21."""
+
+    def __init__(self, shape, eta: float):
+        self.eta = float(eta)
+        self.mean = np.zeros(shape, np.float64)
+        self.var = np.zeros(shape, np.float64)
+        self.alpha_prev = np.full(shape, -np.inf)
+        self.alpha = np.zeros(shape, np.float64)
+
+    def step(self, F, dF, var_F, var_dF) -> np.ndarray:
+        # carry the previous meta-estimate to this iteration (Eq. 6 update)
+        self.mean = self.mean + dF
+        self.var = self.var + var_dF
+        # inverse-variance weight (Eq. 8), clipped (Eq. 17)
+        alpha = var_F / (var_F + self.var + ALPHA_EPS)
+        alpha = np.minimum(alpha, 1.0 / (2.0 - self.alpha_prev))
+        self.alpha_prev = alpha
+        self.alpha = alpha
+        # combine (Eq. 7) and propagate the variance (Eq. 15)
+        self.mean = alpha * self.mean + (1.0 - alpha) * F
+        self.var = alpha ** 2 * self.var + (1.0 - alpha) ** 2 * var_F
+        # stabilised step (Eq. 21)
+        return -self.eta * self.mean / (np.sqrt(self.var) + STEP_EPS)
+
+
+class MetaOptimizer:
+    """One problem's optimisation loop state (supplement: optimisation loop)."""
+
+    def __init__(self, params, lo, hi, eta: float = 1e-3, beta_F: float = 0.99,
+                 beta_D: float = 0.9):
+        self.params = np.asarray(params, np.float32).copy()
+        self.params_prev = self.params.copy()
+        self.lo = np.asarray(lo, np.float32)
+        self.hi = np.asarray(hi, np.float32)
+        n = self.params.shape
+        self.var_F = Moment2(n, beta_F)
+        self.var_D = Moment2(n, beta_D)
+        self.meta = Meta(n, eta)
+        self.iteration = 0
+        self.step_norm2 = 0.0   # ||pi_i - pi_{i-1}||^2 of the step that produced pi_i
+
+    def step(self, F, dF) -> np.ndarray:
+        F = np.asarray(F, np.float64)
+        n2 = self.step_norm2
+        self.var_F.step(F)
+        if self.iteration >= 1 and n2 > 0.0:
+            dF = np.asarray(dF, np.float64)
+            self.var_D.step(dF / math.sqrt(n2))
+            var_dF = self.var_D.m2 * n2
+        else:
+            dF = np.zeros_like(F)
+            var_dF = np.zeros_like(F)
+        d = self.meta.step(F, dF, self.var_F.m2, var_dF)
+        new = np.clip((self.params.astype(np.float64) + d).astype(np.float32), self.lo, self.hi)
+        diff = new.astype(np.float64) - self.params.astype(np.float64)
+        self.step_norm2 = float(np.sum(diff * diff))
+        self.params_prev = self.params
+        self.params = new
+        self.iteration += 1
+        return new
+
+
+class Adam:
+    """Adam (Kingma & Ba) with bias-corrected first and second moments (Eq. 18-20)."""
+
+    def __init__(self, params, lo, hi, eta: float, beta1: float = 0.9, beta2: float = 0.999,
+                 eps: float = 1e-8):
+        self.params = np.asarray(params, np.float32).copy()
+        self.lo = np.asarray(lo, np.float32)
+        self.hi = np.asarray(hi, np.float32)
+        self.eta, self.b1, self.b2, self.eps = float(eta), float(beta1), float(beta2), float(eps)
+        self.m = np.zeros(self.params.shape)
+        self.v = np.zeros(self.params.shape)
+        self.t = 0
+
+    def step(self, g) -> np.ndarray:
+        g = np.asarray(g, np.float64)
+        self.t += 1
+        self.m = self.b1 * self.m + (1 - self.b1) * g
+        self.v = self.b2 * self.v + (1 - self.b2) * g * g
+        mh = self.m / (1 - self.b1 ** self.t)
+        vh = self.v / (1 - self.b2 ** self.t)
+        d = -self.eta * mh / (np.sqrt(vh) + self.eps)
+        self.params = np.clip((self.params.astype(np.float64) + d).astype(np.float32),
+                              self.lo, self.hi)
+        return self.params
+
+
+# ----------------------------------------------------------------------------
+# Figure 2 toy: fit the rate of an exponential distribution so that its mean
+# is 2.0 (ground-truth rate 0.5), 32 samples per iteration.
+# ----------------------------------------------------------------------------
+def toy_samples(lam: float, u: np.ndarray) -> np.ndarray:
+    """Inverse-CDF samples of Exp(lam): x = -ln(1 - u) / lam (dx/dlam = -x/lam)."""
+    return -np.log1p(-u) / lam
+
+
+def toy_grad(lam: float, u: np.ndarray, target: float = 2.0) -> float:
+    """Gradient of the decorrelated L2 loss (xbar_A - t)(xbar_B - t) w.r.t. lam,
+    the 32 samples split in two halves A, B so the product is an unbiased
+    estimate of (E[x] - t)^2."""
+    half = len(u) // 2
+    xa, xb = toy_samples(lam, u[:half]), toy_samples(lam, u[half:])
+    ma, mb = xa.mean(), xb.mean()
+    dma, dmb = -ma / lam, -mb / lam
+    return dma * (mb - target) + (ma - target) * dmb
+
+
+def toy_run(method: str, iters: int, seed: int, lam0: float = 1.0, eta: float = 0.02,
+            beta_F: float = 0.99, beta_D: float = 0.9, n: int = 32):
+    """Optimise the toy with 'meta' (one proportional + one finite-difference
+    sample per iteration, same sample count n each) or 'adam'.  Returns the
+    rate trajectory."""
+    g = np.random.Generator(np.random.PCG64(seed))
+    lo, hi = np.array([1e-2], np.float32), np.array([10.0], np.float32)
+    traj = []
+    if method == "adam":
+        opt = Adam(np.array([lam0], np.float32), lo, hi, eta)
+        for _ in range(iters):
+            gr = toy_grad(float(opt.params[0]), g.random(n))
+            opt.step(np.array([gr]))
+            traj.append(float(opt.params[0]))
+        return np.array(traj)
+    opt = MetaOptimizer(np.array([lam0], np.float32), lo, hi, eta, beta_F, beta_D)
+    for i in range(iters):
+        lam = float(opt.params[0])
+        F = toy_grad(lam, g.random(n))
+        u = g.random(n)  # one set of random numbers used at both rates
+        dF = toy_grad(lam, u) - toy_grad(float(opt.params_prev[0]), u) if i >= 1 else 0.0
+        opt.step(np.array([F]), np.array([dF]))
+        traj.append(float(opt.params[0]))
+    return np.array(traj)

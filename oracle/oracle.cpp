@@ -1,0 +1,775 @@
+// FP64 CPU oracle -- test infrastructure only (see oracle.h).
+//
+// Plain C++17.  Every quantity is double precision.  Intersections are brute
+// force over all primitives, and the derivative of each path is taken from an
+// explicit tape swept backward; the GPU library does neither of these, so the
+// two implementations share no algorithm beyond the estimator they both define.
+#include "oracle.h"
+
+#include <algorithm>
+#include <cmath>
+#include <cstring>
+#include <limits>
+#include <thread>
+#include <vector>
+
+namespace {
+
+constexpr double PI = 3.14159265358979323846;
+constexpr double INF = std::numeric_limits<double>::infinity();
+constexpr double RAY_EPS = 1e-4;      // origin offset along the normal
+constexpr double SHADOW_EPS = 1e-4;   // shadow rays stop this short of the light
+constexpr double ROUGH_MIN = 0.05;    // roughness floor of the material model
+constexpr double P_SPEC = 0.5;        // probability of sampling the specular lobe
+
+enum { T_PRIMAL = 0 };
+
+// --------------------------------------------------------------------------
+// vectors
+// --------------------------------------------------------------------------
+struct V3 {
+  double x, y, z;
+};
+inline V3 operator+(V3 a, V3 b) { return {a.x + b.x, a.y + b.y, a.z + b.z}; }
+inline V3 operator-(V3 a, V3 b) { return {a.x - b.x, a.y - b.y, a.z - b.z}; }
+inline V3 operator*(V3 a, double s) { return {a.x * s, a.y * s, a.z * s}; }
+inline V3 operator*(double s, V3 a) { return {a.x * s, a.y * s, a.z * s}; }
+inline double dot(V3 a, V3 b) { return a.x * b.x + a.y * b.y + a.z * b.z; }
+inline V3 cross(V3 a, V3 b) {
+  return {a.y * b.z - a.z * b.y, a.z * b.x - a.x * b.z, a.x * b.y - a.y * b.x};
+}
+inline double length(V3 a) { return std::sqrt(dot(a, a)); }
+inline V3 normalize(V3 a) { return a * (1.0 / length(a)); }
+inline V3 from(const double* p) { return {p[0], p[1], p[2]}; }
+
+// --------------------------------------------------------------------------
+// random numbers
+// --------------------------------------------------------------------------
+// SplitMix64 (Steele, Lea, Flood 2014): one step of the generator started at x.
+uint64_t splitmix64(uint64_t x) {
+  uint64_t z = x + 0x9E3779B97F4A7C15ull;
+  z = (z ^ (z >> 30)) * 0xBF58476D1CE4E5B9ull;
+  z = (z ^ (z >> 27)) * 0x94D049BB133111EBull;
+  return z ^ (z >> 31);
+}
+
+// Philox4x32 with 10 rounds (Salmon, Moraes, Dror, Shaw, "Parallel random
+// numbers: as easy as 1, 2, 3", SC'11).  Each round multiplies counter words 0
+// and 2 by the two round multipliers (64-bit products), and the new counter is
+// (hi(c2*M1) ^ c1 ^ k0, lo(c2*M1), hi(c0*M0) ^ c3 ^ k1, lo(c0*M0)); the key is
+// advanced by the two Weyl increments before every round after the first.
+void philox(const uint32_t ctr[4], const uint32_t key[2], uint32_t out[4]) {
+  const uint32_t M0 = 0xD2511F53u, M1 = 0xCD9E8D57u;
+  const uint32_t W0 = 0x9E3779B9u, W1 = 0xBB67AE85u;
+  uint32_t c0 = ctr[0], c1 = ctr[1], c2 = ctr[2], c3 = ctr[3];
+  uint32_t k0 = key[0], k1 = key[1];
+  for (int round = 0; round < 10; ++round) {
+    if (round > 0) {
+      k0 += W0;
+      k1 += W1;
+    }
+    uint64_t p0 = (uint64_t)M0 * (uint64_t)c0;
+    uint64_t p1 = (uint64_t)M1 * (uint64_t)c2;
+    uint32_t n0 = (uint32_t)(p1 >> 32) ^ c1 ^ k0;
+    uint32_t n1 = (uint32_t)p1;
+    uint32_t n2 = (uint32_t)(p0 >> 32) ^ c3 ^ k1;
+    uint32_t n3 = (uint32_t)p0;
+    c0 = n0; c1 = n1; c2 = n2; c3 = n3;
+  }
+  out[0] = c0; out[1] = c1; out[2] = c2; out[3] = c3;
+}
+
+uint64_t stream_key(uint64_t seed, uint32_t iteration, uint32_t tag) {
+  return splitmix64(seed ^ splitmix64(((uint64_t)iteration << 8) | (uint64_t)tag));
+}
+
+// The random numbers of one path: counter = (pixel, sample, bounce, block).
+struct PathRng {
+  uint32_t key[2];
+  uint32_t pixel, sample;
+  void draw(uint32_t bounce, uint32_t block, double u[4]) const {
+    uint32_t ctr[4] = {pixel, sample, bounce, block}, r[4];
+    philox(ctr, key, r);
+    for (int i = 0; i < 4; ++i) u[i] = (double)(r[i] >> 8) * (1.0 / 16777216.0);
+  }
+};
+
+// --------------------------------------------------------------------------
+// scene
+// --------------------------------------------------------------------------
+struct Ray {
+  V3 o, d;
+};
+
+enum Kind { K_NONE = 0, K_PLANE, K_SPHERE, K_LIGHT };
+
+struct Hit {
+  Kind kind = K_NONE;
+  int obj = -1;
+  double t = INF;
+  V3 p{0, 0, 0}, n{0, 0, 0};
+};
+
+struct Margin {
+  double m = INF;
+  void add(double v) { m = std::min(m, std::fabs(v)); }
+};
+
+struct Scene {
+  const orc_scene* s;
+  V3 eye, cw, cu, cv;
+  double tan_half, aspect;
+  int n_ch;
+  int ch_slot[5];  // slot of channel bit b in a texel, -1 if not a parameter
+
+  explicit Scene(const orc_scene* sc) : s(sc) {
+    eye = from(sc->cam_eye);
+    cw = normalize(from(sc->cam_target) - eye);
+    cu = normalize(cross(cw, from(sc->cam_up)));
+    cv = cross(cu, cw);
+    tan_half = std::tan(sc->vfov_deg * PI / 360.0);
+    aspect = (double)sc->width / (double)sc->height;
+    n_ch = 0;
+    for (int b = 0; b < 5; ++b) ch_slot[b] = (sc->ch_mask >> b & 1) ? n_ch++ : -1;
+  }
+
+  Ray camera_ray(int x, int y, double jx, double jy) const {
+    double sx = (2.0 * (x + jx) / s->width - 1.0) * tan_half * aspect;
+    double sy = (1.0 - 2.0 * (y + jy) / s->height) * tan_half;
+    return {eye, normalize(cw + cu * sx + cv * sy)};
+  }
+
+  // sphere k against ray; returns t or INF (t must exceed 0)
+  double hit_sphere(int k, const Ray& r, Margin& mg) const {
+    const double* sp = s->spheres + 4 * k;
+    V3 c{sp[0], sp[1], sp[2]};
+    double rad = sp[3];
+    V3 oc = r.o - c;
+    double b = dot(oc, r.d);
+    double cc = dot(oc, oc) - rad * rad;
+    double disc = b * b - cc;
+    mg.add(disc / (rad * rad));
+    if (disc < 0) return INF;
+    double sq = std::sqrt(disc);
+    double t0 = -b - sq, t1 = -b + sq;
+    if (t0 > 0) return t0;
+    if (t1 > 0) return t1;
+    return INF;
+  }
+
+  double hit_plane(const Ray& r, Margin& mg) const {
+    if (!s->plane_enabled) return INF;
+    mg.add(r.d.y);
+    if (!(r.d.y < 0) || !(r.o.y > 0)) return INF;
+    return -r.o.y / r.d.y;
+  }
+
+  double hit_light(const Ray& r, Margin& mg) const {
+    if (!s->light_enabled) return INF;
+    double ly = s->light_center[1];
+    mg.add(r.d.y);
+    if (!(r.d.y > 0) || !(r.o.y < ly)) return INF;
+    double t = (ly - r.o.y) / r.d.y;
+    double h = 0.5 * s->light_side;
+    double dx = r.o.x + t * r.d.x - s->light_center[0];
+    double dz = r.o.z + t * r.d.z - s->light_center[2];
+    mg.add((h - std::fabs(dx)) / s->light_side);
+    mg.add((h - std::fabs(dz)) / s->light_side);
+    if (std::fabs(dx) > h || std::fabs(dz) > h) return INF;
+    return t;
+  }
+
+  // Closest hit; primitive order plane < spheres < light, and a strictly
+  // smaller t is needed to replace the current best (equal t: lower id wins).
+  Hit intersect(const Ray& r, Margin& mg) const {
+    Hit h;
+    double second = INF;
+    auto consider = [&](double t, Kind kind, int obj) {
+      if (t < h.t) {
+        second = h.t;
+        h.t = t;
+        h.kind = kind;
+        h.obj = obj;
+      } else if (t < second) {
+        second = t;
+      }
+    };
+    consider(hit_plane(r, mg), K_PLANE, 0);
+    for (int k = 0; k < s->n_spheres; ++k) consider(hit_sphere(k, r, mg), K_SPHERE, k);
+    consider(hit_light(r, mg), K_LIGHT, 0);
+    if (h.kind == K_NONE) return h;
+    if (second < INF) mg.add((second - h.t) / h.t);
+    h.p = r.o + r.d * h.t;
+    if (h.kind == K_PLANE) {
+      h.n = {0, 1, 0};
+      h.p.y = 0.0;
+    } else if (h.kind == K_SPHERE) {
+      const double* sp = s->spheres + 4 * h.obj;
+      h.n = (h.p - V3{sp[0], sp[1], sp[2]}) * (1.0 / sp[3]);
+    } else {
+      h.n = {0, -1, 0};
+    }
+    return h;
+  }
+
+  // any occluder (plane, spheres) with 0 < t < tmax
+  bool occluded(const Ray& r, double tmax, Margin& mg) const {
+    Margin local;
+    bool occ = false;
+    double tp = hit_plane(r, local);
+    if (tp < INF) {
+      mg.add((tmax - tp) / tmax);
+      if (tp < tmax) occ = true;
+    }
+    for (int k = 0; k < s->n_spheres; ++k) {
+      double t = hit_sphere(k, r, local);
+      if (t < INF) {
+        mg.add((tmax - t) / tmax);
+        if (t < tmax) occ = true;
+      }
+    }
+    mg.add(local.m);
+    return occ;
+  }
+};
+
+// --------------------------------------------------------------------------
+// material and footprint
+// --------------------------------------------------------------------------
+struct Footprint {
+  int n = 0;
+  int texel[4];
+  double w[4];
+};
+
+struct Material {
+  double c[3], metal, rough;
+  bool param = false;
+  Footprint fp;
+};
+
+// Bilinear texture footprint, clamp-to-edge, texel centres at (i + 0.5) / size.
+Footprint bilinear(const orc_scene* s, double u, double v) {
+  Footprint fp;
+  if (s->tex_w == 1 && s->tex_h == 1) {
+    fp.n = 1;
+    fp.texel[0] = 0;
+    fp.w[0] = 1.0;
+    return fp;
+  }
+  double x = u * s->tex_w - 0.5, y = v * s->tex_h - 0.5;
+  double x0 = std::floor(x), y0 = std::floor(y);
+  double fx = x - x0, fy = y - y0;
+  auto cl = [](double a, int n) { return (int)std::min(std::max(a, 0.0), (double)(n - 1)); };
+  int xi0 = cl(x0, s->tex_w), xi1 = cl(x0 + 1, s->tex_w);
+  int yi0 = cl(y0, s->tex_h), yi1 = cl(y0 + 1, s->tex_h);
+  fp.n = 4;
+  fp.texel[0] = yi0 * s->tex_w + xi0; fp.w[0] = (1 - fx) * (1 - fy);
+  fp.texel[1] = yi0 * s->tex_w + xi1; fp.w[1] = fx * (1 - fy);
+  fp.texel[2] = yi1 * s->tex_w + xi0; fp.w[2] = (1 - fx) * fy;
+  fp.texel[3] = yi1 * s->tex_w + xi1; fp.w[3] = fx * fy;
+  return fp;
+}
+
+Material material_at(const Scene& sc, const Hit& h, const double* params, Margin& mg) {
+  const orc_scene* s = sc.s;
+  int mat = h.kind == K_PLANE ? s->plane_mat : s->sphere_mat[h.obj];
+  Material m;
+  if (mat >= 0) {
+    const double* f = s->fixed_mats + 5 * mat;
+    m.c[0] = f[0]; m.c[1] = f[1]; m.c[2] = f[2];
+    m.metal = f[3];
+    m.rough = f[4];
+    return m;
+  }
+  double u, v;
+  if (h.kind == K_PLANE) {
+    u = (h.p.x - s->plane_extent[0]) / (s->plane_extent[1] - s->plane_extent[0]);
+    v = (h.p.z - s->plane_extent[2]) / (s->plane_extent[3] - s->plane_extent[2]);
+  } else {
+    // latitude-longitude map; the seam sits at atan2 = +-pi (n.x < 0, n.z = 0)
+    V3 n = h.n;
+    if (n.x < 0 && s->tex_w > 1) mg.add(n.z);
+    u = 0.5 + std::atan2(n.z, n.x) / (2 * PI);
+    v = std::acos(std::min(1.0, std::max(-1.0, n.y))) / PI;
+  }
+  m.param = true;
+  m.fp = bilinear(s, u, v);
+  double val[5];
+  for (int b = 0; b < 5; ++b) {
+    if (sc.ch_slot[b] < 0) {
+      val[b] = s->fixed_default[b];
+      continue;
+    }
+    double acc = 0;
+    for (int k = 0; k < m.fp.n; ++k) acc += m.fp.w[k] * params[m.fp.texel[k] * sc.n_ch + sc.ch_slot[b]];
+    val[b] = acc;
+  }
+  m.c[0] = val[0]; m.c[1] = val[1]; m.c[2] = val[2];
+  m.metal = val[3];
+  m.rough = val[4];
+  return m;
+}
+
+// --------------------------------------------------------------------------
+// BSDF: metallic-roughness.  f = (1-m) c / pi + D G F / (4 cos_o cos_i) with
+// GGX D (alpha = rough^2), separable Smith G1, Schlick F with
+// F0 = 0.04 (1-m) + m c.  Partials w.r.t. c (per channel), m and rough.
+// --------------------------------------------------------------------------
+struct Bsdf {
+  double f[3] = {0, 0, 0};
+  double dc[3] = {0, 0, 0};  // df^k / dc^k
+  double dm[3] = {0, 0, 0};  // df^k / dm
+  double dr[3] = {0, 0, 0};  // df^k / drough
+  double pdf = 0;            // solid-angle density of the sampler for wi
+};
+
+double sin2(V3 n, V3 v) {
+  V3 c = cross(n, v);
+  return dot(c, c);
+}
+
+Bsdf eval_bsdf(const Material& m, V3 n, V3 wo, V3 wi, int flags) {
+  Bsdf b;
+  double co = dot(n, wo), ci = dot(n, wi);
+  if (!(co > 0) || !(ci > 0)) return b;
+  if (flags & ORC_LAMBERT_ONLY) {
+    for (int k = 0; k < 3; ++k) {
+      b.f[k] = m.c[k] / PI;
+      b.dc[k] = 1.0 / PI;
+    }
+    b.pdf = ci / PI;
+    return b;
+  }
+  double r = std::max(m.rough, ROUGH_MIN);
+  double drough = m.rough >= ROUGH_MIN ? 1.0 : 0.0;
+  double a = r * r;
+  double a2 = a * a;
+  V3 h = normalize(wo + wi);
+  double ch = dot(n, h), sh2 = sin2(n, h);
+  double Q = ch * ch * a2 + sh2;
+  double D = a2 / (PI * Q * Q);
+  auto g1 = [&](double c, double s2, double& dlog) {
+    double q = std::sqrt(a2 * s2 + c * c);
+    dlog = -(a * s2 / q) / (c + q);
+    return 2 * c / (c + q);
+  };
+  double dlgo, dlgi;
+  double Go = g1(co, sin2(n, wo), dlgo);
+  double Gi = g1(ci, sin2(n, wi), dlgi);
+  double S = D * Go * Gi / (4 * co * ci);
+  double dlogS_da = 2.0 / a - 4.0 * ch * ch * a / Q + dlgo + dlgi;
+  double dS_dr = S * dlogS_da * 2.0 * r * drough;
+  double dh = std::min(1.0, dot(wi, h));
+  double w5 = std::pow(1.0 - dh, 5);
+  for (int k = 0; k < 3; ++k) {
+    double F0 = 0.04 * (1 - m.metal) + m.metal * m.c[k];
+    double F = F0 + (1 - F0) * w5;
+    b.f[k] = (1 - m.metal) * m.c[k] / PI + S * F;
+    b.dc[k] = (1 - m.metal) / PI + S * (1 - w5) * m.metal;
+    b.dm[k] = -m.c[k] / PI + S * (1 - w5) * (m.c[k] - 0.04);
+    b.dr[k] = dS_dr * F;
+  }
+  if (flags & ORC_PARAM_INDEP) {
+    b.pdf = ci / PI;
+  } else {
+    double pdf_s = D * ch / (4 * dh);
+    b.pdf = P_SPEC * pdf_s + (1 - P_SPEC) * ci / PI;
+  }
+  return b;
+}
+
+// Orthonormal basis around n (Duff et al., "Building an Orthonormal Basis,
+// Revisited", JCGT 2017).
+void basis(V3 n, V3& b1, V3& b2) {
+  double sign = std::copysign(1.0, n.z);
+  double a = -1.0 / (sign + n.z);
+  double b = n.x * n.y * a;
+  b1 = {1.0 + sign * n.x * n.x * a, sign * b, -sign * n.x};
+  b2 = {b, sign + n.y * n.y * a, -n.y};
+}
+
+// Direction sampling: u[0] picks the lobe (specular if u[0] < P_SPEC), u[1],
+// u[2] place the direction.  GGX half-vectors follow Walter et al. 2007.
+V3 sample_dir(const Material& m, V3 n, V3 wo, const double u[4], int flags, Margin& mg) {
+  V3 b1, b2;
+  if (n.z != 0.0) mg.add(n.z);
+  basis(n, b1, b2);
+  double phi = 2 * PI * u[2];
+  bool spec = !(flags & (ORC_LAMBERT_ONLY | ORC_PARAM_INDEP)) && u[0] < P_SPEC;
+  if (!spec) {
+    double rr = std::sqrt(u[1]);
+    double z = std::sqrt(std::max(0.0, 1.0 - u[1]));
+    return b1 * (rr * std::cos(phi)) + b2 * (rr * std::sin(phi)) + n * z;
+  }
+  double r = std::max(m.rough, ROUGH_MIN);
+  double a = r * r;
+  double t2 = a * a * u[1] / (1.0 - u[1]);
+  double ct = 1.0 / std::sqrt(1.0 + t2);
+  double st = std::sqrt(t2) * ct;
+  V3 h = b1 * (st * std::cos(phi)) + b2 * (st * std::sin(phi)) + n * ct;
+  return h * (2 * dot(wo, h)) - wo;
+}
+
+// --------------------------------------------------------------------------
+// path tracing with an optional tape
+// --------------------------------------------------------------------------
+struct TapeVertex {
+  double beta[3];           // throughput arriving at the vertex (beta_{j-1})
+  bool param;
+  Footprint fp;
+  bool nee = false;
+  double K[3];              // NEE factor: cos Le w_mis / p_light (per unit f)
+  Bsdf nb;                  // BSDF (and partials) towards the light sample
+  bool cont = false;
+  double cw;                // cos_i / (pdf q)
+  Bsdf cb;                  // BSDF (and partials) along the continuation
+  double E[3] = {0, 0, 0};  // emission picked up by the continuation, per unit beta_j
+};
+
+struct PathResult {
+  double L[3] = {0, 0, 0};
+  double margin = INF;
+  std::vector<TapeVertex> tape;
+};
+
+void trace(const Scene& sc, const double* params, const PathRng& rng, int px, int py, int flags,
+           bool record, PathResult& out) {
+  const orc_scene* s = sc.s;
+  Margin mg;
+  double u[4];
+  double jx = 0.5, jy = 0.5;
+  if (!(flags & ORC_PIXEL_CENTER)) {
+    rng.draw(0, 0, u);
+    jx = u[0];
+    jy = u[1];
+  }
+  Ray ray = sc.camera_ray(px, py, jx, jy);
+  Hit hit = sc.intersect(ray, mg);
+  double* L = out.L;
+  if (hit.kind == K_NONE) {
+    for (int k = 0; k < 3; ++k) L[k] += s->env[k];
+    out.margin = mg.m;
+    return;
+  }
+  if (hit.kind == K_LIGHT) {
+    for (int k = 0; k < 3; ++k) L[k] += s->light_Le[k];
+    out.margin = mg.m;
+    return;
+  }
+  double beta[3] = {1, 1, 1};
+  const double area = s->light_side * s->light_side;
+  for (int j = 1; j <= s->depth; ++j) {
+    V3 p = hit.p, n = hit.n, wo = ray.d * -1.0;
+    Material mat = material_at(sc, hit, params, mg);
+    TapeVertex tv;
+    for (int k = 0; k < 3; ++k) tv.beta[k] = beta[k];
+    tv.param = mat.param;
+    tv.fp = mat.fp;
+    V3 p_off = p + n * RAY_EPS;
+
+    // next-event estimation towards the square light
+    if (s->light_enabled && !(flags & ORC_NO_NEE)) {
+      rng.draw(j, 1, u);
+      double h = 0.5 * s->light_side;
+      V3 lp{s->light_center[0] + (2 * u[0] - 1) * h, s->light_center[1],
+            s->light_center[2] + (2 * u[1] - 1) * h};
+      V3 dl = lp - p;
+      double dist2 = dot(dl, dl), dist = std::sqrt(dist2);
+      V3 wl = dl * (1.0 / dist);
+      double cos_l = wl.y, cos_s = dot(n, wl);
+      mg.add(cos_l);
+      mg.add(cos_s);
+      if (cos_l > 0 && cos_s > 0 && !sc.occluded({p_off, wl}, dist - SHADOW_EPS, mg)) {
+        Bsdf nb = eval_bsdf(mat, n, wo, wl, flags);
+        double pl = dist2 / (cos_l * area);
+        double wmis = pl / (pl + nb.pdf);
+        tv.nee = true;
+        tv.nb = nb;
+        for (int k = 0; k < 3; ++k) {
+          tv.K[k] = cos_s * s->light_Le[k] * wmis / pl;
+          L[k] += beta[k] * nb.f[k] * tv.K[k];
+        }
+      }
+    }
+
+    // continuation
+    rng.draw(j, 0, u);
+    V3 wi = sample_dir(mat, n, wo, u, flags, mg);
+    double ci = dot(n, wi);
+    mg.add(ci);
+    bool go = ci > 0;
+    Bsdf cb;
+    double q = 1.0;
+    if (go) {
+      cb = eval_bsdf(mat, n, wo, wi, flags);
+      go = cb.pdf > 0;
+    }
+    if (go && s->rr_start > 0 && j >= s->rr_start) {
+      if (u[3] >= s->rr_q) go = false;
+      q = s->rr_q;
+    }
+    if (!go) {
+      if (record) out.tape.push_back(tv);
+      break;
+    }
+    tv.cont = true;
+    tv.cb = cb;
+    tv.cw = ci / (cb.pdf * q);
+    for (int k = 0; k < 3; ++k) beta[k] *= cb.f[k] * tv.cw;
+    ray = {p_off, wi};
+    hit = sc.intersect(ray, mg);
+    bool end = true;
+    if (hit.kind == K_NONE) {
+      for (int k = 0; k < 3; ++k) tv.E[k] = s->env[k];
+    } else if (hit.kind == K_LIGHT) {
+      double pl = hit.t * hit.t / (wi.y * area);
+      double wb = (flags & ORC_NO_NEE) ? 1.0 : cb.pdf / (cb.pdf + pl);
+      for (int k = 0; k < 3; ++k) tv.E[k] = s->light_Le[k] * wb;
+    } else {
+      end = j == s->depth;
+    }
+    for (int k = 0; k < 3; ++k) L[k] += beta[k] * tv.E[k];
+    if (record) out.tape.push_back(tv);
+    if (end) break;
+  }
+  out.margin = mg.m;
+}
+
+// Reverse sweep over the tape: adjoint dL/dparams += sum_k adj^k dC^k/dparams,
+// where adj is the RGB weight of this path's radiance in the loss.
+//   T_j = N'_j + w_j (E'_j + T_{j+1})   downstream radiance per unit beta_{j-1}
+//   S_j = E'_j + T_{j+1}                downstream per unit beta_j
+// NEE term:          adj beta_{j-1} K df(w_l)/dtheta
+// continuation term: adj beta_{j-1} (cos/(pdf q)) S_j df(w_i)/dtheta
+void backprop(const Scene& sc, const std::vector<TapeVertex>& tape, const double adj[3],
+              double* grad, double* gabs) {
+  const int nv = (int)tape.size();
+  double T_next[3] = {0, 0, 0};
+  for (int j = nv - 1; j >= 0; --j) {
+    const TapeVertex& v = tape[j];
+    double S[3] = {0, 0, 0}, T[3] = {0, 0, 0};
+    for (int k = 0; k < 3; ++k) {
+      S[k] = v.E[k] + T_next[k];
+      double nee = v.nee ? v.nb.f[k] * v.K[k] : 0.0;
+      double cont = v.cont ? v.cb.f[k] * v.cw * S[k] : 0.0;
+      T[k] = nee + cont;
+    }
+    if (v.param) {
+      // material-attribute gradients (R, G, B, metal, rough) for this vertex
+      double g[5] = {0, 0, 0, 0, 0}, ga[5] = {0, 0, 0, 0, 0};
+      for (int k = 0; k < 3; ++k) {
+        double cn = v.nee ? adj[k] * v.beta[k] * v.K[k] : 0.0;
+        double cc = v.cont ? adj[k] * v.beta[k] * v.cw * S[k] : 0.0;
+        double t;
+        t = cn * v.nb.dc[k]; g[k] += t; ga[k] += std::fabs(t);
+        t = cc * v.cb.dc[k]; g[k] += t; ga[k] += std::fabs(t);
+        t = cn * v.nb.dm[k]; g[3] += t; ga[3] += std::fabs(t);
+        t = cc * v.cb.dm[k]; g[3] += t; ga[3] += std::fabs(t);
+        t = cn * v.nb.dr[k]; g[4] += t; ga[4] += std::fabs(t);
+        t = cc * v.cb.dr[k]; g[4] += t; ga[4] += std::fabs(t);
+      }
+      for (int b = 0; b < 5; ++b) {
+        int slot = sc.ch_slot[b];
+        if (slot < 0) continue;
+        for (int f = 0; f < v.fp.n; ++f) {
+          size_t idx = (size_t)v.fp.texel[f] * sc.n_ch + slot;
+          grad[idx] += v.fp.w[f] * g[b];
+          gabs[idx] += v.fp.w[f] * ga[b];
+        }
+      }
+    }
+    for (int k = 0; k < 3; ++k) T_next[k] = T[k];
+  }
+}
+
+struct Crop {
+  int x0, y0, x1, y1;
+};
+
+Crop get_crop(const orc_scene* s, const int* crop) {
+  if (!crop) return {0, 0, s->width, s->height};
+  return {std::max(0, crop[0]), std::max(0, crop[1]), std::min(s->width, crop[2]),
+          std::min(s->height, crop[3])};
+}
+
+PathRng make_rng(uint64_t key, uint32_t pixel, uint32_t sample) {
+  PathRng r;
+  r.key[0] = (uint32_t)key;
+  r.key[1] = (uint32_t)(key >> 32);
+  r.pixel = pixel;
+  r.sample = sample;
+  return r;
+}
+
+size_t n_params(const Scene& sc) { return (size_t)sc.s->tex_w * sc.s->tex_h * sc.n_ch; }
+
+// Run fn(row, thread) over crop rows, one contiguous band of rows per thread.
+template <class Fn>
+void parallel_rows(const Crop& c, int nthreads, Fn fn) {
+  int rows = c.y1 - c.y0;
+  if (rows <= 0) return;
+  nthreads = std::max(1, std::min(nthreads, rows));
+  std::vector<std::thread> pool;
+  for (int t = 0; t < nthreads; ++t) {
+    int r0 = c.y0 + rows * t / nthreads, r1 = c.y0 + rows * (t + 1) / nthreads;
+    pool.emplace_back([=]() {
+      for (int y = r0; y < r1; ++y) fn(y, t);
+    });
+  }
+  for (auto& th : pool) th.join();
+}
+
+int check(const orc_scene* s) {
+  if (!s || s->width <= 0 || s->height <= 0 || s->depth < 1 || s->tex_w < 1 || s->tex_h < 1)
+    return -1;
+  if ((s->ch_mask & ~31) != 0 || s->ch_mask == 0) return -1;
+  return 0;
+}
+
+}  // namespace
+
+// --------------------------------------------------------------------------
+// C API
+// --------------------------------------------------------------------------
+extern "C" {
+
+uint64_t orc_splitmix64(uint64_t x) { return splitmix64(x); }
+
+void orc_philox4x32_10(const uint32_t ctr[4], const uint32_t key[2], uint32_t out[4]) {
+  philox(ctr, key, out);
+}
+
+uint64_t orc_stream_key(uint64_t seed, uint32_t iteration, uint32_t tag) {
+  return stream_key(seed, iteration, tag);
+}
+
+void orc_bsdf(const double mat[5], const double n[3], const double wo[3], const double wi[3],
+              int flags, double out[13]) {
+  Material m;
+  m.c[0] = mat[0]; m.c[1] = mat[1]; m.c[2] = mat[2];
+  m.metal = mat[3];
+  m.rough = mat[4];
+  Bsdf b = eval_bsdf(m, from(n), from(wo), from(wi), flags);
+  for (int k = 0; k < 3; ++k) {
+    out[k] = b.f[k];
+    out[3 + k] = b.dc[k];
+    out[6 + k] = b.dm[k];
+    out[9 + k] = b.dr[k];
+  }
+  out[12] = b.pdf;
+}
+
+void orc_bsdf_many(int count, const double mat[5], const double n[3], const double wo[3],
+                   const double* wi, int flags, double* out) {
+  for (int i = 0; i < count; ++i) orc_bsdf(mat, n, wo, wi + 3 * i, flags, out + 13 * i);
+}
+
+int orc_render(const orc_scene* s, const double* params, uint64_t seed, uint32_t iteration,
+               uint32_t tag, int spp, int flags, const int* crop, double* img, double* margin,
+               int nthreads) {
+  if (check(s) || spp < 1 || !img) return -1;
+  Scene sc(s);
+  Crop c = get_crop(s, crop);
+  uint64_t key = stream_key(seed, iteration, tag);
+  parallel_rows(c, nthreads, [&](int y, int) {
+    for (int x = c.x0; x < c.x1; ++x) {
+      uint32_t pix = (uint32_t)(y * s->width + x);
+      double acc[3] = {0, 0, 0}, mg = INF;
+      for (int smp = 0; smp < spp; ++smp) {
+        PathResult r;
+        trace(sc, params, make_rng(key, pix, smp), x, y, flags, false, r);
+        for (int k = 0; k < 3; ++k) acc[k] += r.L[k];
+        mg = std::min(mg, r.margin);
+      }
+      for (int k = 0; k < 3; ++k) img[3 * (size_t)pix + k] = acc[k] / spp;
+      if (margin) margin[pix] = mg;
+    }
+  });
+  return 0;
+}
+
+static int grad_common(const orc_scene* s, const double* params, uint64_t key_adj, int spp,
+                       const double* dimg, int flags, const Crop& c, const unsigned char* mask,
+                       double* grad, double* gabs, double* margin, int nthreads) {
+  Scene sc(s);
+  size_t np = n_params(sc);
+  int rows = c.y1 - c.y0;
+  int nt = std::max(1, std::min(nthreads, std::max(rows, 1)));
+  std::vector<std::vector<double>> g(nt, std::vector<double>(np, 0.0));
+  std::vector<std::vector<double>> ga(nt, std::vector<double>(np, 0.0));
+  parallel_rows(c, nt, [&](int y, int t) {
+    for (int x = c.x0; x < c.x1; ++x) {
+      uint32_t pix = (uint32_t)(y * s->width + x);
+      if (mask && mask[pix]) continue;
+      double adj[3];
+      for (int k = 0; k < 3; ++k) adj[k] = dimg[3 * (size_t)pix + k] / spp;
+      double mg = margin ? margin[pix] : INF;
+      for (int smp = 0; smp < spp; ++smp) {
+        PathResult r;
+        trace(sc, params, make_rng(key_adj, pix, smp), x, y, flags, true, r);
+        backprop(sc, r.tape, adj, g[t].data(), ga[t].data());
+        mg = std::min(mg, r.margin);
+      }
+      if (margin) margin[pix] = mg;
+    }
+  });
+  for (size_t i = 0; i < np; ++i) {
+    double a = 0, b = 0;
+    for (int t = 0; t < nt; ++t) {
+      a += g[t][i];
+      b += ga[t][i];
+    }
+    grad[i] = a;
+    if (gabs) gabs[i] = b;
+  }
+  return 0;
+}
+
+int orc_grad(const orc_scene* s, const double* params, uint64_t seed, uint32_t iteration,
+             uint32_t tag_primal, uint32_t tag_adj, int spp, const double* target, int flags,
+             const int* crop, const unsigned char* mask, double* grad, double* gabs, double* img,
+             double* margin, int nthreads) {
+  if (check(s) || spp < 1 || !grad || !target) return -1;
+  Crop c = get_crop(s, crop);
+  size_t npix = (size_t)s->width * s->height;
+  std::vector<double> I(3 * npix, 0.0), mg(npix, INF), dimg(3 * npix, 0.0);
+  orc_render(s, params, seed, iteration, tag_primal, spp, flags, crop, I.data(), mg.data(),
+             nthreads);
+  // L = sum (I - T)^2 / (3 W H)  ->  dL/dI = 2 (I - T) / (3 W H)
+  const double norm = 2.0 / (3.0 * (double)npix);
+  for (int y = c.y0; y < c.y1; ++y)
+    for (int x = c.x0; x < c.x1; ++x)
+      for (int k = 0; k < 3; ++k) {
+        size_t i = 3 * ((size_t)y * s->width + x) + k;
+        dimg[i] = norm * (I[i] - target[i]);
+      }
+  int rc = grad_common(s, params, stream_key(seed, iteration, tag_adj), spp, dimg.data(), flags,
+                       c, mask, grad, gabs, mg.data(), nthreads);
+  if (img)
+    for (int y = c.y0; y < c.y1; ++y)
+      for (int x = c.x0; x < c.x1; ++x)
+        for (int k = 0; k < 3; ++k) {
+          size_t i = 3 * ((size_t)y * s->width + x) + k;
+          img[i] = I[i];
+        }
+  if (margin)
+    for (int y = c.y0; y < c.y1; ++y)
+      for (int x = c.x0; x < c.x1; ++x) margin[(size_t)y * s->width + x] = mg[(size_t)y * s->width + x];
+  return rc;
+}
+
+int orc_render_bwd(const orc_scene* s, const double* params, uint64_t seed, uint32_t iteration,
+                   uint32_t tag, int spp, const double* dimg, int flags, const int* crop,
+                   const unsigned char* mask, double* grad, double* gabs, double* margin,
+                   int nthreads) {
+  if (check(s) || spp < 1 || !grad || !dimg) return -1;
+  Crop c = get_crop(s, crop);
+  if (margin)
+    for (int y = c.y0; y < c.y1; ++y)
+      for (int x = c.x0; x < c.x1; ++x) margin[(size_t)y * s->width + x] = INF;
+  return grad_common(s, params, stream_key(seed, iteration, tag), spp, dimg, flags, c, mask, grad,
+                     gabs, margin, nthreads);
+}
+
+}  // extern "C"

@@ -1,0 +1,96 @@
+/*
+ * FP64 CPU oracle for "Joint Sampling and Optimisation for Inverse Rendering"
+ * (Balint, Myszkowski, Seidel, Singh; SIGGRAPH Asia 2023).
+ *
+ * TEST INFRASTRUCTURE ONLY.  This library is the plain, slow, obviously-correct
+ * reference that the GPU path is checked against.  Only the test suite, the
+ * smoke check and the CPU-baseline leg of the benchmark may load it.  It shares
+ * no code, header or constant table with the GPU library.
+ *
+ * What it computes (all in double precision):
+ *   - the counter-based Philox4x32-10 generator (Salmon et al., SC'11) and the
+ *     SplitMix64 mixer (Steele, Lea, Flood, OOPSLA'14) that keys it;
+ *   - a path tracer for the synthetic scenes (analytic sphere/plane, square
+ *     area light, uniform environment, metallic-roughness GGX + Lambert);
+ *   - the proportional gradient sample <F_i> of Eq. 2 (Section 3, Notation)
+ *     for an L2 image loss, with the derivative taken by recording each
+ *     path's vertices on an explicit tape and sweeping it backward (reverse
+ *     mode with detached sampling densities and MIS weights);
+ *   - per-pixel decision margins used to exclude paths whose discrete
+ *     choices are too close to call for an FP32 vs FP64 comparison.
+ * The meta-estimator and optimiser (Sections 4-5, supplement pseudocode) live
+ * in oracle/meta.py (numpy, FP64).
+ */
+#ifndef JSO_ORACLE_H
+#define JSO_ORACLE_H
+#include <stdint.h>
+#ifdef __cplusplus
+extern "C" {
+#endif
+
+typedef struct {
+  int width, height;
+  double cam_eye[3], cam_target[3], cam_up[3];
+  double vfov_deg;
+  int plane_enabled, plane_mat;
+  double plane_extent[4];            /* x0, x1, z0, z1 of the planar UV map   */
+  int n_spheres;
+  const double* spheres;             /* [n][4]: cx, cy, cz, r                 */
+  const int* sphere_mat;             /* [n]: -1 = parameterised, else fixed k */
+  int light_enabled;
+  double light_center[3], light_side, light_Le[3];
+  double env[3];
+  int depth, rr_start;
+  double rr_q;
+  int tex_w, tex_h, ch_mask;         /* parameter texture layout               */
+  double fixed_default[5];           /* non-parameter channels of the param mat */
+  int n_fixed;
+  const double* fixed_mats;          /* [n_fixed][5]: R, G, B, metal, rough    */
+} orc_scene;
+
+/* debug / test-mode flags */
+enum {
+  ORC_NO_NEE = 1,           /* no light sampling; BSDF-sampled light hits weigh 1 */
+  ORC_LAMBERT_ONLY = 2,     /* f = c / pi, cosine sampling                         */
+  ORC_PARAM_INDEP = 4,      /* both lobes sampled by the cosine density           */
+  ORC_PIXEL_CENTER = 8      /* no pixel jitter                                     */
+};
+
+uint64_t orc_splitmix64(uint64_t x);
+void orc_philox4x32_10(const uint32_t ctr[4], const uint32_t key[2], uint32_t out[4]);
+uint64_t orc_stream_key(uint64_t seed, uint32_t iteration, uint32_t tag);
+
+/* BSDF value and partials for one direction pair (tests):
+ * mat = (R,G,B,metal,rough); n, wo, wi unit vectors.
+ * out[0..2] f, [3..5] df^k/dc^k, [6..8] df/dmetal, [9..11] df/drough, [12] pdf. */
+void orc_bsdf(const double mat[5], const double n[3], const double wo[3], const double wi[3],
+              int flags, double out[13]);
+/* The same for `count` directions wi[count][3] with one (mat, n, wo): out[count][13]. */
+void orc_bsdf_many(int count, const double mat[5], const double n[3], const double wo[3],
+                   const double* wi, int flags, double* out);
+
+/* Primal render: img[H*W*3] mean of spp samples; margin[H*W] min decision margin.
+ * crop = {x0, y0, x1, y1} (NULL = full).  Returns 0 on success. */
+int orc_render(const orc_scene* s, const double* params, uint64_t seed, uint32_t iteration,
+               uint32_t tag, int spp, int flags, const int* crop,
+               double* img, double* margin, int nthreads);
+
+/* One gradient sample of the L2 loss L = sum (I - T)^2 / (3 W H):
+ * primal image from (tag_primal), adjoint paths from (tag_adj), both spp per pixel.
+ * grad/gabs[n_params] are overwritten (gabs = sum of |contribution|).
+ * mask[H*W] (nullable): nonzero = skip pixel.  img/margin nullable. */
+int orc_grad(const orc_scene* s, const double* params, uint64_t seed, uint32_t iteration,
+             uint32_t tag_primal, uint32_t tag_adj, int spp, const double* target,
+             int flags, const int* crop, const unsigned char* mask,
+             double* grad, double* gabs, double* img, double* margin, int nthreads);
+
+/* Fixed-adjoint backward: grad = sum_p dimg_p . d(mean_s C_ps)/dparams. */
+int orc_render_bwd(const orc_scene* s, const double* params, uint64_t seed, uint32_t iteration,
+                   uint32_t tag, int spp, const double* dimg, int flags, const int* crop,
+                   const unsigned char* mask, double* grad, double* gabs, double* margin,
+                   int nthreads);
+
+#ifdef __cplusplus
+}
+#endif
+#endif

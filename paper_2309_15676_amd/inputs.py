@@ -1,0 +1,213 @@
+"""Seeded synthetic inputs shared by the HIP path and the FP64 oracle.
+
+This module only *describes* scenes and draws the random numbers that define
+them (sphere placement, texture values, ground-truth and initial parameters,
+synthetic target images for parity cases). It holds none of the method's
+arithmetic: no ray tracing, no shading, no gradients, no optimiser. Both the
+product binding and the oracle's binding marshal a ``SceneSpec`` into their
+own native structs.
+
+The paper's scenes (Banner, Potted Plant, Veach Ajar, ...) are not available;
+these synthetic scenes stand in for its multivariate-material experiment
+(base colour, metalness, roughness; teaser figure and the "Multivariate
+optimisation" paragraph of the Experiments section) and its texture
+optimisation experiment ("Texture optimisation" paragraph).
+
+Parameter layout (shared contract): a parameterised material is a texture of
+``tex_h x tex_w`` texels, texel-interleaved, each texel holding the enabled
+channels of (R, G, B, metalness, roughness) in that order, so parameter
+``(y * tex_w + x) * n_ch + c``.  A 1x1 texture is a "global" material.
+"""
+from __future__ import annotations
+
+import dataclasses
+import math
+from typing import List, Optional, Tuple
+
+import numpy as np
+
+# channel bits of the parameterised material
+CH_R, CH_G, CH_B, CH_M, CH_ROUGH = 1, 2, 4, 8, 16
+CH_ALL = CH_R | CH_G | CH_B | CH_M | CH_ROUGH
+CH_RGB_ROUGH = CH_R | CH_G | CH_B | CH_ROUGH
+
+# lower/upper box of each channel (projection after every step)
+ROUGH_MIN = 0.05
+CHANNEL_BOUNDS = {CH_R: (0.0, 1.0), CH_G: (0.0, 1.0), CH_B: (0.0, 1.0),
+                  CH_M: (0.0, 1.0), CH_ROUGH: (ROUGH_MIN, 1.0)}
+
+MAT_PARAM = -1  # object uses the parameterised (textured / global) material
+
+
+@dataclasses.dataclass
+class SceneSpec:
+    width: int
+    height: int
+    cam_eye: Tuple[float, float, float] = (0.0, 2.0, 6.0)
+    cam_target: Tuple[float, float, float] = (0.0, 0.8, 0.0)
+    cam_up: Tuple[float, float, float] = (0.0, 1.0, 0.0)
+    vfov_deg: float = 40.0
+    plane_enabled: bool = True
+    plane_mat: int = MAT_PARAM
+    plane_extent: Tuple[float, float, float, float] = (-5.0, 5.0, -5.0, 5.0)  # x0,x1,z0,z1 (UV)
+    spheres: np.ndarray = dataclasses.field(default_factory=lambda: np.zeros((0, 4)))  # cx,cy,cz,r
+    sphere_mat: np.ndarray = dataclasses.field(default_factory=lambda: np.zeros((0,), np.int32))
+    light_enabled: bool = True
+    light_center: Tuple[float, float, float] = (1.5, 5.0, 1.5)
+    light_side: float = 1.0
+    light_Le: Tuple[float, float, float] = (10.0, 10.0, 10.0)
+    env: Tuple[float, float, float] = (1.0, 1.0, 1.0)
+    depth: int = 3
+    rr_start: int = 0          # 0 = no Russian roulette; else first vertex whose continuation is rouletted
+    rr_q: float = 0.8          # survival probability (stored as float32 on both sides)
+    tex_w: int = 1
+    tex_h: int = 1
+    ch_mask: int = CH_ALL
+    # values of the parameterised material's channels that are not parameters
+    fixed_default: Tuple[float, float, float, float, float] = (0.5, 0.5, 0.5, 0.0, 0.5)
+    # fixed materials: rows of (R, G, B, metalness, roughness)
+    fixed_mats: np.ndarray = dataclasses.field(default_factory=lambda: np.zeros((0, 5)))
+    # triangle mesh (optional)
+    verts: np.ndarray = dataclasses.field(default_factory=lambda: np.zeros((0, 3)))
+    tris: np.ndarray = dataclasses.field(default_factory=lambda: np.zeros((0, 3), np.int32))
+    mesh_mat: int = MAT_PARAM
+
+    @property
+    def n_ch(self) -> int:
+        return bin(self.ch_mask).count("1")
+
+    @property
+    def n_params(self) -> int:
+        return self.tex_w * self.tex_h * self.n_ch
+
+    @property
+    def n_pixels(self) -> int:
+        return self.width * self.height
+
+    def channel_bits(self) -> List[int]:
+        return [b for b in (CH_R, CH_G, CH_B, CH_M, CH_ROUGH) if self.ch_mask & b]
+
+    def param_bounds(self) -> Tuple[np.ndarray, np.ndarray]:
+        """Per-parameter (lo, hi) boxes in the texel-interleaved layout."""
+        bits = self.channel_bits()
+        lo = np.array([CHANNEL_BOUNDS[b][0] for b in bits], np.float32)
+        hi = np.array([CHANNEL_BOUNDS[b][1] for b in bits], np.float32)
+        n = self.tex_w * self.tex_h
+        return np.tile(lo, n), np.tile(hi, n)
+
+
+def rng(seed: int) -> np.random.Generator:
+    return np.random.Generator(np.random.PCG64(seed))
+
+
+# ----------------------------------------------------------------------------
+# texture family: smooth random-Fourier fields
+# ----------------------------------------------------------------------------
+def random_fourier_field(h: int, w: int, g: np.random.Generator, n_terms: int = 8,
+                         lo: float = 0.1, hi: float = 0.9) -> np.ndarray:
+    """T(u,v) = mid + half * tanh(sum_k a_k sin(2 pi (f_k . (u, v)) + phi_k)).
+
+    a_k ~ N(0, 0.5^2), integer frequencies f_k in {1..4}^2, phi_k ~ U[0, 2 pi).
+    Sampled at texel centres; values lie strictly inside (lo, hi).
+    """
+    a = g.normal(0.0, 0.5, n_terms)
+    f = g.integers(1, 5, size=(n_terms, 2))
+    phi = g.uniform(0.0, 2 * math.pi, n_terms)
+    u = (np.arange(w) + 0.5) / w
+    v = (np.arange(h) + 0.5) / h
+    U, V = np.meshgrid(u, v)
+    s = np.zeros((h, w))
+    for k in range(n_terms):
+        s += a[k] * np.sin(2 * math.pi * (f[k, 0] * U + f[k, 1] * V) + phi[k])
+    mid, half = 0.5 * (lo + hi), 0.5 * (hi - lo)
+    return (mid + half * np.tanh(s)).astype(np.float32)
+
+
+def fourier_params(spec: SceneSpec, seed: int, lo: float = 0.1, hi: float = 0.9) -> np.ndarray:
+    """A texel-interleaved parameter vector with one random-Fourier field per channel."""
+    g = rng(seed)
+    chans = [random_fourier_field(spec.tex_h, spec.tex_w, g, lo=lo, hi=hi)
+             for _ in range(spec.n_ch)]
+    return np.stack(chans, axis=-1).reshape(-1).astype(np.float32)
+
+
+def uniform_params(spec: SceneSpec, seed: int, lo: float, hi: float) -> np.ndarray:
+    g = rng(seed)
+    return g.uniform(lo, hi, spec.n_params).astype(np.float32)
+
+
+# ----------------------------------------------------------------------------
+# scenes
+# ----------------------------------------------------------------------------
+PLANE_GREY = np.array([[0.6, 0.6, 0.6, 0.0, 0.8]])
+
+
+def scene_tiny(width: int = 64, height: int = 64) -> SceneSpec:
+    """Unit sphere at (0,1,0) on the plane y=0; uniform environment 1.0 and the
+    square area light; depth 3, no roulette; 5 global material parameters on
+    the sphere (R, G, B, metalness, roughness); fixed grey plane."""
+    return SceneSpec(width=width, height=height,
+                     spheres=np.array([[0.0, 1.0, 0.0, 1.0]]),
+                     sphere_mat=np.array([MAT_PARAM], np.int32),
+                     plane_mat=0, fixed_mats=PLANE_GREY.copy(),
+                     depth=3, rr_start=0, tex_w=1, tex_h=1, ch_mask=CH_ALL)
+
+
+def place_spheres(n: int, g: np.random.Generator, rmin=0.3, rmax=1.0,
+                  xr=(-3.0, 3.0), zr=(-3.0, 2.0), gap=0.05) -> np.ndarray:
+    """n spheres resting on y=0 with radii U[rmin,rmax], non-overlapping (rejection)."""
+    out = []
+    tries = 0
+    while len(out) < n:
+        tries += 1
+        if tries > 100000:
+            raise RuntimeError("sphere placement failed")
+        r = g.uniform(rmin, rmax)
+        x = g.uniform(*xr)
+        z = g.uniform(*zr)
+        ok = all((x - s[0]) ** 2 + (z - s[2]) ** 2 > (r + s[3] + gap) ** 2 for s in out)
+        if ok:
+            out.append((x, r, z, r))
+    return np.array(out, np.float64)
+
+
+def scene_textured(width: int = 512, height: int = 512, tex: int = 256, seed: int = 0,
+                   n_spheres: int = 8, depth: int = 6, rr_start: int = 3) -> SceneSpec:
+    """Plane + n spheres (radii U[0.3,1], seeded non-overlapping positions); all
+    objects share one texture of base colour RGB + roughness (metalness fixed 0)."""
+    g = rng(seed)
+    sph = place_spheres(n_spheres, g)
+    return SceneSpec(width=width, height=height, spheres=sph,
+                     sphere_mat=np.full((n_spheres,), MAT_PARAM, np.int32),
+                     plane_mat=MAT_PARAM, depth=depth, rr_start=rr_start,
+                     tex_w=tex, tex_h=tex, ch_mask=CH_RGB_ROUGH,
+                     fixed_default=(0.5, 0.5, 0.5, 0.0, 0.5))
+
+
+def scene_white_furnace(width: int = 16, height: int = 16) -> SceneSpec:
+    """Unit sphere alone in a uniform environment of radiance 1 (no plane, no light).
+    With an albedo-1 Lambertian sphere every path returns exactly 1."""
+    return SceneSpec(width=width, height=height, plane_enabled=False, light_enabled=False,
+                     spheres=np.array([[0.0, 1.0, 0.0, 1.0]]),
+                     sphere_mat=np.array([MAT_PARAM], np.int32),
+                     depth=4, tex_w=1, tex_h=1, ch_mask=CH_ALL)
+
+
+def target_image_synthetic(spec: SceneSpec, seed: int) -> np.ndarray:
+    """A seeded stand-in target image (H, W, 3) for parity cases: values U[0, 1.5]."""
+    g = rng(seed)
+    return g.uniform(0.0, 1.5, (spec.height, spec.width, 3)).astype(np.float32)
+
+
+def config_tiny(seed_gt: int = 1, seed_init: int = 2):
+    """64x64 tiny problem: scene, ground-truth and initial global parameters ~U[0.1,0.9]."""
+    s = scene_tiny()
+    return s, uniform_params(s, seed_gt, 0.1, 0.9), uniform_params(s, seed_init, 0.1, 0.9)
+
+
+def config_textured(seed_scene: int = 0, seed_gt: int = 1, seed_init: int = 2,
+                    width: int = 512, height: int = 512, tex: int = 256):
+    """512x512 textured problem: 256x256 base-colour + roughness texture (262,144 params);
+    ground truth = random-Fourier textures; initial texels ~U[0.2,0.8]."""
+    s = scene_textured(width, height, tex, seed_scene)
+    return s, fourier_params(s, seed_gt), uniform_params(s, seed_init, 0.2, 0.8)
