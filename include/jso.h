@@ -1,0 +1,251 @@
+/*
+ * jso -- joint sampling and optimisation for inverse rendering on MI355X.
+ *
+ * C ABI of libjso.so.  Implements, for one GPU (gfx950), the per-iteration
+ * hot path of the gradient meta-estimator of Bálint, Myszkowski, Seidel and
+ * Singh, "Joint Sampling and Optimisation for Inverse Rendering"
+ * (SIGGRAPH Asia 2023): a differentiable path tracer whose adjoint replays
+ * each path from a counter-based generator, the proportional gradient sample
+ * <F_i> (Eq. 1-2), the finite-difference sample <dF_i> (Eq. 3-5) traced with
+ * identical random numbers at the current and previous parameters, and the
+ * fused meta-estimator + stabilised step (Eq. 7-9, 13-17, 21).
+ *
+ * Conventions for every entry point
+ *   - Return value: JSO_OK (0) or a negative JSO_E_* code.  No exceptions
+ *     cross the ABI.  jso_last_error() gives a message for the last failure;
+ *     the string is owned by the context and valid until the next call.
+ *   - "dev" pointers are device memory on the context's device (for example
+ *     torch tensor data_ptr()); they are borrowed, never freed, and used in
+ *     stream order on the context's stream.  "host" pointers are read or
+ *     written before the call returns.
+ *   - A context is not thread-safe; use one context per host thread.
+ *   - All floating-point images are H x W x 3 (row-major, RGB interleaved,
+ *     row 0 at the top).  Parameter vectors use the texel-interleaved layout:
+ *     parameter (y * tex_w + x) * n_ch + c, where the c-th channel is the c-th
+ *     enabled bit of ch_mask in the order R, G, B, metalness, roughness.
+ */
+#ifndef JSO_H
+#define JSO_H
+
+#include <stddef.h>
+#include <stdint.h>
+
+#ifdef __cplusplus
+extern "C" {
+#endif
+
+#define JSO_OK 0
+#define JSO_E_INVALID (-1)     /* bad argument: null pointer, size or id      */
+#define JSO_E_OOM (-2)         /* device allocation failed                    */
+#define JSO_E_HIP (-3)         /* a HIP runtime call failed                   */
+#define JSO_E_STATE (-4)       /* call not valid in the current state         */
+#define JSO_E_UNSUPPORTED (-5) /* feature not supported by this build / device */
+
+/* memory space of a pointer argument */
+#define JSO_MEM_HOST 0
+#define JSO_MEM_DEVICE 1
+
+/* channel bits of the parameterised material */
+#define JSO_CH_R 1
+#define JSO_CH_G 2
+#define JSO_CH_B 4
+#define JSO_CH_METAL 8
+#define JSO_CH_ROUGH 16
+
+/* material index of objects that use the parameterised material */
+#define JSO_MAT_PARAM (-1)
+
+/* random-stream tags: which estimator a path belongs to */
+#define JSO_TAG_TARGET 1
+#define JSO_TAG_PRIMAL_PROP 2
+#define JSO_TAG_ADJ_PROP 3
+#define JSO_TAG_PRIMAL_FD 4
+#define JSO_TAG_ADJ_FD 5
+#define JSO_TAG_ADAM_PRIMAL 6
+#define JSO_TAG_ADAM_ADJ 7
+#define JSO_TAG_EVAL 8
+
+/* render / test-mode flags (jso_render_opts.flags, jso_set_debug) */
+#define JSO_F_NO_NEE 1       /* no light sampling; BSDF-sampled light hits weigh 1 */
+#define JSO_F_LAMBERT_ONLY 2 /* f = c/pi with cosine sampling                      */
+#define JSO_F_PARAM_INDEP 4  /* both lobes sampled with the cosine density         */
+#define JSO_F_PIXEL_CENTER 8 /* no pixel jitter                                    */
+
+#define JSO_MAX_SPHERES 32
+#define JSO_MAX_FIXED_MATS 8
+
+typedef struct jso_ctx jso_ctx;
+
+/* Scene description (host memory; copied by jso_load_scene).
+ * Geometry: optional infinite plane y = 0 (hit only from above), spheres,
+ * a one-sided square area light facing -y, a uniform environment.
+ * The parameterised material is a tex_h x tex_w texture (1 x 1 = one global
+ * material) of the channels in ch_mask; channels not in ch_mask take
+ * fixed_default.  Fixed materials are rows (R, G, B, metalness, roughness). */
+typedef struct {
+  int width, height;
+  float cam_eye[3], cam_target[3], cam_up[3];
+  float vfov_deg;
+  int plane_enabled, plane_mat;
+  float plane_extent[4]; /* x0, x1, z0, z1 of the planar UV map */
+  int n_spheres;         /* <= JSO_MAX_SPHERES                  */
+  const float* spheres;  /* [n][4]: cx, cy, cz, radius         */
+  const int* sphere_mat; /* [n]: JSO_MAT_PARAM or a fixed index */
+  int light_enabled;
+  float light_center[3], light_side, light_Le[3];
+  float env[3];
+  int depth;    /* maximum number of scattering vertices (>= 1)      */
+  int rr_start; /* 0 = no roulette, else first vertex whose continuation is rouletted */
+  float rr_q;   /* survival probability of the roulette                */
+  int tex_w, tex_h, ch_mask;
+  float fixed_default[5];
+  int n_fixed; /* <= JSO_MAX_FIXED_MATS */
+  const float* fixed_mats;
+} jso_scene_desc;
+
+typedef struct {
+  uint32_t flags;            /* JSO_F_*                                          */
+  int crop[4];               /* x0, y0, x1, y1; all zero = whole image            */
+  const uint8_t* pixel_mask; /* dev, H*W, nonzero = skip the pixel; may be NULL   */
+} jso_render_opts;
+
+/* Optimiser of jso_grad_step */
+#define JSO_OPT_META 0
+#define JSO_OPT_ADAM 1
+
+typedef struct {
+  int optimizer;       /* JSO_OPT_META or JSO_OPT_ADAM                            */
+  float eta;           /* learning rate                                           */
+  float beta_F;        /* meta: EMA coefficient of Var[F]   (Eq. 9), e.g. 0.99     */
+  float beta_D;        /* meta: EMA coefficient of Var[dF]_D (Eq. 13), e.g. 0.9    */
+  int spp_prop;        /* meta: proportional samples per pixel (paper: 2)         */
+  int spp_fd;          /* meta: finite-difference samples per pixel (paper: 1)    */
+  float adam_beta1, adam_beta2, adam_eps; /* adam: Eq. 18-20                      */
+  int adam_spp;        /* adam: samples per pixel                                  */
+  uint64_t seed;       /* base seed of all random streams                          */
+  uint32_t flags;      /* JSO_F_* test modes                                       */
+} jso_step_opts;
+
+typedef struct {
+  double loss;         /* L2 loss of the proportional primal image of the step   */
+  double step_norm2;   /* ||pi_{i+1} - pi_i||^2 of the step just applied          */
+  uint32_t iteration;  /* iteration index after the step                          */
+} jso_step_stats;
+
+/* Checkpoint view of one problem's optimiser state (host buffers of n_params). */
+typedef struct {
+  float* params;       /* pi_i                      */
+  float* params_prev;  /* pi_{i-1}                  */
+  double* mean;        /* <F_{i-1}>_M               */
+  double* var;         /* Var[F_{i-1}]_M            */
+  double* alpha_prev;  /* alpha_{i-1}               */
+  double* m2_F;        /* Var[F] EMA                */
+  double* m2_D;        /* Var[dF]_D EMA             */
+  float* adam_m;       /* Adam first moment         */
+  float* adam_v;       /* Adam second moment        */
+  uint32_t iteration, count_F, count_D, adam_t;
+  double step_norm2;   /* ||pi_i - pi_{i-1}||^2     */
+} jso_state;
+
+/* ---- context ---------------------------------------------------------- */
+
+/* Create a context on HIP device `device`.  stream: the hipStream_t all
+ * work is queued on (borrowed; NULL = the device's null stream, which is
+ * also torch's default stream). */
+int jso_create(jso_ctx** out, int device, void* stream);
+/* Destroy the context and free every device buffer it owns.  NULL is a no-op. */
+int jso_destroy(jso_ctx* ctx);
+const char* jso_last_error(const jso_ctx* ctx);
+/* Replace the stream used by subsequent calls (NULL = the null stream). */
+int jso_set_stream(jso_ctx* ctx, void* stream);
+/* Wait for all work queued on the context's stream. */
+int jso_synchronize(jso_ctx* ctx);
+/* Default test-mode flags OR-ed into every render of this context. */
+int jso_set_debug(jso_ctx* ctx, uint32_t flags);
+
+/* ---- counter-based random numbers (row a1) ------------------------------- */
+
+/* 64-bit Philox key of a stream: splitmix64(seed ^ splitmix64((iteration << 8) | tag)),
+ * with SplitMix64 of Steele, Lea and Flood (2014).  Pure function. */
+uint64_t jso_stream_key(uint64_t seed, uint32_t iteration, uint32_t tag);
+/* Philox4x32-10 (Salmon et al., SC'11) on the device: out[i] = philox(ctr[i], key)
+ * for n counters; ctr, out are dev arrays of n x 4 uint32 (key: lo word = k0). */
+int jso_philox(jso_ctx* ctx, uint64_t key, const uint32_t* ctr, size_t n, uint32_t* out);
+
+/* ---- scenes / problems ---------------------------------------------------- */
+
+/* Upload a scene; allocates its parameter, target, gradient and optimiser
+ * buffers on the device.  Parameters start at fixed_default / 0.5. */
+int jso_load_scene(jso_ctx* ctx, const jso_scene_desc* desc, int* scene_id);
+int jso_free_scene(jso_ctx* ctx, int scene_id);
+int jso_scene_info(jso_ctx* ctx, int scene_id, size_t* n_params, int* width, int* height);
+/* Set pi (n = n_params).  Also sets pi_{i-1} = pi and resets the optimiser
+ * state (iteration 0, Moment2 counts 0, alpha_{-1} = -inf, Adam moments 0). */
+int jso_set_params(jso_ctx* ctx, int scene_id, const float* p, size_t n, int mem);
+int jso_get_params(jso_ctx* ctx, int scene_id, float* p, size_t n, int mem);
+int jso_get_params_prev(jso_ctx* ctx, int scene_id, float* p, size_t n, int mem);
+/* Target image (n = H*W*3). */
+int jso_set_target(jso_ctx* ctx, int scene_id, const float* img, size_t n, int mem);
+
+/* ---- rendering and differentiation (rows a2-a6) ---------------------------- */
+
+/* Primal render: img (dev, H*W*3) = mean of spp paths per pixel with the
+ * parameters `params` (dev, n_params), stream (seed, iteration, tag).
+ * Pixels outside the crop or masked are left untouched.  opts may be NULL. */
+int jso_render(jso_ctx* ctx, int scene_id, const float* params, uint64_t seed,
+               uint32_t iteration, uint32_t tag, int spp, const jso_render_opts* opts,
+               float* img);
+/* Replayed adjoint of jso_render: dparams (dev, n_params) += sum over pixels p
+ * of dimg_p . d(mean_s C_ps)/dparams, with C_ps re-traced from the same stream
+ * (no tape).  The derivative treats sampling densities and MIS weights as
+ * constants (detached sampling).  dparams is accumulated into, not cleared. */
+int jso_render_bwd(jso_ctx* ctx, int scene_id, const float* params, uint64_t seed,
+                   uint32_t iteration, uint32_t tag, int spp, const float* dimg,
+                   const jso_render_opts* opts, float* dparams);
+
+/* ---- estimators (rows a5-a7) ------------------------------------------------ */
+
+/* One iteration's gradient samples for the L2 loss sum (I - T)^2 / (3 W H)
+ * against the scene's target, at the scene's pi_i (and pi_{i-1}):
+ *   F  += <F_i>   spp_prop primal paths (tag PRIMAL_PROP) give the adjoint
+ *                 image, spp_prop adjoint paths (tag ADJ_PROP) are replayed;
+ *   dF += <dF_i>  the spp_fd primal and adjoint streams (PRIMAL_FD, ADJ_FD)
+ *                 traced at pi_i and at pi_{i-1} with identical random numbers
+ *                 and differenced per vertex (Eq. 5).  Skipped if dF is NULL.
+ * F, dF: dev, n_params, accumulated into.  img (dev, H*W*3, nullable) receives
+ * the proportional primal image.  iteration selects the random streams.
+ * loss (host, nullable) receives the L2 loss of that primal image. */
+int jso_estimate_gradients(jso_ctx* ctx, int scene_id, uint64_t seed, uint32_t iteration,
+                           int spp_prop, int spp_fd, const jso_render_opts* opts, float* F,
+                           float* dF, float* img, double* loss);
+
+/* ---- optimiser steps (rows a8, a9) ------------------------------------------- */
+
+/* One meta-estimator step on given gradient samples (dev, n_params each):
+ * Moment2 updates of Var[F] and Var[dF]_D (Eq. 9, 13; bias-corrected), the
+ * rescale of Eq. 14 with ||pi_i - pi_{i-1}||^2, alpha (Eq. 8) clipped by
+ * Eq. 17, the recurrence (Eq. 7, 15), the step of Eq. 21, projection onto the
+ * parameter box, and the norm of the applied step for the next iteration.
+ * At iteration 0 or when the last step was zero, dF is ignored (no FD sample).
+ * F and dF are read only. */
+int jso_meta_step(jso_ctx* ctx, int scene_id, const float* F, const float* dF, float eta,
+                  float beta_F, float beta_D);
+/* One Adam step (Eq. 18-20, bias-corrected) on gradient g (dev, n_params). */
+int jso_adam_step(jso_ctx* ctx, int scene_id, const float* g, float eta, float beta1,
+                  float beta2, float eps);
+
+/* One full iteration for each listed problem (the hot path): estimators into
+ * the scene's own gradient buffers, then the fused optimiser step, which also
+ * clears those buffers for the next iteration.  stats (host array of n,
+ * nullable) waits for the stream and reports each problem's loss and step. */
+int jso_grad_step(jso_ctx* ctx, const int* scene_ids, int n, const jso_step_opts* opts,
+                  jso_step_stats* stats);
+
+/* ---- checkpoint ---------------------------------------------------------------- */
+int jso_get_state(jso_ctx* ctx, int scene_id, jso_state* st);
+int jso_set_state(jso_ctx* ctx, int scene_id, const jso_state* st);
+
+#ifdef __cplusplus
+}
+#endif
+#endif /* JSO_H */

@@ -19,6 +19,7 @@ parameter vectors).
 from __future__ import annotations
 
 import ctypes
+import math
 import os
 import subprocess
 from typing import Optional, Sequence, Tuple
@@ -81,13 +82,14 @@ def lib():
         L.orc_stream_key.restype = u64
         L.orc_stream_key.argtypes = [u64, u32, u32]
         L.orc_philox4x32_10.argtypes = [d, d, d]
+        L.orc_set_jitter_offset.argtypes = [ctypes.c_double, ctypes.c_double]
         L.orc_bsdf.argtypes = [d, d, d, d, i, d]
         L.orc_bsdf_many.argtypes = [i, d, d, d, d, i, d]
         L.orc_render.argtypes = [d, d, u64, u32, u32, i, i, d, d, d, i]
         L.orc_render.restype = i
-        L.orc_grad.argtypes = [d, d, u64, u32, u32, u32, i, d, i, d, d, d, d, d, d, i]
+        L.orc_grad.argtypes = [d, d, u64, u32, u32, u32, i, d, i, d, d, d, d, d, d, d, i]
         L.orc_grad.restype = i
-        L.orc_render_bwd.argtypes = [d, d, u64, u32, u32, i, d, i, d, d, d, d, d, i]
+        L.orc_render_bwd.argtypes = [d, d, u64, u32, u32, i, d, i, d, d, d, d, d, d, i]
         L.orc_render_bwd.restype = i
         _lib = L
     return _lib
@@ -97,37 +99,42 @@ def _ptr(a: Optional[np.ndarray]):
     return None if a is None else a.ctypes.data_as(ctypes.c_void_p)
 
 
+def _f32(v):
+    """Scene constants are defined as float32 values (the inputs both sides see)."""
+    return np.asarray(v, np.float32).astype(np.float64)
+
+
 class _Marshalled:
     """Keeps the numpy arrays a _Scene points into alive."""
 
     def __init__(self, spec):
-        self.spheres = np.ascontiguousarray(np.asarray(spec.spheres, np.float64).reshape(-1, 4))
+        self.spheres = np.ascontiguousarray(_f32(spec.spheres).reshape(-1, 4))
         self.sphere_mat = np.ascontiguousarray(np.asarray(spec.sphere_mat, np.int32).reshape(-1))
-        self.fixed = np.ascontiguousarray(np.asarray(spec.fixed_mats, np.float64).reshape(-1, 5))
+        self.fixed = np.ascontiguousarray(_f32(spec.fixed_mats).reshape(-1, 5))
         if len(getattr(spec, "tris", ())) > 0:
             raise NotImplementedError("oracle: triangle meshes are not supported")
         s = _Scene()
         s.width, s.height = spec.width, spec.height
-        s.cam_eye[:] = spec.cam_eye
-        s.cam_target[:] = spec.cam_target
-        s.cam_up[:] = spec.cam_up
-        s.vfov_deg = spec.vfov_deg
+        s.cam_eye[:] = _f32(spec.cam_eye)
+        s.cam_target[:] = _f32(spec.cam_target)
+        s.cam_up[:] = _f32(spec.cam_up)
+        s.vfov_deg = float(_f32(spec.vfov_deg))
         s.plane_enabled = int(spec.plane_enabled)
         s.plane_mat = int(spec.plane_mat)
-        s.plane_extent[:] = spec.plane_extent
+        s.plane_extent[:] = _f32(spec.plane_extent)
         s.n_spheres = self.spheres.shape[0]
         s.spheres = self.spheres.ctypes.data_as(ctypes.POINTER(ctypes.c_double))
         s.sphere_mat = self.sphere_mat.ctypes.data_as(ctypes.POINTER(ctypes.c_int))
         s.light_enabled = int(spec.light_enabled)
-        s.light_center[:] = spec.light_center
-        s.light_side = spec.light_side
-        s.light_Le[:] = spec.light_Le
-        s.env[:] = spec.env
+        s.light_center[:] = _f32(spec.light_center)
+        s.light_side = float(_f32(spec.light_side))
+        s.light_Le[:] = _f32(spec.light_Le)
+        s.env[:] = _f32(spec.env)
         s.depth, s.rr_start = spec.depth, spec.rr_start
         # the survival probability is defined as a float32 value on both sides
         s.rr_q = float(np.float32(spec.rr_q))
         s.tex_w, s.tex_h, s.ch_mask = spec.tex_w, spec.tex_h, spec.ch_mask
-        s.fixed_default[:] = spec.fixed_default
+        s.fixed_default[:] = _f32(spec.fixed_default)
         s.n_fixed = self.fixed.shape[0]
         s.fixed_mats = self.fixed.ctypes.data_as(ctypes.POINTER(ctypes.c_double))
         self.s = s
@@ -199,40 +206,88 @@ def render(spec, params, seed: int, iteration: int, tag: int, spp: int, flags: i
 
 def grad(spec, params, target, seed: int, iteration: int, tag_primal: int, tag_adj: int,
          spp: int, flags: int = 0, crop=None, mask=None, nthreads: Optional[int] = None):
-    """One gradient sample of the L2 loss: returns (grad, gabs, img, margin)."""
+    """One gradient sample of the L2 loss: returns (grad, gabs, img, margin, adj_img)
+    with img the primal image and adj_img the mean radiance of the adjoint paths."""
     m = _Marshalled(spec)
     p = np.ascontiguousarray(np.asarray(params, np.float64))
     t = np.ascontiguousarray(np.asarray(target, np.float64).reshape(spec.height, spec.width, 3))
     g = np.zeros(spec.n_params)
     ga = np.zeros(spec.n_params)
     img = np.zeros((spec.height, spec.width, 3))
+    aimg = np.zeros((spec.height, spec.width, 3))
     mg = np.full((spec.height, spec.width), np.inf)
     mk = None if mask is None else np.ascontiguousarray(np.asarray(mask, np.uint8))
     c = _crop_arr(crop)
     rc = lib().orc_grad(m.ptr(), _ptr(p), seed, iteration, tag_primal, tag_adj, spp, _ptr(t),
                         flags, _ptr(c), _ptr(mk), _ptr(g), _ptr(ga), _ptr(img), _ptr(mg),
-                        _nthreads(nthreads))
+                        _ptr(aimg), _nthreads(nthreads))
     if rc:
         raise ValueError("orc_grad failed")
-    return g, ga, img, mg
+    return g, ga, img, mg, aimg
 
 
 def render_bwd(spec, params, dimg, seed: int, iteration: int, tag: int, spp: int,
                flags: int = 0, crop=None, mask=None, nthreads: Optional[int] = None):
-    """Fixed-adjoint backward pass: (grad, gabs, margin)."""
+    """Fixed-adjoint backward pass: (grad, gabs, margin, adj_img)."""
     m = _Marshalled(spec)
     p = np.ascontiguousarray(np.asarray(params, np.float64))
     d = np.ascontiguousarray(np.asarray(dimg, np.float64).reshape(spec.height, spec.width, 3))
     g = np.zeros(spec.n_params)
     ga = np.zeros(spec.n_params)
     mg = np.full((spec.height, spec.width), np.inf)
+    aimg = np.zeros((spec.height, spec.width, 3))
     mk = None if mask is None else np.ascontiguousarray(np.asarray(mask, np.uint8))
     c = _crop_arr(crop)
     rc = lib().orc_render_bwd(m.ptr(), _ptr(p), seed, iteration, tag, spp, _ptr(d), flags,
-                              _ptr(c), _ptr(mk), _ptr(g), _ptr(ga), _ptr(mg), _nthreads(nthreads))
+                              _ptr(c), _ptr(mk), _ptr(g), _ptr(ga), _ptr(mg), _ptr(aimg),
+                              _nthreads(nthreads))
     if rc:
         raise ValueError("orc_render_bwd failed")
-    return g, ga, mg
+    return g, ga, mg, aimg
+
+
+def rounding_sensitivity(spec, fn, radians: float = 1e-6):
+    """Run fn() and, with the same random numbers, again with every primary ray
+    turned by `radians` in +-x and +-y; return (fn(), max |deviation|).
+
+    1e-6 rad is about 16 single-precision epsilons: the deviation measures how
+    strongly each pixel's (or parameter's) paths amplify rounding of that size
+    -- near-specular GGX peaks and grazing directions amplify it most -- and
+    serves as the per-element floor of an FP32 vs FP64 comparison.
+    fn returns an array, a tuple of arrays (None entries are skipped) or a
+    dict of arrays; the deviation has the same structure."""
+    px = radians / (2.0 * math.tan(math.radians(float(np.float32(spec.vfov_deg))) / 2) /
+                    spec.height)
+    base = fn()
+
+    def dev(a, b):
+        if isinstance(a, dict):
+            return {k: dev(a[k], b[k]) for k in a if isinstance(a[k], np.ndarray)}
+        if isinstance(a, tuple):
+            return tuple(dev(x, y) for x, y in zip(a, b))
+        if a is None:
+            return None
+        a, b = np.asarray(a, np.float64), np.asarray(b, np.float64)
+        with np.errstate(invalid="ignore"):
+            d = np.abs(a - b)
+        return np.where(np.isfinite(d), d, 0.0)  # (unbounded margins compare as 0)
+
+    def worse(w, d):
+        if isinstance(d, dict):
+            return {k: worse(w[k], d[k]) for k in d}
+        if isinstance(d, tuple):
+            return tuple(worse(x, y) for x, y in zip(w, d))
+        return None if d is None else np.maximum(w, d)
+
+    worst = None
+    try:
+        for dx, dy in ((px, 0.0), (-px, 0.0), (0.0, px), (0.0, -px)):
+            lib().orc_set_jitter_offset(dx, dy)
+            d = dev(fn(), base)
+            worst = d if worst is None else worse(worst, d)
+    finally:
+        lib().orc_set_jitter_offset(0.0, 0.0)
+    return base, worst
 
 
 def gradient_pair(spec, params, params_prev, target, seed: int, iteration: int,
@@ -243,18 +298,45 @@ def gradient_pair(spec, params, params_prev, target, seed: int, iteration: int,
     <F_i>: spp_prop primal + spp_prop adjoint paths at pi_i (own streams).
     <dF_i>: the same spp_fd primal/adjoint streams evaluated at pi_i and at
     pi_{i-1}, differenced; zero at i = 0 or when no previous parameters exist.
-    Returns dict with F, dF, F_abs, dF_abs (FP64), I (prop primal) and margin.
+    Returns dict with F, dF, F_abs, dF_abs (FP64), I (prop primal image), margin,
+    and the per-pixel radiance of every stream: A (prop adjoint paths),
+    I_fd1 / I_fd0 (FD primal at pi_i / pi_{i-1}), A_fd1 / A_fd0 (FD adjoint).
     """
-    F, Fa, I, mg = grad(spec, params, target, seed, iteration, TAG_PRIMAL_PROP, TAG_ADJ_PROP,
-                        spp_prop, flags, crop, mask, nthreads)
+    F, Fa, I, mg, A = grad(spec, params, target, seed, iteration, TAG_PRIMAL_PROP,
+                           TAG_ADJ_PROP, spp_prop, flags, crop, mask, nthreads)
+    out = dict(F=F, F_abs=Fa, I=I, A=A)
     dF = np.zeros_like(F)
     dFa = np.zeros_like(F)
     if iteration >= 1 and params_prev is not None:
-        g1, a1, _, m1 = grad(spec, params, target, seed, iteration, TAG_PRIMAL_FD, TAG_ADJ_FD,
-                             spp_fd, flags, crop, mask, nthreads)
-        g0, a0, _, m0 = grad(spec, params_prev, target, seed, iteration, TAG_PRIMAL_FD,
-                             TAG_ADJ_FD, spp_fd, flags, crop, mask, nthreads)
+        g1, a1, i1, m1, A1 = grad(spec, params, target, seed, iteration, TAG_PRIMAL_FD,
+                                  TAG_ADJ_FD, spp_fd, flags, crop, mask, nthreads)
+        g0, a0, i0, m0, A0 = grad(spec, params_prev, target, seed, iteration, TAG_PRIMAL_FD,
+                                  TAG_ADJ_FD, spp_fd, flags, crop, mask, nthreads)
         dF = g1 - g0
         dFa = a1 + a0
         mg = np.minimum(mg, np.minimum(m1, m0))
-    return dict(F=F, dF=dF, F_abs=Fa, dF_abs=dFa, I=I, margin=mg)
+        out.update(I_fd1=i1, I_fd0=i0, A_fd1=A1, A_fd0=A0)
+    out.update(dF=dF, dF_abs=dFa, margin=mg)
+    return out
+
+
+STREAM_IMAGES = ("I", "A", "I_fd1", "I_fd0", "A_fd1", "A_fd0")
+
+
+def ill_conditioned(result: dict, floor: dict, rel: float = 1e-2) -> np.ndarray:
+    """Pixels (H, W) where some stream's radiance moves by more than `rel` of
+    its scale when the primary rays turn by the rounding_sensitivity angle:
+    chaotic paths (curved geometry + textured roughness + specular sampling
+    amplify single-precision rounding into a different path), for which an
+    FP32 vs FP64 comparison of individual samples is not meaningful."""
+    bad = None
+    for k in STREAM_IMAGES:
+        if k not in result:
+            continue
+        img = result[k]
+        traced = np.abs(img).max(-1) > 0  # pixels outside a crop / mask stay zero
+        mean = np.abs(img[traced]).mean() if traced.any() else 0.0
+        scale = np.maximum(np.abs(img), 1e-3 * mean + 1e-300)
+        b = (floor[k] / scale).max(-1) > rel
+        bad = b if bad is None else (bad | b)
+    return bad

@@ -139,66 +139,106 @@ struct Scene {
     return {eye, normalize(cw + cu * sx + cv * sy)};
   }
 
-  // sphere k against ray; returns t or INF (t must exceed 0)
-  double hit_sphere(int k, const Ray& r, Margin& mg) const {
+  // Candidate distances.  Each returns the hit distance (or INF) and, through
+  // `near`, the distance at which a flipped hit/miss decision would place the
+  // primitive together with that decision's relative margin.
+  struct Cand {
+    double t = INF;        // hit distance, INF = miss
+    double t_near = INF;   // where the primitive would be hit if the decision flipped
+    double margin = INF;   // relative distance of the decision from its threshold
+  };
+
+  Cand sphere(int k, const Ray& r) const {
+    Cand c;
     const double* sp = s->spheres + 4 * k;
-    V3 c{sp[0], sp[1], sp[2]};
+    V3 oc = r.o - V3{sp[0], sp[1], sp[2]};
     double rad = sp[3];
-    V3 oc = r.o - c;
     double b = dot(oc, r.d);
     double cc = dot(oc, oc) - rad * rad;
     double disc = b * b - cc;
-    mg.add(disc / (rad * rad));
-    if (disc < 0) return INF;
+    c.margin = std::fabs(disc) / (rad * rad);
+    if (disc < 0) {
+      c.t_near = -b > 0 ? -b : INF;  // closest approach
+      return c;
+    }
     double sq = std::sqrt(disc);
     double t0 = -b - sq, t1 = -b + sq;
-    if (t0 > 0) return t0;
-    if (t1 > 0) return t1;
-    return INF;
+    c.t = t0 > 0 ? t0 : (t1 > 0 ? t1 : INF);
+    c.t_near = c.t;
+    return c;
   }
 
-  double hit_plane(const Ray& r, Margin& mg) const {
-    if (!s->plane_enabled) return INF;
-    mg.add(r.d.y);
-    if (!(r.d.y < 0) || !(r.o.y > 0)) return INF;
-    return -r.o.y / r.d.y;
+  Cand plane(const Ray& r) const {
+    Cand c;
+    if (!s->plane_enabled) return c;
+    if (!(r.o.y > 0)) {
+      // origins just below y = 0 (offset from a sphere's underside) skip the plane
+      if (r.d.y < 0) {
+        c.margin = std::fabs(r.o.y) / RAY_EPS;
+        c.t_near = -r.o.y / r.d.y;
+      }
+      return c;
+    }
+    c.margin = std::fabs(r.d.y);
+    if (r.d.y < 0) c.t = -r.o.y / r.d.y;
+    c.t_near = c.t;  // a flip to d.y > 0 moves the hit to infinity
+    return c;
   }
 
-  double hit_light(const Ray& r, Margin& mg) const {
-    if (!s->light_enabled) return INF;
+  Cand light(const Ray& r) const {
+    Cand c;
+    if (!s->light_enabled) return c;
     double ly = s->light_center[1];
-    mg.add(r.d.y);
-    if (!(r.d.y > 0) || !(r.o.y < ly)) return INF;
+    if (!(r.d.y > 0) || !(r.o.y < ly)) return c;
     double t = (ly - r.o.y) / r.d.y;
     double h = 0.5 * s->light_side;
     double dx = r.o.x + t * r.d.x - s->light_center[0];
     double dz = r.o.z + t * r.d.z - s->light_center[2];
-    mg.add((h - std::fabs(dx)) / s->light_side);
-    mg.add((h - std::fabs(dz)) / s->light_side);
-    if (std::fabs(dx) > h || std::fabs(dz) > h) return INF;
-    return t;
+    c.margin = std::min(std::fabs(h - std::fabs(dx)), std::fabs(h - std::fabs(dz))) / s->light_side;
+    c.t_near = t;
+    if (std::fabs(dx) <= h && std::fabs(dz) <= h) c.t = t;
+    return c;
   }
 
   // Closest hit; primitive order plane < spheres < light, and a strictly
   // smaller t is needed to replace the current best (equal t: lower id wins).
+  // Margins: the winner's own decision, every near miss that would land in
+  // front of the winner, and the gap to the runner-up.
   Hit intersect(const Ray& r, Margin& mg) const {
     Hit h;
-    double second = INF;
-    auto consider = [&](double t, Kind kind, int obj) {
-      if (t < h.t) {
-        second = h.t;
-        h.t = t;
-        h.kind = kind;
-        h.obj = obj;
-      } else if (t < second) {
-        second = t;
+    const int n = s->n_spheres;
+    std::vector<Cand> cs;
+    cs.reserve(n + 2);
+    cs.push_back(plane(r));
+    for (int k = 0; k < n; ++k) cs.push_back(sphere(k, r));
+    cs.push_back(light(r));
+    int best = -1;
+    for (int i = 0; i < (int)cs.size(); ++i)
+      if (cs[i].t < h.t) {
+        h.t = cs[i].t;
+        best = i;
       }
-    };
-    consider(hit_plane(r, mg), K_PLANE, 0);
-    for (int k = 0; k < s->n_spheres; ++k) consider(hit_sphere(k, r, mg), K_SPHERE, k);
-    consider(hit_light(r, mg), K_LIGHT, 0);
-    if (h.kind == K_NONE) return h;
+    double second = INF;
+    for (int i = 0; i < (int)cs.size(); ++i) {
+      if (i == best) {
+        mg.add(cs[i].margin);
+        continue;
+      }
+      if (cs[i].t < second) second = cs[i].t;
+      if (cs[i].t == INF && cs[i].t_near < h.t) mg.add(cs[i].margin);
+    }
+    if (best < 0) return h;
     if (second < INF) mg.add((second - h.t) / h.t);
+    if (best == 0) {
+      h.kind = K_PLANE;
+      h.obj = 0;
+    } else if (best == (int)cs.size() - 1) {
+      h.kind = K_LIGHT;
+      h.obj = 0;
+    } else {
+      h.kind = K_SPHERE;
+      h.obj = best - 1;
+    }
     h.p = r.o + r.d * h.t;
     if (h.kind == K_PLANE) {
       h.n = {0, 1, 0};
@@ -212,23 +252,21 @@ struct Scene {
     return h;
   }
 
-  // any occluder (plane, spheres) with 0 < t < tmax
+  // any occluder (plane, spheres) with 0 < t < tmax; margins of every decision
+  // that could change the answer
   bool occluded(const Ray& r, double tmax, Margin& mg) const {
-    Margin local;
     bool occ = false;
-    double tp = hit_plane(r, local);
-    if (tp < INF) {
-      mg.add((tmax - tp) / tmax);
-      if (tp < tmax) occ = true;
-    }
-    for (int k = 0; k < s->n_spheres; ++k) {
-      double t = hit_sphere(k, r, local);
-      if (t < INF) {
-        mg.add((tmax - t) / tmax);
-        if (t < tmax) occ = true;
+    auto one = [&](const Cand& c) {
+      if (c.t < INF) {
+        mg.add((tmax - c.t) / tmax);
+        mg.add(c.margin);
+        if (c.t < tmax) occ = true;
+      } else if (c.t_near < tmax) {
+        mg.add(c.margin);
       }
-    }
-    mg.add(local.m);
+    };
+    one(plane(r));
+    for (int k = 0; k < s->n_spheres; ++k) one(sphere(k, r));
     return occ;
   }
 };
@@ -249,7 +287,10 @@ struct Material {
 };
 
 // Bilinear texture footprint, clamp-to-edge, texel centres at (i + 0.5) / size.
-Footprint bilinear(const orc_scene* s, double u, double v) {
+// Margin: distance (in texels) of the texel coordinates from an integer --
+// the value is continuous there, but which neighbour texel receives a
+// vanishing weight is a discrete choice.
+Footprint bilinear(const orc_scene* s, double u, double v, Margin& mg) {
   Footprint fp;
   if (s->tex_w == 1 && s->tex_h == 1) {
     fp.n = 1;
@@ -259,6 +300,8 @@ Footprint bilinear(const orc_scene* s, double u, double v) {
   }
   double x = u * s->tex_w - 0.5, y = v * s->tex_h - 0.5;
   double x0 = std::floor(x), y0 = std::floor(y);
+  if (x > 0 && x < s->tex_w - 1) mg.add(x - std::nearbyint(x));
+  if (y > 0 && y < s->tex_h - 1) mg.add(y - std::nearbyint(y));
   double fx = x - x0, fy = y - y0;
   auto cl = [](double a, int n) { return (int)std::min(std::max(a, 0.0), (double)(n - 1)); };
   int xi0 = cl(x0, s->tex_w), xi1 = cl(x0 + 1, s->tex_w);
@@ -291,10 +334,10 @@ Material material_at(const Scene& sc, const Hit& h, const double* params, Margin
     V3 n = h.n;
     if (n.x < 0 && s->tex_w > 1) mg.add(n.z);
     u = 0.5 + std::atan2(n.z, n.x) / (2 * PI);
-    v = std::acos(std::min(1.0, std::max(-1.0, n.y))) / PI;
+    v = std::atan2(std::sqrt(n.x * n.x + n.z * n.z), n.y) / PI;
   }
   m.param = true;
-  m.fp = bilinear(s, u, v);
+  m.fp = bilinear(s, u, v, mg);
   double val[5];
   for (int b = 0; b < 5; ++b) {
     if (sc.ch_slot[b] < 0) {
@@ -433,6 +476,12 @@ struct PathResult {
   std::vector<TapeVertex> tape;
 };
 
+// Test hook: a fixed offset (in pixels) added to every primary sample
+// position.  Tracing the same random numbers with the primary ray turned by
+// about the size of single-precision rounding measures how strongly a path
+// amplifies such rounding (its conditioning).  Zero in normal use.
+double g_jitter_dx = 0.0, g_jitter_dy = 0.0;
+
 void trace(const Scene& sc, const double* params, const PathRng& rng, int px, int py, int flags,
            bool record, PathResult& out) {
   const orc_scene* s = sc.s;
@@ -444,7 +493,7 @@ void trace(const Scene& sc, const double* params, const PathRng& rng, int px, in
     jx = u[0];
     jy = u[1];
   }
-  Ray ray = sc.camera_ray(px, py, jx, jy);
+  Ray ray = sc.camera_ray(px, py, jx + g_jitter_dx, jy + g_jitter_dy);
   Hit hit = sc.intersect(ray, mg);
   double* L = out.L;
   if (hit.kind == K_NONE) {
@@ -478,6 +527,8 @@ void trace(const Scene& sc, const double* params, const PathRng& rng, int px, in
       double dist2 = dot(dl, dl), dist = std::sqrt(dist2);
       V3 wl = dl * (1.0 / dist);
       double cos_l = wl.y, cos_s = dot(n, wl);
+      // the light term vanishes continuously at zero cosines, but which
+      // parameters receive (tiny) derivatives still depends on the sign
       mg.add(cos_l);
       mg.add(cos_s);
       if (cos_l > 0 && cos_s > 0 && !sc.occluded({p_off, wl}, dist - SHADOW_EPS, mg)) {
@@ -497,7 +548,7 @@ void trace(const Scene& sc, const double* params, const PathRng& rng, int px, in
     rng.draw(j, 0, u);
     V3 wi = sample_dir(mat, n, wo, u, flags, mg);
     double ci = dot(n, wi);
-    mg.add(ci);
+    mg.add(ci);  // continuous in value, not in which vertices follow
     bool go = ci > 0;
     Bsdf cb;
     double q = 1.0;
@@ -636,6 +687,11 @@ extern "C" {
 
 uint64_t orc_splitmix64(uint64_t x) { return splitmix64(x); }
 
+void orc_set_jitter_offset(double dx, double dy) {
+  g_jitter_dx = dx;
+  g_jitter_dy = dy;
+}
+
 void orc_philox4x32_10(const uint32_t ctr[4], const uint32_t key[2], uint32_t out[4]) {
   philox(ctr, key, out);
 }
@@ -691,7 +747,8 @@ int orc_render(const orc_scene* s, const double* params, uint64_t seed, uint32_t
 
 static int grad_common(const orc_scene* s, const double* params, uint64_t key_adj, int spp,
                        const double* dimg, int flags, const Crop& c, const unsigned char* mask,
-                       double* grad, double* gabs, double* margin, int nthreads) {
+                       double* grad, double* gabs, double* margin, double* adj_img,
+                       int nthreads) {
   Scene sc(s);
   size_t np = n_params(sc);
   int rows = c.y1 - c.y0;
@@ -705,13 +762,17 @@ static int grad_common(const orc_scene* s, const double* params, uint64_t key_ad
       double adj[3];
       for (int k = 0; k < 3; ++k) adj[k] = dimg[3 * (size_t)pix + k] / spp;
       double mg = margin ? margin[pix] : INF;
+      double acc[3] = {0, 0, 0};
       for (int smp = 0; smp < spp; ++smp) {
         PathResult r;
         trace(sc, params, make_rng(key_adj, pix, smp), x, y, flags, true, r);
         backprop(sc, r.tape, adj, g[t].data(), ga[t].data());
         mg = std::min(mg, r.margin);
+        for (int k = 0; k < 3; ++k) acc[k] += r.L[k];
       }
       if (margin) margin[pix] = mg;
+      if (adj_img)
+        for (int k = 0; k < 3; ++k) adj_img[3 * (size_t)pix + k] = acc[k] / spp;
     }
   });
   for (size_t i = 0; i < np; ++i) {
@@ -729,7 +790,7 @@ static int grad_common(const orc_scene* s, const double* params, uint64_t key_ad
 int orc_grad(const orc_scene* s, const double* params, uint64_t seed, uint32_t iteration,
              uint32_t tag_primal, uint32_t tag_adj, int spp, const double* target, int flags,
              const int* crop, const unsigned char* mask, double* grad, double* gabs, double* img,
-             double* margin, int nthreads) {
+             double* margin, double* adj_img, int nthreads) {
   if (check(s) || spp < 1 || !grad || !target) return -1;
   Crop c = get_crop(s, crop);
   size_t npix = (size_t)s->width * s->height;
@@ -745,7 +806,7 @@ int orc_grad(const orc_scene* s, const double* params, uint64_t seed, uint32_t i
         dimg[i] = norm * (I[i] - target[i]);
       }
   int rc = grad_common(s, params, stream_key(seed, iteration, tag_adj), spp, dimg.data(), flags,
-                       c, mask, grad, gabs, mg.data(), nthreads);
+                       c, mask, grad, gabs, mg.data(), adj_img, nthreads);
   if (img)
     for (int y = c.y0; y < c.y1; ++y)
       for (int x = c.x0; x < c.x1; ++x)
@@ -762,14 +823,14 @@ int orc_grad(const orc_scene* s, const double* params, uint64_t seed, uint32_t i
 int orc_render_bwd(const orc_scene* s, const double* params, uint64_t seed, uint32_t iteration,
                    uint32_t tag, int spp, const double* dimg, int flags, const int* crop,
                    const unsigned char* mask, double* grad, double* gabs, double* margin,
-                   int nthreads) {
+                   double* adj_img, int nthreads) {
   if (check(s) || spp < 1 || !grad || !dimg) return -1;
   Crop c = get_crop(s, crop);
   if (margin)
     for (int y = c.y0; y < c.y1; ++y)
       for (int x = c.x0; x < c.x1; ++x) margin[(size_t)y * s->width + x] = INF;
   return grad_common(s, params, stream_key(seed, iteration, tag), spp, dimg, flags, c, mask, grad,
-                     gabs, margin, nthreads);
+                     gabs, margin, adj_img, nthreads);
 }
 
 }  // extern "C"

@@ -57,6 +57,9 @@ enum {
 };
 
 uint64_t orc_splitmix64(uint64_t x);
+/* Test hook: offset (pixels) added to every primary sample position; used to
+ * measure each path's sensitivity to single-precision rounding.  Default 0. */
+void orc_set_jitter_offset(double dx, double dy);
 void orc_philox4x32_10(const uint32_t ctr[4], const uint32_t key[2], uint32_t out[4]);
 uint64_t orc_stream_key(uint64_t seed, uint32_t iteration, uint32_t tag);
 
@@ -78,17 +81,19 @@ int orc_render(const orc_scene* s, const double* params, uint64_t seed, uint32_t
 /* One gradient sample of the L2 loss L = sum (I - T)^2 / (3 W H):
  * primal image from (tag_primal), adjoint paths from (tag_adj), both spp per pixel.
  * grad/gabs[n_params] are overwritten (gabs = sum of |contribution|).
- * mask[H*W] (nullable): nonzero = skip pixel.  img/margin nullable. */
+ * mask[H*W] (nullable): nonzero = skip pixel.  img (primal image), margin and
+ * adj_img (mean radiance of the adjoint paths, H*W*3) are nullable outputs. */
 int orc_grad(const orc_scene* s, const double* params, uint64_t seed, uint32_t iteration,
              uint32_t tag_primal, uint32_t tag_adj, int spp, const double* target,
              int flags, const int* crop, const unsigned char* mask,
-             double* grad, double* gabs, double* img, double* margin, int nthreads);
+             double* grad, double* gabs, double* img, double* margin, double* adj_img,
+             int nthreads);
 
 /* Fixed-adjoint backward: grad = sum_p dimg_p . d(mean_s C_ps)/dparams. */
 int orc_render_bwd(const orc_scene* s, const double* params, uint64_t seed, uint32_t iteration,
                    uint32_t tag, int spp, const double* dimg, int flags, const int* crop,
                    const unsigned char* mask, double* grad, double* gabs, double* margin,
-                   int nthreads);
+                   double* adj_img, int nthreads);
 
 #ifdef __cplusplus
 }

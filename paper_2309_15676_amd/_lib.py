@@ -1,0 +1,354 @@
+"""ctypes binding of libjso.so (include/jso.h): argument marshalling only.
+
+Every function here has the name of the C entry point it calls and returns
+its status code; `check()` turns a failure into JsoError with the library's
+message.  Device pointers are plain integers (e.g. torch ``data_ptr()``).
+The library must have been built (``python -m paper_2309_15676_amd.build``);
+loading fails loudly otherwise -- there is no fallback path.
+"""
+from __future__ import annotations
+
+import ctypes
+import os
+from typing import Optional
+
+import numpy as np
+
+_HERE = os.path.dirname(os.path.abspath(__file__))
+LIB_PATH = os.path.join(_HERE, "libjso.so")
+
+JSO_OK, JSO_E_INVALID, JSO_E_OOM, JSO_E_HIP, JSO_E_STATE, JSO_E_UNSUPPORTED = 0, -1, -2, -3, -4, -5
+JSO_MEM_HOST, JSO_MEM_DEVICE = 0, 1
+JSO_MAT_PARAM = -1
+JSO_TAG_TARGET, JSO_TAG_PRIMAL_PROP, JSO_TAG_ADJ_PROP = 1, 2, 3
+JSO_TAG_PRIMAL_FD, JSO_TAG_ADJ_FD = 4, 5
+JSO_TAG_ADAM_PRIMAL, JSO_TAG_ADAM_ADJ, JSO_TAG_EVAL = 6, 7, 8
+JSO_F_NO_NEE, JSO_F_LAMBERT_ONLY, JSO_F_PARAM_INDEP, JSO_F_PIXEL_CENTER = 1, 2, 4, 8
+JSO_OPT_META, JSO_OPT_ADAM = 0, 1
+JSO_MAX_SPHERES, JSO_MAX_FIXED_MATS = 32, 8
+
+EXPORTED = [
+    "jso_create", "jso_destroy", "jso_last_error", "jso_set_stream", "jso_synchronize",
+    "jso_set_debug", "jso_stream_key", "jso_philox", "jso_load_scene", "jso_free_scene",
+    "jso_scene_info", "jso_set_params", "jso_get_params", "jso_get_params_prev",
+    "jso_set_target", "jso_render", "jso_render_bwd", "jso_estimate_gradients",
+    "jso_meta_step", "jso_adam_step", "jso_grad_step", "jso_get_state", "jso_set_state",
+]
+
+
+class JsoError(RuntimeError):
+    pass
+
+
+class jso_scene_desc(ctypes.Structure):
+    _fields_ = [
+        ("width", ctypes.c_int), ("height", ctypes.c_int),
+        ("cam_eye", ctypes.c_float * 3), ("cam_target", ctypes.c_float * 3),
+        ("cam_up", ctypes.c_float * 3), ("vfov_deg", ctypes.c_float),
+        ("plane_enabled", ctypes.c_int), ("plane_mat", ctypes.c_int),
+        ("plane_extent", ctypes.c_float * 4),
+        ("n_spheres", ctypes.c_int), ("spheres", ctypes.POINTER(ctypes.c_float)),
+        ("sphere_mat", ctypes.POINTER(ctypes.c_int)),
+        ("light_enabled", ctypes.c_int), ("light_center", ctypes.c_float * 3),
+        ("light_side", ctypes.c_float), ("light_Le", ctypes.c_float * 3),
+        ("env", ctypes.c_float * 3),
+        ("depth", ctypes.c_int), ("rr_start", ctypes.c_int), ("rr_q", ctypes.c_float),
+        ("tex_w", ctypes.c_int), ("tex_h", ctypes.c_int), ("ch_mask", ctypes.c_int),
+        ("fixed_default", ctypes.c_float * 5),
+        ("n_fixed", ctypes.c_int), ("fixed_mats", ctypes.POINTER(ctypes.c_float)),
+    ]
+
+
+class jso_render_opts(ctypes.Structure):
+    _fields_ = [("flags", ctypes.c_uint32), ("crop", ctypes.c_int * 4),
+                ("pixel_mask", ctypes.c_void_p)]
+
+
+class jso_step_opts(ctypes.Structure):
+    _fields_ = [
+        ("optimizer", ctypes.c_int), ("eta", ctypes.c_float), ("beta_F", ctypes.c_float),
+        ("beta_D", ctypes.c_float), ("spp_prop", ctypes.c_int), ("spp_fd", ctypes.c_int),
+        ("adam_beta1", ctypes.c_float), ("adam_beta2", ctypes.c_float),
+        ("adam_eps", ctypes.c_float), ("adam_spp", ctypes.c_int), ("seed", ctypes.c_uint64),
+        ("flags", ctypes.c_uint32),
+    ]
+
+
+class jso_step_stats(ctypes.Structure):
+    _fields_ = [("loss", ctypes.c_double), ("step_norm2", ctypes.c_double),
+                ("iteration", ctypes.c_uint32)]
+
+
+class jso_state(ctypes.Structure):
+    _fields_ = [
+        ("params", ctypes.c_void_p), ("params_prev", ctypes.c_void_p),
+        ("mean", ctypes.c_void_p), ("var", ctypes.c_void_p), ("alpha_prev", ctypes.c_void_p),
+        ("m2_F", ctypes.c_void_p), ("m2_D", ctypes.c_void_p),
+        ("adam_m", ctypes.c_void_p), ("adam_v", ctypes.c_void_p),
+        ("iteration", ctypes.c_uint32), ("count_F", ctypes.c_uint32),
+        ("count_D", ctypes.c_uint32), ("adam_t", ctypes.c_uint32),
+        ("step_norm2", ctypes.c_double),
+    ]
+
+
+_lib: Optional[ctypes.CDLL] = None
+
+
+def load() -> ctypes.CDLL:
+    """Load libjso.so (raises if it was not built)."""
+    global _lib
+    if _lib is not None:
+        return _lib
+    if not os.path.exists(LIB_PATH):
+        raise JsoError("libjso.so not found at %s: build it with "
+                       "`python -m paper_2309_15676_amd.build`" % LIB_PATH)
+    L = ctypes.CDLL(LIB_PATH)
+    P, I, U32, U64, SZ, D = (ctypes.c_void_p, ctypes.c_int, ctypes.c_uint32, ctypes.c_uint64,
+                             ctypes.c_size_t, ctypes.c_double)
+    F = ctypes.c_float
+    sig = {
+        "jso_create": (I, [ctypes.POINTER(P), I, P]),
+        "jso_destroy": (I, [P]),
+        "jso_last_error": (ctypes.c_char_p, [P]),
+        "jso_set_stream": (I, [P, P]),
+        "jso_synchronize": (I, [P]),
+        "jso_set_debug": (I, [P, U32]),
+        "jso_stream_key": (U64, [U64, U32, U32]),
+        "jso_philox": (I, [P, U64, P, SZ, P]),
+        "jso_load_scene": (I, [P, P, ctypes.POINTER(I)]),
+        "jso_free_scene": (I, [P, I]),
+        "jso_scene_info": (I, [P, I, ctypes.POINTER(SZ), ctypes.POINTER(I), ctypes.POINTER(I)]),
+        "jso_set_params": (I, [P, I, P, SZ, I]),
+        "jso_get_params": (I, [P, I, P, SZ, I]),
+        "jso_get_params_prev": (I, [P, I, P, SZ, I]),
+        "jso_set_target": (I, [P, I, P, SZ, I]),
+        "jso_render": (I, [P, I, P, U64, U32, U32, I, P, P]),
+        "jso_render_bwd": (I, [P, I, P, U64, U32, U32, I, P, P, P]),
+        "jso_estimate_gradients": (I, [P, I, U64, U32, I, I, P, P, P, P, P]),
+        "jso_meta_step": (I, [P, I, P, P, F, F, F]),
+        "jso_adam_step": (I, [P, I, P, F, F, F, F]),
+        "jso_grad_step": (I, [P, P, I, P, P]),
+        "jso_get_state": (I, [P, I, P]),
+        "jso_set_state": (I, [P, I, P]),
+    }
+    for name, (res, args) in sig.items():
+        fn = getattr(L, name)
+        fn.restype = res
+        fn.argtypes = args
+    _lib = L
+    return L
+
+
+def check(rc: int, ctx=None, what: str = "") -> None:
+    if rc != JSO_OK:
+        msg = load().jso_last_error(ctx).decode() if ctx else ""
+        raise JsoError("%s failed (%d): %s" % (what or "jso call", rc, msg))
+
+
+# ---------------------------------------------------------------------------
+# same-named wrappers
+# ---------------------------------------------------------------------------
+def jso_create(device: int = 0, stream: int = 0):
+    ctx = ctypes.c_void_p()
+    rc = load().jso_create(ctypes.byref(ctx), device, stream or None)
+    check(rc, None, "jso_create")
+    return ctx
+
+
+def jso_destroy(ctx) -> int:
+    return load().jso_destroy(ctx)
+
+
+def jso_last_error(ctx) -> str:
+    return load().jso_last_error(ctx).decode()
+
+
+def jso_set_stream(ctx, stream: int) -> int:
+    return load().jso_set_stream(ctx, stream or None)
+
+
+def jso_synchronize(ctx) -> int:
+    return load().jso_synchronize(ctx)
+
+
+def jso_set_debug(ctx, flags: int) -> int:
+    return load().jso_set_debug(ctx, flags)
+
+
+def jso_stream_key(seed: int, iteration: int, tag: int) -> int:
+    return int(load().jso_stream_key(seed, iteration, tag))
+
+
+def jso_philox(ctx, key: int, ctr_ptr: int, n: int, out_ptr: int) -> int:
+    return load().jso_philox(ctx, key, ctr_ptr, n, out_ptr)
+
+
+class SceneDesc:
+    """Marshals a SceneSpec-like object into a jso_scene_desc (keeps arrays alive)."""
+
+    def __init__(self, spec):
+        self.spheres = np.ascontiguousarray(np.asarray(spec.spheres, np.float32).reshape(-1, 4))
+        self.sphere_mat = np.ascontiguousarray(np.asarray(spec.sphere_mat, np.int32).reshape(-1))
+        self.fixed = np.ascontiguousarray(np.asarray(spec.fixed_mats, np.float32).reshape(-1, 5))
+        if len(getattr(spec, "tris", ())) > 0:
+            raise JsoError("triangle meshes are not supported by this build")
+        d = jso_scene_desc()
+        d.width, d.height = spec.width, spec.height
+        d.cam_eye[:] = spec.cam_eye
+        d.cam_target[:] = spec.cam_target
+        d.cam_up[:] = spec.cam_up
+        d.vfov_deg = spec.vfov_deg
+        d.plane_enabled = int(spec.plane_enabled)
+        d.plane_mat = int(spec.plane_mat)
+        d.plane_extent[:] = spec.plane_extent
+        d.n_spheres = self.spheres.shape[0]
+        d.spheres = self.spheres.ctypes.data_as(ctypes.POINTER(ctypes.c_float))
+        d.sphere_mat = self.sphere_mat.ctypes.data_as(ctypes.POINTER(ctypes.c_int))
+        d.light_enabled = int(spec.light_enabled)
+        d.light_center[:] = spec.light_center
+        d.light_side = spec.light_side
+        d.light_Le[:] = spec.light_Le
+        d.env[:] = spec.env
+        d.depth, d.rr_start, d.rr_q = spec.depth, spec.rr_start, spec.rr_q
+        d.tex_w, d.tex_h, d.ch_mask = spec.tex_w, spec.tex_h, spec.ch_mask
+        d.fixed_default[:] = spec.fixed_default
+        d.n_fixed = self.fixed.shape[0]
+        d.fixed_mats = self.fixed.ctypes.data_as(ctypes.POINTER(ctypes.c_float))
+        self.desc = d
+
+
+def jso_load_scene(ctx, spec) -> int:
+    sd = SceneDesc(spec)
+    sid = ctypes.c_int(-1)
+    check(load().jso_load_scene(ctx, ctypes.byref(sd.desc), ctypes.byref(sid)), ctx,
+          "jso_load_scene")
+    return sid.value
+
+
+def jso_free_scene(ctx, sid: int) -> int:
+    return load().jso_free_scene(ctx, sid)
+
+
+def jso_scene_info(ctx, sid: int):
+    n, w, h = ctypes.c_size_t(), ctypes.c_int(), ctypes.c_int()
+    check(load().jso_scene_info(ctx, sid, ctypes.byref(n), ctypes.byref(w), ctypes.byref(h)),
+          ctx, "jso_scene_info")
+    return n.value, w.value, h.value
+
+
+def _host_f32(a):
+    return np.ascontiguousarray(np.asarray(a, np.float32).reshape(-1))
+
+
+def jso_set_params(ctx, sid: int, p, mem: int = JSO_MEM_HOST, n: Optional[int] = None) -> int:
+    if mem == JSO_MEM_HOST:
+        a = _host_f32(p)
+        return load().jso_set_params(ctx, sid, a.ctypes.data, a.size, mem)
+    return load().jso_set_params(ctx, sid, p, n, mem)
+
+
+def jso_get_params(ctx, sid: int, out=None, mem: int = JSO_MEM_HOST, n: Optional[int] = None):
+    if mem == JSO_MEM_HOST:
+        P = jso_scene_info(ctx, sid)[0]
+        out = np.zeros(P, np.float32) if out is None else out
+        check(load().jso_get_params(ctx, sid, out.ctypes.data, out.size, mem), ctx,
+              "jso_get_params")
+        return out
+    return load().jso_get_params(ctx, sid, out, n, mem)
+
+
+def jso_get_params_prev(ctx, sid: int):
+    P = jso_scene_info(ctx, sid)[0]
+    out = np.zeros(P, np.float32)
+    check(load().jso_get_params_prev(ctx, sid, out.ctypes.data, out.size, JSO_MEM_HOST), ctx,
+          "jso_get_params_prev")
+    return out
+
+
+def jso_set_target(ctx, sid: int, img, mem: int = JSO_MEM_HOST, n: Optional[int] = None) -> int:
+    if mem == JSO_MEM_HOST:
+        a = _host_f32(img)
+        return load().jso_set_target(ctx, sid, a.ctypes.data, a.size, mem)
+    return load().jso_set_target(ctx, sid, img, n, mem)
+
+
+def render_opts(flags: int = 0, crop=None, mask_ptr: int = 0):
+    o = jso_render_opts()
+    o.flags = flags
+    o.crop[:] = tuple(crop) if crop is not None else (0, 0, 0, 0)
+    o.pixel_mask = mask_ptr or None
+    return o
+
+
+def jso_render(ctx, sid, params_ptr, seed, iteration, tag, spp, opts, img_ptr) -> int:
+    return load().jso_render(ctx, sid, params_ptr, seed, iteration, tag, spp,
+                             ctypes.byref(opts) if opts is not None else None, img_ptr)
+
+
+def jso_render_bwd(ctx, sid, params_ptr, seed, iteration, tag, spp, dimg_ptr, opts,
+                   dparams_ptr) -> int:
+    return load().jso_render_bwd(ctx, sid, params_ptr, seed, iteration, tag, spp, dimg_ptr,
+                                 ctypes.byref(opts) if opts is not None else None, dparams_ptr)
+
+
+def jso_estimate_gradients(ctx, sid, seed, iteration, spp_prop, spp_fd, opts, F_ptr, dF_ptr,
+                           img_ptr=0, want_loss=False):
+    loss = ctypes.c_double(0.0)
+    rc = load().jso_estimate_gradients(ctx, sid, seed, iteration, spp_prop, spp_fd,
+                                       ctypes.byref(opts) if opts is not None else None,
+                                       F_ptr, dF_ptr or None, img_ptr or None,
+                                       ctypes.byref(loss) if want_loss else None)
+    return rc, loss.value
+
+
+def jso_meta_step(ctx, sid, F_ptr, dF_ptr, eta, beta_F, beta_D) -> int:
+    return load().jso_meta_step(ctx, sid, F_ptr, dF_ptr, eta, beta_F, beta_D)
+
+
+def jso_adam_step(ctx, sid, g_ptr, eta, beta1=0.9, beta2=0.999, eps=1e-8) -> int:
+    return load().jso_adam_step(ctx, sid, g_ptr, eta, beta1, beta2, eps)
+
+
+def step_opts(optimizer=JSO_OPT_META, eta=1e-3, beta_F=0.99, beta_D=0.9, spp_prop=2, spp_fd=1,
+              adam_beta1=0.9, adam_beta2=0.999, adam_eps=1e-8, adam_spp=64, seed=0, flags=0):
+    o = jso_step_opts()
+    o.optimizer, o.eta, o.beta_F, o.beta_D = optimizer, eta, beta_F, beta_D
+    o.spp_prop, o.spp_fd = spp_prop, spp_fd
+    o.adam_beta1, o.adam_beta2, o.adam_eps, o.adam_spp = adam_beta1, adam_beta2, adam_eps, adam_spp
+    o.seed, o.flags = seed, flags
+    return o
+
+
+def jso_grad_step(ctx, sids, opts, want_stats=False):
+    ids = (ctypes.c_int * len(sids))(*sids)
+    stats = (jso_step_stats * len(sids))() if want_stats else None
+    rc = load().jso_grad_step(ctx, ids, len(sids), ctypes.byref(opts), stats)
+    return rc, (list(stats) if want_stats else None)
+
+
+def jso_get_state(ctx, sid):
+    P = jso_scene_info(ctx, sid)[0]
+    bufs = dict(params=np.zeros(P, np.float32), params_prev=np.zeros(P, np.float32),
+                mean=np.zeros(P), var=np.zeros(P), alpha_prev=np.zeros(P), m2_F=np.zeros(P),
+                m2_D=np.zeros(P), adam_m=np.zeros(P, np.float32), adam_v=np.zeros(P, np.float32))
+    st = jso_state()
+    for k, v in bufs.items():
+        setattr(st, k, v.ctypes.data)
+    check(load().jso_get_state(ctx, sid, ctypes.byref(st)), ctx, "jso_get_state")
+    bufs.update(iteration=st.iteration, count_F=st.count_F, count_D=st.count_D,
+                adam_t=st.adam_t, step_norm2=st.step_norm2)
+    return bufs
+
+
+def jso_set_state(ctx, sid, state: dict) -> int:
+    st = jso_state()
+    keep = {}
+    for k in ("params", "params_prev", "adam_m", "adam_v"):
+        keep[k] = np.ascontiguousarray(np.asarray(state[k], np.float32))
+        setattr(st, k, keep[k].ctypes.data)
+    for k in ("mean", "var", "alpha_prev", "m2_F", "m2_D"):
+        keep[k] = np.ascontiguousarray(np.asarray(state[k], np.float64))
+        setattr(st, k, keep[k].ctypes.data)
+    st.iteration, st.count_F = state["iteration"], state["count_F"]
+    st.count_D, st.adam_t, st.step_norm2 = state["count_D"], state["adam_t"], state["step_norm2"]
+    return load().jso_set_state(ctx, sid, ctypes.byref(st))

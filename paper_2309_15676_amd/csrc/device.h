@@ -1,0 +1,567 @@
+// Device-side building blocks of the jso path tracer (gfx950, wave64).
+//
+// FP32 radiance arithmetic; each path's radiance ledger is kept in FP64 so
+// that the replayed adjoint can recover the radiance still to come after a
+// vertex (total minus collected) without cancellation.
+#pragma once
+
+#include <hip/hip_runtime.h>
+#include <stdint.h>
+
+#include "jso.h"
+
+namespace jso {
+
+constexpr float kPi = 3.14159265358979323846f;
+constexpr float kInvPi = 0.318309886183790671538f;
+constexpr float kTwoPi = 6.28318530717958647692f;
+constexpr float kRayEps = 1e-4f;     // ray origins move this far along the normal
+constexpr float kShadowEps = 1e-4f;  // shadow rays stop this short of the light
+constexpr float kRoughMin = 0.05f;   // roughness floor of the material model
+constexpr float kPSpec = 0.5f;       // probability of the specular lobe
+constexpr float kInf = __builtin_huge_valf();
+
+// ---------------------------------------------------------------------------
+// scene as seen by the kernels (passed by value as a kernel argument, so all
+// of it lives in the scalar-loaded kernarg segment)
+// ---------------------------------------------------------------------------
+struct DevScene {
+  int width, height;
+  float eye[3], cw[3], cu[3], cv[3];
+  float tan_half, aspect;
+  int plane_enabled, plane_mat;
+  float plane_x0, plane_x1, plane_z0, plane_z1;
+  int n_spheres;
+  float sph[JSO_MAX_SPHERES][4];
+  int sph_mat[JSO_MAX_SPHERES];
+  int light_enabled;
+  float lc[3], lside, lhalf, larea, Le[3];
+  float env[3];
+  int depth, rr_start;
+  float rr_q;
+  int tex_w, tex_h, n_ch;
+  int slot[5];          // slot of channel b inside a texel, -1 if fixed
+  float defaults[5];
+  int n_fixed;
+  float fixed[JSO_MAX_FIXED_MATS][5];
+};
+
+// ---------------------------------------------------------------------------
+// small vector type
+// ---------------------------------------------------------------------------
+struct V3 {
+  float x, y, z;
+};
+__device__ __forceinline__ V3 mk(float x, float y, float z) { return V3{x, y, z}; }
+__device__ __forceinline__ V3 operator+(V3 a, V3 b) { return mk(a.x + b.x, a.y + b.y, a.z + b.z); }
+__device__ __forceinline__ V3 operator-(V3 a, V3 b) { return mk(a.x - b.x, a.y - b.y, a.z - b.z); }
+__device__ __forceinline__ V3 operator*(V3 a, float s) { return mk(a.x * s, a.y * s, a.z * s); }
+__device__ __forceinline__ float dot(V3 a, V3 b) { return a.x * b.x + a.y * b.y + a.z * b.z; }
+__device__ __forceinline__ V3 cross(V3 a, V3 b) {
+  return mk(a.y * b.z - a.z * b.y, a.z * b.x - a.x * b.z, a.x * b.y - a.y * b.x);
+}
+__device__ __forceinline__ V3 normalize(V3 a) { return a * (1.0f / sqrtf(dot(a, a))); }
+__device__ __forceinline__ V3 ld3(const float* p) { return mk(p[0], p[1], p[2]); }
+
+// ---------------------------------------------------------------------------
+// counter-based random numbers
+// ---------------------------------------------------------------------------
+// Philox4x32-10, Salmon, Moraes, Dror, Shaw (SC'11): ten rounds of two
+// 32x32->64 multiplies with xor mixing; the key advances by the Weyl
+// constants between rounds.
+__host__ __device__ __forceinline__ uint32_t mulhi32(uint32_t a, uint32_t b) {
+  return (uint32_t)(((uint64_t)a * (uint64_t)b) >> 32);
+}
+
+__host__ __device__ __forceinline__ uint4 philox10(uint4 c, uint32_t k0, uint32_t k1) {
+#pragma unroll
+  for (int r = 0; r < 10; ++r) {
+    if (r != 0) {
+      k0 += 0x9E3779B9u;
+      k1 += 0xBB67AE85u;
+    }
+    const uint32_t a = c.x, b = c.z;
+    const uint32_t lo_a = 0xD2511F53u * a, hi_a = mulhi32(0xD2511F53u, a);
+    const uint32_t lo_b = 0xCD9E8D57u * b, hi_b = mulhi32(0xCD9E8D57u, b);
+    c = make_uint4(hi_b ^ c.y ^ k0, lo_b, hi_a ^ c.w ^ k1, lo_a);
+  }
+  return c;
+}
+
+// SplitMix64 output function for state x (Steele, Lea, Flood 2014).
+__host__ __device__ __forceinline__ uint64_t splitmix64(uint64_t x) {
+  uint64_t z = x + 0x9E3779B97F4A7C15ull;
+  z = (z ^ (z >> 30)) * 0xBF58476D1CE4E5B9ull;
+  z = (z ^ (z >> 27)) * 0x94D049BB133111EBull;
+  return z ^ (z >> 31);
+}
+
+__host__ __device__ __forceinline__ uint64_t stream_key(uint64_t seed, uint32_t it, uint32_t tag) {
+  return splitmix64(seed ^ splitmix64(((uint64_t)it << 8) | (uint64_t)tag));
+}
+
+// 24 high bits of a word as a float in [0, 1); exact in FP32 and FP64.
+__device__ __forceinline__ float u01(uint32_t x) { return (float)(x >> 8) * (1.0f / 16777216.0f); }
+
+struct Rng {
+  uint32_t k0, k1, pixel, sample;
+  __device__ __forceinline__ void draw(uint32_t bounce, uint32_t block, float u[4]) const {
+    uint4 r = philox10(make_uint4(pixel, sample, bounce, block), k0, k1);
+    u[0] = u01(r.x);
+    u[1] = u01(r.y);
+    u[2] = u01(r.z);
+    u[3] = u01(r.w);
+  }
+};
+
+// ---------------------------------------------------------------------------
+// intersection
+// ---------------------------------------------------------------------------
+enum : int { HIT_NONE = 0, HIT_PLANE = 1, HIT_SPHERE = 2, HIT_LIGHT = 3 };
+
+// Ray-sphere distance in FP32: discriminant from the squared distance of the
+// centre to the ray (no b^2 - c cancellation), roots via q and c/q.
+__device__ __forceinline__ float hit_sphere(const float* sp, V3 o, V3 d) {
+  const V3 oc = o - mk(sp[0], sp[1], sp[2]);
+  const float r2 = sp[3] * sp[3];
+  const float b = dot(oc, d);
+  const V3 f = oc - d * b;
+  const float disc = r2 - dot(f, f);
+  if (!(disc >= 0.0f)) return kInf;
+  const float s = sqrtf(disc);
+  const float q = -(b + copysignf(s, b));
+  if (q == 0.0f) return kInf;
+  const float c = dot(oc, oc) - r2;
+  const float t0 = c / q;
+  const float lo = fminf(t0, q), hi = fmaxf(t0, q);
+  if (lo > 0.0f) return lo;
+  if (hi > 0.0f) return hi;
+  return kInf;
+}
+
+struct Hit {
+  float t;
+  int kind, obj;
+};
+
+// Closest hit; candidates in id order plane < spheres < light, replaced only
+// by a strictly smaller distance, so equal distances keep the lower id.
+__device__ __forceinline__ Hit intersect(const DevScene& S, V3 o, V3 d) {
+  Hit h{kInf, HIT_NONE, -1};
+  if (S.plane_enabled && d.y < 0.0f && o.y > 0.0f) {
+    h.t = -o.y / d.y;
+    h.kind = HIT_PLANE;
+    h.obj = 0;
+  }
+  for (int k = 0; k < S.n_spheres; ++k) {
+    const float t = hit_sphere(S.sph[k], o, d);
+    if (t < h.t) {
+      h.t = t;
+      h.kind = HIT_SPHERE;
+      h.obj = k;
+    }
+  }
+  if (S.light_enabled && d.y > 0.0f && o.y < S.lc[1]) {
+    const float t = (S.lc[1] - o.y) / d.y;
+    const float dx = o.x + t * d.x - S.lc[0], dz = o.z + t * d.z - S.lc[2];
+    if (fabsf(dx) <= S.lhalf && fabsf(dz) <= S.lhalf && t < h.t) {
+      h.t = t;
+      h.kind = HIT_LIGHT;
+      h.obj = 0;
+    }
+  }
+  return h;
+}
+
+__device__ __forceinline__ bool occluded(const DevScene& S, V3 o, V3 d, float tmax) {
+  if (S.plane_enabled && d.y < 0.0f && o.y > 0.0f && -o.y / d.y < tmax) return true;
+  for (int k = 0; k < S.n_spheres; ++k)
+    if (hit_sphere(S.sph[k], o, d) < tmax) return true;
+  return false;
+}
+
+// ---------------------------------------------------------------------------
+// materials
+// ---------------------------------------------------------------------------
+struct Mat {
+  float c[3], m, r;
+};
+
+// Texel footprint of a parameterised-material lookup.  `global` = a 1x1
+// texture (one material for every point).
+struct Footprint {
+  int global;
+  int t00, t01, t10, t11;  // texel indices
+  float fx, fy;            // bilinear fractions
+};
+
+__device__ __forceinline__ void texel_weights(const Footprint& fp, float w[4]) {
+  w[0] = (1.0f - fp.fx) * (1.0f - fp.fy);
+  w[1] = fp.fx * (1.0f - fp.fy);
+  w[2] = (1.0f - fp.fx) * fp.fy;
+  w[3] = fp.fx * fp.fy;
+}
+
+// Bilinear, clamp-to-edge; texel centres at (i + 0.5) / size.
+__device__ __forceinline__ Footprint footprint_uv(const DevScene& S, float u, float v) {
+  Footprint fp;
+  fp.global = 0;
+  const float x = u * (float)S.tex_w - 0.5f, y = v * (float)S.tex_h - 0.5f;
+  const float x0 = floorf(x), y0 = floorf(y);
+  fp.fx = x - x0;
+  fp.fy = y - y0;
+  const int xi0 = (int)fminf(fmaxf(x0, 0.0f), (float)(S.tex_w - 1));
+  const int xi1 = (int)fminf(fmaxf(x0 + 1.0f, 0.0f), (float)(S.tex_w - 1));
+  const int yi0 = (int)fminf(fmaxf(y0, 0.0f), (float)(S.tex_h - 1));
+  const int yi1 = (int)fminf(fmaxf(y0 + 1.0f, 0.0f), (float)(S.tex_h - 1));
+  fp.t00 = yi0 * S.tex_w + xi0;
+  fp.t01 = yi0 * S.tex_w + xi1;
+  fp.t10 = yi1 * S.tex_w + xi0;
+  fp.t11 = yi1 * S.tex_w + xi1;
+  return fp;
+}
+
+// Material at a hit.  Returns true for the parameterised material (then fp is
+// its footprint); fixed materials return false.
+__device__ __forceinline__ bool material_at(const DevScene& S, const float* __restrict__ params,
+                                            int kind, int obj, V3 p, V3 n, Mat& M, Footprint& fp) {
+  const int mat = kind == HIT_PLANE ? S.plane_mat : S.sph_mat[obj];
+  if (mat >= 0) {
+    M.c[0] = S.fixed[mat][0];
+    M.c[1] = S.fixed[mat][1];
+    M.c[2] = S.fixed[mat][2];
+    M.m = S.fixed[mat][3];
+    M.r = S.fixed[mat][4];
+    return false;
+  }
+  float val[5];
+  if (S.tex_w == 1 && S.tex_h == 1) {
+    fp.global = 1;
+    fp.t00 = fp.t01 = fp.t10 = fp.t11 = 0;
+    fp.fx = fp.fy = 0.0f;
+#pragma unroll
+    for (int b = 0; b < 5; ++b) val[b] = S.slot[b] >= 0 ? params[S.slot[b]] : S.defaults[b];
+  } else {
+    float u, v;
+    if (kind == HIT_PLANE) {
+      u = (p.x - S.plane_x0) / (S.plane_x1 - S.plane_x0);
+      v = (p.z - S.plane_z0) / (S.plane_z1 - S.plane_z0);
+    } else {
+      u = 0.5f + atan2f(n.z, n.x) / kTwoPi;
+      v = atan2f(sqrtf(n.x * n.x + n.z * n.z), n.y) * kInvPi;
+    }
+    fp = footprint_uv(S, u, v);
+    float w[4];
+    texel_weights(fp, w);
+    const int nc = S.n_ch;
+#pragma unroll
+    for (int b = 0; b < 5; ++b) {
+      const int s = S.slot[b];
+      if (s < 0) {
+        val[b] = S.defaults[b];
+      } else {
+        val[b] = w[0] * params[fp.t00 * nc + s] + w[1] * params[fp.t01 * nc + s] +
+                 w[2] * params[fp.t10 * nc + s] + w[3] * params[fp.t11 * nc + s];
+      }
+    }
+  }
+  M.c[0] = val[0];
+  M.c[1] = val[1];
+  M.c[2] = val[2];
+  M.m = val[3];
+  M.r = val[4];
+  return true;
+}
+
+// ---------------------------------------------------------------------------
+// BSDF: (1-m) c/pi + D G F / (4 cos_o cos_i), GGX D with alpha = r^2 (via
+// sin^2 of the half-vector from a cross product), separable Smith G1,
+// Schlick F with F0 = 0.04 (1-m) + m c.  With kGrad, the partials of f w.r.t.
+// c (per channel), m and r.  pdf = density of sample_dir for wi.
+// ---------------------------------------------------------------------------
+struct Bsdf {
+  float f[3];
+  float pdf;
+  float dc[3], dm[3], dr[3];
+};
+
+__device__ __forceinline__ float sin2(V3 n, V3 v) {
+  const V3 c = cross(n, v);
+  return dot(c, c);
+}
+
+template <bool kGrad>
+__device__ __forceinline__ void eval_bsdf(const Mat& M, V3 n, V3 wo, V3 wi, uint32_t flags,
+                                          Bsdf& b) {
+  const float co = dot(n, wo), ci = dot(n, wi);
+  b.pdf = 0.0f;
+#pragma unroll
+  for (int k = 0; k < 3; ++k) {
+    b.f[k] = 0.0f;
+    if (kGrad) b.dc[k] = b.dm[k] = b.dr[k] = 0.0f;
+  }
+  if (!(co > 0.0f) || !(ci > 0.0f)) return;
+  if (flags & JSO_F_LAMBERT_ONLY) {
+#pragma unroll
+    for (int k = 0; k < 3; ++k) {
+      b.f[k] = M.c[k] / kPi;
+      if (kGrad) b.dc[k] = 1.0f / kPi;
+    }
+    b.pdf = ci / kPi;
+    return;
+  }
+  const float r = fmaxf(M.r, kRoughMin);
+  const float a = r * r, a2 = a * a;
+  const V3 h = normalize(wo + wi);
+  const float ch = dot(n, h), sh2 = sin2(n, h);
+  const float Q = ch * ch * a2 + sh2;
+  const float D = a2 / (kPi * Q * Q);
+  const float so2 = sin2(n, wo), si2 = sin2(n, wi);
+  const float qo = sqrtf(a2 * so2 + co * co), qi = sqrtf(a2 * si2 + ci * ci);
+  const float Go = 2.0f * co / (co + qo), Gi = 2.0f * ci / (ci + qi);
+  const float S = D * Go * Gi / (4.0f * co * ci);
+  const float dh = fminf(1.0f, dot(wi, h));
+  const float om = 1.0f - dh;
+  const float om2 = om * om;
+  const float w5 = om2 * om2 * om;
+  float dS_dr = 0.0f;
+  if (kGrad && M.r >= kRoughMin) {
+    const float dlog = 2.0f / a - 4.0f * ch * ch * a / Q - (a * so2 / qo) / (co + qo) -
+                       (a * si2 / qi) / (ci + qi);
+    dS_dr = S * dlog * 2.0f * r;
+  }
+#pragma unroll
+  for (int k = 0; k < 3; ++k) {
+    const float F0 = 0.04f * (1.0f - M.m) + M.m * M.c[k];
+    const float F = F0 + (1.0f - F0) * w5;
+    b.f[k] = (1.0f - M.m) * M.c[k] / kPi + S * F;
+    if (kGrad) {
+      b.dc[k] = (1.0f - M.m) / kPi + S * (1.0f - w5) * M.m;
+      b.dm[k] = -M.c[k] / kPi + S * (1.0f - w5) * (M.c[k] - 0.04f);
+      b.dr[k] = dS_dr * F;
+    }
+  }
+  if (flags & JSO_F_PARAM_INDEP) {
+    b.pdf = ci / kPi;
+  } else {
+    b.pdf = kPSpec * (D * ch / (4.0f * dh)) + (1.0f - kPSpec) * (ci / kPi);
+  }
+}
+
+// Orthonormal basis around n (Duff et al., JCGT 2017).
+__device__ __forceinline__ void onb(V3 n, V3& b1, V3& b2) {
+  const float sign = copysignf(1.0f, n.z);
+  const float a = -1.0f / (sign + n.z);
+  const float b = n.x * n.y * a;
+  b1 = mk(1.0f + sign * n.x * n.x * a, sign * b, -sign * n.x);
+  b2 = mk(b, sign + n.y * n.y * a, -n.y);
+}
+
+// u[0] < kPSpec picks the GGX lobe (half-vector after Walter et al. 2007,
+// reflected about it); otherwise a cosine-distributed direction.
+__device__ __forceinline__ V3 sample_dir(const Mat& M, V3 n, V3 wo, const float u[4],
+                                         uint32_t flags) {
+  V3 b1, b2;
+  onb(n, b1, b2);
+  const float phi = kTwoPi * u[2];
+  float sp, cp;
+  sincosf(phi, &sp, &cp);
+  const bool spec = !(flags & (JSO_F_LAMBERT_ONLY | JSO_F_PARAM_INDEP)) && u[0] < kPSpec;
+  if (!spec) {
+    const float rr = sqrtf(u[1]);
+    const float z = sqrtf(fmaxf(0.0f, 1.0f - u[1]));
+    return b1 * (rr * cp) + b2 * (rr * sp) + n * z;
+  }
+  const float r = fmaxf(M.r, kRoughMin);
+  const float a = r * r;
+  const float t2 = a * a * u[1] / (1.0f - u[1]);
+  const float ct = 1.0f / sqrtf(1.0f + t2);
+  const float st = sqrtf(t2) * ct;
+  const V3 h = b1 * (st * cp) + b2 * (st * sp) + n * ct;
+  return h * (2.0f * dot(wo, h)) - wo;
+}
+
+// ---------------------------------------------------------------------------
+// path state and one vertex of a path (forward, or replay with derivatives)
+// ---------------------------------------------------------------------------
+struct Path {
+  V3 o, d;
+  float beta[3];
+  float t;
+  int kind, obj;
+  int j;
+  bool alive;
+  double led[3];  // radiance collected so far (FP64 ledger)
+};
+
+// Material-attribute gradient of one vertex: g = d(adj . C)/d(R, G, B, metal, rough)
+// restricted to this vertex's BSDF evaluations.
+struct VertexGrad {
+  bool valid;
+  Footprint fp;
+  float g[5];
+};
+
+__device__ __forceinline__ void path_begin(const DevScene& S, const Rng& rng, int px, int py,
+                                           uint32_t flags, Path& P) {
+  float jx = 0.5f, jy = 0.5f;
+  if (!(flags & JSO_F_PIXEL_CENTER)) {
+    float u[4];
+    rng.draw(0, 0, u);
+    jx = u[0];
+    jy = u[1];
+  }
+  const float sx = (2.0f * ((float)px + jx) / (float)S.width - 1.0f) * S.tan_half * S.aspect;
+  const float sy = (1.0f - 2.0f * ((float)py + jy) / (float)S.height) * S.tan_half;
+  P.o = ld3(S.eye);
+  P.d = normalize(ld3(S.cw) + ld3(S.cu) * sx + ld3(S.cv) * sy);
+  P.beta[0] = P.beta[1] = P.beta[2] = 1.0f;
+  P.led[0] = P.led[1] = P.led[2] = 0.0;
+  P.j = 1;
+  const Hit h = intersect(S, P.o, P.d);
+  P.t = h.t;
+  P.kind = h.kind;
+  P.obj = h.obj;
+  P.alive = false;
+  if (h.kind == HIT_NONE) {
+#pragma unroll
+    for (int k = 0; k < 3; ++k) P.led[k] += (double)S.env[k];
+  } else if (h.kind == HIT_LIGHT) {
+#pragma unroll
+    for (int k = 0; k < 3; ++k) P.led[k] += (double)S.Le[k];
+  } else {
+    P.alive = true;
+  }
+}
+
+// Process the pending surface vertex of P.  Forward (kGrad = false): adds its
+// NEE and continuation-emission terms to the ledger and moves to the next
+// vertex.  Replay (kGrad = true): recomputes exactly the same terms and, with
+// C = the path's total radiance from the forward pass, forms
+//   NEE:           adj . beta K df(w_l)
+//   continuation:  adj . (R / f) df(w_i),   R = C - collected (after NEE)
+// which is the derivative of adj . C w.r.t. this vertex's material.
+template <bool kGrad>
+__device__ __forceinline__ void path_vertex(const DevScene& S, const float* __restrict__ params,
+                                            const Rng& rng, uint32_t flags, Path& P,
+                                            const float adj[3], const double C[3],
+                                            VertexGrad& vg) {
+  V3 p = P.o + P.d * P.t;
+  V3 n;
+  if (P.kind == HIT_PLANE) {
+    p.y = 0.0f;
+    n = mk(0.0f, 1.0f, 0.0f);
+  } else {
+    n = normalize(p - ld3(S.sph[P.obj]));
+  }
+  const V3 wo = mk(-P.d.x, -P.d.y, -P.d.z);
+  Mat M;
+  vg.valid = material_at(S, params, P.kind, P.obj, p, n, M, vg.fp);
+  if (kGrad) {
+#pragma unroll
+    for (int b = 0; b < 5; ++b) vg.g[b] = 0.0f;
+  }
+  const V3 po = p + n * kRayEps;
+  const int j = P.j;
+  float u[4];
+
+  // next-event estimation towards the square light
+  if (S.light_enabled && !(flags & JSO_F_NO_NEE)) {
+    rng.draw((uint32_t)j, 1, u);
+    const V3 lp = mk(S.lc[0] + (2.0f * u[0] - 1.0f) * S.lhalf, S.lc[1],
+                     S.lc[2] + (2.0f * u[1] - 1.0f) * S.lhalf);
+    const V3 dl = lp - p;
+    const float dist2 = dot(dl, dl), dist = sqrtf(dist2);
+    const V3 wl = dl * (1.0f / dist);
+    const float cos_l = wl.y, cos_s = dot(n, wl);
+    if (cos_l > 0.0f && cos_s > 0.0f && !occluded(S, po, wl, dist - kShadowEps)) {
+      Bsdf nb;
+      eval_bsdf<kGrad>(M, n, wo, wl, flags, nb);
+      const float pl = dist2 / (cos_l * S.larea);
+      const float wmis = pl / (pl + nb.pdf);
+#pragma unroll
+      for (int k = 0; k < 3; ++k) {
+        const float K = cos_s * S.Le[k] * wmis / pl;
+        const float term = P.beta[k] * nb.f[k] * K;
+        P.led[k] += (double)term;
+        if (kGrad) {
+          const float coef = adj[k] * P.beta[k] * K;
+          vg.g[k] += coef * nb.dc[k];
+          vg.g[3] += coef * nb.dm[k];
+          vg.g[4] += coef * nb.dr[k];
+        }
+      }
+    }
+  }
+
+  // continuation
+  rng.draw((uint32_t)j, 0, u);
+  const V3 wi = sample_dir(M, n, wo, u, flags);
+  const float ci = dot(n, wi);
+  bool go = ci > 0.0f;
+  Bsdf cb;
+  float q = 1.0f;
+  if (go) {
+    eval_bsdf<kGrad>(M, n, wo, wi, flags, cb);
+    go = cb.pdf > 0.0f;
+  }
+  if (go && S.rr_start > 0 && j >= S.rr_start) {
+    if (u[3] >= S.rr_q) go = false;
+    q = S.rr_q;
+  }
+  if (!go) {
+    P.alive = false;
+    return;
+  }
+  const float cw = ci / (cb.pdf * q);
+  if (kGrad) {
+#pragma unroll
+    for (int k = 0; k < 3; ++k) {
+      if (cb.f[k] > 0.0f) {
+        const float R = (float)(C[k] - P.led[k]);
+        const float coef = adj[k] * R / cb.f[k];
+        vg.g[k] += coef * cb.dc[k];
+        vg.g[3] += coef * cb.dm[k];
+        vg.g[4] += coef * cb.dr[k];
+      }
+    }
+  }
+#pragma unroll
+  for (int k = 0; k < 3; ++k) P.beta[k] *= cb.f[k] * cw;
+  P.o = po;
+  P.d = wi;
+  const Hit h = intersect(S, po, wi);
+  P.t = h.t;
+  P.kind = h.kind;
+  P.obj = h.obj;
+  if (h.kind == HIT_NONE) {
+#pragma unroll
+    for (int k = 0; k < 3; ++k) P.led[k] += (double)(P.beta[k] * S.env[k]);
+    P.alive = false;
+  } else if (h.kind == HIT_LIGHT) {
+    const float pl = h.t * h.t / (wi.y * S.larea);
+    const float wb = (flags & JSO_F_NO_NEE) ? 1.0f : cb.pdf / (cb.pdf + pl);
+#pragma unroll
+    for (int k = 0; k < 3; ++k) P.led[k] += (double)(P.beta[k] * (S.Le[k] * wb));
+    P.alive = false;
+  } else {
+    P.alive = j < S.depth;
+    P.j = j + 1;
+  }
+}
+
+// Forward pass of one path: its radiance (FP64 ledger total).
+__device__ __forceinline__ void path_radiance(const DevScene& S, const float* __restrict__ params,
+                                              const Rng& rng, int px, int py, uint32_t flags,
+                                              double C[3]) {
+  Path P;
+  path_begin(S, rng, px, py, flags, P);
+  const float zero[3] = {0.0f, 0.0f, 0.0f};
+  VertexGrad vg;
+  while (P.alive) path_vertex<false>(S, params, rng, flags, P, zero, C, vg);
+  C[0] = P.led[0];
+  C[1] = P.led[1];
+  C[2] = P.led[2];
+}
+
+}  // namespace jso

@@ -1,0 +1,410 @@
+// HIP kernels of the jso hot path (gfx950).
+//
+//   k_philox   - Philox4x32-10 block function over a counter array
+//   k_primal   - primal renders of one or more parameter sets; writes the
+//                L2 adjoint image 2 (I - T) / (3 W H) and the loss
+//   k_adjoint  - replayed adjoint: forward pass for each path's radiance, then
+//                a second pass over the same random numbers that forms the
+//                per-vertex material derivatives and scatters them; a
+//                finite-difference job replays the paths at pi_i and pi_{i-1}
+//                in lockstep and differences coinciding vertices in registers
+//   k_meta     - fused meta-estimator + stabilised step (FP64 state)
+//   k_adam     - Adam baseline
+#include <hip/hip_runtime.h>
+
+#include "device.h"
+#include "kernels.h"
+
+namespace jso {
+
+// ---------------------------------------------------------------------------
+__global__ void k_philox(const uint4* __restrict__ ctr, uint32_t n, uint32_t k0, uint32_t k1,
+                         uint4* __restrict__ out) {
+  const uint32_t i = blockIdx.x * blockDim.x + threadIdx.x;
+  if (i < n) out[i] = philox10(ctr[i], k0, k1);
+}
+
+// ---------------------------------------------------------------------------
+__device__ __forceinline__ uint32_t iteration_of(const KeyArgs& k) {
+  return k.iter_ptr ? *k.iter_ptr : k.iteration;
+}
+
+__device__ __forceinline__ Rng make_rng(uint64_t key, uint32_t pixel, uint32_t sample) {
+  Rng r;
+  r.k0 = (uint32_t)key;
+  r.k1 = (uint32_t)(key >> 32);
+  r.pixel = pixel;
+  r.sample = sample;
+  return r;
+}
+
+__device__ __forceinline__ double wave_sum(double v) {
+#pragma unroll
+  for (int off = 32; off > 0; off >>= 1) v += __shfl_xor(v, off, 64);
+  return v;
+}
+
+__device__ __forceinline__ float wave_sum(float v) {
+#pragma unroll
+  for (int off = 32; off > 0; off >>= 1) v += __shfl_xor(v, off, 64);
+  return v;
+}
+
+// blocks are 8 x 8 pixel tiles (one wave64)
+__device__ __forceinline__ bool tile_pixel(const Crop& c, int& px, int& py) {
+  px = c.x0 + (int)blockIdx.x * 8 + (int)(threadIdx.x & 7);
+  py = c.y0 + (int)blockIdx.y * 8 + (int)(threadIdx.x >> 3);
+  return px < c.x1 && py < c.y1;
+}
+
+// ---------------------------------------------------------------------------
+__global__ void __launch_bounds__(64) k_primal(DevScene S, PrimalArgs A) {
+  const PrimalJob& job = A.jobs[blockIdx.z];
+  int px, py;
+  const bool inside = tile_pixel(A.crop, px, py);
+  const uint32_t pix = (uint32_t)(py * S.width + px);
+  const bool active = inside && !(A.mask && A.mask[pix]);
+  double se = 0.0;
+  if (active) {
+    const uint64_t key = stream_key(A.key.seed, iteration_of(A.key), job.tag);
+    double acc[3] = {0.0, 0.0, 0.0};
+    for (int s = 0; s < job.spp; ++s) {
+      double C[3];
+      path_radiance(S, job.params, make_rng(key, pix, (uint32_t)s), px, py, A.flags, C);
+      acc[0] += C[0];
+      acc[1] += C[1];
+      acc[2] += C[2];
+    }
+    const double inv = 1.0 / (double)job.spp;
+#pragma unroll
+    for (int k = 0; k < 3; ++k) {
+      const float I = (float)(acc[k] * inv);
+      if (job.img) job.img[3 * (size_t)pix + k] = I;
+      if (job.delta) {
+        const float T = A.target[3 * (size_t)pix + k];
+        const float e = I - T;
+        job.delta[3 * (size_t)pix + k] = A.delta_scale * e;
+        se += (double)e * (double)e;
+      }
+    }
+  } else if (inside && job.delta) {
+#pragma unroll
+    for (int k = 0; k < 3; ++k) job.delta[3 * (size_t)pix + k] = 0.0f;
+  }
+  if (job.loss2) {
+    se = wave_sum(se);
+    if (threadIdx.x == 0 && se != 0.0)
+      unsafeAtomicAdd(&job.loss2[iteration_of(A.key) & 1u], se * A.loss_scale);
+  }
+}
+
+// ---------------------------------------------------------------------------
+// gradient scatter
+// ---------------------------------------------------------------------------
+__device__ __forceinline__ void scatter_texels(const DevScene& S, float* __restrict__ grad,
+                                               const Footprint& fp, const float g[5], float sign) {
+  float w[4];
+  texel_weights(fp, w);
+  const int t[4] = {fp.t00, fp.t01, fp.t10, fp.t11};
+  const int nc = S.n_ch;
+#pragma unroll
+  for (int b = 0; b < 5; ++b) {
+    const int s = S.slot[b];
+    if (s < 0) continue;
+    const float gb = sign * g[b];
+    if (gb == 0.0f) continue;
+#pragma unroll
+    for (int q = 0; q < 4; ++q) {
+      const float v = w[q] * gb;
+      if (v != 0.0f) unsafeAtomicAdd(grad + (size_t)t[q] * nc + s, v);
+    }
+  }
+}
+
+__device__ __forceinline__ bool same_footprint(const Footprint& a, const Footprint& b) {
+  return a.global == b.global && a.t00 == b.t00 && a.t01 == b.t01 && a.t10 == b.t10 &&
+         a.t11 == b.t11 && __float_as_uint(a.fx) == __float_as_uint(b.fx) &&
+         __float_as_uint(a.fy) == __float_as_uint(b.fy);
+}
+
+// Accumulates vertex gradients: global materials into per-lane registers
+// (reduced over the wave at the end), textured ones straight to memory.
+struct Sink {
+  float acc[5];
+  __device__ __forceinline__ void init() {
+#pragma unroll
+    for (int b = 0; b < 5; ++b) acc[b] = 0.0f;
+  }
+  __device__ __forceinline__ void add(const DevScene& S, float* grad, const VertexGrad& v,
+                                      float sign) {
+    if (!v.valid) return;
+    if (v.fp.global) {
+#pragma unroll
+      for (int b = 0; b < 5; ++b) acc[b] += sign * v.g[b];
+    } else {
+      scatter_texels(S, grad, v.fp, v.g, sign);
+    }
+  }
+  __device__ __forceinline__ void add_diff(const DevScene& S, float* grad, const VertexGrad& a,
+                                           const VertexGrad& b) {
+    if (a.valid && b.valid && same_footprint(a.fp, b.fp)) {
+      VertexGrad d = a;
+#pragma unroll
+      for (int q = 0; q < 5; ++q) d.g[q] = a.g[q] - b.g[q];
+      add(S, grad, d, 1.0f);
+    } else {
+      add(S, grad, a, 1.0f);
+      add(S, grad, b, -1.0f);
+    }
+  }
+  __device__ __forceinline__ void flush(const DevScene& S, float* grad) {
+    // every lane of the wave reaches this point
+#pragma unroll
+    for (int b = 0; b < 5; ++b) {
+      const int s = S.slot[b];
+      const float v = wave_sum(acc[b]);
+      if (s >= 0 && threadIdx.x == 0 && v != 0.0f) unsafeAtomicAdd(grad + s, v);
+    }
+  }
+};
+
+__global__ void __launch_bounds__(64) k_adjoint(DevScene S, AdjointArgs A) {
+  // find the job of this grid slice
+  int ji = 0;
+  while (ji + 1 < A.n_jobs && (int)blockIdx.z >= A.jobs[ji + 1].z0) ++ji;
+  const AdjointJob& job = A.jobs[ji];
+  const uint32_t sample = (uint32_t)(job.sample0 + ((int)blockIdx.z - job.z0));
+  int px, py;
+  const bool inside = tile_pixel(A.crop, px, py);
+  const uint32_t pix = (uint32_t)(py * S.width + px);
+  const bool active = inside && !(A.mask && A.mask[pix]);
+  Sink sink;
+  sink.init();
+  if (active) {
+    const uint64_t key = stream_key(A.key.seed, iteration_of(A.key), job.tag);
+    const Rng rng = make_rng(key, pix, sample);
+    float adj_a[3], adj_b[3];
+#pragma unroll
+    for (int k = 0; k < 3; ++k) {
+      adj_a[k] = job.delta[3 * (size_t)pix + k] * job.adj_scale;
+      adj_b[k] = job.params_b ? job.delta_b[3 * (size_t)pix + k] * job.adj_scale : 0.0f;
+    }
+    double Ca[3];
+    path_radiance(S, job.params, rng, px, py, A.flags, Ca);
+    if (!job.params_b) {
+      Path P;
+      path_begin(S, rng, px, py, A.flags, P);
+      VertexGrad vg;
+      while (P.alive) {
+        path_vertex<true>(S, job.params, rng, A.flags, P, adj_a, Ca, vg);
+        sink.add(S, job.grad, vg, job.sign);
+      }
+    } else {
+      double Cb[3];
+      path_radiance(S, job.params_b, rng, px, py, A.flags, Cb);
+      Path Pa, Pb;
+      path_begin(S, rng, px, py, A.flags, Pa);
+      path_begin(S, rng, px, py, A.flags, Pb);
+      while (Pa.alive || Pb.alive) {
+        VertexGrad va, vb;
+        va.valid = vb.valid = false;
+        if (Pa.alive) path_vertex<true>(S, job.params, rng, A.flags, Pa, adj_a, Ca, va);
+        if (Pb.alive) path_vertex<true>(S, job.params_b, rng, A.flags, Pb, adj_b, Cb, vb);
+        sink.add_diff(S, job.grad, va, vb);
+      }
+    }
+  }
+  sink.flush(S, job.grad);
+}
+
+// ---------------------------------------------------------------------------
+// fused meta-estimator + stabilised step
+// ---------------------------------------------------------------------------
+__global__ void __launch_bounds__(256) k_meta(MetaArgs A) {
+  __shared__ double s_coef[4];
+  __shared__ double s_red[4];
+  Ctl* ctl = A.ctl;
+  const uint32_t it = ctl->iteration;
+  if (threadIdx.x == 0) {
+    const double n2 = ctl->norm2[it & 1u];
+    const uint32_t cF = ctl->count_F + 1u;
+    const bool takeD = it >= 1u && n2 > 0.0;
+    const uint32_t cD = ctl->count_D + (takeD ? 1u : 0u);
+    s_coef[0] = (1.0 - A.beta_F) / (1.0 - pow(A.beta_F, (double)cF));
+    s_coef[1] = takeD ? (1.0 - A.beta_D) / (1.0 - pow(A.beta_D, (double)cD)) : 0.0;
+    s_coef[2] = takeD ? n2 : 0.0;
+    s_coef[3] = takeD ? 1.0 : 0.0;
+  }
+  __syncthreads();
+  const double wF = s_coef[0], wD = s_coef[1], n2 = s_coef[2];
+  const bool takeD = s_coef[3] != 0.0;
+  const double sq_n2 = takeD ? sqrt(n2) : 1.0;
+  double local = 0.0;
+  const size_t stride = (size_t)gridDim.x * blockDim.x;
+  for (size_t i = (size_t)blockIdx.x * blockDim.x + threadIdx.x; i < A.n; i += stride) {
+    const double F = (double)A.F[i];
+    const double dF = takeD ? (double)A.dF[i] : 0.0;
+    // Var[F] (Eq. 9; bias-corrected Moment2)
+    double m2F = A.m2F[i];
+    m2F = m2F + wF * (F * F - m2F);
+    // Var[dF] (Eq. 13-14)
+    double m2D = A.m2D[i];
+    double varD = 0.0;
+    if (takeD) {
+      const double x = dF / sq_n2;
+      m2D = m2D + wD * (x * x - m2D);
+      varD = m2D * n2;
+    }
+    // carry the previous estimate forward, weight (Eq. 8, 17), combine (Eq. 7, 15)
+    double mean = A.mean[i] + dF;
+    double var = A.var[i] + varD;
+    double a = m2F / (m2F + var + 1e-30);
+    a = fmin(a, 1.0 / (2.0 - A.alpha_prev[i]));
+    mean = a * mean + (1.0 - a) * F;
+    var = a * a * var + (1.0 - a) * (1.0 - a) * m2F;
+    // stabilised step (Eq. 21) and projection
+    const double step = -(double)A.eta * mean / (sqrt(var) + 1e-8);
+    const float p = A.params[i];
+    const int ch = (int)(i % (size_t)A.n_ch);
+    const float pn = fminf(fmaxf((float)((double)p + step), A.lo[ch]), A.hi[ch]);
+    const double dp = (double)pn - (double)p;
+    local += dp * dp;
+    A.m2F[i] = m2F;
+    A.m2D[i] = m2D;
+    A.mean[i] = mean;
+    A.var[i] = var;
+    A.alpha_prev[i] = a;
+    A.params_prev[i] = p;
+    A.params[i] = pn;
+    if (A.zero_grads) {
+      A.F[i] = 0.0f;
+      A.dF[i] = 0.0f;
+    }
+  }
+  // ||pi_{i+1} - pi_i||^2 for the next iteration
+  local = wave_sum(local);
+  const int lane = threadIdx.x & 63, wv = threadIdx.x >> 6;
+  if (lane == 0) s_red[wv] = local;
+  __syncthreads();
+  if (threadIdx.x == 0) {
+    double tot = 0.0;
+    for (int w = 0; w < (int)(blockDim.x >> 6); ++w) tot += s_red[w];
+    if (tot != 0.0) unsafeAtomicAdd(&ctl->norm2[(it + 1u) & 1u], tot);
+    __threadfence();
+    const uint32_t done = atomicAdd(&ctl->blocks_done, 1u);
+    if (done == gridDim.x - 1u) {
+      // last block: all blocks have read this iteration's inputs
+      __threadfence();
+      ctl->count_F = ctl->count_F + 1u;
+      if (takeD) ctl->count_D = ctl->count_D + 1u;
+      ctl->norm2[it & 1u] = 0.0;
+      ctl->loss[(it + 1u) & 1u] = 0.0;
+      ctl->iteration = it + 1u;
+      ctl->blocks_done = 0u;
+      __threadfence();
+    }
+  }
+}
+
+// ---------------------------------------------------------------------------
+__global__ void __launch_bounds__(256) k_adam(AdamArgs A) {
+  Ctl* ctl = A.ctl;
+  const uint32_t t = ctl->adam_t + 1u;
+  const float bc1 = (float)(1.0 - pow((double)A.beta1, (double)t));
+  const float bc2 = (float)(1.0 - pow((double)A.beta2, (double)t));
+  const size_t stride = (size_t)gridDim.x * blockDim.x;
+  for (size_t i = (size_t)blockIdx.x * blockDim.x + threadIdx.x; i < A.n; i += stride) {
+    const float g = A.g[i];
+    const float m = A.beta1 * A.m[i] + (1.0f - A.beta1) * g;
+    const float v = A.beta2 * A.v[i] + (1.0f - A.beta2) * g * g;
+    A.m[i] = m;
+    A.v[i] = v;
+    const float mh = m / bc1, vh = v / bc2;
+    const float p = A.params[i];
+    const int ch = (int)(i % (size_t)A.n_ch);
+    const float pn = fminf(fmaxf(p - A.eta * mh / (sqrtf(vh) + A.eps), A.lo[ch]), A.hi[ch]);
+    A.params_prev[i] = p;
+    A.params[i] = pn;
+    if (A.zero_grads) A.g[i] = 0.0f;
+  }
+  if (threadIdx.x == 0) {
+    __threadfence();
+    const uint32_t done = atomicAdd(&ctl->blocks_done, 1u);
+    if (done == gridDim.x - 1u) {
+      __threadfence();
+      ctl->adam_t = t;
+      ctl->iteration = ctl->iteration + 1u;
+      ctl->loss[ctl->iteration & 1u] = 0.0;
+      ctl->blocks_done = 0u;
+      __threadfence();
+    }
+  }
+}
+
+__global__ void k_fill_f64(double* p, size_t n, double v) {
+  const size_t i = (size_t)blockIdx.x * blockDim.x + threadIdx.x;
+  if (i < n) p[i] = v;
+}
+
+__global__ void k_fill_f32(float* p, size_t n, float v) {
+  const size_t i = (size_t)blockIdx.x * blockDim.x + threadIdx.x;
+  if (i < n) p[i] = v;
+}
+
+// ---------------------------------------------------------------------------
+// launchers
+// ---------------------------------------------------------------------------
+static inline unsigned cdiv(size_t a, size_t b) { return (unsigned)((a + b - 1) / b); }
+
+hipError_t launch_philox(const uint32_t* ctr, size_t n, uint64_t key, uint32_t* out,
+                         hipStream_t st) {
+  if (n == 0) return hipSuccess;
+  hipLaunchKernelGGL(k_philox, dim3(cdiv(n, 256)), dim3(256), 0, st,
+                     reinterpret_cast<const uint4*>(ctr), (uint32_t)n, (uint32_t)key,
+                     (uint32_t)(key >> 32), reinterpret_cast<uint4*>(out));
+  return hipGetLastError();
+}
+
+hipError_t launch_primal(const DevScene& S, const PrimalArgs& A, int n_jobs, hipStream_t st) {
+  const int w = A.crop.x1 - A.crop.x0, h = A.crop.y1 - A.crop.y0;
+  if (w <= 0 || h <= 0 || n_jobs <= 0) return hipSuccess;
+  hipLaunchKernelGGL(k_primal, dim3(cdiv(w, 8), cdiv(h, 8), n_jobs), dim3(64), 0, st, S, A);
+  return hipGetLastError();
+}
+
+hipError_t launch_adjoint(const DevScene& S, const AdjointArgs& A, int n_slices, hipStream_t st) {
+  const int w = A.crop.x1 - A.crop.x0, h = A.crop.y1 - A.crop.y0;
+  if (w <= 0 || h <= 0 || n_slices <= 0) return hipSuccess;
+  hipLaunchKernelGGL(k_adjoint, dim3(cdiv(w, 8), cdiv(h, 8), n_slices), dim3(64), 0, st, S, A);
+  return hipGetLastError();
+}
+
+static unsigned elementwise_grid(size_t n) {
+  // at most 8 blocks per CU of 256 CUs; grid-stride beyond that
+  const size_t want = (n + 255) / 256;
+  return (unsigned)(want < 2048 ? (want ? want : 1) : 2048);
+}
+
+hipError_t launch_meta(const MetaArgs& A, hipStream_t st) {
+  hipLaunchKernelGGL(k_meta, dim3(elementwise_grid(A.n)), dim3(256), 0, st, A);
+  return hipGetLastError();
+}
+
+hipError_t launch_adam(const AdamArgs& A, hipStream_t st) {
+  hipLaunchKernelGGL(k_adam, dim3(elementwise_grid(A.n)), dim3(256), 0, st, A);
+  return hipGetLastError();
+}
+
+hipError_t launch_fill_f64(double* p, size_t n, double v, hipStream_t st) {
+  if (!n) return hipSuccess;
+  hipLaunchKernelGGL(k_fill_f64, dim3(cdiv(n, 256)), dim3(256), 0, st, p, n, v);
+  return hipGetLastError();
+}
+
+hipError_t launch_fill_f32(float* p, size_t n, float v, hipStream_t st) {
+  if (!n) return hipSuccess;
+  hipLaunchKernelGGL(k_fill_f32, dim3(cdiv(n, 256)), dim3(256), 0, st, p, n, v);
+  return hipGetLastError();
+}
+
+}  // namespace jso

@@ -172,11 +172,12 @@ def place_spheres(n: int, g: np.random.Generator, rmin=0.3, rmax=1.0,
 
 
 def scene_textured(width: int = 512, height: int = 512, tex: int = 256, seed: int = 0,
-                   n_spheres: int = 8, depth: int = 6, rr_start: int = 3) -> SceneSpec:
+                   n_spheres: int = 8, depth: int = 6, rr_start: int = 3,
+                   rmin: float = 0.3, rmax: float = 1.0) -> SceneSpec:
     """Plane + n spheres (radii U[0.3,1], seeded non-overlapping positions); all
     objects share one texture of base colour RGB + roughness (metalness fixed 0)."""
     g = rng(seed)
-    sph = place_spheres(n_spheres, g)
+    sph = place_spheres(n_spheres, g, rmin, rmax)
     return SceneSpec(width=width, height=height, spheres=sph,
                      sphere_mat=np.full((n_spheres,), MAT_PARAM, np.int32),
                      plane_mat=MAT_PARAM, depth=depth, rr_start=rr_start,

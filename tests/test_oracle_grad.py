@@ -34,7 +34,7 @@ def _scenes():
 def test_adjoint_matches_central_differences(which, flags):
     name, spec, p = _scenes()[which]
     dimg = I.target_image_synthetic(spec, 11).astype(np.float64) - 0.7
-    g, ga, _ = O.render_bwd(spec, p, dimg, 7, 3, O.TAG_ADJ_PROP, 2, flags)
+    g, ga, _, _ = O.render_bwd(spec, p, dimg, 7, 3, O.TAG_ADJ_PROP, 2, flags)
     assert np.count_nonzero(g) > 0
     idx = np.arange(len(p)) if len(p) <= 16 else \
         np.random.Generator(np.random.PCG64(0)).choice(len(p), 24, replace=False)
@@ -57,7 +57,7 @@ def test_adjoint_unbiased_under_importance_sampling():
     K, spp, h = 48, 8, 2e-3
     adj, fd = [], []
     for k in range(K):
-        g, _, _ = O.render_bwd(spec, p, dimg, 100 + k, 0, O.TAG_EVAL, spp)
+        g, _, _, _ = O.render_bwd(spec, p, dimg, 100 + k, 0, O.TAG_EVAL, spp)
         adj.append(g)
         row = []
         for i in range(len(p)):

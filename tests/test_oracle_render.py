@@ -28,16 +28,17 @@ def test_lambert_sphere_radiance_and_gradient_closed_form(rho):
     # weight f cos / p = rho, so I = rho * L on the sphere and L off it; the
     # L2-loss gradient w.r.t. rho is sum_{p on sphere} 2 (rho - T_p) L / (3 N)
     s = I.scene_white_furnace(20, 16)
-    s.env = (0.7, 0.7, 0.7)
+    s.env = (0.75, 0.75, 0.75)
     p = np.array(list(rho) + [0.0, 0.5])
     img, _ = O.render(s, p, 5, 0, O.TAG_EVAL, 1, flags=O.LAMBERT_ONLY | O.NO_NEE)
-    on = np.any(img != 0.7, axis=-1)
+    on = np.any(img != 0.75, axis=-1)
     assert on.sum() > 20
-    np.testing.assert_allclose(img[on], np.tile(0.7 * np.array(rho), (on.sum(), 1)), rtol=1e-14)
+    np.testing.assert_allclose(img[on], np.tile(0.75 * np.array(rho), (on.sum(), 1)), rtol=1e-14)
     T = I.target_image_synthetic(s, 9).astype(np.float64)
-    g, _, _, _ = O.grad(s, p, T, 5, 0, O.TAG_EVAL, O.TAG_EVAL, 1, flags=O.LAMBERT_ONLY | O.NO_NEE)
+    g, _, _, _, _ = O.grad(s, p, T, 5, 0, O.TAG_EVAL, O.TAG_EVAL, 1,
+                           flags=O.LAMBERT_ONLY | O.NO_NEE)
     N = s.n_pixels
-    expect = [np.sum(2 * (0.7 * rho[k] - T[on][:, k]) * 0.7 / (3 * N)) for k in range(3)]
+    expect = [np.sum(2 * (0.75 * rho[k] - T[on][:, k]) * 0.75 / (3 * N)) for k in range(3)]
     np.testing.assert_allclose(g[:3], expect, rtol=1e-12, atol=1e-15)
     assert g[3] == 0 and g[4] == 0
 
@@ -119,7 +120,7 @@ def _hemisphere_quadrature(fn, n_theta=400, n_phi=800):
 
 @pytest.mark.parametrize("mat,theta", [((0.9, 0.6, 0.2, 0.0, 0.6), 0.3),
                                        ((0.8, 0.8, 0.8, 1.0, 0.35), 0.9),
-                                       ((0.3, 0.5, 0.7, 0.5, 0.8), 1.2)])
+                                       ((0.3, 0.5, 0.75, 0.5, 0.8), 1.2)])
 def test_directional_albedo_sampling_matches_quadrature(mat, theta):
     # environment 1 above a plane of this material, depth 1, no light: the pixel
     # value is the directional albedo integral f(wo, wi) cos dwi, which the
