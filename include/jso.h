@@ -241,6 +241,23 @@ int jso_adam_step(jso_ctx* ctx, int scene_id, const float* g, float eta, float b
 int jso_grad_step(jso_ctx* ctx, const int* scene_ids, int n, const jso_step_opts* opts,
                   jso_step_stats* stats);
 
+/* ---- kernel timing --------------------------------------------------------------- */
+
+/* Kernel classes reported by jso_get_kernel_time */
+#define JSO_K_PRIMAL 0  /* primal renders and adjoint images            */
+#define JSO_K_ADJOINT 1 /* replayed adjoint (proportional + FD pairs)    */
+#define JSO_K_META 2    /* fused meta-estimator step                     */
+#define JSO_K_ADAM 3    /* Adam step                                     */
+#define JSO_K_COUNT 4
+
+/* Enable (1) or disable (0) HIP-event timing of every kernel this context
+ * launches (events are recorded on the context's stream around each launch). */
+int jso_set_timing(jso_ctx* ctx, int enable);
+/* Device time (ms) summed over the launches of one kernel class since timing
+ * was enabled or last reset, and their number.  Waits for the recorded
+ * events.  reset != 0 clears the totals afterwards. */
+int jso_get_kernel_time(jso_ctx* ctx, int kernel, double* ms, uint64_t* launches, int reset);
+
 /* ---- checkpoint ---------------------------------------------------------------- */
 int jso_get_state(jso_ctx* ctx, int scene_id, jso_state* st);
 int jso_set_state(jso_ctx* ctx, int scene_id, const jso_state* st);

@@ -83,6 +83,8 @@ def lib():
         L.orc_stream_key.argtypes = [u64, u32, u32]
         L.orc_philox4x32_10.argtypes = [d, d, d]
         L.orc_set_jitter_offset.argtypes = [ctypes.c_double, ctypes.c_double]
+        L.orc_reset_stats.argtypes = []
+        L.orc_get_stats.argtypes = [d]
         L.orc_bsdf.argtypes = [d, d, d, d, i, d]
         L.orc_bsdf_many.argtypes = [i, d, d, d, d, i, d]
         L.orc_render.argtypes = [d, d, u64, u32, u32, i, i, d, d, d, i]
@@ -168,6 +170,17 @@ def philox4x32_10(ctr: Sequence[int], key: Sequence[int]) -> Tuple[int, int, int
     o = np.zeros(4, np.uint32)
     lib().orc_philox4x32_10(_ptr(c), _ptr(k), _ptr(o))
     return tuple(int(v) for v in o)
+
+
+def reset_stats() -> None:
+    lib().orc_reset_stats()
+
+
+def get_stats() -> dict:
+    """Paths traced, their surface vertices and parameterised-material vertices."""
+    out = np.zeros(3, np.uint64)
+    lib().orc_get_stats(_ptr(out))
+    return dict(paths=int(out[0]), vertices=int(out[1]), param_vertices=int(out[2]))
 
 
 def bsdf(mat, n, wo, wi, flags: int = 0) -> np.ndarray:

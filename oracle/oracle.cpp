@@ -7,6 +7,7 @@
 #include "oracle.h"
 
 #include <algorithm>
+#include <atomic>
 #include <cmath>
 #include <cstring>
 #include <limits>
@@ -482,11 +483,16 @@ struct PathResult {
 // amplifies such rounding (its conditioning).  Zero in normal use.
 double g_jitter_dx = 0.0, g_jitter_dy = 0.0;
 
+// Workload statistics: paths traced, surface vertices, vertices on the
+// parameterised material.
+std::atomic<uint64_t> g_paths{0}, g_vertices{0}, g_param_vertices{0};
+
 void trace(const Scene& sc, const double* params, const PathRng& rng, int px, int py, int flags,
            bool record, PathResult& out) {
   const orc_scene* s = sc.s;
   Margin mg;
   double u[4];
+  g_paths.fetch_add(1, std::memory_order_relaxed);
   double jx = 0.5, jy = 0.5;
   if (!(flags & ORC_PIXEL_CENTER)) {
     rng.draw(0, 0, u);
@@ -511,6 +517,8 @@ void trace(const Scene& sc, const double* params, const PathRng& rng, int px, in
   for (int j = 1; j <= s->depth; ++j) {
     V3 p = hit.p, n = hit.n, wo = ray.d * -1.0;
     Material mat = material_at(sc, hit, params, mg);
+    g_vertices.fetch_add(1, std::memory_order_relaxed);
+    if (mat.param) g_param_vertices.fetch_add(1, std::memory_order_relaxed);
     TapeVertex tv;
     for (int k = 0; k < 3; ++k) tv.beta[k] = beta[k];
     tv.param = mat.param;
@@ -686,6 +694,18 @@ int check(const orc_scene* s) {
 extern "C" {
 
 uint64_t orc_splitmix64(uint64_t x) { return splitmix64(x); }
+
+void orc_reset_stats(void) {
+  g_paths = 0;
+  g_vertices = 0;
+  g_param_vertices = 0;
+}
+
+void orc_get_stats(uint64_t out[3]) {
+  out[0] = g_paths.load();
+  out[1] = g_vertices.load();
+  out[2] = g_param_vertices.load();
+}
 
 void orc_set_jitter_offset(double dx, double dy) {
   g_jitter_dx = dx;

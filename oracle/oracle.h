@@ -60,6 +60,10 @@ uint64_t orc_splitmix64(uint64_t x);
 /* Test hook: offset (pixels) added to every primary sample position; used to
  * measure each path's sensitivity to single-precision rounding.  Default 0. */
 void orc_set_jitter_offset(double dx, double dy);
+/* Workload statistics accumulated over all traces since the last reset:
+ * out = {paths, surface vertices, vertices on the parameterised material}. */
+void orc_reset_stats(void);
+void orc_get_stats(uint64_t out[3]);
 void orc_philox4x32_10(const uint32_t ctr[4], const uint32_t key[2], uint32_t out[4]);
 uint64_t orc_stream_key(uint64_t seed, uint32_t iteration, uint32_t tag);
 

@@ -33,7 +33,9 @@ EXPORTED = [
     "jso_scene_info", "jso_set_params", "jso_get_params", "jso_get_params_prev",
     "jso_set_target", "jso_render", "jso_render_bwd", "jso_estimate_gradients",
     "jso_meta_step", "jso_adam_step", "jso_grad_step", "jso_get_state", "jso_set_state",
+    "jso_set_timing", "jso_get_kernel_time",
 ]
+JSO_K_PRIMAL, JSO_K_ADJOINT, JSO_K_META, JSO_K_ADAM = 0, 1, 2, 3
 
 
 class JsoError(RuntimeError):
@@ -130,6 +132,8 @@ def load() -> ctypes.CDLL:
         "jso_grad_step": (I, [P, P, I, P, P]),
         "jso_get_state": (I, [P, I, P]),
         "jso_set_state": (I, [P, I, P]),
+        "jso_set_timing": (I, [P, I]),
+        "jso_get_kernel_time": (I, [P, I, ctypes.POINTER(D), ctypes.POINTER(U64), I]),
     }
     for name, (res, args) in sig.items():
         fn = getattr(L, name)
@@ -352,3 +356,15 @@ def jso_set_state(ctx, sid, state: dict) -> int:
     st.iteration, st.count_F = state["iteration"], state["count_F"]
     st.count_D, st.adam_t, st.step_norm2 = state["count_D"], state["adam_t"], state["step_norm2"]
     return load().jso_set_state(ctx, sid, ctypes.byref(st))
+
+
+def jso_set_timing(ctx, enable: bool) -> int:
+    return load().jso_set_timing(ctx, 1 if enable else 0)
+
+
+def jso_get_kernel_time(ctx, kernel: int, reset: bool = False):
+    """(total ms, launches) of one kernel class since timing was enabled/reset."""
+    ms, n = ctypes.c_double(0.0), ctypes.c_uint64(0)
+    check(load().jso_get_kernel_time(ctx, kernel, ctypes.byref(ms), ctypes.byref(n),
+                                     1 if reset else 0), ctx, "jso_get_kernel_time")
+    return ms.value, n.value

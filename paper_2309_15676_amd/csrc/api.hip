@@ -31,10 +31,54 @@ struct SceneGPU {
   float *adam_m = nullptr, *adam_v = nullptr;
   Ctl* ctl = nullptr;
   double* scratch_loss = nullptr;  // 2 slots for stand-alone estimator calls
+  DevScene* d_scene = nullptr;     // device copy of `dev` read by the kernels
   uint32_t host_iter = 0;          // mirror of ctl->iteration
 };
 
 }  // namespace
+
+// HIP-event timing of kernel launches, per kernel class.
+struct KernelTimer {
+  bool enabled = false;
+  std::vector<hipEvent_t> pool;                                   // free events
+  std::vector<std::pair<hipEvent_t, hipEvent_t>> pending[JSO_K_COUNT];
+  double ms[JSO_K_COUNT] = {0, 0, 0, 0};
+  uint64_t launches[JSO_K_COUNT] = {0, 0, 0, 0};
+
+  hipEvent_t get() {
+    hipEvent_t e = nullptr;
+    if (!pool.empty()) {
+      e = pool.back();
+      pool.pop_back();
+    } else if (hipEventCreate(&e) != hipSuccess) {
+      e = nullptr;
+    }
+    return e;
+  }
+  // fold finished intervals into the totals (waits for them)
+  hipError_t collect() {
+    for (int k = 0; k < JSO_K_COUNT; ++k) {
+      for (auto& pr : pending[k]) {
+        hipError_t e = hipEventSynchronize(pr.second);
+        if (e != hipSuccess) return e;
+        float t = 0.0f;
+        e = hipEventElapsedTime(&t, pr.first, pr.second);
+        if (e != hipSuccess) return e;
+        ms[k] += t;
+        launches[k]++;
+        pool.push_back(pr.first);
+        pool.push_back(pr.second);
+      }
+      pending[k].clear();
+    }
+    return hipSuccess;
+  }
+  void destroy() {
+    (void)collect();
+    for (hipEvent_t e : pool) (void)hipEventDestroy(e);
+    pool.clear();
+  }
+};
 
 struct jso_ctx {
   int device = 0;
@@ -42,6 +86,7 @@ struct jso_ctx {
   uint32_t debug_flags = 0;
   std::string err;
   std::vector<std::unique_ptr<SceneGPU>> scenes;
+  KernelTimer timer;
 };
 
 namespace {
@@ -64,6 +109,22 @@ int fail(jso_ctx* c, int code, const char* fmt, ...) {
                   #expr, hipGetErrorString(e_), __func__);                             \
   } while (0)
 
+// Launch `expr` (returning hipError_t) bracketed by timing events when enabled.
+#define TIMED_LAUNCH(ctx, kind, expr)                                               \
+  do {                                                                              \
+    hipEvent_t t0_ = nullptr, t1_ = nullptr;                                        \
+    if ((ctx)->timer.enabled) {                                                     \
+      t0_ = (ctx)->timer.get();                                                     \
+      t1_ = (ctx)->timer.get();                                                     \
+      if (t0_) HIP_TRY(ctx, hipEventRecord(t0_, (ctx)->stream));                    \
+    }                                                                               \
+    HIP_TRY(ctx, expr);                                                             \
+    if (t0_ && t1_) {                                                               \
+      HIP_TRY(ctx, hipEventRecord(t1_, (ctx)->stream));                             \
+      (ctx)->timer.pending[kind].push_back({t0_, t1_});                             \
+    }                                                                               \
+  } while (0)
+
 struct DeviceGuard {
   int prev = -1;
   explicit DeviceGuard(int dev) {
@@ -83,7 +144,8 @@ SceneGPU* get_scene(jso_ctx* c, int id) {
 void free_scene_buffers(SceneGPU* s) {
   void* bufs[] = {s->params, s->params_prev, s->target, s->F,      s->dF,
                   s->delta,  s->mean,        s->var,    s->alpha_prev, s->m2F,
-                  s->m2D,    s->adam_m,      s->adam_v, s->ctl,    s->scratch_loss};
+                  s->m2D,    s->adam_m,      s->adam_v, s->ctl,    s->scratch_loss,
+                  s->d_scene};
   for (void* b : bufs)
     if (b) (void)hipFree(b);
 }
@@ -256,7 +318,7 @@ int queue_estimators(jso_ctx* c, SceneGPU* s, uint64_t seed, uint32_t iteration,
   pa.delta_scale = (float)(2.0 / (3.0 * (double)s->npix));
   pa.loss_scale = 1.0 / (3.0 * (double)s->npix);
   pa.flags = flags;
-  HIP_TRY(c, launch_primal(s->dev, pa, np, c->stream));
+  TIMED_LAUNCH(c, JSO_K_PRIMAL, launch_primal(s->d_scene, pa, np, c->stream));
 
   AdjointArgs aa{};
   int nj = 0, z = 0;
@@ -273,7 +335,7 @@ int queue_estimators(jso_ctx* c, SceneGPU* s, uint64_t seed, uint32_t iteration,
   aa.crop = crop;
   aa.mask = mask;
   aa.flags = flags;
-  HIP_TRY(c, launch_adjoint(s->dev, aa, z, c->stream));
+  TIMED_LAUNCH(c, JSO_K_ADJOINT, launch_adjoint(s->d_scene, aa, z, c->stream));
   return JSO_OK;
 }
 
@@ -353,6 +415,7 @@ int jso_destroy(jso_ctx* c) {
   (void)hipStreamSynchronize(c->stream);
   for (auto& s : c->scenes)
     if (s) free_scene_buffers(s.get());
+  c->timer.destroy();
   delete c;
   return JSO_OK;
 }
@@ -419,6 +482,7 @@ int jso_load_scene(jso_ctx* c, const jso_scene_desc* d, int* scene_id) {
   A(dalloc(&s->adam_v, P));
   A(dalloc(&s->ctl, 1));
   A(dalloc(&s->scratch_loss, 2));
+  A(dalloc(&s->d_scene, 1));
   if (e != hipSuccess) {
     free_scene_buffers(s.get());
     return fail(c, e == hipErrorOutOfMemory ? JSO_E_OOM : JSO_E_HIP, "scene allocation: %s",
@@ -427,7 +491,8 @@ int jso_load_scene(jso_ctx* c, const jso_scene_desc* d, int* scene_id) {
   // initial parameters: 0.5 for every channel (roughness within its box)
   rc = JSO_OK;
   if (launch_fill_f32(s->params, P, 0.5f, c->stream) != hipSuccess ||
-      hipMemsetAsync(s->target, 0, n3 * sizeof(float), c->stream) != hipSuccess) {
+      hipMemsetAsync(s->target, 0, n3 * sizeof(float), c->stream) != hipSuccess ||
+      hipMemcpy(s->d_scene, &s->dev, sizeof(DevScene), hipMemcpyHostToDevice) != hipSuccess) {
     free_scene_buffers(s.get());
     return fail(c, JSO_E_HIP, "scene initialisation failed");
   }
@@ -513,7 +578,7 @@ int jso_render(jso_ctx* c, int id, const float* params, uint64_t seed, uint32_t 
   pa.mask = opts ? opts->pixel_mask : nullptr;
   pa.target = s->target;
   pa.flags = c->debug_flags | (opts ? opts->flags : 0u);
-  HIP_TRY(c, launch_primal(s->dev, pa, 1, c->stream));
+  TIMED_LAUNCH(c, JSO_K_PRIMAL, launch_primal(s->d_scene, pa, 1, c->stream));
   return JSO_OK;
 }
 
@@ -533,7 +598,7 @@ int jso_render_bwd(jso_ctx* c, int id, const float* params, uint64_t seed, uint3
   aa.crop = crop_of(s, opts);
   aa.mask = opts ? opts->pixel_mask : nullptr;
   aa.flags = c->debug_flags | (opts ? opts->flags : 0u);
-  HIP_TRY(c, launch_adjoint(s->dev, aa, spp, c->stream));
+  TIMED_LAUNCH(c, JSO_K_ADJOINT, launch_adjoint(s->d_scene, aa, spp, c->stream));
   return JSO_OK;
 }
 
@@ -569,7 +634,7 @@ int jso_meta_step(jso_ctx* c, int id, const float* F, const float* dF, float eta
   if (!(beta_F >= 0.0f && beta_F < 1.0f && beta_D >= 0.0f && beta_D < 1.0f))
     return fail(c, JSO_E_INVALID, "beta must lie in [0, 1)");
   DeviceGuard g(c->device);
-  HIP_TRY(c, launch_meta(meta_args(s, F, dF, eta, beta_F, beta_D, 0), c->stream));
+  TIMED_LAUNCH(c, JSO_K_META, launch_meta(meta_args(s, F, dF, eta, beta_F, beta_D, 0), c->stream));
   s->host_iter++;
   return JSO_OK;
 }
@@ -582,7 +647,7 @@ int jso_adam_step(jso_ctx* c, int id, const float* grad, float eta, float beta1,
   if (!(beta1 >= 0.0f && beta1 < 1.0f && beta2 >= 0.0f && beta2 < 1.0f))
     return fail(c, JSO_E_INVALID, "beta must lie in [0, 1)");
   DeviceGuard g(c->device);
-  HIP_TRY(c, launch_adam(adam_args(s, grad, eta, beta1, beta2, eps, 0), c->stream));
+  TIMED_LAUNCH(c, JSO_K_ADAM, launch_adam(adam_args(s, grad, eta, beta1, beta2, eps, 0), c->stream));
   s->host_iter++;
   return JSO_OK;
 }
@@ -608,8 +673,9 @@ int jso_grad_step(jso_ctx* c, const int* ids, int n, const jso_step_opts* o,
                                 s->ctl->loss, JSO_TAG_PRIMAL_PROP, JSO_TAG_ADJ_PROP, full,
                                 nullptr, flags);
       if (rc) return rc;
-      HIP_TRY(c, launch_meta(meta_args(s, s->F, s->dF, o->eta, o->beta_F, o->beta_D, 1),
-                             c->stream));
+      TIMED_LAUNCH(c, JSO_K_META,
+                   launch_meta(meta_args(s, s->F, s->dF, o->eta, o->beta_F, o->beta_D, 1),
+                               c->stream));
     } else if (o->optimizer == JSO_OPT_ADAM) {
       if (o->adam_spp < 1 || o->adam_spp > 4096) return fail(c, JSO_E_INVALID, "adam_spp");
       if (!(o->adam_beta1 >= 0.0f && o->adam_beta1 < 1.0f && o->adam_beta2 >= 0.0f &&
@@ -619,9 +685,10 @@ int jso_grad_step(jso_ctx* c, const int* ids, int n, const jso_step_opts* o,
                                 s->params, s->params_prev, s->F, nullptr, nullptr, s->ctl->loss,
                                 JSO_TAG_ADAM_PRIMAL, JSO_TAG_ADAM_ADJ, full, nullptr, flags);
       if (rc) return rc;
-      HIP_TRY(c, launch_adam(adam_args(s, s->F, o->eta, o->adam_beta1, o->adam_beta2,
-                                       o->adam_eps, 1),
-                             c->stream));
+      TIMED_LAUNCH(c, JSO_K_ADAM,
+                   launch_adam(adam_args(s, s->F, o->eta, o->adam_beta1, o->adam_beta2,
+                                         o->adam_eps, 1),
+                               c->stream));
     } else {
       return fail(c, JSO_E_INVALID, "unknown optimizer %d", o->optimizer);
     }
@@ -638,6 +705,28 @@ int jso_grad_step(jso_ctx* c, const int* ids, int n, const jso_step_opts* o,
       stats[k].step_norm2 = h.norm2[h.iteration & 1u];
       stats[k].iteration = h.iteration;
     }
+  }
+  return JSO_OK;
+}
+
+int jso_set_timing(jso_ctx* c, int enable) {
+  if (!c) return JSO_E_INVALID;
+  DeviceGuard g(c->device);
+  HIP_TRY(c, c->timer.collect());
+  c->timer.enabled = enable != 0;
+  return JSO_OK;
+}
+
+int jso_get_kernel_time(jso_ctx* c, int kernel, double* ms, uint64_t* launches, int reset) {
+  if (!c) return JSO_E_INVALID;
+  if (kernel < 0 || kernel >= JSO_K_COUNT) return fail(c, JSO_E_INVALID, "bad kernel class");
+  DeviceGuard g(c->device);
+  HIP_TRY(c, c->timer.collect());
+  if (ms) *ms = c->timer.ms[kernel];
+  if (launches) *launches = c->timer.launches[kernel];
+  if (reset) {
+    c->timer.ms[kernel] = 0.0;
+    c->timer.launches[kernel] = 0;
   }
   return JSO_OK;
 }

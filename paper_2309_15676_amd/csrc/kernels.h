@@ -107,8 +107,9 @@ struct AdamArgs {
 
 hipError_t launch_philox(const uint32_t* ctr, size_t n, uint64_t key, uint32_t* out,
                          hipStream_t st);
-hipError_t launch_primal(const DevScene& S, const PrimalArgs& A, int n_jobs, hipStream_t st);
-hipError_t launch_adjoint(const DevScene& S, const AdjointArgs& A, int n_slices, hipStream_t st);
+// S: the scene in device memory (uniform reads go through the scalar cache)
+hipError_t launch_primal(const DevScene* S, const PrimalArgs& A, int n_jobs, hipStream_t st);
+hipError_t launch_adjoint(const DevScene* S, const AdjointArgs& A, int n_slices, hipStream_t st);
 hipError_t launch_meta(const MetaArgs& A, hipStream_t st);
 hipError_t launch_adam(const AdamArgs& A, hipStream_t st);
 hipError_t launch_fill_f64(double* p, size_t n, double v, hipStream_t st);

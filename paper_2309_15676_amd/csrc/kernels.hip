@@ -50,15 +50,20 @@ __device__ __forceinline__ float wave_sum(float v) {
   return v;
 }
 
-// blocks are 8 x 8 pixel tiles (one wave64)
+// Blocks are kTile x kTile pixel tiles (256 lanes = four wave64 rows of 16 x 4).
+constexpr int kTile = 16;
+constexpr int kBlock = kTile * kTile;
+
 __device__ __forceinline__ bool tile_pixel(const Crop& c, int& px, int& py) {
-  px = c.x0 + (int)blockIdx.x * 8 + (int)(threadIdx.x & 7);
-  py = c.y0 + (int)blockIdx.y * 8 + (int)(threadIdx.x >> 3);
+  px = c.x0 + (int)blockIdx.x * kTile + (int)(threadIdx.x % kTile);
+  py = c.y0 + (int)blockIdx.y * kTile + (int)(threadIdx.x / kTile);
   return px < c.x1 && py < c.y1;
 }
 
 // ---------------------------------------------------------------------------
-__global__ void __launch_bounds__(64) k_primal(DevScene S, PrimalArgs A) {
+__global__ void __launch_bounds__(kBlock) k_primal(const DevScene* __restrict__ Sp,
+                                                   PrimalArgs A) {
+  const DevScene& S = *Sp;
   const PrimalJob& job = A.jobs[blockIdx.z];
   int px, py;
   const bool inside = tile_pixel(A.crop, px, py);
@@ -93,19 +98,61 @@ __global__ void __launch_bounds__(64) k_primal(DevScene S, PrimalArgs A) {
   }
   if (job.loss2) {
     se = wave_sum(se);
-    if (threadIdx.x == 0 && se != 0.0)
+    if ((threadIdx.x & 63) == 0 && se != 0.0)
       unsafeAtomicAdd(&job.loss2[iteration_of(A.key) & 1u], se * A.loss_scale);
   }
 }
 
 // ---------------------------------------------------------------------------
 // gradient scatter
+//
+// Neighbouring pixels of a tile hit the same texels, and same-address FP32
+// atomics within one instruction serialise in the memory system.  Each block
+// therefore sums its texel contributions in an LDS hash table (open
+// addressing, keys claimed with LDS compare-and-swap, values added with LDS
+// float atomics) and flushes every distinct parameter once with a global
+// atomic at the end.  A congested probe sequence falls back to a direct
+// global atomic, so the table can never lose a contribution.
 // ---------------------------------------------------------------------------
-__device__ __forceinline__ void scatter_texels(const DevScene& S, float* __restrict__ grad,
+constexpr int kTableBits = 12;
+constexpr int kTableSize = 1 << kTableBits;  // 4096 slots, 32 KiB of LDS per block
+constexpr int kMaxProbe = 32;
+constexpr uint32_t kEmpty = 0xFFFFFFFFu;
+
+struct GradTable {
+  uint32_t* keys;  // LDS
+  float* vals;     // LDS
+  float* grad;     // global gradient buffer of this block's job
+};
+
+__device__ __forceinline__ void table_add(const GradTable& T, uint32_t key, float v) {
+  uint32_t h = (key * 2654435761u) >> (32 - kTableBits);
+  for (int p = 0; p < kMaxProbe; ++p) {
+    uint32_t k = T.keys[h];
+    if (k == kEmpty) {
+      const uint32_t old = atomicCAS(&T.keys[h], kEmpty, key);
+      k = old == kEmpty ? key : old;
+    }
+    if (k == key) {
+      __hip_atomic_fetch_add(&T.vals[h], v, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_WORKGROUP);
+      return;
+    }
+    h = (h + 1) & (kTableSize - 1);
+  }
+  unsafeAtomicAdd(T.grad + key, v);
+}
+
+// Texel q of the footprint (q = 0..3: x-offset q & 1, y-offset q >> 1) and its
+// bilinear weight, computed arithmetically so no per-lane array is indexed.
+__device__ __forceinline__ void footprint_texel(const Footprint& fp, int q, int& texel,
+                                                float& w) {
+  const int dx = fp.t01 - fp.t00, dy = fp.t10 - fp.t00;
+  texel = fp.t00 + (q & 1) * dx + (q >> 1) * dy;
+  w = ((q & 1) ? fp.fx : 1.0f - fp.fx) * ((q & 2) ? fp.fy : 1.0f - fp.fy);
+}
+
+__device__ __forceinline__ void scatter_texels(const DevScene& S, const GradTable& T,
                                                const Footprint& fp, const float g[5], float sign) {
-  float w[4];
-  texel_weights(fp, w);
-  const int t[4] = {fp.t00, fp.t01, fp.t10, fp.t11};
   const int nc = S.n_ch;
 #pragma unroll
   for (int b = 0; b < 5; ++b) {
@@ -113,10 +160,13 @@ __device__ __forceinline__ void scatter_texels(const DevScene& S, float* __restr
     if (s < 0) continue;
     const float gb = sign * g[b];
     if (gb == 0.0f) continue;
-#pragma unroll
+#pragma unroll 1
     for (int q = 0; q < 4; ++q) {
-      const float v = w[q] * gb;
-      if (v != 0.0f) unsafeAtomicAdd(grad + (size_t)t[q] * nc + s, v);
+      int texel;
+      float w;
+      footprint_texel(fp, q, texel, w);
+      const float v = w * gb;
+      if (v != 0.0f) table_add(T, (uint32_t)(texel * nc + s), v);
     }
   }
 }
@@ -128,47 +178,60 @@ __device__ __forceinline__ bool same_footprint(const Footprint& a, const Footpri
 }
 
 // Accumulates vertex gradients: global materials into per-lane registers
-// (reduced over the wave at the end), textured ones straight to memory.
+// (reduced over the wave at the end), textured ones into the block's table.
 struct Sink {
   float acc[5];
-  __device__ __forceinline__ void init() {
+  GradTable T;
+  __device__ __forceinline__ void init(const GradTable& t) {
+    T = t;
 #pragma unroll
     for (int b = 0; b < 5; ++b) acc[b] = 0.0f;
   }
-  __device__ __forceinline__ void add(const DevScene& S, float* grad, const VertexGrad& v,
-                                      float sign) {
+  __device__ __forceinline__ void add(const DevScene& S, const VertexGrad& v, float sign) {
     if (!v.valid) return;
     if (v.fp.global) {
 #pragma unroll
       for (int b = 0; b < 5; ++b) acc[b] += sign * v.g[b];
     } else {
-      scatter_texels(S, grad, v.fp, v.g, sign);
+      scatter_texels(S, T, v.fp, v.g, sign);
     }
   }
-  __device__ __forceinline__ void add_diff(const DevScene& S, float* grad, const VertexGrad& a,
+  __device__ __forceinline__ void add_diff(const DevScene& S, const VertexGrad& a,
                                            const VertexGrad& b) {
     if (a.valid && b.valid && same_footprint(a.fp, b.fp)) {
       VertexGrad d = a;
 #pragma unroll
       for (int q = 0; q < 5; ++q) d.g[q] = a.g[q] - b.g[q];
-      add(S, grad, d, 1.0f);
+      add(S, d, 1.0f);
     } else {
-      add(S, grad, a, 1.0f);
-      add(S, grad, b, -1.0f);
+      add(S, a, 1.0f);
+      add(S, b, -1.0f);
     }
   }
-  __device__ __forceinline__ void flush(const DevScene& S, float* grad) {
-    // every lane of the wave reaches this point
+  // every lane of the block reaches this point
+  __device__ __forceinline__ void flush(const DevScene& S) {
 #pragma unroll
     for (int b = 0; b < 5; ++b) {
       const int s = S.slot[b];
       const float v = wave_sum(acc[b]);
-      if (s >= 0 && threadIdx.x == 0 && v != 0.0f) unsafeAtomicAdd(grad + s, v);
+      if (s >= 0 && (threadIdx.x & 63) == 0 && v != 0.0f) unsafeAtomicAdd(T.grad + s, v);
+    }
+    __syncthreads();
+    for (int i = threadIdx.x; i < kTableSize; i += kBlock) {
+      const uint32_t k = T.keys[i];
+      if (k != kEmpty) {
+        const float v = T.vals[i];
+        if (v != 0.0f) unsafeAtomicAdd(T.grad + k, v);
+      }
     }
   }
 };
 
-__global__ void __launch_bounds__(64) k_adjoint(DevScene S, AdjointArgs A) {
+__global__ void __launch_bounds__(kBlock) __attribute__((amdgpu_waves_per_eu(3)))
+k_adjoint(const DevScene* __restrict__ Sp, AdjointArgs A) {
+  const DevScene& S = *Sp;
+  __shared__ uint32_t s_keys[kTableSize];
+  __shared__ float s_vals[kTableSize];
   // find the job of this grid slice
   int ji = 0;
   while (ji + 1 < A.n_jobs && (int)blockIdx.z >= A.jobs[ji + 1].z0) ++ji;
@@ -178,8 +241,13 @@ __global__ void __launch_bounds__(64) k_adjoint(DevScene S, AdjointArgs A) {
   const bool inside = tile_pixel(A.crop, px, py);
   const uint32_t pix = (uint32_t)(py * S.width + px);
   const bool active = inside && !(A.mask && A.mask[pix]);
+  for (int i = threadIdx.x; i < kTableSize; i += kBlock) {
+    s_keys[i] = kEmpty;
+    s_vals[i] = 0.0f;
+  }
+  __syncthreads();
   Sink sink;
-  sink.init();
+  sink.init(GradTable{s_keys, s_vals, job.grad});
   if (active) {
     const uint64_t key = stream_key(A.key.seed, iteration_of(A.key), job.tag);
     const Rng rng = make_rng(key, pix, sample);
@@ -197,7 +265,7 @@ __global__ void __launch_bounds__(64) k_adjoint(DevScene S, AdjointArgs A) {
       VertexGrad vg;
       while (P.alive) {
         path_vertex<true>(S, job.params, rng, A.flags, P, adj_a, Ca, vg);
-        sink.add(S, job.grad, vg, job.sign);
+        sink.add(S, vg, job.sign);
       }
     } else {
       double Cb[3];
@@ -210,11 +278,11 @@ __global__ void __launch_bounds__(64) k_adjoint(DevScene S, AdjointArgs A) {
         va.valid = vb.valid = false;
         if (Pa.alive) path_vertex<true>(S, job.params, rng, A.flags, Pa, adj_a, Ca, va);
         if (Pb.alive) path_vertex<true>(S, job.params_b, rng, A.flags, Pb, adj_b, Cb, vb);
-        sink.add_diff(S, job.grad, va, vb);
+        sink.add_diff(S, va, vb);
       }
     }
   }
-  sink.flush(S, job.grad);
+  sink.flush(S);
 }
 
 // ---------------------------------------------------------------------------
@@ -365,17 +433,19 @@ hipError_t launch_philox(const uint32_t* ctr, size_t n, uint64_t key, uint32_t* 
   return hipGetLastError();
 }
 
-hipError_t launch_primal(const DevScene& S, const PrimalArgs& A, int n_jobs, hipStream_t st) {
+hipError_t launch_primal(const DevScene* S, const PrimalArgs& A, int n_jobs, hipStream_t st) {
   const int w = A.crop.x1 - A.crop.x0, h = A.crop.y1 - A.crop.y0;
   if (w <= 0 || h <= 0 || n_jobs <= 0) return hipSuccess;
-  hipLaunchKernelGGL(k_primal, dim3(cdiv(w, 8), cdiv(h, 8), n_jobs), dim3(64), 0, st, S, A);
+  hipLaunchKernelGGL(k_primal, dim3(cdiv(w, kTile), cdiv(h, kTile), n_jobs), dim3(kBlock), 0, st,
+                     S, A);
   return hipGetLastError();
 }
 
-hipError_t launch_adjoint(const DevScene& S, const AdjointArgs& A, int n_slices, hipStream_t st) {
+hipError_t launch_adjoint(const DevScene* S, const AdjointArgs& A, int n_slices, hipStream_t st) {
   const int w = A.crop.x1 - A.crop.x0, h = A.crop.y1 - A.crop.y0;
   if (w <= 0 || h <= 0 || n_slices <= 0) return hipSuccess;
-  hipLaunchKernelGGL(k_adjoint, dim3(cdiv(w, 8), cdiv(h, 8), n_slices), dim3(64), 0, st, S, A);
+  hipLaunchKernelGGL(k_adjoint, dim3(cdiv(w, kTile), cdiv(h, kTile), n_slices), dim3(kBlock), 0,
+                     st, S, A);
   return hipGetLastError();
 }
 
