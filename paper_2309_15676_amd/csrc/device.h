@@ -398,6 +398,7 @@ struct Path {
 // restricted to this vertex's BSDF evaluations.
 struct VertexGrad {
   bool valid;
+  int j;  // vertex index along the path (1 = first surface hit)
   Footprint fp;
   float g[5];
 };
@@ -457,6 +458,7 @@ __device__ __forceinline__ void path_vertex(const DevScene& S, const float* __re
   const V3 wo = mk(-P.d.x, -P.d.y, -P.d.z);
   Mat M;
   vg.valid = material_at(S, params, P.kind, P.obj, p, n, M, vg.fp);
+  vg.j = P.j;
   if (kGrad) {
 #pragma unroll
     for (int b = 0; b < 5; ++b) vg.g[b] = 0.0f;

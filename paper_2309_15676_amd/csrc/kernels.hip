@@ -114,32 +114,33 @@ __global__ void __launch_bounds__(kBlock) k_primal(const DevScene* __restrict__ 
 // atomic at the end.  A congested probe sequence falls back to a direct
 // global atomic, so the table can never lose a contribution.
 // ---------------------------------------------------------------------------
-constexpr int kTableBits = 12;
-constexpr int kTableSize = 1 << kTableBits;  // 4096 slots, 32 KiB of LDS per block
+constexpr int kTableBits = 11;
+constexpr int kTableSize = 1 << kTableBits;  // texels per block table
+constexpr int kTableCh = 5;                  // value slots per texel (max channels)
 constexpr int kMaxProbe = 32;
 constexpr uint32_t kEmpty = 0xFFFFFFFFu;
+// LDS per block: kTableSize * (4 + 4 * kTableCh) bytes = 48 KiB
 
 struct GradTable {
-  uint32_t* keys;  // LDS
-  float* vals;     // LDS
+  uint32_t* keys;  // LDS: texel index of each slot
+  float* vals;     // LDS: kTableCh gradient values per slot
   float* grad;     // global gradient buffer of this block's job
 };
 
-__device__ __forceinline__ void table_add(const GradTable& T, uint32_t key, float v) {
-  uint32_t h = (key * 2654435761u) >> (32 - kTableBits);
+// Slot of `texel` in the table (claimed if new), or -1 when the probe
+// sequence is congested.
+__device__ __forceinline__ int table_slot(const GradTable& T, uint32_t texel) {
+  uint32_t h = (texel * 2654435761u) >> (32 - kTableBits);
   for (int p = 0; p < kMaxProbe; ++p) {
     uint32_t k = T.keys[h];
     if (k == kEmpty) {
-      const uint32_t old = atomicCAS(&T.keys[h], kEmpty, key);
-      k = old == kEmpty ? key : old;
+      const uint32_t old = atomicCAS(&T.keys[h], kEmpty, texel);
+      k = old == kEmpty ? texel : old;
     }
-    if (k == key) {
-      __hip_atomic_fetch_add(&T.vals[h], v, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_WORKGROUP);
-      return;
-    }
+    if (k == texel) return (int)h;
     h = (h + 1) & (kTableSize - 1);
   }
-  unsafeAtomicAdd(T.grad + key, v);
+  return -1;
 }
 
 // Texel q of the footprint (q = 0..3: x-offset q & 1, y-offset q >> 1) and its
@@ -151,22 +152,32 @@ __device__ __forceinline__ void footprint_texel(const Footprint& fp, int q, int&
   w = ((q & 1) ? fp.fx : 1.0f - fp.fx) * ((q & 2) ? fp.fy : 1.0f - fp.fy);
 }
 
+// Scatter one vertex's material gradient g (R, G, B, metal, rough) onto its
+// four texels.  Primary vertices of a tile overlap heavily and go through the
+// block table; later vertices are scattered over the texture and go straight
+// to memory (direct = true).
 __device__ __forceinline__ void scatter_texels(const DevScene& S, const GradTable& T,
-                                               const Footprint& fp, const float g[5], float sign) {
+                                               const Footprint& fp, const float g[5], float sign,
+                                               bool direct) {
   const int nc = S.n_ch;
-#pragma unroll
-  for (int b = 0; b < 5; ++b) {
-    const int s = S.slot[b];
-    if (s < 0) continue;
-    const float gb = sign * g[b];
-    if (gb == 0.0f) continue;
 #pragma unroll 1
-    for (int q = 0; q < 4; ++q) {
-      int texel;
-      float w;
-      footprint_texel(fp, q, texel, w);
-      const float v = w * gb;
-      if (v != 0.0f) table_add(T, (uint32_t)(texel * nc + s), v);
+  for (int q = 0; q < 4; ++q) {
+    int texel;
+    float w;
+    footprint_texel(fp, q, texel, w);
+    if (w == 0.0f) continue;
+    const int h = direct ? -1 : table_slot(T, (uint32_t)texel);
+#pragma unroll
+    for (int b = 0; b < 5; ++b) {
+      const int s = S.slot[b];
+      if (s < 0) continue;
+      const float v = w * (sign * g[b]);
+      if (v == 0.0f) continue;
+      if (h >= 0)
+        __hip_atomic_fetch_add(&T.vals[h * kTableCh + s], v, __ATOMIC_RELAXED,
+                               __HIP_MEMORY_SCOPE_WORKGROUP);
+      else
+        unsafeAtomicAdd(T.grad + (size_t)texel * nc + s, v);
     }
   }
 }
@@ -193,7 +204,7 @@ struct Sink {
 #pragma unroll
       for (int b = 0; b < 5; ++b) acc[b] += sign * v.g[b];
     } else {
-      scatter_texels(S, T, v.fp, v.g, sign);
+      scatter_texels(S, T, v.fp, v.g, sign, v.j > 1);
     }
   }
   __device__ __forceinline__ void add_diff(const DevScene& S, const VertexGrad& a,
@@ -217,11 +228,13 @@ struct Sink {
       if (s >= 0 && (threadIdx.x & 63) == 0 && v != 0.0f) unsafeAtomicAdd(T.grad + s, v);
     }
     __syncthreads();
+    const int nc = S.n_ch;
     for (int i = threadIdx.x; i < kTableSize; i += kBlock) {
       const uint32_t k = T.keys[i];
-      if (k != kEmpty) {
-        const float v = T.vals[i];
-        if (v != 0.0f) unsafeAtomicAdd(T.grad + k, v);
+      if (k == kEmpty) continue;
+      for (int c = 0; c < nc; ++c) {
+        const float v = T.vals[i * kTableCh + c];
+        if (v != 0.0f) unsafeAtomicAdd(T.grad + (size_t)k * nc + c, v);
       }
     }
   }
@@ -231,7 +244,7 @@ __global__ void __launch_bounds__(kBlock) __attribute__((amdgpu_waves_per_eu(3))
 k_adjoint(const DevScene* __restrict__ Sp, AdjointArgs A) {
   const DevScene& S = *Sp;
   __shared__ uint32_t s_keys[kTableSize];
-  __shared__ float s_vals[kTableSize];
+  __shared__ float s_vals[kTableSize * kTableCh];
   // find the job of this grid slice
   int ji = 0;
   while (ji + 1 < A.n_jobs && (int)blockIdx.z >= A.jobs[ji + 1].z0) ++ji;
@@ -241,10 +254,8 @@ k_adjoint(const DevScene* __restrict__ Sp, AdjointArgs A) {
   const bool inside = tile_pixel(A.crop, px, py);
   const uint32_t pix = (uint32_t)(py * S.width + px);
   const bool active = inside && !(A.mask && A.mask[pix]);
-  for (int i = threadIdx.x; i < kTableSize; i += kBlock) {
-    s_keys[i] = kEmpty;
-    s_vals[i] = 0.0f;
-  }
+  for (int i = threadIdx.x; i < kTableSize; i += kBlock) s_keys[i] = kEmpty;
+  for (int i = threadIdx.x; i < kTableSize * kTableCh; i += kBlock) s_vals[i] = 0.0f;
   __syncthreads();
   Sink sink;
   sink.init(GradTable{s_keys, s_vals, job.grad});
