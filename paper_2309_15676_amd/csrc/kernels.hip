@@ -152,13 +152,12 @@ __device__ __forceinline__ void footprint_texel(const Footprint& fp, int q, int&
   w = ((q & 1) ? fp.fx : 1.0f - fp.fx) * ((q & 2) ? fp.fy : 1.0f - fp.fy);
 }
 
-// Scatter one vertex's material gradient g (R, G, B, metal, rough) onto its
-// four texels.  Primary vertices of a tile overlap heavily and go through the
-// block table; later vertices are scattered over the texture and go straight
-// to memory (direct = true).
+// Add one first-hit vertex's material gradient g (R, G, B, metal, rough) to
+// its four texels in the block table (global atomics when a probe sequence is
+// congested).
 __device__ __forceinline__ void scatter_texels(const DevScene& S, const GradTable& T,
-                                               const Footprint& fp, const float g[5], float sign,
-                                               bool direct) {
+                                               const Footprint& fp, const float g[5],
+                                               float sign) {
   const int nc = S.n_ch;
 #pragma unroll 1
   for (int q = 0; q < 4; ++q) {
@@ -166,7 +165,7 @@ __device__ __forceinline__ void scatter_texels(const DevScene& S, const GradTabl
     float w;
     footprint_texel(fp, q, texel, w);
     if (w == 0.0f) continue;
-    const int h = direct ? -1 : table_slot(T, (uint32_t)texel);
+    const int h = table_slot(T, (uint32_t)texel);
 #pragma unroll
     for (int b = 0; b < 5; ++b) {
       const int s = S.slot[b];
@@ -182,6 +181,49 @@ __device__ __forceinline__ void scatter_texels(const DevScene& S, const GradTabl
   }
 }
 
+// Scatter the later-vertex gradient of every lane with `has` set straight to
+// memory.  Device-scope float atomics are priced per cache line, so the wave
+// spreads each vertex over 4 * n_ch lanes, neighbouring lanes taking the
+// neighbouring channels of one texel: a texel then costs one transaction
+// instead of n_ch.  Must be reached by all 64 lanes of the wave.
+__device__ __forceinline__ void scatter_wave(const DevScene& S, float* __restrict__ grad,
+                                             const VertexGrad& v, float sign, bool has) {
+  uint64_t m = __ballot(has);
+  if (m == 0) return;
+  const int nc = S.n_ch;
+  const int per = 4 * nc;  // lanes per vertex
+  const int nv = 64 / per;  // vertices per round
+  const int lane = (int)__lane_id();
+  const int vi = lane / per;
+  const int within = lane - vi * per;
+  const int q = within / nc;
+  const int c = within - q * nc;
+  while (m != 0) {
+    uint64_t mm = m;
+    for (int k = 0; k < vi && mm != 0; ++k) mm &= mm - 1;
+    const bool work = vi < nv && mm != 0;
+    const int src = work ? __ffsll((unsigned long long)mm) - 1 : lane;
+    const int t00 = __shfl(v.fp.t00, src, 64);
+    const int t01 = __shfl(v.fp.t01, src, 64);
+    const int t10 = __shfl(v.fp.t10, src, 64);
+    const float fx = __shfl(v.fp.fx, src, 64);
+    const float fy = __shfl(v.fp.fy, src, 64);
+    float gc = 0.0f;
+#pragma unroll
+    for (int b = 0; b < 5; ++b) {
+      const float x = __shfl(v.g[b], src, 64);
+      if (S.slot[b] == c) gc = x;
+    }
+    if (work) {
+      const int texel = t00 + (q & 1) * (t01 - t00) + (q >> 1) * (t10 - t00);
+      const float w = ((q & 1) ? fx : 1.0f - fx) * ((q & 2) ? fy : 1.0f - fy);
+      const float val = w * (sign * gc);
+      if (val != 0.0f) unsafeAtomicAdd(grad + (size_t)texel * nc + c, val);
+    }
+    for (int k = 0; k < nv && m != 0; ++k) m &= m - 1;
+  }
+}
+
 __device__ __forceinline__ bool same_footprint(const Footprint& a, const Footprint& b) {
   return a.global == b.global && a.t00 == b.t00 && a.t01 == b.t01 && a.t10 == b.t10 &&
          a.t11 == b.t11 && __float_as_uint(a.fx) == __float_as_uint(b.fx) &&
@@ -189,7 +231,8 @@ __device__ __forceinline__ bool same_footprint(const Footprint& a, const Footpri
 }
 
 // Accumulates vertex gradients: global materials into per-lane registers
-// (reduced over the wave at the end), textured ones into the block's table.
+// (reduced over the wave at the end), first-hit texels into the block's table;
+// later textured vertices are handed back for the wave-cooperative scatter.
 struct Sink {
   float acc[5];
   GradTable T;
@@ -198,26 +241,17 @@ struct Sink {
 #pragma unroll
     for (int b = 0; b < 5; ++b) acc[b] = 0.0f;
   }
-  __device__ __forceinline__ void add(const DevScene& S, const VertexGrad& v, float sign) {
-    if (!v.valid) return;
+  // returns true when v is a later textured vertex left to scatter_wave
+  __device__ __forceinline__ bool add(const DevScene& S, const VertexGrad& v, float sign) {
+    if (!v.valid) return false;
     if (v.fp.global) {
 #pragma unroll
       for (int b = 0; b < 5; ++b) acc[b] += sign * v.g[b];
-    } else {
-      scatter_texels(S, T, v.fp, v.g, sign, v.j > 1);
+      return false;
     }
-  }
-  __device__ __forceinline__ void add_diff(const DevScene& S, const VertexGrad& a,
-                                           const VertexGrad& b) {
-    if (a.valid && b.valid && same_footprint(a.fp, b.fp)) {
-      VertexGrad d = a;
-#pragma unroll
-      for (int q = 0; q < 5; ++q) d.g[q] = a.g[q] - b.g[q];
-      add(S, d, 1.0f);
-    } else {
-      add(S, a, 1.0f);
-      add(S, b, -1.0f);
-    }
+    if (v.j > 1) return true;
+    scatter_texels(S, T, v.fp, v.g, sign);
+    return false;
   }
   // every lane of the block reaches this point
   __device__ __forceinline__ void flush(const DevScene& S) {
@@ -228,18 +262,22 @@ struct Sink {
       if (s >= 0 && (threadIdx.x & 63) == 0 && v != 0.0f) unsafeAtomicAdd(T.grad + s, v);
     }
     __syncthreads();
+    // neighbouring lanes flush neighbouring channels of one texel
     const int nc = S.n_ch;
-    for (int i = threadIdx.x; i < kTableSize; i += kBlock) {
-      const uint32_t k = T.keys[i];
+    for (int i = threadIdx.x; i < kTableSize * nc; i += kBlock) {
+      const int slot = i / nc;
+      const int c = i - slot * nc;
+      const uint32_t k = T.keys[slot];
       if (k == kEmpty) continue;
-      for (int c = 0; c < nc; ++c) {
-        const float v = T.vals[i * kTableCh + c];
-        if (v != 0.0f) unsafeAtomicAdd(T.grad + (size_t)k * nc + c, v);
-      }
+      const float v = T.vals[slot * kTableCh + c];
+      if (v != 0.0f) unsafeAtomicAdd(T.grad + (size_t)k * nc + c, v);
     }
   }
 };
 
+// One block = one kTile x kTile pixel tile of one job's sample.  Each path is
+// traced forward for its radiance, then replayed vertex by vertex; the loop is
+// wave-uniform so the later-vertex scatter can use the whole wave.
 __global__ void __launch_bounds__(kBlock) __attribute__((amdgpu_waves_per_eu(3)))
 k_adjoint(const DevScene* __restrict__ Sp, AdjointArgs A) {
   const DevScene& S = *Sp;
@@ -259,38 +297,51 @@ k_adjoint(const DevScene* __restrict__ Sp, AdjointArgs A) {
   __syncthreads();
   Sink sink;
   sink.init(GradTable{s_keys, s_vals, job.grad});
+  const uint64_t key = stream_key(A.key.seed, iteration_of(A.key), job.tag);
+  const Rng rng = make_rng(key, pix, sample);
+  const bool pair = job.params_b != nullptr;  // uniform over the block
+  float adj_a[3] = {0.0f, 0.0f, 0.0f}, adj_b[3] = {0.0f, 0.0f, 0.0f};
+  double Ca[3] = {0.0, 0.0, 0.0}, Cb[3] = {0.0, 0.0, 0.0};
+  Path Pa, Pb;
+  Pa.alive = Pb.alive = false;
   if (active) {
-    const uint64_t key = stream_key(A.key.seed, iteration_of(A.key), job.tag);
-    const Rng rng = make_rng(key, pix, sample);
-    float adj_a[3], adj_b[3];
 #pragma unroll
     for (int k = 0; k < 3; ++k) {
       adj_a[k] = job.delta[3 * (size_t)pix + k] * job.adj_scale;
-      adj_b[k] = job.params_b ? job.delta_b[3 * (size_t)pix + k] * job.adj_scale : 0.0f;
+      if (pair) adj_b[k] = job.delta_b[3 * (size_t)pix + k] * job.adj_scale;
     }
-    double Ca[3];
     path_radiance(S, job.params, rng, px, py, A.flags, Ca);
-    if (!job.params_b) {
-      Path P;
-      path_begin(S, rng, px, py, A.flags, P);
-      VertexGrad vg;
-      while (P.alive) {
-        path_vertex<true>(S, job.params, rng, A.flags, P, adj_a, Ca, vg);
-        sink.add(S, vg, job.sign);
-      }
-    } else {
-      double Cb[3];
+    path_begin(S, rng, px, py, A.flags, Pa);
+    if (pair) {
       path_radiance(S, job.params_b, rng, px, py, A.flags, Cb);
-      Path Pa, Pb;
-      path_begin(S, rng, px, py, A.flags, Pa);
       path_begin(S, rng, px, py, A.flags, Pb);
-      while (Pa.alive || Pb.alive) {
-        VertexGrad va, vb;
-        va.valid = vb.valid = false;
-        if (Pa.alive) path_vertex<true>(S, job.params, rng, A.flags, Pa, adj_a, Ca, va);
-        if (Pb.alive) path_vertex<true>(S, job.params_b, rng, A.flags, Pb, adj_b, Cb, vb);
-        sink.add_diff(S, va, vb);
+    }
+  }
+  if (!pair) {
+    while (__ballot(Pa.alive) != 0) {
+      VertexGrad va;
+      va.valid = false;
+      if (Pa.alive) path_vertex<true>(S, job.params, rng, A.flags, Pa, adj_a, Ca, va);
+      const bool later = sink.add(S, va, job.sign);
+      scatter_wave(S, job.grad, va, job.sign, later);
+    }
+  } else {
+    // the pair is replayed in lockstep; coinciding vertices are differenced
+    // in registers (+A - B)
+    while (__ballot(Pa.alive || Pb.alive) != 0) {
+      VertexGrad va, vb;
+      va.valid = vb.valid = false;
+      if (Pa.alive) path_vertex<true>(S, job.params, rng, A.flags, Pa, adj_a, Ca, va);
+      if (Pb.alive) path_vertex<true>(S, job.params_b, rng, A.flags, Pb, adj_b, Cb, vb);
+      if (va.valid && vb.valid && same_footprint(va.fp, vb.fp)) {
+#pragma unroll
+        for (int q = 0; q < 5; ++q) va.g[q] -= vb.g[q];
+        vb.valid = false;
       }
+      const bool later_a = sink.add(S, va, 1.0f);
+      const bool later_b = sink.add(S, vb, -1.0f);
+      scatter_wave(S, job.grad, va, 1.0f, later_a);
+      scatter_wave(S, job.grad, vb, -1.0f, later_b);
     }
   }
   sink.flush(S);
