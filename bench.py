@@ -12,8 +12,12 @@ meta-estimator + stabilised step.  Inputs are synthetic and already resident
 on the GPU when the timed region starts.
 
 Prints one JSON line.  `value` = differentiable paths/s (forward + replayed
-adjoint); `roofline` = the dominant kernel (the replayed adjoint) against the
-FP32 vector peak; `cpu_baseline` = the FP64 CPU oracle on the same workload.
+adjoint); `roofline` = the dominant kernel (the replayed adjoint): its
+algorithmic FP32 work (surface vertices counted on the GPU x per-vertex FLOP
+figures) per launch over its HIP-event launch time, against the FP32 vector
+peak, with `traffic` = HBM bytes per launch from the committed rocprofv3
+counter summary (null when the kernel changed since it was taken);
+`cpu_baseline` = the FP64 CPU oracle on the same workload for about 10 s.
 """
 from __future__ import annotations
 
@@ -31,27 +35,48 @@ if ROOT not in sys.path:
 PEAK_HBM_GBS = 8000.0
 PEAK_FP32_VECTOR_TFLOPS = 157.3
 
-# Algorithmic FP32 operations per path vertex (tally of the method's formulas,
-# counting + - * / sqrt and transcendental calls as one each):
-FLOP_CAMERA = 40            # primary ray
-FLOP_INTERSECT_SPHERE = 25  # per sphere per ray
-FLOP_INTERSECT_PLANE_LIGHT = 20
-FLOP_VERTEX_SHADE = 300     # hit point, normal, UV + bilinear lookup (4 texels x 4 ch),
-                            # NEE sample + BSDF eval, direction sample + BSDF eval, throughput
-FLOP_VERTEX_DERIV = 200     # replay only: partials of both BSDF evaluations, adjoint
-                            # coefficients, bilinear scatter weights
+# Algorithmic FP32 work per surface vertex of a path: intersection of the
+# continuation and shadow rays with the scene, texture fetch, BSDF evaluation
+# and sampling, NEE with MIS, throughput update (forward); the replay repeats
+# that and adds the material partials of both BSDF evaluations, the adjoint
+# coefficients and the bilinear scatter weights.
+FLOP_FORWARD_VERTEX = 600
+FLOP_REPLAY_VERTEX = 1000
+
+KERNEL_SOURCES = ("paper_2309_15676_amd/csrc/device.h", "paper_2309_15676_amd/csrc/kernels.h",
+                  "paper_2309_15676_amd/csrc/kernels.hip")
+TRAFFIC_SUMMARY = "profiles/k_adjoint_textured512_hbm_traffic.md"
 
 
-def flops_per_vertex(n_spheres: int, replay: bool) -> int:
-    rays = 2  # continuation + shadow ray
-    f = FLOP_VERTEX_SHADE + rays * (n_spheres * FLOP_INTERSECT_SPHERE + FLOP_INTERSECT_PLANE_LIGHT)
-    return f + (FLOP_VERTEX_DERIV if replay else 0)
+def kernel_source_hash() -> str:
+    import hashlib
+    h = hashlib.sha256()
+    for f in KERNEL_SOURCES:
+        with open(os.path.join(ROOT, f), "rb") as fh:
+            h.update(fh.read())
+    return h.hexdigest()
 
 
-def cpu_baseline(spec, params, target, iters: int, seed: int):
-    """The FP64 oracle, as it stands, timed on this host: `iters` full
-    iterations (proportional + finite-difference gradient samples on the whole
-    image, then the meta-estimator step) of the same workload."""
+def measured_traffic():
+    """HBM bytes per k_adjoint launch from the committed rocprofv3 counter
+    summary, or None when the kernel sources changed since it was taken."""
+    path = os.path.join(ROOT, TRAFFIC_SUMMARY)
+    if not os.path.exists(path):
+        return None
+    with open(path) as fh:
+        for line in fh:
+            if line.startswith("traffic-json: "):
+                rec = json.loads(line[len("traffic-json: "):])
+                if rec.get("source_sha256") == kernel_source_hash():
+                    return rec["bytes_per_launch"]
+    return None
+
+
+def cpu_baseline(spec, params, target, seconds: float, seed: int):
+    """The FP64 oracle, as it stands, timed on this host: whole iterations
+    (proportional + finite-difference gradient samples on the full image, then
+    the meta-estimator step) of the same workload, repeated until `seconds`
+    have passed."""
     import numpy as np
 
     import oracle as O
@@ -59,19 +84,35 @@ def cpu_baseline(spec, params, target, iters: int, seed: int):
 
     lo, hi = spec.param_bounds()
     opt = OM.MetaOptimizer(params, lo, hi, eta=float(np.float32(0.01)))
-    threads = os.cpu_count() or 1
-    O.reset_stats()
+    # this host's share of cores (at most 16 worker threads)
+    threads = max(1, min(len(os.sched_getaffinity(0)), 16))
     t0 = time.perf_counter()
-    for i in range(iters):
+    iters = 0
+    while True:
         r = O.gradient_pair(spec, opt.params.astype(np.float64),
-                            opt.params_prev.astype(np.float64), target, seed, i, nthreads=threads)
+                            opt.params_prev.astype(np.float64), target, seed, iters,
+                            nthreads=threads)
         opt.step(r["F"], r["dF"])
-    dt = time.perf_counter() - t0
-    st = O.get_stats()
-    paths = 4 * spec.n_pixels * iters - (2 * spec.n_pixels if iters > 0 else 0)  # no FD at i = 0
+        iters += 1
+        dt = time.perf_counter() - t0
+        if dt >= seconds or iters >= 1000:
+            break
+    paths = 4 * spec.n_pixels * iters - 2 * spec.n_pixels  # no FD pair at iteration 0
     return dict(value=paths / dt, unit="differentiable paths/s", cores=threads, kind="oracle",
-                sample="%d full iterations of the 512x512 workload (iteration 0 has no FD pair), "
-                       "%.1f s" % (iters, dt)), st
+                sample="first %d iterations of the 512x512 workload from the same initial "
+                       "texture (iteration 0 has no FD pair), %.1f s" % (iters, dt))
+
+
+def copy_calibration(mib: int):
+    """A plain device copy of known size (mib MiB read + mib MiB written), run
+    three times, for scaling the HBM byte counters of a profiled run."""
+    import torch
+    n = mib * (1 << 20) // 4
+    src = torch.ones(n, dtype=torch.float32, device="cuda")
+    dst = torch.empty_like(src)
+    for _ in range(3):
+        torch.mul(src, 1.0, out=dst)
+    torch.cuda.synchronize()
 
 
 def main():
@@ -80,8 +121,10 @@ def main():
     ap.add_argument("--steps", type=int, default=30)
     ap.add_argument("--warmup", type=int, default=3)
     ap.add_argument("--target-spp", type=int, default=4096)
-    ap.add_argument("--cpu-iters", type=int, default=3)
+    ap.add_argument("--cpu-seconds", type=float, default=10.0)
     ap.add_argument("--no-cpu-baseline", action="store_true")
+    ap.add_argument("--copy-mib", type=int, default=0,
+                    help="also run a plain copy of this many MiB (counter calibration)")
     ap.add_argument("--seed", type=int, default=4)
     args = ap.parse_args()
     if args.gpus != 1:
@@ -126,33 +169,39 @@ def main():
     ktimes = {name: L.jso_get_kernel_time(ctx, k) for k, name in
               ((L.JSO_K_PRIMAL, "primal"), (L.JSO_K_ADJOINT, "adjoint"), (L.JSO_K_META, "meta"))}
     L.check(L.jso_set_timing(ctx, False), ctx)
+    # work of the adjoint launches, counted on the GPU (outside the timed region)
+    L.check(L.jso_set_work_counting(ctx, True), ctx)
+    L.jso_get_work(ctx, reset=True)
+    n_count = 3
+    for _ in range(n_count):
+        prob.grad_step(opts)
+    paths_counted, verts_counted = L.jso_get_work(ctx, reset=True)
+    L.check(L.jso_set_work_counting(ctx, False), ctx)
+    vpp = verts_counted / max(paths_counted, 1)
     st = prob.grad_step(opts, want_stats=True)
-    print("[bench] kernel ms per step: %s; loss %.5g" % (
-        {k: round(v[0] / max(v[1], 1), 4) for k, v in ktimes.items()}, st.loss),
+    print("[bench] kernel ms per step: %s; loss %.5g; %.4f vertices per path" % (
+        {k: round(v[0] / max(v[1], 1), 4) for k, v in ktimes.items()}, st.loss, vpp),
         file=sys.stderr, flush=True)
+    if args.copy_mib > 0:
+        copy_calibration(args.copy_mib)
 
     npix = spec.n_pixels
     diff_paths = 4 * npix * args.steps
     value = diff_paths / (total_ms / 1e3)
 
-    # CPU baseline (the oracle) -- also supplies the workload's mean vertex count
+    # CPU baseline: the oracle on this host
     cpu = None
-    vpp = None
     if not args.no_cpu_baseline:
-        print("[bench] CPU oracle baseline (%d iterations)" % args.cpu_iters, file=sys.stderr,
+        print("[bench] CPU oracle baseline (%.0f s)" % args.cpu_seconds, file=sys.stderr,
               flush=True)
         Tn = target.cpu().numpy().astype(np.float64)
-        cpu, stats = cpu_baseline(spec, init, Tn, args.cpu_iters, args.seed)
-        if stats["paths"] > 0:
-            vpp = stats["vertices"] / stats["paths"]
-    if vpp is None:
-        vpp = 3.0  # conservative stand-in when the oracle leg is skipped
+        cpu = cpu_baseline(spec, init, Tn, args.cpu_seconds, args.seed)
     # roofline of the dominant kernel: the replayed adjoint (forward + replay per path)
     adj_ms, adj_n = ktimes["adjoint"]
-    adj_paths = 4 * npix  # per launch: 2 proportional paths + 1 pair per pixel
-    flop_path = FLOP_CAMERA * 2 + vpp * (flops_per_vertex(len(spec.spheres), False) +
-                                         flops_per_vertex(len(spec.spheres), True))
-    achieved = adj_paths * flop_path / (adj_ms / max(adj_n, 1) / 1e3) / 1e12
+    adj_launch_ms = adj_ms / max(adj_n, 1)
+    adj_paths = paths_counted / n_count  # per launch: 2 proportional paths + 1 pair per pixel
+    flop_path = vpp * (FLOP_FORWARD_VERTEX + FLOP_REPLAY_VERTEX)
+    achieved = adj_paths * flop_path / (adj_launch_ms / 1e3) / 1e12
     line = {
         "metric": "differentiable paths/s (fwd+adjoint); time-to-loss vs plain Adam, same GPU",
         "value": value,
@@ -172,9 +221,10 @@ def main():
                    "pixels": npix, "params": spec.n_params, "diff_paths_per_step": 4 * npix},
         "roofline": {"bound": "alu", "achieved": achieved, "peak": PEAK_FP32_VECTOR_TFLOPS,
                      "unit": "TFLOP/s", "frac": achieved / PEAK_FP32_VECTOR_TFLOPS,
-                     "traffic": None, "kernel": "k_adjoint",
-                     "kernel_ms": adj_ms / max(adj_n, 1),
+                     "traffic": measured_traffic(), "kernel": "k_adjoint",
+                     "kernel_ms": adj_launch_ms, "paths_per_launch": adj_paths,
                      "flop_per_path": flop_path, "vertices_per_path": vpp},
+        "vertices_per_s": value * vpp,
         "kernel_ms_per_step": {k: v[0] / max(v[1], 1) for k, v in ktimes.items()},
         "cpu_baseline": cpu,
     }

@@ -258,6 +258,17 @@ int jso_set_timing(jso_ctx* ctx, int enable);
  * events.  reset != 0 clears the totals afterwards. */
 int jso_get_kernel_time(jso_ctx* ctx, int kernel, double* ms, uint64_t* launches, int reset);
 
+/* Work counters of the replayed adjoint, for throughput accounting.  While
+ * enabled, every adjoint launch of this context adds to out[0] the paths it
+ * replays (a finite-difference pair counts two) and to out[1] their surface
+ * vertices (one traversal; forward and replay visit the same vertices).
+ * Enabling allocates 16 bytes of device memory on first use; counting costs
+ * one 64-bit atomic per wave.  jso_get_work waits for the context's stream,
+ * copies the two totals to the host array out[2] and, if reset != 0, clears
+ * them.  Errors: JSO_E_INVALID for a null ctx/out. */
+int jso_set_work_counting(jso_ctx* ctx, int enable);
+int jso_get_work(jso_ctx* ctx, uint64_t out[2], int reset);
+
 /* ---- checkpoint ---------------------------------------------------------------- */
 int jso_get_state(jso_ctx* ctx, int scene_id, jso_state* st);
 int jso_set_state(jso_ctx* ctx, int scene_id, const jso_state* st);

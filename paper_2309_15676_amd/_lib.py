@@ -33,7 +33,7 @@ EXPORTED = [
     "jso_scene_info", "jso_set_params", "jso_get_params", "jso_get_params_prev",
     "jso_set_target", "jso_render", "jso_render_bwd", "jso_estimate_gradients",
     "jso_meta_step", "jso_adam_step", "jso_grad_step", "jso_get_state", "jso_set_state",
-    "jso_set_timing", "jso_get_kernel_time",
+    "jso_set_timing", "jso_get_kernel_time", "jso_set_work_counting", "jso_get_work",
 ]
 JSO_K_PRIMAL, JSO_K_ADJOINT, JSO_K_META, JSO_K_ADAM = 0, 1, 2, 3
 
@@ -134,6 +134,8 @@ def load() -> ctypes.CDLL:
         "jso_set_state": (I, [P, I, P]),
         "jso_set_timing": (I, [P, I]),
         "jso_get_kernel_time": (I, [P, I, ctypes.POINTER(D), ctypes.POINTER(U64), I]),
+        "jso_set_work_counting": (I, [P, I]),
+        "jso_get_work": (I, [P, ctypes.POINTER(U64), I]),
     }
     for name, (res, args) in sig.items():
         fn = getattr(L, name)
@@ -368,3 +370,14 @@ def jso_get_kernel_time(ctx, kernel: int, reset: bool = False):
     check(load().jso_get_kernel_time(ctx, kernel, ctypes.byref(ms), ctypes.byref(n),
                                      1 if reset else 0), ctx, "jso_get_kernel_time")
     return ms.value, n.value
+
+
+def jso_set_work_counting(ctx, enable: bool) -> int:
+    return load().jso_set_work_counting(ctx, 1 if enable else 0)
+
+
+def jso_get_work(ctx, reset: bool = False):
+    """(paths, surface vertices) replayed by the adjoint since counting was enabled/reset."""
+    out = (ctypes.c_uint64 * 2)()
+    check(load().jso_get_work(ctx, out, 1 if reset else 0), ctx, "jso_get_work")
+    return int(out[0]), int(out[1])

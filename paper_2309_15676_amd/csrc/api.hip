@@ -87,6 +87,8 @@ struct jso_ctx {
   std::string err;
   std::vector<std::unique_ptr<SceneGPU>> scenes;
   KernelTimer timer;
+  unsigned long long* d_work = nullptr;  // adjoint work counters (paths, vertices)
+  bool counting = false;
 };
 
 namespace {
@@ -320,21 +322,25 @@ int queue_estimators(jso_ctx* c, SceneGPU* s, uint64_t seed, uint32_t iteration,
   pa.flags = flags;
   TIMED_LAUNCH(c, JSO_K_PRIMAL, launch_primal(s->d_scene, pa, np, c->stream));
 
+  // Pair slices come first: blocks are dispatched in slice order, and a pair
+  // block traces twice the paths of a single one, so the long blocks start
+  // early and the short ones fill the end of the launch.
   AdjointArgs aa{};
   int nj = 0, z = 0;
-  aa.jobs[nj++] = AdjointJob{params, d_prop, nullptr, nullptr, F, 1.0f,
-                             (float)(1.0 / spp_prop), prop_adj_tag, 0, z};
-  z += spp_prop;
   if (fd) {
     aa.jobs[nj++] = AdjointJob{params, d_cur, params_prev, d_prev, dF, 1.0f,
                                (float)(1.0 / spp_fd), JSO_TAG_ADJ_FD, 0, z};
     z += spp_fd;
   }
+  aa.jobs[nj++] = AdjointJob{params, d_prop, nullptr, nullptr, F, 1.0f,
+                             (float)(1.0 / spp_prop), prop_adj_tag, 0, z};
+  z += spp_prop;
   aa.n_jobs = nj;
   aa.key = pa.key;
   aa.crop = crop;
   aa.mask = mask;
   aa.flags = flags;
+  aa.work = c->counting ? c->d_work : nullptr;
   TIMED_LAUNCH(c, JSO_K_ADJOINT, launch_adjoint(s->d_scene, aa, z, c->stream));
   return JSO_OK;
 }
@@ -416,6 +422,7 @@ int jso_destroy(jso_ctx* c) {
   for (auto& s : c->scenes)
     if (s) free_scene_buffers(s.get());
   c->timer.destroy();
+  if (c->d_work) (void)hipFree(c->d_work);
   delete c;
   return JSO_OK;
 }
@@ -598,6 +605,7 @@ int jso_render_bwd(jso_ctx* c, int id, const float* params, uint64_t seed, uint3
   aa.crop = crop_of(s, opts);
   aa.mask = opts ? opts->pixel_mask : nullptr;
   aa.flags = c->debug_flags | (opts ? opts->flags : 0u);
+  aa.work = c->counting ? c->d_work : nullptr;
   TIMED_LAUNCH(c, JSO_K_ADJOINT, launch_adjoint(s->d_scene, aa, spp, c->stream));
   return JSO_OK;
 }
@@ -728,6 +736,32 @@ int jso_get_kernel_time(jso_ctx* c, int kernel, double* ms, uint64_t* launches, 
     c->timer.ms[kernel] = 0.0;
     c->timer.launches[kernel] = 0;
   }
+  return JSO_OK;
+}
+
+int jso_set_work_counting(jso_ctx* c, int enable) {
+  if (!c) return JSO_E_INVALID;
+  DeviceGuard g(c->device);
+  if (enable && !c->d_work) {
+    HIP_TRY(c, hipMalloc(&c->d_work, 2 * sizeof(unsigned long long)));
+    HIP_TRY(c, hipMemset(c->d_work, 0, 2 * sizeof(unsigned long long)));
+  }
+  c->counting = enable != 0;
+  return JSO_OK;
+}
+
+int jso_get_work(jso_ctx* c, uint64_t out[2], int reset) {
+  if (!c) return JSO_E_INVALID;
+  if (!out) return fail(c, JSO_E_INVALID, "null output");
+  out[0] = out[1] = 0;
+  if (!c->d_work) return JSO_OK;
+  DeviceGuard g(c->device);
+  HIP_TRY(c, hipStreamSynchronize(c->stream));
+  unsigned long long h[2];
+  HIP_TRY(c, hipMemcpy(h, c->d_work, sizeof(h), hipMemcpyDeviceToHost));
+  out[0] = h[0];
+  out[1] = h[1];
+  if (reset) HIP_TRY(c, hipMemset(c->d_work, 0, sizeof(h)));
   return JSO_OK;
 }
 

@@ -75,6 +75,7 @@ struct AdjointArgs {
   Crop crop;
   const uint8_t* mask;
   uint32_t flags;
+  unsigned long long* work;  // nullable: [0] += paths replayed, [1] += their surface vertices
 };
 
 struct MetaArgs {

@@ -50,6 +50,12 @@ __device__ __forceinline__ float wave_sum(float v) {
   return v;
 }
 
+__device__ __forceinline__ int wave_sum(int v) {
+#pragma unroll
+  for (int off = 32; off > 0; off >>= 1) v += __shfl_xor(v, off, 64);
+  return v;
+}
+
 // Blocks are kTile x kTile pixel tiles (256 lanes = four wave64 rows of 16 x 4).
 constexpr int kTile = 16;
 constexpr int kBlock = kTile * kTile;
@@ -317,10 +323,12 @@ k_adjoint(const DevScene* __restrict__ Sp, AdjointArgs A) {
       path_begin(S, rng, px, py, A.flags, Pb);
     }
   }
+  int n_vert = 0;
   if (!pair) {
     while (__ballot(Pa.alive) != 0) {
       VertexGrad va;
       va.valid = false;
+      n_vert += Pa.alive ? 1 : 0;
       if (Pa.alive) path_vertex<true>(S, job.params, rng, A.flags, Pa, adj_a, Ca, va);
       const bool later = sink.add(S, va, job.sign);
       scatter_wave(S, job.grad, va, job.sign, later);
@@ -331,6 +339,7 @@ k_adjoint(const DevScene* __restrict__ Sp, AdjointArgs A) {
     while (__ballot(Pa.alive || Pb.alive) != 0) {
       VertexGrad va, vb;
       va.valid = vb.valid = false;
+      n_vert += (Pa.alive ? 1 : 0) + (Pb.alive ? 1 : 0);
       if (Pa.alive) path_vertex<true>(S, job.params, rng, A.flags, Pa, adj_a, Ca, va);
       if (Pb.alive) path_vertex<true>(S, job.params_b, rng, A.flags, Pb, adj_b, Cb, vb);
       if (va.valid && vb.valid && same_footprint(va.fp, vb.fp)) {
@@ -342,6 +351,14 @@ k_adjoint(const DevScene* __restrict__ Sp, AdjointArgs A) {
       const bool later_b = sink.add(S, vb, -1.0f);
       scatter_wave(S, job.grad, va, 1.0f, later_a);
       scatter_wave(S, job.grad, vb, -1.0f, later_b);
+    }
+  }
+  if (A.work) {
+    const int paths = wave_sum(active ? (pair ? 2 : 1) : 0);
+    const int verts = wave_sum(n_vert);
+    if ((threadIdx.x & 63) == 0) {
+      atomicAdd(A.work, (unsigned long long)paths);
+      atomicAdd(A.work + 1, (unsigned long long)verts);
     }
   }
   sink.flush(S);

@@ -266,6 +266,32 @@ def test_render_bwd_and_autograd(ctx):
     assert torch.equal(img.detach(), fwd)
 
 
+def test_work_counters_match_oracle_path_statistics(ctx):
+    """The adjoint's path and surface-vertex counters against the oracle's own
+    count of the same traces: paths exactly, vertices up to the few paths that
+    FP32 rounding sends elsewhere."""
+    import torch
+    from paper_2309_15676_amd import _lib as L
+    _say("work counters")
+    spec, p = _case("textured")
+    prob = _problem(ctx, spec)
+    dimg = (I.target_image_synthetic(spec, 12) - 0.75).astype(np.float32)
+    seed, it, tag, spp = 7, 2, O.TAG_EVAL, 2
+    O.reset_stats()
+    O.render_bwd(spec, p.astype(np.float64), dimg.astype(np.float64), seed, it, tag, spp)
+    ref = O.get_stats()
+    L.check(L.jso_set_work_counting(prob.ctx, True), prob.ctx)
+    L.jso_get_work(prob.ctx, reset=True)
+    prob.render_bwd(p, torch.from_numpy(dimg).cuda(), seed, it, tag, spp)
+    paths, verts = L.jso_get_work(prob.ctx, reset=True)
+    L.check(L.jso_set_work_counting(prob.ctx, False), prob.ctx)
+    assert paths == ref["paths"] == spec.n_pixels * spp
+    assert abs(verts - ref["vertices"]) <= 2e-3 * ref["vertices"], (verts, ref)
+    # counting off: the totals stay put
+    prob.render_bwd(p, torch.from_numpy(dimg).cuda(), seed, it, tag, spp)
+    assert L.jso_get_work(prob.ctx) == (0, 0)
+
+
 def _meta_problem(ctx, tex=16):
     spec = I.scene_textured(8, 8, tex, seed=0, depth=2)
     return spec, _problem(ctx, spec)
