@@ -31,6 +31,7 @@ struct SceneGPU {
   float *adam_m = nullptr, *adam_v = nullptr;
   Ctl* ctl = nullptr;
   double* scratch_loss = nullptr;  // 2 slots for stand-alone estimator calls
+  double* partials = nullptr;      // per-block partial sums of the meta step
   DevScene* d_scene = nullptr;     // device copy of `dev` read by the kernels
   uint32_t host_iter = 0;          // mirror of ctl->iteration
 };
@@ -147,7 +148,7 @@ void free_scene_buffers(SceneGPU* s) {
   void* bufs[] = {s->params, s->params_prev, s->target, s->F,      s->dF,
                   s->delta,  s->mean,        s->var,    s->alpha_prev, s->m2F,
                   s->m2D,    s->adam_m,      s->adam_v, s->ctl,    s->scratch_loss,
-                  s->d_scene};
+                  s->partials, s->d_scene};
   for (void* b : bufs)
     if (b) (void)hipFree(b);
 }
@@ -358,6 +359,7 @@ MetaArgs meta_args(SceneGPU* s, const float* F, const float* dF, float eta, floa
   m.m2F = s->m2F;
   m.m2D = s->m2D;
   m.ctl = s->ctl;
+  m.partials = s->partials;
   m.n = s->P;
   m.n_ch = s->n_ch;
   for (int k = 0; k < 5; ++k) {
@@ -489,6 +491,7 @@ int jso_load_scene(jso_ctx* c, const jso_scene_desc* d, int* scene_id) {
   A(dalloc(&s->adam_v, P));
   A(dalloc(&s->ctl, 1));
   A(dalloc(&s->scratch_loss, 2));
+  A(dalloc(&s->partials, kMetaMaxBlocks));
   A(dalloc(&s->d_scene, 1));
   if (e != hipSuccess) {
     free_scene_buffers(s.get());

@@ -33,6 +33,7 @@ struct KeyArgs {
 };
 
 constexpr int kMaxPrimalJobs = 4;
+constexpr int kMetaMaxBlocks = 1024;
 constexpr int kMaxAdjointJobs = 4;
 
 struct PrimalJob {
@@ -85,6 +86,7 @@ struct MetaArgs {
   float* dF;
   double *mean, *var, *alpha_prev, *m2F, *m2D;
   Ctl* ctl;
+  double* partials;  // kMetaMaxBlocks per-block sums of the squared step
   size_t n;
   int n_ch;
   float lo[5], hi[5];

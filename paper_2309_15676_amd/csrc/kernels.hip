@@ -367,9 +367,18 @@ k_adjoint(const DevScene* __restrict__ Sp, AdjointArgs A) {
 // ---------------------------------------------------------------------------
 // fused meta-estimator + stabilised step
 // ---------------------------------------------------------------------------
-__global__ void __launch_bounds__(256) k_meta(MetaArgs A) {
+// Each thread takes kMetaK elements, one block-width apart, with every load
+// issued before the arithmetic so the HBM latency is paid once.  The squared
+// step is reduced per block into A.partials; the last block to finish sums
+// the partials in block order (a deterministic ||pi_{i+1} - pi_i||^2) and
+// advances the iteration state.
+constexpr int kMetaK = 4;
+constexpr int kMetaBlock = 256;
+
+__global__ void __launch_bounds__(kMetaBlock) k_meta(MetaArgs A) {
   __shared__ double s_coef[4];
-  __shared__ double s_red[4];
+  __shared__ double s_red[kMetaBlock / 64];
+  __shared__ bool s_last;
   Ctl* ctl = A.ctl;
   const uint32_t it = ctl->iteration;
   if (threadIdx.x == 0) {
@@ -386,46 +395,65 @@ __global__ void __launch_bounds__(256) k_meta(MetaArgs A) {
   const double wF = s_coef[0], wD = s_coef[1], n2 = s_coef[2];
   const bool takeD = s_coef[3] != 0.0;
   const double sq_n2 = takeD ? sqrt(n2) : 1.0;
+  const uint32_t n = (uint32_t)A.n, nc = (uint32_t)A.n_ch;
   double local = 0.0;
-  const size_t stride = (size_t)gridDim.x * blockDim.x;
-  for (size_t i = (size_t)blockIdx.x * blockDim.x + threadIdx.x; i < A.n; i += stride) {
-    const double F = (double)A.F[i];
-    const double dF = takeD ? (double)A.dF[i] : 0.0;
-    // Var[F] (Eq. 9; bias-corrected Moment2)
-    double m2F = A.m2F[i];
-    m2F = m2F + wF * (F * F - m2F);
-    // Var[dF] (Eq. 13-14)
-    double m2D = A.m2D[i];
-    double varD = 0.0;
-    if (takeD) {
-      const double x = dF / sq_n2;
-      m2D = m2D + wD * (x * x - m2D);
-      varD = m2D * n2;
+  const uint32_t span = kMetaBlock * kMetaK;
+  for (uint32_t base = blockIdx.x * span + threadIdx.x; base < n; base += gridDim.x * span) {
+    float F[kMetaK], dF[kMetaK], p[kMetaK];
+    double m2F[kMetaK], m2D[kMetaK], mean[kMetaK], var[kMetaK], ap[kMetaK];
+#pragma unroll
+    for (int e = 0; e < kMetaK; ++e) {
+      const uint32_t i = base + (uint32_t)e * kMetaBlock;
+      if (i < n) {
+        F[e] = A.F[i];
+        dF[e] = takeD ? A.dF[i] : 0.0f;
+        p[e] = A.params[i];
+        m2F[e] = A.m2F[i];
+        m2D[e] = A.m2D[i];
+        mean[e] = A.mean[i];
+        var[e] = A.var[i];
+        ap[e] = A.alpha_prev[i];
+      }
     }
-    // carry the previous estimate forward, weight (Eq. 8, 17), combine (Eq. 7, 15)
-    double mean = A.mean[i] + dF;
-    double var = A.var[i] + varD;
-    double a = m2F / (m2F + var + 1e-30);
-    a = fmin(a, 1.0 / (2.0 - A.alpha_prev[i]));
-    mean = a * mean + (1.0 - a) * F;
-    var = a * a * var + (1.0 - a) * (1.0 - a) * m2F;
-    // stabilised step (Eq. 21) and projection
-    const double step = -(double)A.eta * mean / (sqrt(var) + 1e-8);
-    const float p = A.params[i];
-    const int ch = (int)(i % (size_t)A.n_ch);
-    const float pn = fminf(fmaxf((float)((double)p + step), A.lo[ch]), A.hi[ch]);
-    const double dp = (double)pn - (double)p;
-    local += dp * dp;
-    A.m2F[i] = m2F;
-    A.m2D[i] = m2D;
-    A.mean[i] = mean;
-    A.var[i] = var;
-    A.alpha_prev[i] = a;
-    A.params_prev[i] = p;
-    A.params[i] = pn;
-    if (A.zero_grads) {
-      A.F[i] = 0.0f;
-      A.dF[i] = 0.0f;
+#pragma unroll
+    for (int e = 0; e < kMetaK; ++e) {
+      const uint32_t i = base + (uint32_t)e * kMetaBlock;
+      if (i >= n) continue;
+      const double f = (double)F[e], df = (double)dF[e];
+      // Var[F] (Eq. 9; bias-corrected Moment2)
+      const double mF = m2F[e] + wF * (f * f - m2F[e]);
+      // Var[dF] (Eq. 13-14)
+      double mD = m2D[e];
+      double varD = 0.0;
+      if (takeD) {
+        const double x = df / sq_n2;
+        mD = mD + wD * (x * x - mD);
+        varD = mD * n2;
+      }
+      // carry the previous estimate forward, weight (Eq. 8, 17), combine (Eq. 7, 15)
+      double mu = mean[e] + df;
+      double v = var[e] + varD;
+      double a = mF / (mF + v + 1e-30);
+      a = fmin(a, 1.0 / (2.0 - ap[e]));
+      mu = a * mu + (1.0 - a) * f;
+      v = a * a * v + (1.0 - a) * (1.0 - a) * mF;
+      // stabilised step (Eq. 21) and projection
+      const double step = -(double)A.eta * mu / (sqrt(v) + 1e-8);
+      const uint32_t ch = i % nc;
+      const float pn = fminf(fmaxf((float)((double)p[e] + step), A.lo[ch]), A.hi[ch]);
+      const double dp = (double)pn - (double)p[e];
+      local += dp * dp;
+      A.m2F[i] = mF;
+      A.m2D[i] = mD;
+      A.mean[i] = mu;
+      A.var[i] = v;
+      A.alpha_prev[i] = a;
+      A.params_prev[i] = p[e];
+      A.params[i] = pn;
+      if (A.zero_grads) {
+        A.F[i] = 0.0f;
+        A.dF[i] = 0.0f;
+      }
     }
   }
   // ||pi_{i+1} - pi_i||^2 for the next iteration
@@ -435,21 +463,30 @@ __global__ void __launch_bounds__(256) k_meta(MetaArgs A) {
   __syncthreads();
   if (threadIdx.x == 0) {
     double tot = 0.0;
-    for (int w = 0; w < (int)(blockDim.x >> 6); ++w) tot += s_red[w];
-    if (tot != 0.0) unsafeAtomicAdd(&ctl->norm2[(it + 1u) & 1u], tot);
+    for (int w = 0; w < kMetaBlock / 64; ++w) tot += s_red[w];
+    A.partials[blockIdx.x] = tot;
     __threadfence();
-    const uint32_t done = atomicAdd(&ctl->blocks_done, 1u);
-    if (done == gridDim.x - 1u) {
-      // last block: all blocks have read this iteration's inputs
-      __threadfence();
-      ctl->count_F = ctl->count_F + 1u;
-      if (takeD) ctl->count_D = ctl->count_D + 1u;
-      ctl->norm2[it & 1u] = 0.0;
-      ctl->loss[(it + 1u) & 1u] = 0.0;
-      ctl->iteration = it + 1u;
-      ctl->blocks_done = 0u;
-      __threadfence();
-    }
+    s_last = atomicAdd(&ctl->blocks_done, 1u) == gridDim.x - 1u;
+  }
+  __syncthreads();
+  if (!s_last) return;
+  // last block: every block's partial is visible and every block has read
+  // this iteration's inputs
+  __threadfence();
+  double sum = 0.0;
+  if (threadIdx.x < 64) {
+    for (uint32_t b = threadIdx.x; b < gridDim.x; b += 64) sum += A.partials[b];
+    sum = wave_sum(sum);
+  }
+  if (threadIdx.x == 0) {
+    ctl->norm2[(it + 1u) & 1u] = sum;
+    ctl->count_F = ctl->count_F + 1u;
+    if (takeD) ctl->count_D = ctl->count_D + 1u;
+    ctl->norm2[it & 1u] = 0.0;
+    ctl->loss[(it + 1u) & 1u] = 0.0;
+    ctl->iteration = it + 1u;
+    ctl->blocks_done = 0u;
+    __threadfence();
   }
 }
 
@@ -535,7 +572,10 @@ static unsigned elementwise_grid(size_t n) {
 }
 
 hipError_t launch_meta(const MetaArgs& A, hipStream_t st) {
-  hipLaunchKernelGGL(k_meta, dim3(elementwise_grid(A.n)), dim3(256), 0, st, A);
+  if (A.n >= (size_t)1 << 31 || A.n_ch < 1 || !A.partials) return hipErrorInvalidValue;
+  const size_t want = cdiv(A.n, (size_t)kMetaBlock * kMetaK);
+  const unsigned grid = (unsigned)(want < 1 ? 1 : (want > kMetaMaxBlocks ? kMetaMaxBlocks : want));
+  hipLaunchKernelGGL(k_meta, dim3(grid), dim3(kMetaBlock), 0, st, A);
   return hipGetLastError();
 }
 
