@@ -12,11 +12,12 @@ meta-estimator + stabilised step.  Inputs are synthetic and already resident
 on the GPU when the timed region starts.
 
 Prints one JSON line.  `value` = differentiable paths/s (forward + replayed
-adjoint); `roofline` = the dominant kernel (the replayed adjoint): its
-algorithmic FP32 work (surface vertices counted on the GPU x per-vertex FLOP
-figures) per launch over its HIP-event launch time, against the FP32 vector
-peak, with `traffic` = HBM bytes per launch from the committed rocprofv3
-counter summary (null when the kernel changed since it was taken);
+adjoint); `roofline` = the dominant kernel (forward tracing or the replayed
+adjoint, whichever takes longer): its algorithmic FP32 work (surface vertices
+counted on the GPU x per-vertex FLOP figures) per launch over its HIP-event
+launch time, against the FP32 vector peak, with `traffic` = HBM bytes per
+launch from the committed rocprofv3 counter summary (null when the kernel
+changed since it was taken);
 `cpu_baseline` = the FP64 CPU oracle on the same workload for about 10 s.
 """
 from __future__ import annotations
@@ -45,7 +46,7 @@ FLOP_REPLAY_VERTEX = 1000
 
 KERNEL_SOURCES = ("paper_2309_15676_amd/csrc/device.h", "paper_2309_15676_amd/csrc/kernels.h",
                   "paper_2309_15676_amd/csrc/kernels.hip")
-TRAFFIC_SUMMARY = "profiles/k_adjoint_textured512_hbm_traffic.md"
+TRAFFIC_SUMMARY = "profiles/%s_textured512_hbm_traffic.md"
 
 
 def kernel_source_hash() -> str:
@@ -57,10 +58,10 @@ def kernel_source_hash() -> str:
     return h.hexdigest()
 
 
-def measured_traffic():
-    """HBM bytes per k_adjoint launch from the committed rocprofv3 counter
+def measured_traffic(kernel: str):
+    """HBM bytes per launch of `kernel` from the committed rocprofv3 counter
     summary, or None when the kernel sources changed since it was taken."""
-    path = os.path.join(ROOT, TRAFFIC_SUMMARY)
+    path = os.path.join(ROOT, TRAFFIC_SUMMARY % kernel)
     if not os.path.exists(path):
         return None
     with open(path) as fh:
@@ -156,7 +157,7 @@ def main():
         prob.grad_step(opts)
     torch.cuda.synchronize()
     L.check(L.jso_set_timing(ctx, True), ctx)
-    for k in range(4):
+    for k in range(L.JSO_K_COUNT):
         L.jso_get_kernel_time(ctx, k, reset=True)
     e0, e1 = torch.cuda.Event(enable_timing=True), torch.cuda.Event(enable_timing=True)
     torch.cuda.synchronize()
@@ -167,17 +168,18 @@ def main():
     torch.cuda.synchronize()
     total_ms = e0.elapsed_time(e1)
     ktimes = {name: L.jso_get_kernel_time(ctx, k) for k, name in
-              ((L.JSO_K_PRIMAL, "primal"), (L.JSO_K_ADJOINT, "adjoint"), (L.JSO_K_META, "meta"))}
+              ((L.JSO_K_FORWARD, "forward"), (L.JSO_K_FINALIZE, "finalize"),
+               (L.JSO_K_ADJOINT, "adjoint"), (L.JSO_K_META, "meta"))}
     L.check(L.jso_set_timing(ctx, False), ctx)
-    # work of the adjoint launches, counted on the GPU (outside the timed region)
+    # work of the path-tracing launches, counted on the GPU (outside the timed region)
     L.check(L.jso_set_work_counting(ctx, True), ctx)
     L.jso_get_work(ctx, reset=True)
     n_count = 3
     for _ in range(n_count):
         prob.grad_step(opts)
-    paths_counted, verts_counted = L.jso_get_work(ctx, reset=True)
+    rep_paths, rep_verts, fwd_paths, fwd_verts = L.jso_get_work(ctx, reset=True)
     L.check(L.jso_set_work_counting(ctx, False), ctx)
-    vpp = verts_counted / max(paths_counted, 1)
+    vpp = rep_verts / max(rep_paths, 1)
     st = prob.grad_step(opts, want_stats=True)
     print("[bench] kernel ms per step: %s; loss %.5g; %.4f vertices per path" % (
         {k: round(v[0] / max(v[1], 1), 4) for k, v in ktimes.items()}, st.loss, vpp),
@@ -196,12 +198,18 @@ def main():
               flush=True)
         Tn = target.cpu().numpy().astype(np.float64)
         cpu = cpu_baseline(spec, init, Tn, args.cpu_seconds, args.seed)
-    # roofline of the dominant kernel: the replayed adjoint (forward + replay per path)
-    adj_ms, adj_n = ktimes["adjoint"]
-    adj_launch_ms = adj_ms / max(adj_n, 1)
-    adj_paths = paths_counted / n_count  # per launch: 2 proportional paths + 1 pair per pixel
-    flop_path = vpp * (FLOP_FORWARD_VERTEX + FLOP_REPLAY_VERTEX)
-    achieved = adj_paths * flop_path / (adj_launch_ms / 1e3) / 1e12
+    # roofline of the dominant kernel: algorithmic FP32 work per launch over
+    # its average launch time
+    cands = {
+        "k_forward": (ktimes["forward"], fwd_verts / n_count * FLOP_FORWARD_VERTEX,
+                      fwd_paths / n_count, fwd_verts / max(fwd_paths, 1)),
+        "k_adjoint": (ktimes["adjoint"], rep_verts / n_count * FLOP_REPLAY_VERTEX,
+                      rep_paths / n_count, vpp),
+    }
+    kname = max(cands, key=lambda k: cands[k][0][0])
+    (k_ms, k_n), k_flop, k_paths, k_vpp = cands[kname]
+    k_launch_ms = k_ms / max(k_n, 1)
+    achieved = k_flop / (k_launch_ms / 1e3) / 1e12
     line = {
         "metric": "differentiable paths/s (fwd+adjoint); time-to-loss vs plain Adam, same GPU",
         "value": value,
@@ -221,9 +229,9 @@ def main():
                    "pixels": npix, "params": spec.n_params, "diff_paths_per_step": 4 * npix},
         "roofline": {"bound": "alu", "achieved": achieved, "peak": PEAK_FP32_VECTOR_TFLOPS,
                      "unit": "TFLOP/s", "frac": achieved / PEAK_FP32_VECTOR_TFLOPS,
-                     "traffic": measured_traffic(), "kernel": "k_adjoint",
-                     "kernel_ms": adj_launch_ms, "paths_per_launch": adj_paths,
-                     "flop_per_path": flop_path, "vertices_per_path": vpp},
+                     "traffic": measured_traffic(kname), "kernel": kname,
+                     "kernel_ms": k_launch_ms, "paths_per_launch": k_paths,
+                     "vertices_per_path": k_vpp},
         "vertices_per_s": value * vpp,
         "kernel_ms_per_step": {k: v[0] / max(v[1], 1) for k, v in ktimes.items()},
         "cpu_baseline": cpu,

@@ -244,11 +244,12 @@ int jso_grad_step(jso_ctx* ctx, const int* scene_ids, int n, const jso_step_opts
 /* ---- kernel timing --------------------------------------------------------------- */
 
 /* Kernel classes reported by jso_get_kernel_time */
-#define JSO_K_PRIMAL 0  /* primal renders and adjoint images            */
-#define JSO_K_ADJOINT 1 /* replayed adjoint (proportional + FD pairs)    */
-#define JSO_K_META 2    /* fused meta-estimator step                     */
-#define JSO_K_ADAM 3    /* Adam step                                     */
-#define JSO_K_COUNT 4
+#define JSO_K_FORWARD 0  /* forward path tracing (primal and adjoint paths) */
+#define JSO_K_ADJOINT 1  /* replayed adjoint (proportional + FD pairs)      */
+#define JSO_K_META 2     /* fused meta-estimator step                       */
+#define JSO_K_ADAM 3     /* Adam step                                       */
+#define JSO_K_FINALIZE 4 /* primal images, adjoint images and loss          */
+#define JSO_K_COUNT 5
 
 /* Enable (1) or disable (0) HIP-event timing of every kernel this context
  * launches (events are recorded on the context's stream around each launch). */
@@ -258,16 +259,17 @@ int jso_set_timing(jso_ctx* ctx, int enable);
  * events.  reset != 0 clears the totals afterwards. */
 int jso_get_kernel_time(jso_ctx* ctx, int kernel, double* ms, uint64_t* launches, int reset);
 
-/* Work counters of the replayed adjoint, for throughput accounting.  While
- * enabled, every adjoint launch of this context adds to out[0] the paths it
- * replays (a finite-difference pair counts two) and to out[1] their surface
- * vertices (one traversal; forward and replay visit the same vertices).
- * Enabling allocates 16 bytes of device memory on first use; counting costs
- * one 64-bit atomic per wave.  jso_get_work waits for the context's stream,
- * copies the two totals to the host array out[2] and, if reset != 0, clears
- * them.  Errors: JSO_E_INVALID for a null ctx/out. */
+/* Work counters, for throughput accounting.  While enabled, the launches of
+ * this context add: out[0] the paths the adjoint replays (a finite-difference
+ * pair counts two), out[1] their surface vertices; out[2] the paths traced
+ * forward (primal samples and the adjoint paths' forward passes), out[3]
+ * their surface vertices.  Enabling allocates 32 bytes of device memory on
+ * first use; counting costs one 64-bit atomic per wave and counter.
+ * jso_get_work waits for the context's stream, copies the four totals to the
+ * host array out[4] and, if reset != 0, clears them.
+ * Errors: JSO_E_INVALID for a null ctx/out. */
 int jso_set_work_counting(jso_ctx* ctx, int enable);
-int jso_get_work(jso_ctx* ctx, uint64_t out[2], int reset);
+int jso_get_work(jso_ctx* ctx, uint64_t out[4], int reset);
 
 /* ---- checkpoint ---------------------------------------------------------------- */
 int jso_get_state(jso_ctx* ctx, int scene_id, jso_state* st);

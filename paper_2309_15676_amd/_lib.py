@@ -35,7 +35,8 @@ EXPORTED = [
     "jso_meta_step", "jso_adam_step", "jso_grad_step", "jso_get_state", "jso_set_state",
     "jso_set_timing", "jso_get_kernel_time", "jso_set_work_counting", "jso_get_work",
 ]
-JSO_K_PRIMAL, JSO_K_ADJOINT, JSO_K_META, JSO_K_ADAM = 0, 1, 2, 3
+JSO_K_FORWARD, JSO_K_ADJOINT, JSO_K_META, JSO_K_ADAM, JSO_K_FINALIZE = 0, 1, 2, 3, 4
+JSO_K_COUNT = 5
 
 
 class JsoError(RuntimeError):
@@ -377,7 +378,8 @@ def jso_set_work_counting(ctx, enable: bool) -> int:
 
 
 def jso_get_work(ctx, reset: bool = False):
-    """(paths, surface vertices) replayed by the adjoint since counting was enabled/reset."""
-    out = (ctypes.c_uint64 * 2)()
+    """(replayed paths, their vertices, forward-traced paths, their vertices)
+    since counting was enabled/reset."""
+    out = (ctypes.c_uint64 * 4)()
     check(load().jso_get_work(ctx, out, 1 if reset else 0), ctx, "jso_get_work")
-    return int(out[0]), int(out[1])
+    return tuple(int(v) for v in out)

@@ -25,6 +25,10 @@ FLAGS = [
     "-ffp-contract=on",
     # no packed-FP32 instructions
     "-Xclang", "-target-feature", "-Xclang", "-packed-fp32-ops",
+    # FP32 division and square root by the hardware reciprocal / square-root
+    # instructions (about 1 ulp) instead of the correctly rounded sequences;
+    # far inside the FP32-vs-FP64 tolerance, 15% fewer instructions per vertex
+    "-fno-hip-fp32-correctly-rounded-divide-sqrt",
     "-I" + os.path.join(ROOT, "include"),
     "-I" + CSRC,
 ]

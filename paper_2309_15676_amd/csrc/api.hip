@@ -32,6 +32,8 @@ struct SceneGPU {
   Ctl* ctl = nullptr;
   double* scratch_loss = nullptr;  // 2 slots for stand-alone estimator calls
   double* partials = nullptr;      // per-block partial sums of the meta step
+  double* slots = nullptr;         // per-path radiance, kMaxSlots per pixel (3 doubles each)
+  double* accum = nullptr;         // per-pixel radiance sums of up to 3 primal images
   DevScene* d_scene = nullptr;     // device copy of `dev` read by the kernels
   uint32_t host_iter = 0;          // mirror of ctl->iteration
 };
@@ -88,7 +90,7 @@ struct jso_ctx {
   std::string err;
   std::vector<std::unique_ptr<SceneGPU>> scenes;
   KernelTimer timer;
-  unsigned long long* d_work = nullptr;  // adjoint work counters (paths, vertices)
+  unsigned long long* d_work = nullptr;  // work counters (replay paths/vertices, forward paths/vertices)
   bool counting = false;
 };
 
@@ -148,7 +150,7 @@ void free_scene_buffers(SceneGPU* s) {
   void* bufs[] = {s->params, s->params_prev, s->target, s->F,      s->dF,
                   s->delta,  s->mean,        s->var,    s->alpha_prev, s->m2F,
                   s->m2D,    s->adam_m,      s->adam_v, s->ctl,    s->scratch_loss,
-                  s->partials, s->d_scene};
+                  s->partials, s->slots,     s->accum,  s->d_scene};
   for (void* b : bufs)
     if (b) (void)hipFree(b);
 }
@@ -294,7 +296,172 @@ hipMemcpyKind kind_from_dev(int mem) {
   return mem == JSO_MEM_DEVICE ? hipMemcpyDeviceToDevice : hipMemcpyDeviceToHost;
 }
 
-// Queue the primal + adjoint kernels of one gradient sample set.
+// ---------------------------------------------------------------------------
+// launch schedule
+//
+// Every path is traced by k_forward into a radiance slot; a primal image is
+// then reduced from its slots by k_finalize, and an adjoint path is replayed
+// by k_adjoint from its slot.  One k_forward launch fills at most kMaxSlots
+// slots per pixel, so larger sample counts run in chunks: a chunk of primal
+// samples is finalized (accumulated) before the next overwrites the slots,
+// and the replay of a chunk of adjoint samples follows their forward launch.
+// ---------------------------------------------------------------------------
+struct PrimalSpec {
+  const float* params;
+  uint32_t tag;
+  int spp;
+  float* img;     // nullable
+  float* delta;   // nullable
+  double* loss2;  // nullable
+};
+
+struct AdjointSpec {
+  const float* params;
+  const float* params_b;  // null: single paths; else finite-difference pairs (+A - B)
+  const float* delta;
+  const float* delta_b;
+  float* grad;
+  float sign;
+  uint32_t tag;
+  int spp;
+};
+
+struct Schedule {
+  jso_ctx* c;
+  SceneGPU* s;
+  KeyArgs key;
+  Crop crop;
+  const uint8_t* mask;
+  uint32_t flags;
+};
+
+FwdArgs fwd_args(const Schedule& q) {
+  FwdArgs f{};
+  f.key = q.key;
+  f.crop = q.crop;
+  f.mask = q.mask;
+  f.slots = q.s->slots;
+  f.npix = (uint32_t)q.s->npix;
+  f.flags = q.flags;
+  f.work = q.c->counting ? q.c->d_work : nullptr;
+  return f;
+}
+
+RepArgs rep_args(const Schedule& q) {
+  RepArgs r{};
+  r.key = q.key;
+  r.crop = q.crop;
+  r.mask = q.mask;
+  r.slots = q.s->slots;
+  r.npix = (uint32_t)q.s->npix;
+  r.flags = q.flags;
+  r.work = q.c->counting ? q.c->d_work : nullptr;
+  return r;
+}
+
+// One replay slice and the forward slices it needs.
+struct RepUnit {
+  int job, sample;
+};
+
+// Trace the primal images and reduce them; then trace and replay the adjoint
+// samples.  The adjoint's forward slices share the last primal launch when
+// they fit.
+int run_schedule(const Schedule& q, const PrimalSpec* pj, int np, const AdjointSpec* aj, int na) {
+  jso_ctx* c = q.c;
+  SceneGPU* s = q.s;
+  // replay units, pairs first: within a launch blocks are dispatched in slice
+  // order and a pair block traces twice the paths of a single one
+  std::vector<RepUnit> units;
+  for (int pass = 0; pass < 2; ++pass)
+    for (int j = 0; j < na; ++j)
+      if ((aj[j].params_b != nullptr) == (pass == 0))
+        for (int k = 0; k < aj[j].spp; ++k) units.push_back({j, k});
+  size_t next_unit = 0;
+  auto unit_slots = [&](const RepUnit& u) { return aj[u.job].params_b ? 2 : 1; };
+
+  // primal samples in job order
+  std::vector<std::pair<int, int>> prim;
+  for (int j = 0; j < np; ++j)
+    for (int k = 0; k < pj[j].spp; ++k) prim.push_back({j, k});
+  size_t next_prim = 0;
+  const FinArgs fin_base = [&] {
+    FinArgs f{};
+    f.slots = s->slots;
+    f.npix = (uint32_t)s->npix;
+    f.key = q.key;
+    f.crop = q.crop;
+    f.mask = q.mask;
+    f.target = s->target;
+    f.delta_scale = (float)(2.0 / (3.0 * (double)s->npix));
+    f.loss_scale = 1.0 / (3.0 * (double)s->npix);
+    return f;
+  }();
+
+  while (next_prim < prim.size() || next_unit < units.size()) {
+    FwdArgs f = fwd_args(q);
+    int n = 0;
+    // primal slices of this launch
+    FinArgs fin = fin_base;
+    while (next_prim < prim.size() && n < kMaxSlots) {
+      const int j = prim[next_prim].first, k = prim[next_prim].second;
+      f.sl[n] = FwdSlice{pj[j].params, pj[j].tag, (uint32_t)k, n};
+      if (fin.n_jobs == 0 || fin.jobs[fin.n_jobs - 1].slot0 + fin.jobs[fin.n_jobs - 1].n != n ||
+          fin.jobs[fin.n_jobs - 1].accum != s->accum + (size_t)j * 3 * s->npix) {
+        FinJob fj{};
+        fj.slot0 = n;
+        fj.n = 0;
+        fj.accum = s->accum + (size_t)j * 3 * s->npix;
+        fj.first = k == 0;
+        fj.inv_spp = 1.0 / (double)pj[j].spp;
+        fj.img = pj[j].img;
+        fj.delta = pj[j].delta;
+        fj.loss2 = pj[j].loss2;
+        fin.jobs[fin.n_jobs++] = fj;
+      }
+      FinJob& fj = fin.jobs[fin.n_jobs - 1];
+      fj.n++;
+      fj.last = k == pj[j].spp - 1;
+      ++n;
+      ++next_prim;
+    }
+    // adjoint forward slices, once every primal sample has a slot
+    RepArgs r = rep_args(q);
+    int nr = 0;
+    if (next_prim == prim.size()) {
+      while (next_unit < units.size() && n + unit_slots(units[next_unit]) <= kMaxSlots) {
+        const RepUnit u = units[next_unit++];
+        const AdjointSpec& a = aj[u.job];
+        RepSlice rs{};
+        rs.params = a.params;
+        rs.params_b = a.params_b;
+        rs.delta = a.delta;
+        rs.delta_b = a.delta_b;
+        rs.grad = a.grad;
+        rs.sign = a.sign;
+        rs.adj_scale = (float)(1.0 / (double)a.spp);
+        rs.tag = a.tag;
+        rs.sample = (uint32_t)u.sample;
+        rs.slot_a = n;
+        f.sl[n++] = FwdSlice{a.params, a.tag, (uint32_t)u.sample, rs.slot_a};
+        if (a.params_b) {
+          rs.slot_b = n;
+          f.sl[n++] = FwdSlice{a.params_b, a.tag, (uint32_t)u.sample, rs.slot_b};
+        }
+        r.sl[nr++] = rs;
+      }
+    }
+    if (n == 0) return fail(c, JSO_E_INVALID, "schedule: empty launch");
+    TIMED_LAUNCH(c, JSO_K_FORWARD, launch_forward(s->d_scene, f, n, c->stream));
+    if (fin.n_jobs > 0)
+      TIMED_LAUNCH(c, JSO_K_FINALIZE, launch_finalize(fin, s->width, c->stream));
+    if (nr > 0)
+      TIMED_LAUNCH(c, JSO_K_ADJOINT, launch_adjoint(s->d_scene, r, nr, s->n_ch, c->stream));
+  }
+  return JSO_OK;
+}
+
+// Queue the kernels of one gradient sample set.
 //   prop:  F += <F_i> from spp_prop paths at params
 //   fd:    dF += <dF_i> from spp_fd path pairs at (params, params_prev)
 int queue_estimators(jso_ctx* c, SceneGPU* s, uint64_t seed, uint32_t iteration,
@@ -306,44 +473,21 @@ int queue_estimators(jso_ctx* c, SceneGPU* s, uint64_t seed, uint32_t iteration,
   float* d_prop = s->delta;
   float* d_cur = s->delta + n3;
   float* d_prev = s->delta + 2 * n3;
-  PrimalArgs pa{};
-  int np = 0;
-  pa.jobs[np++] = PrimalJob{params, prop_primal_tag, spp_prop, d_prop, img, loss2};
   const bool fd = dF != nullptr && spp_fd > 0;
+  PrimalSpec pj[3];
+  int np = 0;
+  pj[np++] = PrimalSpec{params, prop_primal_tag, spp_prop, img, d_prop, loss2};
   if (fd) {
-    pa.jobs[np++] = PrimalJob{params, JSO_TAG_PRIMAL_FD, spp_fd, d_cur, nullptr, nullptr};
-    pa.jobs[np++] = PrimalJob{params_prev, JSO_TAG_PRIMAL_FD, spp_fd, d_prev, nullptr, nullptr};
+    pj[np++] = PrimalSpec{params, JSO_TAG_PRIMAL_FD, spp_fd, nullptr, d_cur, nullptr};
+    pj[np++] = PrimalSpec{params_prev, JSO_TAG_PRIMAL_FD, spp_fd, nullptr, d_prev, nullptr};
   }
-  pa.key = KeyArgs{seed, iteration, iter_ptr};
-  pa.crop = crop;
-  pa.mask = mask;
-  pa.target = s->target;
-  pa.delta_scale = (float)(2.0 / (3.0 * (double)s->npix));
-  pa.loss_scale = 1.0 / (3.0 * (double)s->npix);
-  pa.flags = flags;
-  TIMED_LAUNCH(c, JSO_K_PRIMAL, launch_primal(s->d_scene, pa, np, c->stream));
-
-  // Pair slices come first: blocks are dispatched in slice order, and a pair
-  // block traces twice the paths of a single one, so the long blocks start
-  // early and the short ones fill the end of the launch.
-  AdjointArgs aa{};
-  int nj = 0, z = 0;
-  if (fd) {
-    aa.jobs[nj++] = AdjointJob{params, d_cur, params_prev, d_prev, dF, 1.0f,
-                               (float)(1.0 / spp_fd), JSO_TAG_ADJ_FD, 0, z};
-    z += spp_fd;
-  }
-  aa.jobs[nj++] = AdjointJob{params, d_prop, nullptr, nullptr, F, 1.0f,
-                             (float)(1.0 / spp_prop), prop_adj_tag, 0, z};
-  z += spp_prop;
-  aa.n_jobs = nj;
-  aa.key = pa.key;
-  aa.crop = crop;
-  aa.mask = mask;
-  aa.flags = flags;
-  aa.work = c->counting ? c->d_work : nullptr;
-  TIMED_LAUNCH(c, JSO_K_ADJOINT, launch_adjoint(s->d_scene, aa, z, c->stream));
-  return JSO_OK;
+  AdjointSpec aj[2];
+  int na = 0;
+  aj[na++] = AdjointSpec{params, nullptr, d_prop, nullptr, F, 1.0f, prop_adj_tag, spp_prop};
+  if (fd)
+    aj[na++] = AdjointSpec{params, params_prev, d_cur, d_prev, dF, 1.0f, JSO_TAG_ADJ_FD, spp_fd};
+  const Schedule q{c, s, KeyArgs{seed, iteration, iter_ptr}, crop, mask, flags};
+  return run_schedule(q, pj, np, aj, na);
 }
 
 MetaArgs meta_args(SceneGPU* s, const float* F, const float* dF, float eta, float bF, float bD,
@@ -492,6 +636,8 @@ int jso_load_scene(jso_ctx* c, const jso_scene_desc* d, int* scene_id) {
   A(dalloc(&s->ctl, 1));
   A(dalloc(&s->scratch_loss, 2));
   A(dalloc(&s->partials, kMetaMaxBlocks));
+  A(dalloc(&s->slots, (size_t)kMaxSlots * n3));
+  A(dalloc(&s->accum, 3 * n3));
   A(dalloc(&s->d_scene, 1));
   if (e != hipSuccess) {
     free_scene_buffers(s.get());
@@ -581,15 +727,10 @@ int jso_render(jso_ctx* c, int id, const float* params, uint64_t seed, uint32_t 
   if (!params || !img) return fail(c, JSO_E_INVALID, "null params/img");
   if (spp < 1) return fail(c, JSO_E_INVALID, "spp must be >= 1");
   DeviceGuard g(c->device);
-  PrimalArgs pa{};
-  pa.jobs[0] = PrimalJob{params, tag, spp, nullptr, img, nullptr};
-  pa.key = KeyArgs{seed, iteration, nullptr};
-  pa.crop = crop_of(s, opts);
-  pa.mask = opts ? opts->pixel_mask : nullptr;
-  pa.target = s->target;
-  pa.flags = c->debug_flags | (opts ? opts->flags : 0u);
-  TIMED_LAUNCH(c, JSO_K_PRIMAL, launch_primal(s->d_scene, pa, 1, c->stream));
-  return JSO_OK;
+  const PrimalSpec pj{params, tag, spp, img, nullptr, nullptr};
+  const Schedule q{c, s, KeyArgs{seed, iteration, nullptr}, crop_of(s, opts),
+                   opts ? opts->pixel_mask : nullptr, c->debug_flags | (opts ? opts->flags : 0u)};
+  return run_schedule(q, &pj, 1, nullptr, 0);
 }
 
 int jso_render_bwd(jso_ctx* c, int id, const float* params, uint64_t seed, uint32_t iteration,
@@ -600,17 +741,10 @@ int jso_render_bwd(jso_ctx* c, int id, const float* params, uint64_t seed, uint3
   if (!params || !dimg || !dparams) return fail(c, JSO_E_INVALID, "null argument");
   if (spp < 1) return fail(c, JSO_E_INVALID, "spp must be >= 1");
   DeviceGuard g(c->device);
-  AdjointArgs aa{};
-  aa.jobs[0] = AdjointJob{params, dimg, nullptr, nullptr, dparams, 1.0f, (float)(1.0 / spp),
-                          tag, 0, 0};
-  aa.n_jobs = 1;
-  aa.key = KeyArgs{seed, iteration, nullptr};
-  aa.crop = crop_of(s, opts);
-  aa.mask = opts ? opts->pixel_mask : nullptr;
-  aa.flags = c->debug_flags | (opts ? opts->flags : 0u);
-  aa.work = c->counting ? c->d_work : nullptr;
-  TIMED_LAUNCH(c, JSO_K_ADJOINT, launch_adjoint(s->d_scene, aa, spp, c->stream));
-  return JSO_OK;
+  const AdjointSpec aj{params, nullptr, dimg, nullptr, dparams, 1.0f, tag, spp};
+  const Schedule q{c, s, KeyArgs{seed, iteration, nullptr}, crop_of(s, opts),
+                   opts ? opts->pixel_mask : nullptr, c->debug_flags | (opts ? opts->flags : 0u)};
+  return run_schedule(q, nullptr, 0, &aj, 1);
 }
 
 int jso_estimate_gradients(jso_ctx* c, int id, uint64_t seed, uint32_t iteration, int spp_prop,
@@ -746,24 +880,23 @@ int jso_set_work_counting(jso_ctx* c, int enable) {
   if (!c) return JSO_E_INVALID;
   DeviceGuard g(c->device);
   if (enable && !c->d_work) {
-    HIP_TRY(c, hipMalloc(&c->d_work, 2 * sizeof(unsigned long long)));
-    HIP_TRY(c, hipMemset(c->d_work, 0, 2 * sizeof(unsigned long long)));
+    HIP_TRY(c, hipMalloc(&c->d_work, 4 * sizeof(unsigned long long)));
+    HIP_TRY(c, hipMemset(c->d_work, 0, 4 * sizeof(unsigned long long)));
   }
   c->counting = enable != 0;
   return JSO_OK;
 }
 
-int jso_get_work(jso_ctx* c, uint64_t out[2], int reset) {
+int jso_get_work(jso_ctx* c, uint64_t out[4], int reset) {
   if (!c) return JSO_E_INVALID;
   if (!out) return fail(c, JSO_E_INVALID, "null output");
-  out[0] = out[1] = 0;
+  out[0] = out[1] = out[2] = out[3] = 0;
   if (!c->d_work) return JSO_OK;
   DeviceGuard g(c->device);
   HIP_TRY(c, hipStreamSynchronize(c->stream));
-  unsigned long long h[2];
+  unsigned long long h[4];
   HIP_TRY(c, hipMemcpy(h, c->d_work, sizeof(h), hipMemcpyDeviceToHost));
-  out[0] = h[0];
-  out[1] = h[1];
+  for (int k = 0; k < 4; ++k) out[k] = h[k];
   if (reset) HIP_TRY(c, hipMemset(c->d_work, 0, sizeof(h)));
   return JSO_OK;
 }

@@ -436,17 +436,18 @@ __device__ __forceinline__ void path_begin(const DevScene& S, const Rng& rng, in
 }
 
 // Process the pending surface vertex of P.  Forward (kGrad = false): adds its
-// NEE and continuation-emission terms to the ledger and moves to the next
-// vertex.  Replay (kGrad = true): recomputes exactly the same terms and, with
-// C = the path's total radiance from the forward pass, forms
+// NEE and continuation-emission terms to the ledger P.led and moves to the next
+// vertex.  Replay (kGrad = true): P.led holds the radiance still to come
+// (the path's total from the forward pass minus what the replay has
+// reproduced so far); the same terms are recomputed and subtracted, and with
+// R = that remainder after this vertex's NEE the vertex contributes
 //   NEE:           adj . beta K df(w_l)
-//   continuation:  adj . (R / f) df(w_i),   R = C - collected (after NEE)
+//   continuation:  adj . (R / f) df(w_i)
 // which is the derivative of adj . C w.r.t. this vertex's material.
 template <bool kGrad>
 __device__ __forceinline__ void path_vertex(const DevScene& S, const float* __restrict__ params,
                                             const Rng& rng, uint32_t flags, Path& P,
-                                            const float adj[3], const double C[3],
-                                            VertexGrad& vg) {
+                                            const float adj[3], VertexGrad& vg) {
   V3 p = P.o + P.d * P.t;
   V3 n;
   if (P.kind == HIT_PLANE) {
@@ -485,7 +486,7 @@ __device__ __forceinline__ void path_vertex(const DevScene& S, const float* __re
       for (int k = 0; k < 3; ++k) {
         const float K = cos_s * S.Le[k] * wmis / pl;
         const float term = P.beta[k] * nb.f[k] * K;
-        P.led[k] += (double)term;
+        P.led[k] += kGrad ? -(double)term : (double)term;
         if (kGrad) {
           const float coef = adj[k] * P.beta[k] * K;
           vg.g[k] += coef * nb.dc[k];
@@ -520,7 +521,7 @@ __device__ __forceinline__ void path_vertex(const DevScene& S, const float* __re
 #pragma unroll
     for (int k = 0; k < 3; ++k) {
       if (cb.f[k] > 0.0f) {
-        const float R = (float)(C[k] - P.led[k]);
+        const float R = (float)P.led[k];
         const float coef = adj[k] * R / cb.f[k];
         vg.g[k] += coef * cb.dc[k];
         vg.g[3] += coef * cb.dm[k];
@@ -538,32 +539,24 @@ __device__ __forceinline__ void path_vertex(const DevScene& S, const float* __re
   P.obj = h.obj;
   if (h.kind == HIT_NONE) {
 #pragma unroll
-    for (int k = 0; k < 3; ++k) P.led[k] += (double)(P.beta[k] * S.env[k]);
+    for (int k = 0; k < 3; ++k) {
+      const double e = (double)(P.beta[k] * S.env[k]);
+      P.led[k] += kGrad ? -e : e;
+    }
     P.alive = false;
   } else if (h.kind == HIT_LIGHT) {
     const float pl = h.t * h.t / (wi.y * S.larea);
     const float wb = (flags & JSO_F_NO_NEE) ? 1.0f : cb.pdf / (cb.pdf + pl);
 #pragma unroll
-    for (int k = 0; k < 3; ++k) P.led[k] += (double)(P.beta[k] * (S.Le[k] * wb));
+    for (int k = 0; k < 3; ++k) {
+      const double e = (double)(P.beta[k] * (S.Le[k] * wb));
+      P.led[k] += kGrad ? -e : e;
+    }
     P.alive = false;
   } else {
     P.alive = j < S.depth;
     P.j = j + 1;
   }
-}
-
-// Forward pass of one path: its radiance (FP64 ledger total).
-__device__ __forceinline__ void path_radiance(const DevScene& S, const float* __restrict__ params,
-                                              const Rng& rng, int px, int py, uint32_t flags,
-                                              double C[3]) {
-  Path P;
-  path_begin(S, rng, px, py, flags, P);
-  const float zero[3] = {0.0f, 0.0f, 0.0f};
-  VertexGrad vg;
-  while (P.alive) path_vertex<false>(S, params, rng, flags, P, zero, C, vg);
-  C[0] = P.led[0];
-  C[1] = P.led[1];
-  C[2] = P.led[2];
 }
 
 }  // namespace jso

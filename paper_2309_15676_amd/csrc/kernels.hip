@@ -1,13 +1,15 @@
 // HIP kernels of the jso hot path (gfx950).
 //
 //   k_philox   - Philox4x32-10 block function over a counter array
-//   k_primal   - primal renders of one or more parameter sets; writes the
-//                L2 adjoint image 2 (I - T) / (3 W H) and the loss
-//   k_adjoint  - replayed adjoint: forward pass for each path's radiance, then
-//                a second pass over the same random numbers that forms the
-//                per-vertex material derivatives and scatters them; a
-//                finite-difference job replays the paths at pi_i and pi_{i-1}
-//                in lockstep and differences coinciding vertices in registers
+//   k_forward  - forward path tracing: each path's radiance into a slot
+//                (primal samples, and the adjoint paths' forward passes)
+//   k_finalize - primal image from its slots; L2 adjoint image
+//                2 (I - T) / (3 W H) and the loss
+//   k_adjoint  - replayed adjoint: a second pass over each path's random
+//                numbers that forms the per-vertex material derivatives and
+//                scatters them; a finite-difference slice replays the paths at
+//                pi_i and pi_{i-1} in lockstep and differences coinciding
+//                vertices in registers
 //   k_meta     - fused meta-estimator + stabilised step (FP64 state)
 //   k_adam     - Adam baseline
 #include <hip/hip_runtime.h>
@@ -67,45 +69,229 @@ __device__ __forceinline__ bool tile_pixel(const Crop& c, int& px, int& py) {
 }
 
 // ---------------------------------------------------------------------------
-__global__ void __launch_bounds__(kBlock) k_primal(const DevScene* __restrict__ Sp,
-                                                   PrimalArgs A) {
+// in-block path compaction
+//
+// A wave steps its paths vertex by vertex for as long as its longest path
+// lives, and most paths end at their first surface vertex.  Each block takes
+// every path's first vertex in place (neighbouring pixels: coherent texture
+// and scene accesses), then moves the surviving paths into its lowest lanes,
+// kXchg at a time through LDS, and finishes them on as few waves as they
+// fill.  Waves left without a path exit at once, which returns their
+// registers to the CU for other blocks.  A moved path keeps the pixel
+// identity of the lane it came from (src), so it draws the same random
+// numbers and writes to the same pixel.
+// ---------------------------------------------------------------------------
+constexpr int kXchg = 64;         // paths per exchange round
+constexpr int kCompactMax = 192;  // with more survivors than this, paths finish in place
+
+// Identity of the paths of one block: tile origin and random stream.
+struct BlockPaths {
+  uint64_t key;
+  uint32_t sample;
+  int x0, y0, width;
+  uint32_t flags;
+  __device__ __forceinline__ uint32_t pixel(int src) const {
+    return (uint32_t)((y0 + src / kTile) * width + (x0 + src % kTile));
+  }
+  __device__ __forceinline__ Rng rng(int src) const { return make_rng(key, pixel(src), sample); }
+};
+
+__device__ __forceinline__ BlockPaths block_paths(const Crop& c, const DevScene& S, uint64_t key,
+                                                  uint32_t sample, uint32_t flags) {
+  return BlockPaths{key, sample, c.x0 + (int)blockIdx.x * kTile, c.y0 + (int)blockIdx.y * kTile,
+                    S.width, flags};
+}
+
+// Rank of this lane among the lanes of the block with `flag` set, and their
+// number (block-uniform).  Every lane of the block must call it.
+__device__ __forceinline__ int block_rank(bool flag, int& total, int* s_cnt) {
+  const uint64_t m = __ballot(flag);
+  const int lane = (int)__lane_id(), wv = (int)threadIdx.x >> 6;
+  const int below = __popcll(m & ((1ull << lane) - 1ull));
+  if (lane == 0) s_cnt[wv] = __popcll(m);
+  __syncthreads();
+  int off = 0, tot = 0;
+#pragma unroll
+  for (int w = 0; w < kBlock / 64; ++w) {
+    const int c = s_cnt[w];
+    off += w < wv ? c : 0;
+    tot += c;
+  }
+  __syncthreads();
+  total = tot;
+  return off + below;
+}
+
+// LDS exchange buffer, word-major (word i of slot k at i * kXchg + k), so a
+// wave's accesses fall in distinct banks.
+template <class T>
+__device__ __forceinline__ void xchg_put(uint32_t* buf, int slot, const T& v) {
+  static_assert(sizeof(T) % 4 == 0, "exchange item size");
+  uint32_t w[sizeof(T) / 4];
+  __builtin_memcpy(w, &v, sizeof(T));
+#pragma unroll
+  for (int i = 0; i < (int)(sizeof(T) / 4); ++i) buf[i * kXchg + slot] = w[i];
+}
+
+template <class T>
+__device__ __forceinline__ void xchg_get(const uint32_t* buf, int slot, T& v) {
+  uint32_t w[sizeof(T) / 4];
+#pragma unroll
+  for (int i = 0; i < (int)(sizeof(T) / 4); ++i) w[i] = buf[i * kXchg + slot];
+  __builtin_memcpy(&v, w, sizeof(T));
+}
+
+// Move the item of every lane with `live` set (rank r among n) to lane r.
+// Lanes below n receive one item in `out`; the others keep theirs.
+template <class T>
+__device__ __forceinline__ void pack(uint32_t* buf, bool live, int r, int n, const T& in, T& out) {
+  const int t = (int)threadIdx.x;
+  for (int base = 0; base < n; base += kXchg) {
+    if (live && r >= base && r < base + kXchg) xchg_put(buf, r - base, in);
+    __syncthreads();
+    if (t >= base && t < base + kXchg && t < n) xchg_get(buf, t - base, out);
+    __syncthreads();
+  }
+}
+
+__device__ __forceinline__ void store_radiance(double* __restrict__ out, uint32_t pix,
+                                               const double led[3]) {
+#pragma unroll
+  for (int k = 0; k < 3; ++k) out[3 * (size_t)pix + k] = led[k];
+}
+
+// Work counters: one 64-bit atomic per wave and counter.
+__device__ __forceinline__ void count_work(unsigned long long* w, int paths, int verts) {
+  if (!w) return;
+  paths = wave_sum(paths);
+  verts = wave_sum(verts);
+  if ((threadIdx.x & 63) == 0) {
+    atomicAdd(w, (unsigned long long)paths);
+    atomicAdd(w + 1, (unsigned long long)verts);
+  }
+}
+
+struct FwdItem {
+  Path P;
+  int src, pad_;
+};
+
+constexpr int kFwdXchgWords = (int)(sizeof(FwdItem) / 4);
+
+// ---------------------------------------------------------------------------
+// forward pass: one block = one tile of one slice; each path's radiance (its
+// FP64 ledger total) goes to the slice's slot.
+// ---------------------------------------------------------------------------
+__global__ void __launch_bounds__(kBlock) __attribute__((amdgpu_waves_per_eu(4)))
+k_forward(const DevScene* __restrict__ Sp, FwdArgs A) {
   const DevScene& S = *Sp;
-  const PrimalJob& job = A.jobs[blockIdx.z];
+  __shared__ uint32_t s_xchg[kFwdXchgWords * kXchg];
+  __shared__ int s_cnt[kBlock / 64];
+  const FwdSlice& sl = A.sl[blockIdx.z];
   int px, py;
   const bool inside = tile_pixel(A.crop, px, py);
   const uint32_t pix = (uint32_t)(py * S.width + px);
   const bool active = inside && !(A.mask && A.mask[pix]);
-  double se = 0.0;
+  const uint64_t key = stream_key(A.key.seed, iteration_of(A.key), sl.tag);
+  const BlockPaths B = block_paths(A.crop, S, key, sl.sample, A.flags);
+  double* out = A.slots + (size_t)sl.slot * A.npix * 3;
+  const float zero[3] = {0.0f, 0.0f, 0.0f};
+  VertexGrad vg;
+  int n_vert = 0;
+  Path P;
+  P.alive = false;
   if (active) {
-    const uint64_t key = stream_key(A.key.seed, iteration_of(A.key), job.tag);
-    double acc[3] = {0.0, 0.0, 0.0};
-    for (int s = 0; s < job.spp; ++s) {
-      double C[3];
-      path_radiance(S, job.params, make_rng(key, pix, (uint32_t)s), px, py, A.flags, C);
-      acc[0] += C[0];
-      acc[1] += C[1];
-      acc[2] += C[2];
+    const Rng rng = B.rng((int)threadIdx.x);
+    path_begin(S, rng, px, py, A.flags, P);
+    if (P.alive) {
+      ++n_vert;
+      path_vertex<false>(S, sl.params, rng, A.flags, P, zero, vg);
     }
-    const double inv = 1.0 / (double)job.spp;
-#pragma unroll
-    for (int k = 0; k < 3; ++k) {
-      const float I = (float)(acc[k] * inv);
-      if (job.img) job.img[3 * (size_t)pix + k] = I;
-      if (job.delta) {
-        const float T = A.target[3 * (size_t)pix + k];
-        const float e = I - T;
-        job.delta[3 * (size_t)pix + k] = A.delta_scale * e;
-        se += (double)e * (double)e;
-      }
-    }
-  } else if (inside && job.delta) {
-#pragma unroll
-    for (int k = 0; k < 3; ++k) job.delta[3 * (size_t)pix + k] = 0.0f;
+    if (!P.alive) store_radiance(out, pix, P.led);
   }
-  if (job.loss2) {
+  int n;
+  const int r = block_rank(P.alive, n, s_cnt);
+  FwdItem W;
+  if (n > kCompactMax) {
+    W.P = P;
+    W.src = (int)threadIdx.x;
+  } else {
+    FwdItem mine;
+    mine.P = P;
+    mine.src = (int)threadIdx.x;
+    W.P.alive = false;
+    W.src = (int)threadIdx.x;
+    if (n > 0) pack(s_xchg, P.alive, r, n, mine, W);
+  }
+  // no barrier below: waves without a path leave
+  if (W.P.alive) {
+    const Rng rng = B.rng(W.src);
+    while (W.P.alive) {
+      ++n_vert;
+      path_vertex<false>(S, sl.params, rng, A.flags, W.P, zero, vg);
+    }
+    store_radiance(out, B.pixel(W.src), W.P.led);
+  }
+  count_work(A.work ? A.work + 2 : nullptr, active ? 1 : 0, n_vert);
+}
+
+// ---------------------------------------------------------------------------
+// primal images from their slots: mean radiance, adjoint image, loss.  Grid
+// (blocks, jobs); blocks stride over the crop's pixels and reduce the loss to
+// one atomic each.
+// ---------------------------------------------------------------------------
+constexpr int kFinBlock = 256;
+constexpr int kFinMaxBlocks = 256;
+
+__global__ void __launch_bounds__(kFinBlock) k_finalize(FinArgs A, int width) {
+  __shared__ double s_red[kFinBlock / 64];
+  const FinJob& job = A.jobs[blockIdx.y];
+  const int cw = A.crop.x1 - A.crop.x0, chh = A.crop.y1 - A.crop.y0;
+  double se = 0.0;
+  for (int i = (int)(blockIdx.x * kFinBlock + threadIdx.x); i < cw * chh;
+       i += (int)gridDim.x * kFinBlock) {
+    const uint32_t pix = (uint32_t)((A.crop.y0 + i / cw) * width + (A.crop.x0 + i % cw));
+    if (!(A.mask && A.mask[pix])) {
+      double sum[3] = {0.0, 0.0, 0.0};
+      for (int s = 0; s < job.n; ++s) {
+        const double* c = A.slots + ((size_t)(job.slot0 + s) * A.npix + pix) * 3;
+#pragma unroll
+        for (int k = 0; k < 3; ++k) sum[k] += c[k];
+      }
+      if (!job.first) {
+#pragma unroll
+        for (int k = 0; k < 3; ++k) sum[k] = job.accum[3 * (size_t)pix + k] + sum[k];
+      }
+      if (!job.last) {
+#pragma unroll
+        for (int k = 0; k < 3; ++k) job.accum[3 * (size_t)pix + k] = sum[k];
+      } else {
+#pragma unroll
+        for (int k = 0; k < 3; ++k) {
+          const float I = (float)(sum[k] * job.inv_spp);
+          if (job.img) job.img[3 * (size_t)pix + k] = I;
+          if (job.delta) {
+            const float e = I - A.target[3 * (size_t)pix + k];
+            job.delta[3 * (size_t)pix + k] = A.delta_scale * e;
+            se += (double)e * (double)e;
+          }
+        }
+      }
+    } else if (job.last && job.delta) {
+#pragma unroll
+      for (int k = 0; k < 3; ++k) job.delta[3 * (size_t)pix + k] = 0.0f;
+    }
+  }
+  if (job.last && job.loss2) {
     se = wave_sum(se);
-    if ((threadIdx.x & 63) == 0 && se != 0.0)
-      unsafeAtomicAdd(&job.loss2[iteration_of(A.key) & 1u], se * A.loss_scale);
+    if ((threadIdx.x & 63) == 0) s_red[threadIdx.x >> 6] = se;
+    __syncthreads();
+    if (threadIdx.x == 0) {
+      double tot = 0.0;
+#pragma unroll
+      for (int w = 0; w < kFinBlock / 64; ++w) tot += s_red[w];
+      if (tot != 0.0) unsafeAtomicAdd(&job.loss2[iteration_of(A.key) & 1u], tot * A.loss_scale);
+    }
   }
 }
 
@@ -120,16 +306,16 @@ __global__ void __launch_bounds__(kBlock) k_primal(const DevScene* __restrict__ 
 // atomic at the end.  A congested probe sequence falls back to a direct
 // global atomic, so the table can never lose a contribution.
 // ---------------------------------------------------------------------------
-constexpr int kTableBits = 11;
+constexpr int kTableBits = 10;
 constexpr int kTableSize = 1 << kTableBits;  // texels per block table
-constexpr int kTableCh = 5;                  // value slots per texel (max channels)
 constexpr int kMaxProbe = 32;
 constexpr uint32_t kEmpty = 0xFFFFFFFFu;
-// LDS per block: kTableSize * (4 + 4 * kTableCh) bytes = 48 KiB
+// LDS per block (dynamic): kTableSize * 4 * (1 + n_ch) bytes, 20 KiB for
+// RGB + roughness.  Only first vertices (one tile's footprint) enter it.
 
 struct GradTable {
   uint32_t* keys;  // LDS: texel index of each slot
-  float* vals;     // LDS: kTableCh gradient values per slot
+  float* vals;     // LDS: n_ch gradient values per slot
   float* grad;     // global gradient buffer of this block's job
 };
 
@@ -179,7 +365,7 @@ __device__ __forceinline__ void scatter_texels(const DevScene& S, const GradTabl
       const float v = w * (sign * g[b]);
       if (v == 0.0f) continue;
       if (h >= 0)
-        __hip_atomic_fetch_add(&T.vals[h * kTableCh + s], v, __ATOMIC_RELAXED,
+        __hip_atomic_fetch_add(&T.vals[h * nc + s], v, __ATOMIC_RELAXED,
                                __HIP_MEMORY_SCOPE_WORKGROUP);
       else
         unsafeAtomicAdd(T.grad + (size_t)texel * nc + s, v);
@@ -237,8 +423,9 @@ __device__ __forceinline__ bool same_footprint(const Footprint& a, const Footpri
 }
 
 // Accumulates vertex gradients: global materials into per-lane registers
-// (reduced over the wave at the end), first-hit texels into the block's table;
-// later textured vertices are handed back for the wave-cooperative scatter.
+// (reduced over the wave when it leaves), first-hit texels into the block's
+// table; later textured vertices are handed back for the wave-cooperative
+// scatter.
 struct Sink {
   float acc[5];
   GradTable T;
@@ -259,109 +446,211 @@ struct Sink {
     scatter_texels(S, T, v.fp, v.g, sign);
     return false;
   }
-  // every lane of the block reaches this point
-  __device__ __forceinline__ void flush(const DevScene& S) {
-#pragma unroll
-    for (int b = 0; b < 5; ++b) {
-      const int s = S.slot[b];
-      const float v = wave_sum(acc[b]);
-      if (s >= 0 && (threadIdx.x & 63) == 0 && v != 0.0f) unsafeAtomicAdd(T.grad + s, v);
-    }
-    __syncthreads();
-    // neighbouring lanes flush neighbouring channels of one texel
+  // every lane of the block, after a barrier; neighbouring lanes flush
+  // neighbouring channels of one texel
+  __device__ __forceinline__ void flush_table(const DevScene& S) {
     const int nc = S.n_ch;
     for (int i = threadIdx.x; i < kTableSize * nc; i += kBlock) {
       const int slot = i / nc;
       const int c = i - slot * nc;
       const uint32_t k = T.keys[slot];
       if (k == kEmpty) continue;
-      const float v = T.vals[slot * kTableCh + c];
+      const float v = T.vals[i];
       if (v != 0.0f) unsafeAtomicAdd(T.grad + (size_t)k * nc + c, v);
+    }
+  }
+  // every lane of the wave
+  __device__ __forceinline__ void flush_acc(const DevScene& S) {
+#pragma unroll
+    for (int b = 0; b < 5; ++b) {
+      const int s = S.slot[b];
+      const float v = wave_sum(acc[b]);
+      if (s >= 0 && (threadIdx.x & 63) == 0 && v != 0.0f) unsafeAtomicAdd(T.grad + s, v);
     }
   }
 };
 
-// One block = one kTile x kTile pixel tile of one job's sample.  Each path is
-// traced forward for its radiance, then replayed vertex by vertex; the loop is
-// wave-uniform so the later-vertex scatter can use the whole wave.
+// Replay state of one path (single) or one finite-difference pair, moved
+// between lanes by the compaction.
+struct RepItem {
+  Path P;
+  float adj[3];
+  int src;
+};
+
+struct RepPairItem {
+  Path Pa, Pb;
+  float adj_a[3], adj_b[3];
+  int src, pad_;
+};
+
+constexpr int kRepXchgWords = (int)(sizeof(RepPairItem) / 4);
+
+// Start the replay of a path: P.led = the radiance still to come.
+__device__ __forceinline__ void replay_begin(const DevScene& S, const Rng& rng, int px, int py,
+                                             uint32_t flags, const double* __restrict__ C,
+                                             Path& P) {
+  path_begin(S, rng, px, py, flags, P);
+#pragma unroll
+  for (int k = 0; k < 3; ++k) P.led[k] = C[k] - P.led[k];
+}
+
+// One block = one kTile x kTile pixel tile of one slice.  Each path is
+// replayed vertex by vertex from its forward radiance: first vertices in place
+// (their gradients go to the block table, flushed right after), later ones on
+// the compacted lanes in a wave-uniform loop, so the later-vertex scatter can
+// use the whole wave.  The exchange buffer reuses the table's LDS.
 __global__ void __launch_bounds__(kBlock) __attribute__((amdgpu_waves_per_eu(3)))
-k_adjoint(const DevScene* __restrict__ Sp, AdjointArgs A) {
+k_adjoint(const DevScene* __restrict__ Sp, RepArgs A) {
   const DevScene& S = *Sp;
-  __shared__ uint32_t s_keys[kTableSize];
-  __shared__ float s_vals[kTableSize * kTableCh];
-  // find the job of this grid slice
-  int ji = 0;
-  while (ji + 1 < A.n_jobs && (int)blockIdx.z >= A.jobs[ji + 1].z0) ++ji;
-  const AdjointJob& job = A.jobs[ji];
-  const uint32_t sample = (uint32_t)(job.sample0 + ((int)blockIdx.z - job.z0));
+  extern __shared__ uint32_t s_dyn[];
+  __shared__ int s_cnt[kBlock / 64];
+  uint32_t* s_keys = s_dyn;
+  float* s_vals = reinterpret_cast<float*>(s_dyn + kTableSize);
+  const RepSlice& sl = A.sl[blockIdx.z];
+  const bool pair = sl.params_b != nullptr;  // uniform over the block
   int px, py;
   const bool inside = tile_pixel(A.crop, px, py);
   const uint32_t pix = (uint32_t)(py * S.width + px);
   const bool active = inside && !(A.mask && A.mask[pix]);
   for (int i = threadIdx.x; i < kTableSize; i += kBlock) s_keys[i] = kEmpty;
-  for (int i = threadIdx.x; i < kTableSize * kTableCh; i += kBlock) s_vals[i] = 0.0f;
+  for (int i = threadIdx.x; i < kTableSize * S.n_ch; i += kBlock) s_vals[i] = 0.0f;
   __syncthreads();
   Sink sink;
-  sink.init(GradTable{s_keys, s_vals, job.grad});
-  const uint64_t key = stream_key(A.key.seed, iteration_of(A.key), job.tag);
-  const Rng rng = make_rng(key, pix, sample);
-  const bool pair = job.params_b != nullptr;  // uniform over the block
+  sink.init(GradTable{s_keys, s_vals, sl.grad});
+  const uint64_t key = stream_key(A.key.seed, iteration_of(A.key), sl.tag);
+  const BlockPaths B = block_paths(A.crop, S, key, sl.sample, A.flags);
+  const Rng rng = B.rng((int)threadIdx.x);
+  const int tid = (int)threadIdx.x;
   float adj_a[3] = {0.0f, 0.0f, 0.0f}, adj_b[3] = {0.0f, 0.0f, 0.0f};
-  double Ca[3] = {0.0, 0.0, 0.0}, Cb[3] = {0.0, 0.0, 0.0};
   Path Pa, Pb;
   Pa.alive = Pb.alive = false;
-  if (active) {
-#pragma unroll
-    for (int k = 0; k < 3; ++k) {
-      adj_a[k] = job.delta[3 * (size_t)pix + k] * job.adj_scale;
-      if (pair) adj_b[k] = job.delta_b[3 * (size_t)pix + k] * job.adj_scale;
-    }
-    path_radiance(S, job.params, rng, px, py, A.flags, Ca);
-    path_begin(S, rng, px, py, A.flags, Pa);
-    if (pair) {
-      path_radiance(S, job.params_b, rng, px, py, A.flags, Cb);
-      path_begin(S, rng, px, py, A.flags, Pb);
-    }
-  }
   int n_vert = 0;
+  {
+    VertexGrad va, vb;
+    va.valid = vb.valid = false;
+    if (active) {
+#pragma unroll
+      for (int k = 0; k < 3; ++k) {
+        adj_a[k] = sl.delta[3 * (size_t)pix + k] * sl.adj_scale;
+        if (pair) adj_b[k] = sl.delta_b[3 * (size_t)pix + k] * sl.adj_scale;
+      }
+      replay_begin(S, rng, px, py, A.flags,
+                   A.slots + ((size_t)sl.slot_a * A.npix + pix) * 3, Pa);
+      if (Pa.alive) {
+        ++n_vert;
+        path_vertex<true>(S, sl.params, rng, A.flags, Pa, adj_a, va);
+      }
+      if (pair) {
+        replay_begin(S, rng, px, py, A.flags,
+                     A.slots + ((size_t)sl.slot_b * A.npix + pix) * 3, Pb);
+        if (Pb.alive) {
+          ++n_vert;
+          path_vertex<true>(S, sl.params_b, rng, A.flags, Pb, adj_b, vb);
+        }
+        if (va.valid && vb.valid && same_footprint(va.fp, vb.fp)) {
+#pragma unroll
+          for (int q = 0; q < 5; ++q) va.g[q] -= vb.g[q];
+          vb.valid = false;
+        }
+      }
+    }
+    // first vertices (j = 1) go to the table
+    sink.add(S, va, pair ? 1.0f : sl.sign);
+    sink.add(S, vb, -1.0f);
+  }
+  __syncthreads();
+  sink.flush_table(S);
+  const int paths = active ? (pair ? 2 : 1) : 0;
+  const bool live = Pa.alive || Pb.alive;
+  int n;
+  const int r = block_rank(live, n, s_cnt);  // its barriers also retire the table
+  uint32_t* xbuf = s_dyn;
   if (!pair) {
-    while (__ballot(Pa.alive) != 0) {
-      VertexGrad va;
-      va.valid = false;
-      n_vert += Pa.alive ? 1 : 0;
-      if (Pa.alive) path_vertex<true>(S, job.params, rng, A.flags, Pa, adj_a, Ca, va);
-      const bool later = sink.add(S, va, job.sign);
-      scatter_wave(S, job.grad, va, job.sign, later);
+    RepItem W;
+    if (n > kCompactMax) {
+      W.P = Pa;
+      W.src = tid;
+#pragma unroll
+      for (int k = 0; k < 3; ++k) W.adj[k] = adj_a[k];
+    } else {
+      RepItem mine;
+      mine.P = Pa;
+      mine.src = tid;
+#pragma unroll
+      for (int k = 0; k < 3; ++k) mine.adj[k] = adj_a[k];
+      W.P.alive = false;
+      W.src = tid;
+      if (n > 0) pack(xbuf, live, r, n, mine, W);
+    }
+    // no barrier below: waves without a path leave
+    if (__ballot(W.P.alive) != 0) {
+      const Rng wr = B.rng(W.src);
+      while (__ballot(W.P.alive) != 0) {
+        VertexGrad v;
+        v.valid = false;
+        if (W.P.alive) {
+          ++n_vert;
+          path_vertex<true>(S, sl.params, wr, A.flags, W.P, W.adj, v);
+        }
+        const bool later = sink.add(S, v, sl.sign);
+        scatter_wave(S, sl.grad, v, sl.sign, later);
+      }
     }
   } else {
-    // the pair is replayed in lockstep; coinciding vertices are differenced
-    // in registers (+A - B)
-    while (__ballot(Pa.alive || Pb.alive) != 0) {
-      VertexGrad va, vb;
-      va.valid = vb.valid = false;
-      n_vert += (Pa.alive ? 1 : 0) + (Pb.alive ? 1 : 0);
-      if (Pa.alive) path_vertex<true>(S, job.params, rng, A.flags, Pa, adj_a, Ca, va);
-      if (Pb.alive) path_vertex<true>(S, job.params_b, rng, A.flags, Pb, adj_b, Cb, vb);
-      if (va.valid && vb.valid && same_footprint(va.fp, vb.fp)) {
+    RepPairItem W;
+    if (n > kCompactMax) {
+      W.Pa = Pa;
+      W.Pb = Pb;
+      W.src = tid;
 #pragma unroll
-        for (int q = 0; q < 5; ++q) va.g[q] -= vb.g[q];
-        vb.valid = false;
+      for (int k = 0; k < 3; ++k) {
+        W.adj_a[k] = adj_a[k];
+        W.adj_b[k] = adj_b[k];
       }
-      const bool later_a = sink.add(S, va, 1.0f);
-      const bool later_b = sink.add(S, vb, -1.0f);
-      scatter_wave(S, job.grad, va, 1.0f, later_a);
-      scatter_wave(S, job.grad, vb, -1.0f, later_b);
+    } else {
+      RepPairItem mine;
+      mine.Pa = Pa;
+      mine.Pb = Pb;
+      mine.src = tid;
+#pragma unroll
+      for (int k = 0; k < 3; ++k) {
+        mine.adj_a[k] = adj_a[k];
+        mine.adj_b[k] = adj_b[k];
+      }
+      W.Pa.alive = W.Pb.alive = false;
+      W.src = tid;
+      if (n > 0) pack(xbuf, live, r, n, mine, W);
+    }
+    // no barrier below: waves without a path leave; the pair is replayed in
+    // lockstep and coinciding vertices are differenced in registers
+    if (__ballot(W.Pa.alive || W.Pb.alive) != 0) {
+      const Rng wr = B.rng(W.src);
+      while (__ballot(W.Pa.alive || W.Pb.alive) != 0) {
+        VertexGrad va, vb;
+        va.valid = vb.valid = false;
+        if (W.Pa.alive) {
+          ++n_vert;
+          path_vertex<true>(S, sl.params, wr, A.flags, W.Pa, W.adj_a, va);
+        }
+        if (W.Pb.alive) {
+          ++n_vert;
+          path_vertex<true>(S, sl.params_b, wr, A.flags, W.Pb, W.adj_b, vb);
+        }
+        if (va.valid && vb.valid && same_footprint(va.fp, vb.fp)) {
+#pragma unroll
+          for (int q = 0; q < 5; ++q) va.g[q] -= vb.g[q];
+          vb.valid = false;
+        }
+        const bool later_a = sink.add(S, va, 1.0f);
+        const bool later_b = sink.add(S, vb, -1.0f);
+        scatter_wave(S, sl.grad, va, 1.0f, later_a);
+        scatter_wave(S, sl.grad, vb, -1.0f, later_b);
+      }
     }
   }
-  if (A.work) {
-    const int paths = wave_sum(active ? (pair ? 2 : 1) : 0);
-    const int verts = wave_sum(n_vert);
-    if ((threadIdx.x & 63) == 0) {
-      atomicAdd(A.work, (unsigned long long)paths);
-      atomicAdd(A.work + 1, (unsigned long long)verts);
-    }
-  }
-  sink.flush(S);
+  sink.flush_acc(S);
+  count_work(A.work, paths, n_vert);
 }
 
 // ---------------------------------------------------------------------------
@@ -549,19 +838,33 @@ hipError_t launch_philox(const uint32_t* ctr, size_t n, uint64_t key, uint32_t* 
   return hipGetLastError();
 }
 
-hipError_t launch_primal(const DevScene* S, const PrimalArgs& A, int n_jobs, hipStream_t st) {
+hipError_t launch_forward(const DevScene* S, const FwdArgs& A, int n, hipStream_t st) {
   const int w = A.crop.x1 - A.crop.x0, h = A.crop.y1 - A.crop.y0;
-  if (w <= 0 || h <= 0 || n_jobs <= 0) return hipSuccess;
-  hipLaunchKernelGGL(k_primal, dim3(cdiv(w, kTile), cdiv(h, kTile), n_jobs), dim3(kBlock), 0, st,
-                     S, A);
+  if (w <= 0 || h <= 0 || n <= 0) return hipSuccess;
+  if (n > kMaxSlots) return hipErrorInvalidValue;
+  hipLaunchKernelGGL(k_forward, dim3(cdiv(w, kTile), cdiv(h, kTile), n), dim3(kBlock), 0, st, S, A);
   return hipGetLastError();
 }
 
-hipError_t launch_adjoint(const DevScene* S, const AdjointArgs& A, int n_slices, hipStream_t st) {
+hipError_t launch_finalize(const FinArgs& A, int width, hipStream_t st) {
   const int w = A.crop.x1 - A.crop.x0, h = A.crop.y1 - A.crop.y0;
-  if (w <= 0 || h <= 0 || n_slices <= 0) return hipSuccess;
-  hipLaunchKernelGGL(k_adjoint, dim3(cdiv(w, kTile), cdiv(h, kTile), n_slices), dim3(kBlock), 0,
-                     st, S, A);
+  if (w <= 0 || h <= 0 || A.n_jobs <= 0) return hipSuccess;
+  if (A.n_jobs > 3) return hipErrorInvalidValue;
+  const unsigned want = cdiv((size_t)w * h, kFinBlock);
+  hipLaunchKernelGGL(k_finalize, dim3(want < kFinMaxBlocks ? want : kFinMaxBlocks, A.n_jobs),
+                     dim3(kFinBlock), 0, st, A, width);
+  return hipGetLastError();
+}
+
+hipError_t launch_adjoint(const DevScene* S, const RepArgs& A, int n, int n_ch, hipStream_t st) {
+  const int w = A.crop.x1 - A.crop.x0, h = A.crop.y1 - A.crop.y0;
+  if (w <= 0 || h <= 0 || n <= 0) return hipSuccess;
+  if (n > kMaxSlots || n_ch < 0 || n_ch > 5) return hipErrorInvalidValue;
+  const size_t table = (size_t)kTableSize * 4 * (1 + (size_t)n_ch);
+  const size_t xchg = (size_t)kRepXchgWords * kXchg * 4;
+  const size_t lds = table > xchg ? table : xchg;
+  hipLaunchKernelGGL(k_adjoint, dim3(cdiv(w, kTile), cdiv(h, kTile), n), dim3(kBlock), lds, st, S,
+                     A);
   return hipGetLastError();
 }
 

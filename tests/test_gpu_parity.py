@@ -283,13 +283,15 @@ def test_work_counters_match_oracle_path_statistics(ctx):
     L.check(L.jso_set_work_counting(prob.ctx, True), prob.ctx)
     L.jso_get_work(prob.ctx, reset=True)
     prob.render_bwd(p, torch.from_numpy(dimg).cuda(), seed, it, tag, spp)
-    paths, verts = L.jso_get_work(prob.ctx, reset=True)
+    paths, verts, fpaths, fverts = L.jso_get_work(prob.ctx, reset=True)
     L.check(L.jso_set_work_counting(prob.ctx, False), prob.ctx)
     assert paths == ref["paths"] == spec.n_pixels * spp
     assert abs(verts - ref["vertices"]) <= 2e-3 * ref["vertices"], (verts, ref)
+    # the replay takes exactly the vertices of the forward pass
+    assert (fpaths, fverts) == (paths, verts)
     # counting off: the totals stay put
     prob.render_bwd(p, torch.from_numpy(dimg).cuda(), seed, it, tag, spp)
-    assert L.jso_get_work(prob.ctx) == (0, 0)
+    assert L.jso_get_work(prob.ctx) == (0, 0, 0, 0)
 
 
 def _meta_problem(ctx, tex=16):
