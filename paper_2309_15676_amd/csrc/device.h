@@ -191,8 +191,8 @@ struct Mat {
 // texture (one material for every point).
 struct Footprint {
   int global;
-  int t00, t01, t10, t11;  // texel indices
-  float fx, fy;            // bilinear fractions
+  int t00, t01, t10;  // texel indices (the fourth is t01 + t10 - t00)
+  float fx, fy;       // bilinear fractions
 };
 
 __device__ __forceinline__ void texel_weights(const Footprint& fp, float w[4]) {
@@ -217,7 +217,6 @@ __device__ __forceinline__ Footprint footprint_uv(const DevScene& S, float u, fl
   fp.t00 = yi0 * S.tex_w + xi0;
   fp.t01 = yi0 * S.tex_w + xi1;
   fp.t10 = yi1 * S.tex_w + xi0;
-  fp.t11 = yi1 * S.tex_w + xi1;
   return fp;
 }
 
@@ -237,7 +236,7 @@ __device__ __forceinline__ bool material_at(const DevScene& S, const float* __re
   float val[5];
   if (S.tex_w == 1 && S.tex_h == 1) {
     fp.global = 1;
-    fp.t00 = fp.t01 = fp.t10 = fp.t11 = 0;
+    fp.t00 = fp.t01 = fp.t10 = 0;
     fp.fx = fp.fy = 0.0f;
 #pragma unroll
     for (int b = 0; b < 5; ++b) val[b] = S.slot[b] >= 0 ? params[S.slot[b]] : S.defaults[b];
@@ -254,6 +253,7 @@ __device__ __forceinline__ bool material_at(const DevScene& S, const float* __re
     float w[4];
     texel_weights(fp, w);
     const int nc = S.n_ch;
+    const int t11 = fp.t01 + fp.t10 - fp.t00;
 #pragma unroll
     for (int b = 0; b < 5; ++b) {
       const int s = S.slot[b];
@@ -261,7 +261,7 @@ __device__ __forceinline__ bool material_at(const DevScene& S, const float* __re
         val[b] = S.defaults[b];
       } else {
         val[b] = w[0] * params[fp.t00 * nc + s] + w[1] * params[fp.t01 * nc + s] +
-                 w[2] * params[fp.t10 * nc + s] + w[3] * params[fp.t11 * nc + s];
+                 w[2] * params[fp.t10 * nc + s] + w[3] * params[t11 * nc + s];
       }
     }
   }
@@ -385,13 +385,18 @@ __device__ __forceinline__ V3 sample_dir(const Mat& M, V3 n, V3 wo, const float 
 // path state and one vertex of a path (forward, or replay with derivatives)
 // ---------------------------------------------------------------------------
 struct Path {
-  V3 o, d;
+  double led[3];  // FP64 ledger: radiance collected so far (replay: still to come)
+  V3 o;           // pending hit point
+  V3 d;           // direction of the ray that reached it
   float beta[3];
-  float t;
-  int kind, obj;
-  int j;
+  uint32_t hit;   // pending hit: kind | object << 2 | vertex index j << 10
   bool alive;
-  double led[3];  // radiance collected so far (FP64 ledger)
+  __device__ __forceinline__ int kind() const { return (int)(hit & 3u); }
+  __device__ __forceinline__ int obj() const { return (int)((hit >> 2) & 255u); }
+  __device__ __forceinline__ int j() const { return (int)(hit >> 10); }
+  __device__ __forceinline__ void set_hit(int kind, int obj, int j) {
+    hit = (uint32_t)kind | ((uint32_t)obj << 2) | ((uint32_t)j << 10);
+  }
 };
 
 // Material-attribute gradient of one vertex: g = d(adj . C)/d(R, G, B, metal, rough)
@@ -414,15 +419,13 @@ __device__ __forceinline__ void path_begin(const DevScene& S, const Rng& rng, in
   }
   const float sx = (2.0f * ((float)px + jx) / (float)S.width - 1.0f) * S.tan_half * S.aspect;
   const float sy = (1.0f - 2.0f * ((float)py + jy) / (float)S.height) * S.tan_half;
-  P.o = ld3(S.eye);
+  const V3 eye = ld3(S.eye);
   P.d = normalize(ld3(S.cw) + ld3(S.cu) * sx + ld3(S.cv) * sy);
   P.beta[0] = P.beta[1] = P.beta[2] = 1.0f;
   P.led[0] = P.led[1] = P.led[2] = 0.0;
-  P.j = 1;
-  const Hit h = intersect(S, P.o, P.d);
-  P.t = h.t;
-  P.kind = h.kind;
-  P.obj = h.obj;
+  const Hit h = intersect(S, eye, P.d);
+  P.o = eye + P.d * h.t;
+  P.set_hit(h.kind, h.obj, 1);
   P.alive = false;
   if (h.kind == HIT_NONE) {
 #pragma unroll
@@ -448,24 +451,24 @@ template <bool kGrad>
 __device__ __forceinline__ void path_vertex(const DevScene& S, const float* __restrict__ params,
                                             const Rng& rng, uint32_t flags, Path& P,
                                             const float adj[3], VertexGrad& vg) {
-  V3 p = P.o + P.d * P.t;
+  V3 p = P.o;
+  const int kind = P.kind(), obj = P.obj(), j = P.j();
   V3 n;
-  if (P.kind == HIT_PLANE) {
+  if (kind == HIT_PLANE) {
     p.y = 0.0f;
     n = mk(0.0f, 1.0f, 0.0f);
   } else {
-    n = normalize(p - ld3(S.sph[P.obj]));
+    n = normalize(p - ld3(S.sph[obj]));
   }
   const V3 wo = mk(-P.d.x, -P.d.y, -P.d.z);
   Mat M;
-  vg.valid = material_at(S, params, P.kind, P.obj, p, n, M, vg.fp);
-  vg.j = P.j;
+  vg.valid = material_at(S, params, kind, obj, p, n, M, vg.fp);
+  vg.j = j;
   if (kGrad) {
 #pragma unroll
     for (int b = 0; b < 5; ++b) vg.g[b] = 0.0f;
   }
   const V3 po = p + n * kRayEps;
-  const int j = P.j;
   float u[4];
 
   // next-event estimation towards the square light
@@ -531,12 +534,9 @@ __device__ __forceinline__ void path_vertex(const DevScene& S, const float* __re
   }
 #pragma unroll
   for (int k = 0; k < 3; ++k) P.beta[k] *= cb.f[k] * cw;
-  P.o = po;
   P.d = wi;
   const Hit h = intersect(S, po, wi);
-  P.t = h.t;
-  P.kind = h.kind;
-  P.obj = h.obj;
+  P.o = po + wi * h.t;
   if (h.kind == HIT_NONE) {
 #pragma unroll
     for (int k = 0; k < 3; ++k) {
@@ -555,7 +555,7 @@ __device__ __forceinline__ void path_vertex(const DevScene& S, const float* __re
     P.alive = false;
   } else {
     P.alive = j < S.depth;
-    P.j = j + 1;
+    P.set_hit(h.kind, h.obj, j + 1);
   }
 }
 

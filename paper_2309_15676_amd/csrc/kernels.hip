@@ -418,7 +418,7 @@ __device__ __forceinline__ void scatter_wave(const DevScene& S, float* __restric
 
 __device__ __forceinline__ bool same_footprint(const Footprint& a, const Footprint& b) {
   return a.global == b.global && a.t00 == b.t00 && a.t01 == b.t01 && a.t10 == b.t10 &&
-         a.t11 == b.t11 && __float_as_uint(a.fx) == __float_as_uint(b.fx) &&
+         __float_as_uint(a.fx) == __float_as_uint(b.fx) &&
          __float_as_uint(a.fy) == __float_as_uint(b.fy);
 }
 
