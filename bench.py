@@ -116,6 +116,84 @@ def copy_calibration(mib: int):
     torch.cuda.synchronize()
 
 
+def time_to_loss(prob, init, gt, target, args, iters: int, label: str):
+    """Wall-clock (grad_step calls only; evaluations off the clock) for the
+    meta-estimator at 2 proportional + 1 FD spp to reach the best evaluation
+    loss plain Adam at 64 spp reaches within `iters` iterations, each method
+    with its best learning rate from a small grid; same GPU, same process."""
+    import torch
+
+    from paper_2309_15676_amd import _lib as L
+
+    ev_seed, ev_spp = 777, 256
+    T = target.float()
+    every = max(iters // 40, 1)
+
+    def eval_loss(p=None):
+        p = prob.get_params() if p is None else p
+        img = prob.render(p, seed=ev_seed, iteration=0, tag=L.JSO_TAG_EVAL, spp=ev_spp)
+        return float(((img - T) ** 2).mean())
+
+    floor = eval_loss(gt)  # the evaluation's own noise: loss at the ground truth
+
+    def run(opts, n, stop_at=None):
+        prob.set_params(init)  # also resets the optimiser state
+        e0, e1 = torch.cuda.Event(enable_timing=True), torch.cuda.Event(enable_timing=True)
+        clock, hist = 0.0, [(0, 0.0, eval_loss())]
+        done = 0
+        while done < n:
+            k = min(every, n - done)
+            torch.cuda.synchronize()
+            e0.record()
+            for _ in range(k):
+                prob.grad_step(opts)
+            e1.record()
+            torch.cuda.synchronize()
+            clock += e0.elapsed_time(e1) / 1e3
+            done += k
+            hist.append((done, clock, eval_loss()))
+            if stop_at is not None and hist[-1][2] <= stop_at:
+                break
+        return hist
+
+    grid = [float(x) for x in args.ttl_etas.split(",")]
+    adam = {}
+    for eta in grid:
+        o = L.step_opts(optimizer=L.JSO_OPT_ADAM, eta=eta, adam_spp=64, seed=args.seed + 1)
+        adam[eta] = run(o, iters)
+    best_eta = min(adam, key=lambda e: min(h[2] for h in adam[e]))
+    ha = adam[best_eta]
+    target_loss = min(h[2] for h in ha)
+    it_adam, t_adam = next((h[0], h[1]) for h in ha if h[2] <= target_loss)
+    meta = {}
+    for eta in grid:
+        o = L.step_opts(optimizer=L.JSO_OPT_META, eta=eta, beta_F=0.99, beta_D=0.9, spp_prop=2,
+                        spp_fd=1, seed=args.seed + 2)
+        meta[eta] = run(o, args.ttl_meta_factor * iters, stop_at=target_loss)
+    ok = {e: next(h for h in meta[e] if h[2] <= target_loss) for e in grid
+          if any(h[2] <= target_loss for h in meta[e])}
+    if ok:
+        m_eta = min(ok, key=lambda e: ok[e][1])
+        it_meta, t_meta = ok[m_eta][0], ok[m_eta][1]
+    else:
+        m_eta = min(meta, key=lambda e: min(h[2] for h in meta[e]))
+        it_meta, t_meta = None, None
+    return {
+        "workload": label,
+        "evaluation": "L2 of a %d-spp render (fixed evaluation stream) against the target, "
+                      "every %d iterations, off the clock" % (ev_spp, every),
+        "target_loss": target_loss,
+        "loss_at_ground_truth": floor,
+        "adam": {"spp": 64, "eta": best_eta, "iterations": it_adam, "seconds": t_adam,
+                 "best_loss_by_eta": {str(e): min(h[2] for h in adam[e]) for e in grid},
+                 "iteration_budget": iters},
+        "meta": {"spp": "2 prop + 1 FD", "eta": m_eta, "iterations": it_meta, "seconds": t_meta,
+                 "best_loss_by_eta": {str(e): min(h[2] for h in meta[e]) for e in grid},
+                 "iteration_budget": args.ttl_meta_factor * iters},
+        "speedup": (t_adam / t_meta) if t_meta else None,
+    }
+
+
 def main():
     ap = argparse.ArgumentParser(description=__doc__.split("\n")[0])
     ap.add_argument("--gpus", type=int, default=1)
@@ -127,6 +205,12 @@ def main():
     ap.add_argument("--copy-mib", type=int, default=0,
                     help="also run a plain copy of this many MiB (counter calibration)")
     ap.add_argument("--seed", type=int, default=4)
+    ap.add_argument("--ttl-iters", type=int, default=500,
+                    help="Adam-64 iteration budget of the textured time-to-loss comparison "
+                         "(0: skip both comparisons)")
+    ap.add_argument("--ttl-meta-factor", type=int, default=4,
+                    help="meta-estimator iteration budget, in multiples of --ttl-iters")
+    ap.add_argument("--ttl-etas", default="0.003,0.01,0.03,0.1")
     args = ap.parse_args()
     if args.gpus != 1:
         print("bench.py: this build runs on one GPU; --gpus %d is not supported "
@@ -198,6 +282,25 @@ def main():
               flush=True)
         Tn = target.cpu().numpy().astype(np.float64)
         cpu = cpu_baseline(spec, init, Tn, args.cpu_seconds, args.seed)
+    ttl = None
+    if args.ttl_iters > 0:
+        print("[bench] time to loss: Adam-64 vs meta-estimator", file=sys.stderr, flush=True)
+        ttl = {}
+        # the paper's multivariate-material case: 5 global parameters
+        tspec, tgt, tinit = I.config_tiny()
+        tprob = Problem(tspec, context=prob.context)
+        ttarget = tprob.render(tgt, seed=12345, iteration=0, tag=L.JSO_TAG_TARGET, spp=1024)
+        tprob.set_target(ttarget)
+        ttl["tiny"] = time_to_loss(
+            tprob, tinit, tgt, ttarget, args, 200,
+            "64x64, unit sphere on a grey plane, 5 global parameters (RGB, metalness, "
+            "roughness), depth 3, target at 1024 spp")
+        print("[bench] time to loss: %s" % json.dumps(ttl["tiny"]), file=sys.stderr, flush=True)
+        ttl["textured"] = time_to_loss(
+            prob, init, gt, target, args, args.ttl_iters,
+            "the 512x512 textured problem (262,144 texel parameters, no preconditioning)")
+        print("[bench] time to loss: %s" % json.dumps(ttl["textured"]), file=sys.stderr,
+              flush=True)
     # roofline of the dominant kernel: algorithmic FP32 work per launch over
     # its average launch time
     cands = {
@@ -235,6 +338,7 @@ def main():
         "vertices_per_s": value * vpp,
         "kernel_ms_per_step": {k: v[0] / max(v[1], 1) for k, v in ktimes.items()},
         "cpu_baseline": cpu,
+        "time_to_loss": ttl,
     }
     print(json.dumps(line))
 
