@@ -194,6 +194,73 @@ def time_to_loss(prob, init, gt, target, args, iters: int, label: str):
     }
 
 
+def batched_throughput(ctx_problem, args):
+    """64 independent problems of uneven size (image side 64-512, 5-65,536
+    parameters, own seeds and iteration budgets): differentiable paths/s of
+    one iteration for all of them, (a) as a batch replayed from a captured
+    HIP graph, (b) as one jso_grad_step over all problems (one launch per
+    kernel), (c) as one jso_grad_step per problem."""
+    import torch
+
+    from paper_2309_15676_amd import _lib as L
+    from paper_2309_15676_amd import inputs as I
+    from paper_2309_15676_amd.problem import Batch, Problem, grad_step_many
+
+    cfg = I.config_batched(64, seed=args.seed)
+    ctx = ctx_problem.context
+    probs = []
+    for k, c in enumerate(cfg):
+        p = Problem(c["spec"], context=ctx)
+        p.set_target(p.render(c["gt"], seed=1000 + k, iteration=0, tag=L.JSO_TAG_TARGET,
+                              spp=args.batch_target_spp))
+        p.set_params(c["init"])
+        probs.append(p)
+    opts = L.step_opts(optimizer=L.JSO_OPT_META, eta=0.01, beta_F=0.99, beta_D=0.9,
+                       spp_prop=2, spp_fd=1, seed=args.seed)
+    pixels = sum(c["spec"].n_pixels for c in cfg)
+    steps = args.batch_steps
+
+    def timed(fn):
+        fn(3)
+        torch.cuda.synchronize()
+        e0, e1 = torch.cuda.Event(enable_timing=True), torch.cuda.Event(enable_timing=True)
+        e0.record()
+        fn(steps)
+        e1.record()
+        torch.cuda.synchronize()
+        return e0.elapsed_time(e1) / steps
+
+    b = Batch(probs, opts, max_iters=[c["max_iter"] for c in cfg], use_graph=True)
+    ms_graph = timed(lambda n: b.step(n))
+    b.close()
+
+    def together(n):
+        for _ in range(n):
+            grad_step_many(probs, opts)
+
+    def one_by_one(n):
+        for _ in range(n):
+            for p in probs:
+                p.grad_step(opts)
+
+    ms_together = timed(together)
+    ms_each = timed(one_by_one)
+    paths = 4 * pixels
+    return {
+        "workload": "64 problems, image side log-uniform 64-512 (multiple of 8), 5-65,536 "
+                    "parameters log-uniform (global material at <= 5, else an RGB + roughness "
+                    "texture), own seeds, meta-estimator 2 prop + 1 FD spp",
+        "pixels": pixels,
+        "params": sum(c["spec"].n_params for c in cfg),
+        "steps": steps,
+        "graph": {"ms_per_iteration": ms_graph, "paths_per_s": paths / (ms_graph / 1e3)},
+        "one_launch_per_kernel": {"ms_per_iteration": ms_together,
+                                  "paths_per_s": paths / (ms_together / 1e3)},
+        "one_grad_step_per_problem": {"ms_per_iteration": ms_each,
+                                      "paths_per_s": paths / (ms_each / 1e3)},
+    }
+
+
 def main():
     ap = argparse.ArgumentParser(description=__doc__.split("\n")[0])
     ap.add_argument("--gpus", type=int, default=1)
@@ -211,6 +278,9 @@ def main():
     ap.add_argument("--ttl-meta-factor", type=int, default=4,
                     help="meta-estimator iteration budget, in multiples of --ttl-iters")
     ap.add_argument("--ttl-etas", default="0.003,0.01,0.03,0.1")
+    ap.add_argument("--batch-steps", type=int, default=20,
+                    help="iterations timed for the 64-problem batch (0: skip it)")
+    ap.add_argument("--batch-target-spp", type=int, default=256)
     args = ap.parse_args()
     if args.gpus != 1:
         print("bench.py: this build runs on one GPU; --gpus %d is not supported "
@@ -282,6 +352,11 @@ def main():
               flush=True)
         Tn = target.cpu().numpy().astype(np.float64)
         cpu = cpu_baseline(spec, init, Tn, args.cpu_seconds, args.seed)
+    bat = None
+    if args.batch_steps > 0:
+        print("[bench] 64-problem batch", file=sys.stderr, flush=True)
+        bat = batched_throughput(prob, args)
+        print("[bench] batch: %s" % json.dumps(bat), file=sys.stderr, flush=True)
     ttl = None
     if args.ttl_iters > 0:
         print("[bench] time to loss: Adam-64 vs meta-estimator", file=sys.stderr, flush=True)
@@ -339,6 +414,7 @@ def main():
         "kernel_ms_per_step": {k: v[0] / max(v[1], 1) for k, v in ktimes.items()},
         "cpu_baseline": cpu,
         "time_to_loss": ttl,
+        "batched": bat,
     }
     print(json.dumps(line))
 

@@ -236,10 +236,36 @@ int jso_adam_step(jso_ctx* ctx, int scene_id, const float* g, float eta, float b
 
 /* One full iteration for each listed problem (the hot path): estimators into
  * the scene's own gradient buffers, then the fused optimiser step, which also
- * clears those buffers for the next iteration.  stats (host array of n,
- * nullable) waits for the stream and reports each problem's loss and step. */
+ * clears those buffers for the next iteration.  All listed problems share one
+ * launch per kernel (Section 5's loop, run for many independent problems at
+ * once); scene ids must be distinct.  stats (host array of n, nullable) waits
+ * for the stream and reports each problem's loss and step. */
 int jso_grad_step(jso_ctx* ctx, const int* scene_ids, int n, const jso_step_opts* opts,
                   jso_step_stats* stats);
+
+/* ---- batches ------------------------------------------------------------------------ */
+
+/* A fixed set of independent problems optimised together (the loop of
+ * Section 5 for each): every iteration is one launch per kernel for all of
+ * them, from launch descriptors uploaded once at creation, optionally
+ * captured in a HIP graph and replayed.  max_iters (host array of n,
+ * nullable): problem k stops changing once its own iteration counter reaches
+ * max_iters[k] (0 = no limit); the kernels skip finished problems.  The
+ * options, scene ids and the scenes' buffers are fixed at creation: do not
+ * free a scene or replace its buffers (jso_load_scene of new sizes) while a
+ * batch refers to it.  jso_set_params, jso_set_target and jso_set_state
+ * remain valid between steps.  Not thread-safe per context; the batch runs
+ * on its context's stream.  Errors: JSO_E_INVALID (bad ids/options),
+ * JSO_E_OOM, JSO_E_HIP. */
+typedef struct jso_batch jso_batch;
+int jso_batch_create(jso_ctx* ctx, const int* scene_ids, int n, const jso_step_opts* opts,
+                     const uint32_t* max_iters, int use_graph, jso_batch** out);
+/* Run `iterations` iterations of every active problem (returns when queued). */
+int jso_batch_step(jso_batch* b, int iterations);
+/* Number of problems whose iteration counter is still below its limit
+ * (waits for the stream). */
+int jso_batch_active(jso_batch* b, int* active);
+int jso_batch_destroy(jso_batch* b);
 
 /* ---- kernel timing --------------------------------------------------------------- */
 

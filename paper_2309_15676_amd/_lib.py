@@ -34,6 +34,7 @@ EXPORTED = [
     "jso_set_target", "jso_render", "jso_render_bwd", "jso_estimate_gradients",
     "jso_meta_step", "jso_adam_step", "jso_grad_step", "jso_get_state", "jso_set_state",
     "jso_set_timing", "jso_get_kernel_time", "jso_set_work_counting", "jso_get_work",
+    "jso_batch_create", "jso_batch_step", "jso_batch_active", "jso_batch_destroy",
 ]
 JSO_K_FORWARD, JSO_K_ADJOINT, JSO_K_META, JSO_K_ADAM, JSO_K_FINALIZE = 0, 1, 2, 3, 4
 JSO_K_COUNT = 5
@@ -137,6 +138,11 @@ def load() -> ctypes.CDLL:
         "jso_get_kernel_time": (I, [P, I, ctypes.POINTER(D), ctypes.POINTER(U64), I]),
         "jso_set_work_counting": (I, [P, I]),
         "jso_get_work": (I, [P, ctypes.POINTER(U64), I]),
+        "jso_batch_create": (I, [P, ctypes.POINTER(I), I, ctypes.c_void_p,
+                                 ctypes.POINTER(ctypes.c_uint32), I, ctypes.POINTER(P)]),
+        "jso_batch_step": (I, [P, I]),
+        "jso_batch_active": (I, [P, ctypes.POINTER(I)]),
+        "jso_batch_destroy": (I, [P]),
     }
     for name, (res, args) in sig.items():
         fn = getattr(L, name)
@@ -375,6 +381,31 @@ def jso_get_kernel_time(ctx, kernel: int, reset: bool = False):
 
 def jso_set_work_counting(ctx, enable: bool) -> int:
     return load().jso_set_work_counting(ctx, 1 if enable else 0)
+
+
+def jso_batch_create(ctx, sids, opts, max_iters=None, use_graph: bool = True):
+    """A batch of problems stepped together; returns the batch handle."""
+    n = len(sids)
+    ids = (ctypes.c_int * n)(*sids)
+    mi = None if max_iters is None else (ctypes.c_uint32 * n)(*[int(m) for m in max_iters])
+    out = ctypes.c_void_p()
+    check(load().jso_batch_create(ctx, ids, n, ctypes.byref(opts), mi, 1 if use_graph else 0,
+                                  ctypes.byref(out)), ctx, "jso_batch_create")
+    return out
+
+
+def jso_batch_step(ctx, batch, iterations: int = 1) -> None:
+    check(load().jso_batch_step(batch, iterations), ctx, "jso_batch_step")
+
+
+def jso_batch_active(ctx, batch) -> int:
+    out = ctypes.c_int(0)
+    check(load().jso_batch_active(batch, ctypes.byref(out)), ctx, "jso_batch_active")
+    return out.value
+
+
+def jso_batch_destroy(batch) -> int:
+    return load().jso_batch_destroy(batch)
 
 
 def jso_get_work(ctx, reset: bool = False):

@@ -2,6 +2,8 @@
 // declared in include/jso.h.
 #include <hip/hip_runtime.h>
 
+#include <algorithm>
+#include <atomic>
 #include <cmath>
 #include <cstdarg>
 #include <cstdio>
@@ -36,9 +38,13 @@ struct SceneGPU {
   double* accum = nullptr;         // per-pixel radiance sums of up to 3 primal images
   DevScene* d_scene = nullptr;     // device copy of `dev` read by the kernels
   uint32_t host_iter = 0;          // mirror of ctl->iteration
+  uint64_t generation = 0;         // unique per loaded scene (plan cache key)
 };
 
 }  // namespace
+
+// Source of SceneGPU::generation.
+std::atomic<uint64_t> g_scene_generation{0};
 
 // HIP-event timing of kernel launches, per kernel class.
 struct KernelTimer {
@@ -83,7 +89,98 @@ struct KernelTimer {
   }
 };
 
+// Device copies of launch descriptors (unit arrays).  A host-built array is
+// staged in pinned memory and copied on the context's stream; a slot is
+// reused only once the event recorded behind its copy has completed.
+struct DescRing {
+  static constexpr int kSlots = 64;
+  static constexpr size_t kSlotBytes = 64 * 1024;
+  uint8_t* host = nullptr;  // pinned
+  uint8_t* dev = nullptr;
+  hipEvent_t ev[kSlots] = {};
+  bool pending[kSlots] = {};
+  int next = 0;
+
+  hipError_t init() {
+    if (host) return hipSuccess;
+    hipError_t e = hipHostMalloc(reinterpret_cast<void**>(&host), kSlots * kSlotBytes, 0);
+    if (e != hipSuccess) return e;
+    e = hipMalloc(reinterpret_cast<void**>(&dev), kSlots * kSlotBytes);
+    if (e != hipSuccess) return e;
+    for (int k = 0; k < kSlots; ++k) {
+      e = hipEventCreateWithFlags(&ev[k], hipEventDisableTiming);
+      if (e != hipSuccess) return e;
+    }
+    return hipSuccess;
+  }
+  // copy `bytes` to device memory in stream order; *out = its device address
+  hipError_t put(const void* src, size_t bytes, hipStream_t st, const void** out) {
+    if (bytes > kSlotBytes) return hipErrorInvalidValue;
+    hipError_t e = init();
+    if (e != hipSuccess) return e;
+    const int k = next;
+    next = (next + 1) % kSlots;
+    if (pending[k]) {
+      e = hipEventSynchronize(ev[k]);
+      if (e != hipSuccess) return e;
+    }
+    std::memcpy(host + (size_t)k * kSlotBytes, src, bytes);
+    e = hipMemcpyAsync(dev + (size_t)k * kSlotBytes, host + (size_t)k * kSlotBytes, bytes,
+                       hipMemcpyHostToDevice, st);
+    if (e != hipSuccess) return e;
+    e = hipEventRecord(ev[k], st);
+    if (e != hipSuccess) return e;
+    pending[k] = true;
+    *out = dev + (size_t)k * kSlotBytes;
+    return hipSuccess;
+  }
+  void destroy() {
+    for (int k = 0; k < kSlots; ++k)
+      if (ev[k]) {
+        if (pending[k]) (void)hipEventSynchronize(ev[k]);
+        (void)hipEventDestroy(ev[k]);
+      }
+    if (dev) (void)hipFree(dev);
+    if (host) (void)hipHostFree(host);
+  }
+};
+
+// The plan of the last grad_step, its unit arrays kept in device memory: a
+// step repeated with the same problems and options launches from them
+// directly.  `sig` identifies the plan (scenes by load generation, options,
+// flags); launch records keep their metadata, their units live on the device.
+struct CachedLaunch {
+  int kind, timer, n;
+  uint32_t blocks;
+  size_t lds, offset;
+};
+
+struct CachedPlan {
+  std::vector<uint64_t> sig;
+  std::vector<CachedLaunch> launches;
+  uint8_t* dev = nullptr;   // unit arrays
+  uint8_t* host = nullptr;  // pinned staging copy (source of the upload)
+  uint64_t last_use = 0;
+};
+
+struct PlanCache {
+  static constexpr size_t kMaxPlans = 64;
+  std::vector<CachedPlan> plans;
+  uint64_t clock = 0;
+  static void release(CachedPlan& p) {
+    if (p.dev) (void)hipFree(p.dev);
+    if (p.host) (void)hipHostFree(p.host);
+    p.dev = p.host = nullptr;
+  }
+  void destroy() {
+    for (CachedPlan& p : plans) release(p);
+    plans.clear();
+  }
+};
+
 struct jso_ctx {
+  DescRing ring;
+  PlanCache plan_cache;
   int device = 0;
   hipStream_t stream = nullptr;  // nullptr = the device's null (default) stream
   uint32_t debug_flags = 0;
@@ -297,7 +394,7 @@ hipMemcpyKind kind_from_dev(int mem) {
 }
 
 // ---------------------------------------------------------------------------
-// launch schedule
+// launch plans
 //
 // Every path is traced by k_forward into a radiance slot; a primal image is
 // then reduced from its slots by k_finalize, and an adjoint path is replayed
@@ -305,6 +402,10 @@ hipMemcpyKind kind_from_dev(int mem) {
 // slots per pixel, so larger sample counts run in chunks: a chunk of primal
 // samples is finalized (accumulated) before the next overwrites the slots,
 // and the replay of a chunk of adjoint samples follows their forward launch.
+//
+// A plan is the launch sequence of one step for one or more problems with
+// the same estimator configuration: each launch carries one unit per problem
+// (or per slice group), so a single launch serves all of them.
 // ---------------------------------------------------------------------------
 struct PrimalSpec {
   const float* params;
@@ -326,184 +427,241 @@ struct AdjointSpec {
   int spp;
 };
 
-struct Schedule {
-  jso_ctx* c;
+// One problem's part of a plan.
+struct ProbPlan {
   SceneGPU* s;
   KeyArgs key;
   Crop crop;
   const uint8_t* mask;
   uint32_t flags;
+  uint32_t max_iter;  // 0: always active
+  PrimalSpec pj[3];
+  int np;
+  AdjointSpec aj[2];
+  int na;
 };
 
-FwdArgs fwd_args(const Schedule& q) {
-  FwdArgs f{};
-  f.key = q.key;
-  f.crop = q.crop;
-  f.mask = q.mask;
-  f.slots = q.s->slots;
-  f.npix = (uint32_t)q.s->npix;
-  f.flags = q.flags;
-  f.work = q.c->counting ? q.c->d_work : nullptr;
-  return f;
-}
+enum class Kern { Forward, Finalize, Adjoint, Meta, Adam };
 
-RepArgs rep_args(const Schedule& q) {
-  RepArgs r{};
-  r.key = q.key;
-  r.crop = q.crop;
-  r.mask = q.mask;
-  r.slots = q.s->slots;
-  r.npix = (uint32_t)q.s->npix;
-  r.flags = q.flags;
-  r.work = q.c->counting ? q.c->d_work : nullptr;
-  return r;
-}
-
-// One replay slice and the forward slices it needs.
-struct RepUnit {
-  int job, sample;
+struct LaunchRec {
+  Kern kind;
+  int timer;                   // JSO_K_* class
+  std::vector<uint8_t> units;  // host copy of the unit array
+  int n = 0;
+  uint32_t blocks = 0;
+  size_t lds = 0;
+  size_t dev_offset = 0;       // batches: offset of the units in the device arena
 };
 
-// Trace the primal images and reduce them; then trace and replay the adjoint
-// samples.  The adjoint's forward slices share the last primal launch when
-// they fit.
-int run_schedule(const Schedule& q, const PrimalSpec* pj, int np, const AdjointSpec* aj, int na) {
-  jso_ctx* c = q.c;
-  SceneGPU* s = q.s;
-  // replay units, pairs first: within a launch blocks are dispatched in slice
-  // order and a pair block traces twice the paths of a single one
-  std::vector<RepUnit> units;
-  for (int pass = 0; pass < 2; ++pass)
-    for (int j = 0; j < na; ++j)
-      if ((aj[j].params_b != nullptr) == (pass == 0))
-        for (int k = 0; k < aj[j].spp; ++k) units.push_back({j, k});
-  size_t next_unit = 0;
-  auto unit_slots = [&](const RepUnit& u) { return aj[u.job].params_b ? 2 : 1; };
+using Plan = std::vector<LaunchRec>;
 
-  // primal samples in job order
+template <class U>
+void push_unit(LaunchRec& r, U u, uint32_t blocks) {
+  u.h.block0 = r.blocks;
+  const size_t off = r.units.size();
+  r.units.resize(off + sizeof(U));
+  std::memcpy(r.units.data() + off, &u, sizeof(U));
+  r.n++;
+  r.blocks += blocks;
+}
+
+uint32_t tiles_x(const Crop& c) { return (uint32_t)((c.x1 - c.x0 + kTile - 1) / kTile); }
+uint32_t tiles_of(const Crop& c) {
+  return tiles_x(c) * (uint32_t)((c.y1 - c.y0 + kTile - 1) / kTile);
+}
+
+bool crop_empty(const Crop& c) { return c.x1 <= c.x0 || c.y1 <= c.y0; }
+
+// The launches of the estimator part of a step for problems `ps` (all with the
+// same job structure).
+void plan_estimators(const std::vector<ProbPlan>& ps, Plan& plan) {
+  if (ps.empty()) return;
+  const ProbPlan& p0 = ps[0];
+  // primal samples in job order; replay units, pairs first: within a launch
+  // blocks are dispatched in order and a pair block traces twice the paths of
+  // a single one
   std::vector<std::pair<int, int>> prim;
-  for (int j = 0; j < np; ++j)
-    for (int k = 0; k < pj[j].spp; ++k) prim.push_back({j, k});
-  size_t next_prim = 0;
-  const FinArgs fin_base = [&] {
-    FinArgs f{};
-    f.slots = s->slots;
-    f.npix = (uint32_t)s->npix;
-    f.key = q.key;
-    f.crop = q.crop;
-    f.mask = q.mask;
-    f.target = s->target;
-    f.delta_scale = (float)(2.0 / (3.0 * (double)s->npix));
-    f.loss_scale = 1.0 / (3.0 * (double)s->npix);
-    return f;
-  }();
-
+  for (int j = 0; j < p0.np; ++j)
+    for (int k = 0; k < p0.pj[j].spp; ++k) prim.push_back({j, k});
+  std::vector<std::pair<int, int>> units;
+  for (int pass = 0; pass < 2; ++pass)
+    for (int j = 0; j < p0.na; ++j)
+      if ((p0.aj[j].params_b != nullptr) == (pass == 0))
+        for (int k = 0; k < p0.aj[j].spp; ++k) units.push_back({j, k});
+  size_t next_prim = 0, next_unit = 0;
+  int max_ch = 0;
+  for (const ProbPlan& p : ps) max_ch = std::max(max_ch, p.s->n_ch);
   while (next_prim < prim.size() || next_unit < units.size()) {
-    FwdArgs f = fwd_args(q);
-    int n = 0;
-    // primal slices of this launch
-    FinArgs fin = fin_base;
-    while (next_prim < prim.size() && n < kMaxSlots) {
+    // slice layout of this launch (shared by all problems)
+    struct FSl { int kind, job, sample; };  // kind 0 primal, 1 adjoint A, 2 adjoint B
+    std::vector<FSl> fsl;
+    std::vector<std::pair<int, int>> fin_jobs;  // (job, first slot)
+    while (next_prim < prim.size() && (int)fsl.size() < kMaxSlots) {
       const int j = prim[next_prim].first, k = prim[next_prim].second;
-      f.sl[n] = FwdSlice{pj[j].params, pj[j].tag, (uint32_t)k, n};
-      if (fin.n_jobs == 0 || fin.jobs[fin.n_jobs - 1].slot0 + fin.jobs[fin.n_jobs - 1].n != n ||
-          fin.jobs[fin.n_jobs - 1].accum != s->accum + (size_t)j * 3 * s->npix) {
-        FinJob fj{};
-        fj.slot0 = n;
-        fj.n = 0;
-        fj.accum = s->accum + (size_t)j * 3 * s->npix;
-        fj.first = k == 0;
-        fj.inv_spp = 1.0 / (double)pj[j].spp;
-        fj.img = pj[j].img;
-        fj.delta = pj[j].delta;
-        fj.loss2 = pj[j].loss2;
-        fin.jobs[fin.n_jobs++] = fj;
-      }
-      FinJob& fj = fin.jobs[fin.n_jobs - 1];
-      fj.n++;
-      fj.last = k == pj[j].spp - 1;
-      ++n;
+      if (fin_jobs.empty() || fin_jobs.back().first != j) fin_jobs.push_back({j, (int)fsl.size()});
+      fsl.push_back({0, j, k});
       ++next_prim;
     }
-    // adjoint forward slices, once every primal sample has a slot
-    RepArgs r = rep_args(q);
-    int nr = 0;
+    std::vector<std::pair<int, int>> reps;  // replay units of this launch
+    std::vector<std::pair<int, int>> rep_slot;
     if (next_prim == prim.size()) {
-      while (next_unit < units.size() && n + unit_slots(units[next_unit]) <= kMaxSlots) {
-        const RepUnit u = units[next_unit++];
-        const AdjointSpec& a = aj[u.job];
-        RepSlice rs{};
-        rs.params = a.params;
-        rs.params_b = a.params_b;
-        rs.delta = a.delta;
-        rs.delta_b = a.delta_b;
-        rs.grad = a.grad;
-        rs.sign = a.sign;
-        rs.adj_scale = (float)(1.0 / (double)a.spp);
-        rs.tag = a.tag;
-        rs.sample = (uint32_t)u.sample;
-        rs.slot_a = n;
-        f.sl[n++] = FwdSlice{a.params, a.tag, (uint32_t)u.sample, rs.slot_a};
-        if (a.params_b) {
-          rs.slot_b = n;
-          f.sl[n++] = FwdSlice{a.params_b, a.tag, (uint32_t)u.sample, rs.slot_b};
+      while (next_unit < units.size()) {
+        const auto u = units[next_unit];
+        const int need = p0.aj[u.first].params_b ? 2 : 1;
+        if ((int)fsl.size() + need > kMaxSlots) break;
+        const int sa = (int)fsl.size();
+        fsl.push_back({1, u.first, u.second});
+        int sb = -1;
+        if (need == 2) {
+          sb = (int)fsl.size();
+          fsl.push_back({2, u.first, u.second});
         }
-        r.sl[nr++] = rs;
+        reps.push_back(u);
+        rep_slot.push_back({sa, sb});
+        ++next_unit;
       }
     }
-    if (n == 0) return fail(c, JSO_E_INVALID, "schedule: empty launch");
-    TIMED_LAUNCH(c, JSO_K_FORWARD, launch_forward(s->d_scene, f, n, c->stream));
-    if (fin.n_jobs > 0)
-      TIMED_LAUNCH(c, JSO_K_FINALIZE, launch_finalize(fin, s->width, c->stream));
-    if (nr > 0)
-      TIMED_LAUNCH(c, JSO_K_ADJOINT, launch_adjoint(s->d_scene, r, nr, s->n_ch, c->stream));
+    // k_forward
+    LaunchRec fw;
+    fw.kind = Kern::Forward;
+    fw.timer = JSO_K_FORWARD;
+    for (const ProbPlan& p : ps) {
+      if (crop_empty(p.crop)) continue;
+      FwdArgs f{};
+      f.h.max_iter = p.max_iter;
+      f.scene = cmem((const DevScene*)p.s->d_scene);
+      for (size_t i = 0; i < fsl.size(); ++i) {
+        const FSl& x = fsl[i];
+        if (x.kind == 0)
+          f.sl[i] = FwdSlice{gmem(p.pj[x.job].params), p.pj[x.job].tag, (uint32_t)x.sample, (int)i};
+        else
+          f.sl[i] = FwdSlice{gmem(x.kind == 1 ? p.aj[x.job].params : p.aj[x.job].params_b),
+                             p.aj[x.job].tag, (uint32_t)x.sample, (int)i};
+      }
+      f.n_slices = (int)fsl.size();
+      f.key = p.key;
+      f.crop = p.crop;
+      f.mask = gmem(p.mask);
+      f.slots = gmem(p.s->slots);
+      f.npix = (uint32_t)p.s->npix;
+      f.flags = p.flags;
+      f.tiles_x = tiles_x(p.crop);
+      f.tiles = tiles_of(p.crop);
+      push_unit(fw, f, f.tiles * (uint32_t)f.n_slices);
+    }
+    plan.push_back(std::move(fw));
+    // k_finalize of the primal jobs with samples in this launch
+    if (!fin_jobs.empty()) {
+      LaunchRec fr;
+      fr.kind = Kern::Finalize;
+      fr.timer = JSO_K_FINALIZE;
+      for (const ProbPlan& p : ps) {
+        if (crop_empty(p.crop)) continue;
+        FinArgs f{};
+        f.h.max_iter = p.max_iter;
+        for (size_t q = 0; q < fin_jobs.size(); ++q) {
+          const int j = fin_jobs[q].first, s0 = fin_jobs[q].second;
+          int n = 0, first_sample = -1, last_sample = -1;
+          for (const FSl& x : fsl)
+            if (x.kind == 0 && x.job == j) {
+              if (first_sample < 0) first_sample = x.sample;
+              last_sample = x.sample;
+              ++n;
+            }
+          FinJob fj{};
+          fj.slot0 = s0;
+          fj.n = n;
+          fj.accum = gmem(p.s->accum + (size_t)j * 3 * p.s->npix);
+          fj.first = first_sample == 0;
+          fj.last = last_sample == p.pj[j].spp - 1;
+          fj.inv_spp = 1.0 / (double)p.pj[j].spp;
+          fj.img = gmem(p.pj[j].img);
+          fj.delta = gmem(p.pj[j].delta);
+          fj.loss2 = gmem(p.pj[j].loss2);
+          f.jobs[f.n_jobs++] = fj;
+        }
+        f.slots = gmem(p.s->slots);
+        f.npix = (uint32_t)p.s->npix;
+        f.width = p.s->width;
+        f.key = p.key;
+        f.crop = p.crop;
+        f.mask = gmem(p.mask);
+        f.target = gmem((const float*)p.s->target);
+        f.delta_scale = (float)(2.0 / (3.0 * (double)p.s->npix));
+        f.loss_scale = 1.0 / (3.0 * (double)p.s->npix);
+        const size_t pix = (size_t)(p.crop.x1 - p.crop.x0) * (size_t)(p.crop.y1 - p.crop.y0);
+        const size_t want = (pix + kFinBlock - 1) / kFinBlock;
+        f.nblocks = (uint32_t)std::min<size_t>(std::max<size_t>(want, 1), kFinMaxBlocks);
+        push_unit(fr, f, f.nblocks * (uint32_t)f.n_jobs);
+      }
+      plan.push_back(std::move(fr));
+    }
+    // k_adjoint: pair units of every problem first, then single-path units
+    if (!reps.empty()) {
+      LaunchRec ad;
+      ad.kind = Kern::Adjoint;
+      ad.timer = JSO_K_ADJOINT;
+      ad.lds = adjoint_lds_bytes(max_ch);
+      for (int pass = 0; pass < 2; ++pass) {
+        for (const ProbPlan& p : ps) {
+          if (crop_empty(p.crop)) continue;
+          RepArgs r{};
+          r.h.max_iter = p.max_iter;
+          r.scene = cmem((const DevScene*)p.s->d_scene);
+          for (size_t i = 0; i < reps.size(); ++i) {
+            const AdjointSpec& a = p.aj[reps[i].first];
+            if ((a.params_b != nullptr) != (pass == 0)) continue;
+            RepSlice rs{};
+            rs.params = gmem(a.params);
+            rs.params_b = gmem(a.params_b);
+            rs.delta = gmem(a.delta);
+            rs.delta_b = gmem(a.delta_b);
+            rs.grad = gmem(a.grad);
+            rs.sign = a.sign;
+            rs.adj_scale = (float)(1.0 / (double)a.spp);
+            rs.tag = a.tag;
+            rs.sample = (uint32_t)reps[i].second;
+            rs.slot_a = rep_slot[i].first;
+            rs.slot_b = rep_slot[i].second;
+            r.sl[r.n_slices++] = rs;
+          }
+          if (r.n_slices == 0) continue;
+          r.key = p.key;
+          r.crop = p.crop;
+          r.mask = gmem(p.mask);
+          r.slots = gmem((const double*)p.s->slots);
+          r.npix = (uint32_t)p.s->npix;
+          r.flags = p.flags;
+          r.tiles_x = tiles_x(p.crop);
+          r.tiles = tiles_of(p.crop);
+          push_unit(ad, r, r.tiles * (uint32_t)r.n_slices);
+        }
+      }
+      plan.push_back(std::move(ad));
+    }
   }
-  return JSO_OK;
 }
 
-// Queue the kernels of one gradient sample set.
-//   prop:  F += <F_i> from spp_prop paths at params
-//   fd:    dF += <dF_i> from spp_fd path pairs at (params, params_prev)
-int queue_estimators(jso_ctx* c, SceneGPU* s, uint64_t seed, uint32_t iteration,
-                     const uint32_t* iter_ptr, int spp_prop, int spp_fd, const float* params,
-                     const float* params_prev, float* F, float* dF, float* img, double* loss2,
-                     uint32_t prop_primal_tag, uint32_t prop_adj_tag, const Crop& crop,
-                     const uint8_t* mask, uint32_t flags) {
-  const size_t n3 = 3 * s->npix;
-  float* d_prop = s->delta;
-  float* d_cur = s->delta + n3;
-  float* d_prev = s->delta + 2 * n3;
-  const bool fd = dF != nullptr && spp_fd > 0;
-  PrimalSpec pj[3];
-  int np = 0;
-  pj[np++] = PrimalSpec{params, prop_primal_tag, spp_prop, img, d_prop, loss2};
-  if (fd) {
-    pj[np++] = PrimalSpec{params, JSO_TAG_PRIMAL_FD, spp_fd, nullptr, d_cur, nullptr};
-    pj[np++] = PrimalSpec{params_prev, JSO_TAG_PRIMAL_FD, spp_fd, nullptr, d_prev, nullptr};
-  }
-  AdjointSpec aj[2];
-  int na = 0;
-  aj[na++] = AdjointSpec{params, nullptr, d_prop, nullptr, F, 1.0f, prop_adj_tag, spp_prop};
-  if (fd)
-    aj[na++] = AdjointSpec{params, params_prev, d_cur, d_prev, dF, 1.0f, JSO_TAG_ADJ_FD, spp_fd};
-  const Schedule q{c, s, KeyArgs{seed, iteration, iter_ptr}, crop, mask, flags};
-  return run_schedule(q, pj, np, aj, na);
+uint32_t meta_blocks(size_t P) {
+  const size_t want = (P + (size_t)kMetaBlock * kMetaK - 1) / ((size_t)kMetaBlock * kMetaK);
+  return (uint32_t)std::min<size_t>(std::max<size_t>(want, 1), kMetaMaxBlocks);
 }
 
 MetaArgs meta_args(SceneGPU* s, const float* F, const float* dF, float eta, float bF, float bD,
                    int zero_grads) {
   MetaArgs m{};
-  m.params = s->params;
-  m.params_prev = s->params_prev;
-  m.F = const_cast<float*>(F);
-  m.dF = const_cast<float*>(dF);
-  m.mean = s->mean;
-  m.var = s->var;
-  m.alpha_prev = s->alpha_prev;
-  m.m2F = s->m2F;
-  m.m2D = s->m2D;
-  m.ctl = s->ctl;
-  m.partials = s->partials;
+  m.nblocks = meta_blocks(s->P);
+  m.params = gmem(s->params);
+  m.params_prev = gmem(s->params_prev);
+  m.F = gmem(const_cast<float*>(F));
+  m.dF = gmem(const_cast<float*>(dF));
+  m.mean = gmem(s->mean);
+  m.var = gmem(s->var);
+  m.alpha_prev = gmem(s->alpha_prev);
+  m.m2F = gmem(s->m2F);
+  m.m2D = gmem(s->m2D);
+  m.ctl = gmem(s->ctl);
+  m.partials = gmem(s->partials);
   m.n = s->P;
   m.n_ch = s->n_ch;
   for (int k = 0; k < 5; ++k) {
@@ -520,12 +678,14 @@ MetaArgs meta_args(SceneGPU* s, const float* F, const float* dF, float eta, floa
 AdamArgs adam_args(SceneGPU* s, const float* g, float eta, float b1, float b2, float eps,
                    int zero_grads) {
   AdamArgs a{};
-  a.params = s->params;
-  a.params_prev = s->params_prev;
-  a.g = const_cast<float*>(g);
-  a.m = s->adam_m;
-  a.v = s->adam_v;
-  a.ctl = s->ctl;
+  const size_t want = (s->P + kMetaBlock - 1) / kMetaBlock;
+  a.nblocks = (uint32_t)std::min<size_t>(std::max<size_t>(want, 1), 2048);
+  a.params = gmem(s->params);
+  a.params_prev = gmem(s->params_prev);
+  a.g = gmem(const_cast<float*>(g));
+  a.m = gmem(s->adam_m);
+  a.v = gmem(s->adam_v);
+  a.ctl = gmem(s->ctl);
   a.n = s->P;
   a.n_ch = s->n_ch;
   for (int k = 0; k < 5; ++k) {
@@ -538,6 +698,207 @@ AdamArgs adam_args(SceneGPU* s, const float* g, float eta, float b1, float b2, f
   a.eps = eps;
   a.zero_grads = zero_grads;
   return a;
+}
+
+// The optimiser launch of a step over problems ps.
+void plan_optimizer(const std::vector<ProbPlan>& ps, const jso_step_opts& o, Plan& plan) {
+  LaunchRec r;
+  if (o.optimizer == JSO_OPT_META) {
+    r.kind = Kern::Meta;
+    r.timer = JSO_K_META;
+    for (const ProbPlan& p : ps) {
+      MetaArgs m = meta_args(p.s, p.s->F, p.s->dF, o.eta, o.beta_F, o.beta_D, 1);
+      m.h.max_iter = p.max_iter;
+      push_unit(r, m, m.nblocks);
+    }
+  } else {
+    r.kind = Kern::Adam;
+    r.timer = JSO_K_ADAM;
+    for (const ProbPlan& p : ps) {
+      AdamArgs a = adam_args(p.s, p.s->F, o.eta, o.adam_beta1, o.adam_beta2, o.adam_eps, 1);
+      a.h.max_iter = p.max_iter;
+      push_unit(r, a, a.nblocks);
+    }
+  }
+  plan.push_back(std::move(r));
+}
+
+// One problem of a grad_step: the estimator jobs of its optimiser.
+ProbPlan step_problem(SceneGPU* s, const jso_step_opts& o, uint32_t flags, uint32_t max_iter) {
+  ProbPlan p{};
+  p.s = s;
+  p.key = KeyArgs{o.seed, 0u, gmem((const uint32_t*)&s->ctl->iteration)};  // the kernels read the device counter
+  p.crop = Crop{0, 0, s->width, s->height};
+  p.mask = nullptr;
+  p.flags = flags;
+  p.max_iter = max_iter;
+  const size_t n3 = 3 * s->npix;
+  float* d_prop = s->delta;
+  if (o.optimizer == JSO_OPT_META) {
+    const bool fd = o.spp_fd > 0;
+    p.pj[p.np++] = PrimalSpec{s->params, JSO_TAG_PRIMAL_PROP, o.spp_prop, nullptr, d_prop,
+                              s->ctl->loss};
+    if (fd) {
+      p.pj[p.np++] = PrimalSpec{s->params, JSO_TAG_PRIMAL_FD, o.spp_fd, nullptr, s->delta + n3,
+                                nullptr};
+      p.pj[p.np++] = PrimalSpec{s->params_prev, JSO_TAG_PRIMAL_FD, o.spp_fd, nullptr,
+                                s->delta + 2 * n3, nullptr};
+    }
+    p.aj[p.na++] = AdjointSpec{s->params, nullptr, d_prop, nullptr, s->F, 1.0f,
+                               JSO_TAG_ADJ_PROP, o.spp_prop};
+    if (fd)
+      p.aj[p.na++] = AdjointSpec{s->params, s->params_prev, s->delta + n3, s->delta + 2 * n3,
+                                 s->dF, 1.0f, JSO_TAG_ADJ_FD, o.spp_fd};
+  } else {
+    p.pj[p.np++] = PrimalSpec{s->params, JSO_TAG_ADAM_PRIMAL, o.adam_spp, nullptr, d_prop,
+                              s->ctl->loss};
+    p.aj[p.na++] = AdjointSpec{s->params, nullptr, d_prop, nullptr, s->F, 1.0f,
+                               JSO_TAG_ADAM_ADJ, o.adam_spp};
+  }
+  return p;
+}
+
+int check_step_opts(jso_ctx* c, const jso_step_opts* o) {
+  if (o->optimizer == JSO_OPT_META) {
+    if (o->spp_prop < 1 || o->spp_prop > 64 || o->spp_fd < 0 || o->spp_fd > 64)
+      return fail(c, JSO_E_INVALID, "spp out of range");
+    if (!(o->beta_F >= 0.0f && o->beta_F < 1.0f && o->beta_D >= 0.0f && o->beta_D < 1.0f))
+      return fail(c, JSO_E_INVALID, "beta must lie in [0, 1)");
+  } else if (o->optimizer == JSO_OPT_ADAM) {
+    if (o->adam_spp < 1 || o->adam_spp > 4096) return fail(c, JSO_E_INVALID, "adam_spp");
+    if (!(o->adam_beta1 >= 0.0f && o->adam_beta1 < 1.0f && o->adam_beta2 >= 0.0f &&
+          o->adam_beta2 < 1.0f))
+      return fail(c, JSO_E_INVALID, "beta must lie in [0, 1)");
+  } else {
+    return fail(c, JSO_E_INVALID, "unknown optimizer %d", o->optimizer);
+  }
+  return JSO_OK;
+}
+
+hipError_t launch_rec(const LaunchRec& r, const void* dev_units, unsigned long long* work,
+                      hipStream_t st) {
+  switch (r.kind) {
+    case Kern::Forward:
+      return launch_forward(static_cast<const FwdArgs*>(dev_units), r.n, r.blocks, work, st);
+    case Kern::Finalize:
+      return launch_finalize(static_cast<const FinArgs*>(dev_units), r.n, r.blocks, st);
+    case Kern::Adjoint:
+      return launch_adjoint(static_cast<const RepArgs*>(dev_units), r.n, r.blocks, r.lds, work,
+                            st);
+    case Kern::Meta:
+      return launch_meta(static_cast<const MetaArgs*>(dev_units), r.n, r.blocks, st);
+    case Kern::Adam:
+      return launch_adam(static_cast<const AdamArgs*>(dev_units), r.n, r.blocks, st);
+  }
+  return hipErrorInvalidValue;
+}
+
+// Run a plan now: each launch's units are staged through the context's ring.
+int exec_plan(jso_ctx* c, const Plan& plan) {
+  unsigned long long* work = c->counting ? c->d_work : nullptr;
+  for (const LaunchRec& r : plan) {
+    if (r.n == 0) continue;
+    const void* dev = nullptr;
+    HIP_TRY(c, c->ring.put(r.units.data(), r.units.size(), c->stream, &dev));
+    TIMED_LAUNCH(c, r.timer, launch_rec(r, dev, work, c->stream));
+  }
+  return JSO_OK;
+}
+
+// Concatenate a plan's unit arrays (256-byte aligned) and note each offset.
+std::vector<uint8_t> pack_plan(const Plan& plan, std::vector<size_t>& off) {
+  std::vector<uint8_t> all;
+  off.clear();
+  for (const LaunchRec& r : plan) {
+    off.push_back(all.size());
+    all.insert(all.end(), r.units.begin(), r.units.end());
+    all.resize((all.size() + 255) & ~(size_t)255);
+  }
+  return all;
+}
+
+// grad_step: launch the cached plan when `sig` matches, else build it with
+// `build`, upload it once and cache it.
+template <class Build>
+int exec_cached(jso_ctx* c, const std::vector<uint64_t>& sig, Build build) {
+  PlanCache& pc = c->plan_cache;
+  CachedPlan* hit = nullptr;
+  for (CachedPlan& p : pc.plans)
+    if (p.sig == sig) hit = &p;
+  if (!hit) {
+    Plan plan;
+    build(plan);
+    std::vector<size_t> off;
+    const std::vector<uint8_t> all = pack_plan(plan, off);
+    if (pc.plans.size() >= PlanCache::kMaxPlans) {
+      // evict the least recently used plan once no launch can still read it
+      size_t lru = 0;
+      for (size_t k = 1; k < pc.plans.size(); ++k)
+        if (pc.plans[k].last_use < pc.plans[lru].last_use) lru = k;
+      HIP_TRY(c, hipStreamSynchronize(c->stream));
+      PlanCache::release(pc.plans[lru]);
+      pc.plans.erase(pc.plans.begin() + (long)lru);
+    }
+    CachedPlan np;
+    if (hipHostMalloc(reinterpret_cast<void**>(&np.host), all.size(), 0) != hipSuccess ||
+        hipMalloc(reinterpret_cast<void**>(&np.dev), all.size()) != hipSuccess) {
+      PlanCache::release(np);
+      return fail(c, JSO_E_OOM, "launch descriptors");
+    }
+    std::memcpy(np.host, all.data(), all.size());
+    const hipError_t e =
+        hipMemcpyAsync(np.dev, np.host, all.size(), hipMemcpyHostToDevice, c->stream);
+    if (e != hipSuccess) {
+      PlanCache::release(np);
+      HIP_TRY(c, e);
+    }
+    for (size_t k = 0; k < plan.size(); ++k) {
+      const LaunchRec& r = plan[k];
+      np.launches.push_back(CachedLaunch{(int)r.kind, r.timer, r.n, r.blocks, r.lds, off[k]});
+    }
+    np.sig = sig;
+    pc.plans.push_back(std::move(np));
+    hit = &pc.plans.back();
+  }
+  hit->last_use = ++pc.clock;
+  unsigned long long* work = c->counting ? c->d_work : nullptr;
+  for (const CachedLaunch& l : hit->launches) {
+    if (l.n == 0) continue;
+    LaunchRec r;
+    r.kind = (Kern)l.kind;
+    r.n = l.n;
+    r.blocks = l.blocks;
+    r.lds = l.lds;
+    TIMED_LAUNCH(c, l.timer, launch_rec(r, hit->dev + l.offset, work, c->stream));
+  }
+  return JSO_OK;
+}
+
+// The estimator jobs of jso_estimate_gradients (same streams as a meta step).
+ProbPlan estimate_problem(SceneGPU* s, uint64_t seed, uint32_t iteration, int spp_prop,
+                          int spp_fd, float* F, float* dF, float* img, double* loss2,
+                          const Crop& crop, const uint8_t* mask, uint32_t flags) {
+  ProbPlan p{};
+  p.s = s;
+  p.key = KeyArgs{seed, iteration, nullptr};
+  p.crop = crop;
+  p.mask = mask;
+  p.flags = flags;
+  const size_t n3 = 3 * s->npix;
+  const bool fd = dF != nullptr && spp_fd > 0;
+  p.pj[p.np++] = PrimalSpec{s->params, JSO_TAG_PRIMAL_PROP, spp_prop, img, s->delta, loss2};
+  if (fd) {
+    p.pj[p.np++] = PrimalSpec{s->params, JSO_TAG_PRIMAL_FD, spp_fd, nullptr, s->delta + n3,
+                              nullptr};
+    p.pj[p.np++] = PrimalSpec{s->params_prev, JSO_TAG_PRIMAL_FD, spp_fd, nullptr,
+                              s->delta + 2 * n3, nullptr};
+  }
+  p.aj[p.na++] = AdjointSpec{s->params, nullptr, s->delta, nullptr, F, 1.0f, JSO_TAG_ADJ_PROP,
+                             spp_prop};
+  if (fd)
+    p.aj[p.na++] = AdjointSpec{s->params, s->params_prev, s->delta + n3, s->delta + 2 * n3, dF,
+                               1.0f, JSO_TAG_ADJ_FD, spp_fd};
+  return p;
 }
 
 }  // namespace
@@ -568,6 +929,8 @@ int jso_destroy(jso_ctx* c) {
   for (auto& s : c->scenes)
     if (s) free_scene_buffers(s.get());
   c->timer.destroy();
+  c->ring.destroy();
+  c->plan_cache.destroy();
   if (c->d_work) (void)hipFree(c->d_work);
   delete c;
   return JSO_OK;
@@ -613,6 +976,7 @@ int jso_load_scene(jso_ctx* c, const jso_scene_desc* d, int* scene_id) {
   DeviceGuard g(c->device);
   std::unique_ptr<SceneGPU> s(new (std::nothrow) SceneGPU());
   if (!s) return fail(c, JSO_E_OOM, "host allocation failed");
+  s->generation = ++g_scene_generation;
   int rc = build_devscene(c, d, s.get());
   if (rc) return rc;
   const size_t P = s->P, n3 = 3 * s->npix;
@@ -727,10 +1091,16 @@ int jso_render(jso_ctx* c, int id, const float* params, uint64_t seed, uint32_t 
   if (!params || !img) return fail(c, JSO_E_INVALID, "null params/img");
   if (spp < 1) return fail(c, JSO_E_INVALID, "spp must be >= 1");
   DeviceGuard g(c->device);
-  const PrimalSpec pj{params, tag, spp, img, nullptr, nullptr};
-  const Schedule q{c, s, KeyArgs{seed, iteration, nullptr}, crop_of(s, opts),
-                   opts ? opts->pixel_mask : nullptr, c->debug_flags | (opts ? opts->flags : 0u)};
-  return run_schedule(q, &pj, 1, nullptr, 0);
+  ProbPlan p{};
+  p.s = s;
+  p.key = KeyArgs{seed, iteration, nullptr};
+  p.crop = crop_of(s, opts);
+  p.mask = opts ? opts->pixel_mask : nullptr;
+  p.flags = c->debug_flags | (opts ? opts->flags : 0u);
+  p.pj[p.np++] = PrimalSpec{params, tag, spp, img, nullptr, nullptr};
+  Plan plan;
+  plan_estimators({p}, plan);
+  return exec_plan(c, plan);
 }
 
 int jso_render_bwd(jso_ctx* c, int id, const float* params, uint64_t seed, uint32_t iteration,
@@ -741,10 +1111,16 @@ int jso_render_bwd(jso_ctx* c, int id, const float* params, uint64_t seed, uint3
   if (!params || !dimg || !dparams) return fail(c, JSO_E_INVALID, "null argument");
   if (spp < 1) return fail(c, JSO_E_INVALID, "spp must be >= 1");
   DeviceGuard g(c->device);
-  const AdjointSpec aj{params, nullptr, dimg, nullptr, dparams, 1.0f, tag, spp};
-  const Schedule q{c, s, KeyArgs{seed, iteration, nullptr}, crop_of(s, opts),
-                   opts ? opts->pixel_mask : nullptr, c->debug_flags | (opts ? opts->flags : 0u)};
-  return run_schedule(q, nullptr, 0, &aj, 1);
+  ProbPlan p{};
+  p.s = s;
+  p.key = KeyArgs{seed, iteration, nullptr};
+  p.crop = crop_of(s, opts);
+  p.mask = opts ? opts->pixel_mask : nullptr;
+  p.flags = c->debug_flags | (opts ? opts->flags : 0u);
+  p.aj[p.na++] = AdjointSpec{params, nullptr, dimg, nullptr, dparams, 1.0f, tag, spp};
+  Plan plan;
+  plan_estimators({p}, plan);
+  return exec_plan(c, plan);
 }
 
 int jso_estimate_gradients(jso_ctx* c, int id, uint64_t seed, uint32_t iteration, int spp_prop,
@@ -757,10 +1133,13 @@ int jso_estimate_gradients(jso_ctx* c, int id, uint64_t seed, uint32_t iteration
     return fail(c, JSO_E_INVALID, "spp out of range");
   DeviceGuard g(c->device);
   HIP_TRY(c, hipMemsetAsync(s->scratch_loss, 0, 2 * sizeof(double), c->stream));
-  int rc = queue_estimators(c, s, seed, iteration, nullptr, spp_prop, spp_fd, s->params,
-                            s->params_prev, F, dF, img, s->scratch_loss, JSO_TAG_PRIMAL_PROP,
-                            JSO_TAG_ADJ_PROP, crop_of(s, opts), opts ? opts->pixel_mask : nullptr,
-                            c->debug_flags | (opts ? opts->flags : 0u));
+  Plan plan;
+  plan_estimators({estimate_problem(s, seed, iteration, spp_prop, spp_fd, F, dF, img,
+                                    s->scratch_loss, crop_of(s, opts),
+                                    opts ? opts->pixel_mask : nullptr,
+                                    c->debug_flags | (opts ? opts->flags : 0u))},
+                  plan);
+  int rc = exec_plan(c, plan);
   if (rc) return rc;
   if (loss) {
     double l2[2];
@@ -779,7 +1158,13 @@ int jso_meta_step(jso_ctx* c, int id, const float* F, const float* dF, float eta
   if (!(beta_F >= 0.0f && beta_F < 1.0f && beta_D >= 0.0f && beta_D < 1.0f))
     return fail(c, JSO_E_INVALID, "beta must lie in [0, 1)");
   DeviceGuard g(c->device);
-  TIMED_LAUNCH(c, JSO_K_META, launch_meta(meta_args(s, F, dF, eta, beta_F, beta_D, 0), c->stream));
+  LaunchRec r;
+  r.kind = Kern::Meta;
+  r.timer = JSO_K_META;
+  const MetaArgs m = meta_args(s, F, dF, eta, beta_F, beta_D, 0);
+  push_unit(r, m, m.nblocks);
+  int rc = exec_plan(c, Plan{r});
+  if (rc) return rc;
   s->host_iter++;
   return JSO_OK;
 }
@@ -792,8 +1177,28 @@ int jso_adam_step(jso_ctx* c, int id, const float* grad, float eta, float beta1,
   if (!(beta1 >= 0.0f && beta1 < 1.0f && beta2 >= 0.0f && beta2 < 1.0f))
     return fail(c, JSO_E_INVALID, "beta must lie in [0, 1)");
   DeviceGuard g(c->device);
-  TIMED_LAUNCH(c, JSO_K_ADAM, launch_adam(adam_args(s, grad, eta, beta1, beta2, eps, 0), c->stream));
+  LaunchRec r;
+  r.kind = Kern::Adam;
+  r.timer = JSO_K_ADAM;
+  const AdamArgs a = adam_args(s, grad, eta, beta1, beta2, eps, 0);
+  push_unit(r, a, a.nblocks);
+  int rc = exec_plan(c, Plan{r});
+  if (rc) return rc;
   s->host_iter++;
+  return JSO_OK;
+}
+
+int read_stats(jso_ctx* c, const int* ids, int n, jso_step_stats* stats) {
+  HIP_TRY(c, hipStreamSynchronize(c->stream));
+  for (int k = 0; k < n; ++k) {
+    SceneGPU* s = get_scene(c, ids[k]);
+    Ctl h;
+    HIP_TRY(c, hipMemcpy(&h, s->ctl, sizeof(Ctl), hipMemcpyDeviceToHost));
+    const uint32_t done = h.iteration - 1u;  // the iteration just completed
+    stats[k].loss = h.loss[done & 1u];
+    stats[k].step_norm2 = h.norm2[h.iteration & 1u];
+    stats[k].iteration = h.iteration;
+  }
   return JSO_OK;
 }
 
@@ -801,56 +1206,165 @@ int jso_grad_step(jso_ctx* c, const int* ids, int n, const jso_step_opts* o,
                   jso_step_stats* stats) {
   if (!c) return JSO_E_INVALID;
   if (!ids || n <= 0 || !o) return fail(c, JSO_E_INVALID, "null/empty argument");
-  for (int k = 0; k < n; ++k)
+  for (int k = 0; k < n; ++k) {
     if (!get_scene(c, ids[k])) return fail(c, JSO_E_INVALID, "bad scene id %d", ids[k]);
+    for (int q = 0; q < k; ++q)
+      if (ids[q] == ids[k]) return fail(c, JSO_E_INVALID, "scene %d listed twice", ids[k]);
+  }
+  int rc = check_step_opts(c, o);
+  if (rc) return rc;
   DeviceGuard g(c->device);
   const uint32_t flags = c->debug_flags | o->flags;
+  std::vector<uint64_t> sig;
+  auto bits = [](float f) {
+    uint32_t u;
+    std::memcpy(&u, &f, 4);
+    return (uint64_t)u;
+  };
   for (int k = 0; k < n; ++k) {
-    SceneGPU* s = get_scene(c, ids[k]);
-    const Crop full{0, 0, s->width, s->height};
-    if (o->optimizer == JSO_OPT_META) {
-      if (o->spp_prop < 1 || o->spp_prop > 64 || o->spp_fd < 0 || o->spp_fd > 64)
-        return fail(c, JSO_E_INVALID, "spp out of range");
-      if (!(o->beta_F >= 0.0f && o->beta_F < 1.0f && o->beta_D >= 0.0f && o->beta_D < 1.0f))
-        return fail(c, JSO_E_INVALID, "beta must lie in [0, 1)");
-      int rc = queue_estimators(c, s, o->seed, s->host_iter, &s->ctl->iteration, o->spp_prop,
-                                o->spp_fd, s->params, s->params_prev, s->F, s->dF, nullptr,
-                                s->ctl->loss, JSO_TAG_PRIMAL_PROP, JSO_TAG_ADJ_PROP, full,
-                                nullptr, flags);
-      if (rc) return rc;
-      TIMED_LAUNCH(c, JSO_K_META,
-                   launch_meta(meta_args(s, s->F, s->dF, o->eta, o->beta_F, o->beta_D, 1),
-                               c->stream));
-    } else if (o->optimizer == JSO_OPT_ADAM) {
-      if (o->adam_spp < 1 || o->adam_spp > 4096) return fail(c, JSO_E_INVALID, "adam_spp");
-      if (!(o->adam_beta1 >= 0.0f && o->adam_beta1 < 1.0f && o->adam_beta2 >= 0.0f &&
-            o->adam_beta2 < 1.0f))
-        return fail(c, JSO_E_INVALID, "beta must lie in [0, 1)");
-      int rc = queue_estimators(c, s, o->seed, s->host_iter, &s->ctl->iteration, o->adam_spp, 0,
-                                s->params, s->params_prev, s->F, nullptr, nullptr, s->ctl->loss,
-                                JSO_TAG_ADAM_PRIMAL, JSO_TAG_ADAM_ADJ, full, nullptr, flags);
-      if (rc) return rc;
-      TIMED_LAUNCH(c, JSO_K_ADAM,
-                   launch_adam(adam_args(s, s->F, o->eta, o->adam_beta1, o->adam_beta2,
-                                         o->adam_eps, 1),
-                               c->stream));
+    sig.push_back((uint64_t)ids[k]);
+    sig.push_back(get_scene(c, ids[k])->generation);
+  }
+  for (uint64_t v : {(uint64_t)o->optimizer, bits(o->eta), bits(o->beta_F), bits(o->beta_D),
+                     (uint64_t)o->spp_prop, (uint64_t)o->spp_fd, bits(o->adam_beta1),
+                     bits(o->adam_beta2), bits(o->adam_eps), (uint64_t)o->adam_spp, o->seed,
+                     (uint64_t)flags})
+    sig.push_back(v);
+  rc = exec_cached(c, sig, [&](Plan& plan) {
+    std::vector<ProbPlan> ps;
+    for (int k = 0; k < n; ++k) ps.push_back(step_problem(get_scene(c, ids[k]), *o, flags, 0));
+    plan_estimators(ps, plan);
+    plan_optimizer(ps, *o, plan);
+  });
+  if (rc) return rc;
+  for (int k = 0; k < n; ++k) get_scene(c, ids[k])->host_iter++;
+  if (stats) return read_stats(c, ids, n, stats);
+  return JSO_OK;
+}
+
+// ---------------------------------------------------------------------------
+// batches
+// ---------------------------------------------------------------------------
+}  // extern "C"
+
+struct jso_batch {
+  jso_ctx* c = nullptr;
+  std::vector<int> ids;
+  std::vector<uint32_t> max_iters;
+  Plan plan;
+  uint8_t* dev = nullptr;  // unit arrays of the plan
+  std::vector<size_t> off;
+  hipStream_t capture = nullptr;
+  hipGraph_t graph = nullptr;
+  hipGraphExec_t exec = nullptr;
+};
+
+namespace {
+
+void batch_free(jso_batch* b) {
+  if (b->exec) (void)hipGraphExecDestroy(b->exec);
+  if (b->graph) (void)hipGraphDestroy(b->graph);
+  if (b->capture) (void)hipStreamDestroy(b->capture);
+  if (b->dev) (void)hipFree(b->dev);
+  delete b;
+}
+
+int batch_launch_all(jso_batch* b, hipStream_t st) {
+  for (size_t k = 0; k < b->plan.size(); ++k) {
+    const LaunchRec& r = b->plan[k];
+    if (r.n == 0) continue;
+    HIP_TRY(b->c, launch_rec(r, b->dev + b->off[k], nullptr, st));
+  }
+  return JSO_OK;
+}
+
+}  // namespace
+
+extern "C" {
+
+int jso_batch_create(jso_ctx* c, const int* ids, int n, const jso_step_opts* o,
+                     const uint32_t* max_iters, int use_graph, jso_batch** out) {
+  if (!c) return JSO_E_INVALID;
+  if (!out || !ids || n <= 0 || !o) return fail(c, JSO_E_INVALID, "null/empty argument");
+  *out = nullptr;
+  for (int k = 0; k < n; ++k) {
+    if (!get_scene(c, ids[k])) return fail(c, JSO_E_INVALID, "bad scene id %d", ids[k]);
+    for (int q = 0; q < k; ++q)
+      if (ids[q] == ids[k]) return fail(c, JSO_E_INVALID, "scene %d listed twice", ids[k]);
+  }
+  int rc = check_step_opts(c, o);
+  if (rc) return rc;
+  DeviceGuard g(c->device);
+  std::unique_ptr<jso_batch, void (*)(jso_batch*)> b(new (std::nothrow) jso_batch, batch_free);
+  if (!b) return fail(c, JSO_E_OOM, "batch");
+  b->c = c;
+  b->ids.assign(ids, ids + n);
+  b->max_iters.assign(n, 0u);
+  if (max_iters) b->max_iters.assign(max_iters, max_iters + n);
+  const uint32_t flags = c->debug_flags | o->flags;
+  std::vector<ProbPlan> ps;
+  for (int k = 0; k < n; ++k)
+    ps.push_back(step_problem(get_scene(c, ids[k]), *o, flags, b->max_iters[k]));
+  plan_estimators(ps, b->plan);
+  plan_optimizer(ps, *o, b->plan);
+  const std::vector<uint8_t> all = pack_plan(b->plan, b->off);
+  HIP_TRY(c, hipMalloc(reinterpret_cast<void**>(&b->dev), all.size()));
+  HIP_TRY(c, hipMemcpy(b->dev, all.data(), all.size(), hipMemcpyHostToDevice));
+  if (use_graph) {
+    // capture on a private stream; replays run on the context's stream
+    HIP_TRY(c, hipStreamCreateWithFlags(&b->capture, hipStreamNonBlocking));
+    HIP_TRY(c, hipStreamBeginCapture(b->capture, hipStreamCaptureModeThreadLocal));
+    rc = batch_launch_all(b.get(), b->capture);
+    hipGraph_t graph = nullptr;
+    const hipError_t e = hipStreamEndCapture(b->capture, &graph);
+    b->graph = graph;
+    if (rc) return rc;
+    HIP_TRY(c, e);
+    HIP_TRY(c, hipGraphInstantiate(&b->exec, b->graph, nullptr, nullptr, 0));
+  }
+  *out = b.release();
+  return JSO_OK;
+}
+
+int jso_batch_step(jso_batch* b, int iterations) {
+  if (!b) return JSO_E_INVALID;
+  jso_ctx* c = b->c;
+  if (iterations < 0) return fail(c, JSO_E_INVALID, "iterations < 0");
+  DeviceGuard g(c->device);
+  for (int it = 0; it < iterations; ++it) {
+    if (b->exec) {
+      HIP_TRY(c, hipGraphLaunch(b->exec, c->stream));
     } else {
-      return fail(c, JSO_E_INVALID, "unknown optimizer %d", o->optimizer);
-    }
-    s->host_iter++;
-  }
-  if (stats) {
-    HIP_TRY(c, hipStreamSynchronize(c->stream));
-    for (int k = 0; k < n; ++k) {
-      SceneGPU* s = get_scene(c, ids[k]);
-      Ctl h;
-      HIP_TRY(c, hipMemcpy(&h, s->ctl, sizeof(Ctl), hipMemcpyDeviceToHost));
-      const uint32_t done = h.iteration - 1u;  // the iteration just completed
-      stats[k].loss = h.loss[done & 1u];
-      stats[k].step_norm2 = h.norm2[h.iteration & 1u];
-      stats[k].iteration = h.iteration;
+      const int rc = batch_launch_all(b, c->stream);
+      if (rc) return rc;
     }
   }
+  return JSO_OK;
+}
+
+int jso_batch_active(jso_batch* b, int* active) {
+  if (!b) return JSO_E_INVALID;
+  jso_ctx* c = b->c;
+  if (!active) return fail(c, JSO_E_INVALID, "null output");
+  DeviceGuard g(c->device);
+  HIP_TRY(c, hipStreamSynchronize(c->stream));
+  int a = 0;
+  for (size_t k = 0; k < b->ids.size(); ++k) {
+    SceneGPU* s = get_scene(c, b->ids[k]);
+    if (!s) return fail(c, JSO_E_STATE, "scene %d of the batch was freed", b->ids[k]);
+    uint32_t it = 0;
+    HIP_TRY(c, hipMemcpy(&it, &s->ctl->iteration, sizeof(it), hipMemcpyDeviceToHost));
+    if (b->max_iters[k] == 0 || it < b->max_iters[k]) ++a;
+  }
+  *active = a;
+  return JSO_OK;
+}
+
+int jso_batch_destroy(jso_batch* b) {
+  if (!b) return JSO_OK;
+  DeviceGuard g(b->c->device);
+  (void)hipStreamSynchronize(b->c->stream);
+  batch_free(b);
   return JSO_OK;
 }
 

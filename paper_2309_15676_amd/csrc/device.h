@@ -239,7 +239,12 @@ __device__ __forceinline__ bool material_at(const DevScene& S, const float* __re
     fp.t00 = fp.t01 = fp.t10 = 0;
     fp.fx = fp.fy = 0.0f;
 #pragma unroll
-    for (int b = 0; b < 5; ++b) val[b] = S.slot[b] >= 0 ? params[S.slot[b]] : S.defaults[b];
+    for (int b = 0; b < 5; ++b) {
+      // load both and select the value (a select of the two addresses would
+      // mix address spaces)
+      const float pv = params[S.slot[b] >= 0 ? S.slot[b] : 0];
+      val[b] = S.slot[b] >= 0 ? pv : S.defaults[b];
+    }
   } else {
     float u, v;
     if (kind == HIT_PLANE) {

@@ -9,6 +9,25 @@ namespace jso {
 
 struct DevScene;
 
+// Device pointers inside launch descriptors point to global memory.  The
+// descriptors themselves live in device memory, and a pointer loaded from
+// memory is generic unless its type says otherwise; declaring the fields in
+// the global address space keeps the kernels' loads global (and scalar for
+// uniform data such as the scene).
+#define JSO_GMEM __attribute__((address_space(1)))
+template <class T>
+__host__ __device__ inline JSO_GMEM T* gmem(T* p) {
+  return (JSO_GMEM T*)p;
+}
+// Read-only data that no kernel writes (the scene) is declared in the
+// constant address space: uniform reads of it stay scalar even next to the
+// kernels' stores and atomics.
+#define JSO_CMEM __attribute__((address_space(4)))
+template <class T>
+__host__ __device__ inline JSO_CMEM const T* cmem(const T* p) {
+  return (JSO_CMEM const T*)p;
+}
+
 // Per-problem control block, resident on the device so a captured iteration
 // can be replayed without host involvement.
 struct Ctl {
@@ -29,10 +48,20 @@ struct Crop {
 struct KeyArgs {
   uint64_t seed;
   uint32_t iteration;        // used when iter_ptr is null
-  const uint32_t* iter_ptr;  // device iteration counter (graph replays)
+  JSO_GMEM const uint32_t* iter_ptr;  // device iteration counter (graph replays)
 };
 
 constexpr int kMetaMaxBlocks = 1024;
+
+// Every launch of the path and optimiser kernels covers one or more units:
+// the work of one problem, or of one group of its grid slices.  A unit owns
+// the grid blocks [block0, next unit's block0); units are sorted by block0
+// and live in device memory, so one launch serves any number of problems of
+// uneven size.
+struct UnitHead {
+  uint32_t block0;    // first grid block of the unit
+  uint32_t max_iter;  // nonzero: the unit is idle once its problem's iteration reaches it
+};
 
 // Path radiance is handed from the forward kernel to its consumers through
 // per-path slots: slot k of pixel p holds 3 doubles at ((k * npix) + p) * 3.
@@ -40,21 +69,24 @@ constexpr int kMaxSlots = 8;  // path slots per pixel per launch
 
 // One grid slice of k_forward: the paths of one sample of one parameter set.
 struct FwdSlice {
-  const float* params;
+  JSO_GMEM const float* params;
   uint32_t tag;     // random stream
   uint32_t sample;  // sample index within the stream
   int slot;         // output slot
 };
 
 struct FwdArgs {
+  UnitHead h;
+  JSO_CMEM const DevScene* scene;  // read-only
   FwdSlice sl[kMaxSlots];
+  int n_slices;
   KeyArgs key;
   Crop crop;
-  const uint8_t* mask;
-  double* slots;
+  JSO_GMEM const uint8_t* mask;
+  JSO_GMEM double* slots;
   uint32_t npix;
   uint32_t flags;
-  unsigned long long* work;  // nullable: [2] += paths traced, [3] += their surface vertices
+  uint32_t tiles_x, tiles;  // kTile x kTile tiles of the crop: per row, per slice
 };
 
 // One primal image of k_finalize: n slots of this launch summed per pixel,
@@ -62,35 +94,38 @@ struct FwdArgs {
 // the adjoint image and the loss.
 struct FinJob {
   int slot0, n;
-  double* accum;    // per-pixel running sums (3 doubles), used unless first && last
+  JSO_GMEM double* accum;  // per-pixel running sums (3 doubles), used unless first && last
   int first, last;
   double inv_spp;   // 1 / total samples of the image
-  float* img;       // nullable
-  float* delta;     // nullable: 2 (I - T) / (3 W H)
-  double* loss2;    // nullable: 2 loss slots indexed by iteration parity
+  JSO_GMEM float* img;     // nullable
+  JSO_GMEM float* delta;   // nullable: 2 (I - T) / (3 W H)
+  JSO_GMEM double* loss2;  // nullable: 2 loss slots indexed by iteration parity
 };
 
 struct FinArgs {
+  UnitHead h;
   FinJob jobs[3];
   int n_jobs;
-  const double* slots;
+  JSO_GMEM const double* slots;
   uint32_t npix;
+  int width;
   KeyArgs key;
   Crop crop;
-  const uint8_t* mask;
-  const float* target;
+  JSO_GMEM const uint8_t* mask;
+  JSO_GMEM const float* target;
   float delta_scale;   // 2 / (3 W H)
   double loss_scale;   // 1 / (3 W H)
+  uint32_t nblocks;    // blocks per job
 };
 
 // One grid slice of k_adjoint: the replay of one sample of one job, a single
 // path (params_b null) or a finite-difference pair (+A - B).
 struct RepSlice {
-  const float* params;
-  const float* params_b;
-  const float* delta;    // adjoint image of path A
-  const float* delta_b;
-  float* grad;
+  JSO_GMEM const float* params;
+  JSO_GMEM const float* params_b;
+  JSO_GMEM const float* delta;  // adjoint image of path A
+  JSO_GMEM const float* delta_b;
+  JSO_GMEM float* grad;
   float sign;            // sign of a single path's contribution
   float adj_scale;       // 1 / spp
   uint32_t tag;
@@ -99,24 +134,29 @@ struct RepSlice {
 };
 
 struct RepArgs {
+  UnitHead h;
+  JSO_CMEM const DevScene* scene;  // read-only
   RepSlice sl[kMaxSlots];
+  int n_slices;
   KeyArgs key;
   Crop crop;
-  const uint8_t* mask;
-  const double* slots;
+  JSO_GMEM const uint8_t* mask;
+  JSO_GMEM const double* slots;
   uint32_t npix;
   uint32_t flags;
-  unsigned long long* work;  // nullable: [0] += paths replayed, [1] += their surface vertices
+  uint32_t tiles_x, tiles;
 };
 
 struct MetaArgs {
-  float* params;
-  float* params_prev;
-  float* F;
-  float* dF;
-  double *mean, *var, *alpha_prev, *m2F, *m2D;
-  Ctl* ctl;
-  double* partials;  // kMetaMaxBlocks per-block sums of the squared step
+  UnitHead h;
+  uint32_t nblocks;
+  JSO_GMEM float* params;
+  JSO_GMEM float* params_prev;
+  JSO_GMEM float* F;
+  JSO_GMEM float* dF;
+  JSO_GMEM double *mean, *var, *alpha_prev, *m2F, *m2D;
+  JSO_GMEM Ctl* ctl;
+  JSO_GMEM double* partials;  // kMetaMaxBlocks per-block sums of the squared step
   size_t n;
   int n_ch;
   float lo[5], hi[5];
@@ -126,11 +166,13 @@ struct MetaArgs {
 };
 
 struct AdamArgs {
-  float* params;
-  float* params_prev;
-  float* g;
-  float *m, *v;
-  Ctl* ctl;
+  UnitHead h;
+  uint32_t nblocks;
+  JSO_GMEM float* params;
+  JSO_GMEM float* params_prev;
+  JSO_GMEM float* g;
+  JSO_GMEM float *m, *v;
+  JSO_GMEM Ctl* ctl;
   size_t n;
   int n_ch;
   float lo[5], hi[5];
@@ -140,16 +182,26 @@ struct AdamArgs {
 
 hipError_t launch_philox(const uint32_t* ctr, size_t n, uint64_t key, uint32_t* out,
                          hipStream_t st);
-// S: the scene in device memory (uniform reads go through the scalar cache);
-// n: grid slices (A.sl entries used)
-hipError_t launch_forward(const DevScene* S, const FwdArgs& A, int n, hipStream_t st);
-// width: image width (pixel index = y * width + x)
-hipError_t launch_finalize(const FinArgs& A, int width, hipStream_t st);
-// n_ch: channels per texel of the parameter texture (0..5; sizes the LDS table)
-hipError_t launch_adjoint(const DevScene* S, const RepArgs& A, int n, int n_ch, hipStream_t st);
-hipError_t launch_meta(const MetaArgs& A, hipStream_t st);
-hipError_t launch_adam(const AdamArgs& A, hipStream_t st);
+// Unit arrays U[n] in device memory; `blocks` = the total grid size.
+// work (nullable): forward [2] += paths traced, [3] += surface vertices;
+// adjoint [0] += paths replayed, [1] += surface vertices.
+hipError_t launch_forward(const FwdArgs* U, int n, uint32_t blocks, unsigned long long* work,
+                          hipStream_t st);
+hipError_t launch_finalize(const FinArgs* U, int n, uint32_t blocks, hipStream_t st);
+// lds: dynamic LDS bytes (adjoint_lds_bytes of the largest channel count)
+hipError_t launch_adjoint(const RepArgs* U, int n, uint32_t blocks, size_t lds,
+                          unsigned long long* work, hipStream_t st);
+hipError_t launch_meta(const MetaArgs* U, int n, uint32_t blocks, hipStream_t st);
+hipError_t launch_adam(const AdamArgs* U, int n, uint32_t blocks, hipStream_t st);
 hipError_t launch_fill_f64(double* p, size_t n, double v, hipStream_t st);
 hipError_t launch_fill_f32(float* p, size_t n, float v, hipStream_t st);
+
+// Grid geometry the host needs to build units.
+constexpr int kTile = 16;        // path kernels: kTile x kTile pixel tiles
+constexpr int kFinBlock = 256;   // k_finalize threads per block
+constexpr int kFinMaxBlocks = 256;
+constexpr int kMetaBlock = 256;  // k_meta / k_adam threads per block
+constexpr int kMetaK = 4;        // parameters per k_meta thread
+size_t adjoint_lds_bytes(int n_ch);
 
 }  // namespace jso

@@ -19,6 +19,17 @@
 
 namespace jso {
 
+// A descriptor's global-memory pointer as an ordinary pointer; its uses stay
+// in the global address space.
+template <class T>
+__device__ __forceinline__ T* G(JSO_GMEM T* p) {
+  return (T*)p;
+}
+template <class T>
+__device__ __forceinline__ const T* G(JSO_CMEM const T* p) {
+  return (const T*)p;
+}
+
 // ---------------------------------------------------------------------------
 __global__ void k_philox(const uint4* __restrict__ ctr, uint32_t n, uint32_t k0, uint32_t k1,
                          uint4* __restrict__ out) {
@@ -59,12 +70,37 @@ __device__ __forceinline__ int wave_sum(int v) {
 }
 
 // Blocks are kTile x kTile pixel tiles (256 lanes = four wave64 rows of 16 x 4).
-constexpr int kTile = 16;
 constexpr int kBlock = kTile * kTile;
 
-__device__ __forceinline__ bool tile_pixel(const Crop& c, int& px, int& py) {
-  px = c.x0 + (int)blockIdx.x * kTile + (int)(threadIdx.x % kTile);
-  py = c.y0 + (int)blockIdx.y * kTile + (int)(threadIdx.x / kTile);
+// The unit owning this block: the last one whose block0 <= blockIdx.x.
+template <class U>
+__device__ __forceinline__ const U& unit_of(const U* __restrict__ u, int n) {
+  const uint32_t b = blockIdx.x;
+  int lo = 0, hi = n - 1;
+  while (lo < hi) {
+    const int mid = (lo + hi + 1) >> 1;
+    if (u[mid].h.block0 <= b) lo = mid;
+    else hi = mid - 1;
+  }
+  return u[lo];
+}
+
+// A path unit's block: its slice and its tile's pixel origin.
+struct TileBlock {
+  int slice, x0, y0;
+};
+
+template <class U>
+__device__ __forceinline__ TileBlock tile_block(const U& u) {
+  const uint32_t local = blockIdx.x - u.h.block0;
+  const uint32_t t = local % u.tiles;
+  return TileBlock{(int)(local / u.tiles), u.crop.x0 + (int)(t % u.tiles_x) * kTile,
+                   u.crop.y0 + (int)(t / u.tiles_x) * kTile};
+}
+
+__device__ __forceinline__ bool tile_pixel(const Crop& c, const TileBlock& tb, int& px, int& py) {
+  px = tb.x0 + (int)(threadIdx.x % kTile);
+  py = tb.y0 + (int)(threadIdx.x / kTile);
   return px < c.x1 && py < c.y1;
 }
 
@@ -96,10 +132,9 @@ struct BlockPaths {
   __device__ __forceinline__ Rng rng(int src) const { return make_rng(key, pixel(src), sample); }
 };
 
-__device__ __forceinline__ BlockPaths block_paths(const Crop& c, const DevScene& S, uint64_t key,
-                                                  uint32_t sample, uint32_t flags) {
-  return BlockPaths{key, sample, c.x0 + (int)blockIdx.x * kTile, c.y0 + (int)blockIdx.y * kTile,
-                    S.width, flags};
+__device__ __forceinline__ BlockPaths block_paths(const TileBlock& tb, const DevScene& S,
+                                                  uint64_t key, uint32_t sample, uint32_t flags) {
+  return BlockPaths{key, sample, tb.x0, tb.y0, S.width, flags};
 }
 
 // Rank of this lane among the lanes of the block with `flag` set, and their
@@ -182,19 +217,21 @@ constexpr int kFwdXchgWords = (int)(sizeof(FwdItem) / 4);
 // forward pass: one block = one tile of one slice; each path's radiance (its
 // FP64 ledger total) goes to the slice's slot.
 // ---------------------------------------------------------------------------
-__global__ void __launch_bounds__(kBlock) __attribute__((amdgpu_waves_per_eu(4)))
-k_forward(const DevScene* __restrict__ Sp, FwdArgs A) {
+// The kernel bodies take the scene through a restrict-qualified parameter:
+// nothing the kernels write aliases it, so its fields stay in registers.
+__device__ __forceinline__ void forward_tile(const FwdArgs& A, const DevScene* __restrict__ Sp,
+                                             uint32_t iter, uint32_t* s_xchg, int* s_cnt,
+                                             unsigned long long* work) {
   const DevScene& S = *Sp;
-  __shared__ uint32_t s_xchg[kFwdXchgWords * kXchg];
-  __shared__ int s_cnt[kBlock / 64];
-  const FwdSlice& sl = A.sl[blockIdx.z];
+  const TileBlock tb = tile_block(A);
+  const FwdSlice& sl = A.sl[tb.slice];
   int px, py;
-  const bool inside = tile_pixel(A.crop, px, py);
+  const bool inside = tile_pixel(A.crop, tb, px, py);
   const uint32_t pix = (uint32_t)(py * S.width + px);
-  const bool active = inside && !(A.mask && A.mask[pix]);
-  const uint64_t key = stream_key(A.key.seed, iteration_of(A.key), sl.tag);
-  const BlockPaths B = block_paths(A.crop, S, key, sl.sample, A.flags);
-  double* out = A.slots + (size_t)sl.slot * A.npix * 3;
+  const bool active = inside && !(G(A.mask) && G(A.mask)[pix]);
+  const uint64_t key = stream_key(A.key.seed, iter, sl.tag);
+  const BlockPaths B = block_paths(tb, S, key, sl.sample, A.flags);
+  double* out = G(A.slots) + (size_t)sl.slot * A.npix * 3;
   const float zero[3] = {0.0f, 0.0f, 0.0f};
   VertexGrad vg;
   int n_vert = 0;
@@ -205,7 +242,7 @@ k_forward(const DevScene* __restrict__ Sp, FwdArgs A) {
     path_begin(S, rng, px, py, A.flags, P);
     if (P.alive) {
       ++n_vert;
-      path_vertex<false>(S, sl.params, rng, A.flags, P, zero, vg);
+      path_vertex<false>(S, G(sl.params), rng, A.flags, P, zero, vg);
     }
     if (!P.alive) store_radiance(out, pix, P.led);
   }
@@ -228,11 +265,21 @@ k_forward(const DevScene* __restrict__ Sp, FwdArgs A) {
     const Rng rng = B.rng(W.src);
     while (W.P.alive) {
       ++n_vert;
-      path_vertex<false>(S, sl.params, rng, A.flags, W.P, zero, vg);
+      path_vertex<false>(S, G(sl.params), rng, A.flags, W.P, zero, vg);
     }
     store_radiance(out, B.pixel(W.src), W.P.led);
   }
-  count_work(A.work ? A.work + 2 : nullptr, active ? 1 : 0, n_vert);
+  count_work(work ? work + 2 : nullptr, active ? 1 : 0, n_vert);
+}
+
+__global__ void __launch_bounds__(kBlock) __attribute__((amdgpu_waves_per_eu(4)))
+k_forward(const FwdArgs* __restrict__ Units, int n_units, unsigned long long* work) {
+  __shared__ uint32_t s_xchg[kFwdXchgWords * kXchg];
+  __shared__ int s_cnt[kBlock / 64];
+  const FwdArgs& A = unit_of(Units, n_units);
+  const uint32_t iter = iteration_of(A.key);
+  if (A.h.max_iter && iter >= A.h.max_iter) return;  // finished problem
+  forward_tile(A, G(A.scene), iter, s_xchg, s_cnt, work);
 }
 
 // ---------------------------------------------------------------------------
@@ -240,49 +287,51 @@ k_forward(const DevScene* __restrict__ Sp, FwdArgs A) {
 // (blocks, jobs); blocks stride over the crop's pixels and reduce the loss to
 // one atomic each.
 // ---------------------------------------------------------------------------
-constexpr int kFinBlock = 256;
-constexpr int kFinMaxBlocks = 256;
-
-__global__ void __launch_bounds__(kFinBlock) k_finalize(FinArgs A, int width) {
+__global__ void __launch_bounds__(kFinBlock) k_finalize(const FinArgs* __restrict__ Units,
+                                                         int n_units) {
   __shared__ double s_red[kFinBlock / 64];
-  const FinJob& job = A.jobs[blockIdx.y];
+  const FinArgs& A = unit_of(Units, n_units);
+  const uint32_t iter = iteration_of(A.key);
+  if (A.h.max_iter && iter >= A.h.max_iter) return;  // finished problem
+  const uint32_t local = blockIdx.x - A.h.block0;
+  const FinJob& job = A.jobs[local / A.nblocks];
+  const int bx = (int)(local % A.nblocks);
   const int cw = A.crop.x1 - A.crop.x0, chh = A.crop.y1 - A.crop.y0;
   double se = 0.0;
-  for (int i = (int)(blockIdx.x * kFinBlock + threadIdx.x); i < cw * chh;
-       i += (int)gridDim.x * kFinBlock) {
-    const uint32_t pix = (uint32_t)((A.crop.y0 + i / cw) * width + (A.crop.x0 + i % cw));
-    if (!(A.mask && A.mask[pix])) {
+  for (int i = bx * kFinBlock + (int)threadIdx.x; i < cw * chh; i += (int)A.nblocks * kFinBlock) {
+    const uint32_t pix = (uint32_t)((A.crop.y0 + i / cw) * A.width + (A.crop.x0 + i % cw));
+    if (!(G(A.mask) && G(A.mask)[pix])) {
       double sum[3] = {0.0, 0.0, 0.0};
       for (int s = 0; s < job.n; ++s) {
-        const double* c = A.slots + ((size_t)(job.slot0 + s) * A.npix + pix) * 3;
+        const double* c = G(A.slots) + ((size_t)(job.slot0 + s) * A.npix + pix) * 3;
 #pragma unroll
         for (int k = 0; k < 3; ++k) sum[k] += c[k];
       }
       if (!job.first) {
 #pragma unroll
-        for (int k = 0; k < 3; ++k) sum[k] = job.accum[3 * (size_t)pix + k] + sum[k];
+        for (int k = 0; k < 3; ++k) sum[k] = G(job.accum)[3 * (size_t)pix + k] + sum[k];
       }
       if (!job.last) {
 #pragma unroll
-        for (int k = 0; k < 3; ++k) job.accum[3 * (size_t)pix + k] = sum[k];
+        for (int k = 0; k < 3; ++k) G(job.accum)[3 * (size_t)pix + k] = sum[k];
       } else {
 #pragma unroll
         for (int k = 0; k < 3; ++k) {
           const float I = (float)(sum[k] * job.inv_spp);
-          if (job.img) job.img[3 * (size_t)pix + k] = I;
-          if (job.delta) {
-            const float e = I - A.target[3 * (size_t)pix + k];
-            job.delta[3 * (size_t)pix + k] = A.delta_scale * e;
+          if (G(job.img)) G(job.img)[3 * (size_t)pix + k] = I;
+          if (G(job.delta)) {
+            const float e = I - G(A.target)[3 * (size_t)pix + k];
+            G(job.delta)[3 * (size_t)pix + k] = A.delta_scale * e;
             se += (double)e * (double)e;
           }
         }
       }
-    } else if (job.last && job.delta) {
+    } else if (job.last && G(job.delta)) {
 #pragma unroll
-      for (int k = 0; k < 3; ++k) job.delta[3 * (size_t)pix + k] = 0.0f;
+      for (int k = 0; k < 3; ++k) G(job.delta)[3 * (size_t)pix + k] = 0.0f;
     }
   }
-  if (job.last && job.loss2) {
+  if (job.last && G(job.loss2)) {
     se = wave_sum(se);
     if ((threadIdx.x & 63) == 0) s_red[threadIdx.x >> 6] = se;
     __syncthreads();
@@ -290,7 +339,7 @@ __global__ void __launch_bounds__(kFinBlock) k_finalize(FinArgs A, int width) {
       double tot = 0.0;
 #pragma unroll
       for (int w = 0; w < kFinBlock / 64; ++w) tot += s_red[w];
-      if (tot != 0.0) unsafeAtomicAdd(&job.loss2[iteration_of(A.key) & 1u], tot * A.loss_scale);
+      if (tot != 0.0) unsafeAtomicAdd(&G(job.loss2)[iter & 1u], tot * A.loss_scale);
     }
   }
 }
@@ -500,26 +549,26 @@ __device__ __forceinline__ void replay_begin(const DevScene& S, const Rng& rng, 
 // (their gradients go to the block table, flushed right after), later ones on
 // the compacted lanes in a wave-uniform loop, so the later-vertex scatter can
 // use the whole wave.  The exchange buffer reuses the table's LDS.
-__global__ void __launch_bounds__(kBlock) __attribute__((amdgpu_waves_per_eu(3)))
-k_adjoint(const DevScene* __restrict__ Sp, RepArgs A) {
+__device__ __forceinline__ void adjoint_tile(const RepArgs& A, const DevScene* __restrict__ Sp,
+                                             uint32_t iter, uint32_t* s_dyn, int* s_cnt,
+                                             unsigned long long* work) {
   const DevScene& S = *Sp;
-  extern __shared__ uint32_t s_dyn[];
-  __shared__ int s_cnt[kBlock / 64];
   uint32_t* s_keys = s_dyn;
   float* s_vals = reinterpret_cast<float*>(s_dyn + kTableSize);
-  const RepSlice& sl = A.sl[blockIdx.z];
-  const bool pair = sl.params_b != nullptr;  // uniform over the block
+  const TileBlock tb = tile_block(A);
+  const RepSlice& sl = A.sl[tb.slice];
+  const bool pair = G(sl.params_b) != nullptr;  // uniform over the block
   int px, py;
-  const bool inside = tile_pixel(A.crop, px, py);
+  const bool inside = tile_pixel(A.crop, tb, px, py);
   const uint32_t pix = (uint32_t)(py * S.width + px);
-  const bool active = inside && !(A.mask && A.mask[pix]);
+  const bool active = inside && !(G(A.mask) && G(A.mask)[pix]);
   for (int i = threadIdx.x; i < kTableSize; i += kBlock) s_keys[i] = kEmpty;
   for (int i = threadIdx.x; i < kTableSize * S.n_ch; i += kBlock) s_vals[i] = 0.0f;
   __syncthreads();
   Sink sink;
-  sink.init(GradTable{s_keys, s_vals, sl.grad});
-  const uint64_t key = stream_key(A.key.seed, iteration_of(A.key), sl.tag);
-  const BlockPaths B = block_paths(A.crop, S, key, sl.sample, A.flags);
+  sink.init(GradTable{s_keys, s_vals, G(sl.grad)});
+  const uint64_t key = stream_key(A.key.seed, iter, sl.tag);
+  const BlockPaths B = block_paths(tb, S, key, sl.sample, A.flags);
   const Rng rng = B.rng((int)threadIdx.x);
   const int tid = (int)threadIdx.x;
   float adj_a[3] = {0.0f, 0.0f, 0.0f}, adj_b[3] = {0.0f, 0.0f, 0.0f};
@@ -532,21 +581,21 @@ k_adjoint(const DevScene* __restrict__ Sp, RepArgs A) {
     if (active) {
 #pragma unroll
       for (int k = 0; k < 3; ++k) {
-        adj_a[k] = sl.delta[3 * (size_t)pix + k] * sl.adj_scale;
-        if (pair) adj_b[k] = sl.delta_b[3 * (size_t)pix + k] * sl.adj_scale;
+        adj_a[k] = G(sl.delta)[3 * (size_t)pix + k] * sl.adj_scale;
+        if (pair) adj_b[k] = G(sl.delta_b)[3 * (size_t)pix + k] * sl.adj_scale;
       }
       replay_begin(S, rng, px, py, A.flags,
-                   A.slots + ((size_t)sl.slot_a * A.npix + pix) * 3, Pa);
+                   G(A.slots) + ((size_t)sl.slot_a * A.npix + pix) * 3, Pa);
       if (Pa.alive) {
         ++n_vert;
-        path_vertex<true>(S, sl.params, rng, A.flags, Pa, adj_a, va);
+        path_vertex<true>(S, G(sl.params), rng, A.flags, Pa, adj_a, va);
       }
       if (pair) {
         replay_begin(S, rng, px, py, A.flags,
-                     A.slots + ((size_t)sl.slot_b * A.npix + pix) * 3, Pb);
+                     G(A.slots) + ((size_t)sl.slot_b * A.npix + pix) * 3, Pb);
         if (Pb.alive) {
           ++n_vert;
-          path_vertex<true>(S, sl.params_b, rng, A.flags, Pb, adj_b, vb);
+          path_vertex<true>(S, G(sl.params_b), rng, A.flags, Pb, adj_b, vb);
         }
         if (va.valid && vb.valid && same_footprint(va.fp, vb.fp)) {
 #pragma unroll
@@ -591,10 +640,10 @@ k_adjoint(const DevScene* __restrict__ Sp, RepArgs A) {
         v.valid = false;
         if (W.P.alive) {
           ++n_vert;
-          path_vertex<true>(S, sl.params, wr, A.flags, W.P, W.adj, v);
+          path_vertex<true>(S, G(sl.params), wr, A.flags, W.P, W.adj, v);
         }
         const bool later = sink.add(S, v, sl.sign);
-        scatter_wave(S, sl.grad, v, sl.sign, later);
+        scatter_wave(S, G(sl.grad), v, sl.sign, later);
       }
     }
   } else {
@@ -631,11 +680,11 @@ k_adjoint(const DevScene* __restrict__ Sp, RepArgs A) {
         va.valid = vb.valid = false;
         if (W.Pa.alive) {
           ++n_vert;
-          path_vertex<true>(S, sl.params, wr, A.flags, W.Pa, W.adj_a, va);
+          path_vertex<true>(S, G(sl.params), wr, A.flags, W.Pa, W.adj_a, va);
         }
         if (W.Pb.alive) {
           ++n_vert;
-          path_vertex<true>(S, sl.params_b, wr, A.flags, W.Pb, W.adj_b, vb);
+          path_vertex<true>(S, G(sl.params_b), wr, A.flags, W.Pb, W.adj_b, vb);
         }
         if (va.valid && vb.valid && same_footprint(va.fp, vb.fp)) {
 #pragma unroll
@@ -644,13 +693,23 @@ k_adjoint(const DevScene* __restrict__ Sp, RepArgs A) {
         }
         const bool later_a = sink.add(S, va, 1.0f);
         const bool later_b = sink.add(S, vb, -1.0f);
-        scatter_wave(S, sl.grad, va, 1.0f, later_a);
-        scatter_wave(S, sl.grad, vb, -1.0f, later_b);
+        scatter_wave(S, G(sl.grad), va, 1.0f, later_a);
+        scatter_wave(S, G(sl.grad), vb, -1.0f, later_b);
       }
     }
   }
   sink.flush_acc(S);
-  count_work(A.work, paths, n_vert);
+  count_work(work, paths, n_vert);
+}
+
+__global__ void __launch_bounds__(kBlock) __attribute__((amdgpu_waves_per_eu(3)))
+k_adjoint(const RepArgs* __restrict__ Units, int n_units, unsigned long long* work) {
+  extern __shared__ uint32_t s_dyn[];
+  __shared__ int s_cnt[kBlock / 64];
+  const RepArgs& A = unit_of(Units, n_units);
+  const uint32_t iter = iteration_of(A.key);
+  if (A.h.max_iter && iter >= A.h.max_iter) return;  // finished problem
+  adjoint_tile(A, G(A.scene), iter, s_dyn, s_cnt, work);
 }
 
 // ---------------------------------------------------------------------------
@@ -658,18 +717,19 @@ k_adjoint(const DevScene* __restrict__ Sp, RepArgs A) {
 // ---------------------------------------------------------------------------
 // Each thread takes kMetaK elements, one block-width apart, with every load
 // issued before the arithmetic so the HBM latency is paid once.  The squared
-// step is reduced per block into A.partials; the last block to finish sums
+// step is reduced per block into the partials buffer; the last block to finish sums
 // the partials in block order (a deterministic ||pi_{i+1} - pi_i||^2) and
 // advances the iteration state.
-constexpr int kMetaK = 4;
-constexpr int kMetaBlock = 256;
-
-__global__ void __launch_bounds__(kMetaBlock) k_meta(MetaArgs A) {
+__global__ void __launch_bounds__(kMetaBlock) k_meta(const MetaArgs* __restrict__ Units,
+                                                     int n_units) {
   __shared__ double s_coef[4];
   __shared__ double s_red[kMetaBlock / 64];
   __shared__ bool s_last;
-  Ctl* ctl = A.ctl;
+  const MetaArgs& A = unit_of(Units, n_units);
+  Ctl* ctl = G(A.ctl);
   const uint32_t it = ctl->iteration;
+  if (A.h.max_iter && it >= A.h.max_iter) return;  // finished problem
+  const uint32_t lb = blockIdx.x - A.h.block0, nb = A.nblocks;
   if (threadIdx.x == 0) {
     const double n2 = ctl->norm2[it & 1u];
     const uint32_t cF = ctl->count_F + 1u;
@@ -687,21 +747,21 @@ __global__ void __launch_bounds__(kMetaBlock) k_meta(MetaArgs A) {
   const uint32_t n = (uint32_t)A.n, nc = (uint32_t)A.n_ch;
   double local = 0.0;
   const uint32_t span = kMetaBlock * kMetaK;
-  for (uint32_t base = blockIdx.x * span + threadIdx.x; base < n; base += gridDim.x * span) {
+  for (uint32_t base = lb * span + threadIdx.x; base < n; base += nb * span) {
     float F[kMetaK], dF[kMetaK], p[kMetaK];
     double m2F[kMetaK], m2D[kMetaK], mean[kMetaK], var[kMetaK], ap[kMetaK];
 #pragma unroll
     for (int e = 0; e < kMetaK; ++e) {
       const uint32_t i = base + (uint32_t)e * kMetaBlock;
       if (i < n) {
-        F[e] = A.F[i];
-        dF[e] = takeD ? A.dF[i] : 0.0f;
-        p[e] = A.params[i];
-        m2F[e] = A.m2F[i];
-        m2D[e] = A.m2D[i];
-        mean[e] = A.mean[i];
-        var[e] = A.var[i];
-        ap[e] = A.alpha_prev[i];
+        F[e] = G(A.F)[i];
+        dF[e] = takeD ? G(A.dF)[i] : 0.0f;
+        p[e] = G(A.params)[i];
+        m2F[e] = G(A.m2F)[i];
+        m2D[e] = G(A.m2D)[i];
+        mean[e] = G(A.mean)[i];
+        var[e] = G(A.var)[i];
+        ap[e] = G(A.alpha_prev)[i];
       }
     }
 #pragma unroll
@@ -732,16 +792,16 @@ __global__ void __launch_bounds__(kMetaBlock) k_meta(MetaArgs A) {
       const float pn = fminf(fmaxf((float)((double)p[e] + step), A.lo[ch]), A.hi[ch]);
       const double dp = (double)pn - (double)p[e];
       local += dp * dp;
-      A.m2F[i] = mF;
-      A.m2D[i] = mD;
-      A.mean[i] = mu;
-      A.var[i] = v;
-      A.alpha_prev[i] = a;
-      A.params_prev[i] = p[e];
-      A.params[i] = pn;
+      G(A.m2F)[i] = mF;
+      G(A.m2D)[i] = mD;
+      G(A.mean)[i] = mu;
+      G(A.var)[i] = v;
+      G(A.alpha_prev)[i] = a;
+      G(A.params_prev)[i] = p[e];
+      G(A.params)[i] = pn;
       if (A.zero_grads) {
-        A.F[i] = 0.0f;
-        A.dF[i] = 0.0f;
+        G(A.F)[i] = 0.0f;
+        G(A.dF)[i] = 0.0f;
       }
     }
   }
@@ -753,9 +813,9 @@ __global__ void __launch_bounds__(kMetaBlock) k_meta(MetaArgs A) {
   if (threadIdx.x == 0) {
     double tot = 0.0;
     for (int w = 0; w < kMetaBlock / 64; ++w) tot += s_red[w];
-    A.partials[blockIdx.x] = tot;
+    G(A.partials)[lb] = tot;
     __threadfence();
-    s_last = atomicAdd(&ctl->blocks_done, 1u) == gridDim.x - 1u;
+    s_last = atomicAdd(&ctl->blocks_done, 1u) == nb - 1u;
   }
   __syncthreads();
   if (!s_last) return;
@@ -764,7 +824,7 @@ __global__ void __launch_bounds__(kMetaBlock) k_meta(MetaArgs A) {
   __threadfence();
   double sum = 0.0;
   if (threadIdx.x < 64) {
-    for (uint32_t b = threadIdx.x; b < gridDim.x; b += 64) sum += A.partials[b];
+    for (uint32_t b = threadIdx.x; b < nb; b += 64) sum += G(A.partials)[b];
     sum = wave_sum(sum);
   }
   if (threadIdx.x == 0) {
@@ -780,30 +840,34 @@ __global__ void __launch_bounds__(kMetaBlock) k_meta(MetaArgs A) {
 }
 
 // ---------------------------------------------------------------------------
-__global__ void __launch_bounds__(256) k_adam(AdamArgs A) {
-  Ctl* ctl = A.ctl;
+__global__ void __launch_bounds__(kMetaBlock) k_adam(const AdamArgs* __restrict__ Units,
+                                                     int n_units) {
+  const AdamArgs& A = unit_of(Units, n_units);
+  Ctl* ctl = G(A.ctl);
+  if (A.h.max_iter && ctl->iteration >= A.h.max_iter) return;  // finished problem
+  const uint32_t lb = blockIdx.x - A.h.block0, nb = A.nblocks;
   const uint32_t t = ctl->adam_t + 1u;
   const float bc1 = (float)(1.0 - pow((double)A.beta1, (double)t));
   const float bc2 = (float)(1.0 - pow((double)A.beta2, (double)t));
-  const size_t stride = (size_t)gridDim.x * blockDim.x;
-  for (size_t i = (size_t)blockIdx.x * blockDim.x + threadIdx.x; i < A.n; i += stride) {
-    const float g = A.g[i];
-    const float m = A.beta1 * A.m[i] + (1.0f - A.beta1) * g;
-    const float v = A.beta2 * A.v[i] + (1.0f - A.beta2) * g * g;
-    A.m[i] = m;
-    A.v[i] = v;
+  const size_t stride = (size_t)nb * kMetaBlock;
+  for (size_t i = (size_t)lb * kMetaBlock + threadIdx.x; i < A.n; i += stride) {
+    const float g = G(A.g)[i];
+    const float m = A.beta1 * G(A.m)[i] + (1.0f - A.beta1) * g;
+    const float v = A.beta2 * G(A.v)[i] + (1.0f - A.beta2) * g * g;
+    G(A.m)[i] = m;
+    G(A.v)[i] = v;
     const float mh = m / bc1, vh = v / bc2;
-    const float p = A.params[i];
+    const float p = G(A.params)[i];
     const int ch = (int)(i % (size_t)A.n_ch);
     const float pn = fminf(fmaxf(p - A.eta * mh / (sqrtf(vh) + A.eps), A.lo[ch]), A.hi[ch]);
-    A.params_prev[i] = p;
-    A.params[i] = pn;
-    if (A.zero_grads) A.g[i] = 0.0f;
+    G(A.params_prev)[i] = p;
+    G(A.params)[i] = pn;
+    if (A.zero_grads) G(A.g)[i] = 0.0f;
   }
   if (threadIdx.x == 0) {
     __threadfence();
     const uint32_t done = atomicAdd(&ctl->blocks_done, 1u);
-    if (done == gridDim.x - 1u) {
+    if (done == nb - 1u) {
       __threadfence();
       ctl->adam_t = t;
       ctl->iteration = ctl->iteration + 1u;
@@ -838,52 +902,42 @@ hipError_t launch_philox(const uint32_t* ctr, size_t n, uint64_t key, uint32_t* 
   return hipGetLastError();
 }
 
-hipError_t launch_forward(const DevScene* S, const FwdArgs& A, int n, hipStream_t st) {
-  const int w = A.crop.x1 - A.crop.x0, h = A.crop.y1 - A.crop.y0;
-  if (w <= 0 || h <= 0 || n <= 0) return hipSuccess;
-  if (n > kMaxSlots) return hipErrorInvalidValue;
-  hipLaunchKernelGGL(k_forward, dim3(cdiv(w, kTile), cdiv(h, kTile), n), dim3(kBlock), 0, st, S, A);
+hipError_t launch_forward(const FwdArgs* U, int n, uint32_t blocks, unsigned long long* work,
+                          hipStream_t st) {
+  if (n <= 0 || blocks == 0) return hipSuccess;
+  hipLaunchKernelGGL(k_forward, dim3(blocks), dim3(kBlock), 0, st, U, n, work);
   return hipGetLastError();
 }
 
-hipError_t launch_finalize(const FinArgs& A, int width, hipStream_t st) {
-  const int w = A.crop.x1 - A.crop.x0, h = A.crop.y1 - A.crop.y0;
-  if (w <= 0 || h <= 0 || A.n_jobs <= 0) return hipSuccess;
-  if (A.n_jobs > 3) return hipErrorInvalidValue;
-  const unsigned want = cdiv((size_t)w * h, kFinBlock);
-  hipLaunchKernelGGL(k_finalize, dim3(want < kFinMaxBlocks ? want : kFinMaxBlocks, A.n_jobs),
-                     dim3(kFinBlock), 0, st, A, width);
+hipError_t launch_finalize(const FinArgs* U, int n, uint32_t blocks, hipStream_t st) {
+  if (n <= 0 || blocks == 0) return hipSuccess;
+  hipLaunchKernelGGL(k_finalize, dim3(blocks), dim3(kFinBlock), 0, st, U, n);
   return hipGetLastError();
 }
 
-hipError_t launch_adjoint(const DevScene* S, const RepArgs& A, int n, int n_ch, hipStream_t st) {
-  const int w = A.crop.x1 - A.crop.x0, h = A.crop.y1 - A.crop.y0;
-  if (w <= 0 || h <= 0 || n <= 0) return hipSuccess;
-  if (n > kMaxSlots || n_ch < 0 || n_ch > 5) return hipErrorInvalidValue;
+size_t adjoint_lds_bytes(int n_ch) {
   const size_t table = (size_t)kTableSize * 4 * (1 + (size_t)n_ch);
   const size_t xchg = (size_t)kRepXchgWords * kXchg * 4;
-  const size_t lds = table > xchg ? table : xchg;
-  hipLaunchKernelGGL(k_adjoint, dim3(cdiv(w, kTile), cdiv(h, kTile), n), dim3(kBlock), lds, st, S,
-                     A);
+  return table > xchg ? table : xchg;
+}
+
+hipError_t launch_adjoint(const RepArgs* U, int n, uint32_t blocks, size_t lds,
+                          unsigned long long* work, hipStream_t st) {
+  if (n <= 0 || blocks == 0) return hipSuccess;
+  if (lds < adjoint_lds_bytes(0) || lds > adjoint_lds_bytes(5)) return hipErrorInvalidValue;
+  hipLaunchKernelGGL(k_adjoint, dim3(blocks), dim3(kBlock), lds, st, U, n, work);
   return hipGetLastError();
 }
 
-static unsigned elementwise_grid(size_t n) {
-  // at most 8 blocks per CU of 256 CUs; grid-stride beyond that
-  const size_t want = (n + 255) / 256;
-  return (unsigned)(want < 2048 ? (want ? want : 1) : 2048);
-}
-
-hipError_t launch_meta(const MetaArgs& A, hipStream_t st) {
-  if (A.n >= (size_t)1 << 31 || A.n_ch < 1 || !A.partials) return hipErrorInvalidValue;
-  const size_t want = cdiv(A.n, (size_t)kMetaBlock * kMetaK);
-  const unsigned grid = (unsigned)(want < 1 ? 1 : (want > kMetaMaxBlocks ? kMetaMaxBlocks : want));
-  hipLaunchKernelGGL(k_meta, dim3(grid), dim3(kMetaBlock), 0, st, A);
+hipError_t launch_meta(const MetaArgs* U, int n, uint32_t blocks, hipStream_t st) {
+  if (n <= 0 || blocks == 0) return hipSuccess;
+  hipLaunchKernelGGL(k_meta, dim3(blocks), dim3(kMetaBlock), 0, st, U, n);
   return hipGetLastError();
 }
 
-hipError_t launch_adam(const AdamArgs& A, hipStream_t st) {
-  hipLaunchKernelGGL(k_adam, dim3(elementwise_grid(A.n)), dim3(256), 0, st, A);
+hipError_t launch_adam(const AdamArgs* U, int n, uint32_t blocks, hipStream_t st) {
+  if (n <= 0 || blocks == 0) return hipSuccess;
+  hipLaunchKernelGGL(k_adam, dim3(blocks), dim3(kMetaBlock), 0, st, U, n);
   return hipGetLastError();
 }
 

@@ -212,3 +212,32 @@ def config_textured(seed_scene: int = 0, seed_gt: int = 1, seed_init: int = 2,
     ground truth = random-Fourier textures; initial texels ~U[0.2,0.8]."""
     s = scene_textured(width, height, tex, seed_scene)
     return s, fourier_params(s, seed_gt), uniform_params(s, seed_init, 0.2, 0.8)
+
+
+def config_batched(n: int = 64, seed: int = 0):
+    """Many independent problems of uneven size: image side = multiple of 8
+    nearest 64 * 8^U (64..512), parameter count P = round(5 * 13107^U)
+    (5..65,536): P <= 5 is the global material (5 parameters, unit sphere on a
+    grey plane, depth 3), otherwise a plane + spheres scene sharing one square
+    texture of RGB + roughness with side ceil(sqrt(P / 4)) (depth 6, roulette
+    from vertex 3).  Iteration budget ~ U{200..1000}; each problem has its own
+    scene, ground truth, initial parameters and optimisation seed.
+    Returns a list of dicts (spec, gt, init, max_iter, seed)."""
+    g = rng(seed)
+    out = []
+    for k in range(n):
+        side = int(round(64 * 8 ** g.uniform() / 8.0)) * 8
+        side = min(max(side, 64), 512)
+        P = int(round(5 * 13107 ** g.uniform()))
+        max_iter = int(g.integers(200, 1001))
+        sub = int(g.integers(0, 2 ** 31))
+        if P <= 5:
+            s = scene_tiny()
+            s.width = s.height = side
+            gt, init = uniform_params(s, sub + 1, 0.1, 0.9), uniform_params(s, sub + 2, 0.1, 0.9)
+        else:
+            tex = int(np.ceil(np.sqrt(P / 4.0)))
+            s = scene_textured(side, side, tex, seed=sub, n_spheres=int(g.integers(1, 9)))
+            gt, init = fourier_params(s, sub + 1), uniform_params(s, sub + 2, 0.2, 0.8)
+        out.append(dict(spec=s, gt=gt, init=init, max_iter=max_iter, seed=sub))
+    return out

@@ -164,3 +164,36 @@ def grad_step_many(problems: Sequence[Problem], opts, want_stats: bool = False):
     rc, stats = L.jso_grad_step(problems[0].ctx, [p.sid for p in problems], opts, want_stats)
     L.check(rc, problems[0].context.ctx, "jso_grad_step")
     return stats
+
+
+class Batch:
+    """Problems of one context optimised together: one launch per kernel per
+    iteration for all of them, replayed from a captured HIP graph when
+    use_graph is set.  max_iters[k] = 0 means no limit for problem k."""
+
+    def __init__(self, problems: Sequence[Problem], opts, max_iters=None,
+                 use_graph: bool = True):
+        ctxs = {id(p.context) for p in problems}
+        if len(ctxs) != 1:
+            raise ValueError("problems must share one Context")
+        self.context = problems[0].context
+        self.problems = list(problems)
+        self.batch = L.jso_batch_create(self.context.bind(), [p.sid for p in problems], opts,
+                                        max_iters, use_graph)
+
+    def step(self, iterations: int = 1) -> None:
+        L.jso_batch_step(self.context.bind(), self.batch, iterations)
+
+    def active(self) -> int:
+        return L.jso_batch_active(self.context.bind(), self.batch)
+
+    def close(self) -> None:
+        if self.batch:
+            L.jso_batch_destroy(self.batch)
+            self.batch = None
+
+    def __del__(self):
+        try:
+            self.close()
+        except Exception:
+            pass

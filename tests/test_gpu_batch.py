@@ -1,0 +1,114 @@
+"""GPU tests of many problems per launch: jso_grad_step over several problems
+and jso_batch (descriptors uploaded once, optional HIP graph replay) against
+stepping each problem on its own.
+
+Gradients are summed with float atomics, whose order depends on block
+scheduling, so two runs of the same step agree to float rounding, not bit
+for bit: states are compared with a tolerance of 1e-5 of each array's scale
+(one step of rounding noise through the FP64 meta-estimator state)."""
+import sys
+
+import numpy as np
+import pytest
+
+from paper_2309_15676_amd import inputs as I
+
+pytestmark = pytest.mark.gpu
+
+
+def _say(*a):
+    print("[case]", *a, flush=True)
+    sys.stdout.flush()
+
+
+@pytest.fixture(scope="module")
+def ctx():
+    torch = pytest.importorskip("torch")
+    if not torch.cuda.is_available():
+        pytest.skip("no GPU")
+    from paper_2309_15676_amd.problem import Context
+    c = Context(0)
+    yield c
+    c.close()
+
+
+def _specs():
+    """Three uneven problems: a global material, two textures of different
+    sizes, one with a ragged image (not a multiple of the 16x16 tile)."""
+    tiny, gt, init = I.config_tiny()
+    tiny.width, tiny.height = 40, 24
+    t1 = I.scene_textured(48, 32, 16, seed=1, depth=4, rr_start=3)
+    t2 = I.scene_textured(37, 21, 8, seed=2, depth=6, rr_start=3)
+    return [
+        (tiny, np.asarray(gt, np.float32), np.asarray(init, np.float32)),
+        (t1, I.fourier_params(t1, 1), I.uniform_params(t1, 2, 0.2, 0.8)),
+        (t2, I.fourier_params(t2, 3), I.uniform_params(t2, 4, 0.2, 0.8)),
+    ]
+
+
+def _make(ctx):
+    from paper_2309_15676_amd import _lib as L
+    from paper_2309_15676_amd.problem import Problem
+    probs = []
+    for spec, gt, init in _specs():
+        p = Problem(spec, context=ctx)
+        p.set_target(p.render(gt, seed=9, iteration=0, tag=L.JSO_TAG_TARGET, spp=16))
+        p.set_params(init)
+        probs.append(p)
+    return probs
+
+
+def _close_states(a, b, what):
+    for key in ("params", "params_prev", "mean", "var", "m2_F", "m2_D"):
+        x, y = np.asarray(a[key], np.float64), np.asarray(b[key], np.float64)
+        scale = max(np.abs(y).max(), 1e-30)
+        assert np.abs(x - y).max() <= 1e-5 * scale, "%s %s: %g" % (what, key,
+                                                                np.abs(x - y).max() / scale)
+    assert a["iteration"] == b["iteration"], what
+
+
+@pytest.mark.parametrize("optimizer", ["meta", "adam"])
+def test_grad_step_over_several_problems_matches_one_by_one(ctx, optimizer):
+    from paper_2309_15676_amd import _lib as L
+    from paper_2309_15676_amd.problem import grad_step_many
+    _say("grad_step several problems", optimizer)
+    opt = L.JSO_OPT_META if optimizer == "meta" else L.JSO_OPT_ADAM
+    opts = L.step_opts(optimizer=opt, eta=0.02, adam_spp=3, seed=11)
+    together, alone = _make(ctx), _make(ctx)
+    for it in range(3):
+        st = grad_step_many(together, opts, want_stats=True)
+        for k, p in enumerate(alone):
+            s1 = p.grad_step(opts, want_stats=True)
+            assert st[k].iteration == s1.iteration == it + 1
+            assert abs(st[k].loss - s1.loss) <= 1e-6 * max(s1.loss, 1e-30)
+        for k in range(len(alone)):
+            _close_states(together[k].get_state(), alone[k].get_state(), "problem %d it %d" % (k, it))
+
+
+@pytest.mark.parametrize("use_graph", [True, False])
+def test_batch_matches_grad_step_and_stops_at_its_limit(ctx, use_graph):
+    import torch
+    from paper_2309_15676_amd import _lib as L
+    from paper_2309_15676_amd.problem import Batch, grad_step_many
+    _say("batch", "graph" if use_graph else "eager")
+    opts = L.step_opts(optimizer=L.JSO_OPT_META, eta=0.02, seed=5)
+    batched, ref = _make(ctx), _make(ctx)
+    limits = [2, 0, 4]
+    b = Batch(batched, opts, max_iters=limits, use_graph=use_graph)
+    assert b.active() == 3
+    for it in range(5):
+        b.step(1)
+        # eager work and a synchronisation between replays
+        junk = batched[1].render(batched[1].get_params(), seed=1, iteration=0, tag=L.JSO_TAG_EVAL,
+                                 spp=1)
+        torch.cuda.synchronize()
+        assert torch.isfinite(junk).all()
+        live = [p for p, m in zip(ref, limits) if m == 0 or it < m]
+        grad_step_many(live, opts)
+        for k, p in enumerate(batched):
+            want = min(it + 1, limits[k]) if limits[k] else it + 1
+            sb, sr = p.get_state(), ref[k].get_state()
+            assert sb["iteration"] == want, (k, sb["iteration"], want)
+            _close_states(sb, sr, "graph=%s problem %d after %d" % (use_graph, k, it + 1))
+    assert b.active() == 1
+    b.close()
