@@ -198,8 +198,9 @@ def batched_throughput(ctx_problem, args):
     """64 independent problems of uneven size (image side 64-512, 5-65,536
     parameters, own seeds and iteration budgets): differentiable paths/s of
     one iteration for all of them, (a) as a batch replayed from a captured
-    HIP graph, (b) as one jso_grad_step over all problems (one launch per
-    kernel), (c) as one jso_grad_step per problem."""
+    HIP graph with the tile shape picked by the autotuner, (b) as one
+    jso_grad_step over all problems (one launch per kernel, tuned shape),
+    (c) as one jso_grad_step per problem."""
     import torch
 
     from paper_2309_15676_amd import _lib as L
@@ -231,6 +232,7 @@ def batched_throughput(ctx_problem, args):
         return e0.elapsed_time(e1) / steps
 
     b = Batch(probs, opts, max_iters=[c["max_iter"] for c in cfg], use_graph=True)
+    shape, shape_ms = b.autotune(3)  # state is restored after each trial
     ms_graph = timed(lambda n: b.step(n))
     b.close()
 
@@ -253,6 +255,8 @@ def batched_throughput(ctx_problem, args):
         "pixels": pixels,
         "params": sum(c["spec"].n_params for c in cfg),
         "steps": steps,
+        "autotune": {"tile": ["16x16", "16x8", "8x8"][shape],
+                     "ms_per_iteration": {t: m for t, m in zip(["16x16", "16x8", "8x8"], shape_ms)}},
         "graph": {"ms_per_iteration": ms_graph, "paths_per_s": paths / (ms_graph / 1e3)},
         "one_launch_per_kernel": {"ms_per_iteration": ms_together,
                                   "paths_per_s": paths / (ms_together / 1e3)},

@@ -267,6 +267,24 @@ int jso_batch_step(jso_batch* b, int iterations);
 int jso_batch_active(jso_batch* b, int* active);
 int jso_batch_destroy(jso_batch* b);
 
+/* Pixel tiles of the path kernels: one workgroup traces one tile. */
+#define JSO_TILE_16x16 0 /* 256 lanes */
+#define JSO_TILE_16x8 1  /* 128 lanes */
+#define JSO_TILE_8x8 2   /* 64 lanes  */
+#define JSO_TILE_SHAPES 3
+/* Time `iterations` real iterations of the batch with each tile shape (the
+ * problems' optimiser state is restored after each trial), keep the fastest
+ * for this batch and remember it, for this GPU architecture and
+ * configuration (image sizes, parameter layouts, sample counts), for every
+ * later batch or jso_grad_step of the process with the same configuration.
+ * best_shape (nullable) receives JSO_TILE_*; ms (nullable host array of
+ * JSO_TILE_SHAPES) the milliseconds per iteration of each shape.  Waits for
+ * the stream.  Errors: JSO_E_INVALID, JSO_E_OOM, JSO_E_HIP. */
+int jso_batch_autotune(jso_batch* b, int iterations, int* best_shape, double* ms);
+/* Tile shape used when the tuner has no entry for a configuration
+ * (JSO_TILE_*, default JSO_TILE_16x16). */
+int jso_set_tile_shape(jso_ctx* ctx, int shape);
+
 /* ---- kernel timing --------------------------------------------------------------- */
 
 /* Kernel classes reported by jso_get_kernel_time */

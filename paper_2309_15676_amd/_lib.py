@@ -35,7 +35,9 @@ EXPORTED = [
     "jso_meta_step", "jso_adam_step", "jso_grad_step", "jso_get_state", "jso_set_state",
     "jso_set_timing", "jso_get_kernel_time", "jso_set_work_counting", "jso_get_work",
     "jso_batch_create", "jso_batch_step", "jso_batch_active", "jso_batch_destroy",
+    "jso_batch_autotune", "jso_set_tile_shape",
 ]
+JSO_TILE_16x16, JSO_TILE_16x8, JSO_TILE_8x8, JSO_TILE_SHAPES = 0, 1, 2, 3
 JSO_K_FORWARD, JSO_K_ADJOINT, JSO_K_META, JSO_K_ADAM, JSO_K_FINALIZE = 0, 1, 2, 3, 4
 JSO_K_COUNT = 5
 
@@ -143,6 +145,8 @@ def load() -> ctypes.CDLL:
         "jso_batch_step": (I, [P, I]),
         "jso_batch_active": (I, [P, ctypes.POINTER(I)]),
         "jso_batch_destroy": (I, [P]),
+        "jso_batch_autotune": (I, [P, I, ctypes.POINTER(I), ctypes.POINTER(D)]),
+        "jso_set_tile_shape": (I, [P, I]),
     }
     for name, (res, args) in sig.items():
         fn = getattr(L, name)
@@ -402,6 +406,19 @@ def jso_batch_active(ctx, batch) -> int:
     out = ctypes.c_int(0)
     check(load().jso_batch_active(batch, ctypes.byref(out)), ctx, "jso_batch_active")
     return out.value
+
+
+def jso_batch_autotune(ctx, batch, iterations: int = 3):
+    """(best tile shape, ms per iteration of each shape)."""
+    best = ctypes.c_int(0)
+    ms = (ctypes.c_double * JSO_TILE_SHAPES)()
+    check(load().jso_batch_autotune(batch, iterations, ctypes.byref(best), ms), ctx,
+          "jso_batch_autotune")
+    return best.value, list(ms)
+
+
+def jso_set_tile_shape(ctx, shape: int) -> None:
+    check(load().jso_set_tile_shape(ctx, shape), ctx, "jso_set_tile_shape")
 
 
 def jso_batch_destroy(batch) -> int:

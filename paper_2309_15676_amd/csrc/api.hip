@@ -8,7 +8,9 @@
 #include <cstdarg>
 #include <cstdio>
 #include <cstring>
+#include <map>
 #include <memory>
+#include <mutex>
 #include <new>
 #include <string>
 #include <vector>
@@ -45,6 +47,11 @@ struct SceneGPU {
 
 // Source of SceneGPU::generation.
 std::atomic<uint64_t> g_scene_generation{0};
+
+// Tile shapes picked by the autotuner, by (GPU architecture, configuration
+// hash); shared by every context of the process.
+std::mutex g_tuned_mu;
+std::map<std::pair<std::string, uint64_t>, int> g_tuned;
 
 // HIP-event timing of kernel launches, per kernel class.
 struct KernelTimer {
@@ -150,7 +157,7 @@ struct DescRing {
 // directly.  `sig` identifies the plan (scenes by load generation, options,
 // flags); launch records keep their metadata, their units live on the device.
 struct CachedLaunch {
-  int kind, timer, n;
+  int kind, timer, shape, n;
   uint32_t blocks;
   size_t lds, offset;
 };
@@ -181,6 +188,8 @@ struct PlanCache {
 struct jso_ctx {
   DescRing ring;
   PlanCache plan_cache;
+  std::string arch;     // gcnArchName of the device
+  int tile_shape = 0;   // default tile shape when the tuner has no entry
   int device = 0;
   hipStream_t stream = nullptr;  // nullptr = the device's null (default) stream
   uint32_t debug_flags = 0;
@@ -446,6 +455,7 @@ enum class Kern { Forward, Finalize, Adjoint, Meta, Adam };
 struct LaunchRec {
   Kern kind;
   int timer;                   // JSO_K_* class
+  int shape = 0;               // path kernels: tile shape (kShapeW / kShapeH)
   std::vector<uint8_t> units;  // host copy of the unit array
   int n = 0;
   uint32_t blocks = 0;
@@ -465,16 +475,18 @@ void push_unit(LaunchRec& r, U u, uint32_t blocks) {
   r.blocks += blocks;
 }
 
-uint32_t tiles_x(const Crop& c) { return (uint32_t)((c.x1 - c.x0 + kTile - 1) / kTile); }
-uint32_t tiles_of(const Crop& c) {
-  return tiles_x(c) * (uint32_t)((c.y1 - c.y0 + kTile - 1) / kTile);
+uint32_t tiles_x(const Crop& c, int shape) {
+  return (uint32_t)((c.x1 - c.x0 + kShapeW[shape] - 1) / kShapeW[shape]);
+}
+uint32_t tiles_of(const Crop& c, int shape) {
+  return tiles_x(c, shape) * (uint32_t)((c.y1 - c.y0 + kShapeH[shape] - 1) / kShapeH[shape]);
 }
 
 bool crop_empty(const Crop& c) { return c.x1 <= c.x0 || c.y1 <= c.y0; }
 
 // The launches of the estimator part of a step for problems `ps` (all with the
-// same job structure).
-void plan_estimators(const std::vector<ProbPlan>& ps, Plan& plan) {
+// same job structure), with pixel tiles of the given shape.
+void plan_estimators(const std::vector<ProbPlan>& ps, Plan& plan, int shape = 0) {
   if (ps.empty()) return;
   const ProbPlan& p0 = ps[0];
   // primal samples in job order; replay units, pairs first: within a launch
@@ -525,6 +537,7 @@ void plan_estimators(const std::vector<ProbPlan>& ps, Plan& plan) {
     LaunchRec fw;
     fw.kind = Kern::Forward;
     fw.timer = JSO_K_FORWARD;
+    fw.shape = shape;
     for (const ProbPlan& p : ps) {
       if (crop_empty(p.crop)) continue;
       FwdArgs f{};
@@ -545,8 +558,8 @@ void plan_estimators(const std::vector<ProbPlan>& ps, Plan& plan) {
       f.slots = gmem(p.s->slots);
       f.npix = (uint32_t)p.s->npix;
       f.flags = p.flags;
-      f.tiles_x = tiles_x(p.crop);
-      f.tiles = tiles_of(p.crop);
+      f.tiles_x = tiles_x(p.crop, shape);
+      f.tiles = tiles_of(p.crop, shape);
       push_unit(fw, f, f.tiles * (uint32_t)f.n_slices);
     }
     plan.push_back(std::move(fw));
@@ -601,6 +614,7 @@ void plan_estimators(const std::vector<ProbPlan>& ps, Plan& plan) {
       LaunchRec ad;
       ad.kind = Kern::Adjoint;
       ad.timer = JSO_K_ADJOINT;
+      ad.shape = shape;
       ad.lds = adjoint_lds_bytes(max_ch);
       for (int pass = 0; pass < 2; ++pass) {
         for (const ProbPlan& p : ps) {
@@ -632,8 +646,8 @@ void plan_estimators(const std::vector<ProbPlan>& ps, Plan& plan) {
           r.slots = gmem((const double*)p.s->slots);
           r.npix = (uint32_t)p.s->npix;
           r.flags = p.flags;
-          r.tiles_x = tiles_x(p.crop);
-          r.tiles = tiles_of(p.crop);
+          r.tiles_x = tiles_x(p.crop, shape);
+          r.tiles = tiles_of(p.crop, shape);
           push_unit(ad, r, r.tiles * (uint32_t)r.n_slices);
         }
       }
@@ -779,18 +793,49 @@ hipError_t launch_rec(const LaunchRec& r, const void* dev_units, unsigned long l
                       hipStream_t st) {
   switch (r.kind) {
     case Kern::Forward:
-      return launch_forward(static_cast<const FwdArgs*>(dev_units), r.n, r.blocks, work, st);
+      return launch_forward(static_cast<const FwdArgs*>(dev_units), r.n, r.blocks, r.shape, work,
+                            st);
     case Kern::Finalize:
       return launch_finalize(static_cast<const FinArgs*>(dev_units), r.n, r.blocks, st);
     case Kern::Adjoint:
-      return launch_adjoint(static_cast<const RepArgs*>(dev_units), r.n, r.blocks, r.lds, work,
-                            st);
+      return launch_adjoint(static_cast<const RepArgs*>(dev_units), r.n, r.blocks, r.shape, r.lds,
+                            work, st);
     case Kern::Meta:
       return launch_meta(static_cast<const MetaArgs*>(dev_units), r.n, r.blocks, st);
     case Kern::Adam:
       return launch_adam(static_cast<const AdamArgs*>(dev_units), r.n, r.blocks, st);
   }
   return hipErrorInvalidValue;
+}
+
+// Identity of a step configuration for the tuner: estimator/optimiser sample
+// counts and, per problem, image and parameter layout (FNV-1a).
+uint64_t config_hash(const std::vector<SceneGPU*>& ss, const jso_step_opts& o) {
+  uint64_t h = 1469598103934665603ull;
+  auto mix = [&](uint64_t v) {
+    for (int k = 0; k < 8; ++k) {
+      h ^= (v >> (8 * k)) & 0xFF;
+      h *= 1099511628211ull;
+    }
+  };
+  mix((uint64_t)o.optimizer);
+  mix((uint64_t)o.spp_prop);
+  mix((uint64_t)o.spp_fd);
+  mix((uint64_t)o.adam_spp);
+  for (SceneGPU* s : ss) {
+    mix((uint64_t)s->width);
+    mix((uint64_t)s->height);
+    mix((uint64_t)s->n_ch);
+    mix((uint64_t)s->P);
+    mix((uint64_t)s->dev.depth);
+  }
+  return h;
+}
+
+int chosen_shape(jso_ctx* c, uint64_t hash) {
+  std::lock_guard<std::mutex> lock(g_tuned_mu);
+  auto it = g_tuned.find({c->arch, hash});
+  return it != g_tuned.end() ? it->second : c->tile_shape;
 }
 
 // Run a plan now: each launch's units are staged through the context's ring.
@@ -854,7 +899,8 @@ int exec_cached(jso_ctx* c, const std::vector<uint64_t>& sig, Build build) {
     }
     for (size_t k = 0; k < plan.size(); ++k) {
       const LaunchRec& r = plan[k];
-      np.launches.push_back(CachedLaunch{(int)r.kind, r.timer, r.n, r.blocks, r.lds, off[k]});
+      np.launches.push_back(
+          CachedLaunch{(int)r.kind, r.timer, r.shape, r.n, r.blocks, r.lds, off[k]});
     }
     np.sig = sig;
     pc.plans.push_back(std::move(np));
@@ -866,6 +912,7 @@ int exec_cached(jso_ctx* c, const std::vector<uint64_t>& sig, Build build) {
     if (l.n == 0) continue;
     LaunchRec r;
     r.kind = (Kern)l.kind;
+    r.shape = l.shape;
     r.n = l.n;
     r.blocks = l.blocks;
     r.lds = l.lds;
@@ -918,6 +965,8 @@ int jso_create(jso_ctx** out, int device, void* stream) {
   if (!c) return JSO_E_OOM;
   c->device = device;
   c->stream = (hipStream_t)stream;
+  hipDeviceProp_t prop;
+  if (hipGetDeviceProperties(&prop, device) == hipSuccess) c->arch = prop.gcnArchName;
   *out = c;
   return JSO_OK;
 }
@@ -1099,7 +1148,7 @@ int jso_render(jso_ctx* c, int id, const float* params, uint64_t seed, uint32_t 
   p.flags = c->debug_flags | (opts ? opts->flags : 0u);
   p.pj[p.np++] = PrimalSpec{params, tag, spp, img, nullptr, nullptr};
   Plan plan;
-  plan_estimators({p}, plan);
+  plan_estimators({p}, plan, c->tile_shape);
   return exec_plan(c, plan);
 }
 
@@ -1119,7 +1168,7 @@ int jso_render_bwd(jso_ctx* c, int id, const float* params, uint64_t seed, uint3
   p.flags = c->debug_flags | (opts ? opts->flags : 0u);
   p.aj[p.na++] = AdjointSpec{params, nullptr, dimg, nullptr, dparams, 1.0f, tag, spp};
   Plan plan;
-  plan_estimators({p}, plan);
+  plan_estimators({p}, plan, c->tile_shape);
   return exec_plan(c, plan);
 }
 
@@ -1138,7 +1187,7 @@ int jso_estimate_gradients(jso_ctx* c, int id, uint64_t seed, uint32_t iteration
                                     s->scratch_loss, crop_of(s, opts),
                                     opts ? opts->pixel_mask : nullptr,
                                     c->debug_flags | (opts ? opts->flags : 0u))},
-                  plan);
+                  plan, c->tile_shape);
   int rc = exec_plan(c, plan);
   if (rc) return rc;
   if (loss) {
@@ -1221,10 +1270,14 @@ int jso_grad_step(jso_ctx* c, const int* ids, int n, const jso_step_opts* o,
     std::memcpy(&u, &f, 4);
     return (uint64_t)u;
   };
+  std::vector<SceneGPU*> ss;
   for (int k = 0; k < n; ++k) {
     sig.push_back((uint64_t)ids[k]);
     sig.push_back(get_scene(c, ids[k])->generation);
+    ss.push_back(get_scene(c, ids[k]));
   }
+  const int shape = chosen_shape(c, config_hash(ss, *o));
+  sig.push_back((uint64_t)shape);
   for (uint64_t v : {(uint64_t)o->optimizer, bits(o->eta), bits(o->beta_F), bits(o->beta_D),
                      (uint64_t)o->spp_prop, (uint64_t)o->spp_fd, bits(o->adam_beta1),
                      bits(o->adam_beta2), bits(o->adam_eps), (uint64_t)o->adam_spp, o->seed,
@@ -1233,7 +1286,7 @@ int jso_grad_step(jso_ctx* c, const int* ids, int n, const jso_step_opts* o,
   rc = exec_cached(c, sig, [&](Plan& plan) {
     std::vector<ProbPlan> ps;
     for (int k = 0; k < n; ++k) ps.push_back(step_problem(get_scene(c, ids[k]), *o, flags, 0));
-    plan_estimators(ps, plan);
+    plan_estimators(ps, plan, shape);
     plan_optimizer(ps, *o, plan);
   });
   if (rc) return rc;
@@ -1251,6 +1304,11 @@ struct jso_batch {
   jso_ctx* c = nullptr;
   std::vector<int> ids;
   std::vector<uint32_t> max_iters;
+  jso_step_opts opts{};
+  uint32_t flags = 0;
+  bool use_graph = false;
+  int shape = 0;
+  uint64_t hash = 0;
   Plan plan;
   uint8_t* dev = nullptr;  // unit arrays of the plan
   std::vector<size_t> off;
@@ -1261,11 +1319,20 @@ struct jso_batch {
 
 namespace {
 
-void batch_free(jso_batch* b) {
+void batch_release(jso_batch* b) {
   if (b->exec) (void)hipGraphExecDestroy(b->exec);
   if (b->graph) (void)hipGraphDestroy(b->graph);
-  if (b->capture) (void)hipStreamDestroy(b->capture);
   if (b->dev) (void)hipFree(b->dev);
+  b->exec = nullptr;
+  b->graph = nullptr;
+  b->dev = nullptr;
+  b->plan.clear();
+  b->off.clear();
+}
+
+void batch_free(jso_batch* b) {
+  batch_release(b);
+  if (b->capture) (void)hipStreamDestroy(b->capture);
   delete b;
 }
 
@@ -1275,6 +1342,87 @@ int batch_launch_all(jso_batch* b, hipStream_t st) {
     if (r.n == 0) continue;
     HIP_TRY(b->c, launch_rec(r, b->dev + b->off[k], nullptr, st));
   }
+  return JSO_OK;
+}
+
+// (Re)build the batch's plan for a tile shape: descriptors uploaded once, the
+// iteration captured in a graph when requested.
+int batch_build(jso_batch* b, int shape) {
+  jso_ctx* c = b->c;
+  HIP_TRY(c, hipStreamSynchronize(c->stream));  // the old descriptors may be in use
+  batch_release(b);
+  b->shape = shape;
+  std::vector<ProbPlan> ps;
+  for (size_t k = 0; k < b->ids.size(); ++k) {
+    SceneGPU* s = get_scene(c, b->ids[k]);
+    if (!s) return fail(c, JSO_E_STATE, "scene %d of the batch was freed", b->ids[k]);
+    ps.push_back(step_problem(s, b->opts, b->flags, b->max_iters[k]));
+  }
+  plan_estimators(ps, b->plan, shape);
+  plan_optimizer(ps, b->opts, b->plan);
+  const std::vector<uint8_t> all = pack_plan(b->plan, b->off);
+  HIP_TRY(c, hipMalloc(reinterpret_cast<void**>(&b->dev), all.size()));
+  HIP_TRY(c, hipMemcpy(b->dev, all.data(), all.size(), hipMemcpyHostToDevice));
+  if (b->use_graph) {
+    // capture on a private stream; replays run on the context's stream
+    if (!b->capture) HIP_TRY(c, hipStreamCreateWithFlags(&b->capture, hipStreamNonBlocking));
+    HIP_TRY(c, hipStreamBeginCapture(b->capture, hipStreamCaptureModeThreadLocal));
+    const int rc = batch_launch_all(b, b->capture);
+    hipGraph_t graph = nullptr;
+    const hipError_t e = hipStreamEndCapture(b->capture, &graph);
+    b->graph = graph;
+    if (rc) return rc;
+    HIP_TRY(c, e);
+    HIP_TRY(c, hipGraphInstantiate(&b->exec, b->graph, nullptr, nullptr, 0));
+  }
+  return JSO_OK;
+}
+
+int batch_run(jso_batch* b, int iterations) {
+  jso_ctx* c = b->c;
+  for (int it = 0; it < iterations; ++it) {
+    if (b->exec) {
+      HIP_TRY(c, hipGraphLaunch(b->exec, c->stream));
+    } else {
+      const int rc = batch_launch_all(b, c->stream);
+      if (rc) return rc;
+    }
+  }
+  return JSO_OK;
+}
+
+// Device copies of the optimiser state of a batch's problems (the tuner runs
+// real iterations and puts everything back afterwards).
+struct StateCopy {
+  std::vector<std::pair<void*, std::pair<void*, size_t>>> bufs;  // (copy, (live, bytes))
+  ~StateCopy() {
+    for (auto& x : bufs) (void)hipFree(x.first);
+  }
+};
+
+int snapshot(jso_ctx* c, const std::vector<int>& ids, StateCopy& sc) {
+  for (int id : ids) {
+    SceneGPU* s = get_scene(c, id);
+    const size_t P = s->P;
+    const std::pair<void*, size_t> live[] = {
+        {s->params, P * 4},      {s->params_prev, P * 4}, {s->F, P * 4},
+        {s->dF, P * 4},          {s->mean, P * 8},        {s->var, P * 8},
+        {s->alpha_prev, P * 8},  {s->m2F, P * 8},         {s->m2D, P * 8},
+        {s->adam_m, P * 4},      {s->adam_v, P * 4},      {s->ctl, sizeof(Ctl)}};
+    for (const auto& l : live) {
+      void* copy = nullptr;
+      HIP_TRY(c, hipMalloc(&copy, l.second));
+      sc.bufs.push_back({copy, l});
+      HIP_TRY(c, hipMemcpyAsync(copy, l.first, l.second, hipMemcpyDeviceToDevice, c->stream));
+    }
+  }
+  return JSO_OK;
+}
+
+int restore(jso_ctx* c, const StateCopy& sc) {
+  for (const auto& x : sc.bufs)
+    HIP_TRY(c, hipMemcpyAsync(x.second.first, x.first, x.second.second,
+                              hipMemcpyDeviceToDevice, c->stream));
   return JSO_OK;
 }
 
@@ -1301,27 +1449,14 @@ int jso_batch_create(jso_ctx* c, const int* ids, int n, const jso_step_opts* o,
   b->ids.assign(ids, ids + n);
   b->max_iters.assign(n, 0u);
   if (max_iters) b->max_iters.assign(max_iters, max_iters + n);
-  const uint32_t flags = c->debug_flags | o->flags;
-  std::vector<ProbPlan> ps;
-  for (int k = 0; k < n; ++k)
-    ps.push_back(step_problem(get_scene(c, ids[k]), *o, flags, b->max_iters[k]));
-  plan_estimators(ps, b->plan);
-  plan_optimizer(ps, *o, b->plan);
-  const std::vector<uint8_t> all = pack_plan(b->plan, b->off);
-  HIP_TRY(c, hipMalloc(reinterpret_cast<void**>(&b->dev), all.size()));
-  HIP_TRY(c, hipMemcpy(b->dev, all.data(), all.size(), hipMemcpyHostToDevice));
-  if (use_graph) {
-    // capture on a private stream; replays run on the context's stream
-    HIP_TRY(c, hipStreamCreateWithFlags(&b->capture, hipStreamNonBlocking));
-    HIP_TRY(c, hipStreamBeginCapture(b->capture, hipStreamCaptureModeThreadLocal));
-    rc = batch_launch_all(b.get(), b->capture);
-    hipGraph_t graph = nullptr;
-    const hipError_t e = hipStreamEndCapture(b->capture, &graph);
-    b->graph = graph;
-    if (rc) return rc;
-    HIP_TRY(c, e);
-    HIP_TRY(c, hipGraphInstantiate(&b->exec, b->graph, nullptr, nullptr, 0));
-  }
+  b->opts = *o;
+  b->flags = c->debug_flags | o->flags;
+  b->use_graph = use_graph != 0;
+  std::vector<SceneGPU*> ss;
+  for (int k = 0; k < n; ++k) ss.push_back(get_scene(c, ids[k]));
+  b->hash = config_hash(ss, *o);
+  rc = batch_build(b.get(), chosen_shape(c, b->hash));
+  if (rc) return rc;
   *out = b.release();
   return JSO_OK;
 }
@@ -1331,14 +1466,59 @@ int jso_batch_step(jso_batch* b, int iterations) {
   jso_ctx* c = b->c;
   if (iterations < 0) return fail(c, JSO_E_INVALID, "iterations < 0");
   DeviceGuard g(c->device);
-  for (int it = 0; it < iterations; ++it) {
-    if (b->exec) {
-      HIP_TRY(c, hipGraphLaunch(b->exec, c->stream));
-    } else {
-      const int rc = batch_launch_all(b, c->stream);
-      if (rc) return rc;
+  return batch_run(b, iterations);
+}
+
+int jso_batch_autotune(jso_batch* b, int iterations, int* best_shape, double* ms) {
+  if (!b) return JSO_E_INVALID;
+  jso_ctx* c = b->c;
+  if (iterations < 1) return fail(c, JSO_E_INVALID, "iterations < 1");
+  DeviceGuard g(c->device);
+  StateCopy sc;
+  int rc = snapshot(c, b->ids, sc);
+  if (rc) return rc;
+  hipEvent_t e0 = nullptr, e1 = nullptr;
+  HIP_TRY(c, hipEventCreate(&e0));
+  std::unique_ptr<void, void (*)(void*)> g0(e0, [](void* e) { (void)hipEventDestroy((hipEvent_t)e); });
+  HIP_TRY(c, hipEventCreate(&e1));
+  std::unique_ptr<void, void (*)(void*)> g1(e1, [](void* e) { (void)hipEventDestroy((hipEvent_t)e); });
+  int best = b->shape;
+  float best_ms = 0.0f;
+  for (int shape = 0; shape < kShapes; ++shape) {
+    rc = batch_build(b, shape);
+    if (rc) return rc;
+    rc = batch_run(b, 1);  // warm-up (first launches of this shape)
+    if (rc) return rc;
+    HIP_TRY(c, hipEventRecord(e0, c->stream));
+    rc = batch_run(b, iterations);
+    if (rc) return rc;
+    HIP_TRY(c, hipEventRecord(e1, c->stream));
+    HIP_TRY(c, hipEventSynchronize(e1));
+    float t = 0.0f;
+    HIP_TRY(c, hipEventElapsedTime(&t, e0, e1));
+    if (ms) ms[shape] = t / (float)iterations;
+    if (shape == 0 || t < best_ms) {
+      best = shape;
+      best_ms = t;
     }
+    rc = restore(c, sc);
+    if (rc) return rc;
   }
+  {
+    std::lock_guard<std::mutex> lock(g_tuned_mu);
+    g_tuned[{c->arch, b->hash}] = best;
+  }
+  rc = batch_build(b, best);
+  if (rc) return rc;
+  HIP_TRY(c, hipStreamSynchronize(c->stream));
+  if (best_shape) *best_shape = best;
+  return JSO_OK;
+}
+
+int jso_set_tile_shape(jso_ctx* c, int shape) {
+  if (!c) return JSO_E_INVALID;
+  if (shape < 0 || shape >= kShapes) return fail(c, JSO_E_INVALID, "tile shape %d", shape);
+  c->tile_shape = shape;
   return JSO_OK;
 }
 

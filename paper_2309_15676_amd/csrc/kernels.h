@@ -86,7 +86,7 @@ struct FwdArgs {
   JSO_GMEM double* slots;
   uint32_t npix;
   uint32_t flags;
-  uint32_t tiles_x, tiles;  // kTile x kTile tiles of the crop: per row, per slice
+  uint32_t tiles_x, tiles;  // tiles of the crop (launch's tile shape): per row, per slice
 };
 
 // One primal image of k_finalize: n slots of this launch summed per pixel,
@@ -185,11 +185,12 @@ hipError_t launch_philox(const uint32_t* ctr, size_t n, uint64_t key, uint32_t* 
 // Unit arrays U[n] in device memory; `blocks` = the total grid size.
 // work (nullable): forward [2] += paths traced, [3] += surface vertices;
 // adjoint [0] += paths replayed, [1] += surface vertices.
-hipError_t launch_forward(const FwdArgs* U, int n, uint32_t blocks, unsigned long long* work,
-                          hipStream_t st);
+// shape: index into kShapeW / kShapeH (the tiles the units were built for)
+hipError_t launch_forward(const FwdArgs* U, int n, uint32_t blocks, int shape,
+                          unsigned long long* work, hipStream_t st);
 hipError_t launch_finalize(const FinArgs* U, int n, uint32_t blocks, hipStream_t st);
 // lds: dynamic LDS bytes (adjoint_lds_bytes of the largest channel count)
-hipError_t launch_adjoint(const RepArgs* U, int n, uint32_t blocks, size_t lds,
+hipError_t launch_adjoint(const RepArgs* U, int n, uint32_t blocks, int shape, size_t lds,
                           unsigned long long* work, hipStream_t st);
 hipError_t launch_meta(const MetaArgs* U, int n, uint32_t blocks, hipStream_t st);
 hipError_t launch_adam(const AdamArgs* U, int n, uint32_t blocks, hipStream_t st);
@@ -197,7 +198,11 @@ hipError_t launch_fill_f64(double* p, size_t n, double v, hipStream_t st);
 hipError_t launch_fill_f32(float* p, size_t n, float v, hipStream_t st);
 
 // Grid geometry the host needs to build units.
-constexpr int kTile = 16;        // path kernels: kTile x kTile pixel tiles
+// Pixel tiles of the path kernels (one block = one tile): 16x16 (256 lanes),
+// 16x8 (128) and 8x8 (64), chosen per plan.
+constexpr int kShapes = 3;
+constexpr int kShapeW[kShapes] = {16, 16, 8};
+constexpr int kShapeH[kShapes] = {16, 8, 8};
 constexpr int kFinBlock = 256;   // k_finalize threads per block
 constexpr int kFinMaxBlocks = 256;
 constexpr int kMetaBlock = 256;  // k_meta / k_adam threads per block

@@ -69,8 +69,13 @@ __device__ __forceinline__ int wave_sum(int v) {
   return v;
 }
 
-// Blocks are kTile x kTile pixel tiles (256 lanes = four wave64 rows of 16 x 4).
-constexpr int kBlock = kTile * kTile;
+// A block is one TW x TH pixel tile (lane = y * TW + x; 16 x 16 = four
+// wave64 rows of 16 x 4).
+template <int TW, int TH>
+struct Shape {
+  static constexpr int W = TW, H = TH, N = TW * TH, WAVES = N / 64;
+  static_assert(N % 64 == 0 && (TW & (TW - 1)) == 0, "tile shape");
+};
 
 // The unit owning this block: the last one whose block0 <= blockIdx.x.
 template <class U>
@@ -90,17 +95,18 @@ struct TileBlock {
   int slice, x0, y0;
 };
 
-template <class U>
+template <class SH, class U>
 __device__ __forceinline__ TileBlock tile_block(const U& u) {
   const uint32_t local = blockIdx.x - u.h.block0;
   const uint32_t t = local % u.tiles;
-  return TileBlock{(int)(local / u.tiles), u.crop.x0 + (int)(t % u.tiles_x) * kTile,
-                   u.crop.y0 + (int)(t / u.tiles_x) * kTile};
+  return TileBlock{(int)(local / u.tiles), u.crop.x0 + (int)(t % u.tiles_x) * SH::W,
+                   u.crop.y0 + (int)(t / u.tiles_x) * SH::H};
 }
 
+template <class SH>
 __device__ __forceinline__ bool tile_pixel(const Crop& c, const TileBlock& tb, int& px, int& py) {
-  px = tb.x0 + (int)(threadIdx.x % kTile);
-  py = tb.y0 + (int)(threadIdx.x / kTile);
+  px = tb.x0 + (int)(threadIdx.x % SH::W);
+  py = tb.y0 + (int)(threadIdx.x / SH::W);
   return px < c.x1 && py < c.y1;
 }
 
@@ -117,28 +123,37 @@ __device__ __forceinline__ bool tile_pixel(const Crop& c, const TileBlock& tb, i
 // identity of the lane it came from (src), so it draws the same random
 // numbers and writes to the same pixel.
 // ---------------------------------------------------------------------------
-constexpr int kXchg = 64;         // paths per exchange round
-constexpr int kCompactMax = 192;  // with more survivors than this, paths finish in place
+constexpr int kXchg = 64;  // paths per exchange round
+// Survivors are packed only when that frees at least one wave (a one-wave
+// block never packs).
+template <class SH>
+constexpr int compact_max() {
+  return SH::N - 64;
+}
 
 // Identity of the paths of one block: tile origin and random stream.
+template <class SH>
 struct BlockPaths {
   uint64_t key;
   uint32_t sample;
   int x0, y0, width;
   uint32_t flags;
   __device__ __forceinline__ uint32_t pixel(int src) const {
-    return (uint32_t)((y0 + src / kTile) * width + (x0 + src % kTile));
+    return (uint32_t)((y0 + src / SH::W) * width + (x0 + src % SH::W));
   }
   __device__ __forceinline__ Rng rng(int src) const { return make_rng(key, pixel(src), sample); }
 };
 
-__device__ __forceinline__ BlockPaths block_paths(const TileBlock& tb, const DevScene& S,
-                                                  uint64_t key, uint32_t sample, uint32_t flags) {
-  return BlockPaths{key, sample, tb.x0, tb.y0, S.width, flags};
+template <class SH>
+__device__ __forceinline__ BlockPaths<SH> block_paths(const TileBlock& tb, const DevScene& S,
+                                                      uint64_t key, uint32_t sample,
+                                                      uint32_t flags) {
+  return BlockPaths<SH>{key, sample, tb.x0, tb.y0, S.width, flags};
 }
 
 // Rank of this lane among the lanes of the block with `flag` set, and their
 // number (block-uniform).  Every lane of the block must call it.
+template <class SH>
 __device__ __forceinline__ int block_rank(bool flag, int& total, int* s_cnt) {
   const uint64_t m = __ballot(flag);
   const int lane = (int)__lane_id(), wv = (int)threadIdx.x >> 6;
@@ -147,7 +162,7 @@ __device__ __forceinline__ int block_rank(bool flag, int& total, int* s_cnt) {
   __syncthreads();
   int off = 0, tot = 0;
 #pragma unroll
-  for (int w = 0; w < kBlock / 64; ++w) {
+  for (int w = 0; w < SH::WAVES; ++w) {
     const int c = s_cnt[w];
     off += w < wv ? c : 0;
     tot += c;
@@ -219,18 +234,19 @@ constexpr int kFwdXchgWords = (int)(sizeof(FwdItem) / 4);
 // ---------------------------------------------------------------------------
 // The kernel bodies take the scene through a restrict-qualified parameter:
 // nothing the kernels write aliases it, so its fields stay in registers.
+template <class SH>
 __device__ __forceinline__ void forward_tile(const FwdArgs& A, const DevScene* __restrict__ Sp,
                                              uint32_t iter, uint32_t* s_xchg, int* s_cnt,
                                              unsigned long long* work) {
   const DevScene& S = *Sp;
-  const TileBlock tb = tile_block(A);
+  const TileBlock tb = tile_block<SH>(A);
   const FwdSlice& sl = A.sl[tb.slice];
   int px, py;
-  const bool inside = tile_pixel(A.crop, tb, px, py);
+  const bool inside = tile_pixel<SH>(A.crop, tb, px, py);
   const uint32_t pix = (uint32_t)(py * S.width + px);
   const bool active = inside && !(G(A.mask) && G(A.mask)[pix]);
   const uint64_t key = stream_key(A.key.seed, iter, sl.tag);
-  const BlockPaths B = block_paths(tb, S, key, sl.sample, A.flags);
+  const BlockPaths<SH> B = block_paths<SH>(tb, S, key, sl.sample, A.flags);
   double* out = G(A.slots) + (size_t)sl.slot * A.npix * 3;
   const float zero[3] = {0.0f, 0.0f, 0.0f};
   VertexGrad vg;
@@ -247,9 +263,9 @@ __device__ __forceinline__ void forward_tile(const FwdArgs& A, const DevScene* _
     if (!P.alive) store_radiance(out, pix, P.led);
   }
   int n;
-  const int r = block_rank(P.alive, n, s_cnt);
+  const int r = block_rank<SH>(P.alive, n, s_cnt);
   FwdItem W;
-  if (n > kCompactMax) {
+  if (n > compact_max<SH>()) {
     W.P = P;
     W.src = (int)threadIdx.x;
   } else {
@@ -272,14 +288,16 @@ __device__ __forceinline__ void forward_tile(const FwdArgs& A, const DevScene* _
   count_work(work ? work + 2 : nullptr, active ? 1 : 0, n_vert);
 }
 
-__global__ void __launch_bounds__(kBlock) __attribute__((amdgpu_waves_per_eu(4)))
+template <int TW, int TH>
+__global__ void __launch_bounds__(TW * TH) __attribute__((amdgpu_waves_per_eu(4)))
 k_forward(const FwdArgs* __restrict__ Units, int n_units, unsigned long long* work) {
+  using SH = Shape<TW, TH>;
   __shared__ uint32_t s_xchg[kFwdXchgWords * kXchg];
-  __shared__ int s_cnt[kBlock / 64];
+  __shared__ int s_cnt[SH::WAVES];
   const FwdArgs& A = unit_of(Units, n_units);
   const uint32_t iter = iteration_of(A.key);
   if (A.h.max_iter && iter >= A.h.max_iter) return;  // finished problem
-  forward_tile(A, G(A.scene), iter, s_xchg, s_cnt, work);
+  forward_tile<SH>(A, G(A.scene), iter, s_xchg, s_cnt, work);
 }
 
 // ---------------------------------------------------------------------------
@@ -495,11 +513,11 @@ struct Sink {
     scatter_texels(S, T, v.fp, v.g, sign);
     return false;
   }
-  // every lane of the block, after a barrier; neighbouring lanes flush
-  // neighbouring channels of one texel
-  __device__ __forceinline__ void flush_table(const DevScene& S) {
+  // every lane of the block (nthreads), after a barrier; neighbouring lanes
+  // flush neighbouring channels of one texel
+  __device__ __forceinline__ void flush_table(const DevScene& S, int nthreads) {
     const int nc = S.n_ch;
-    for (int i = threadIdx.x; i < kTableSize * nc; i += kBlock) {
+    for (int i = threadIdx.x; i < kTableSize * nc; i += nthreads) {
       const int slot = i / nc;
       const int c = i - slot * nc;
       const uint32_t k = T.keys[slot];
@@ -544,31 +562,32 @@ __device__ __forceinline__ void replay_begin(const DevScene& S, const Rng& rng, 
   for (int k = 0; k < 3; ++k) P.led[k] = C[k] - P.led[k];
 }
 
-// One block = one kTile x kTile pixel tile of one slice.  Each path is
+// One block = one pixel tile of one slice.  Each path is
 // replayed vertex by vertex from its forward radiance: first vertices in place
 // (their gradients go to the block table, flushed right after), later ones on
 // the compacted lanes in a wave-uniform loop, so the later-vertex scatter can
 // use the whole wave.  The exchange buffer reuses the table's LDS.
+template <class SH>
 __device__ __forceinline__ void adjoint_tile(const RepArgs& A, const DevScene* __restrict__ Sp,
                                              uint32_t iter, uint32_t* s_dyn, int* s_cnt,
                                              unsigned long long* work) {
   const DevScene& S = *Sp;
   uint32_t* s_keys = s_dyn;
   float* s_vals = reinterpret_cast<float*>(s_dyn + kTableSize);
-  const TileBlock tb = tile_block(A);
+  const TileBlock tb = tile_block<SH>(A);
   const RepSlice& sl = A.sl[tb.slice];
   const bool pair = G(sl.params_b) != nullptr;  // uniform over the block
   int px, py;
-  const bool inside = tile_pixel(A.crop, tb, px, py);
+  const bool inside = tile_pixel<SH>(A.crop, tb, px, py);
   const uint32_t pix = (uint32_t)(py * S.width + px);
   const bool active = inside && !(G(A.mask) && G(A.mask)[pix]);
-  for (int i = threadIdx.x; i < kTableSize; i += kBlock) s_keys[i] = kEmpty;
-  for (int i = threadIdx.x; i < kTableSize * S.n_ch; i += kBlock) s_vals[i] = 0.0f;
+  for (int i = threadIdx.x; i < kTableSize; i += SH::N) s_keys[i] = kEmpty;
+  for (int i = threadIdx.x; i < kTableSize * S.n_ch; i += SH::N) s_vals[i] = 0.0f;
   __syncthreads();
   Sink sink;
   sink.init(GradTable{s_keys, s_vals, G(sl.grad)});
   const uint64_t key = stream_key(A.key.seed, iter, sl.tag);
-  const BlockPaths B = block_paths(tb, S, key, sl.sample, A.flags);
+  const BlockPaths<SH> B = block_paths<SH>(tb, S, key, sl.sample, A.flags);
   const Rng rng = B.rng((int)threadIdx.x);
   const int tid = (int)threadIdx.x;
   float adj_a[3] = {0.0f, 0.0f, 0.0f}, adj_b[3] = {0.0f, 0.0f, 0.0f};
@@ -609,15 +628,15 @@ __device__ __forceinline__ void adjoint_tile(const RepArgs& A, const DevScene* _
     sink.add(S, vb, -1.0f);
   }
   __syncthreads();
-  sink.flush_table(S);
+  sink.flush_table(S, SH::N);
   const int paths = active ? (pair ? 2 : 1) : 0;
   const bool live = Pa.alive || Pb.alive;
   int n;
-  const int r = block_rank(live, n, s_cnt);  // its barriers also retire the table
+  const int r = block_rank<SH>(live, n, s_cnt);  // its barriers also retire the table
   uint32_t* xbuf = s_dyn;
   if (!pair) {
     RepItem W;
-    if (n > kCompactMax) {
+    if (n > compact_max<SH>()) {
       W.P = Pa;
       W.src = tid;
 #pragma unroll
@@ -648,7 +667,7 @@ __device__ __forceinline__ void adjoint_tile(const RepArgs& A, const DevScene* _
     }
   } else {
     RepPairItem W;
-    if (n > kCompactMax) {
+    if (n > compact_max<SH>()) {
       W.Pa = Pa;
       W.Pb = Pb;
       W.src = tid;
@@ -702,14 +721,16 @@ __device__ __forceinline__ void adjoint_tile(const RepArgs& A, const DevScene* _
   count_work(work, paths, n_vert);
 }
 
-__global__ void __launch_bounds__(kBlock) __attribute__((amdgpu_waves_per_eu(3)))
+template <int TW, int TH>
+__global__ void __launch_bounds__(TW * TH) __attribute__((amdgpu_waves_per_eu(3)))
 k_adjoint(const RepArgs* __restrict__ Units, int n_units, unsigned long long* work) {
+  using SH = Shape<TW, TH>;
   extern __shared__ uint32_t s_dyn[];
-  __shared__ int s_cnt[kBlock / 64];
+  __shared__ int s_cnt[SH::WAVES];
   const RepArgs& A = unit_of(Units, n_units);
   const uint32_t iter = iteration_of(A.key);
   if (A.h.max_iter && iter >= A.h.max_iter) return;  // finished problem
-  adjoint_tile(A, G(A.scene), iter, s_dyn, s_cnt, work);
+  adjoint_tile<SH>(A, G(A.scene), iter, s_dyn, s_cnt, work);
 }
 
 // ---------------------------------------------------------------------------
@@ -902,10 +923,15 @@ hipError_t launch_philox(const uint32_t* ctr, size_t n, uint64_t key, uint32_t* 
   return hipGetLastError();
 }
 
-hipError_t launch_forward(const FwdArgs* U, int n, uint32_t blocks, unsigned long long* work,
-                          hipStream_t st) {
+hipError_t launch_forward(const FwdArgs* U, int n, uint32_t blocks, int shape,
+                          unsigned long long* work, hipStream_t st) {
   if (n <= 0 || blocks == 0) return hipSuccess;
-  hipLaunchKernelGGL(k_forward, dim3(blocks), dim3(kBlock), 0, st, U, n, work);
+  switch (shape) {
+    case 0: hipLaunchKernelGGL((k_forward<16, 16>), dim3(blocks), dim3(256), 0, st, U, n, work); break;
+    case 1: hipLaunchKernelGGL((k_forward<16, 8>), dim3(blocks), dim3(128), 0, st, U, n, work); break;
+    case 2: hipLaunchKernelGGL((k_forward<8, 8>), dim3(blocks), dim3(64), 0, st, U, n, work); break;
+    default: return hipErrorInvalidValue;
+  }
   return hipGetLastError();
 }
 
@@ -921,11 +947,16 @@ size_t adjoint_lds_bytes(int n_ch) {
   return table > xchg ? table : xchg;
 }
 
-hipError_t launch_adjoint(const RepArgs* U, int n, uint32_t blocks, size_t lds,
+hipError_t launch_adjoint(const RepArgs* U, int n, uint32_t blocks, int shape, size_t lds,
                           unsigned long long* work, hipStream_t st) {
   if (n <= 0 || blocks == 0) return hipSuccess;
   if (lds < adjoint_lds_bytes(0) || lds > adjoint_lds_bytes(5)) return hipErrorInvalidValue;
-  hipLaunchKernelGGL(k_adjoint, dim3(blocks), dim3(kBlock), lds, st, U, n, work);
+  switch (shape) {
+    case 0: hipLaunchKernelGGL((k_adjoint<16, 16>), dim3(blocks), dim3(256), lds, st, U, n, work); break;
+    case 1: hipLaunchKernelGGL((k_adjoint<16, 8>), dim3(blocks), dim3(128), lds, st, U, n, work); break;
+    case 2: hipLaunchKernelGGL((k_adjoint<8, 8>), dim3(blocks), dim3(64), lds, st, U, n, work); break;
+    default: return hipErrorInvalidValue;
+  }
   return hipGetLastError();
 }
 

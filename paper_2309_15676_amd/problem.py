@@ -187,6 +187,10 @@ class Batch:
     def active(self) -> int:
         return L.jso_batch_active(self.context.bind(), self.batch)
 
+    def autotune(self, iterations: int = 3):
+        """Pick the fastest tile shape for this batch; returns (shape, ms per shape)."""
+        return L.jso_batch_autotune(self.context.bind(), self.batch, iterations)
+
     def close(self) -> None:
         if self.batch:
             L.jso_batch_destroy(self.batch)

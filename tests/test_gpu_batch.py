@@ -112,3 +112,55 @@ def test_batch_matches_grad_step_and_stops_at_its_limit(ctx, use_graph):
             _close_states(sb, sr, "graph=%s problem %d after %d" % (use_graph, k, it + 1))
     assert b.active() == 1
     b.close()
+
+
+@pytest.mark.parametrize("shape", [1, 2])
+def test_tile_shapes_agree(ctx, shape):
+    """Every path is traced and replayed identically whatever the tile shape:
+    the image is bit-identical and the gradient equal up to atomic order."""
+    import torch
+    from paper_2309_15676_amd import _lib as L
+    _say("tile shape", shape)
+    probs = _make(ctx)
+    try:
+        for p, (spec, gt, init) in zip(probs, _specs()):
+            dimg = torch.from_numpy(I.target_image_synthetic(spec, 5) - 0.7).cuda()
+            L.jso_set_tile_shape(ctx.bind(), 0)
+            img0 = p.render(init, seed=3, iteration=1, tag=L.JSO_TAG_EVAL, spp=2)
+            g0 = p.render_bwd(init, dimg, seed=3, iteration=1, tag=L.JSO_TAG_EVAL, spp=2)
+            L.jso_set_tile_shape(ctx.bind(), shape)
+            img1 = p.render(init, seed=3, iteration=1, tag=L.JSO_TAG_EVAL, spp=2)
+            g1 = p.render_bwd(init, dimg, seed=3, iteration=1, tag=L.JSO_TAG_EVAL, spp=2)
+            assert torch.equal(img0, img1)
+            scale = float(g0.abs().max())
+            assert float((g1 - g0).abs().max()) <= 1e-5 * scale
+    finally:
+        L.jso_set_tile_shape(ctx.bind(), 0)
+
+
+def test_autotune_restores_state_and_picks_a_shape(ctx):
+    import torch
+    from paper_2309_15676_amd import _lib as L
+    from paper_2309_15676_amd.problem import Batch, grad_step_many
+    _say("autotune")
+    opts = L.step_opts(optimizer=L.JSO_OPT_META, eta=0.02, seed=8)
+    probs, ref = _make(ctx), _make(ctx)
+    b = Batch(probs, opts, use_graph=True)
+    b.step(2)
+    grad_step_many(ref, opts)
+    grad_step_many(ref, opts)
+    before = [p.get_state() for p in probs]
+    best, ms = b.autotune(2)
+    assert best in (0, 1, 2) and all(m > 0 for m in ms), (best, ms)
+    for p, st in zip(probs, before):
+        after = p.get_state()
+        for key in ("params", "params_prev", "mean", "var", "m2_F", "m2_D", "alpha_prev"):
+            assert np.array_equal(after[key], st[key]), key
+        assert after["iteration"] == st["iteration"]
+    # the tuned batch keeps optimising like the reference
+    b.step(1)
+    torch.cuda.synchronize()
+    grad_step_many(ref, opts)
+    for k in range(len(probs)):
+        _close_states(probs[k].get_state(), ref[k].get_state(), "after autotune %d" % k)
+    b.close()
