@@ -65,6 +65,9 @@ class _Scene(ctypes.Structure):
         ("tex_w", ctypes.c_int), ("tex_h", ctypes.c_int), ("ch_mask", ctypes.c_int),
         ("fixed_default", ctypes.c_double * 5),
         ("n_fixed", ctypes.c_int), ("fixed_mats", ctypes.POINTER(ctypes.c_double)),
+        ("n_verts", ctypes.c_int), ("n_tris", ctypes.c_int),
+        ("verts", ctypes.POINTER(ctypes.c_double)), ("tris", ctypes.POINTER(ctypes.c_int)),
+        ("mesh_mat", ctypes.c_int), ("param_layout", ctypes.c_int),
     ]
 
 
@@ -113,8 +116,8 @@ class _Marshalled:
         self.spheres = np.ascontiguousarray(_f32(spec.spheres).reshape(-1, 4))
         self.sphere_mat = np.ascontiguousarray(np.asarray(spec.sphere_mat, np.int32).reshape(-1))
         self.fixed = np.ascontiguousarray(_f32(spec.fixed_mats).reshape(-1, 5))
-        if len(getattr(spec, "tris", ())) > 0:
-            raise NotImplementedError("oracle: triangle meshes are not supported")
+        self.verts = np.ascontiguousarray(_f32(spec.verts).reshape(-1, 3))
+        self.tris = np.ascontiguousarray(np.asarray(spec.tris, np.int32).reshape(-1, 3))
         s = _Scene()
         s.width, s.height = spec.width, spec.height
         s.cam_eye[:] = _f32(spec.cam_eye)
@@ -139,6 +142,11 @@ class _Marshalled:
         s.fixed_default[:] = _f32(spec.fixed_default)
         s.n_fixed = self.fixed.shape[0]
         s.fixed_mats = self.fixed.ctypes.data_as(ctypes.POINTER(ctypes.c_double))
+        s.n_verts, s.n_tris = self.verts.shape[0], self.tris.shape[0]
+        s.verts = self.verts.ctypes.data_as(ctypes.POINTER(ctypes.c_double))
+        s.tris = self.tris.ctypes.data_as(ctypes.POINTER(ctypes.c_int))
+        s.mesh_mat = int(spec.mesh_mat)
+        s.param_layout = int(getattr(spec, "param_layout", 0))
         self.s = s
 
     def ptr(self):

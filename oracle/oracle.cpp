@@ -102,12 +102,13 @@ struct Ray {
   V3 o, d;
 };
 
-enum Kind { K_NONE = 0, K_PLANE, K_SPHERE, K_LIGHT };
+enum Kind { K_NONE = 0, K_PLANE, K_SPHERE, K_LIGHT, K_MESH };
 
 struct Hit {
   Kind kind = K_NONE;
-  int obj = -1;
+  int obj = -1;             // sphere or triangle index
   double t = INF;
+  double bu = 0, bv = 0;    // triangle: barycentrics of vertices 1 and 2
   V3 p{0, 0, 0}, n{0, 0, 0};
 };
 
@@ -186,6 +187,41 @@ struct Scene {
     return c;
   }
 
+  V3 vert(int i) const { return from(s->verts + 3 * (size_t)i); }
+
+  // Moller-Trumbore.  Margin: the barycentric distance to the nearest edge
+  // (which decides hit or miss), or, for a triangle behind the origin, how far
+  // behind it lies in units of the ray offset.
+  Cand triangle(int k, const Ray& r, double* bu, double* bv) const {
+    Cand c;
+    const int* tr = s->tris + 3 * (size_t)k;
+    const V3 v0 = vert(tr[0]), e1 = vert(tr[1]) - v0, e2 = vert(tr[2]) - v0;
+    const V3 pv = cross(r.d, e2);
+    const double det = dot(e1, pv);
+    if (det == 0.0) return c;
+    const double inv = 1.0 / det;
+    const V3 sv = r.o - v0;
+    const double u = dot(sv, pv) * inv;
+    const V3 qv = cross(sv, e1);
+    const double v = dot(r.d, qv) * inv;
+    const double t = dot(e2, qv) * inv;
+    const double bm = std::min(std::min(std::fabs(u), std::fabs(v)), std::fabs(1.0 - u - v));
+    if (!(t > 0.0)) {
+      if (u >= 0 && v >= 0 && u + v <= 1) {
+        c.margin = std::fabs(t) / RAY_EPS;
+        c.t_near = 0.0;
+      }
+      return c;
+    }
+    c.margin = bm;
+    c.t_near = t;
+    if (u < 0 || v < 0 || u + v > 1) return c;
+    c.t = t;
+    *bu = u;
+    *bv = v;
+    return c;
+  }
+
   Cand light(const Ray& r) const {
     Cand c;
     if (!s->light_enabled) return c;
@@ -206,6 +242,7 @@ struct Scene {
   // Margins: the winner's own decision, every near miss that would land in
   // front of the winner, and the gap to the runner-up.
   Hit intersect(const Ray& r, Margin& mg) const {
+    const Margin mg_in = mg;
     Hit h;
     const int n = s->n_spheres;
     std::vector<Cand> cs;
@@ -228,8 +265,60 @@ struct Scene {
       if (cs[i].t < second) second = cs[i].t;
       if (cs[i].t == INF && cs[i].t_near < h.t) mg.add(cs[i].margin);
     }
-    if (best < 0) return h;
+    // mesh triangles rank after the spheres and before the light
+    int best_tri = -1;
+    double tri_t = INF, tbu = 0, tbv = 0;
+    if (s->n_tris > 0) {
+      const double t_analytic = best >= 0 && best < (int)cs.size() - 1 ? h.t : INF;
+      for (int k = 0; k < s->n_tris; ++k) {
+        double bu, bv;
+        const Cand c = triangle(k, r, &bu, &bv);
+        if (c.t < tri_t) {
+          tri_t = c.t;
+          best_tri = k;
+          tbu = bu;
+          tbv = bv;
+        }
+      }
+      const double t_light = best == (int)cs.size() - 1 ? h.t : INF;
+      if (best_tri >= 0 && tri_t < t_analytic && !(t_light < tri_t)) {
+        // the mesh wins: redo the margins of the analytic candidates
+        mg = Margin{mg_in.m};
+        h.t = tri_t;
+        second = INF;
+        for (int i = 0; i < (int)cs.size(); ++i) {
+          if (cs[i].t < second) second = cs[i].t;
+          if (cs[i].t == INF && cs[i].t_near < h.t) mg.add(cs[i].margin);
+        }
+        best = -2;
+      }
+      for (int k = 0; k < s->n_tris; ++k) {
+        double bu, bv;
+        const Cand c = triangle(k, r, &bu, &bv);
+        if (best == -2 && k == best_tri) {
+          mg.add(c.margin);
+          continue;
+        }
+        if (c.t < second) second = c.t;
+        if (c.t == INF && c.t_near < h.t) mg.add(c.margin);
+      }
+    }
+    if (best == -1) return h;
     if (second < INF) mg.add((second - h.t) / h.t);
+    if (best == -2) {
+      h.kind = K_MESH;
+      h.obj = best_tri;
+      h.bu = tbu;
+      h.bv = tbv;
+      h.p = r.o + r.d * h.t;
+      const int* tr = s->tris + 3 * (size_t)best_tri;
+      const V3 v0 = vert(tr[0]);
+      const V3 ng = normalize(cross(vert(tr[1]) - v0, vert(tr[2]) - v0));
+      const double dn = dot(ng, r.d);
+      mg.add(dn);  // which side faces the ray
+      h.n = dn < 0 ? ng : ng * -1.0;
+      return h;
+    }
     if (best == 0) {
       h.kind = K_PLANE;
       h.obj = 0;
@@ -268,6 +357,10 @@ struct Scene {
     };
     one(plane(r));
     for (int k = 0; k < s->n_spheres; ++k) one(sphere(k, r));
+    for (int k = 0; k < s->n_tris; ++k) {
+      double bu, bv;
+      one(triangle(k, r, &bu, &bv));
+    }
     return occ;
   }
 };
@@ -317,7 +410,7 @@ Footprint bilinear(const orc_scene* s, double u, double v, Margin& mg) {
 
 Material material_at(const Scene& sc, const Hit& h, const double* params, Margin& mg) {
   const orc_scene* s = sc.s;
-  int mat = h.kind == K_PLANE ? s->plane_mat : s->sphere_mat[h.obj];
+  int mat = h.kind == K_PLANE ? s->plane_mat : (h.kind == K_MESH ? s->mesh_mat : s->sphere_mat[h.obj]);
   Material m;
   if (mat >= 0) {
     const double* f = s->fixed_mats + 5 * mat;
@@ -327,7 +420,18 @@ Material material_at(const Scene& sc, const Hit& h, const double* params, Margin
     return m;
   }
   double u, v;
-  if (h.kind == K_PLANE) {
+  if (h.kind == K_MESH && s->param_layout == 1) {
+    // per-vertex parameters, interpolated barycentrically
+    const int* tr = s->tris + 3 * (size_t)h.obj;
+    m.param = true;
+    m.fp.n = 3;
+    m.fp.texel[0] = tr[0];
+    m.fp.w[0] = 1.0 - h.bu - h.bv;
+    m.fp.texel[1] = tr[1];
+    m.fp.w[1] = h.bu;
+    m.fp.texel[2] = tr[2];
+    m.fp.w[2] = h.bv;
+  } else if (h.kind == K_PLANE || h.kind == K_MESH) {
     u = (h.p.x - s->plane_extent[0]) / (s->plane_extent[1] - s->plane_extent[0]);
     v = (h.p.z - s->plane_extent[2]) / (s->plane_extent[3] - s->plane_extent[2]);
   } else {
@@ -337,8 +441,10 @@ Material material_at(const Scene& sc, const Hit& h, const double* params, Margin
     u = 0.5 + std::atan2(n.z, n.x) / (2 * PI);
     v = std::atan2(std::sqrt(n.x * n.x + n.z * n.z), n.y) / PI;
   }
-  m.param = true;
-  m.fp = bilinear(s, u, v, mg);
+  if (!m.param) {
+    m.param = true;
+    m.fp = bilinear(s, u, v, mg);
+  }
   double val[5];
   for (int b = 0; b < 5; ++b) {
     if (sc.ch_slot[b] < 0) {
@@ -661,7 +767,11 @@ PathRng make_rng(uint64_t key, uint32_t pixel, uint32_t sample) {
   return r;
 }
 
-size_t n_params(const Scene& sc) { return (size_t)sc.s->tex_w * sc.s->tex_h * sc.n_ch; }
+size_t n_params(const Scene& sc) {
+  const size_t elems = sc.s->param_layout == 1 ? (size_t)sc.s->n_verts
+                                               : (size_t)sc.s->tex_w * sc.s->tex_h;
+  return elems * sc.n_ch;
+}
 
 // Run fn(row, thread) over crop rows, one contiguous band of rows per thread.
 template <class Fn>
@@ -683,6 +793,18 @@ int check(const orc_scene* s) {
   if (!s || s->width <= 0 || s->height <= 0 || s->depth < 1 || s->tex_w < 1 || s->tex_h < 1)
     return -1;
   if ((s->ch_mask & ~31) != 0 || s->ch_mask == 0) return -1;
+  if (s->n_tris < 0 || s->n_verts < 0 || (s->n_tris > 0 && (!s->tris || !s->verts))) return -1;
+  for (long k = 0; k < 3L * s->n_tris; ++k)
+    if (s->tris[k] < 0 || s->tris[k] >= s->n_verts) return -1;
+  if (s->param_layout == 1) {
+    // only the mesh may carry per-vertex parameters
+    if (s->n_tris == 0 || s->mesh_mat != -1) return -1;
+    if (s->plane_enabled && s->plane_mat < 0) return -1;
+    for (int k = 0; k < s->n_spheres; ++k)
+      if (s->sphere_mat[k] < 0) return -1;
+  } else if (s->param_layout != 0) {
+    return -1;
+  }
   return 0;
 }
 

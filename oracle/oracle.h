@@ -10,7 +10,8 @@
  * What it computes (all in double precision):
  *   - the counter-based Philox4x32-10 generator (Salmon et al., SC'11) and the
  *     SplitMix64 mixer (Steele, Lea, Flood, OOPSLA'14) that keys it;
- *   - a path tracer for the synthetic scenes (analytic sphere/plane, square
+ *   - a path tracer for the synthetic scenes (analytic sphere/plane, a
+ *     triangle mesh intersected by brute force over every triangle, square
  *     area light, uniform environment, metallic-roughness GGX + Lambert);
  *   - the proportional gradient sample <F_i> of Eq. 2 (Section 3, Notation)
  *     for an L2 image loss, with the derivative taken by recording each
@@ -46,6 +47,13 @@ typedef struct {
   double fixed_default[5];           /* non-parameter channels of the param mat */
   int n_fixed;
   const double* fixed_mats;          /* [n_fixed][5]: R, G, B, metal, rough    */
+  /* triangle mesh (optional): two-sided, geometric normals */
+  int n_verts, n_tris;
+  const double* verts;               /* [n_verts][3]                           */
+  const int* tris;                   /* [n_tris][3] vertex indices             */
+  int mesh_mat;                      /* -1 = parameterised, else fixed k       */
+  int param_layout;                  /* 0: texture (mesh: planar UV over the plane
+                                        extent); 1: per mesh vertex            */
 } orc_scene;
 
 /* debug / test-mode flags */

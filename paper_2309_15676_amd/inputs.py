@@ -16,7 +16,11 @@ optimisation experiment ("Texture optimisation" paragraph).
 Parameter layout (shared contract): a parameterised material is a texture of
 ``tex_h x tex_w`` texels, texel-interleaved, each texel holding the enabled
 channels of (R, G, B, metalness, roughness) in that order, so parameter
-``(y * tex_w + x) * n_ch + c``.  A 1x1 texture is a "global" material.
+``(y * tex_w + x) * n_ch + c``.  A 1x1 texture is a "global" material.  The
+plane and a triangle mesh map the texture by planar UV over the plane's
+extent; spheres by latitude-longitude.  With ``param_layout = LAYOUT_VERTEX``
+the parameters belong to the mesh vertices instead (``v * n_ch + c``),
+interpolated barycentrically; only the mesh may then be parameterised.
 """
 from __future__ import annotations
 
@@ -37,6 +41,8 @@ CHANNEL_BOUNDS = {CH_R: (0.0, 1.0), CH_G: (0.0, 1.0), CH_B: (0.0, 1.0),
                   CH_M: (0.0, 1.0), CH_ROUGH: (ROUGH_MIN, 1.0)}
 
 MAT_PARAM = -1  # object uses the parameterised (textured / global) material
+
+LAYOUT_TEXTURE, LAYOUT_VERTEX = 0, 1
 
 
 @dataclasses.dataclass
@@ -71,14 +77,22 @@ class SceneSpec:
     verts: np.ndarray = dataclasses.field(default_factory=lambda: np.zeros((0, 3)))
     tris: np.ndarray = dataclasses.field(default_factory=lambda: np.zeros((0, 3), np.int32))
     mesh_mat: int = MAT_PARAM
+    param_layout: int = LAYOUT_TEXTURE
 
     @property
     def n_ch(self) -> int:
         return bin(self.ch_mask).count("1")
 
     @property
+    def n_elems(self) -> int:
+        """Texels, or mesh vertices in the per-vertex layout."""
+        if self.param_layout == LAYOUT_VERTEX:
+            return int(np.asarray(self.verts).reshape(-1, 3).shape[0])
+        return self.tex_w * self.tex_h
+
+    @property
     def n_params(self) -> int:
-        return self.tex_w * self.tex_h * self.n_ch
+        return self.n_elems * self.n_ch
 
     @property
     def n_pixels(self) -> int:
@@ -92,7 +106,7 @@ class SceneSpec:
         bits = self.channel_bits()
         lo = np.array([CHANNEL_BOUNDS[b][0] for b in bits], np.float32)
         hi = np.array([CHANNEL_BOUNDS[b][1] for b in bits], np.float32)
-        n = self.tex_w * self.tex_h
+        n = self.n_elems
         return np.tile(lo, n), np.tile(hi, n)
 
 
@@ -212,6 +226,97 @@ def config_textured(seed_scene: int = 0, seed_gt: int = 1, seed_init: int = 2,
     ground truth = random-Fourier textures; initial texels ~U[0.2,0.8]."""
     s = scene_textured(width, height, tex, seed_scene)
     return s, fourier_params(s, seed_gt), uniform_params(s, seed_init, 0.2, 0.8)
+
+
+# ----------------------------------------------------------------------------
+# triangle meshes
+# ----------------------------------------------------------------------------
+def smooth_field_3d(p: np.ndarray, g: np.random.Generator, n_terms: int = 8) -> np.ndarray:
+    """The random-Fourier family in 3-D: tanh(sum_k a_k sin(2 pi f_k . p + phi_k)),
+    a_k ~ N(0, 0.5^2), integer f_k in {1..3}^3, phi_k ~ U[0, 2 pi); values in (-1, 1)."""
+    a = g.normal(0.0, 0.5, n_terms)
+    f = g.integers(1, 4, size=(n_terms, 3))
+    phi = g.uniform(0.0, 2 * math.pi, n_terms)
+    s = np.zeros(p.shape[0])
+    for k in range(n_terms):
+        s += a[k] * np.sin(2 * math.pi * (p @ f[k]) + phi[k])
+    return np.tanh(s)
+
+
+def icosphere(freq: int, center=(0.0, 1.2, 0.0), radius: float = 1.0, disp: float = 0.1,
+              seed: int = 0):
+    """Geodesic sphere: each icosahedron face split into freq^2 triangles
+    (20 freq^2 triangles, 10 freq^2 + 2 vertices), projected to the sphere and
+    displaced radially by radius * disp * (smooth field of the direction).
+    Triangles wind counter-clockwise seen from outside."""
+    t = (1.0 + math.sqrt(5.0)) / 2.0
+    ico_v = np.array([[-1, t, 0], [1, t, 0], [-1, -t, 0], [1, -t, 0], [0, -1, t], [0, 1, t],
+                      [0, -1, -t], [0, 1, -t], [t, 0, -1], [t, 0, 1], [-t, 0, -1], [-t, 0, 1]],
+                     np.float64)
+    ico_f = [(0, 11, 5), (0, 5, 1), (0, 1, 7), (0, 7, 10), (0, 10, 11), (1, 5, 9), (5, 11, 4),
+             (11, 10, 2), (10, 7, 6), (7, 1, 8), (3, 9, 4), (3, 4, 2), (3, 2, 6), (3, 6, 8),
+             (3, 8, 9), (4, 9, 5), (2, 4, 11), (6, 2, 10), (8, 6, 7), (9, 8, 1)]
+    index = {}
+    verts = []
+
+    def vid(face, a, b):
+        # point a/f along edge (0->1) and b/f along (0->2) of the face; keyed by
+        # its corner weights so points on shared edges are shared
+        c = freq - a - b
+        key = tuple(sorted((ci, w) for ci, w in zip(face, (c, a, b)) if w > 0))
+        if key not in index:
+            index[key] = len(verts)
+            p = sum(w * ico_v[ci] for ci, w in key) / freq
+            verts.append(p / np.linalg.norm(p))
+        return index[key]
+
+    tris = []
+    for face in ico_f:
+        for a in range(freq):
+            for b in range(freq - a):
+                v00, v10, v01 = vid(face, a, b), vid(face, a + 1, b), vid(face, a, b + 1)
+                tris.append((v00, v10, v01))
+                if a + b < freq - 1:
+                    tris.append((v10, vid(face, a + 1, b + 1), v01))
+    d = np.array(verts)
+    r = radius * (1.0 + disp * smooth_field_3d(d, rng(seed)))
+    v = np.asarray(center) + d * r[:, None]
+    return v, np.array(tris, np.int32)
+
+
+def heightfield(n: int, extent=(-5.0, 5.0, -5.0, 5.0), amp: float = 0.4, seed: int = 0):
+    """n x n quads (2 n^2 triangles) over the plane extent, height
+    amp * (1 + smooth field of (x, z) / extent) >= 0."""
+    x0, x1, z0, z1 = extent
+    xs, zs = np.linspace(x0, x1, n + 1), np.linspace(z0, z1, n + 1)
+    X, Z = np.meshgrid(xs, zs)
+    pts = np.stack([(X - x0) / (x1 - x0), np.zeros_like(X), (Z - z0) / (z1 - z0)], -1).reshape(-1, 3)
+    Y = amp * (1.0 + smooth_field_3d(pts, rng(seed)))
+    v = np.stack([X.reshape(-1), Y, Z.reshape(-1)], -1)
+    idx = np.arange((n + 1) * (n + 1)).reshape(n + 1, n + 1)
+    a, b, c, d = idx[:-1, :-1], idx[:-1, 1:], idx[1:, :-1], idx[1:, 1:]
+    tris = np.concatenate([np.stack([a, c, b], -1).reshape(-1, 3),
+                           np.stack([b, c, d], -1).reshape(-1, 3)])
+    return v, tris.astype(np.int32)
+
+
+def vertex_fourier_params(spec: SceneSpec, seed: int, lo: float = 0.1, hi: float = 0.9):
+    """Per-vertex parameters: one smooth field of the vertex position per channel."""
+    g = rng(seed)
+    v = np.asarray(spec.verts).reshape(-1, 3)
+    chans = [lo + (hi - lo) * 0.5 * (1.0 + smooth_field_3d(v * 0.5, g)) for _ in range(spec.n_ch)]
+    return np.stack(chans, -1).reshape(-1).astype(np.float32)
+
+
+def scene_mesh_sphere(width: int = 1024, height: int = 1024, freq: int = 100, seed: int = 0,
+                      depth: int = 8, rr_start: int = 3) -> SceneSpec:
+    """A displaced geodesic sphere (20 freq^2 triangles) on a fixed grey plane,
+    with per-vertex base colour RGB + roughness parameters (metalness 0)."""
+    v, t = icosphere(freq, seed=seed)
+    return SceneSpec(width=width, height=height, plane_mat=0, fixed_mats=PLANE_GREY.copy(),
+                     verts=v, tris=t, mesh_mat=MAT_PARAM, param_layout=LAYOUT_VERTEX,
+                     depth=depth, rr_start=rr_start, ch_mask=CH_RGB_ROUGH,
+                     fixed_default=(0.5, 0.5, 0.5, 0.0, 0.5))
 
 
 def config_batched(n: int = 64, seed: int = 0):
