@@ -189,9 +189,12 @@ struct Scene {
 
   V3 vert(int i) const { return from(s->verts + 3 * (size_t)i); }
 
-  // Moller-Trumbore.  Margin: the barycentric distance to the nearest edge
-  // (which decides hit or miss), or, for a triangle behind the origin, how far
-  // behind it lies in units of the ray offset.
+  // Moller-Trumbore.  Margin of the inside/outside decision in barycentric
+  // units: for a hit, the distance to the nearest edge, min(u, v, 1 - u - v);
+  // for a miss, how far outside the point lies, max(-u, -v, u + v - 1) (every
+  // violated edge would have to flip).  A triangle behind the origin that the
+  // ray's line crosses inside counts how far behind it lies, in units of the
+  // ray offset.
   Cand triangle(int k, const Ray& r, double* bu, double* bv) const {
     Cand c;
     const int* tr = s->tris + 3 * (size_t)k;
@@ -205,17 +208,18 @@ struct Scene {
     const V3 qv = cross(sv, e1);
     const double v = dot(r.d, qv) * inv;
     const double t = dot(e2, qv) * inv;
-    const double bm = std::min(std::min(std::fabs(u), std::fabs(v)), std::fabs(1.0 - u - v));
+    const bool inside = u >= 0 && v >= 0 && u + v <= 1;
     if (!(t > 0.0)) {
-      if (u >= 0 && v >= 0 && u + v <= 1) {
+      if (inside) {
         c.margin = std::fabs(t) / RAY_EPS;
         c.t_near = 0.0;
       }
       return c;
     }
-    c.margin = bm;
+    c.margin = inside ? std::min(std::min(u, v), 1.0 - u - v)
+                      : std::max(std::max(-u, -v), u + v - 1.0);
     c.t_near = t;
-    if (u < 0 || v < 0 || u + v > 1) return c;
+    if (!inside) return c;
     c.t = t;
     *bu = u;
     *bv = v;
@@ -541,9 +545,12 @@ void basis(V3 n, V3& b1, V3& b2) {
 
 // Direction sampling: u[0] picks the lobe (specular if u[0] < P_SPEC), u[1],
 // u[2] place the direction.  GGX half-vectors follow Walter et al. 2007.
-V3 sample_dir(const Material& m, V3 n, V3 wo, const double u[4], int flags, Margin& mg) {
+// The basis flips with the sign of n.z; that is a decision unless the normal
+// is exactly axis-aligned by construction (exact_normal: the plane's).
+V3 sample_dir(const Material& m, V3 n, V3 wo, const double u[4], int flags, Margin& mg,
+              bool exact_normal) {
   V3 b1, b2;
-  if (n.z != 0.0) mg.add(n.z);
+  if (!(exact_normal && n.z == 0.0)) mg.add(n.z);
   basis(n, b1, b2);
   double phi = 2 * PI * u[2];
   bool spec = !(flags & (ORC_LAMBERT_ONLY | ORC_PARAM_INDEP)) && u[0] < P_SPEC;
@@ -660,7 +667,7 @@ void trace(const Scene& sc, const double* params, const PathRng& rng, int px, in
 
     // continuation
     rng.draw(j, 0, u);
-    V3 wi = sample_dir(mat, n, wo, u, flags, mg);
+    V3 wi = sample_dir(mat, n, wo, u, flags, mg, hit.kind == K_PLANE);
     double ci = dot(n, wi);
     mg.add(ci);  // continuous in value, not in which vertices follow
     bool go = ci > 0;

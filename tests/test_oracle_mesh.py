@@ -62,14 +62,16 @@ def test_triangle_fan_replaces_the_plane(which, clockwise):
     for flags in (0, O.NO_NEE):
         a, ma = O.render(spec, p, 4, 2, O.TAG_EVAL, 2, flags)
         b, mb = O.render(mesh, p, 4, 2, O.TAG_EVAL, 2, flags)
-        # both sides are FP64: only decisions within rounding of a boundary may differ
-        ok = np.minimum(ma, mb) > 1e-11
+        # both sides are FP64: only decisions within rounding of a boundary may
+        # differ.  (The fan's margins also count the basis sign at n.z = 0,
+        # which both sides take identically here, so the plane's are used.)
+        ok = ma > 1e-11
         assert ok.mean() > 0.95, (name, ok.mean())
         np.testing.assert_allclose(b[ok], a[ok], rtol=1e-9, atol=1e-12)
     dimg = I.target_image_synthetic(spec, 6).astype(np.float64) - 0.7
     ga_, _, mga, _ = O.render_bwd(spec, p, dimg, 4, 2, O.TAG_EVAL, 2)
     gb_, _, mgb, _ = O.render_bwd(mesh, p, dimg, 4, 2, O.TAG_EVAL, 2)
-    assert np.min(np.minimum(mga, mgb)) > 1e-11, "a decision near its boundary: pick another seed"
+    assert np.min(mga) > 1e-11, "a decision near its boundary: pick another seed"
     scale = np.abs(ga_).max()
     assert scale > 0
     np.testing.assert_allclose(gb_, ga_, rtol=0, atol=1e-9 * scale)
@@ -124,14 +126,14 @@ def test_linear_vertex_field_equals_bilinear_texture():
     ex = st.plane_extent
     vert = np.array([field((p[0] - ex[0]) / (ex[1] - ex[0]), (p[2] - ex[2]) / (ex[3] - ex[2]))
                      for p in v])
-    a, ma = O.render(st, tex.reshape(-1), 2, 0, O.TAG_EVAL, 2)
-    b, mb = O.render(sv, vert.reshape(-1), 2, 0, O.TAG_EVAL, 2)
+    a, _ = O.render(st, tex.reshape(-1), 2, 0, O.TAG_EVAL, 2)
+    b, _ = O.render(sv, vert.reshape(-1), 2, 0, O.TAG_EVAL, 2)
     # most pixels see the mesh
     blank, _ = O.render(sv, np.zeros(sv.n_params) + 0.5, 2, 0, O.TAG_EVAL, 2)
     assert np.mean(np.any(np.abs(b - blank) > 1e-6, -1)) > 0.3
-    ok = np.minimum(ma, mb) > 1e-11
-    assert ok.mean() > 0.95
-    np.testing.assert_allclose(b[ok], a[ok], rtol=1e-10, atol=1e-13)
+    # same geometry on both sides: the paths only see material values that
+    # agree to rounding, so every pixel is compared
+    np.testing.assert_allclose(b, a, rtol=1e-10, atol=1e-13)
 
 
 def test_mesh_shadow_matches_quadrature():
