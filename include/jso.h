@@ -21,8 +21,9 @@
  *   - A context is not thread-safe; use one context per host thread.
  *   - All floating-point images are H x W x 3 (row-major, RGB interleaved,
  *     row 0 at the top).  Parameter vectors use the texel-interleaved layout:
- *     parameter (y * tex_w + x) * n_ch + c, where the c-th channel is the c-th
- *     enabled bit of ch_mask in the order R, G, B, metalness, roughness.
+ *     parameter (y * tex_w + x) * n_ch + c (or v * n_ch + c per mesh vertex,
+ *     JSO_LAYOUT_VERTEX), where the c-th channel is the c-th enabled bit of
+ *     ch_mask in the order R, G, B, metalness, roughness.
  */
 #ifndef JSO_H
 #define JSO_H
@@ -73,15 +74,29 @@ extern "C" {
 
 #define JSO_MAX_SPHERES 32
 #define JSO_MAX_FIXED_MATS 8
+#define JSO_MAX_TRIS 4194304 /* triangles of the optional mesh */
+
+/* layout of the parameter vector (jso_scene_desc.param_layout) */
+#define JSO_LAYOUT_TEXTURE 0 /* texels: (y * tex_w + x) * n_ch + c                */
+#define JSO_LAYOUT_VERTEX 1  /* mesh vertices: v * n_ch + c, interpolated with the
+                                barycentric weights of the hit point; only the
+                                mesh may then use JSO_MAT_PARAM                  */
 
 typedef struct jso_ctx jso_ctx;
 
 /* Scene description (host memory; copied by jso_load_scene).
  * Geometry: optional infinite plane y = 0 (hit only from above), spheres,
- * a one-sided square area light facing -y, a uniform environment.
+ * an optional triangle mesh (two-sided, shaded with its geometric normal),
+ * a one-sided square area light facing -y, a uniform environment.  On equal
+ * distance the plane wins over spheres, spheres over the mesh, the mesh over
+ * the light, and a lower triangle index over a higher one.
  * The parameterised material is a tex_h x tex_w texture (1 x 1 = one global
- * material) of the channels in ch_mask; channels not in ch_mask take
- * fixed_default.  Fixed materials are rows (R, G, B, metalness, roughness). */
+ * material) of the channels in ch_mask, mapped to the plane and the mesh by
+ * planar UV over plane_extent and to spheres by latitude-longitude; or, with
+ * param_layout = JSO_LAYOUT_VERTEX, one set of channels per mesh vertex.
+ * Channels not in ch_mask take fixed_default.  Fixed materials are rows
+ * (R, G, B, metalness, roughness).  The mesh is indexed by a bounding volume
+ * hierarchy built on the host when the scene is loaded. */
 typedef struct {
   int width, height;
   float cam_eye[3], cam_target[3], cam_up[3];
@@ -101,6 +116,12 @@ typedef struct {
   float fixed_default[5];
   int n_fixed; /* <= JSO_MAX_FIXED_MATS */
   const float* fixed_mats;
+  /* triangle mesh (n_tris = 0: none) */
+  int n_verts, n_tris;   /* n_tris <= JSO_MAX_TRIS                         */
+  const float* verts;    /* [n_verts][3]: x, y, z                           */
+  const int* tris;       /* [n_tris][3]: vertex indices                     */
+  int mesh_mat;          /* JSO_MAT_PARAM or a fixed index                  */
+  int param_layout;      /* JSO_LAYOUT_TEXTURE or JSO_LAYOUT_VERTEX         */
 } jso_scene_desc;
 
 typedef struct {

@@ -25,7 +25,8 @@ JSO_TAG_PRIMAL_FD, JSO_TAG_ADJ_FD = 4, 5
 JSO_TAG_ADAM_PRIMAL, JSO_TAG_ADAM_ADJ, JSO_TAG_EVAL = 6, 7, 8
 JSO_F_NO_NEE, JSO_F_LAMBERT_ONLY, JSO_F_PARAM_INDEP, JSO_F_PIXEL_CENTER = 1, 2, 4, 8
 JSO_OPT_META, JSO_OPT_ADAM = 0, 1
-JSO_MAX_SPHERES, JSO_MAX_FIXED_MATS = 32, 8
+JSO_MAX_SPHERES, JSO_MAX_FIXED_MATS, JSO_MAX_TRIS = 32, 8, 4194304
+JSO_LAYOUT_TEXTURE, JSO_LAYOUT_VERTEX = 0, 1
 
 EXPORTED = [
     "jso_create", "jso_destroy", "jso_last_error", "jso_set_stream", "jso_synchronize",
@@ -62,6 +63,9 @@ class jso_scene_desc(ctypes.Structure):
         ("tex_w", ctypes.c_int), ("tex_h", ctypes.c_int), ("ch_mask", ctypes.c_int),
         ("fixed_default", ctypes.c_float * 5),
         ("n_fixed", ctypes.c_int), ("fixed_mats", ctypes.POINTER(ctypes.c_float)),
+        ("n_verts", ctypes.c_int), ("n_tris", ctypes.c_int),
+        ("verts", ctypes.POINTER(ctypes.c_float)), ("tris", ctypes.POINTER(ctypes.c_int)),
+        ("mesh_mat", ctypes.c_int), ("param_layout", ctypes.c_int),
     ]
 
 
@@ -207,8 +211,10 @@ class SceneDesc:
         self.spheres = np.ascontiguousarray(np.asarray(spec.spheres, np.float32).reshape(-1, 4))
         self.sphere_mat = np.ascontiguousarray(np.asarray(spec.sphere_mat, np.int32).reshape(-1))
         self.fixed = np.ascontiguousarray(np.asarray(spec.fixed_mats, np.float32).reshape(-1, 5))
-        if len(getattr(spec, "tris", ())) > 0:
-            raise JsoError("triangle meshes are not supported by this build")
+        self.verts = np.ascontiguousarray(
+            np.asarray(getattr(spec, "verts", np.zeros((0, 3))), np.float32).reshape(-1, 3))
+        self.tris = np.ascontiguousarray(
+            np.asarray(getattr(spec, "tris", np.zeros((0, 3))), np.int32).reshape(-1, 3))
         d = jso_scene_desc()
         d.width, d.height = spec.width, spec.height
         d.cam_eye[:] = spec.cam_eye
@@ -231,6 +237,11 @@ class SceneDesc:
         d.fixed_default[:] = spec.fixed_default
         d.n_fixed = self.fixed.shape[0]
         d.fixed_mats = self.fixed.ctypes.data_as(ctypes.POINTER(ctypes.c_float))
+        d.n_verts, d.n_tris = self.verts.shape[0], self.tris.shape[0]
+        d.verts = self.verts.ctypes.data_as(ctypes.POINTER(ctypes.c_float))
+        d.tris = self.tris.ctypes.data_as(ctypes.POINTER(ctypes.c_int))
+        d.mesh_mat = int(getattr(spec, "mesh_mat", JSO_MAT_PARAM))
+        d.param_layout = int(getattr(spec, "param_layout", JSO_LAYOUT_TEXTURE))
         self.desc = d
 
 

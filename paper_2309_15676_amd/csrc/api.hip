@@ -15,6 +15,7 @@
 #include <string>
 #include <vector>
 
+#include "bvh.h"
 #include "device.h"
 #include "jso.h"
 #include "kernels.h"
@@ -39,6 +40,10 @@ struct SceneGPU {
   double* slots = nullptr;         // per-path radiance, kMaxSlots per pixel (3 doubles each)
   double* accum = nullptr;         // per-pixel radiance sums of up to 3 primal images
   DevScene* d_scene = nullptr;     // device copy of `dev` read by the kernels
+  float* bvh_nodes = nullptr;      // mesh hierarchy (layout of bvh.h)
+  float* bvh_tris = nullptr;
+  int* bvh_tri_id = nullptr;
+  int stack = 0;                   // traversal-stack entries its mesh needs (0: no mesh)
   uint32_t host_iter = 0;          // mirror of ctl->iteration
   uint64_t generation = 0;         // unique per loaded scene (plan cache key)
 };
@@ -157,7 +162,7 @@ struct DescRing {
 // directly.  `sig` identifies the plan (scenes by load generation, options,
 // flags); launch records keep their metadata, their units live on the device.
 struct CachedLaunch {
-  int kind, timer, shape, n;
+  int kind, timer, shape, n, stack;
   uint32_t blocks;
   size_t lds, offset;
 };
@@ -256,7 +261,8 @@ void free_scene_buffers(SceneGPU* s) {
   void* bufs[] = {s->params, s->params_prev, s->target, s->F,      s->dF,
                   s->delta,  s->mean,        s->var,    s->alpha_prev, s->m2F,
                   s->m2D,    s->adam_m,      s->adam_v, s->ctl,    s->scratch_loss,
-                  s->partials, s->slots,     s->accum,  s->d_scene};
+                  s->partials, s->slots,     s->accum,  s->d_scene, s->bvh_nodes,
+                  s->bvh_tris, s->bvh_tri_id};
   for (void* b : bufs)
     if (b) (void)hipFree(b);
 }
@@ -289,6 +295,23 @@ int build_devscene(jso_ctx* c, const jso_scene_desc* d, SceneGPU* s) {
   }
   if (d->light_enabled && !(d->light_side > 0.0f))
     return fail(c, JSO_E_INVALID, "light side must be positive");
+  if (d->n_tris < 0 || d->n_tris > JSO_MAX_TRIS || d->n_verts < 0 ||
+      (d->n_tris > 0 && (!d->tris || !d->verts || d->n_verts == 0)))
+    return fail(c, JSO_E_INVALID, "mesh of %d triangles invalid (max %d)", d->n_tris,
+                JSO_MAX_TRIS);
+  if (d->n_tris > 0 && !check_mat(d->mesh_mat))
+    return fail(c, JSO_E_INVALID, "mesh material %d invalid", d->mesh_mat);
+  if (d->param_layout == JSO_LAYOUT_VERTEX) {
+    if (d->n_tris == 0 || d->mesh_mat != JSO_MAT_PARAM)
+      return fail(c, JSO_E_INVALID, "per-vertex parameters need a mesh with JSO_MAT_PARAM");
+    bool other = d->plane_enabled && d->plane_mat == JSO_MAT_PARAM;
+    for (int k = 0; k < d->n_spheres; ++k)
+      other = other || (d->sphere_mat ? d->sphere_mat[k] : JSO_MAT_PARAM) == JSO_MAT_PARAM;
+    if (other)
+      return fail(c, JSO_E_INVALID, "with per-vertex parameters only the mesh may use them");
+  } else if (d->param_layout != JSO_LAYOUT_TEXTURE) {
+    return fail(c, JSO_E_INVALID, "param_layout %d invalid", d->param_layout);
+  }
 
   DevScene& S = s->dev;
   std::memset(&S, 0, sizeof(S));
@@ -361,8 +384,46 @@ int build_devscene(jso_ctx* c, const jso_scene_desc* d, SceneGPU* s) {
   s->width = d->width;
   s->height = d->height;
   s->n_ch = nc;
+  S.n_tris = d->n_tris;
+  S.mesh_mat = d->n_tris > 0 ? d->mesh_mat : 0;
+  S.layout = d->param_layout;
   s->npix = (size_t)d->width * d->height;
-  s->P = (size_t)d->tex_w * d->tex_h * nc;
+  s->P = (d->param_layout == JSO_LAYOUT_VERTEX ? (size_t)d->n_verts
+                                               : (size_t)d->tex_w * d->tex_h) * nc;
+  return JSO_OK;
+}
+
+// Build the mesh hierarchy on the host and upload it; fills the scene's
+// device pointers.
+int upload_mesh(jso_ctx* c, const jso_scene_desc* d, SceneGPU* s) {
+  if (d->n_tris == 0) return JSO_OK;
+  BvhBuild b;
+  const std::string err = build_bvh(d->verts, d->n_verts, d->tris, d->n_tris, b);
+  if (!err.empty()) return fail(c, JSO_E_INVALID, "%s", err.c_str());
+  hipError_t e = hipSuccess;
+  auto A = [&](hipError_t x) {
+    if (e == hipSuccess) e = x;
+  };
+  A(dalloc(&s->bvh_nodes, b.nodes.size() * 16));
+  A(dalloc(&s->bvh_tris, b.tris.size()));
+  A(dalloc(&s->bvh_tri_id, b.order.size()));
+  if (e == hipSuccess) {
+    A(hipMemcpy(s->bvh_nodes, b.nodes.data(), b.nodes.size() * sizeof(BvhNode),
+                hipMemcpyHostToDevice));
+    A(hipMemcpy(s->bvh_tris, b.tris.data(), b.tris.size() * sizeof(float),
+                hipMemcpyHostToDevice));
+    A(hipMemcpy(s->bvh_tri_id, b.order.data(), b.order.size() * sizeof(int32_t),
+                hipMemcpyHostToDevice));
+  }
+  if (e != hipSuccess)
+    return fail(c, e == hipErrorOutOfMemory ? JSO_E_OOM : JSO_E_HIP, "mesh upload: %s",
+                hipGetErrorString(e));
+  DevScene& S = s->dev;
+  S.bvh_nodes = gmem((const float4*)s->bvh_nodes);
+  S.bvh_tris = gmem((const float4*)s->bvh_tris);
+  S.bvh_tri_id = gmem((const int*)s->bvh_tri_id);
+  S.bvh_depth = b.depth;
+  s->stack = b.depth;
   return JSO_OK;
 }
 
@@ -460,6 +521,7 @@ struct LaunchRec {
   int n = 0;
   uint32_t blocks = 0;
   size_t lds = 0;
+  int stack = 0;               // path kernels: BVH stack entries (deepest mesh of the units)
   size_t dev_offset = 0;       // batches: offset of the units in the device arena
 };
 
@@ -560,6 +622,7 @@ void plan_estimators(const std::vector<ProbPlan>& ps, Plan& plan, int shape = 0)
       f.flags = p.flags;
       f.tiles_x = tiles_x(p.crop, shape);
       f.tiles = tiles_of(p.crop, shape);
+      fw.stack = std::max(fw.stack, p.s->stack);
       push_unit(fw, f, f.tiles * (uint32_t)f.n_slices);
     }
     plan.push_back(std::move(fw));
@@ -648,6 +711,7 @@ void plan_estimators(const std::vector<ProbPlan>& ps, Plan& plan, int shape = 0)
           r.flags = p.flags;
           r.tiles_x = tiles_x(p.crop, shape);
           r.tiles = tiles_of(p.crop, shape);
+          ad.stack = std::max(ad.stack, p.s->stack);
           push_unit(ad, r, r.tiles * (uint32_t)r.n_slices);
         }
       }
@@ -793,13 +857,13 @@ hipError_t launch_rec(const LaunchRec& r, const void* dev_units, unsigned long l
                       hipStream_t st) {
   switch (r.kind) {
     case Kern::Forward:
-      return launch_forward(static_cast<const FwdArgs*>(dev_units), r.n, r.blocks, r.shape, work,
-                            st);
+      return launch_forward(static_cast<const FwdArgs*>(dev_units), r.n, r.blocks, r.shape,
+                            r.stack, work, st);
     case Kern::Finalize:
       return launch_finalize(static_cast<const FinArgs*>(dev_units), r.n, r.blocks, st);
     case Kern::Adjoint:
       return launch_adjoint(static_cast<const RepArgs*>(dev_units), r.n, r.blocks, r.shape, r.lds,
-                            work, st);
+                            r.stack, work, st);
     case Kern::Meta:
       return launch_meta(static_cast<const MetaArgs*>(dev_units), r.n, r.blocks, st);
     case Kern::Adam:
@@ -828,6 +892,7 @@ uint64_t config_hash(const std::vector<SceneGPU*>& ss, const jso_step_opts& o) {
     mix((uint64_t)s->n_ch);
     mix((uint64_t)s->P);
     mix((uint64_t)s->dev.depth);
+    mix((uint64_t)s->dev.n_tris);
   }
   return h;
 }
@@ -900,7 +965,7 @@ int exec_cached(jso_ctx* c, const std::vector<uint64_t>& sig, Build build) {
     for (size_t k = 0; k < plan.size(); ++k) {
       const LaunchRec& r = plan[k];
       np.launches.push_back(
-          CachedLaunch{(int)r.kind, r.timer, r.shape, r.n, r.blocks, r.lds, off[k]});
+          CachedLaunch{(int)r.kind, r.timer, r.shape, r.n, r.stack, r.blocks, r.lds, off[k]});
     }
     np.sig = sig;
     pc.plans.push_back(std::move(np));
@@ -916,6 +981,7 @@ int exec_cached(jso_ctx* c, const std::vector<uint64_t>& sig, Build build) {
     r.n = l.n;
     r.blocks = l.blocks;
     r.lds = l.lds;
+    r.stack = l.stack;
     TIMED_LAUNCH(c, l.timer, launch_rec(r, hit->dev + l.offset, work, c->stream));
   }
   return JSO_OK;
@@ -1056,6 +1122,11 @@ int jso_load_scene(jso_ctx* c, const jso_scene_desc* d, int* scene_id) {
     free_scene_buffers(s.get());
     return fail(c, e == hipErrorOutOfMemory ? JSO_E_OOM : JSO_E_HIP, "scene allocation: %s",
                 hipGetErrorString(e));
+  }
+  rc = upload_mesh(c, d, s.get());
+  if (rc) {
+    free_scene_buffers(s.get());
+    return rc;
   }
   // initial parameters: 0.5 for every channel (roughness within its box)
   rc = JSO_OK;

@@ -8,7 +8,9 @@
 #include <hip/hip_runtime.h>
 #include <stdint.h>
 
+#include "bvh.h"
 #include "jso.h"
+#include "kernels.h"
 
 namespace jso {
 
@@ -44,6 +46,11 @@ struct DevScene {
   float defaults[5];
   int n_fixed;
   float fixed[JSO_MAX_FIXED_MATS][5];
+  // triangle mesh (n_tris = 0: none), indexed by a BVH in the layout of bvh.h
+  int n_tris, mesh_mat, layout, bvh_depth;
+  JSO_GMEM const float4* bvh_nodes;  // 4 words per node
+  JSO_GMEM const float4* bvh_tris;   // 3 words per triangle, leaf order
+  JSO_GMEM const int* bvh_tri_id;    // original index of each reordered triangle
 };
 
 // ---------------------------------------------------------------------------
@@ -117,7 +124,7 @@ struct Rng {
 // ---------------------------------------------------------------------------
 // intersection
 // ---------------------------------------------------------------------------
-enum : int { HIT_NONE = 0, HIT_PLANE = 1, HIT_SPHERE = 2, HIT_LIGHT = 3 };
+enum : int { HIT_NONE = 0, HIT_PLANE = 1, HIT_SPHERE = 2, HIT_LIGHT = 3, HIT_MESH = 4 };
 
 // Ray-sphere distance in FP32: discriminant from the squared distance of the
 // centre to the ray (no b^2 - c cancellation), roots via q and c/q.
@@ -141,12 +148,159 @@ __device__ __forceinline__ float hit_sphere(const float* sp, V3 o, V3 d) {
 
 struct Hit {
   float t;
-  int kind, obj;
+  int kind, obj;  // obj: sphere index, or triangle index in BVH leaf order
 };
 
-// Closest hit; candidates in id order plane < spheres < light, replaced only
-// by a strictly smaller distance, so equal distances keep the lower id.
-__device__ __forceinline__ Hit intersect(const DevScene& S, V3 o, V3 d) {
+// Per-lane BVH traversal stack in LDS: entry k of this lane at base[k * stride]
+// (base already offset by the lane, stride = lanes of the block, so the lanes
+// of a wave touch consecutive words).
+struct TravStack {
+  uint32_t* base;
+  int stride;
+};
+
+// A ray prepared for slab tests: o * (1/d) precomputed so each slab bound is
+// one fma.  Zero direction components are nudged to +-1e-20 (finite inverse).
+struct RayQ {
+  V3 o, d, inv, oinv;
+};
+
+__device__ __forceinline__ float safe_inv(float x) {
+  return 1.0f / (fabsf(x) > 1e-20f ? x : copysignf(1e-20f, x));
+}
+
+__device__ __forceinline__ RayQ make_rayq(V3 o, V3 d) {
+  RayQ r;
+  r.o = o;
+  r.d = d;
+  r.inv = mk(safe_inv(d.x), safe_inv(d.y), safe_inv(d.z));
+  r.oinv = mk(o.x * r.inv.x, o.y * r.inv.y, o.z * r.inv.z);
+  return r;
+}
+
+// Distance at which the ray enters the box within [0, tmax], or kInf.
+__device__ __forceinline__ float box_entry(const RayQ& r, float lx, float ly, float lz, float hx,
+                                           float hy, float hz, float tmax) {
+  const float ax = fmaf(lx, r.inv.x, -r.oinv.x), bx = fmaf(hx, r.inv.x, -r.oinv.x);
+  const float ay = fmaf(ly, r.inv.y, -r.oinv.y), by = fmaf(hy, r.inv.y, -r.oinv.y);
+  const float az = fmaf(lz, r.inv.z, -r.oinv.z), bz = fmaf(hz, r.inv.z, -r.oinv.z);
+  const float t0 = fmaxf(fmaxf(fminf(ax, bx), fminf(ay, by)), fmaxf(fminf(az, bz), 0.0f));
+  const float t1 = fminf(fminf(fmaxf(ax, bx), fmaxf(ay, by)), fminf(fmaxf(az, bz), tmax));
+  return t0 <= t1 ? t0 : kInf;
+}
+
+// Moller-Trumbore (J. Graphics Tools 1997) in FP32: distance of the hit in
+// (0, tmax], or kInf.  Edges count as inside (u, v >= 0, u + v <= 1).
+__device__ __forceinline__ float tri_hit(const RayQ& r, V3 v0, V3 e1, V3 e2, float tmax) {
+  const V3 pv = cross(r.d, e2);
+  const float det = dot(e1, pv);
+  if (det == 0.0f) return kInf;
+  const float inv = 1.0f / det;
+  const V3 sv = r.o - v0;
+  const float u = dot(sv, pv) * inv;
+  const V3 qv = cross(sv, e1);
+  const float v = dot(r.d, qv) * inv;
+  const float t = dot(e2, qv) * inv;
+  return (u >= 0.0f && v >= 0.0f && u + v <= 1.0f && t > 0.0f && t <= tmax) ? t : kInf;
+}
+
+// 16-byte load from global memory (the cast back to a generic pointer keeps the
+// access global once inlined).
+__device__ __forceinline__ float4 ldg4(JSO_GMEM const float4* p) { return *(const float4*)p; }
+
+// Closest triangle strictly nearer than `best_t` (or at best_t with a lower
+// original index than the triangle already held).  Nearer child first; the
+// other is deferred on the stack, so at most one entry per inner level.
+__device__ __forceinline__ void bvh_closest(const DevScene& S, const TravStack& st, V3 o, V3 d,
+                                            float& best_t, int& best_tri) {
+  const RayQ r = make_rayq(o, d);
+  int sp = 0;
+  int32_t link = 0;
+  for (;;) {
+    if (link >= 0) {
+      JSO_GMEM const float4* nd = S.bvh_nodes + 4 * (size_t)link;
+      const float4 a = ldg4(nd), b = ldg4(nd + 1), c = ldg4(nd + 2), e = ldg4(nd + 3);
+      const float t0 = box_entry(r, a.x, a.y, a.z, a.w, b.x, b.y, best_t);
+      const float t1 = box_entry(r, b.z, b.w, c.x, c.y, c.z, c.w, best_t);
+      const int32_t l0 = __float_as_int(e.x), l1 = __float_as_int(e.y);
+      if (t0 != kInf && t1 != kInf) {
+        const bool near0 = t0 <= t1;
+        st.base[sp * st.stride] = (uint32_t)(near0 ? l1 : l0);
+        ++sp;
+        link = near0 ? l0 : l1;
+        continue;
+      }
+      if (t0 != kInf) {
+        link = l0;
+        continue;
+      }
+      if (t1 != kInf) {
+        link = l1;
+        continue;
+      }
+    } else {
+      const uint32_t v = ~(uint32_t)link;
+      const int first = (int)(v >> kLeafBits), end = first + (int)(v & (uint32_t)kLeafMax);
+      for (int i = first; i < end; ++i) {
+        JSO_GMEM const float4* tp = S.bvh_tris + 3 * (size_t)i;
+        const float4 a = ldg4(tp), b = ldg4(tp + 1), c = ldg4(tp + 2);
+        const float t = tri_hit(r, mk(a.x, a.y, a.z), mk(b.x, b.y, b.z), mk(c.x, c.y, c.z), best_t);
+        if (t < best_t ||
+            (t == best_t && best_tri >= 0 && S.bvh_tri_id[i] < S.bvh_tri_id[best_tri])) {
+          best_t = t;
+          best_tri = i;
+        }
+      }
+    }
+    if (sp == 0) break;
+    --sp;
+    link = (int32_t)st.base[sp * st.stride];
+  }
+}
+
+// Whether any triangle lies at a distance in (0, tmax).
+__device__ __forceinline__ bool bvh_any(const DevScene& S, const TravStack& st, V3 o, V3 d,
+                                        float tmax) {
+  const RayQ r = make_rayq(o, d);
+  int sp = 0;
+  int32_t link = 0;
+  for (;;) {
+    if (link >= 0) {
+      JSO_GMEM const float4* nd = S.bvh_nodes + 4 * (size_t)link;
+      const float4 a = ldg4(nd), b = ldg4(nd + 1), c = ldg4(nd + 2), e = ldg4(nd + 3);
+      const bool h0 = box_entry(r, a.x, a.y, a.z, a.w, b.x, b.y, tmax) != kInf;
+      const bool h1 = box_entry(r, b.z, b.w, c.x, c.y, c.z, c.w, tmax) != kInf;
+      const int32_t l0 = __float_as_int(e.x), l1 = __float_as_int(e.y);
+      if (h0 && h1) {
+        st.base[sp * st.stride] = (uint32_t)l1;
+        ++sp;
+      }
+      if (h0 || h1) {
+        link = h0 ? l0 : l1;
+        continue;
+      }
+    } else {
+      const uint32_t v = ~(uint32_t)link;
+      const int first = (int)(v >> kLeafBits), end = first + (int)(v & (uint32_t)kLeafMax);
+      for (int i = first; i < end; ++i) {
+        JSO_GMEM const float4* tp = S.bvh_tris + 3 * (size_t)i;
+        const float4 a = ldg4(tp), b = ldg4(tp + 1), c = ldg4(tp + 2);
+        if (tri_hit(r, mk(a.x, a.y, a.z), mk(b.x, b.y, b.z), mk(c.x, c.y, c.z), tmax) < tmax)
+          return true;
+      }
+    }
+    if (sp == 0) break;
+    --sp;
+    link = (int32_t)st.base[sp * st.stride];
+  }
+  return false;
+}
+
+// Closest hit; candidates in the order plane < spheres < mesh < light, each
+// replacing the current one only at a strictly smaller distance, so equal
+// distances keep the earlier kind.
+template <bool kMesh>
+__device__ __forceinline__ Hit intersect(const DevScene& S, const TravStack& st, V3 o, V3 d) {
   Hit h{kInf, HIT_NONE, -1};
   if (S.plane_enabled && d.y < 0.0f && o.y > 0.0f) {
     h.t = -o.y / d.y;
@@ -161,6 +315,16 @@ __device__ __forceinline__ Hit intersect(const DevScene& S, V3 o, V3 d) {
       h.obj = k;
     }
   }
+  if (kMesh && S.n_tris > 0) {
+    int tri = -1;
+    float t = h.t;
+    bvh_closest(S, st, o, d, t, tri);
+    if (tri >= 0) {
+      h.t = t;
+      h.kind = HIT_MESH;
+      h.obj = tri;
+    }
+  }
   if (S.light_enabled && d.y > 0.0f && o.y < S.lc[1]) {
     const float t = (S.lc[1] - o.y) / d.y;
     const float dx = o.x + t * d.x - S.lc[0], dz = o.z + t * d.z - S.lc[2];
@@ -173,10 +337,13 @@ __device__ __forceinline__ Hit intersect(const DevScene& S, V3 o, V3 d) {
   return h;
 }
 
-__device__ __forceinline__ bool occluded(const DevScene& S, V3 o, V3 d, float tmax) {
+template <bool kMesh>
+__device__ __forceinline__ bool occluded(const DevScene& S, const TravStack& st, V3 o, V3 d,
+                                         float tmax) {
   if (S.plane_enabled && d.y < 0.0f && o.y > 0.0f && -o.y / d.y < tmax) return true;
   for (int k = 0; k < S.n_spheres; ++k)
     if (hit_sphere(S.sph[k], o, d) < tmax) return true;
+  if (kMesh && S.n_tris > 0) return bvh_any(S, st, o, d, tmax);
   return false;
 }
 
@@ -187,25 +354,36 @@ struct Mat {
   float c[3], m, r;
 };
 
-// Texel footprint of a parameterised-material lookup.  `global` = a 1x1
-// texture (one material for every point).
+// Footprint of a parameterised-material lookup: the (up to four) parameter
+// elements the material at a point interpolates, and their weights.
+//   bilinear texture: texels t00, t01 (x + 1), t10 (y + 1) and t01 + t10 - t00,
+//     weights from the fractions (fx, fy);
+//   global (1x1 texture): element 0, weight 1;
+//   triangle (per-vertex layout): vertices t00, t01, t10 with the barycentric
+//     weights 1 - fx - fy, fx, fy (fourth weight 0).
 struct Footprint {
   int global;
-  int t00, t01, t10;  // texel indices (the fourth is t01 + t10 - t00)
-  float fx, fy;       // bilinear fractions
+  int tri;
+  int t00, t01, t10;
+  float fx, fy;
 };
 
+// Weight of element q (0..3) of the footprint.
+__device__ __forceinline__ float footprint_weight(const Footprint& fp, int q) {
+  if (fp.tri) return q == 0 ? (1.0f - fp.fx) - fp.fy : (q == 1 ? fp.fx : (q == 2 ? fp.fy : 0.0f));
+  return ((q & 1) ? fp.fx : 1.0f - fp.fx) * ((q & 2) ? fp.fy : 1.0f - fp.fy);
+}
+
 __device__ __forceinline__ void texel_weights(const Footprint& fp, float w[4]) {
-  w[0] = (1.0f - fp.fx) * (1.0f - fp.fy);
-  w[1] = fp.fx * (1.0f - fp.fy);
-  w[2] = (1.0f - fp.fx) * fp.fy;
-  w[3] = fp.fx * fp.fy;
+#pragma unroll
+  for (int q = 0; q < 4; ++q) w[q] = footprint_weight(fp, q);
 }
 
 // Bilinear, clamp-to-edge; texel centres at (i + 0.5) / size.
 __device__ __forceinline__ Footprint footprint_uv(const DevScene& S, float u, float v) {
   Footprint fp;
   fp.global = 0;
+  fp.tri = 0;
   const float x = u * (float)S.tex_w - 0.5f, y = v * (float)S.tex_h - 0.5f;
   const float x0 = floorf(x), y0 = floorf(y);
   fp.fx = x - x0;
@@ -220,11 +398,21 @@ __device__ __forceinline__ Footprint footprint_uv(const DevScene& S, float u, fl
   return fp;
 }
 
-// Material at a hit.  Returns true for the parameterised material (then fp is
-// its footprint); fixed materials return false.
+// A surface point being shaded.  Mesh points also carry the triangle's vertex
+// indices and the barycentric weights (bu, bv) of vertices 1 and 2.
+struct Surf {
+  int kind, obj;
+  V3 p, n;
+  int vid[3];
+  float bu, bv;
+};
+
+// Material at a surface point.  Returns true for the parameterised material
+// (then fp is its footprint); fixed materials return false.
 __device__ __forceinline__ bool material_at(const DevScene& S, const float* __restrict__ params,
-                                            int kind, int obj, V3 p, V3 n, Mat& M, Footprint& fp) {
-  const int mat = kind == HIT_PLANE ? S.plane_mat : S.sph_mat[obj];
+                                            const Surf& x, Mat& M, Footprint& fp) {
+  const int mat = x.kind == HIT_PLANE ? S.plane_mat
+                                      : (x.kind == HIT_MESH ? S.mesh_mat : S.sph_mat[x.obj]);
   if (mat >= 0) {
     M.c[0] = S.fixed[mat][0];
     M.c[1] = S.fixed[mat][1];
@@ -234,8 +422,9 @@ __device__ __forceinline__ bool material_at(const DevScene& S, const float* __re
     return false;
   }
   float val[5];
-  if (S.tex_w == 1 && S.tex_h == 1) {
+  if (S.layout == JSO_LAYOUT_TEXTURE && S.tex_w == 1 && S.tex_h == 1) {
     fp.global = 1;
+    fp.tri = 0;
     fp.t00 = fp.t01 = fp.t10 = 0;
     fp.fx = fp.fy = 0.0f;
 #pragma unroll
@@ -246,19 +435,31 @@ __device__ __forceinline__ bool material_at(const DevScene& S, const float* __re
       val[b] = S.slot[b] >= 0 ? pv : S.defaults[b];
     }
   } else {
-    float u, v;
-    if (kind == HIT_PLANE) {
-      u = (p.x - S.plane_x0) / (S.plane_x1 - S.plane_x0);
-      v = (p.z - S.plane_z0) / (S.plane_z1 - S.plane_z0);
+    if (x.kind == HIT_MESH && S.layout == JSO_LAYOUT_VERTEX) {
+      fp.global = 0;
+      fp.tri = 1;
+      fp.t00 = x.vid[0];
+      fp.t01 = x.vid[1];
+      fp.t10 = x.vid[2];
+      fp.fx = x.bu;
+      fp.fy = x.bv;
     } else {
-      u = 0.5f + atan2f(n.z, n.x) / kTwoPi;
-      v = atan2f(sqrtf(n.x * n.x + n.z * n.z), n.y) * kInvPi;
+      float u, v;
+      if (x.kind == HIT_PLANE || x.kind == HIT_MESH) {
+        u = (x.p.x - S.plane_x0) / (S.plane_x1 - S.plane_x0);
+        v = (x.p.z - S.plane_z0) / (S.plane_z1 - S.plane_z0);
+      } else {
+        const V3 n = x.n;
+        u = 0.5f + atan2f(n.z, n.x) / kTwoPi;
+        v = atan2f(sqrtf(n.x * n.x + n.z * n.z), n.y) * kInvPi;
+      }
+      fp = footprint_uv(S, u, v);
     }
-    fp = footprint_uv(S, u, v);
     float w[4];
     texel_weights(fp, w);
     const int nc = S.n_ch;
-    const int t11 = fp.t01 + fp.t10 - fp.t00;
+    // the fourth element of a triangle footprint has weight 0 and is not read
+    const int t11 = fp.tri ? fp.t00 : fp.t01 + fp.t10 - fp.t00;
 #pragma unroll
     for (int b = 0; b < 5; ++b) {
       const int s = S.slot[b];
@@ -394,13 +595,13 @@ struct Path {
   V3 o;           // pending hit point
   V3 d;           // direction of the ray that reached it
   float beta[3];
-  uint32_t hit;   // pending hit: kind | object << 2 | vertex index j << 10
+  uint32_t hit;   // pending hit: kind | vertex index j << 3 | object << 10
   bool alive;
-  __device__ __forceinline__ int kind() const { return (int)(hit & 3u); }
-  __device__ __forceinline__ int obj() const { return (int)((hit >> 2) & 255u); }
-  __device__ __forceinline__ int j() const { return (int)(hit >> 10); }
+  __device__ __forceinline__ int kind() const { return (int)(hit & 7u); }
+  __device__ __forceinline__ int j() const { return (int)((hit >> 3) & 127u); }
+  __device__ __forceinline__ int obj() const { return (int)(hit >> 10); }
   __device__ __forceinline__ void set_hit(int kind, int obj, int j) {
-    hit = (uint32_t)kind | ((uint32_t)obj << 2) | ((uint32_t)j << 10);
+    hit = (uint32_t)kind | ((uint32_t)j << 3) | ((uint32_t)obj << 10);
   }
 };
 
@@ -413,8 +614,9 @@ struct VertexGrad {
   float g[5];
 };
 
-__device__ __forceinline__ void path_begin(const DevScene& S, const Rng& rng, int px, int py,
-                                           uint32_t flags, Path& P) {
+template <bool kMesh>
+__device__ __forceinline__ void path_begin(const DevScene& S, const TravStack& st, const Rng& rng,
+                                           int px, int py, uint32_t flags, Path& P) {
   float jx = 0.5f, jy = 0.5f;
   if (!(flags & JSO_F_PIXEL_CENTER)) {
     float u[4];
@@ -428,7 +630,7 @@ __device__ __forceinline__ void path_begin(const DevScene& S, const Rng& rng, in
   P.d = normalize(ld3(S.cw) + ld3(S.cu) * sx + ld3(S.cv) * sy);
   P.beta[0] = P.beta[1] = P.beta[2] = 1.0f;
   P.led[0] = P.led[1] = P.led[2] = 0.0;
-  const Hit h = intersect(S, eye, P.d);
+  const Hit h = intersect<kMesh>(S, st, eye, P.d);
   P.o = eye + P.d * h.t;
   P.set_hit(h.kind, h.obj, 1);
   P.alive = false;
@@ -452,22 +654,53 @@ __device__ __forceinline__ void path_begin(const DevScene& S, const Rng& rng, in
 //   NEE:           adj . beta K df(w_l)
 //   continuation:  adj . (R / f) df(w_i)
 // which is the derivative of adj . C w.r.t. this vertex's material.
-template <bool kGrad>
-__device__ __forceinline__ void path_vertex(const DevScene& S, const float* __restrict__ params,
-                                            const Rng& rng, uint32_t flags, Path& P,
-                                            const float adj[3], VertexGrad& vg) {
-  V3 p = P.o;
-  const int kind = P.kind(), obj = P.obj(), j = P.j();
-  V3 n;
-  if (kind == HIT_PLANE) {
-    p.y = 0.0f;
-    n = mk(0.0f, 1.0f, 0.0f);
+template <bool kGrad, bool kMesh>
+__device__ __forceinline__ void path_vertex(const DevScene& S, const TravStack& st,
+                                            const float* __restrict__ params, const Rng& rng,
+                                            uint32_t flags, Path& P, const float adj[3],
+                                            VertexGrad& vg) {
+  Surf x;
+  x.p = P.o;
+  x.kind = P.kind();
+  x.obj = P.obj();
+  const int j = P.j();
+  if (x.kind == HIT_PLANE) {
+    x.p.y = 0.0f;
+    x.n = mk(0.0f, 1.0f, 0.0f);
+  } else if (kMesh && x.kind == HIT_MESH) {
+    // two-sided: the geometric normal turned towards the incoming ray
+    JSO_GMEM const float4* tp = S.bvh_tris + 3 * (size_t)x.obj;
+    const float4 a = ldg4(tp), b = ldg4(tp + 1), c = ldg4(tp + 2);
+    const V3 e1 = mk(b.x, b.y, b.z), e2 = mk(c.x, c.y, c.z);
+    const V3 ng = normalize(cross(e1, e2));
+    x.n = dot(ng, P.d) < 0.0f ? ng : ng * -1.0f;
+    x.vid[0] = __float_as_int(a.w);
+    x.vid[1] = __float_as_int(b.w);
+    x.vid[2] = __float_as_int(c.w);
+    x.bu = x.bv = 0.0f;
+    if (S.layout == JSO_LAYOUT_VERTEX) {
+      // barycentrics of the hit point: Moller-Trumbore's (u, v) from the point
+      // itself along the ray direction, clamped into the triangle
+      const V3 pv = cross(P.d, e2);
+      const float inv = 1.0f / dot(e1, pv);
+      const V3 sv = x.p - mk(a.x, a.y, a.z);
+      float bu = fmaxf(dot(sv, pv) * inv, 0.0f);
+      float bv = fmaxf(dot(P.d, cross(sv, e1)) * inv, 0.0f);
+      const float sum = bu + bv;
+      if (sum > 1.0f) {
+        bu /= sum;
+        bv /= sum;
+      }
+      x.bu = bu;
+      x.bv = bv;
+    }
   } else {
-    n = normalize(p - ld3(S.sph[obj]));
+    x.n = normalize(x.p - ld3(S.sph[x.obj]));
   }
+  const V3 p = x.p, n = x.n;
   const V3 wo = mk(-P.d.x, -P.d.y, -P.d.z);
   Mat M;
-  vg.valid = material_at(S, params, kind, obj, p, n, M, vg.fp);
+  vg.valid = material_at(S, params, x, M, vg.fp);
   vg.j = j;
   if (kGrad) {
 #pragma unroll
@@ -485,7 +718,7 @@ __device__ __forceinline__ void path_vertex(const DevScene& S, const float* __re
     const float dist2 = dot(dl, dl), dist = sqrtf(dist2);
     const V3 wl = dl * (1.0f / dist);
     const float cos_l = wl.y, cos_s = dot(n, wl);
-    if (cos_l > 0.0f && cos_s > 0.0f && !occluded(S, po, wl, dist - kShadowEps)) {
+    if (cos_l > 0.0f && cos_s > 0.0f && !occluded<kMesh>(S, st, po, wl, dist - kShadowEps)) {
       Bsdf nb;
       eval_bsdf<kGrad>(M, n, wo, wl, flags, nb);
       const float pl = dist2 / (cos_l * S.larea);
@@ -540,7 +773,7 @@ __device__ __forceinline__ void path_vertex(const DevScene& S, const float* __re
 #pragma unroll
   for (int k = 0; k < 3; ++k) P.beta[k] *= cb.f[k] * cw;
   P.d = wi;
-  const Hit h = intersect(S, po, wi);
+  const Hit h = intersect<kMesh>(S, st, po, wi);
   P.o = po + wi * h.t;
   if (h.kind == HIT_NONE) {
 #pragma unroll

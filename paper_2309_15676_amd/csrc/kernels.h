@@ -186,12 +186,14 @@ hipError_t launch_philox(const uint32_t* ctr, size_t n, uint64_t key, uint32_t* 
 // work (nullable): forward [2] += paths traced, [3] += surface vertices;
 // adjoint [0] += paths replayed, [1] += surface vertices.
 // shape: index into kShapeW / kShapeH (the tiles the units were built for)
-hipError_t launch_forward(const FwdArgs* U, int n, uint32_t blocks, int shape,
+// stack: BVH traversal-stack entries per lane (the deepest mesh among the
+// units' scenes; 0 = no scene of the launch has a mesh), at most kBvhMaxStack
+hipError_t launch_forward(const FwdArgs* U, int n, uint32_t blocks, int shape, int stack,
                           unsigned long long* work, hipStream_t st);
 hipError_t launch_finalize(const FinArgs* U, int n, uint32_t blocks, hipStream_t st);
 // lds: dynamic LDS bytes (adjoint_lds_bytes of the largest channel count)
 hipError_t launch_adjoint(const RepArgs* U, int n, uint32_t blocks, int shape, size_t lds,
-                          unsigned long long* work, hipStream_t st);
+                          int stack, unsigned long long* work, hipStream_t st);
 hipError_t launch_meta(const MetaArgs* U, int n, uint32_t blocks, hipStream_t st);
 hipError_t launch_adam(const AdamArgs* U, int n, uint32_t blocks, hipStream_t st);
 hipError_t launch_fill_f64(double* p, size_t n, double v, hipStream_t st);

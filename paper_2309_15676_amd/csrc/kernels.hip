@@ -234,10 +234,10 @@ constexpr int kFwdXchgWords = (int)(sizeof(FwdItem) / 4);
 // ---------------------------------------------------------------------------
 // The kernel bodies take the scene through a restrict-qualified parameter:
 // nothing the kernels write aliases it, so its fields stay in registers.
-template <class SH>
+template <class SH, bool kMesh>
 __device__ __forceinline__ void forward_tile(const FwdArgs& A, const DevScene* __restrict__ Sp,
                                              uint32_t iter, uint32_t* s_xchg, int* s_cnt,
-                                             unsigned long long* work) {
+                                             const TravStack& st, unsigned long long* work) {
   const DevScene& S = *Sp;
   const TileBlock tb = tile_block<SH>(A);
   const FwdSlice& sl = A.sl[tb.slice];
@@ -255,10 +255,10 @@ __device__ __forceinline__ void forward_tile(const FwdArgs& A, const DevScene* _
   P.alive = false;
   if (active) {
     const Rng rng = B.rng((int)threadIdx.x);
-    path_begin(S, rng, px, py, A.flags, P);
+    path_begin<kMesh>(S, st, rng, px, py, A.flags, P);
     if (P.alive) {
       ++n_vert;
-      path_vertex<false>(S, G(sl.params), rng, A.flags, P, zero, vg);
+      path_vertex<false, kMesh>(S, st, G(sl.params), rng, A.flags, P, zero, vg);
     }
     if (!P.alive) store_radiance(out, pix, P.led);
   }
@@ -281,23 +281,27 @@ __device__ __forceinline__ void forward_tile(const FwdArgs& A, const DevScene* _
     const Rng rng = B.rng(W.src);
     while (W.P.alive) {
       ++n_vert;
-      path_vertex<false>(S, G(sl.params), rng, A.flags, W.P, zero, vg);
+      path_vertex<false, kMesh>(S, st, G(sl.params), rng, A.flags, W.P, zero, vg);
     }
     store_radiance(out, B.pixel(W.src), W.P.led);
   }
   count_work(work ? work + 2 : nullptr, active ? 1 : 0, n_vert);
 }
 
-template <int TW, int TH>
+// kMesh: the launch's scenes may hold a triangle mesh; the dynamic LDS then
+// holds the lanes' traversal stacks.
+template <int TW, int TH, bool kMesh>
 __global__ void __launch_bounds__(TW * TH) __attribute__((amdgpu_waves_per_eu(4)))
 k_forward(const FwdArgs* __restrict__ Units, int n_units, unsigned long long* work) {
   using SH = Shape<TW, TH>;
   __shared__ uint32_t s_xchg[kFwdXchgWords * kXchg];
   __shared__ int s_cnt[SH::WAVES];
+  extern __shared__ uint32_t s_dyn[];
   const FwdArgs& A = unit_of(Units, n_units);
   const uint32_t iter = iteration_of(A.key);
   if (A.h.max_iter && iter >= A.h.max_iter) return;  // finished problem
-  forward_tile<SH>(A, G(A.scene), iter, s_xchg, s_cnt, work);
+  const TravStack st{s_dyn + threadIdx.x, SH::N};
+  forward_tile<SH, kMesh>(A, G(A.scene), iter, s_xchg, s_cnt, st, work);
 }
 
 // ---------------------------------------------------------------------------
@@ -402,13 +406,14 @@ __device__ __forceinline__ int table_slot(const GradTable& T, uint32_t texel) {
   return -1;
 }
 
-// Texel q of the footprint (q = 0..3: x-offset q & 1, y-offset q >> 1) and its
-// bilinear weight, computed arithmetically so no per-lane array is indexed.
+// Element q of the footprint (q = 0..3: t00, t01, t10, t01 + t10 - t00) and
+// its weight, computed arithmetically so no per-lane array is indexed.  A
+// triangle's fourth element has weight 0 and is never touched.
 __device__ __forceinline__ void footprint_texel(const Footprint& fp, int q, int& texel,
                                                 float& w) {
   const int dx = fp.t01 - fp.t00, dy = fp.t10 - fp.t00;
   texel = fp.t00 + (q & 1) * dx + (q >> 1) * dy;
-  w = ((q & 1) ? fp.fx : 1.0f - fp.fx) * ((q & 2) ? fp.fy : 1.0f - fp.fy);
+  w = footprint_weight(fp, q);
 }
 
 // Add one first-hit vertex's material gradient g (R, G, B, metal, rough) to
@@ -462,11 +467,14 @@ __device__ __forceinline__ void scatter_wave(const DevScene& S, float* __restric
     for (int k = 0; k < vi && mm != 0; ++k) mm &= mm - 1;
     const bool work = vi < nv && mm != 0;
     const int src = work ? __ffsll((unsigned long long)mm) - 1 : lane;
-    const int t00 = __shfl(v.fp.t00, src, 64);
-    const int t01 = __shfl(v.fp.t01, src, 64);
-    const int t10 = __shfl(v.fp.t10, src, 64);
-    const float fx = __shfl(v.fp.fx, src, 64);
-    const float fy = __shfl(v.fp.fy, src, 64);
+    Footprint fp;
+    fp.global = 0;
+    fp.tri = __shfl(v.fp.tri, src, 64);
+    fp.t00 = __shfl(v.fp.t00, src, 64);
+    fp.t01 = __shfl(v.fp.t01, src, 64);
+    fp.t10 = __shfl(v.fp.t10, src, 64);
+    fp.fx = __shfl(v.fp.fx, src, 64);
+    fp.fy = __shfl(v.fp.fy, src, 64);
     float gc = 0.0f;
 #pragma unroll
     for (int b = 0; b < 5; ++b) {
@@ -474,17 +482,19 @@ __device__ __forceinline__ void scatter_wave(const DevScene& S, float* __restric
       if (S.slot[b] == c) gc = x;
     }
     if (work) {
-      const int texel = t00 + (q & 1) * (t01 - t00) + (q >> 1) * (t10 - t00);
-      const float w = ((q & 1) ? fx : 1.0f - fx) * ((q & 2) ? fy : 1.0f - fy);
+      int texel;
+      float w;
+      footprint_texel(fp, q, texel, w);
       const float val = w * (sign * gc);
-      if (val != 0.0f) unsafeAtomicAdd(grad + (size_t)texel * nc + c, val);
+      if (w != 0.0f && val != 0.0f) unsafeAtomicAdd(grad + (size_t)texel * nc + c, val);
     }
     for (int k = 0; k < nv && m != 0; ++k) m &= m - 1;
   }
 }
 
 __device__ __forceinline__ bool same_footprint(const Footprint& a, const Footprint& b) {
-  return a.global == b.global && a.t00 == b.t00 && a.t01 == b.t01 && a.t10 == b.t10 &&
+  return a.global == b.global && a.tri == b.tri && a.t00 == b.t00 && a.t01 == b.t01 &&
+         a.t10 == b.t10 &&
          __float_as_uint(a.fx) == __float_as_uint(b.fx) &&
          __float_as_uint(a.fy) == __float_as_uint(b.fy);
 }
@@ -554,10 +564,11 @@ struct RepPairItem {
 constexpr int kRepXchgWords = (int)(sizeof(RepPairItem) / 4);
 
 // Start the replay of a path: P.led = the radiance still to come.
-__device__ __forceinline__ void replay_begin(const DevScene& S, const Rng& rng, int px, int py,
-                                             uint32_t flags, const double* __restrict__ C,
-                                             Path& P) {
-  path_begin(S, rng, px, py, flags, P);
+template <bool kMesh>
+__device__ __forceinline__ void replay_begin(const DevScene& S, const TravStack& st,
+                                             const Rng& rng, int px, int py, uint32_t flags,
+                                             const double* __restrict__ C, Path& P) {
+  path_begin<kMesh>(S, st, rng, px, py, flags, P);
 #pragma unroll
   for (int k = 0; k < 3; ++k) P.led[k] = C[k] - P.led[k];
 }
@@ -567,10 +578,10 @@ __device__ __forceinline__ void replay_begin(const DevScene& S, const Rng& rng, 
 // (their gradients go to the block table, flushed right after), later ones on
 // the compacted lanes in a wave-uniform loop, so the later-vertex scatter can
 // use the whole wave.  The exchange buffer reuses the table's LDS.
-template <class SH>
+template <class SH, bool kMesh>
 __device__ __forceinline__ void adjoint_tile(const RepArgs& A, const DevScene* __restrict__ Sp,
                                              uint32_t iter, uint32_t* s_dyn, int* s_cnt,
-                                             unsigned long long* work) {
+                                             const TravStack& st, unsigned long long* work) {
   const DevScene& S = *Sp;
   uint32_t* s_keys = s_dyn;
   float* s_vals = reinterpret_cast<float*>(s_dyn + kTableSize);
@@ -603,18 +614,18 @@ __device__ __forceinline__ void adjoint_tile(const RepArgs& A, const DevScene* _
         adj_a[k] = G(sl.delta)[3 * (size_t)pix + k] * sl.adj_scale;
         if (pair) adj_b[k] = G(sl.delta_b)[3 * (size_t)pix + k] * sl.adj_scale;
       }
-      replay_begin(S, rng, px, py, A.flags,
-                   G(A.slots) + ((size_t)sl.slot_a * A.npix + pix) * 3, Pa);
+      replay_begin<kMesh>(S, st, rng, px, py, A.flags,
+                          G(A.slots) + ((size_t)sl.slot_a * A.npix + pix) * 3, Pa);
       if (Pa.alive) {
         ++n_vert;
-        path_vertex<true>(S, G(sl.params), rng, A.flags, Pa, adj_a, va);
+        path_vertex<true, kMesh>(S, st, G(sl.params), rng, A.flags, Pa, adj_a, va);
       }
       if (pair) {
-        replay_begin(S, rng, px, py, A.flags,
-                     G(A.slots) + ((size_t)sl.slot_b * A.npix + pix) * 3, Pb);
+        replay_begin<kMesh>(S, st, rng, px, py, A.flags,
+                            G(A.slots) + ((size_t)sl.slot_b * A.npix + pix) * 3, Pb);
         if (Pb.alive) {
           ++n_vert;
-          path_vertex<true>(S, G(sl.params_b), rng, A.flags, Pb, adj_b, vb);
+          path_vertex<true, kMesh>(S, st, G(sl.params_b), rng, A.flags, Pb, adj_b, vb);
         }
         if (va.valid && vb.valid && same_footprint(va.fp, vb.fp)) {
 #pragma unroll
@@ -659,7 +670,7 @@ __device__ __forceinline__ void adjoint_tile(const RepArgs& A, const DevScene* _
         v.valid = false;
         if (W.P.alive) {
           ++n_vert;
-          path_vertex<true>(S, G(sl.params), wr, A.flags, W.P, W.adj, v);
+          path_vertex<true, kMesh>(S, st, G(sl.params), wr, A.flags, W.P, W.adj, v);
         }
         const bool later = sink.add(S, v, sl.sign);
         scatter_wave(S, G(sl.grad), v, sl.sign, later);
@@ -699,11 +710,11 @@ __device__ __forceinline__ void adjoint_tile(const RepArgs& A, const DevScene* _
         va.valid = vb.valid = false;
         if (W.Pa.alive) {
           ++n_vert;
-          path_vertex<true>(S, G(sl.params), wr, A.flags, W.Pa, W.adj_a, va);
+          path_vertex<true, kMesh>(S, st, G(sl.params), wr, A.flags, W.Pa, W.adj_a, va);
         }
         if (W.Pb.alive) {
           ++n_vert;
-          path_vertex<true>(S, G(sl.params_b), wr, A.flags, W.Pb, W.adj_b, vb);
+          path_vertex<true, kMesh>(S, st, G(sl.params_b), wr, A.flags, W.Pb, W.adj_b, vb);
         }
         if (va.valid && vb.valid && same_footprint(va.fp, vb.fp)) {
 #pragma unroll
@@ -721,16 +732,20 @@ __device__ __forceinline__ void adjoint_tile(const RepArgs& A, const DevScene* _
   count_work(work, paths, n_vert);
 }
 
-template <int TW, int TH>
+// Dynamic LDS: with kMesh, `stack` traversal-stack entries per lane first,
+// then the gradient table / exchange buffer.
+template <int TW, int TH, bool kMesh>
 __global__ void __launch_bounds__(TW * TH) __attribute__((amdgpu_waves_per_eu(3)))
-k_adjoint(const RepArgs* __restrict__ Units, int n_units, unsigned long long* work) {
+k_adjoint(const RepArgs* __restrict__ Units, int n_units, int stack, unsigned long long* work) {
   using SH = Shape<TW, TH>;
   extern __shared__ uint32_t s_dyn[];
   __shared__ int s_cnt[SH::WAVES];
   const RepArgs& A = unit_of(Units, n_units);
   const uint32_t iter = iteration_of(A.key);
   if (A.h.max_iter && iter >= A.h.max_iter) return;  // finished problem
-  adjoint_tile<SH>(A, G(A.scene), iter, s_dyn, s_cnt, work);
+  const TravStack st{s_dyn + threadIdx.x, SH::N};
+  adjoint_tile<SH, kMesh>(A, G(A.scene), iter, s_dyn + (kMesh ? stack * SH::N : 0), s_cnt, st,
+                          work);
 }
 
 // ---------------------------------------------------------------------------
@@ -923,13 +938,23 @@ hipError_t launch_philox(const uint32_t* ctr, size_t n, uint64_t key, uint32_t* 
   return hipGetLastError();
 }
 
-hipError_t launch_forward(const FwdArgs* U, int n, uint32_t blocks, int shape,
+template <int TW, int TH>
+static void fwd_launch(const FwdArgs* U, int n, uint32_t blocks, int stack,
+                       unsigned long long* work, hipStream_t st) {
+  const size_t lds = (size_t)stack * TW * TH * 4;
+  if (stack > 0)
+    hipLaunchKernelGGL((k_forward<TW, TH, true>), dim3(blocks), dim3(TW * TH), lds, st, U, n, work);
+  else
+    hipLaunchKernelGGL((k_forward<TW, TH, false>), dim3(blocks), dim3(TW * TH), 0, st, U, n, work);
+}
+hipError_t launch_forward(const FwdArgs* U, int n, uint32_t blocks, int shape, int stack,
                           unsigned long long* work, hipStream_t st) {
   if (n <= 0 || blocks == 0) return hipSuccess;
+  if (stack < 0 || stack > kBvhMaxStack) return hipErrorInvalidValue;
   switch (shape) {
-    case 0: hipLaunchKernelGGL((k_forward<16, 16>), dim3(blocks), dim3(256), 0, st, U, n, work); break;
-    case 1: hipLaunchKernelGGL((k_forward<16, 8>), dim3(blocks), dim3(128), 0, st, U, n, work); break;
-    case 2: hipLaunchKernelGGL((k_forward<8, 8>), dim3(blocks), dim3(64), 0, st, U, n, work); break;
+    case 0: fwd_launch<16, 16>(U, n, blocks, stack, work, st); break;
+    case 1: fwd_launch<16, 8>(U, n, blocks, stack, work, st); break;
+    case 2: fwd_launch<8, 8>(U, n, blocks, stack, work, st); break;
     default: return hipErrorInvalidValue;
   }
   return hipGetLastError();
@@ -947,14 +972,26 @@ size_t adjoint_lds_bytes(int n_ch) {
   return table > xchg ? table : xchg;
 }
 
+template <int TW, int TH>
+static void adj_launch(const RepArgs* U, int n, uint32_t blocks, size_t lds, int stack,
+                       unsigned long long* work, hipStream_t st) {
+  if (stack > 0)
+    hipLaunchKernelGGL((k_adjoint<TW, TH, true>), dim3(blocks), dim3(TW * TH),
+                       lds + (size_t)stack * TW * TH * 4, st, U, n, stack, work);
+  else
+    hipLaunchKernelGGL((k_adjoint<TW, TH, false>), dim3(blocks), dim3(TW * TH), lds, st, U, n, 0,
+                       work);
+}
+
 hipError_t launch_adjoint(const RepArgs* U, int n, uint32_t blocks, int shape, size_t lds,
-                          unsigned long long* work, hipStream_t st) {
+                          int stack, unsigned long long* work, hipStream_t st) {
   if (n <= 0 || blocks == 0) return hipSuccess;
   if (lds < adjoint_lds_bytes(0) || lds > adjoint_lds_bytes(5)) return hipErrorInvalidValue;
+  if (stack < 0 || stack > kBvhMaxStack) return hipErrorInvalidValue;
   switch (shape) {
-    case 0: hipLaunchKernelGGL((k_adjoint<16, 16>), dim3(blocks), dim3(256), lds, st, U, n, work); break;
-    case 1: hipLaunchKernelGGL((k_adjoint<16, 8>), dim3(blocks), dim3(128), lds, st, U, n, work); break;
-    case 2: hipLaunchKernelGGL((k_adjoint<8, 8>), dim3(blocks), dim3(64), lds, st, U, n, work); break;
+    case 0: adj_launch<16, 16>(U, n, blocks, lds, stack, work, st); break;
+    case 1: adj_launch<16, 8>(U, n, blocks, lds, stack, work, st); break;
+    case 2: adj_launch<8, 8>(U, n, blocks, lds, stack, work, st); break;
     default: return hipErrorInvalidValue;
   }
   return hipGetLastError();
