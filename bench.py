@@ -265,6 +265,90 @@ def batched_throughput(ctx_problem, args):
     }
 
 
+def mesh_workloads(context, args):
+    """Throughput of the mesh workloads (BVH traversal): the 1024x1024,
+    200,000-triangle displaced sphere with per-vertex RGB + roughness
+    (replayed adjoint of one sample per pixel, and a full meta-estimator step),
+    and the 2048x2048 scene of a 1.0M-triangle terrain + 32 spheres with a
+    512x512x5 texture (meta-estimator step, depth 12)."""
+    import torch
+    from paper_2309_15676_amd import _lib as L
+    from paper_2309_15676_amd import inputs as I
+    from paper_2309_15676_amd.problem import Problem
+    ctx = context.bind()
+    out = {}
+
+    def timed(fn, n):
+        for _ in range(2):
+            fn()
+        torch.cuda.synchronize()
+        L.check(L.jso_set_timing(ctx, True), ctx)
+        for k in range(L.JSO_K_COUNT):
+            L.jso_get_kernel_time(ctx, k, reset=True)
+        e0, e1 = torch.cuda.Event(enable_timing=True), torch.cuda.Event(enable_timing=True)
+        e0.record()
+        for _ in range(n):
+            fn()
+        e1.record()
+        torch.cuda.synchronize()
+        kt = {name: L.jso_get_kernel_time(ctx, k)[0] / n for k, name in
+              ((L.JSO_K_FORWARD, "forward"), (L.JSO_K_FINALIZE, "finalize"),
+               (L.JSO_K_ADJOINT, "adjoint"), (L.JSO_K_META, "meta"))}
+        L.check(L.jso_set_timing(ctx, False), ctx)
+        return e0.elapsed_time(e1) / n, kt
+
+    t0 = time.time()
+    spec = I.scene_mesh_sphere()
+    prob = Problem(spec, context=context)
+    load_s = time.time() - t0
+    gt = I.vertex_fourier_params(spec, 1)
+    init = I.uniform_params(spec, 2, 0.2, 0.8)
+    prob.set_target(prob.render(gt, seed=12345, iteration=0, tag=L.JSO_TAG_TARGET, spp=64))
+    prob.set_params(init)
+    npix = spec.n_pixels
+    dimg = torch.zeros(spec.height, spec.width, 3, device="cuda") + 0.25
+    g = torch.zeros(spec.n_params, device="cuda")
+    init_t = torch.from_numpy(init).cuda()
+    ms_bwd, kt_bwd = timed(lambda: prob.render_bwd(init_t, dimg, 9, 1, L.JSO_TAG_EVAL, 1, out=g),
+                           args.mesh_steps)
+    opts = L.step_opts(optimizer=L.JSO_OPT_META, eta=0.01, seed=args.seed)
+    ms_step, kt_step = timed(lambda: prob.grad_step(opts), args.mesh_steps)
+    out["sphere_200k"] = {
+        "workload": "1024x1024, displaced geodesic sphere of 200,000 triangles on a grey "
+                    "plane, per-vertex RGB + roughness (400,008 params), depth 8, roulette "
+                    "from vertex 3",
+        "scene_load_s": load_s,
+        "adjoint_1spp": {"ms": ms_bwd, "diff_paths_per_s": npix / (ms_bwd / 1e3),
+                         "kernel_ms": kt_bwd},
+        "meta_step": {"ms": ms_step, "diff_paths_per_s": 4 * npix / (ms_step / 1e3),
+                      "kernel_ms": kt_step},
+    }
+    print("[bench] mesh sphere: %s" % json.dumps(out["sphere_200k"]), file=sys.stderr, flush=True)
+    del prob
+    torch.cuda.empty_cache()
+
+    t0 = time.time()
+    spec, gt, init = I.config_large()
+    prob = Problem(spec, context=context)
+    load_s = time.time() - t0
+    prob.set_target(prob.render(gt, seed=12345, iteration=0, tag=L.JSO_TAG_TARGET, spp=16))
+    prob.set_params(init)
+    npix = spec.n_pixels
+    ms_step, kt_step = timed(lambda: prob.grad_step(opts), max(2, args.mesh_steps // 2))
+    out["terrain_1m"] = {
+        "workload": "2048x2048, fractal terrain of 999,698 triangles + 32 spheres, 512x512 "
+                    "texture of RGB + metalness + roughness (1,310,720 params), depth 12, "
+                    "roulette from vertex 3, meta-estimator 2 prop + 1 FD spp",
+        "scene_load_s": load_s,
+        "meta_step": {"ms": ms_step, "diff_paths_per_s": 4 * npix / (ms_step / 1e3),
+                      "kernel_ms": kt_step},
+    }
+    print("[bench] terrain: %s" % json.dumps(out["terrain_1m"]), file=sys.stderr, flush=True)
+    del prob
+    torch.cuda.empty_cache()
+    return out
+
+
 def main():
     ap = argparse.ArgumentParser(description=__doc__.split("\n")[0])
     ap.add_argument("--gpus", type=int, default=1)
@@ -285,6 +369,8 @@ def main():
     ap.add_argument("--batch-steps", type=int, default=20,
                     help="iterations timed for the 64-problem batch (0: skip it)")
     ap.add_argument("--batch-target-spp", type=int, default=256)
+    ap.add_argument("--mesh-steps", type=int, default=10,
+                    help="timed calls per mesh workload (0 = skip the mesh workloads)")
     args = ap.parse_args()
     if args.gpus != 1:
         print("bench.py: this build runs on one GPU; --gpus %d is not supported "
@@ -361,6 +447,10 @@ def main():
         print("[bench] 64-problem batch", file=sys.stderr, flush=True)
         bat = batched_throughput(prob, args)
         print("[bench] batch: %s" % json.dumps(bat), file=sys.stderr, flush=True)
+    mesh = None
+    if args.mesh_steps > 0:
+        print("[bench] mesh workloads", file=sys.stderr, flush=True)
+        mesh = mesh_workloads(prob.context, args)
     ttl = None
     if args.ttl_iters > 0:
         print("[bench] time to loss: Adam-64 vs meta-estimator", file=sys.stderr, flush=True)
@@ -419,6 +509,7 @@ def main():
         "cpu_baseline": cpu,
         "time_to_loss": ttl,
         "batched": bat,
+        "meshes": mesh,
     }
     print(json.dumps(line))
 

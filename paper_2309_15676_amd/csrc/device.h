@@ -368,15 +368,19 @@ struct Footprint {
   float fx, fy;
 };
 
-// Weight of element q (0..3) of the footprint.
+// Weight of element q (0..3) of the footprint.  kMesh = false: the scene has
+// no mesh, so no footprint is a triangle's.
+template <bool kMesh>
 __device__ __forceinline__ float footprint_weight(const Footprint& fp, int q) {
-  if (fp.tri) return q == 0 ? (1.0f - fp.fx) - fp.fy : (q == 1 ? fp.fx : (q == 2 ? fp.fy : 0.0f));
+  if (kMesh && fp.tri)
+    return q == 0 ? (1.0f - fp.fx) - fp.fy : (q == 1 ? fp.fx : (q == 2 ? fp.fy : 0.0f));
   return ((q & 1) ? fp.fx : 1.0f - fp.fx) * ((q & 2) ? fp.fy : 1.0f - fp.fy);
 }
 
+template <bool kMesh>
 __device__ __forceinline__ void texel_weights(const Footprint& fp, float w[4]) {
 #pragma unroll
-  for (int q = 0; q < 4; ++q) w[q] = footprint_weight(fp, q);
+  for (int q = 0; q < 4; ++q) w[q] = footprint_weight<kMesh>(fp, q);
 }
 
 // Bilinear, clamp-to-edge; texel centres at (i + 0.5) / size.
@@ -409,6 +413,7 @@ struct Surf {
 
 // Material at a surface point.  Returns true for the parameterised material
 // (then fp is its footprint); fixed materials return false.
+template <bool kMesh>
 __device__ __forceinline__ bool material_at(const DevScene& S, const float* __restrict__ params,
                                             const Surf& x, Mat& M, Footprint& fp) {
   const int mat = x.kind == HIT_PLANE ? S.plane_mat
@@ -435,7 +440,7 @@ __device__ __forceinline__ bool material_at(const DevScene& S, const float* __re
       val[b] = S.slot[b] >= 0 ? pv : S.defaults[b];
     }
   } else {
-    if (x.kind == HIT_MESH && S.layout == JSO_LAYOUT_VERTEX) {
+    if (kMesh && x.kind == HIT_MESH && S.layout == JSO_LAYOUT_VERTEX) {
       fp.global = 0;
       fp.tri = 1;
       fp.t00 = x.vid[0];
@@ -445,7 +450,7 @@ __device__ __forceinline__ bool material_at(const DevScene& S, const float* __re
       fp.fy = x.bv;
     } else {
       float u, v;
-      if (x.kind == HIT_PLANE || x.kind == HIT_MESH) {
+      if (x.kind == HIT_PLANE || (kMesh && x.kind == HIT_MESH)) {
         u = (x.p.x - S.plane_x0) / (S.plane_x1 - S.plane_x0);
         v = (x.p.z - S.plane_z0) / (S.plane_z1 - S.plane_z0);
       } else {
@@ -456,10 +461,10 @@ __device__ __forceinline__ bool material_at(const DevScene& S, const float* __re
       fp = footprint_uv(S, u, v);
     }
     float w[4];
-    texel_weights(fp, w);
+    texel_weights<kMesh>(fp, w);
     const int nc = S.n_ch;
     // the fourth element of a triangle footprint has weight 0 and is not read
-    const int t11 = fp.tri ? fp.t00 : fp.t01 + fp.t10 - fp.t00;
+    const int t11 = (kMesh && fp.tri) ? fp.t00 : fp.t01 + fp.t10 - fp.t00;
 #pragma unroll
     for (int b = 0; b < 5; ++b) {
       const int s = S.slot[b];
@@ -700,7 +705,7 @@ __device__ __forceinline__ void path_vertex(const DevScene& S, const TravStack& 
   const V3 p = x.p, n = x.n;
   const V3 wo = mk(-P.d.x, -P.d.y, -P.d.z);
   Mat M;
-  vg.valid = material_at(S, params, x, M, vg.fp);
+  vg.valid = material_at<kMesh>(S, params, x, M, vg.fp);
   vg.j = j;
   if (kGrad) {
 #pragma unroll

@@ -409,16 +409,18 @@ __device__ __forceinline__ int table_slot(const GradTable& T, uint32_t texel) {
 // Element q of the footprint (q = 0..3: t00, t01, t10, t01 + t10 - t00) and
 // its weight, computed arithmetically so no per-lane array is indexed.  A
 // triangle's fourth element has weight 0 and is never touched.
+template <bool kMesh>
 __device__ __forceinline__ void footprint_texel(const Footprint& fp, int q, int& texel,
                                                 float& w) {
   const int dx = fp.t01 - fp.t00, dy = fp.t10 - fp.t00;
   texel = fp.t00 + (q & 1) * dx + (q >> 1) * dy;
-  w = footprint_weight(fp, q);
+  w = footprint_weight<kMesh>(fp, q);
 }
 
 // Add one first-hit vertex's material gradient g (R, G, B, metal, rough) to
 // its four texels in the block table (global atomics when a probe sequence is
 // congested).
+template <bool kMesh>
 __device__ __forceinline__ void scatter_texels(const DevScene& S, const GradTable& T,
                                                const Footprint& fp, const float g[5],
                                                float sign) {
@@ -427,7 +429,7 @@ __device__ __forceinline__ void scatter_texels(const DevScene& S, const GradTabl
   for (int q = 0; q < 4; ++q) {
     int texel;
     float w;
-    footprint_texel(fp, q, texel, w);
+    footprint_texel<kMesh>(fp, q, texel, w);
     if (w == 0.0f) continue;
     const int h = table_slot(T, (uint32_t)texel);
 #pragma unroll
@@ -450,6 +452,7 @@ __device__ __forceinline__ void scatter_texels(const DevScene& S, const GradTabl
 // spreads each vertex over 4 * n_ch lanes, neighbouring lanes taking the
 // neighbouring channels of one texel: a texel then costs one transaction
 // instead of n_ch.  Must be reached by all 64 lanes of the wave.
+template <bool kMesh>
 __device__ __forceinline__ void scatter_wave(const DevScene& S, float* __restrict__ grad,
                                              const VertexGrad& v, float sign, bool has) {
   uint64_t m = __ballot(has);
@@ -469,7 +472,7 @@ __device__ __forceinline__ void scatter_wave(const DevScene& S, float* __restric
     const int src = work ? __ffsll((unsigned long long)mm) - 1 : lane;
     Footprint fp;
     fp.global = 0;
-    fp.tri = __shfl(v.fp.tri, src, 64);
+    fp.tri = kMesh ? __shfl(v.fp.tri, src, 64) : 0;
     fp.t00 = __shfl(v.fp.t00, src, 64);
     fp.t01 = __shfl(v.fp.t01, src, 64);
     fp.t10 = __shfl(v.fp.t10, src, 64);
@@ -484,7 +487,7 @@ __device__ __forceinline__ void scatter_wave(const DevScene& S, float* __restric
     if (work) {
       int texel;
       float w;
-      footprint_texel(fp, q, texel, w);
+      footprint_texel<kMesh>(fp, q, texel, w);
       const float val = w * (sign * gc);
       if (w != 0.0f && val != 0.0f) unsafeAtomicAdd(grad + (size_t)texel * nc + c, val);
     }
@@ -512,6 +515,7 @@ struct Sink {
     for (int b = 0; b < 5; ++b) acc[b] = 0.0f;
   }
   // returns true when v is a later textured vertex left to scatter_wave
+  template <bool kMesh>
   __device__ __forceinline__ bool add(const DevScene& S, const VertexGrad& v, float sign) {
     if (!v.valid) return false;
     if (v.fp.global) {
@@ -520,7 +524,7 @@ struct Sink {
       return false;
     }
     if (v.j > 1) return true;
-    scatter_texels(S, T, v.fp, v.g, sign);
+    scatter_texels<kMesh>(S, T, v.fp, v.g, sign);
     return false;
   }
   // every lane of the block (nthreads), after a barrier; neighbouring lanes
@@ -635,8 +639,8 @@ __device__ __forceinline__ void adjoint_tile(const RepArgs& A, const DevScene* _
       }
     }
     // first vertices (j = 1) go to the table
-    sink.add(S, va, pair ? 1.0f : sl.sign);
-    sink.add(S, vb, -1.0f);
+    sink.template add<kMesh>(S, va, pair ? 1.0f : sl.sign);
+    sink.template add<kMesh>(S, vb, -1.0f);
   }
   __syncthreads();
   sink.flush_table(S, SH::N);
@@ -672,8 +676,8 @@ __device__ __forceinline__ void adjoint_tile(const RepArgs& A, const DevScene* _
           ++n_vert;
           path_vertex<true, kMesh>(S, st, G(sl.params), wr, A.flags, W.P, W.adj, v);
         }
-        const bool later = sink.add(S, v, sl.sign);
-        scatter_wave(S, G(sl.grad), v, sl.sign, later);
+        const bool later = sink.template add<kMesh>(S, v, sl.sign);
+        scatter_wave<kMesh>(S, G(sl.grad), v, sl.sign, later);
       }
     }
   } else {
@@ -721,10 +725,10 @@ __device__ __forceinline__ void adjoint_tile(const RepArgs& A, const DevScene* _
           for (int q = 0; q < 5; ++q) va.g[q] -= vb.g[q];
           vb.valid = false;
         }
-        const bool later_a = sink.add(S, va, 1.0f);
-        const bool later_b = sink.add(S, vb, -1.0f);
-        scatter_wave(S, G(sl.grad), va, 1.0f, later_a);
-        scatter_wave(S, G(sl.grad), vb, -1.0f, later_b);
+        const bool later_a = sink.template add<kMesh>(S, va, 1.0f);
+        const bool later_b = sink.template add<kMesh>(S, vb, -1.0f);
+        scatter_wave<kMesh>(S, G(sl.grad), va, 1.0f, later_a);
+        scatter_wave<kMesh>(S, G(sl.grad), vb, -1.0f, later_b);
       }
     }
   }

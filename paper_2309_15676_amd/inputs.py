@@ -284,20 +284,45 @@ def icosphere(freq: int, center=(0.0, 1.2, 0.0), radius: float = 1.0, disp: floa
     return v, np.array(tris, np.int32)
 
 
-def heightfield(n: int, extent=(-5.0, 5.0, -5.0, 5.0), amp: float = 0.4, seed: int = 0):
-    """n x n quads (2 n^2 triangles) over the plane extent, height
-    amp * (1 + smooth field of (x, z) / extent) >= 0."""
+def heightfield(n: int, extent=(-5.0, 5.0, -5.0, 5.0), amp: float = 0.4, seed: int = 0,
+                octaves: int = 1):
+    """n x n quads (2 n^2 triangles) over the plane extent.  Height
+    amp * (1 + f(x, z)) >= 0 with f the smooth field of the normalised (x, z);
+    with octaves > 1, a fractal sum: octave o adds 0.5^o f_o(2^o (x, z)) of
+    its own random field, and the sum is rescaled into (-1, 1)."""
     x0, x1, z0, z1 = extent
     xs, zs = np.linspace(x0, x1, n + 1), np.linspace(z0, z1, n + 1)
     X, Z = np.meshgrid(xs, zs)
     pts = np.stack([(X - x0) / (x1 - x0), np.zeros_like(X), (Z - z0) / (z1 - z0)], -1).reshape(-1, 3)
-    Y = amp * (1.0 + smooth_field_3d(pts, rng(seed)))
+    Y = amp * (1.0 + fbm_field(pts, seed, octaves))
     v = np.stack([X.reshape(-1), Y, Z.reshape(-1)], -1)
     idx = np.arange((n + 1) * (n + 1)).reshape(n + 1, n + 1)
     a, b, c, d = idx[:-1, :-1], idx[:-1, 1:], idx[1:, :-1], idx[1:, 1:]
     tris = np.concatenate([np.stack([a, c, b], -1).reshape(-1, 3),
                            np.stack([b, c, d], -1).reshape(-1, 3)])
     return v, tris.astype(np.int32)
+
+
+def fbm_field(p: np.ndarray, seed: int, octaves: int = 1) -> np.ndarray:
+    """Fractal sum of smooth fields (octave o: weight 0.5^o, frequency 2^o),
+    in (-1, 1); one octave is the smooth field itself."""
+    g = rng(seed)
+    if octaves == 1:
+        return smooth_field_3d(p, g)
+    s = np.zeros(p.shape[0])
+    w = 0.0
+    for o in range(octaves):
+        s += 0.5 ** o * smooth_field_3d(p * 2.0 ** o, g)
+        w += 0.5 ** o
+    return s / w
+
+
+def terrain_height(spec_extent, amp: float, seed: int, octaves: int, x, z):
+    """Height of the heightfield surface (before triangulation) at (x, z)."""
+    x0, x1, z0, z1 = spec_extent
+    pts = np.stack([(np.asarray(x) - x0) / (x1 - x0), np.zeros_like(np.asarray(x, float)),
+                    (np.asarray(z) - z0) / (z1 - z0)], -1).reshape(-1, 3)
+    return amp * (1.0 + fbm_field(pts, seed, octaves))
 
 
 def vertex_fourier_params(spec: SceneSpec, seed: int, lo: float = 0.1, hi: float = 0.9):
@@ -317,6 +342,33 @@ def scene_mesh_sphere(width: int = 1024, height: int = 1024, freq: int = 100, se
                      verts=v, tris=t, mesh_mat=MAT_PARAM, param_layout=LAYOUT_VERTEX,
                      depth=depth, rr_start=rr_start, ch_mask=CH_RGB_ROUGH,
                      fixed_default=(0.5, 0.5, 0.5, 0.0, 0.5))
+
+
+def scene_terrain(width: int = 2048, height: int = 2048, n: int = 707, n_spheres: int = 32,
+                  tex: int = 512, seed: int = 0, depth: int = 12, rr_start: int = 3,
+                  amp: float = 0.4, octaves: int = 5) -> SceneSpec:
+    """Large scene: a fractal heightfield terrain of 2 n^2 triangles over the
+    plane extent (the plane itself disabled) and n_spheres spheres (radii
+    U[0.15, 0.45], non-overlapping, resting on the terrain); all share one
+    tex x tex texture of all five channels (RGB, metalness, roughness), mapped
+    to the terrain by planar UV and to the spheres by latitude-longitude."""
+    v, t = heightfield(n, amp=amp, seed=seed, octaves=octaves)
+    g = rng(seed + 1)
+    sph = place_spheres(n_spheres, g, 0.15, 0.45, xr=(-4.0, 4.0), zr=(-4.0, 3.0))
+    ext = SceneSpec(width=1, height=1).plane_extent
+    sph[:, 1] = terrain_height(ext, amp, seed, octaves, sph[:, 0], sph[:, 2]) + sph[:, 3]
+    return SceneSpec(width=width, height=height, plane_enabled=False, verts=v, tris=t,
+                     mesh_mat=MAT_PARAM, spheres=sph,
+                     sphere_mat=np.full((n_spheres,), MAT_PARAM, np.int32), depth=depth,
+                     rr_start=rr_start, tex_w=tex, tex_h=tex, ch_mask=CH_ALL)
+
+
+def config_large(seed_scene: int = 0, seed_gt: int = 1, seed_init: int = 2, **kw):
+    """2048 x 2048 terrain problem: 1.0M-triangle terrain + 32 spheres, a
+    512 x 512 texture of 5 channels (1,310,720 parameters); ground truth =
+    random-Fourier textures, initial texels ~U[0.2, 0.8]."""
+    s = scene_terrain(seed=seed_scene, **kw)
+    return s, fourier_params(s, seed_gt), uniform_params(s, seed_init, 0.2, 0.8)
 
 
 def config_batched(n: int = 64, seed: int = 0):

@@ -126,14 +126,14 @@ def test_mesh_fd_sample_bitwise_zero_for_equal_params(ctx):
 def test_mesh_sphere_full_size_sampled(ctx):
     """The 200,000-triangle displaced sphere at 1024 x 1024 (per-vertex RGB +
     roughness, depth 8, roulette from vertex 3), in the launch configuration of
-    a full optimisation step; radiance and gradients of a 8 x 8 crop against
-    the oracle's brute force over every triangle."""
+    a full optimisation step; radiance and gradients of a 16 x 16 crop centred
+    on the sphere against the oracle's brute force over every triangle."""
     import torch
     _say("mesh sphere 200k, crop")
     spec = I.scene_mesh_sphere()
     assert len(spec.tris) == 200000 and spec.width == 1024
     p = I.vertex_fourier_params(spec, 1)
-    crop = (508, 470, 516, 478)
+    crop = (504, 466, 520, 482)
     prob = _problem(ctx, spec)
     img = prob.render(p, seed=5, iteration=3, tag=O.TAG_EVAL, spp=1, crop=crop).cpu().numpy()
     pd = p.astype(np.float64)
@@ -160,6 +160,41 @@ def test_mesh_sphere_full_size_sampled(ctx):
                          mask=torch.from_numpy(mask.reshape(-1)).cuda())
     _check_grad(gg.cpu().numpy().astype(np.float64), gref, gabs, gfl[0], "render_bwd", spec)
     assert np.count_nonzero(gref) > 20
+
+
+def test_mesh_sphere_adjoint_matches_central_differences(ctx):
+    """Replayed adjoint of the full 1024 x 1024, 200,000-triangle scene (one
+    sample per pixel, fixed seed) against central differences of the rendered
+    loss J = sum dimg . I with h = 1e-3 on 64 random per-vertex parameters.
+    Sampling that does not depend on the parameters makes J smooth in them;
+    J(p + h) - J(p - h) is summed in FP64 from the two FP32 images, whose
+    untouched pixels are bit-identical."""
+    import torch
+    from paper_2309_15676_amd import _lib as L
+    _say("mesh sphere 200k, central differences")
+    spec = I.scene_mesh_sphere()
+    prob = _problem(ctx, spec)
+    p = I.vertex_fourier_params(spec, 1)
+    dimg = torch.from_numpy(I.target_image_synthetic(spec, 3) - 0.75).cuda()
+    seed, it, tag, spp, flags = 9, 1, L.JSO_TAG_EVAL, 1, O.PARAM_INDEP
+    g = prob.render_bwd(p, dimg, seed, it, tag, spp, flags=flags).cpu().numpy()
+    live = np.flatnonzero(np.abs(g) > 1e-3 * np.abs(g).max())
+    assert len(live) > 1000
+    idx = np.random.Generator(np.random.PCG64(2)).choice(live, 64, replace=False)
+    h = 1e-3
+    d64 = dimg.double()
+    worst = 0.0
+    for i in idx:
+        pp, pm = p.copy(), p.copy()
+        pp[i] += h
+        pm[i] -= h
+        a = prob.render(pp, seed, it, tag, spp, flags=flags).double()
+        b = prob.render(pm, seed, it, tag, spp, flags=flags).double()
+        cd = float(((a - b) * d64).sum()) / (2 * h)
+        err = abs(cd - g[i]) / abs(g[i])
+        worst = max(worst, err)
+        assert err <= 2e-2, (i, cd, g[i])
+    print("central differences: worst relative error %.2e" % worst, flush=True)
 
 
 def test_mesh_scene_errors(ctx):
