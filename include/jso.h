@@ -145,6 +145,12 @@ typedef struct {
   int adam_spp;        /* adam: samples per pixel                                  */
   uint64_t seed;       /* base seed of all random streams                          */
   uint32_t flags;      /* JSO_F_* test modes                                       */
+  float precond_lambda; /* > 0: replace each texture-gradient sample g (per channel)
+                           by (I + lambda L)^-1 g, L the Laplacian of the 4-neighbour
+                           texel grid (Large Steps, Nicolet et al. 2021, as used for
+                           the texture tasks of the Experiments section); 0 = off.
+                           Problems with a 1x1 texture are unaffected; per-vertex
+                           parameters are rejected.                                */
 } jso_step_opts;
 
 typedef struct {
@@ -207,6 +213,15 @@ int jso_get_params(jso_ctx* ctx, int scene_id, float* p, size_t n, int mem);
 int jso_get_params_prev(jso_ctx* ctx, int scene_id, float* p, size_t n, int mem);
 /* Target image (n = H*W*3). */
 int jso_set_target(jso_ctx* ctx, int scene_id, const float* img, size_t n, int mem);
+
+/* Texture-gradient preconditioner (Large Steps; Nicolet, Jacobson, Jakob 2021,
+ * cited in the Experiments section for texture tasks): g (dev, n_params) is
+ * replaced in place, channel by channel, by the solution y of
+ * (I + lambda L) y = g, L = degree minus adjacency of the 4-neighbour
+ * tex_h x tex_w grid.  Solved exactly in the grid's cosine basis (which
+ * diagonalises L), in FP32.  lambda >= 0; a 1x1 texture is left unchanged.
+ * Errors: JSO_E_INVALID (bad id, null g, lambda < 0, per-vertex layout). */
+int jso_precondition(jso_ctx* ctx, int scene_id, float* g, float lambda);
 
 /* ---- rendering and differentiation (rows a2-a6) ---------------------------- */
 
@@ -314,7 +329,8 @@ int jso_set_tile_shape(jso_ctx* ctx, int shape);
 #define JSO_K_META 2     /* fused meta-estimator step                       */
 #define JSO_K_ADAM 3     /* Adam step                                       */
 #define JSO_K_FINALIZE 4 /* primal images, adjoint images and loss          */
-#define JSO_K_COUNT 5
+#define JSO_K_PRECOND 5  /* texture-gradient preconditioner passes          */
+#define JSO_K_COUNT 6
 
 /* Enable (1) or disable (0) HIP-event timing of every kernel this context
  * launches (events are recorded on the context's stream around each launch). */

@@ -36,11 +36,12 @@ EXPORTED = [
     "jso_meta_step", "jso_adam_step", "jso_grad_step", "jso_get_state", "jso_set_state",
     "jso_set_timing", "jso_get_kernel_time", "jso_set_work_counting", "jso_get_work",
     "jso_batch_create", "jso_batch_step", "jso_batch_active", "jso_batch_destroy",
-    "jso_batch_autotune", "jso_set_tile_shape",
+    "jso_batch_autotune", "jso_set_tile_shape", "jso_precondition",
 ]
 JSO_TILE_16x16, JSO_TILE_16x8, JSO_TILE_8x8, JSO_TILE_SHAPES = 0, 1, 2, 3
 JSO_K_FORWARD, JSO_K_ADJOINT, JSO_K_META, JSO_K_ADAM, JSO_K_FINALIZE = 0, 1, 2, 3, 4
-JSO_K_COUNT = 5
+JSO_K_PRECOND = 5
+JSO_K_COUNT = 6
 
 
 class JsoError(RuntimeError):
@@ -80,7 +81,7 @@ class jso_step_opts(ctypes.Structure):
         ("beta_D", ctypes.c_float), ("spp_prop", ctypes.c_int), ("spp_fd", ctypes.c_int),
         ("adam_beta1", ctypes.c_float), ("adam_beta2", ctypes.c_float),
         ("adam_eps", ctypes.c_float), ("adam_spp", ctypes.c_int), ("seed", ctypes.c_uint64),
-        ("flags", ctypes.c_uint32),
+        ("flags", ctypes.c_uint32), ("precond_lambda", ctypes.c_float),
     ]
 
 
@@ -151,6 +152,7 @@ def load() -> ctypes.CDLL:
         "jso_batch_destroy": (I, [P]),
         "jso_batch_autotune": (I, [P, I, ctypes.POINTER(I), ctypes.POINTER(D)]),
         "jso_set_tile_shape": (I, [P, I]),
+        "jso_precondition": (I, [P, I, P, F]),
     }
     for name, (res, args) in sig.items():
         fn = getattr(L, name)
@@ -338,13 +340,18 @@ def jso_adam_step(ctx, sid, g_ptr, eta, beta1=0.9, beta2=0.999, eps=1e-8) -> int
 
 
 def step_opts(optimizer=JSO_OPT_META, eta=1e-3, beta_F=0.99, beta_D=0.9, spp_prop=2, spp_fd=1,
-              adam_beta1=0.9, adam_beta2=0.999, adam_eps=1e-8, adam_spp=64, seed=0, flags=0):
+              adam_beta1=0.9, adam_beta2=0.999, adam_eps=1e-8, adam_spp=64, seed=0, flags=0,
+              precond_lambda=0.0):
     o = jso_step_opts()
     o.optimizer, o.eta, o.beta_F, o.beta_D = optimizer, eta, beta_F, beta_D
     o.spp_prop, o.spp_fd = spp_prop, spp_fd
     o.adam_beta1, o.adam_beta2, o.adam_eps, o.adam_spp = adam_beta1, adam_beta2, adam_eps, adam_spp
-    o.seed, o.flags = seed, flags
+    o.seed, o.flags, o.precond_lambda = seed, flags, precond_lambda
     return o
+
+
+def jso_precondition(ctx, sid: int, g_ptr: int, lam: float) -> int:
+    return load().jso_precondition(ctx, sid, g_ptr, lam)
 
 
 def jso_grad_step(ctx, sids, opts, want_stats=False):

@@ -44,6 +44,11 @@ struct SceneGPU {
   float* bvh_tris = nullptr;
   int* bvh_tri_id = nullptr;
   int stack = 0;                   // traversal-stack entries its mesh needs (0: no mesh)
+  // texture-gradient preconditioner (textures larger than 1x1): orthonormal
+  // cosine-transform matrices C_W (W x W), C_H (H x H) and the eigenvalues of
+  // the path-graph Laplacians, 2 - 2 cos(pi k / n), for both axes
+  float* pc = nullptr;
+  float* pc_tmp = nullptr;         // 2 x P scratch (one per gradient vector)
   uint32_t host_iter = 0;          // mirror of ctl->iteration
   uint64_t generation = 0;         // unique per loaded scene (plan cache key)
 };
@@ -262,7 +267,7 @@ void free_scene_buffers(SceneGPU* s) {
                   s->delta,  s->mean,        s->var,    s->alpha_prev, s->m2F,
                   s->m2D,    s->adam_m,      s->adam_v, s->ctl,    s->scratch_loss,
                   s->partials, s->slots,     s->accum,  s->d_scene, s->bvh_nodes,
-                  s->bvh_tris, s->bvh_tri_id};
+                  s->bvh_tris, s->bvh_tri_id, s->pc, s->pc_tmp};
   for (void* b : bufs)
     if (b) (void)hipFree(b);
 }
@@ -395,6 +400,38 @@ int build_devscene(jso_ctx* c, const jso_scene_desc* d, SceneGPU* s) {
 
 // Build the mesh hierarchy on the host and upload it; fills the scene's
 // device pointers.
+// Tables of the texture-gradient preconditioner: the orthonormal DCT-II
+// matrices of both texture axes (row k: s_k cos(pi k (i + 1/2) / n)), which
+// diagonalise the Laplacians of the path graphs along the axes, and their
+// eigenvalues 2 - 2 cos(pi k / n).
+int upload_precond(jso_ctx* c, SceneGPU* s) {
+  const DevScene& S = s->dev;
+  if (S.layout != JSO_LAYOUT_TEXTURE || S.tex_w * S.tex_h <= 1) return JSO_OK;
+  const int W = S.tex_w, H = S.tex_h;
+  std::vector<float> t((size_t)W * W + (size_t)H * H + W + H);
+  auto fill = [](float* m, float* eig, int n) {
+    for (int k = 0; k < n; ++k) {
+      const double sk = std::sqrt((k == 0 ? 1.0 : 2.0) / n);
+      for (int i = 0; i < n; ++i) m[(size_t)k * n + i] = (float)(sk * std::cos(M_PI * k * (i + 0.5) / n));
+      eig[k] = (float)(2.0 - 2.0 * std::cos(M_PI * k / n));
+    }
+  };
+  float* cw = t.data();
+  float* ch = cw + (size_t)W * W;
+  float* mu = ch + (size_t)H * H;
+  float* nu = mu + W;
+  fill(cw, mu, W);
+  fill(ch, nu, H);
+  hipError_t e = dalloc(&s->pc, t.size());
+  if (e == hipSuccess) e = dalloc(&s->pc_tmp, 2 * s->P);
+  if (e == hipSuccess)
+    e = hipMemcpy(s->pc, t.data(), t.size() * sizeof(float), hipMemcpyHostToDevice);
+  if (e != hipSuccess)
+    return fail(c, e == hipErrorOutOfMemory ? JSO_E_OOM : JSO_E_HIP, "preconditioner: %s",
+                hipGetErrorString(e));
+  return JSO_OK;
+}
+
 int upload_mesh(jso_ctx* c, const jso_scene_desc* d, SceneGPU* s) {
   if (d->n_tris == 0) return JSO_OK;
   BvhBuild b;
@@ -511,7 +548,7 @@ struct ProbPlan {
   int na;
 };
 
-enum class Kern { Forward, Finalize, Adjoint, Meta, Adam };
+enum class Kern { Forward, Finalize, Adjoint, Meta, Adam, Dct };
 
 struct LaunchRec {
   Kern kind;
@@ -720,6 +757,75 @@ void plan_estimators(const std::vector<ProbPlan>& ps, Plan& plan, int shape = 0)
   }
 }
 
+// The four cosine-transform passes that replace vec by (I + lambda L)^-1 vec
+// (along W, along H with the spectral scaling, back along H, back along W),
+// as units appended to rec[0..3]; tmp holds P floats.
+void push_precond(LaunchRec rec[4], SceneGPU* s, float* vec, float* tmp, float lambda,
+                  uint32_t max_iter) {
+  const DevScene& S = s->dev;
+  const int W = S.tex_w, H = S.tex_h, C = S.n_ch;
+  const float* cw = s->pc;
+  const float* ch = cw + (size_t)W * W;
+  const float* mu = ch + (size_t)H * H;
+  const float* nu = mu + W;
+  auto tiles = [](int n) { return (uint32_t)((n + kDctTile - 1) / kDctTile); };
+  for (int pass = 0; pass < 4; ++pass) {
+    DctArgs a{};
+    a.h.max_iter = max_iter;
+    const bool along_w = pass == 0 || pass == 3;
+    a.A = gmem(along_w ? cw : ch);
+    a.transA = pass >= 2;
+    a.in = gmem((const float*)(pass % 2 == 0 ? vec : tmp));
+    a.out = gmem(pass % 2 == 0 ? tmp : vec);
+    if (along_w) {  // element (w, (h, c)) at w C + h W C + c
+      a.n = W;
+      a.N = H * C;
+      a.sk = C;
+      a.jin = C;
+      a.sjo = W * C;
+    } else {        // element (h, (w, c)) at h W C + (w C + c)
+      a.n = H;
+      a.N = W * C;
+      a.sk = W * C;
+      a.jin = W * C;
+      a.sjo = 0;
+    }
+    if (pass == 1) {
+      a.eig_m = gmem(nu);
+      a.eig_j = gmem(mu);
+      a.jdiv = C;
+      a.lambda = lambda;
+    } else {
+      a.jdiv = 1;
+    }
+    a.tiles_j = tiles(a.N);
+    push_unit(rec[pass], a, tiles(a.n) * a.tiles_j);
+  }
+}
+
+bool preconditioned(const SceneGPU* s) {
+  return s->dev.layout == JSO_LAYOUT_TEXTURE && s->dev.tex_w * s->dev.tex_h > 1;
+}
+
+// Preconditioner launches of a step: both gradient samples of the
+// meta-estimator (or Adam's gradient) of every textured problem.
+void plan_precond(const std::vector<ProbPlan>& ps, const jso_step_opts& o, Plan& plan) {
+  if (!(o.precond_lambda > 0.0f)) return;
+  LaunchRec rec[4];
+  for (LaunchRec& r : rec) {
+    r.kind = Kern::Dct;
+    r.timer = JSO_K_PRECOND;
+  }
+  for (const ProbPlan& p : ps) {
+    if (!preconditioned(p.s)) continue;
+    push_precond(rec, p.s, p.s->F, p.s->pc_tmp, o.precond_lambda, p.max_iter);
+    if (o.optimizer == JSO_OPT_META && o.spp_fd > 0)
+      push_precond(rec, p.s, p.s->dF, p.s->pc_tmp + p.s->P, o.precond_lambda, p.max_iter);
+  }
+  if (rec[0].n == 0) return;
+  for (LaunchRec& r : rec) plan.push_back(std::move(r));
+}
+
 uint32_t meta_blocks(size_t P) {
   const size_t want = (P + (size_t)kMetaBlock * kMetaK - 1) / ((size_t)kMetaBlock * kMetaK);
   return (uint32_t)std::min<size_t>(std::max<size_t>(want, 1), kMetaMaxBlocks);
@@ -837,6 +943,8 @@ ProbPlan step_problem(SceneGPU* s, const jso_step_opts& o, uint32_t flags, uint3
 }
 
 int check_step_opts(jso_ctx* c, const jso_step_opts* o) {
+  if (!(o->precond_lambda >= 0.0f && std::isfinite(o->precond_lambda)))
+    return fail(c, JSO_E_INVALID, "precond_lambda must be finite and >= 0");
   if (o->optimizer == JSO_OPT_META) {
     if (o->spp_prop < 1 || o->spp_prop > 64 || o->spp_fd < 0 || o->spp_fd > 64)
       return fail(c, JSO_E_INVALID, "spp out of range");
@@ -850,6 +958,14 @@ int check_step_opts(jso_ctx* c, const jso_step_opts* o) {
   } else {
     return fail(c, JSO_E_INVALID, "unknown optimizer %d", o->optimizer);
   }
+  return JSO_OK;
+}
+
+int check_precond_layout(jso_ctx* c, const std::vector<SceneGPU*>& ss, const jso_step_opts& o) {
+  if (!(o.precond_lambda > 0.0f)) return JSO_OK;
+  for (SceneGPU* s : ss)
+    if (s->dev.layout != JSO_LAYOUT_TEXTURE)
+      return fail(c, JSO_E_INVALID, "preconditioning needs texture parameters");
   return JSO_OK;
 }
 
@@ -868,6 +984,8 @@ hipError_t launch_rec(const LaunchRec& r, const void* dev_units, unsigned long l
       return launch_meta(static_cast<const MetaArgs*>(dev_units), r.n, r.blocks, st);
     case Kern::Adam:
       return launch_adam(static_cast<const AdamArgs*>(dev_units), r.n, r.blocks, st);
+    case Kern::Dct:
+      return launch_dct(static_cast<const DctArgs*>(dev_units), r.n, r.blocks, st);
   }
   return hipErrorInvalidValue;
 }
@@ -893,6 +1011,7 @@ uint64_t config_hash(const std::vector<SceneGPU*>& ss, const jso_step_opts& o) {
     mix((uint64_t)s->P);
     mix((uint64_t)s->dev.depth);
     mix((uint64_t)s->dev.n_tris);
+    mix((uint64_t)(o.precond_lambda > 0.0f && preconditioned(s)));
   }
   return h;
 }
@@ -1124,6 +1243,7 @@ int jso_load_scene(jso_ctx* c, const jso_scene_desc* d, int* scene_id) {
                 hipGetErrorString(e));
   }
   rc = upload_mesh(c, d, s.get());
+  if (rc == JSO_OK) rc = upload_precond(c, s.get());
   if (rc) {
     free_scene_buffers(s.get());
     return rc;
@@ -1270,6 +1390,25 @@ int jso_estimate_gradients(jso_ctx* c, int id, uint64_t seed, uint32_t iteration
   return JSO_OK;
 }
 
+int jso_precondition(jso_ctx* c, int id, float* g, float lambda) {
+  SceneGPU* s = get_scene(c, id);
+  if (!s) return c ? fail(c, JSO_E_INVALID, "bad scene id %d", id) : JSO_E_INVALID;
+  if (!g) return fail(c, JSO_E_INVALID, "null gradient");
+  if (!(lambda >= 0.0f && std::isfinite(lambda)))
+    return fail(c, JSO_E_INVALID, "lambda must be finite and >= 0");
+  if (s->dev.layout != JSO_LAYOUT_TEXTURE)
+    return fail(c, JSO_E_INVALID, "preconditioning needs texture parameters");
+  if (!preconditioned(s) || lambda == 0.0f) return JSO_OK;
+  DeviceGuard dg(c->device);
+  LaunchRec rec[4];
+  for (LaunchRec& r : rec) {
+    r.kind = Kern::Dct;
+    r.timer = JSO_K_PRECOND;
+  }
+  push_precond(rec, s, g, s->pc_tmp, lambda, 0);
+  return exec_plan(c, Plan{rec[0], rec[1], rec[2], rec[3]});
+}
+
 int jso_meta_step(jso_ctx* c, int id, const float* F, const float* dF, float eta, float beta_F,
                   float beta_D) {
   SceneGPU* s = get_scene(c, id);
@@ -1347,17 +1486,20 @@ int jso_grad_step(jso_ctx* c, const int* ids, int n, const jso_step_opts* o,
     sig.push_back(get_scene(c, ids[k])->generation);
     ss.push_back(get_scene(c, ids[k]));
   }
+  rc = check_precond_layout(c, ss, *o);
+  if (rc) return rc;
   const int shape = chosen_shape(c, config_hash(ss, *o));
   sig.push_back((uint64_t)shape);
   for (uint64_t v : {(uint64_t)o->optimizer, bits(o->eta), bits(o->beta_F), bits(o->beta_D),
                      (uint64_t)o->spp_prop, (uint64_t)o->spp_fd, bits(o->adam_beta1),
                      bits(o->adam_beta2), bits(o->adam_eps), (uint64_t)o->adam_spp, o->seed,
-                     (uint64_t)flags})
+                     (uint64_t)flags, bits(o->precond_lambda)})
     sig.push_back(v);
   rc = exec_cached(c, sig, [&](Plan& plan) {
     std::vector<ProbPlan> ps;
     for (int k = 0; k < n; ++k) ps.push_back(step_problem(get_scene(c, ids[k]), *o, flags, 0));
     plan_estimators(ps, plan, shape);
+    plan_precond(ps, *o, plan);
     plan_optimizer(ps, *o, plan);
   });
   if (rc) return rc;
@@ -1430,6 +1572,7 @@ int batch_build(jso_batch* b, int shape) {
     ps.push_back(step_problem(s, b->opts, b->flags, b->max_iters[k]));
   }
   plan_estimators(ps, b->plan, shape);
+  plan_precond(ps, b->opts, b->plan);
   plan_optimizer(ps, b->opts, b->plan);
   const std::vector<uint8_t> all = pack_plan(b->plan, b->off);
   HIP_TRY(c, hipMalloc(reinterpret_cast<void**>(&b->dev), all.size()));
@@ -1525,6 +1668,8 @@ int jso_batch_create(jso_ctx* c, const int* ids, int n, const jso_step_opts* o,
   b->use_graph = use_graph != 0;
   std::vector<SceneGPU*> ss;
   for (int k = 0; k < n; ++k) ss.push_back(get_scene(c, ids[k]));
+  rc = check_precond_layout(c, ss, *o);
+  if (rc) return rc;
   b->hash = config_hash(ss, *o);
   rc = batch_build(b.get(), chosen_shape(c, b->hash));
   if (rc) return rc;

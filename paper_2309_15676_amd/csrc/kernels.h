@@ -180,8 +180,29 @@ struct AdamArgs {
   int zero_grads;
 };
 
+// One pass of the texture-gradient preconditioner: a cosine transform along
+// one texture axis, out(m, j) = sum_k A[m][k] in(k, j) (A^T with transA),
+// optionally scaled by 1 / (1 + lambda (eig_m[m] + eig_j[j / jdiv])).  Element
+// (k, j) of a vector lives at k * sk + (j / jin) * sjo + (j % jin).  One unit =
+// one vector of one problem; it owns tiles_m * tiles_j blocks of kDctTile^2
+// outputs.
+struct DctArgs {
+  UnitHead h;
+  JSO_GMEM const float* A;      // n x n, row-major
+  JSO_GMEM const float* in;
+  JSO_GMEM float* out;          // never aliases in
+  JSO_GMEM const float* eig_m;  // n entries, or null: no scaling
+  JSO_GMEM const float* eig_j;
+  int n, N, sk, jin, sjo, jdiv, transA;
+  float lambda;
+  uint32_t tiles_j;
+};
+constexpr int kDctTile = 64;   // outputs per block side
+constexpr int kDctBlock = 256;
+
 hipError_t launch_philox(const uint32_t* ctr, size_t n, uint64_t key, uint32_t* out,
                          hipStream_t st);
+hipError_t launch_dct(const DctArgs* U, int n, uint32_t blocks, hipStream_t st);
 // Unit arrays U[n] in device memory; `blocks` = the total grid size.
 // work (nullable): forward [2] += paths traced, [3] += surface vertices;
 // adjoint [0] += paths replayed, [1] += surface vertices.

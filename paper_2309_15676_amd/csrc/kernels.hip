@@ -918,6 +918,77 @@ __global__ void __launch_bounds__(kMetaBlock) k_adam(const AdamArgs* __restrict_
   }
 }
 
+// ---------------------------------------------------------------------------
+// texture-gradient preconditioner: one cosine-transform pass
+// ---------------------------------------------------------------------------
+// 64 x 64 outputs per block, k in chunks of 16 staged through LDS; each
+// thread accumulates a 4 x 4 patch (rows m, columns j) in FP32.
+constexpr int kDctK = 16;
+
+__device__ __forceinline__ size_t dct_addr(const DctArgs& U, int k, int j) {
+  return (size_t)k * U.sk + (size_t)(j / U.jin) * U.sjo + (size_t)(j % U.jin);
+}
+
+__global__ void __launch_bounds__(kDctBlock) k_dct(const DctArgs* __restrict__ Units,
+                                                   int n_units) {
+  __shared__ float s_a[kDctK][kDctTile + 1];
+  __shared__ float s_b[kDctK][kDctTile + 1];
+  const DctArgs& U = unit_of(Units, n_units);
+  const uint32_t local = blockIdx.x - U.h.block0;
+  const int m0 = (int)(local / U.tiles_j) * kDctTile, j0 = (int)(local % U.tiles_j) * kDctTile;
+  const int tid = (int)threadIdx.x;
+  const int tx = tid % 16, ty = tid / 16;  // outputs: rows m0 + ty + 16 r, columns j0 + tx + 16 q
+  const float* A = G(U.A);
+  const float* in = G(U.in);
+  float acc[4][4];
+#pragma unroll
+  for (int r = 0; r < 4; ++r)
+#pragma unroll
+    for (int q = 0; q < 4; ++q) acc[r][q] = 0.0f;
+  for (int k0 = 0; k0 < U.n; k0 += kDctK) {
+    // stage A[m0 .. m0+63][k0 .. k0+15] and in(k0 .. k0+15, j0 .. j0+63)
+#pragma unroll
+    for (int e = tid; e < kDctK * kDctTile; e += kDctBlock) {
+      const int kk = e % kDctK, mm = e / kDctK;
+      const int m = m0 + mm, k = k0 + kk;
+      float a = 0.0f;
+      if (m < U.n && k < U.n) a = U.transA ? A[(size_t)k * U.n + m] : A[(size_t)m * U.n + k];
+      s_a[kk][mm] = a;
+      const int jj = e % kDctTile, kb = e / kDctTile;
+      const int j = j0 + jj, kr = k0 + kb;
+      s_b[kb][jj] = (j < U.N && kr < U.n) ? in[dct_addr(U, kr, j)] : 0.0f;
+    }
+    __syncthreads();
+#pragma unroll
+    for (int kk = 0; kk < kDctK; ++kk) {
+      float a[4], b[4];
+#pragma unroll
+      for (int r = 0; r < 4; ++r) a[r] = s_a[kk][ty + 16 * r];
+#pragma unroll
+      for (int q = 0; q < 4; ++q) b[q] = s_b[kk][tx + 16 * q];
+#pragma unroll
+      for (int r = 0; r < 4; ++r)
+#pragma unroll
+        for (int q = 0; q < 4; ++q) acc[r][q] = fmaf(a[r], b[q], acc[r][q]);
+    }
+    __syncthreads();
+  }
+  float* out = G(U.out);
+#pragma unroll
+  for (int r = 0; r < 4; ++r) {
+    const int m = m0 + ty + 16 * r;
+    if (m >= U.n) continue;
+#pragma unroll
+    for (int q = 0; q < 4; ++q) {
+      const int j = j0 + tx + 16 * q;
+      if (j >= U.N) continue;
+      float v = acc[r][q];
+      if (G(U.eig_m)) v /= 1.0f + U.lambda * (G(U.eig_m)[m] + G(U.eig_j)[j / U.jdiv]);
+      out[dct_addr(U, m, j)] = v;
+    }
+  }
+}
+
 __global__ void k_fill_f64(double* p, size_t n, double v) {
   const size_t i = (size_t)blockIdx.x * blockDim.x + threadIdx.x;
   if (i < n) p[i] = v;
@@ -998,6 +1069,12 @@ hipError_t launch_adjoint(const RepArgs* U, int n, uint32_t blocks, int shape, s
     case 2: adj_launch<8, 8>(U, n, blocks, lds, stack, work, st); break;
     default: return hipErrorInvalidValue;
   }
+  return hipGetLastError();
+}
+
+hipError_t launch_dct(const DctArgs* U, int n, uint32_t blocks, hipStream_t st) {
+  if (n <= 0 || blocks == 0) return hipSuccess;
+  hipLaunchKernelGGL(k_dct, dim3(blocks), dim3(kDctBlock), 0, st, U, n);
   return hipGetLastError();
 }
 

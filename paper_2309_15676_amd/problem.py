@@ -134,6 +134,15 @@ class Problem:
         return dict(F=F, dF=dF, img=img, loss=loss)
 
     # -- optimisation -------------------------------------------------------
+    def precondition(self, g: torch.Tensor, lam: float) -> torch.Tensor:
+        """(I + lam L)^-1 g per channel on the texel grid, in place (g: device
+        float32 tensor of n_params)."""
+        assert g.is_cuda and g.dtype == torch.float32 and g.is_contiguous()
+        assert g.numel() == self.n_params
+        L.check(L.jso_precondition(self.ctx, self.sid, g.data_ptr(), lam), self.context.ctx,
+                "jso_precondition")
+        return g
+
     def meta_step(self, F: torch.Tensor, dF: torch.Tensor, eta: float, beta_F: float = 0.99,
                   beta_D: float = 0.9) -> None:
         L.check(L.jso_meta_step(self.ctx, self.sid, _dptr(F.contiguous()),
