@@ -116,11 +116,19 @@ def copy_calibration(mib: int):
     torch.cuda.synchronize()
 
 
-def time_to_loss(prob, init, gt, target, args, iters: int, label: str):
-    """Wall-clock (grad_step calls only; evaluations off the clock) for the
-    meta-estimator at 2 proportional + 1 FD spp to reach the best evaluation
-    loss plain Adam at 64 spp reaches within `iters` iterations, each method
-    with its best learning rate from a small grid; same GPU, same process."""
+def time_to_loss(prob, init, gt, target, args, iters: int, label: str, lam: float = 0.0,
+                 etas=None):
+    """Loss against wall-clock (grad_step calls only; evaluations off the
+    clock) of plain Adam at 64 spp and of the meta-estimator at 2 proportional
+    + 1 FD spp, same GPU, same process.  Adam runs `iters` iterations; the
+    meta-estimator gets the same wall-clock budget.  Each method uses the
+    learning rate of a small grid that reaches its lowest loss.
+
+    Reported: the time each needs to reach Adam's best loss (speedup, or null
+    when the meta-estimator does not reach it within its budget), and the
+    same for the losses Adam reaches after 1/8, 1/4 and 1/2 of its
+    iterations (speedup_by_level).  lam > 0: both methods precondition their
+    texture gradients (Large Steps)."""
     import torch
 
     from paper_2309_15676_amd import _lib as L
@@ -136,12 +144,12 @@ def time_to_loss(prob, init, gt, target, args, iters: int, label: str):
 
     floor = eval_loss(gt)  # the evaluation's own noise: loss at the ground truth
 
-    def run(opts, n, stop_at=None):
+    def run(opts, n, every, seconds=None):
         prob.set_params(init)  # also resets the optimiser state
         e0, e1 = torch.cuda.Event(enable_timing=True), torch.cuda.Event(enable_timing=True)
         clock, hist = 0.0, [(0, 0.0, eval_loss())]
         done = 0
-        while done < n:
+        while done < n and (seconds is None or clock < seconds):
             k = min(every, n - done)
             torch.cuda.synchronize()
             e0.record()
@@ -152,45 +160,54 @@ def time_to_loss(prob, init, gt, target, args, iters: int, label: str):
             clock += e0.elapsed_time(e1) / 1e3
             done += k
             hist.append((done, clock, eval_loss()))
-            if stop_at is not None and hist[-1][2] <= stop_at:
-                break
         return hist
 
-    grid = [float(x) for x in args.ttl_etas.split(",")]
+    def first(hist, level):
+        return next(((h[0], h[1]) for h in hist if h[2] <= level), (None, None))
+
+    grid = etas or [float(x) for x in args.ttl_etas.split(",")]
     adam = {}
     for eta in grid:
-        o = L.step_opts(optimizer=L.JSO_OPT_ADAM, eta=eta, adam_spp=64, seed=args.seed + 1)
-        adam[eta] = run(o, iters)
+        o = L.step_opts(optimizer=L.JSO_OPT_ADAM, eta=eta, adam_spp=64, seed=args.seed + 1,
+                        precond_lambda=lam)
+        adam[eta] = run(o, iters, every)
     best_eta = min(adam, key=lambda e: min(h[2] for h in adam[e]))
     ha = adam[best_eta]
     target_loss = min(h[2] for h in ha)
-    it_adam, t_adam = next((h[0], h[1]) for h in ha if h[2] <= target_loss)
+    it_adam, t_adam = first(ha, target_loss)
+    budget_s = ha[-1][1]
     meta = {}
     for eta in grid:
         o = L.step_opts(optimizer=L.JSO_OPT_META, eta=eta, beta_F=0.99, beta_D=0.9, spp_prop=2,
-                        spp_fd=1, seed=args.seed + 2)
-        meta[eta] = run(o, args.ttl_meta_factor * iters, stop_at=target_loss)
-    ok = {e: next(h for h in meta[e] if h[2] <= target_loss) for e in grid
-          if any(h[2] <= target_loss for h in meta[e])}
-    if ok:
-        m_eta = min(ok, key=lambda e: ok[e][1])
-        it_meta, t_meta = ok[m_eta][0], ok[m_eta][1]
-    else:
-        m_eta = min(meta, key=lambda e: min(h[2] for h in meta[e]))
-        it_meta, t_meta = None, None
+                        spp_fd=1, seed=args.seed + 2, precond_lambda=lam)
+        meta[eta] = run(o, 10 ** 9, every * 4, seconds=budget_s)
+    m_eta = min(meta, key=lambda e: min(h[2] for h in meta[e]))
+    hm = meta[m_eta]
+    it_meta, t_meta = first(hm, target_loss)
+    levels = {}
+    for frac in (8, 4, 2):
+        lv = next(h[2] for h in ha if h[0] >= iters // frac)
+        ia, ta = first(ha, lv)
+        im, tm = first(hm, lv)
+        levels["adam_iters_%d" % (iters // frac)] = {
+            "loss": lv, "adam_seconds": ta, "meta_seconds": tm, "meta_iterations": im,
+            "speedup": (ta / tm) if tm else None}
     return {
         "workload": label,
         "evaluation": "L2 of a %d-spp render (fixed evaluation stream) against the target, "
-                      "every %d iterations, off the clock" % (ev_spp, every),
+                      "off the clock" % ev_spp,
         "target_loss": target_loss,
         "loss_at_ground_truth": floor,
         "adam": {"spp": 64, "eta": best_eta, "iterations": it_adam, "seconds": t_adam,
                  "best_loss_by_eta": {str(e): min(h[2] for h in adam[e]) for e in grid},
-                 "iteration_budget": iters},
+                 "iteration_budget": iters, "seconds_budget": budget_s},
         "meta": {"spp": "2 prop + 1 FD", "eta": m_eta, "iterations": it_meta, "seconds": t_meta,
+                 "best_loss": min(h[2] for h in hm), "iterations_run": hm[-1][0],
                  "best_loss_by_eta": {str(e): min(h[2] for h in meta[e]) for e in grid},
-                 "iteration_budget": args.ttl_meta_factor * iters},
+                 "seconds_budget": budget_s},
         "speedup": (t_adam / t_meta) if t_meta else None,
+        "speedup_by_level": levels,
+        "precond_lambda": lam,
     }
 
 
@@ -360,12 +377,13 @@ def main():
     ap.add_argument("--copy-mib", type=int, default=0,
                     help="also run a plain copy of this many MiB (counter calibration)")
     ap.add_argument("--seed", type=int, default=4)
-    ap.add_argument("--ttl-iters", type=int, default=500,
+    ap.add_argument("--ttl-iters", type=int, default=300,
                     help="Adam-64 iteration budget of the textured time-to-loss comparison "
-                         "(0: skip both comparisons)")
-    ap.add_argument("--ttl-meta-factor", type=int, default=4,
-                    help="meta-estimator iteration budget, in multiples of --ttl-iters")
+                         "(0: skip the comparisons)")
     ap.add_argument("--ttl-etas", default="0.003,0.01,0.03,0.1")
+    ap.add_argument("--ttl-lambda", type=float, default=20.0,
+                    help="also compare both methods with preconditioned texture gradients "
+                         "(Large Steps) at this lambda (0: skip)")
     ap.add_argument("--batch-steps", type=int, default=20,
                     help="iterations timed for the 64-problem batch (0: skip it)")
     ap.add_argument("--batch-target-spp", type=int, default=256)
@@ -470,6 +488,13 @@ def main():
             "the 512x512 textured problem (262,144 texel parameters, no preconditioning)")
         print("[bench] time to loss: %s" % json.dumps(ttl["textured"]), file=sys.stderr,
               flush=True)
+        if args.ttl_lambda > 0:
+            ttl["textured_preconditioned"] = time_to_loss(
+                prob, init, gt, target, args, args.ttl_iters,
+                "the 512x512 textured problem, both methods with Large-Steps preconditioned "
+                "texture gradients", lam=args.ttl_lambda, etas=[0.01, 0.03, 0.1, 0.3])
+            print("[bench] time to loss: %s" % json.dumps(ttl["textured_preconditioned"]),
+                  file=sys.stderr, flush=True)
     # roofline of the dominant kernel: algorithmic FP32 work per launch over
     # its average launch time
     cands = {
