@@ -34,7 +34,7 @@ TAG_TARGET, TAG_PRIMAL_PROP, TAG_ADJ_PROP = 1, 2, 3
 TAG_PRIMAL_FD, TAG_ADJ_FD = 4, 5
 TAG_ADAM_PRIMAL, TAG_ADAM_ADJ, TAG_EVAL = 6, 7, 8
 
-NO_NEE, LAMBERT_ONLY, PARAM_INDEP, PIXEL_CENTER = 1, 2, 4, 8
+NO_NEE, LAMBERT_ONLY, PARAM_INDEP, PIXEL_CENTER, RELATIVE_LOSS = 1, 2, 4, 8, 16
 
 
 def build(force: bool = False) -> str:

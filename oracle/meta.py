@@ -40,25 +40,40 @@ STEP_EPS = 1e-8     # epsilon of the stabilised step
 
 class Moment2:
     """Zero-centred second moment, exponential moving average with start-up
-    bias correction: after `count` steps the weights of the samples sum to 1."""
+    bias correction: after `count` steps the weights of the samples sum to 1.
 
-    def __init__(self, shape, decay: float):
+    centred=True is the ablation of the Experiments section ("Zero-centred
+    EMAs"): the same weights also average x, and the variance is the second
+    moment minus the squared mean (floored at 0)."""
+
+    def __init__(self, shape, decay: float, centred: bool = False):
         self.decay = float(decay)
         self.count = 0
+        self.centred = centred
         self.m2 = np.zeros(shape, np.float64)
+        self.m1 = np.zeros(shape, np.float64)
 
     def step(self, x: np.ndarray) -> None:
         self.count += 1
         w = 1.0 - self.decay
         w_sum = 1.0 - self.decay ** self.count
-        self.m2 = self.m2 + (w / w_sum) * (np.asarray(x, np.float64) ** 2 - self.m2)
+        x = np.asarray(x, np.float64)
+        self.m2 = self.m2 + (w / w_sum) * (x ** 2 - self.m2)
+        self.m1 = self.m1 + (w / w_sum) * (x - self.m1)
+
+    @property
+    def var(self) -> np.ndarray:
+        if not self.centred:
+            return self.m2
+        return np.maximum(self.m2 - self.m1 ** 2, 0.0)
 
 
 class Meta:
     """Recurrent meta-estimator <F_i>_M with its variance, and the step of Eq. 21."""
 
-    def __init__(self, shape, eta: float):
+    def __init__(self, shape, eta: float, clip: bool = True):
         self.eta = float(eta)
+        self.clip = clip  # False: the "Alpha clipping" ablation of the Experiments section
         self.mean = np.zeros(shape, np.float64)
         self.var = np.zeros(shape, np.float64)
         self.alpha_prev = np.full(shape, -np.inf)
@@ -70,7 +85,8 @@ class Meta:
         self.var = self.var + var_dF
         # inverse-variance weight (Eq. 8), clipped (Eq. 17)
         alpha = var_F / (var_F + self.var + ALPHA_EPS)
-        alpha = np.minimum(alpha, 1.0 / (2.0 - self.alpha_prev))
+        if self.clip:
+            alpha = np.minimum(alpha, 1.0 / (2.0 - self.alpha_prev))
         self.alpha_prev = alpha
         self.alpha = alpha
         # combine (Eq. 7) and propagate the variance (Eq. 15)
@@ -81,33 +97,39 @@ class Meta:
 
 
 class MetaOptimizer:
-    """One problem's optimisation loop state (supplement: optimisation loop)."""
+    """One problem's optimisation loop state (supplement: optimisation loop).
+
+    Ablations of the Experiments section: centred (non-zero-centred variance
+    EMAs), clip=False (no alpha clipping); and, in step(), separate samples
+    F_var / dF_var for the variance EMAs ("Sample reuse": uncorrelated
+    variance samples instead of the ones the estimate is made of)."""
 
     def __init__(self, params, lo, hi, eta: float = 1e-3, beta_F: float = 0.99,
-                 beta_D: float = 0.9):
+                 beta_D: float = 0.9, centred: bool = False, clip: bool = True):
         self.params = np.asarray(params, np.float32).copy()
         self.params_prev = self.params.copy()
         self.lo = np.asarray(lo, np.float32)
         self.hi = np.asarray(hi, np.float32)
         n = self.params.shape
-        self.var_F = Moment2(n, beta_F)
-        self.var_D = Moment2(n, beta_D)
-        self.meta = Meta(n, eta)
+        self.var_F = Moment2(n, beta_F, centred)
+        self.var_D = Moment2(n, beta_D, centred)
+        self.meta = Meta(n, eta, clip)
         self.iteration = 0
         self.step_norm2 = 0.0   # ||pi_i - pi_{i-1}||^2 of the step that produced pi_i
 
-    def step(self, F, dF) -> np.ndarray:
+    def step(self, F, dF, F_var=None, dF_var=None) -> np.ndarray:
         F = np.asarray(F, np.float64)
         n2 = self.step_norm2
-        self.var_F.step(F)
+        self.var_F.step(F if F_var is None else F_var)
         if self.iteration >= 1 and n2 > 0.0:
             dF = np.asarray(dF, np.float64)
-            self.var_D.step(dF / math.sqrt(n2))
-            var_dF = self.var_D.m2 * n2
+            xd = dF if dF_var is None else np.asarray(dF_var, np.float64)
+            self.var_D.step(xd / math.sqrt(n2))
+            var_dF = self.var_D.var * n2
         else:
             dF = np.zeros_like(F)
             var_dF = np.zeros_like(F)
-        d = self.meta.step(F, dF, self.var_F.m2, var_dF)
+        d = self.meta.step(F, dF, self.var_F.var, var_dF)
         new = np.clip((self.params.astype(np.float64) + d).astype(np.float32), self.lo, self.hi)
         diff = new.astype(np.float64) - self.params.astype(np.float64)
         self.step_norm2 = float(np.sum(diff * diff))

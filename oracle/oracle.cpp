@@ -19,6 +19,7 @@ namespace {
 constexpr double PI = 3.14159265358979323846;
 constexpr double INF = std::numeric_limits<double>::infinity();
 constexpr double RAY_EPS = 1e-4;      // origin offset along the normal
+constexpr double REL_EPS = 0.01;  // relative loss: (I - T)^2 / (T^2 + REL_EPS)
 constexpr double SHADOW_EPS = 1e-4;   // shadow rays stop this short of the light
 constexpr double ROUGH_MIN = 0.05;    // roughness floor of the material model
 constexpr double P_SPEC = 0.5;        // probability of sampling the specular lobe
@@ -946,13 +947,17 @@ int orc_grad(const orc_scene* s, const double* params, uint64_t seed, uint32_t i
   std::vector<double> I(3 * npix, 0.0), mg(npix, INF), dimg(3 * npix, 0.0);
   orc_render(s, params, seed, iteration, tag_primal, spp, flags, crop, I.data(), mg.data(),
              nthreads);
-  // L = sum (I - T)^2 / (3 W H)  ->  dL/dI = 2 (I - T) / (3 W H)
+  // L = sum (I - T)^2 / (3 W H)  ->  dL/dI = 2 (I - T) / (3 W H); the relative
+  // form divides each term by T^2 + REL_EPS (a constant per pixel, so the
+  // primal from its own stream keeps the gradient sample unbiased)
   const double norm = 2.0 / (3.0 * (double)npix);
+  const bool relative = (flags & ORC_RELATIVE_LOSS) != 0;
   for (int y = c.y0; y < c.y1; ++y)
     for (int x = c.x0; x < c.x1; ++x)
       for (int k = 0; k < 3; ++k) {
         size_t i = 3 * ((size_t)y * s->width + x) + k;
-        dimg[i] = norm * (I[i] - target[i]);
+        const double w = relative ? 1.0 / (target[i] * target[i] + REL_EPS) : 1.0;
+        dimg[i] = norm * (I[i] - target[i]) * w;
       }
   int rc = grad_common(s, params, stream_key(seed, iteration, tag_adj), spp, dimg.data(), flags,
                        c, mask, grad, gabs, mg.data(), adj_img, nthreads);

@@ -61,7 +61,9 @@ enum {
   ORC_NO_NEE = 1,           /* no light sampling; BSDF-sampled light hits weigh 1 */
   ORC_LAMBERT_ONLY = 2,     /* f = c / pi, cosine sampling                         */
   ORC_PARAM_INDEP = 4,      /* both lobes sampled by the cosine density           */
-  ORC_PIXEL_CENTER = 8      /* no pixel jitter                                     */
+  ORC_PIXEL_CENTER = 8,     /* no pixel jitter                                     */
+  ORC_RELATIVE_LOSS = 16    /* orc_grad: relative squared error
+                               (I - T)^2 / (T^2 + 0.01) instead of (I - T)^2       */
 };
 
 uint64_t orc_splitmix64(uint64_t x);
