@@ -65,6 +65,23 @@ extern "C" {
 #define JSO_TAG_ADAM_PRIMAL 6
 #define JSO_TAG_ADAM_ADJ 7
 #define JSO_TAG_EVAL 8
+/* separate variance samples of the "uncorrelated samples" ablation */
+#define JSO_TAG_VAR_PRIMAL_PROP 9
+#define JSO_TAG_VAR_ADJ_PROP 10
+#define JSO_TAG_VAR_PRIMAL_FD 11
+#define JSO_TAG_VAR_ADJ_FD 12
+
+/* image loss (jso_render_opts.loss, jso_step_opts.loss) */
+#define JSO_LOSS_L2 0       /* sum (I - T)^2 / (3 W H)                             */
+#define JSO_LOSS_RELATIVE 1 /* sum (I - T)^2 / (T^2 + 0.01) / (3 W H): the relative
+                               squared error of the Experiments section, normalised
+                               by the target so each pixel's weight is a constant */
+
+/* meta-estimator ablations of the Experiments section (jso_step_opts.ablate) */
+#define JSO_ABLATE_CENTRED 1      /* variance EMAs subtract their squared mean    */
+#define JSO_ABLATE_NO_CLIP 2      /* no alpha clipping (Eq. 17)                   */
+#define JSO_ABLATE_UNCORRELATED 4 /* variance EMAs fed by a second, independent
+                                     proportional + FD sample (tags VAR_*)        */
 
 /* render / test-mode flags (jso_render_opts.flags, jso_set_debug) */
 #define JSO_F_NO_NEE 1       /* no light sampling; BSDF-sampled light hits weigh 1 */
@@ -128,6 +145,7 @@ typedef struct {
   uint32_t flags;            /* JSO_F_*                                          */
   int crop[4];               /* x0, y0, x1, y1; all zero = whole image            */
   const uint8_t* pixel_mask; /* dev, H*W, nonzero = skip the pixel; may be NULL   */
+  int loss;                  /* JSO_LOSS_* of the adjoint image (estimators)        */
 } jso_render_opts;
 
 /* Optimiser of jso_grad_step */
@@ -151,6 +169,8 @@ typedef struct {
                            the texture tasks of the Experiments section); 0 = off.
                            Problems with a 1x1 texture are unaffected; per-vertex
                            parameters are rejected.                                */
+  int loss;             /* JSO_LOSS_*                                               */
+  uint32_t ablate;      /* meta: JSO_ABLATE_* bits (0 = the method as published)    */
 } jso_step_opts;
 
 typedef struct {
@@ -241,8 +261,9 @@ int jso_render_bwd(jso_ctx* ctx, int scene_id, const float* params, uint64_t see
 
 /* ---- estimators (rows a5-a7) ------------------------------------------------ */
 
-/* One iteration's gradient samples for the L2 loss sum (I - T)^2 / (3 W H)
- * against the scene's target, at the scene's pi_i (and pi_{i-1}):
+/* One iteration's gradient samples for the loss opts->loss (L2 by default,
+ * sum (I - T)^2 / (3 W H)) against the scene's target, at the scene's pi_i
+ * (and pi_{i-1}):
  *   F  += <F_i>   spp_prop primal paths (tag PRIMAL_PROP) give the adjoint
  *                 image, spp_prop adjoint paths (tag ADJ_PROP) are replayed;
  *   dF += <dF_i>  the spp_fd primal and adjoint streams (PRIMAL_FD, ADJ_FD)
@@ -250,7 +271,7 @@ int jso_render_bwd(jso_ctx* ctx, int scene_id, const float* params, uint64_t see
  *                 and differenced per vertex (Eq. 5).  Skipped if dF is NULL.
  * F, dF: dev, n_params, accumulated into.  img (dev, H*W*3, nullable) receives
  * the proportional primal image.  iteration selects the random streams.
- * loss (host, nullable) receives the L2 loss of that primal image. */
+ * loss (host, nullable) receives the loss of that primal image. */
 int jso_estimate_gradients(jso_ctx* ctx, int scene_id, uint64_t seed, uint32_t iteration,
                            int spp_prop, int spp_fd, const jso_render_opts* opts, float* F,
                            float* dF, float* img, double* loss);

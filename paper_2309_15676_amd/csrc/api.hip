@@ -49,6 +49,10 @@ struct SceneGPU {
   // the path-graph Laplacians, 2 - 2 cos(pi k / n), for both axes
   float* pc = nullptr;
   float* pc_tmp = nullptr;         // 2 x P scratch (one per gradient vector)
+  // meta-estimator ablations: first moments of centred variance EMAs, and
+  // the separate variance samples of the uncorrelated ablation
+  double *m1F = nullptr, *m1D = nullptr;
+  float *Fv = nullptr, *dFv = nullptr;
   uint32_t host_iter = 0;          // mirror of ctl->iteration
   uint64_t generation = 0;         // unique per loaded scene (plan cache key)
 };
@@ -267,7 +271,8 @@ void free_scene_buffers(SceneGPU* s) {
                   s->delta,  s->mean,        s->var,    s->alpha_prev, s->m2F,
                   s->m2D,    s->adam_m,      s->adam_v, s->ctl,    s->scratch_loss,
                   s->partials, s->slots,     s->accum,  s->d_scene, s->bvh_nodes,
-                  s->bvh_tris, s->bvh_tri_id, s->pc, s->pc_tmp};
+                  s->bvh_tris, s->bvh_tri_id, s->pc, s->pc_tmp, s->m1F,
+                  s->m1D,    s->Fv,          s->dFv};
   for (void* b : bufs)
     if (b) (void)hipFree(b);
 }
@@ -488,6 +493,10 @@ int reset_optimizer(jso_ctx* c, SceneGPU* s) {
   HIP_TRY(c, hipMemsetAsync(s->adam_v, 0, P * sizeof(float), c->stream));
   HIP_TRY(c, hipMemsetAsync(s->F, 0, P * sizeof(float), c->stream));
   HIP_TRY(c, hipMemsetAsync(s->dF, 0, P * sizeof(float), c->stream));
+  HIP_TRY(c, hipMemsetAsync(s->m1F, 0, P * sizeof(double), c->stream));
+  HIP_TRY(c, hipMemsetAsync(s->m1D, 0, P * sizeof(double), c->stream));
+  HIP_TRY(c, hipMemsetAsync(s->Fv, 0, P * sizeof(float), c->stream));
+  HIP_TRY(c, hipMemsetAsync(s->dFv, 0, P * sizeof(float), c->stream));
   HIP_TRY(c, hipMemsetAsync(s->ctl, 0, sizeof(Ctl), c->stream));
   s->host_iter = 0;
   return JSO_OK;
@@ -542,6 +551,7 @@ struct ProbPlan {
   const uint8_t* mask;
   uint32_t flags;
   uint32_t max_iter;  // 0: always active
+  int relative;       // relative loss (JSO_LOSS_RELATIVE)
   PrimalSpec pj[3];
   int np;
   AdjointSpec aj[2];
@@ -702,6 +712,7 @@ void plan_estimators(const std::vector<ProbPlan>& ps, Plan& plan, int shape = 0)
         f.target = gmem((const float*)p.s->target);
         f.delta_scale = (float)(2.0 / (3.0 * (double)p.s->npix));
         f.loss_scale = 1.0 / (3.0 * (double)p.s->npix);
+        f.relative = p.relative;
         const size_t pix = (size_t)(p.crop.x1 - p.crop.x0) * (size_t)(p.crop.y1 - p.crop.y0);
         const size_t want = (pix + kFinBlock - 1) / kFinBlock;
         f.nblocks = (uint32_t)std::min<size_t>(std::max<size_t>(want, 1), kFinMaxBlocks);
@@ -856,6 +867,11 @@ MetaArgs meta_args(SceneGPU* s, const float* F, const float* dF, float eta, floa
   m.beta_D = bD;
   m.eta = eta;
   m.zero_grads = zero_grads;
+  m.ablate = 0;
+  m.m1F = gmem(s->m1F);
+  m.m1D = gmem(s->m1D);
+  m.Fv = gmem(s->Fv);
+  m.dFv = gmem(s->dFv);
   return m;
 }
 
@@ -893,6 +909,7 @@ void plan_optimizer(const std::vector<ProbPlan>& ps, const jso_step_opts& o, Pla
     for (const ProbPlan& p : ps) {
       MetaArgs m = meta_args(p.s, p.s->F, p.s->dF, o.eta, o.beta_F, o.beta_D, 1);
       m.h.max_iter = p.max_iter;
+      m.ablate = o.ablate;
       push_unit(r, m, m.nblocks);
     }
   } else {
@@ -911,6 +928,7 @@ void plan_optimizer(const std::vector<ProbPlan>& ps, const jso_step_opts& o, Pla
 ProbPlan step_problem(SceneGPU* s, const jso_step_opts& o, uint32_t flags, uint32_t max_iter) {
   ProbPlan p{};
   p.s = s;
+  p.relative = o.loss == JSO_LOSS_RELATIVE;
   p.key = KeyArgs{o.seed, 0u, gmem((const uint32_t*)&s->ctl->iteration)};  // the kernels read the device counter
   p.crop = Crop{0, 0, s->width, s->height};
   p.mask = nullptr;
@@ -942,7 +960,39 @@ ProbPlan step_problem(SceneGPU* s, const jso_step_opts& o, uint32_t flags, uint3
   return p;
 }
 
+// The separate variance samples of the uncorrelated ablation: the same
+// estimators as step_problem's meta-estimator jobs on their own streams
+// (VAR_* tags), into Fv / dFv; they reuse the adjoint-image buffers after the
+// main estimators' replay and add nothing to the loss.
+ProbPlan variance_problem(SceneGPU* s, const jso_step_opts& o, uint32_t flags,
+                          uint32_t max_iter) {
+  ProbPlan p = step_problem(s, o, flags, max_iter);
+  const size_t n3 = 3 * s->npix;
+  p.np = p.na = 0;
+  p.pj[p.np++] = PrimalSpec{s->params, JSO_TAG_VAR_PRIMAL_PROP, o.spp_prop, nullptr, s->delta,
+                            nullptr};
+  if (o.spp_fd > 0) {
+    p.pj[p.np++] = PrimalSpec{s->params, JSO_TAG_VAR_PRIMAL_FD, o.spp_fd, nullptr, s->delta + n3,
+                              nullptr};
+    p.pj[p.np++] = PrimalSpec{s->params_prev, JSO_TAG_VAR_PRIMAL_FD, o.spp_fd, nullptr,
+                              s->delta + 2 * n3, nullptr};
+  }
+  p.aj[p.na++] = AdjointSpec{s->params, nullptr, s->delta, nullptr, s->Fv, 1.0f,
+                             JSO_TAG_VAR_ADJ_PROP, o.spp_prop};
+  if (o.spp_fd > 0)
+    p.aj[p.na++] = AdjointSpec{s->params, s->params_prev, s->delta + n3, s->delta + 2 * n3,
+                               s->dFv, 1.0f, JSO_TAG_VAR_ADJ_FD, o.spp_fd};
+  return p;
+}
+
+bool uncorrelated(const jso_step_opts& o) {
+  return o.optimizer == JSO_OPT_META && (o.ablate & JSO_ABLATE_UNCORRELATED) != 0;
+}
+
 int check_step_opts(jso_ctx* c, const jso_step_opts* o) {
+  if (o->loss != JSO_LOSS_L2 && o->loss != JSO_LOSS_RELATIVE)
+    return fail(c, JSO_E_INVALID, "unknown loss %d", o->loss);
+  if (o->ablate & ~7u) return fail(c, JSO_E_INVALID, "unknown ablation bits 0x%x", o->ablate);
   if (!(o->precond_lambda >= 0.0f && std::isfinite(o->precond_lambda)))
     return fail(c, JSO_E_INVALID, "precond_lambda must be finite and >= 0");
   if (o->optimizer == JSO_OPT_META) {
@@ -1012,6 +1062,7 @@ uint64_t config_hash(const std::vector<SceneGPU*>& ss, const jso_step_opts& o) {
     mix((uint64_t)s->dev.depth);
     mix((uint64_t)s->dev.n_tris);
     mix((uint64_t)(o.precond_lambda > 0.0f && preconditioned(s)));
+    mix((uint64_t)uncorrelated(o));
   }
   return h;
 }
@@ -1109,9 +1160,10 @@ int exec_cached(jso_ctx* c, const std::vector<uint64_t>& sig, Build build) {
 // The estimator jobs of jso_estimate_gradients (same streams as a meta step).
 ProbPlan estimate_problem(SceneGPU* s, uint64_t seed, uint32_t iteration, int spp_prop,
                           int spp_fd, float* F, float* dF, float* img, double* loss2,
-                          const Crop& crop, const uint8_t* mask, uint32_t flags) {
+                          const Crop& crop, const uint8_t* mask, uint32_t flags, int loss) {
   ProbPlan p{};
   p.s = s;
+  p.relative = loss == JSO_LOSS_RELATIVE;
   p.key = KeyArgs{seed, iteration, nullptr};
   p.crop = crop;
   p.mask = mask;
@@ -1231,6 +1283,10 @@ int jso_load_scene(jso_ctx* c, const jso_scene_desc* d, int* scene_id) {
   A(dalloc(&s->m2D, P));
   A(dalloc(&s->adam_m, P));
   A(dalloc(&s->adam_v, P));
+  A(dalloc(&s->m1F, P));
+  A(dalloc(&s->m1D, P));
+  A(dalloc(&s->Fv, P));
+  A(dalloc(&s->dFv, P));
   A(dalloc(&s->ctl, 1));
   A(dalloc(&s->scratch_loss, 2));
   A(dalloc(&s->partials, kMetaMaxBlocks));
@@ -1371,13 +1427,16 @@ int jso_estimate_gradients(jso_ctx* c, int id, uint64_t seed, uint32_t iteration
   if (!F) return fail(c, JSO_E_INVALID, "null F");
   if (spp_prop < 1 || spp_prop > 64 || spp_fd < 0 || spp_fd > 64)
     return fail(c, JSO_E_INVALID, "spp out of range");
+  const int lossk = opts ? opts->loss : JSO_LOSS_L2;
+  if (lossk != JSO_LOSS_L2 && lossk != JSO_LOSS_RELATIVE)
+    return fail(c, JSO_E_INVALID, "unknown loss %d", lossk);
   DeviceGuard g(c->device);
   HIP_TRY(c, hipMemsetAsync(s->scratch_loss, 0, 2 * sizeof(double), c->stream));
   Plan plan;
   plan_estimators({estimate_problem(s, seed, iteration, spp_prop, spp_fd, F, dF, img,
                                     s->scratch_loss, crop_of(s, opts),
                                     opts ? opts->pixel_mask : nullptr,
-                                    c->debug_flags | (opts ? opts->flags : 0u))},
+                                    c->debug_flags | (opts ? opts->flags : 0u), lossk)},
                   plan, c->tile_shape);
   int rc = exec_plan(c, plan);
   if (rc) return rc;
@@ -1493,12 +1552,17 @@ int jso_grad_step(jso_ctx* c, const int* ids, int n, const jso_step_opts* o,
   for (uint64_t v : {(uint64_t)o->optimizer, bits(o->eta), bits(o->beta_F), bits(o->beta_D),
                      (uint64_t)o->spp_prop, (uint64_t)o->spp_fd, bits(o->adam_beta1),
                      bits(o->adam_beta2), bits(o->adam_eps), (uint64_t)o->adam_spp, o->seed,
-                     (uint64_t)flags, bits(o->precond_lambda)})
+                     (uint64_t)flags, bits(o->precond_lambda), (uint64_t)o->loss,
+                     (uint64_t)o->ablate})
     sig.push_back(v);
   rc = exec_cached(c, sig, [&](Plan& plan) {
-    std::vector<ProbPlan> ps;
-    for (int k = 0; k < n; ++k) ps.push_back(step_problem(get_scene(c, ids[k]), *o, flags, 0));
+    std::vector<ProbPlan> ps, pv;
+    for (int k = 0; k < n; ++k) {
+      ps.push_back(step_problem(get_scene(c, ids[k]), *o, flags, 0));
+      if (uncorrelated(*o)) pv.push_back(variance_problem(get_scene(c, ids[k]), *o, flags, 0));
+    }
     plan_estimators(ps, plan, shape);
+    if (!pv.empty()) plan_estimators(pv, plan, shape);
     plan_precond(ps, *o, plan);
     plan_optimizer(ps, *o, plan);
   });
@@ -1565,13 +1629,15 @@ int batch_build(jso_batch* b, int shape) {
   HIP_TRY(c, hipStreamSynchronize(c->stream));  // the old descriptors may be in use
   batch_release(b);
   b->shape = shape;
-  std::vector<ProbPlan> ps;
+  std::vector<ProbPlan> ps, pv;
   for (size_t k = 0; k < b->ids.size(); ++k) {
     SceneGPU* s = get_scene(c, b->ids[k]);
     if (!s) return fail(c, JSO_E_STATE, "scene %d of the batch was freed", b->ids[k]);
     ps.push_back(step_problem(s, b->opts, b->flags, b->max_iters[k]));
+    if (uncorrelated(b->opts)) pv.push_back(variance_problem(s, b->opts, b->flags, b->max_iters[k]));
   }
   plan_estimators(ps, b->plan, shape);
+  if (!pv.empty()) plan_estimators(pv, b->plan, shape);
   plan_precond(ps, b->opts, b->plan);
   plan_optimizer(ps, b->opts, b->plan);
   const std::vector<uint8_t> all = pack_plan(b->plan, b->off);
@@ -1622,7 +1688,9 @@ int snapshot(jso_ctx* c, const std::vector<int>& ids, StateCopy& sc) {
         {s->params, P * 4},      {s->params_prev, P * 4}, {s->F, P * 4},
         {s->dF, P * 4},          {s->mean, P * 8},        {s->var, P * 8},
         {s->alpha_prev, P * 8},  {s->m2F, P * 8},         {s->m2D, P * 8},
-        {s->adam_m, P * 4},      {s->adam_v, P * 4},      {s->ctl, sizeof(Ctl)}};
+        {s->adam_m, P * 4},      {s->adam_v, P * 4},      {s->ctl, sizeof(Ctl)},
+        {s->m1F, P * 8},         {s->m1D, P * 8},         {s->Fv, P * 4},
+        {s->dFv, P * 4}};
     for (const auto& l : live) {
       void* copy = nullptr;
       HIP_TRY(c, hipMalloc(&copy, l.second));

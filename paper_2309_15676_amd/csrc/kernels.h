@@ -116,7 +116,9 @@ struct FinArgs {
   float delta_scale;   // 2 / (3 W H)
   double loss_scale;   // 1 / (3 W H)
   uint32_t nblocks;    // blocks per job
+  int relative;        // relative loss: each term over T^2 + kRelEps
 };
+constexpr float kRelEps = 0.01f;
 
 // One grid slice of k_adjoint: the replay of one sample of one job, a single
 // path (params_b null) or a finite-difference pair (+A - B).
@@ -163,6 +165,11 @@ struct MetaArgs {
   double beta_F, beta_D;
   float eta;
   int zero_grads;
+  // ablations (JSO_ABLATE_*): centred EMAs keep their first moments in
+  // m1F / m1D; uncorrelated variance samples come from Fv / dFv
+  uint32_t ablate;
+  JSO_GMEM double *m1F, *m1D;
+  JSO_GMEM float *Fv, *dFv;
 };
 
 struct AdamArgs {

@@ -342,9 +342,11 @@ __global__ void __launch_bounds__(kFinBlock) k_finalize(const FinArgs* __restric
           const float I = (float)(sum[k] * job.inv_spp);
           if (G(job.img)) G(job.img)[3 * (size_t)pix + k] = I;
           if (G(job.delta)) {
-            const float e = I - G(A.target)[3 * (size_t)pix + k];
-            G(job.delta)[3 * (size_t)pix + k] = A.delta_scale * e;
-            se += (double)e * (double)e;
+            const float t = G(A.target)[3 * (size_t)pix + k];
+            const float e = I - t;
+            const float w = A.relative ? 1.0f / (t * t + kRelEps) : 1.0f;
+            G(job.delta)[3 * (size_t)pix + k] = A.delta_scale * e * w;
+            se += (double)e * (double)e * (double)w;
           }
         }
       }
@@ -787,6 +789,10 @@ __global__ void __launch_bounds__(kMetaBlock) k_meta(const MetaArgs* __restrict_
   const uint32_t n = (uint32_t)A.n, nc = (uint32_t)A.n_ch;
   double local = 0.0;
   const uint32_t span = kMetaBlock * kMetaK;
+  const uint32_t ab = A.ablate;  // uniform
+  const bool centred = (ab & JSO_ABLATE_CENTRED) != 0;
+  const bool uncorr = (ab & JSO_ABLATE_UNCORRELATED) != 0;
+  const bool clip = (ab & JSO_ABLATE_NO_CLIP) == 0;
   for (uint32_t base = lb * span + threadIdx.x; base < n; base += nb * span) {
     float F[kMetaK], dF[kMetaK], p[kMetaK];
     double m2F[kMetaK], m2D[kMetaK], mean[kMetaK], var[kMetaK], ap[kMetaK];
@@ -810,22 +816,35 @@ __global__ void __launch_bounds__(kMetaBlock) k_meta(const MetaArgs* __restrict_
       if (i >= n) continue;
       const double f = (double)F[e], df = (double)dF[e];
       // Var[F] (Eq. 9; bias-corrected Moment2)
-      const double mF = m2F[e] + wF * (f * f - m2F[e]);
+      const double xF = uncorr ? (double)G(A.Fv)[i] : f;
+      const double mF = m2F[e] + wF * (xF * xF - m2F[e]);
+      double varF = mF;
+      if (centred) {
+        const double m1 = G(A.m1F)[i] + wF * (xF - G(A.m1F)[i]);
+        G(A.m1F)[i] = m1;
+        varF = fmax(mF - m1 * m1, 0.0);
+      }
       // Var[dF] (Eq. 13-14)
       double mD = m2D[e];
       double varD = 0.0;
       if (takeD) {
-        const double x = df / sq_n2;
+        const double x = (uncorr ? (double)G(A.dFv)[i] : df) / sq_n2;
         mD = mD + wD * (x * x - mD);
-        varD = mD * n2;
+        double vd = mD;
+        if (centred) {
+          const double m1 = G(A.m1D)[i] + wD * (x - G(A.m1D)[i]);
+          G(A.m1D)[i] = m1;
+          vd = fmax(mD - m1 * m1, 0.0);
+        }
+        varD = vd * n2;
       }
       // carry the previous estimate forward, weight (Eq. 8, 17), combine (Eq. 7, 15)
       double mu = mean[e] + df;
       double v = var[e] + varD;
-      double a = mF / (mF + v + 1e-30);
-      a = fmin(a, 1.0 / (2.0 - ap[e]));
+      double a = varF / (varF + v + 1e-30);
+      if (clip) a = fmin(a, 1.0 / (2.0 - ap[e]));
       mu = a * mu + (1.0 - a) * f;
-      v = a * a * v + (1.0 - a) * (1.0 - a) * mF;
+      v = a * a * v + (1.0 - a) * (1.0 - a) * varF;
       // stabilised step (Eq. 21) and projection
       const double step = -(double)A.eta * mu / (sqrt(v) + 1e-8);
       const uint32_t ch = i % nc;
@@ -842,6 +861,10 @@ __global__ void __launch_bounds__(kMetaBlock) k_meta(const MetaArgs* __restrict_
       if (A.zero_grads) {
         G(A.F)[i] = 0.0f;
         G(A.dF)[i] = 0.0f;
+        if (uncorr) {
+          G(A.Fv)[i] = 0.0f;
+          G(A.dFv)[i] = 0.0f;
+        }
       }
     }
   }
