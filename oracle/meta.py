@@ -87,6 +87,10 @@ class Meta:
         alpha = var_F / (var_F + self.var + ALPHA_EPS)
         if self.clip:
             alpha = np.minimum(alpha, 1.0 / (2.0 - self.alpha_prev))
+        else:
+            # the ablation drops Eq. 17 only; Eq. 7's initialisation
+            # <F_0>_M = <F_0> (alpha_0 = 0) stays
+            alpha = np.where(np.isneginf(self.alpha_prev), 0.0, alpha)
         self.alpha_prev = alpha
         self.alpha = alpha
         # combine (Eq. 7) and propagate the variance (Eq. 15)

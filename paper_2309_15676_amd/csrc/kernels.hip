@@ -842,7 +842,10 @@ __global__ void __launch_bounds__(kMetaBlock) k_meta(const MetaArgs* __restrict_
       double mu = mean[e] + df;
       double v = var[e] + varD;
       double a = varF / (varF + v + 1e-30);
-      if (clip) a = fmin(a, 1.0 / (2.0 - ap[e]));
+      if (clip)
+        a = fmin(a, 1.0 / (2.0 - ap[e]));
+      else if (isinf(ap[e]))
+        a = 0.0;  // the ablation drops Eq. 17 only: alpha_0 = 0 (Eq. 7's initialisation)
       mu = a * mu + (1.0 - a) * f;
       v = a * a * v + (1.0 - a) * (1.0 - a) * varF;
       // stabilised step (Eq. 21) and projection

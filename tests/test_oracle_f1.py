@@ -71,13 +71,22 @@ def test_no_alpha_clip_keeps_the_unclipped_weight():
     clipped = OM.Meta((3,), 0.1)
     free = OM.Meta((3,), 0.1, clip=False)
     vF = F * F
-    clipped.step(F, np.zeros(3), vF, np.zeros(3))
-    free.step(F, np.zeros(3), vF, np.zeros(3))
-    # Eq. 17 with alpha_{-1} = -inf gives alpha_0 = 0; unclipped, Eq. 8 with an
-    # empty history gives Var[F] / (Var[F] + 0) = 1 (up to the guard)
-    np.testing.assert_array_equal(clipped.alpha, 0.0)
-    np.testing.assert_allclose(free.alpha, 1.0, rtol=1e-12)
-    np.testing.assert_allclose(clipped.mean, F, rtol=1e-15)
+    for m in (clipped, free):
+        m.step(F, np.zeros(3), vF, np.zeros(3))
+        # Eq. 7's initialisation holds with or without the clip: alpha_0 = 0
+        np.testing.assert_array_equal(m.alpha, 0.0)
+        np.testing.assert_allclose(m.mean, F, rtol=1e-15)
+    # second step with a small carried variance: Eq. 8 gives
+    # Var[F] / (Var[F] + Var_M + Var[dF]); the clip of Eq. 17 caps it at
+    # 1 / (2 - alpha_0) = 1/2
+    vF2 = 4.0 * vF
+    dF, vdF = np.zeros(3), 0.01 * vF
+    clipped.step(F, dF, vF2, vdF)
+    free.step(F, dF, vF2, vdF)
+    want = vF2 / (vF2 + vF + vdF)
+    np.testing.assert_allclose(free.alpha, want, rtol=1e-12)
+    np.testing.assert_allclose(clipped.alpha, np.minimum(want, 0.5), rtol=1e-12)
+    assert np.all(free.alpha > 0.5)
 
 
 def test_sample_reuse_ablation_plumbing():
