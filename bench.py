@@ -24,6 +24,7 @@ from __future__ import annotations
 
 import argparse
 import json
+import math
 import os
 import sys
 import time
@@ -211,6 +212,49 @@ def time_to_loss(prob, init, gt, target, args, iters: int, label: str, lam: floa
     }
 
 
+def ablations(prob, init, target, iters: int, eta: float, seed: int, label: str):
+    """The meta-estimator as published and with each ablation of the
+    Experiments section (non-zero-centred variance EMAs, no alpha clipping,
+    uncorrelated variance samples), same learning rate and random streams:
+    evaluation loss (256 spp, fixed stream, off the clock) after `iters`
+    iterations, the lowest loss seen, and the GPU time per iteration."""
+    import torch
+
+    from paper_2309_15676_amd import _lib as L
+
+    T = target.float()
+
+    def eval_loss():
+        img = prob.render(prob.get_params(), seed=777, iteration=0, tag=L.JSO_TAG_EVAL,
+                          spp=256)
+        return float(((img - T) ** 2).mean())
+
+    out = {"workload": label, "iterations": iters, "eta": eta}
+    variants = {"published": 0, "non_zero_centred": L.JSO_ABLATE_CENTRED,
+                "no_alpha_clip": L.JSO_ABLATE_NO_CLIP,
+                "uncorrelated_variance": L.JSO_ABLATE_UNCORRELATED}
+    every = max(iters // 10, 1)
+    for name, ab in variants.items():
+        prob.set_params(init)
+        opts = L.step_opts(optimizer=L.JSO_OPT_META, eta=eta, seed=seed, ablate=ab)
+        first = eval_loss()
+        losses, ms = [], 0.0
+        e0, e1 = torch.cuda.Event(enable_timing=True), torch.cuda.Event(enable_timing=True)
+        for done in range(0, iters, every):
+            torch.cuda.synchronize()
+            e0.record()
+            for _ in range(min(every, iters - done)):
+                prob.grad_step(opts)
+            e1.record()
+            torch.cuda.synchronize()
+            ms += e0.elapsed_time(e1)
+            losses.append(eval_loss())
+        out[name] = {"initial_loss": first, "final_loss": losses[-1], "best_loss": min(losses),
+                     "diverged": bool(losses[-1] > first or not all(map(math.isfinite, losses))),
+                     "ms_per_iteration": ms / iters}
+    return out
+
+
 def batched_throughput(ctx_problem, args):
     """64 independent problems of uneven size (image side 64-512, 5-65,536
     parameters, own seeds and iteration budgets): differentiable paths/s of
@@ -387,6 +431,9 @@ def main():
     ap.add_argument("--batch-steps", type=int, default=20,
                     help="iterations timed for the 64-problem batch (0: skip it)")
     ap.add_argument("--batch-target-spp", type=int, default=256)
+    ap.add_argument("--ablation-iters", type=int, default=1000,
+                    help="meta-estimator iterations of the ablation runs on the textured "
+                         "problem (the tiny problem runs 200; 0: skip)")
     ap.add_argument("--mesh-steps", type=int, default=10,
                     help="timed calls per mesh workload (0 = skip the mesh workloads)")
     args = ap.parse_args()
@@ -495,6 +542,18 @@ def main():
                 "texture gradients", lam=args.ttl_lambda, etas=[0.01, 0.03, 0.1, 0.3])
             print("[bench] time to loss: %s" % json.dumps(ttl["textured_preconditioned"]),
                   file=sys.stderr, flush=True)
+    abl = None
+    if args.ablation_iters > 0:
+        print("[bench] meta-estimator ablations", file=sys.stderr, flush=True)
+        tspec, tgt, tinit = I.config_tiny()
+        tprob = Problem(tspec, context=prob.context)
+        ttarget = tprob.render(tgt, seed=12345, iteration=0, tag=L.JSO_TAG_TARGET, spp=1024)
+        tprob.set_target(ttarget)
+        abl = {"tiny": ablations(tprob, tinit, ttarget, 200, 0.01, args.seed + 2,
+                                 "64x64, 5 global parameters"),
+               "textured": ablations(prob, init, target, args.ablation_iters, 0.003,
+                                     args.seed + 2, "512x512, 262,144 texel parameters")}
+        print("[bench] ablations: %s" % json.dumps(abl), file=sys.stderr, flush=True)
     # roofline of the dominant kernel: algorithmic FP32 work per launch over
     # its average launch time
     cands = {
@@ -535,6 +594,7 @@ def main():
         "time_to_loss": ttl,
         "batched": bat,
         "meshes": mesh,
+        "ablations": abl,
     }
     print(json.dumps(line))
 
