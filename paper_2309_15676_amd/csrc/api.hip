@@ -446,11 +446,11 @@ int upload_mesh(jso_ctx* c, const jso_scene_desc* d, SceneGPU* s) {
   auto A = [&](hipError_t x) {
     if (e == hipSuccess) e = x;
   };
-  A(dalloc(&s->bvh_nodes, b.nodes.size() * 16));
+  A(dalloc(&s->bvh_nodes, b.nodes4.size() * (sizeof(Bvh4Node) / sizeof(float))));
   A(dalloc(&s->bvh_tris, b.tris.size()));
   A(dalloc(&s->bvh_tri_id, b.order.size()));
   if (e == hipSuccess) {
-    A(hipMemcpy(s->bvh_nodes, b.nodes.data(), b.nodes.size() * sizeof(BvhNode),
+    A(hipMemcpy(s->bvh_nodes, b.nodes4.data(), b.nodes4.size() * sizeof(Bvh4Node),
                 hipMemcpyHostToDevice));
     A(hipMemcpy(s->bvh_tris, b.tris.data(), b.tris.size() * sizeof(float),
                 hipMemcpyHostToDevice));
@@ -464,8 +464,8 @@ int upload_mesh(jso_ctx* c, const jso_scene_desc* d, SceneGPU* s) {
   S.bvh_nodes = gmem((const float4*)s->bvh_nodes);
   S.bvh_tris = gmem((const float4*)s->bvh_tris);
   S.bvh_tri_id = gmem((const int*)s->bvh_tri_id);
-  S.bvh_depth = b.depth;
-  s->stack = b.depth;
+  S.bvh_depth = b.depth4;
+  s->stack = b.stack4;
   return JSO_OK;
 }
 

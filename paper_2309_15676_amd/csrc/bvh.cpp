@@ -92,7 +92,7 @@ struct Builder {
       // every centroid coincides: halve the range
       return b + n / 2;
     }
-    if (level > kBvhMaxStack - kMedianLevels) {
+    if (level > kBvh2MaxDepth - kMedianLevels) {
       const int mid = b + n / 2;
       std::nth_element(idx.begin() + b, idx.begin() + mid, idx.begin() + e, [&](int x, int y) {
         return cen[3 * (size_t)x + axis] < cen[3 * (size_t)y + axis];
@@ -158,12 +158,12 @@ struct Builder {
   int32_t build(int b, int e, int level, Box& box) {
     box = range_box(b, e);
     const int n = e - b;
-    if (level > kBvhMaxStack) {
+    if (level > kBvh2MaxDepth) {
       if (n > kLeafMax) {
         char msg[160];
         std::snprintf(msg, sizeof(msg),
                       "BVH: %d triangles share one leaf at the depth limit %d "
-                      "(degenerate mesh)", n, kBvhMaxStack);
+                      "(degenerate mesh)", n, kBvh2MaxDepth);
         err = msg;
         return 0;
       }
@@ -205,6 +205,94 @@ struct Builder {
     return node;
   }
 };
+
+// Collapse the binary hierarchy into four-wide nodes: a node's children start
+// as the binary node's two, and the inner child with the largest box surface
+// is replaced by its own two children until there are four or only leaves
+// are left.  Nodes are numbered breadth-first (the top levels come first).
+struct Child {
+  float lo[3], hi[3];
+  int32_t link;  // binary-hierarchy link
+};
+
+double child_area(const Child& c) {
+  const double x = c.hi[0] - c.lo[0], y = c.hi[1] - c.lo[1], z = c.hi[2] - c.lo[2];
+  return 2.0 * (x * y + y * z + z * x);
+}
+
+void collapse(BvhBuild& b) {
+  const std::vector<BvhNode>& N = b.nodes;
+  auto kids = [&](int32_t node, std::vector<Child>& out) {
+    const BvhNode& n = N[node];
+    Child a, c;
+    for (int k = 0; k < 3; ++k) {
+      a.lo[k] = n.lo0[k];
+      a.hi[k] = n.hi0[k];
+      c.lo[k] = n.lo1[k];
+      c.hi[k] = n.hi1[k];
+    }
+    a.link = n.link0;
+    c.link = n.link1;
+    out.push_back(a);
+    out.push_back(c);
+  };
+  struct Item {
+    int32_t bin;   // binary node this four-wide node stands for
+    int level;     // inner level (root = 1)
+    int stack;     // pushes on the path above it
+  };
+  std::vector<Item> queue{{0, 1, 0}};
+  b.nodes4.clear();
+  b.nodes4.push_back(Bvh4Node{});
+  b.depth4 = 0;
+  b.stack4 = 0;
+  for (size_t q = 0; q < queue.size(); ++q) {
+    const Item it = queue[q];
+    std::vector<Child> ch;
+    kids(it.bin, ch);
+    while (ch.size() < 4) {
+      int best = -1;
+      double area = -1.0;
+      for (int i = 0; i < (int)ch.size(); ++i)
+        if (ch[i].link >= 0 && child_area(ch[i]) > area) {
+          area = child_area(ch[i]);
+          best = i;
+        }
+      if (best < 0) break;
+      const int32_t inner = ch[best].link;
+      ch.erase(ch.begin() + best);
+      kids(inner, ch);
+    }
+    const int pushes = it.stack + (int)ch.size() - 1;
+    b.stack4 = std::max(b.stack4, pushes);
+    b.depth4 = std::max(b.depth4, it.level);
+    Bvh4Node nd{};
+    for (int k = 0; k < 4; ++k) {
+      if (k < (int)ch.size()) {
+        const Child& c = ch[k];
+        nd.lo_x[k] = c.lo[0];
+        nd.hi_x[k] = c.hi[0];
+        nd.lo_y[k] = c.lo[1];
+        nd.hi_y[k] = c.hi[1];
+        nd.lo_z[k] = c.lo[2];
+        nd.hi_z[k] = c.hi[2];
+        if (c.link >= 0) {
+          nd.link[k] = (int32_t)b.nodes4.size();
+          b.nodes4.push_back(Bvh4Node{});
+          queue.push_back({c.link, it.level + 1, pushes});
+        } else {
+          nd.link[k] = c.link;
+        }
+      } else {  // unused slot: an empty leaf with a point box
+        nd.lo_x[k] = nd.hi_x[k] = ch[0].lo[0];
+        nd.lo_y[k] = nd.hi_y[k] = ch[0].lo[1];
+        nd.lo_z[k] = nd.hi_z[k] = ch[0].lo[2];
+        nd.link[k] = ~(int32_t)0;
+      }
+    }
+    b.nodes4[q] = nd;
+  }
+}
 
 }  // namespace
 
@@ -259,6 +347,13 @@ std::string build_bvh(const float* verts, int n_verts, const int* tris, int n_tr
   for (BvhNode& N : out.nodes) {
     widen(N.lo0, N.hi0);
     widen(N.lo1, N.hi1);
+  }
+  collapse(out);
+  if (out.stack4 > kBvhMaxStack) {
+    char msg[160];
+    std::snprintf(msg, sizeof(msg), "BVH: traversal needs %d stack entries (limit %d)",
+                  out.stack4, kBvhMaxStack);
+    return msg;
   }
   return "";
 }

@@ -48,7 +48,7 @@ struct DevScene {
   float fixed[JSO_MAX_FIXED_MATS][5];
   // triangle mesh (n_tris = 0: none), indexed by a BVH in the layout of bvh.h
   int n_tris, mesh_mat, layout, bvh_depth;
-  JSO_GMEM const float4* bvh_nodes;  // 4 words per node
+  JSO_GMEM const float4* bvh_nodes;  // four-wide nodes, 8 words each
   JSO_GMEM const float4* bvh_tris;   // 3 words per triangle, leaf order
   JSO_GMEM const int* bvh_tri_id;    // original index of each reordered triangle
 };
@@ -151,12 +151,20 @@ struct Hit {
   int kind, obj;  // obj: sphere index, or triangle index in BVH leaf order
 };
 
-// Per-lane BVH traversal stack in LDS: entry k of this lane at base[k * stride]
-// (base already offset by the lane, stride = lanes of the block, so the lanes
-// of a wave touch consecutive words).
+// Per-lane BVH traversal stack: the first `cap` entries in LDS, entry k of
+// this lane at base[k * stride] (base already offset by the lane, stride =
+// lanes of the block, so the lanes of a wave touch consecutive words); deeper
+// entries, which few rays reach, spill to a private array.
+constexpr int kLdsStack = 16;  // LDS entries per lane at most
+
 struct TravStack {
   uint32_t* base;
   int stride;
+  int cap;  // LDS entries per lane (<= kLdsStack)
+};
+
+struct StackSpill {
+  uint32_t v[kBvhMaxStack - kLdsStack];
 };
 
 // A ray prepared for slab tests: o * (1/d) precomputed so each slab bound is
@@ -208,34 +216,76 @@ __device__ __forceinline__ float tri_hit(const RayQ& r, V3 v0, V3 e1, V3 e2, flo
 // access global once inlined).
 __device__ __forceinline__ float4 ldg4(JSO_GMEM const float4* p) { return *(const float4*)p; }
 
+// Four-wide node: the entry distances of its four child boxes (kInf = missed)
+// and their links.
+struct Node4 {
+  float t[4];
+  int32_t l[4];
+};
+
+__device__ __forceinline__ Node4 load_node4(const DevScene& S, const RayQ& r, int32_t link,
+                                            float tmax) {
+  JSO_GMEM const float4* nd = S.bvh_nodes + 8 * (size_t)link;
+  const float4 lx = ldg4(nd), hx = ldg4(nd + 1), ly = ldg4(nd + 2), hy = ldg4(nd + 3);
+  const float4 lz = ldg4(nd + 4), hz = ldg4(nd + 5), ln = ldg4(nd + 6);
+  Node4 n;
+  n.t[0] = box_entry(r, lx.x, ly.x, lz.x, hx.x, hy.x, hz.x, tmax);
+  n.t[1] = box_entry(r, lx.y, ly.y, lz.y, hx.y, hy.y, hz.y, tmax);
+  n.t[2] = box_entry(r, lx.z, ly.z, lz.z, hx.z, hy.z, hz.z, tmax);
+  n.t[3] = box_entry(r, lx.w, ly.w, lz.w, hx.w, hy.w, hz.w, tmax);
+  n.l[0] = __float_as_int(ln.x);
+  n.l[1] = __float_as_int(ln.y);
+  n.l[2] = __float_as_int(ln.z);
+  n.l[3] = __float_as_int(ln.w);
+  return n;
+}
+
+__device__ __forceinline__ void order2(float& ta, int32_t& la, float& tb, int32_t& lb) {
+  const bool sw = tb < ta;
+  const float t = sw ? tb : ta;
+  const int32_t l = sw ? lb : la;
+  tb = sw ? ta : tb;
+  lb = sw ? la : lb;
+  ta = t;
+  la = l;
+}
+
+__device__ __forceinline__ void push(const TravStack& st, StackSpill& sv, int& sp, int32_t link) {
+  if (sp < st.cap)
+    st.base[sp * st.stride] = (uint32_t)link;
+  else
+    sv.v[sp - st.cap] = (uint32_t)link;
+  ++sp;
+}
+
+__device__ __forceinline__ int32_t pop(const TravStack& st, const StackSpill& sv, int& sp) {
+  --sp;
+  return (int32_t)(sp < st.cap ? st.base[sp * st.stride] : sv.v[sp - st.cap]);
+}
+
 // Closest triangle strictly nearer than `best_t` (or at best_t with a lower
-// original index than the triangle already held).  Nearer child first; the
-// other is deferred on the stack, so at most one entry per inner level.
+// original index than the triangle already held).  At each node the hit
+// children are sorted by entry distance (a 5-exchange network); the nearest is
+// visited next and the others are deferred on the stack, nearest on top.
 __device__ __forceinline__ void bvh_closest(const DevScene& S, const TravStack& st, V3 o, V3 d,
                                             float& best_t, int& best_tri) {
   const RayQ r = make_rayq(o, d);
+  StackSpill sv;
   int sp = 0;
   int32_t link = 0;
   for (;;) {
     if (link >= 0) {
-      JSO_GMEM const float4* nd = S.bvh_nodes + 4 * (size_t)link;
-      const float4 a = ldg4(nd), b = ldg4(nd + 1), c = ldg4(nd + 2), e = ldg4(nd + 3);
-      const float t0 = box_entry(r, a.x, a.y, a.z, a.w, b.x, b.y, best_t);
-      const float t1 = box_entry(r, b.z, b.w, c.x, c.y, c.z, c.w, best_t);
-      const int32_t l0 = __float_as_int(e.x), l1 = __float_as_int(e.y);
-      if (t0 != kInf && t1 != kInf) {
-        const bool near0 = t0 <= t1;
-        st.base[sp * st.stride] = (uint32_t)(near0 ? l1 : l0);
-        ++sp;
-        link = near0 ? l0 : l1;
-        continue;
-      }
-      if (t0 != kInf) {
-        link = l0;
-        continue;
-      }
-      if (t1 != kInf) {
-        link = l1;
+      Node4 n = load_node4(S, r, link, best_t);
+      order2(n.t[0], n.l[0], n.t[1], n.l[1]);
+      order2(n.t[2], n.l[2], n.t[3], n.l[3]);
+      order2(n.t[0], n.l[0], n.t[2], n.l[2]);
+      order2(n.t[1], n.l[1], n.t[3], n.l[3]);
+      order2(n.t[1], n.l[1], n.t[2], n.l[2]);
+      if (n.t[0] != kInf) {
+        if (n.t[3] != kInf) push(st, sv, sp, n.l[3]);
+        if (n.t[2] != kInf) push(st, sv, sp, n.l[2]);
+        if (n.t[1] != kInf) push(st, sv, sp, n.l[1]);
+        link = n.l[0];
         continue;
       }
     } else {
@@ -253,30 +303,32 @@ __device__ __forceinline__ void bvh_closest(const DevScene& S, const TravStack& 
       }
     }
     if (sp == 0) break;
-    --sp;
-    link = (int32_t)st.base[sp * st.stride];
+    link = pop(st, sv, sp);
   }
 }
 
-// Whether any triangle lies at a distance in (0, tmax).
+// Whether any triangle lies at a distance in (0, tmax).  Children in slot
+// order, the first hit one visited next.
 __device__ __forceinline__ bool bvh_any(const DevScene& S, const TravStack& st, V3 o, V3 d,
                                         float tmax) {
   const RayQ r = make_rayq(o, d);
+  StackSpill sv;
   int sp = 0;
   int32_t link = 0;
   for (;;) {
     if (link >= 0) {
-      JSO_GMEM const float4* nd = S.bvh_nodes + 4 * (size_t)link;
-      const float4 a = ldg4(nd), b = ldg4(nd + 1), c = ldg4(nd + 2), e = ldg4(nd + 3);
-      const bool h0 = box_entry(r, a.x, a.y, a.z, a.w, b.x, b.y, tmax) != kInf;
-      const bool h1 = box_entry(r, b.z, b.w, c.x, c.y, c.z, c.w, tmax) != kInf;
-      const int32_t l0 = __float_as_int(e.x), l1 = __float_as_int(e.y);
-      if (h0 && h1) {
-        st.base[sp * st.stride] = (uint32_t)l1;
-        ++sp;
+      const Node4 n = load_node4(S, r, link, tmax);
+      int32_t next = 0;
+      bool any = false;
+#pragma unroll
+      for (int k = 0; k < 4; ++k) {
+        if (n.t[k] == kInf) continue;
+        if (any) push(st, sv, sp, n.l[k]);
+        else next = n.l[k];
+        any = true;
       }
-      if (h0 || h1) {
-        link = h0 ? l0 : l1;
+      if (any) {
+        link = next;
         continue;
       }
     } else {
@@ -290,8 +342,7 @@ __device__ __forceinline__ bool bvh_any(const DevScene& S, const TravStack& st, 
       }
     }
     if (sp == 0) break;
-    --sp;
-    link = (int32_t)st.base[sp * st.stride];
+    link = pop(st, sv, sp);
   }
   return false;
 }

@@ -7,7 +7,10 @@
 //     traversal stack,
 //   - a closest-hit search through the boxes finds the same triangle as a
 //     brute-force search over all triangles, for random rays.
-// Prints "ok <depth> <nodes>" or the first violation.
+// The same for the four-wide hierarchy the kernels traverse, whose stack use
+// in a nearest-first traversal must stay within the bound the builder reports.
+// Prints "ok <depth> <nodes> <hits>" or the first violation.
+#include <algorithm>
 #include <cmath>
 #include <cstdio>
 #include <cstring>
@@ -103,6 +106,83 @@ static bool box_hit(const float* lo, const float* hi, const double* o, const dou
   return t0 <= t1;
 }
 
+static bool walk4(const BvhBuild& b, std::vector<int>& seen_node, std::vector<int>& seen_tri,
+                  int32_t link, const float* lo, const float* hi, int level, int& max_level) {
+  if (link >= 0) {
+    if (link >= (int)b.nodes4.size() || seen_node[link]++) return false;
+    max_level = std::max(max_level, level);
+    const Bvh4Node& N = b.nodes4[link];
+    for (int k = 0; k < 4; ++k) {
+      const float clo[3] = {N.lo_x[k], N.lo_y[k], N.lo_z[k]};
+      const float chi[3] = {N.hi_x[k], N.hi_y[k], N.hi_z[k]};
+      if (!walk4(b, seen_node, seen_tri, N.link[k], clo, chi, level + 1, max_level)) return false;
+    }
+    return true;
+  }
+  const uint32_t v = ~(uint32_t)link;
+  const int first = (int)(v >> kLeafBits), cnt = (int)(v & kLeafMax);
+  for (int i = first; i < first + cnt; ++i) {
+    if (i >= (int)b.order.size() || seen_tri[i]++) return false;
+    const float* w = &b.tris[(size_t)kTriWords * i];
+    for (int k = 0; k < 3; ++k) {
+      float p[3];
+      for (int a = 0; a < 3; ++a) p[a] = w[a] + (k == 1 ? w[4 + a] : k == 2 ? w[8 + a] : 0.0f);
+      if (!inside(lo, hi, p)) return false;
+    }
+  }
+  return true;
+}
+
+// nearest-first traversal of the four-wide hierarchy (FP64 box tests);
+// returns the largest stack depth it used
+static int closest4(const BvhBuild& b, const float* V, const int* T, const double* o,
+                    const double* d, double& best, int& best_tri) {
+  std::vector<int32_t> st;
+  int max_sp = 0;
+  int32_t link = 0;
+  for (;;) {
+    if (link >= 0) {
+      const Bvh4Node& N = b.nodes4[link];
+      std::vector<std::pair<double, int32_t>> hit;
+      for (int k = 0; k < 4; ++k) {
+        const float lo[3] = {N.lo_x[k], N.lo_y[k], N.lo_z[k]};
+        const float hi[3] = {N.hi_x[k], N.hi_y[k], N.hi_z[k]};
+        if (box_hit(lo, hi, o, d, best)) {
+          double t0 = 0;
+          for (int a = 0; a < 3; ++a)
+            if (d[a] != 0) t0 = std::max(t0, std::min((lo[a] - o[a]) / d[a], (hi[a] - o[a]) / d[a]));
+          hit.push_back({t0, N.link[k]});
+        }
+      }
+      if (!hit.empty()) {
+        std::sort(hit.begin(), hit.end(),
+                  [](const std::pair<double, int32_t>& x, const std::pair<double, int32_t>& y) {
+                    return x.first < y.first;
+                  });
+        for (size_t k = hit.size() - 1; k >= 1; --k) st.push_back(hit[k].second);
+        max_sp = std::max(max_sp, (int)st.size());
+        link = hit[0].second;
+        continue;
+      }
+    } else {
+      const uint32_t v = ~(uint32_t)link;
+      const int first = (int)(v >> kLeafBits), cnt = (int)(v & kLeafMax);
+      for (int i = first; i < first + cnt; ++i) {
+        const int t = b.order[i];
+        const double x = tri_t(V, T, t, o, d);
+        if (x < best || (x == best && t < best_tri)) {
+          best = x;
+          best_tri = t;
+        }
+      }
+    }
+    if (st.empty()) break;
+    link = st.back();
+    st.pop_back();
+  }
+  return max_sp;
+}
+
 static void closest(const BvhBuild& b, const float* V, const int* T, int32_t link, const double* o,
                     const double* d, double& best, int& best_tri) {
   if (link >= 0) {
@@ -167,7 +247,19 @@ int main(int argc, char** argv) {
   for (int x : c.seen_tri)
     if (x != 1) return fail("triangle not in exactly one leaf");
   if (c.max_level != b.depth) return fail("depth");
-  if (b.depth > kBvhMaxStack) return fail("depth limit");
+  if (b.depth > kBvh2MaxDepth) return fail("depth limit");
+  // four-wide hierarchy
+  {
+    std::vector<int> sn(b.nodes4.size(), 0), stt(nt, 0);
+    int ml = 0;
+    if (!walk4(b, sn, stt, 0, nullptr, nullptr, 1, ml)) return fail("4-wide containment");
+    for (int x : sn)
+      if (x != 1) return fail("4-wide unreachable node");
+    for (int x : stt)
+      if (x != 1) return fail("4-wide triangle not in exactly one leaf");
+    if (ml != b.depth4) return fail("4-wide depth");
+    if (b.stack4 > kBvhMaxStack) return fail("4-wide stack limit");
+  }
   // random rays from a box around the mesh towards random mesh points
   float lo[3] = {1e30f, 1e30f, 1e30f}, hi[3] = {-1e30f, -1e30f, -1e30f};
   for (int i = 0; i < nv; ++i)
@@ -209,6 +301,14 @@ int main(int argc, char** argv) {
       std::printf("FAIL ray %d: brute %d %.17g bvh %d %.17g\n", r, bft, bf, btt, bt);
       return 1;
     }
+    double b4 = INFINITY;
+    int b4t = -1;
+    const int sp = closest4(b, V.data(), T.data(), o, d, b4, b4t);
+    if (bft != b4t || !(bf == b4 || (std::isinf(bf) && std::isinf(b4)))) {
+      std::printf("FAIL ray %d: brute %d %.17g 4-wide %d %.17g\n", r, bft, bf, b4t, b4);
+      return 1;
+    }
+    if (sp > b.stack4) return fail("4-wide stack bound exceeded");
     hits += bft >= 0;
   }
   std::printf("ok %d %zu %d\n", b.depth, b.nodes.size(), hits);

@@ -61,7 +61,7 @@ def test_bvh_structure_and_closest_hit(checker, tmp_path, mesh):
     out = _run(checker, tmp_path, v, t)
     assert out[0] == "ok", out
     depth, nodes, hits = int(out[1]), int(out[2]), int(out[3])
-    assert 1 <= depth <= 32 and nodes >= 1
+    assert 1 <= depth <= 48 and nodes >= 1
     if mesh not in ("one", "two"):
         assert hits > 100
 
