@@ -255,6 +255,77 @@ def ablations(prob, init, target, iters: int, eta: float, seed: int, label: str)
     return out
 
 
+def large_time_to_rmse(context, args):
+    """The 2048x2048 terrain problem (1.0M triangles + 32 spheres, 512x512
+    texture of 5 channels): parameter-space RMSE against the ground truth
+    over wall-clock (grad_step calls only) for the meta-estimator (2 prop +
+    1 FD spp) and plain Adam at 32 and 64 spp.  The RMSE counts the
+    observable parameters only: every channel of the texels that a 64-spp
+    backward pass at the ground truth touches.  Each run stops at RMSE 1e-2,
+    at 2000 iterations, or at args.large_ttl_seconds of GPU time."""
+    import numpy as np
+    import torch
+
+    from paper_2309_15676_amd import _lib as L
+    from paper_2309_15676_amd import inputs as I
+    from paper_2309_15676_amd.problem import Problem
+
+    spec, gt, init = I.config_large()
+    prob = Problem(spec, context=context)
+    target = prob.render(gt, seed=12345, iteration=0, tag=L.JSO_TAG_TARGET, spp=256)
+    prob.set_target(target)
+    ones = torch.ones(spec.height, spec.width, 3, device="cuda")
+    g = prob.render_bwd(gt, ones, seed=99, iteration=0, tag=L.JSO_TAG_EVAL, spp=64)
+    texel_seen = (g.abs().reshape(-1, spec.n_ch) > 0).any(dim=1)
+    obs = texel_seen.repeat_interleave(spec.n_ch).cpu().numpy()
+    gt64 = np.asarray(gt, np.float64)[obs]
+
+    def rmse_of(p):
+        return float(np.sqrt(np.mean((np.asarray(p)[obs].astype(np.float64) - gt64) ** 2)))
+
+    def rmse():
+        return rmse_of(prob.get_params())
+
+    r0 = rmse_of(init)
+    # RMSE 1e-2 and 95 / 90 / 85 / 80 % of the initial RMSE
+    levels = [1e-2] + [f * r0 for f in (0.95, 0.9, 0.85, 0.8)]
+    runs = {}
+    for name, opts in (
+            ("meta_eta0.003", L.step_opts(optimizer=L.JSO_OPT_META, eta=0.003, seed=args.seed)),
+            ("meta_eta0.01", L.step_opts(optimizer=L.JSO_OPT_META, eta=0.01, seed=args.seed)),
+            ("adam32_eta0.01", L.step_opts(optimizer=L.JSO_OPT_ADAM, eta=0.01, adam_spp=32,
+                                           seed=args.seed)),
+            ("adam64_eta0.01", L.step_opts(optimizer=L.JSO_OPT_ADAM, eta=0.01, adam_spp=64,
+                                           seed=args.seed))):
+        prob.set_params(init)
+        e0, e1 = torch.cuda.Event(enable_timing=True), torch.cuda.Event(enable_timing=True)
+        clock, it, hist = 0.0, 0, [(0, 0.0, rmse())]
+        chunk = 20 if opts.optimizer == L.JSO_OPT_META else 2
+        while it < 2000 and clock < args.large_ttl_seconds and hist[-1][2] > 1e-2:
+            torch.cuda.synchronize()
+            e0.record()
+            for _ in range(chunk):
+                prob.grad_step(opts)
+            e1.record()
+            torch.cuda.synchronize()
+            clock += e0.elapsed_time(e1) / 1e3
+            it += chunk
+            hist.append((it, clock, rmse()))
+        reach = {"%.4g" % lv: next((h[1] for h in hist if h[2] <= lv), None) for lv in levels}
+        runs[name] = {"seconds_to_rmse": reach, "final_rmse": hist[-1][2],
+                      "iterations": it, "seconds": clock,
+                      "ms_per_iteration": 1e3 * clock / max(it, 1)}
+        print("[bench] large problem %s: %s" % (name, json.dumps(runs[name])), file=sys.stderr,
+              flush=True)
+    del prob
+    torch.cuda.empty_cache()
+    return {"workload": "2048x2048 terrain (999,698 triangles) + 32 spheres, 512x512 texture "
+                        "of RGB + metalness + roughness (1,310,720 params), depth 12, roulette "
+                        "from vertex 3; target at 256 spp",
+            "observable_params": int(obs.sum()), "total_params": spec.n_params,
+            "initial_rmse": r0, "budget_seconds": args.large_ttl_seconds, "runs": runs}
+
+
 def batched_throughput(ctx_problem, args):
     """64 independent problems of uneven size (image side 64-512, 5-65,536
     parameters, own seeds and iteration budgets): differentiable paths/s of
@@ -434,6 +505,9 @@ def main():
     ap.add_argument("--ablation-iters", type=int, default=1000,
                     help="meta-estimator iterations of the ablation runs on the textured "
                          "problem (the tiny problem runs 200; 0: skip)")
+    ap.add_argument("--large-ttl-seconds", type=float, default=0.0,
+                    help="GPU-seconds per run of the terrain time-to-RMSE comparison "
+                         "(meta-estimator vs Adam at 32 and 64 spp; 0: skip)")
     ap.add_argument("--mesh-steps", type=int, default=10,
                     help="timed calls per mesh workload (0 = skip the mesh workloads)")
     args = ap.parse_args()
@@ -516,6 +590,10 @@ def main():
     if args.mesh_steps > 0:
         print("[bench] mesh workloads", file=sys.stderr, flush=True)
         mesh = mesh_workloads(prob.context, args)
+    large = None
+    if args.large_ttl_seconds > 0:
+        print("[bench] terrain time to RMSE", file=sys.stderr, flush=True)
+        large = large_time_to_rmse(prob.context, args)
     ttl = None
     if args.ttl_iters > 0:
         print("[bench] time to loss: Adam-64 vs meta-estimator", file=sys.stderr, flush=True)
@@ -595,6 +673,7 @@ def main():
         "batched": bat,
         "meshes": mesh,
         "ablations": abl,
+        "large_time_to_rmse": large,
     }
     print(json.dumps(line))
 
