@@ -96,6 +96,13 @@ def lib():
         L.orc_grad.restype = i
         L.orc_render_bwd.argtypes = [d, d, u64, u32, u32, i, d, i, d, d, d, d, d, d, i]
         L.orc_render_bwd.restype = i
+        L.orc_render_sampled.argtypes = [d, d, d, u64, u32, u32, i, i, d, d, d, i]
+        L.orc_render_sampled.restype = i
+        L.orc_grad_sampled.argtypes = [d, d, d, u64, u32, u32, u32, i, d, i, d, d, d, d, d, d, d,
+                                       i]
+        L.orc_grad_sampled.restype = i
+        L.orc_render_bwd_sampled.argtypes = [d, d, d, u64, u32, u32, i, d, i, d, d, d, d, d, d, i]
+        L.orc_render_bwd_sampled.restype = i
         _lib = L
     return _lib
 
@@ -210,27 +217,45 @@ def bsdf_many(mat, n, wo, wi, flags: int = 0) -> np.ndarray:
 # ----------------------------------------------------------------------------
 # rendering and gradient samples
 # ----------------------------------------------------------------------------
+def _sample_arr(spec, sample_params):
+    if sample_params is None:
+        return None
+    sp = np.ascontiguousarray(np.asarray(sample_params, np.float64))
+    if sp.size != spec.n_params:
+        raise ValueError("sample_params has %d entries, the scene %d" % (sp.size, spec.n_params))
+    return sp
+
+
 def render(spec, params, seed: int, iteration: int, tag: int, spp: int, flags: int = 0,
-           crop=None, nthreads: Optional[int] = None):
-    """Primal image (H, W, 3) and per-pixel decision margins (H, W)."""
+           crop=None, nthreads: Optional[int] = None, sample_params=None):
+    """Primal image (H, W, 3) and per-pixel decision margins (H, W).
+
+    sample_params (optional): draw the paths at these parameters and weight
+    them by f(x; params) / p(x; sample_params) (every BSDF density taken at
+    sample_params): the previous-parameter half of Eq. 5's finite-difference
+    sample when params = pi_{i-1} and sample_params = pi_i."""
     m = _Marshalled(spec)
     p = np.ascontiguousarray(np.asarray(params, np.float64))
+    sp = _sample_arr(spec, sample_params)
     img = np.zeros((spec.height, spec.width, 3))
     mg = np.full((spec.height, spec.width), np.inf)
     c = _crop_arr(crop)
-    rc = lib().orc_render(m.ptr(), _ptr(p), seed, iteration, tag, spp, flags, _ptr(c),
-                          _ptr(img), _ptr(mg), _nthreads(nthreads))
+    rc = lib().orc_render_sampled(m.ptr(), _ptr(p), _ptr(sp), seed, iteration, tag, spp, flags,
+                                  _ptr(c), _ptr(img), _ptr(mg), _nthreads(nthreads))
     if rc:
         raise ValueError("orc_render failed")
     return img, mg
 
 
 def grad(spec, params, target, seed: int, iteration: int, tag_primal: int, tag_adj: int,
-         spp: int, flags: int = 0, crop=None, mask=None, nthreads: Optional[int] = None):
+         spp: int, flags: int = 0, crop=None, mask=None, nthreads: Optional[int] = None,
+         sample_params=None):
     """One gradient sample of the L2 loss: returns (grad, gabs, img, margin, adj_img)
-    with img the primal image and adj_img the mean radiance of the adjoint paths."""
+    with img the primal image and adj_img the mean radiance of the adjoint paths.
+    sample_params: as in render(), for the primal and the adjoint paths."""
     m = _Marshalled(spec)
     p = np.ascontiguousarray(np.asarray(params, np.float64))
+    sp = _sample_arr(spec, sample_params)
     t = np.ascontiguousarray(np.asarray(target, np.float64).reshape(spec.height, spec.width, 3))
     g = np.zeros(spec.n_params)
     ga = np.zeros(spec.n_params)
@@ -239,19 +264,22 @@ def grad(spec, params, target, seed: int, iteration: int, tag_primal: int, tag_a
     mg = np.full((spec.height, spec.width), np.inf)
     mk = None if mask is None else np.ascontiguousarray(np.asarray(mask, np.uint8))
     c = _crop_arr(crop)
-    rc = lib().orc_grad(m.ptr(), _ptr(p), seed, iteration, tag_primal, tag_adj, spp, _ptr(t),
-                        flags, _ptr(c), _ptr(mk), _ptr(g), _ptr(ga), _ptr(img), _ptr(mg),
-                        _ptr(aimg), _nthreads(nthreads))
+    rc = lib().orc_grad_sampled(m.ptr(), _ptr(p), _ptr(sp), seed, iteration, tag_primal,
+                                tag_adj, spp, _ptr(t), flags, _ptr(c), _ptr(mk), _ptr(g),
+                                _ptr(ga), _ptr(img), _ptr(mg), _ptr(aimg), _nthreads(nthreads))
     if rc:
         raise ValueError("orc_grad failed")
     return g, ga, img, mg, aimg
 
 
 def render_bwd(spec, params, dimg, seed: int, iteration: int, tag: int, spp: int,
-               flags: int = 0, crop=None, mask=None, nthreads: Optional[int] = None):
-    """Fixed-adjoint backward pass: (grad, gabs, margin, adj_img)."""
+               flags: int = 0, crop=None, mask=None, nthreads: Optional[int] = None,
+               sample_params=None):
+    """Fixed-adjoint backward pass: (grad, gabs, margin, adj_img).
+    sample_params: as in render()."""
     m = _Marshalled(spec)
     p = np.ascontiguousarray(np.asarray(params, np.float64))
+    sp = _sample_arr(spec, sample_params)
     d = np.ascontiguousarray(np.asarray(dimg, np.float64).reshape(spec.height, spec.width, 3))
     g = np.zeros(spec.n_params)
     ga = np.zeros(spec.n_params)
@@ -259,9 +287,9 @@ def render_bwd(spec, params, dimg, seed: int, iteration: int, tag: int, spp: int
     aimg = np.zeros((spec.height, spec.width, 3))
     mk = None if mask is None else np.ascontiguousarray(np.asarray(mask, np.uint8))
     c = _crop_arr(crop)
-    rc = lib().orc_render_bwd(m.ptr(), _ptr(p), seed, iteration, tag, spp, _ptr(d), flags,
-                              _ptr(c), _ptr(mk), _ptr(g), _ptr(ga), _ptr(mg), _ptr(aimg),
-                              _nthreads(nthreads))
+    rc = lib().orc_render_bwd_sampled(m.ptr(), _ptr(p), _ptr(sp), seed, iteration, tag, spp,
+                                      _ptr(d), flags, _ptr(c), _ptr(mk), _ptr(g), _ptr(ga),
+                                      _ptr(mg), _ptr(aimg), _nthreads(nthreads))
     if rc:
         raise ValueError("orc_render_bwd failed")
     return g, ga, mg, aimg
@@ -313,12 +341,16 @@ def rounding_sensitivity(spec, fn, radians: float = 1e-6):
 
 def gradient_pair(spec, params, params_prev, target, seed: int, iteration: int,
                   spp_prop: int = 2, spp_fd: int = 1, flags: int = 0, crop=None, mask=None,
-                  nthreads: Optional[int] = None):
+                  nthreads: Optional[int] = None, fd_shared: bool = False):
     """<F_i> (Eq. 2) and <dF_i> (Eq. 5) for one iteration.
 
     <F_i>: spp_prop primal + spp_prop adjoint paths at pi_i (own streams).
     <dF_i>: the same spp_fd primal/adjoint streams evaluated at pi_i and at
     pi_{i-1}, differenced; zero at i = 0 or when no previous parameters exist.
+    By default each half draws its paths at its own parameters from the same
+    random numbers (primary-sample-space replay); fd_shared: the pi_{i-1} half
+    takes the paths drawn at pi_i, weighted by f(x; pi_{i-1}) / p(x; pi_i) --
+    Eq. 5 as written: one path, the integrand at both parameter vectors.
     Returns dict with F, dF, F_abs, dF_abs (FP64), I (prop primal image), margin,
     and the per-pixel radiance of every stream: A (prop adjoint paths),
     I_fd1 / I_fd0 (FD primal at pi_i / pi_{i-1}), A_fd1 / A_fd0 (FD adjoint).
@@ -332,7 +364,8 @@ def gradient_pair(spec, params, params_prev, target, seed: int, iteration: int,
         g1, a1, i1, m1, A1 = grad(spec, params, target, seed, iteration, TAG_PRIMAL_FD,
                                   TAG_ADJ_FD, spp_fd, flags, crop, mask, nthreads)
         g0, a0, i0, m0, A0 = grad(spec, params_prev, target, seed, iteration, TAG_PRIMAL_FD,
-                                  TAG_ADJ_FD, spp_fd, flags, crop, mask, nthreads)
+                                  TAG_ADJ_FD, spp_fd, flags, crop, mask, nthreads,
+                                  sample_params=params if fd_shared else None)
         dF = g1 - g0
         dFa = a1 + a0
         mg = np.minimum(mg, np.minimum(m1, m0))

@@ -601,8 +601,15 @@ double g_jitter_dx = 0.0, g_jitter_dy = 0.0;
 // parameterised material.
 std::atomic<uint64_t> g_paths{0}, g_vertices{0}, g_param_vertices{0};
 
-void trace(const Scene& sc, const double* params, const PathRng& rng, int px, int py, int flags,
-           bool record, PathResult& out) {
+// sample_params (nullable, else = params): the parameters whose BSDF
+// densities choose the directions.  The path is then drawn at sample_params
+// and weighted by f(x; params) / p(x; sample_params) -- every density (the
+// continuation's, and those in both MIS weights) is taken at sample_params --
+// which is the finite-difference sample of Eq. 5 when params = pi_{i-1} and
+// sample_params = pi_i: one path, the integrand evaluated at both parameter
+// vectors over the density of the current ones.
+void trace(const Scene& sc, const double* params, const double* sample_params,
+           const PathRng& rng, int px, int py, int flags, bool record, PathResult& out) {
   const orc_scene* s = sc.s;
   Margin mg;
   double u[4];
@@ -631,6 +638,7 @@ void trace(const Scene& sc, const double* params, const PathRng& rng, int px, in
   for (int j = 1; j <= s->depth; ++j) {
     V3 p = hit.p, n = hit.n, wo = ray.d * -1.0;
     Material mat = material_at(sc, hit, params, mg);
+    Material smat = sample_params ? material_at(sc, hit, sample_params, mg) : mat;
     g_vertices.fetch_add(1, std::memory_order_relaxed);
     if (mat.param) g_param_vertices.fetch_add(1, std::memory_order_relaxed);
     TapeVertex tv;
@@ -655,6 +663,7 @@ void trace(const Scene& sc, const double* params, const PathRng& rng, int px, in
       mg.add(cos_s);
       if (cos_l > 0 && cos_s > 0 && !sc.occluded({p_off, wl}, dist - SHADOW_EPS, mg)) {
         Bsdf nb = eval_bsdf(mat, n, wo, wl, flags);
+        if (sample_params) nb.pdf = eval_bsdf(smat, n, wo, wl, flags).pdf;
         double pl = dist2 / (cos_l * area);
         double wmis = pl / (pl + nb.pdf);
         tv.nee = true;
@@ -668,7 +677,7 @@ void trace(const Scene& sc, const double* params, const PathRng& rng, int px, in
 
     // continuation
     rng.draw(j, 0, u);
-    V3 wi = sample_dir(mat, n, wo, u, flags, mg, hit.kind == K_PLANE);
+    V3 wi = sample_dir(smat, n, wo, u, flags, mg, hit.kind == K_PLANE);
     double ci = dot(n, wi);
     mg.add(ci);  // continuous in value, not in which vertices follow
     bool go = ci > 0;
@@ -676,6 +685,7 @@ void trace(const Scene& sc, const double* params, const PathRng& rng, int px, in
     double q = 1.0;
     if (go) {
       cb = eval_bsdf(mat, n, wo, wi, flags);
+      if (sample_params) cb.pdf = eval_bsdf(smat, n, wo, wi, flags).pdf;
       go = cb.pdf > 0;
     }
     if (go && s->rr_start > 0 && j >= s->rr_start) {
@@ -874,6 +884,13 @@ void orc_bsdf_many(int count, const double mat[5], const double n[3], const doub
 int orc_render(const orc_scene* s, const double* params, uint64_t seed, uint32_t iteration,
                uint32_t tag, int spp, int flags, const int* crop, double* img, double* margin,
                int nthreads) {
+  return orc_render_sampled(s, params, nullptr, seed, iteration, tag, spp, flags, crop, img,
+                            margin, nthreads);
+}
+
+int orc_render_sampled(const orc_scene* s, const double* params, const double* sample_params,
+                       uint64_t seed, uint32_t iteration, uint32_t tag, int spp, int flags,
+                       const int* crop, double* img, double* margin, int nthreads) {
   if (check(s) || spp < 1 || !img) return -1;
   Scene sc(s);
   Crop c = get_crop(s, crop);
@@ -884,7 +901,7 @@ int orc_render(const orc_scene* s, const double* params, uint64_t seed, uint32_t
       double acc[3] = {0, 0, 0}, mg = INF;
       for (int smp = 0; smp < spp; ++smp) {
         PathResult r;
-        trace(sc, params, make_rng(key, pix, smp), x, y, flags, false, r);
+        trace(sc, params, sample_params, make_rng(key, pix, smp), x, y, flags, false, r);
         for (int k = 0; k < 3; ++k) acc[k] += r.L[k];
         mg = std::min(mg, r.margin);
       }
@@ -895,7 +912,8 @@ int orc_render(const orc_scene* s, const double* params, uint64_t seed, uint32_t
   return 0;
 }
 
-static int grad_common(const orc_scene* s, const double* params, uint64_t key_adj, int spp,
+static int grad_common(const orc_scene* s, const double* params, const double* sample_params,
+                       uint64_t key_adj, int spp,
                        const double* dimg, int flags, const Crop& c, const unsigned char* mask,
                        double* grad, double* gabs, double* margin, double* adj_img,
                        int nthreads) {
@@ -915,7 +933,7 @@ static int grad_common(const orc_scene* s, const double* params, uint64_t key_ad
       double acc[3] = {0, 0, 0};
       for (int smp = 0; smp < spp; ++smp) {
         PathResult r;
-        trace(sc, params, make_rng(key_adj, pix, smp), x, y, flags, true, r);
+        trace(sc, params, sample_params, make_rng(key_adj, pix, smp), x, y, flags, true, r);
         backprop(sc, r.tape, adj, g[t].data(), ga[t].data());
         mg = std::min(mg, r.margin);
         for (int k = 0; k < 3; ++k) acc[k] += r.L[k];
@@ -941,12 +959,21 @@ int orc_grad(const orc_scene* s, const double* params, uint64_t seed, uint32_t i
              uint32_t tag_primal, uint32_t tag_adj, int spp, const double* target, int flags,
              const int* crop, const unsigned char* mask, double* grad, double* gabs, double* img,
              double* margin, double* adj_img, int nthreads) {
+  return orc_grad_sampled(s, params, nullptr, seed, iteration, tag_primal, tag_adj, spp, target,
+                          flags, crop, mask, grad, gabs, img, margin, adj_img, nthreads);
+}
+
+int orc_grad_sampled(const orc_scene* s, const double* params, const double* sample_params,
+                     uint64_t seed, uint32_t iteration, uint32_t tag_primal, uint32_t tag_adj,
+                     int spp, const double* target, int flags, const int* crop,
+                     const unsigned char* mask, double* grad, double* gabs, double* img,
+                     double* margin, double* adj_img, int nthreads) {
   if (check(s) || spp < 1 || !grad || !target) return -1;
   Crop c = get_crop(s, crop);
   size_t npix = (size_t)s->width * s->height;
   std::vector<double> I(3 * npix, 0.0), mg(npix, INF), dimg(3 * npix, 0.0);
-  orc_render(s, params, seed, iteration, tag_primal, spp, flags, crop, I.data(), mg.data(),
-             nthreads);
+  orc_render_sampled(s, params, sample_params, seed, iteration, tag_primal, spp, flags, crop,
+                     I.data(), mg.data(), nthreads);
   // L = sum (I - T)^2 / (3 W H)  ->  dL/dI = 2 (I - T) / (3 W H); the relative
   // form divides each term by T^2 + REL_EPS (a constant per pixel, so the
   // primal from its own stream keeps the gradient sample unbiased)
@@ -959,8 +986,8 @@ int orc_grad(const orc_scene* s, const double* params, uint64_t seed, uint32_t i
         const double w = relative ? 1.0 / (target[i] * target[i] + REL_EPS) : 1.0;
         dimg[i] = norm * (I[i] - target[i]) * w;
       }
-  int rc = grad_common(s, params, stream_key(seed, iteration, tag_adj), spp, dimg.data(), flags,
-                       c, mask, grad, gabs, mg.data(), adj_img, nthreads);
+  int rc = grad_common(s, params, sample_params, stream_key(seed, iteration, tag_adj), spp,
+                       dimg.data(), flags, c, mask, grad, gabs, mg.data(), adj_img, nthreads);
   if (img)
     for (int y = c.y0; y < c.y1; ++y)
       for (int x = c.x0; x < c.x1; ++x)
@@ -978,13 +1005,22 @@ int orc_render_bwd(const orc_scene* s, const double* params, uint64_t seed, uint
                    uint32_t tag, int spp, const double* dimg, int flags, const int* crop,
                    const unsigned char* mask, double* grad, double* gabs, double* margin,
                    double* adj_img, int nthreads) {
+  return orc_render_bwd_sampled(s, params, nullptr, seed, iteration, tag, spp, dimg, flags, crop,
+                                mask, grad, gabs, margin, adj_img, nthreads);
+}
+
+int orc_render_bwd_sampled(const orc_scene* s, const double* params,
+                           const double* sample_params, uint64_t seed, uint32_t iteration,
+                           uint32_t tag, int spp, const double* dimg, int flags, const int* crop,
+                           const unsigned char* mask, double* grad, double* gabs, double* margin,
+                           double* adj_img, int nthreads) {
   if (check(s) || spp < 1 || !grad || !dimg) return -1;
   Crop c = get_crop(s, crop);
   if (margin)
     for (int y = c.y0; y < c.y1; ++y)
       for (int x = c.x0; x < c.x1; ++x) margin[(size_t)y * s->width + x] = INF;
-  return grad_common(s, params, stream_key(seed, iteration, tag), spp, dimg, flags, c, mask, grad,
-                     gabs, margin, adj_img, nthreads);
+  return grad_common(s, params, sample_params, stream_key(seed, iteration, tag), spp, dimg, flags,
+                     c, mask, grad, gabs, margin, adj_img, nthreads);
 }
 
 }  // extern "C"

@@ -109,6 +109,26 @@ int orc_render_bwd(const orc_scene* s, const double* params, uint64_t seed, uint
                    const unsigned char* mask, double* grad, double* gabs, double* margin,
                    double* adj_img, int nthreads);
 
+/* The same three with the paths drawn at sample_params (nullable: = params)
+ * and weighted by f(x; params) / p(x; sample_params): every BSDF density --
+ * the continuation's and those in both MIS weights -- is taken at
+ * sample_params.  With params = pi_{i-1} and sample_params = pi_i this is the
+ * previous-parameter half of Eq. 5's finite-difference sample (the path of
+ * pi_i, its integrand at pi_{i-1}). */
+int orc_render_sampled(const orc_scene* s, const double* params, const double* sample_params,
+                       uint64_t seed, uint32_t iteration, uint32_t tag, int spp, int flags,
+                       const int* crop, double* img, double* margin, int nthreads);
+int orc_grad_sampled(const orc_scene* s, const double* params, const double* sample_params,
+                     uint64_t seed, uint32_t iteration, uint32_t tag_primal, uint32_t tag_adj,
+                     int spp, const double* target, int flags, const int* crop,
+                     const unsigned char* mask, double* grad, double* gabs, double* img,
+                     double* margin, double* adj_img, int nthreads);
+int orc_render_bwd_sampled(const orc_scene* s, const double* params,
+                           const double* sample_params, uint64_t seed, uint32_t iteration,
+                           uint32_t tag, int spp, const double* dimg, int flags, const int* crop,
+                           const unsigned char* mask, double* grad, double* gabs, double* margin,
+                           double* adj_img, int nthreads);
+
 #ifdef __cplusplus
 }
 #endif
