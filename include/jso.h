@@ -83,6 +83,15 @@ extern "C" {
 #define JSO_ABLATE_UNCORRELATED 4 /* variance EMAs fed by a second, independent
                                      proportional + FD sample (tags VAR_*)        */
 
+/* finite-difference sample <dF_i> (jso_render_opts.fd_mode, jso_step_opts.fd_mode) */
+#define JSO_FD_REPLAY 0 /* two paths from the same random numbers, each drawn at its own
+                           parameters (pi_i, pi_{i-1}) and differenced per vertex     */
+#define JSO_FD_SHARED 1 /* Eq. 5 as written: one path drawn at pi_i, its integrand
+                           evaluated at pi_i and at pi_{i-1} over the density of pi_i
+                           (every BSDF pdf, hence every MIS weight, at pi_i); the two
+                           gradients share each vertex's footprint and are differenced
+                           before one scatter.  Halves the finite-difference tracing. */
+
 /* render / test-mode flags (jso_render_opts.flags, jso_set_debug) */
 #define JSO_F_NO_NEE 1       /* no light sampling; BSDF-sampled light hits weigh 1 */
 #define JSO_F_LAMBERT_ONLY 2 /* f = c/pi with cosine sampling                      */
@@ -146,6 +155,7 @@ typedef struct {
   int crop[4];               /* x0, y0, x1, y1; all zero = whole image            */
   const uint8_t* pixel_mask; /* dev, H*W, nonzero = skip the pixel; may be NULL   */
   int loss;                  /* JSO_LOSS_* of the adjoint image (estimators)        */
+  int fd_mode;               /* JSO_FD_* of jso_estimate_gradients' dF              */
 } jso_render_opts;
 
 /* Optimiser of jso_grad_step */
@@ -171,6 +181,7 @@ typedef struct {
                            parameters are rejected.                                */
   int loss;             /* JSO_LOSS_*                                               */
   uint32_t ablate;      /* meta: JSO_ABLATE_* bits (0 = the method as published)    */
+  int fd_mode;          /* meta: JSO_FD_* form of the finite-difference sample       */
 } jso_step_opts;
 
 typedef struct {
@@ -268,7 +279,9 @@ int jso_render_bwd(jso_ctx* ctx, int scene_id, const float* params, uint64_t see
  *                 image, spp_prop adjoint paths (tag ADJ_PROP) are replayed;
  *   dF += <dF_i>  the spp_fd primal and adjoint streams (PRIMAL_FD, ADJ_FD)
  *                 traced at pi_i and at pi_{i-1} with identical random numbers
- *                 and differenced per vertex (Eq. 5).  Skipped if dF is NULL.
+ *                 and differenced per vertex (Eq. 5); opts->fd_mode =
+ *                 JSO_FD_SHARED traces each path once, at pi_i, and evaluates
+ *                 it at both.  Skipped if dF is NULL.
  * F, dF: dev, n_params, accumulated into.  img (dev, H*W*3, nullable) receives
  * the proportional primal image.  iteration selects the random streams.
  * loss (host, nullable) receives the loss of that primal image. */

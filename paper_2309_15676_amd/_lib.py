@@ -28,6 +28,7 @@ JSO_OPT_META, JSO_OPT_ADAM = 0, 1
 JSO_TAG_VAR_PRIMAL_PROP, JSO_TAG_VAR_ADJ_PROP, JSO_TAG_VAR_PRIMAL_FD, JSO_TAG_VAR_ADJ_FD = 9, 10, 11, 12
 JSO_LOSS_L2, JSO_LOSS_RELATIVE = 0, 1
 JSO_ABLATE_CENTRED, JSO_ABLATE_NO_CLIP, JSO_ABLATE_UNCORRELATED = 1, 2, 4
+JSO_FD_REPLAY, JSO_FD_SHARED = 0, 1
 JSO_MAX_SPHERES, JSO_MAX_FIXED_MATS, JSO_MAX_TRIS = 32, 8, 4194304
 JSO_LAYOUT_TEXTURE, JSO_LAYOUT_VERTEX = 0, 1
 
@@ -75,7 +76,8 @@ class jso_scene_desc(ctypes.Structure):
 
 class jso_render_opts(ctypes.Structure):
     _fields_ = [("flags", ctypes.c_uint32), ("crop", ctypes.c_int * 4),
-                ("pixel_mask", ctypes.c_void_p), ("loss", ctypes.c_int)]
+                ("pixel_mask", ctypes.c_void_p), ("loss", ctypes.c_int),
+                ("fd_mode", ctypes.c_int)]
 
 
 class jso_step_opts(ctypes.Structure):
@@ -85,7 +87,7 @@ class jso_step_opts(ctypes.Structure):
         ("adam_beta1", ctypes.c_float), ("adam_beta2", ctypes.c_float),
         ("adam_eps", ctypes.c_float), ("adam_spp", ctypes.c_int), ("seed", ctypes.c_uint64),
         ("flags", ctypes.c_uint32), ("precond_lambda", ctypes.c_float),
-        ("loss", ctypes.c_int), ("ablate", ctypes.c_uint32),
+        ("loss", ctypes.c_int), ("ablate", ctypes.c_uint32), ("fd_mode", ctypes.c_int),
     ]
 
 
@@ -306,12 +308,14 @@ def jso_set_target(ctx, sid: int, img, mem: int = JSO_MEM_HOST, n: Optional[int]
     return load().jso_set_target(ctx, sid, img, n, mem)
 
 
-def render_opts(flags: int = 0, crop=None, mask_ptr: int = 0, loss: int = JSO_LOSS_L2):
+def render_opts(flags: int = 0, crop=None, mask_ptr: int = 0, loss: int = JSO_LOSS_L2,
+                fd_mode: int = JSO_FD_REPLAY):
     o = jso_render_opts()
     o.flags = flags
     o.crop[:] = tuple(crop) if crop is not None else (0, 0, 0, 0)
     o.pixel_mask = mask_ptr or None
     o.loss = loss
+    o.fd_mode = fd_mode
     return o
 
 
@@ -346,13 +350,13 @@ def jso_adam_step(ctx, sid, g_ptr, eta, beta1=0.9, beta2=0.999, eps=1e-8) -> int
 
 def step_opts(optimizer=JSO_OPT_META, eta=1e-3, beta_F=0.99, beta_D=0.9, spp_prop=2, spp_fd=1,
               adam_beta1=0.9, adam_beta2=0.999, adam_eps=1e-8, adam_spp=64, seed=0, flags=0,
-              precond_lambda=0.0, loss=JSO_LOSS_L2, ablate=0):
+              precond_lambda=0.0, loss=JSO_LOSS_L2, ablate=0, fd_mode=JSO_FD_REPLAY):
     o = jso_step_opts()
     o.optimizer, o.eta, o.beta_F, o.beta_D = optimizer, eta, beta_F, beta_D
     o.spp_prop, o.spp_fd = spp_prop, spp_fd
     o.adam_beta1, o.adam_beta2, o.adam_eps, o.adam_spp = adam_beta1, adam_beta2, adam_eps, adam_spp
     o.seed, o.flags, o.precond_lambda = seed, flags, precond_lambda
-    o.loss, o.ablate = loss, ablate
+    o.loss, o.ablate, o.fd_mode = loss, ablate, fd_mode
     return o
 
 

@@ -172,6 +172,7 @@ struct DescRing {
 // flags); launch records keep their metadata, their units live on the device.
 struct CachedLaunch {
   int kind, timer, shape, n, stack;
+  bool shared;
   uint32_t blocks;
   size_t lds, offset;
 };
@@ -530,6 +531,10 @@ struct PrimalSpec {
   float* img;     // nullable
   float* delta;   // nullable
   double* loss2;  // nullable
+  // shared-path pair: the paths drawn at `params` are also evaluated at
+  // params_b, whose adjoint image goes to delta_b (its loss is not reported)
+  const float* params_b = nullptr;
+  float* delta_b = nullptr;
 };
 
 struct AdjointSpec {
@@ -541,6 +546,7 @@ struct AdjointSpec {
   float sign;
   uint32_t tag;
   int spp;
+  bool shared = false;    // pair: one path drawn at A, evaluated at A and B (Eq. 5)
 };
 
 // One problem's part of a plan.
@@ -569,6 +575,7 @@ struct LaunchRec {
   uint32_t blocks = 0;
   size_t lds = 0;
   int stack = 0;               // path kernels: BVH stack entries (deepest mesh of the units)
+  bool shared = false;         // path kernels: units hold shared-path pair slices
   size_t dev_offset = 0;       // batches: offset of the units in the device arena
 };
 
@@ -604,6 +611,9 @@ void plan_estimators(const std::vector<ProbPlan>& ps, Plan& plan, int shape = 0)
   std::vector<std::pair<int, int>> prim;
   for (int j = 0; j < p0.np; ++j)
     for (int k = 0; k < p0.pj[j].spp; ++k) prim.push_back({j, k});
+  const bool shared_pairs = std::any_of(p0.aj, p0.aj + p0.na, [](const AdjointSpec& a) {
+    return a.params_b != nullptr && a.shared;
+  });
   std::vector<std::pair<int, int>> units;
   for (int pass = 0; pass < 2; ++pass)
     for (int j = 0; j < p0.na; ++j)
@@ -613,29 +623,55 @@ void plan_estimators(const std::vector<ProbPlan>& ps, Plan& plan, int shape = 0)
   int max_ch = 0;
   for (const ProbPlan& p : ps) max_ch = std::max(max_ch, p.s->n_ch);
   while (next_prim < prim.size() || next_unit < units.size()) {
-    // slice layout of this launch (shared by all problems)
-    struct FSl { int kind, job, sample; };  // kind 0 primal, 1 adjoint A, 2 adjoint B
+    // slice layout of this launch (shared by all problems).  kind 0 primal,
+    // 1 adjoint A, 2 adjoint B (replay pair), 3 adjoint shared pair; a slice
+    // with slot_b >= 0 also writes the radiance of its second ledger there.
+    // The slots of one primal job's samples are contiguous (a shared pair:
+    // all first ledgers, then all second ledgers).
+    struct FSl { int kind, job, sample, slot, slot_b; };
     std::vector<FSl> fsl;
-    std::vector<std::pair<int, int>> fin_jobs;  // (job, first slot)
-    while (next_prim < prim.size() && (int)fsl.size() < kMaxSlots) {
-      const int j = prim[next_prim].first, k = prim[next_prim].second;
-      if (fin_jobs.empty() || fin_jobs.back().first != j) fin_jobs.push_back({j, (int)fsl.size()});
-      fsl.push_back({0, j, k});
-      ++next_prim;
+    int nslot = 0;
+    while (next_prim < prim.size()) {
+      const int j = prim[next_prim].first;
+      if (p0.pj[j].params_b == nullptr) {
+        if (nslot + 1 > kMaxSlots) break;
+        fsl.push_back({0, j, prim[next_prim].second, nslot++, -1});
+        ++next_prim;
+        continue;
+      }
+      int m = 0;
+      while (next_prim + m < prim.size() && prim[next_prim + m].first == j &&
+             nslot + 2 * (m + 1) <= kMaxSlots)
+        ++m;
+      if (m == 0) break;
+      for (int t = 0; t < m; ++t)
+        fsl.push_back({0, j, prim[next_prim + t].second, nslot + t, nslot + m + t});
+      nslot += 2 * m;
+      next_prim += m;
+    }
+    // finalize jobs: (job, second ledger?)
+    std::vector<std::pair<int, int>> fin_jobs;
+    for (const FSl& x : fsl) {
+      if (fin_jobs.empty() || fin_jobs.back().first != x.job) {
+        fin_jobs.push_back({x.job, 0});
+        if (x.slot_b >= 0) fin_jobs.push_back({x.job, 1});
+      }
     }
     std::vector<std::pair<int, int>> reps;  // replay units of this launch
     std::vector<std::pair<int, int>> rep_slot;
     if (next_prim == prim.size()) {
       while (next_unit < units.size()) {
         const auto u = units[next_unit];
-        const int need = p0.aj[u.first].params_b ? 2 : 1;
-        if ((int)fsl.size() + need > kMaxSlots) break;
-        const int sa = (int)fsl.size();
-        fsl.push_back({1, u.first, u.second});
-        int sb = -1;
-        if (need == 2) {
-          sb = (int)fsl.size();
-          fsl.push_back({2, u.first, u.second});
+        const AdjointSpec& a = p0.aj[u.first];
+        const int need = a.params_b ? 2 : 1;
+        if (nslot + need > kMaxSlots) break;
+        const int sa = nslot++;
+        const int sb = need == 2 ? nslot++ : -1;
+        if (a.params_b && a.shared) {
+          fsl.push_back({3, u.first, u.second, sa, sb});
+        } else {
+          fsl.push_back({1, u.first, u.second, sa, -1});
+          if (need == 2) fsl.push_back({2, u.first, u.second, sb, -1});
         }
         reps.push_back(u);
         rep_slot.push_back({sa, sb});
@@ -654,11 +690,21 @@ void plan_estimators(const std::vector<ProbPlan>& ps, Plan& plan, int shape = 0)
       f.scene = cmem((const DevScene*)p.s->d_scene);
       for (size_t i = 0; i < fsl.size(); ++i) {
         const FSl& x = fsl[i];
-        if (x.kind == 0)
-          f.sl[i] = FwdSlice{gmem(p.pj[x.job].params), p.pj[x.job].tag, (uint32_t)x.sample, (int)i};
-        else
-          f.sl[i] = FwdSlice{gmem(x.kind == 1 ? p.aj[x.job].params : p.aj[x.job].params_b),
-                             p.aj[x.job].tag, (uint32_t)x.sample, (int)i};
+        FwdSlice& fs = f.sl[i];
+        fs.sample = (uint32_t)x.sample;
+        fs.slot = x.slot;
+        fs.slot_b = x.slot_b;
+        if (x.kind == 0) {
+          fs.params = gmem(p.pj[x.job].params);
+          fs.params_b = x.slot_b >= 0 ? gmem(p.pj[x.job].params_b) : gmem((const float*)nullptr);
+          fs.tag = p.pj[x.job].tag;
+        } else {
+          const AdjointSpec& a = p.aj[x.job];
+          fs.params = gmem(x.kind == 2 ? a.params_b : a.params);
+          fs.params_b = x.kind == 3 ? gmem(a.params_b) : gmem((const float*)nullptr);
+          fs.tag = a.tag;
+        }
+        if (x.slot_b >= 0) fw.shared = true;
       }
       f.n_slices = (int)fsl.size();
       f.key = p.key;
@@ -683,24 +729,31 @@ void plan_estimators(const std::vector<ProbPlan>& ps, Plan& plan, int shape = 0)
         FinArgs f{};
         f.h.max_iter = p.max_iter;
         for (size_t q = 0; q < fin_jobs.size(); ++q) {
-          const int j = fin_jobs[q].first, s0 = fin_jobs[q].second;
-          int n = 0, first_sample = -1, last_sample = -1;
+          const int j = fin_jobs[q].first;
+          const bool second = fin_jobs[q].second != 0;
+          int n = 0, s0 = -1, first_sample = -1, last_sample = -1;
           for (const FSl& x : fsl)
             if (x.kind == 0 && x.job == j) {
-              if (first_sample < 0) first_sample = x.sample;
+              if (first_sample < 0) {
+                first_sample = x.sample;
+                s0 = second ? x.slot_b : x.slot;
+              }
               last_sample = x.sample;
               ++n;
             }
           FinJob fj{};
           fj.slot0 = s0;
           fj.n = n;
-          fj.accum = gmem(p.s->accum + (size_t)j * 3 * p.s->npix);
+          // a second ledger sums into the accumulator after the plan's jobs
+          // (the plan has at most 2 jobs when one is a shared pair)
+          const int acc = second ? p.np : j;
+          fj.accum = gmem(p.s->accum + (size_t)acc * 3 * p.s->npix);
           fj.first = first_sample == 0;
           fj.last = last_sample == p.pj[j].spp - 1;
           fj.inv_spp = 1.0 / (double)p.pj[j].spp;
-          fj.img = gmem(p.pj[j].img);
-          fj.delta = gmem(p.pj[j].delta);
-          fj.loss2 = gmem(p.pj[j].loss2);
+          fj.img = second ? gmem((float*)nullptr) : gmem(p.pj[j].img);
+          fj.delta = gmem(second ? p.pj[j].delta_b : p.pj[j].delta);
+          fj.loss2 = second ? gmem((double*)nullptr) : gmem(p.pj[j].loss2);
           f.jobs[f.n_jobs++] = fj;
         }
         f.slots = gmem(p.s->slots);
@@ -727,6 +780,7 @@ void plan_estimators(const std::vector<ProbPlan>& ps, Plan& plan, int shape = 0)
       ad.timer = JSO_K_ADJOINT;
       ad.shape = shape;
       ad.lds = adjoint_lds_bytes(max_ch);
+      ad.shared = shared_pairs;
       for (int pass = 0; pass < 2; ++pass) {
         for (const ProbPlan& p : ps) {
           if (crop_empty(p.crop)) continue;
@@ -924,6 +978,27 @@ void plan_optimizer(const std::vector<ProbPlan>& ps, const jso_step_opts& o, Pla
   plan.push_back(std::move(r));
 }
 
+// The finite-difference jobs of <dF_i> (Eq. 5): primal images at pi_i and
+// pi_{i-1} (adjoint images delta1, delta0) and the differenced adjoint paths,
+// as a replay pair (two paths per sample) or, with JSO_FD_SHARED, one path per
+// sample drawn at pi_i and evaluated at both.
+void add_fd_jobs(ProbPlan& p, SceneGPU* s, int fd_mode, uint32_t tag_primal, uint32_t tag_adj,
+                 int spp, float* delta1, float* delta0, float* dF) {
+  if (fd_mode == JSO_FD_SHARED) {
+    PrimalSpec ps{s->params, tag_primal, spp, nullptr, delta1, nullptr};
+    ps.params_b = s->params_prev;
+    ps.delta_b = delta0;
+    p.pj[p.np++] = ps;
+    AdjointSpec as{s->params, s->params_prev, delta1, delta0, dF, 1.0f, tag_adj, spp};
+    as.shared = true;
+    p.aj[p.na++] = as;
+    return;
+  }
+  p.pj[p.np++] = PrimalSpec{s->params, tag_primal, spp, nullptr, delta1, nullptr};
+  p.pj[p.np++] = PrimalSpec{s->params_prev, tag_primal, spp, nullptr, delta0, nullptr};
+  p.aj[p.na++] = AdjointSpec{s->params, s->params_prev, delta1, delta0, dF, 1.0f, tag_adj, spp};
+}
+
 // One problem of a grad_step: the estimator jobs of its optimiser.
 ProbPlan step_problem(SceneGPU* s, const jso_step_opts& o, uint32_t flags, uint32_t max_iter) {
   ProbPlan p{};
@@ -940,17 +1015,11 @@ ProbPlan step_problem(SceneGPU* s, const jso_step_opts& o, uint32_t flags, uint3
     const bool fd = o.spp_fd > 0;
     p.pj[p.np++] = PrimalSpec{s->params, JSO_TAG_PRIMAL_PROP, o.spp_prop, nullptr, d_prop,
                               s->ctl->loss};
-    if (fd) {
-      p.pj[p.np++] = PrimalSpec{s->params, JSO_TAG_PRIMAL_FD, o.spp_fd, nullptr, s->delta + n3,
-                                nullptr};
-      p.pj[p.np++] = PrimalSpec{s->params_prev, JSO_TAG_PRIMAL_FD, o.spp_fd, nullptr,
-                                s->delta + 2 * n3, nullptr};
-    }
     p.aj[p.na++] = AdjointSpec{s->params, nullptr, d_prop, nullptr, s->F, 1.0f,
                                JSO_TAG_ADJ_PROP, o.spp_prop};
     if (fd)
-      p.aj[p.na++] = AdjointSpec{s->params, s->params_prev, s->delta + n3, s->delta + 2 * n3,
-                                 s->dF, 1.0f, JSO_TAG_ADJ_FD, o.spp_fd};
+      add_fd_jobs(p, s, o.fd_mode, JSO_TAG_PRIMAL_FD, JSO_TAG_ADJ_FD, o.spp_fd, s->delta + n3,
+                  s->delta + 2 * n3, s->dF);
   } else {
     p.pj[p.np++] = PrimalSpec{s->params, JSO_TAG_ADAM_PRIMAL, o.adam_spp, nullptr, d_prop,
                               s->ctl->loss};
@@ -971,17 +1040,11 @@ ProbPlan variance_problem(SceneGPU* s, const jso_step_opts& o, uint32_t flags,
   p.np = p.na = 0;
   p.pj[p.np++] = PrimalSpec{s->params, JSO_TAG_VAR_PRIMAL_PROP, o.spp_prop, nullptr, s->delta,
                             nullptr};
-  if (o.spp_fd > 0) {
-    p.pj[p.np++] = PrimalSpec{s->params, JSO_TAG_VAR_PRIMAL_FD, o.spp_fd, nullptr, s->delta + n3,
-                              nullptr};
-    p.pj[p.np++] = PrimalSpec{s->params_prev, JSO_TAG_VAR_PRIMAL_FD, o.spp_fd, nullptr,
-                              s->delta + 2 * n3, nullptr};
-  }
   p.aj[p.na++] = AdjointSpec{s->params, nullptr, s->delta, nullptr, s->Fv, 1.0f,
                              JSO_TAG_VAR_ADJ_PROP, o.spp_prop};
   if (o.spp_fd > 0)
-    p.aj[p.na++] = AdjointSpec{s->params, s->params_prev, s->delta + n3, s->delta + 2 * n3,
-                               s->dFv, 1.0f, JSO_TAG_VAR_ADJ_FD, o.spp_fd};
+    add_fd_jobs(p, s, o.fd_mode, JSO_TAG_VAR_PRIMAL_FD, JSO_TAG_VAR_ADJ_FD, o.spp_fd,
+                s->delta + n3, s->delta + 2 * n3, s->dFv);
   return p;
 }
 
@@ -993,6 +1056,8 @@ int check_step_opts(jso_ctx* c, const jso_step_opts* o) {
   if (o->loss != JSO_LOSS_L2 && o->loss != JSO_LOSS_RELATIVE)
     return fail(c, JSO_E_INVALID, "unknown loss %d", o->loss);
   if (o->ablate & ~7u) return fail(c, JSO_E_INVALID, "unknown ablation bits 0x%x", o->ablate);
+  if (o->fd_mode != JSO_FD_REPLAY && o->fd_mode != JSO_FD_SHARED)
+    return fail(c, JSO_E_INVALID, "unknown fd_mode %d", o->fd_mode);
   if (!(o->precond_lambda >= 0.0f && std::isfinite(o->precond_lambda)))
     return fail(c, JSO_E_INVALID, "precond_lambda must be finite and >= 0");
   if (o->optimizer == JSO_OPT_META) {
@@ -1024,12 +1089,12 @@ hipError_t launch_rec(const LaunchRec& r, const void* dev_units, unsigned long l
   switch (r.kind) {
     case Kern::Forward:
       return launch_forward(static_cast<const FwdArgs*>(dev_units), r.n, r.blocks, r.shape,
-                            r.stack, work, st);
+                            r.stack, r.shared, work, st);
     case Kern::Finalize:
       return launch_finalize(static_cast<const FinArgs*>(dev_units), r.n, r.blocks, st);
     case Kern::Adjoint:
       return launch_adjoint(static_cast<const RepArgs*>(dev_units), r.n, r.blocks, r.shape, r.lds,
-                            r.stack, work, st);
+                            r.stack, r.shared, work, st);
     case Kern::Meta:
       return launch_meta(static_cast<const MetaArgs*>(dev_units), r.n, r.blocks, st);
     case Kern::Adam:
@@ -1063,6 +1128,7 @@ uint64_t config_hash(const std::vector<SceneGPU*>& ss, const jso_step_opts& o) {
     mix((uint64_t)s->dev.n_tris);
     mix((uint64_t)(o.precond_lambda > 0.0f && preconditioned(s)));
     mix((uint64_t)uncorrelated(o));
+    mix((uint64_t)(o.optimizer == JSO_OPT_META && o.spp_fd > 0 ? o.fd_mode : 0));
   }
   return h;
 }
@@ -1135,7 +1201,8 @@ int exec_cached(jso_ctx* c, const std::vector<uint64_t>& sig, Build build) {
     for (size_t k = 0; k < plan.size(); ++k) {
       const LaunchRec& r = plan[k];
       np.launches.push_back(
-          CachedLaunch{(int)r.kind, r.timer, r.shape, r.n, r.stack, r.blocks, r.lds, off[k]});
+          CachedLaunch{(int)r.kind, r.timer, r.shape, r.n, r.stack, r.shared, r.blocks, r.lds,
+                       off[k]});
     }
     np.sig = sig;
     pc.plans.push_back(std::move(np));
@@ -1152,6 +1219,7 @@ int exec_cached(jso_ctx* c, const std::vector<uint64_t>& sig, Build build) {
     r.blocks = l.blocks;
     r.lds = l.lds;
     r.stack = l.stack;
+    r.shared = l.shared;
     TIMED_LAUNCH(c, l.timer, launch_rec(r, hit->dev + l.offset, work, c->stream));
   }
   return JSO_OK;
@@ -1160,7 +1228,8 @@ int exec_cached(jso_ctx* c, const std::vector<uint64_t>& sig, Build build) {
 // The estimator jobs of jso_estimate_gradients (same streams as a meta step).
 ProbPlan estimate_problem(SceneGPU* s, uint64_t seed, uint32_t iteration, int spp_prop,
                           int spp_fd, float* F, float* dF, float* img, double* loss2,
-                          const Crop& crop, const uint8_t* mask, uint32_t flags, int loss) {
+                          const Crop& crop, const uint8_t* mask, uint32_t flags, int loss,
+                          int fd_mode) {
   ProbPlan p{};
   p.s = s;
   p.relative = loss == JSO_LOSS_RELATIVE;
@@ -1171,17 +1240,11 @@ ProbPlan estimate_problem(SceneGPU* s, uint64_t seed, uint32_t iteration, int sp
   const size_t n3 = 3 * s->npix;
   const bool fd = dF != nullptr && spp_fd > 0;
   p.pj[p.np++] = PrimalSpec{s->params, JSO_TAG_PRIMAL_PROP, spp_prop, img, s->delta, loss2};
-  if (fd) {
-    p.pj[p.np++] = PrimalSpec{s->params, JSO_TAG_PRIMAL_FD, spp_fd, nullptr, s->delta + n3,
-                              nullptr};
-    p.pj[p.np++] = PrimalSpec{s->params_prev, JSO_TAG_PRIMAL_FD, spp_fd, nullptr,
-                              s->delta + 2 * n3, nullptr};
-  }
   p.aj[p.na++] = AdjointSpec{s->params, nullptr, s->delta, nullptr, F, 1.0f, JSO_TAG_ADJ_PROP,
                              spp_prop};
   if (fd)
-    p.aj[p.na++] = AdjointSpec{s->params, s->params_prev, s->delta + n3, s->delta + 2 * n3, dF,
-                               1.0f, JSO_TAG_ADJ_FD, spp_fd};
+    add_fd_jobs(p, s, fd_mode, JSO_TAG_PRIMAL_FD, JSO_TAG_ADJ_FD, spp_fd, s->delta + n3,
+                s->delta + 2 * n3, dF);
   return p;
 }
 
@@ -1430,13 +1493,17 @@ int jso_estimate_gradients(jso_ctx* c, int id, uint64_t seed, uint32_t iteration
   const int lossk = opts ? opts->loss : JSO_LOSS_L2;
   if (lossk != JSO_LOSS_L2 && lossk != JSO_LOSS_RELATIVE)
     return fail(c, JSO_E_INVALID, "unknown loss %d", lossk);
+  const int fd_mode = opts ? opts->fd_mode : JSO_FD_REPLAY;
+  if (fd_mode != JSO_FD_REPLAY && fd_mode != JSO_FD_SHARED)
+    return fail(c, JSO_E_INVALID, "unknown fd_mode %d", fd_mode);
   DeviceGuard g(c->device);
   HIP_TRY(c, hipMemsetAsync(s->scratch_loss, 0, 2 * sizeof(double), c->stream));
   Plan plan;
   plan_estimators({estimate_problem(s, seed, iteration, spp_prop, spp_fd, F, dF, img,
                                     s->scratch_loss, crop_of(s, opts),
                                     opts ? opts->pixel_mask : nullptr,
-                                    c->debug_flags | (opts ? opts->flags : 0u), lossk)},
+                                    c->debug_flags | (opts ? opts->flags : 0u), lossk,
+                                    fd_mode)},
                   plan, c->tile_shape);
   int rc = exec_plan(c, plan);
   if (rc) return rc;
@@ -1553,7 +1620,7 @@ int jso_grad_step(jso_ctx* c, const int* ids, int n, const jso_step_opts* o,
                      (uint64_t)o->spp_prop, (uint64_t)o->spp_fd, bits(o->adam_beta1),
                      bits(o->adam_beta2), bits(o->adam_eps), (uint64_t)o->adam_spp, o->seed,
                      (uint64_t)flags, bits(o->precond_lambda), (uint64_t)o->loss,
-                     (uint64_t)o->ablate})
+                     (uint64_t)o->ablate, (uint64_t)o->fd_mode})
     sig.push_back(v);
   rc = exec_cached(c, sig, [&](Plan& plan) {
     std::vector<ProbPlan> ps, pv;

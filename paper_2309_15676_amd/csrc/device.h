@@ -670,6 +670,16 @@ struct VertexGrad {
   float g[5];
 };
 
+// Second ledger of a shared-path finite-difference pair (Eq. 5): the path
+// drawn at the first parameter vector, weighted by the BSDF of the second one
+// over the first one's densities (continuation divisions and both MIS weights
+// keep the first vector's pdf).  Forward: radiance collected so far; replay:
+// radiance still to come.
+struct Ledger2 {
+  double led[3];
+  float beta[3];
+};
+
 template <bool kMesh>
 __device__ __forceinline__ void path_begin(const DevScene& S, const TravStack& st, const Rng& rng,
                                            int px, int py, uint32_t flags, Path& P) {
@@ -710,11 +720,17 @@ __device__ __forceinline__ void path_begin(const DevScene& S, const TravStack& s
 //   NEE:           adj . beta K df(w_l)
 //   continuation:  adj . (R / f) df(w_i)
 // which is the derivative of adj . C w.r.t. this vertex's material.
-template <bool kGrad, bool kMesh>
-__device__ __forceinline__ void path_vertex(const DevScene& S, const TravStack& st,
-                                            const float* __restrict__ params, const Rng& rng,
-                                            uint32_t flags, Path& P, const float adj[3],
-                                            VertexGrad& vg) {
+// kTwo: P also carries the second ledger L2 of a shared-path pair, evaluated
+// with the material of params_b at the same point and directions; with kGrad
+// vg.g is then (gradient of ledger 1) - (gradient of ledger 2, adjoint adj_b)
+// over the one footprint both share.
+template <bool kGrad, bool kMesh, bool kTwo>
+__device__ __forceinline__ void path_vertex2(const DevScene& S, const TravStack& st,
+                                             const float* __restrict__ params,
+                                             const float* __restrict__ params_b, const Rng& rng,
+                                             uint32_t flags, Path& P, Ledger2& L2,
+                                             const float adj[3], const float adj_b[3],
+                                             VertexGrad& vg) {
   Surf x;
   x.p = P.o;
   x.kind = P.kind();
@@ -755,12 +771,19 @@ __device__ __forceinline__ void path_vertex(const DevScene& S, const TravStack& 
   }
   const V3 p = x.p, n = x.n;
   const V3 wo = mk(-P.d.x, -P.d.y, -P.d.z);
-  Mat M;
+  Mat M, Mb;
   vg.valid = material_at<kMesh>(S, params, x, M, vg.fp);
+  if constexpr (kTwo) {
+    Footprint fpb;
+    material_at<kMesh>(S, params_b, x, Mb, fpb);
+  }
   vg.j = j;
+  // kTwo: the second ledger's gradient is summed apart and subtracted at the
+  // end, so equal parameter vectors give an exactly zero difference
+  float gb[5];
   if (kGrad) {
 #pragma unroll
-    for (int b = 0; b < 5; ++b) vg.g[b] = 0.0f;
+    for (int b = 0; b < 5; ++b) vg.g[b] = gb[b] = 0.0f;
   }
   const V3 po = p + n * kRayEps;
   float u[4];
@@ -779,6 +802,8 @@ __device__ __forceinline__ void path_vertex(const DevScene& S, const TravStack& 
       eval_bsdf<kGrad>(M, n, wo, wl, flags, nb);
       const float pl = dist2 / (cos_l * S.larea);
       const float wmis = pl / (pl + nb.pdf);
+      Bsdf nbb;
+      if constexpr (kTwo) eval_bsdf<kGrad>(Mb, n, wo, wl, flags, nbb);
 #pragma unroll
       for (int k = 0; k < 3; ++k) {
         const float K = cos_s * S.Le[k] * wmis / pl;
@@ -789,6 +814,16 @@ __device__ __forceinline__ void path_vertex(const DevScene& S, const TravStack& 
           vg.g[k] += coef * nb.dc[k];
           vg.g[3] += coef * nb.dm[k];
           vg.g[4] += coef * nb.dr[k];
+        }
+        if constexpr (kTwo) {
+          const float tb = L2.beta[k] * nbb.f[k] * K;
+          L2.led[k] += kGrad ? -(double)tb : (double)tb;
+          if (kGrad) {
+            const float coef = adj_b[k] * L2.beta[k] * K;
+            gb[k] += coef * nbb.dc[k];
+            gb[3] += coef * nbb.dm[k];
+            gb[4] += coef * nbb.dr[k];
+          }
         }
       }
     }
@@ -810,10 +845,16 @@ __device__ __forceinline__ void path_vertex(const DevScene& S, const TravStack& 
     q = S.rr_q;
   }
   if (!go) {
+    if constexpr (kTwo && kGrad) {
+#pragma unroll
+      for (int b = 0; b < 5; ++b) vg.g[b] -= gb[b];
+    }
     P.alive = false;
     return;
   }
   const float cw = ci / (cb.pdf * q);
+  Bsdf cbb;
+  if constexpr (kTwo) eval_bsdf<kGrad>(Mb, n, wo, wi, flags, cbb);
   if (kGrad) {
 #pragma unroll
     for (int k = 0; k < 3; ++k) {
@@ -824,10 +865,26 @@ __device__ __forceinline__ void path_vertex(const DevScene& S, const TravStack& 
         vg.g[3] += coef * cb.dm[k];
         vg.g[4] += coef * cb.dr[k];
       }
+      if constexpr (kTwo) {
+        if (cbb.f[k] > 0.0f) {
+          const float R = (float)L2.led[k];
+          const float coef = adj_b[k] * R / cbb.f[k];
+          gb[k] += coef * cbb.dc[k];
+          gb[3] += coef * cbb.dm[k];
+          gb[4] += coef * cbb.dr[k];
+        }
+      }
+    }
+    if constexpr (kTwo) {
+#pragma unroll
+      for (int b = 0; b < 5; ++b) vg.g[b] -= gb[b];
     }
   }
 #pragma unroll
-  for (int k = 0; k < 3; ++k) P.beta[k] *= cb.f[k] * cw;
+  for (int k = 0; k < 3; ++k) {
+    P.beta[k] *= cb.f[k] * cw;
+    if constexpr (kTwo) L2.beta[k] *= cbb.f[k] * cw;
+  }
   P.d = wi;
   const Hit h = intersect<kMesh>(S, st, po, wi);
   P.o = po + wi * h.t;
@@ -836,6 +893,10 @@ __device__ __forceinline__ void path_vertex(const DevScene& S, const TravStack& 
     for (int k = 0; k < 3; ++k) {
       const double e = (double)(P.beta[k] * S.env[k]);
       P.led[k] += kGrad ? -e : e;
+      if constexpr (kTwo) {
+        const double eb = (double)(L2.beta[k] * S.env[k]);
+        L2.led[k] += kGrad ? -eb : eb;
+      }
     }
     P.alive = false;
   } else if (h.kind == HIT_LIGHT) {
@@ -845,12 +906,26 @@ __device__ __forceinline__ void path_vertex(const DevScene& S, const TravStack& 
     for (int k = 0; k < 3; ++k) {
       const double e = (double)(P.beta[k] * (S.Le[k] * wb));
       P.led[k] += kGrad ? -e : e;
+      if constexpr (kTwo) {
+        const double eb = (double)(L2.beta[k] * (S.Le[k] * wb));
+        L2.led[k] += kGrad ? -eb : eb;
+      }
     }
     P.alive = false;
   } else {
     P.alive = j < S.depth;
     P.set_hit(h.kind, h.obj, j + 1);
   }
+}
+
+template <bool kGrad, bool kMesh>
+__device__ __forceinline__ void path_vertex(const DevScene& S, const TravStack& st,
+                                            const float* __restrict__ params, const Rng& rng,
+                                            uint32_t flags, Path& P, const float adj[3],
+                                            VertexGrad& vg) {
+  Ledger2 unused;
+  path_vertex2<kGrad, kMesh, false>(S, st, params, nullptr, rng, flags, P, unused, adj, nullptr,
+                                    vg);
 }
 
 }  // namespace jso

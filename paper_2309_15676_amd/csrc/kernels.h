@@ -70,9 +70,13 @@ constexpr int kMaxSlots = 8;  // path slots per pixel per launch
 // One grid slice of k_forward: the paths of one sample of one parameter set.
 struct FwdSlice {
   JSO_GMEM const float* params;
+  // non-null: a shared-path pair (Eq. 5): the paths drawn at `params` are also
+  // evaluated at params_b, whose radiance goes to slot_b
+  JSO_GMEM const float* params_b;
   uint32_t tag;     // random stream
   uint32_t sample;  // sample index within the stream
   int slot;         // output slot
+  int slot_b;
 };
 
 struct FwdArgs {
@@ -121,7 +125,9 @@ struct FinArgs {
 constexpr float kRelEps = 0.01f;
 
 // One grid slice of k_adjoint: the replay of one sample of one job, a single
-// path (params_b null) or a finite-difference pair (+A - B).
+// path (params_b null) or a finite-difference pair (+A - B): two paths from the
+// same random numbers, each drawn at its own parameters, or (shared) one path
+// drawn at A's parameters with a second ledger evaluated at B's.
 struct RepSlice {
   JSO_GMEM const float* params;
   JSO_GMEM const float* params_b;
@@ -216,12 +222,14 @@ hipError_t launch_dct(const DctArgs* U, int n, uint32_t blocks, hipStream_t st);
 // shape: index into kShapeW / kShapeH (the tiles the units were built for)
 // stack: BVH traversal-stack entries per lane (the deepest mesh among the
 // units' scenes; 0 = no scene of the launch has a mesh), at most kBvhMaxStack
+// shared: the units may hold shared-path pair slices (forward: params_b set;
+// adjoint: pair slices are then all shared-path pairs, none a replay pair)
 hipError_t launch_forward(const FwdArgs* U, int n, uint32_t blocks, int shape, int stack,
-                          unsigned long long* work, hipStream_t st);
+                          bool shared, unsigned long long* work, hipStream_t st);
 hipError_t launch_finalize(const FinArgs* U, int n, uint32_t blocks, hipStream_t st);
 // lds: dynamic LDS bytes (adjoint_lds_bytes of the largest channel count)
 hipError_t launch_adjoint(const RepArgs* U, int n, uint32_t blocks, int shape, size_t lds,
-                          int stack, unsigned long long* work, hipStream_t st);
+                          int stack, bool shared, unsigned long long* work, hipStream_t st);
 hipError_t launch_meta(const MetaArgs* U, int n, uint32_t blocks, hipStream_t st);
 hipError_t launch_adam(const AdamArgs* U, int n, uint32_t blocks, hipStream_t st);
 hipError_t launch_fill_f64(double* p, size_t n, double v, hipStream_t st);

@@ -14,6 +14,8 @@
 //   k_adam     - Adam baseline
 #include <hip/hip_runtime.h>
 
+#include <type_traits>
+
 #include "device.h"
 #include "kernels.h"
 
@@ -226,7 +228,18 @@ struct FwdItem {
   int src, pad_;
 };
 
+struct FwdItem2 {  // a shared-path pair: the path and its second ledger
+  Path P;
+  Ledger2 L2;
+  int src, pad_;
+};
+
 constexpr int kFwdXchgWords = (int)(sizeof(FwdItem) / 4);
+constexpr int kFwd2XchgWords = (int)(sizeof(FwdItem2) / 4);
+
+// The second ledger of an exchange item (single paths have none: `none`).
+__device__ __forceinline__ Ledger2& ledger2(FwdItem2& w, Ledger2&) { return w.L2; }
+__device__ __forceinline__ Ledger2& ledger2(FwdItem&, Ledger2& none) { return none; }
 
 // ---------------------------------------------------------------------------
 // forward pass: one block = one tile of one slice; each path's radiance (its
@@ -234,12 +247,15 @@ constexpr int kFwdXchgWords = (int)(sizeof(FwdItem) / 4);
 // ---------------------------------------------------------------------------
 // The kernel bodies take the scene through a restrict-qualified parameter:
 // nothing the kernels write aliases it, so its fields stay in registers.
-template <class SH, bool kMesh>
+// kTwo: the slice is a shared-path pair (params_b set): each path also
+// carries the ledger of params_b, stored to slot_b.
+template <class SH, bool kMesh, bool kTwo>
 __device__ __forceinline__ void forward_tile(const FwdArgs& A, const DevScene* __restrict__ Sp,
-                                             uint32_t iter, uint32_t* s_xchg, int* s_cnt,
-                                             const TravStack& st, unsigned long long* work) {
+                                             const TileBlock& tb, uint32_t iter,
+                                             uint32_t* s_xchg, int* s_cnt, const TravStack& st,
+                                             unsigned long long* work) {
+  using Item = typename std::conditional<kTwo, FwdItem2, FwdItem>::type;
   const DevScene& S = *Sp;
-  const TileBlock tb = tile_block<SH>(A);
   const FwdSlice& sl = A.sl[tb.slice];
   int px, py;
   const bool inside = tile_pixel<SH>(A.crop, tb, px, py);
@@ -248,62 +264,87 @@ __device__ __forceinline__ void forward_tile(const FwdArgs& A, const DevScene* _
   const uint64_t key = stream_key(A.key.seed, iter, sl.tag);
   const BlockPaths<SH> B = block_paths<SH>(tb, S, key, sl.sample, A.flags);
   double* out = G(A.slots) + (size_t)sl.slot * A.npix * 3;
+  double* out_b = kTwo ? G(A.slots) + (size_t)sl.slot_b * A.npix * 3 : nullptr;
+  const float* params_b = kTwo ? G(sl.params_b) : nullptr;
   const float zero[3] = {0.0f, 0.0f, 0.0f};
   VertexGrad vg;
   int n_vert = 0;
-  Path P;
+  Item mine;
+  Ledger2 none;
+  Path& P = mine.P;
+  Ledger2& L2 = ledger2(mine, none);
   P.alive = false;
   if (active) {
     const Rng rng = B.rng((int)threadIdx.x);
     path_begin<kMesh>(S, st, rng, px, py, A.flags, P);
+    if (kTwo) {
+#pragma unroll
+      for (int k = 0; k < 3; ++k) {
+        L2.led[k] = P.led[k];  // what the camera ray sees does not depend on the material
+        L2.beta[k] = 1.0f;
+      }
+    }
     if (P.alive) {
       ++n_vert;
-      path_vertex<false, kMesh>(S, st, G(sl.params), rng, A.flags, P, zero, vg);
+      path_vertex2<false, kMesh, kTwo>(S, st, G(sl.params), params_b, rng, A.flags, P, L2, zero,
+                                       zero, vg);
     }
-    if (!P.alive) store_radiance(out, pix, P.led);
+    if (!P.alive) {
+      store_radiance(out, pix, P.led);
+      if (kTwo) store_radiance(out_b, pix, L2.led);
+    }
   }
   int n;
-  const int r = block_rank<SH>(P.alive, n, s_cnt);
-  FwdItem W;
+  const bool alive = P.alive;
+  const int r = block_rank<SH>(alive, n, s_cnt);
+  mine.src = (int)threadIdx.x;
+  Item W;
   if (n > compact_max<SH>()) {
-    W.P = P;
-    W.src = (int)threadIdx.x;
+    W = mine;
   } else {
-    FwdItem mine;
-    mine.P = P;
-    mine.src = (int)threadIdx.x;
     W.P.alive = false;
     W.src = (int)threadIdx.x;
-    if (n > 0) pack(s_xchg, P.alive, r, n, mine, W);
+    if (n > 0) pack(s_xchg, alive, r, n, mine, W);
   }
   // no barrier below: waves without a path leave
   if (W.P.alive) {
     const Rng rng = B.rng(W.src);
+    Ledger2& WL = ledger2(W, none);
     while (W.P.alive) {
       ++n_vert;
-      path_vertex<false, kMesh>(S, st, G(sl.params), rng, A.flags, W.P, zero, vg);
+      path_vertex2<false, kMesh, kTwo>(S, st, G(sl.params), params_b, rng, A.flags, W.P, WL, zero,
+                                       zero, vg);
     }
     store_radiance(out, B.pixel(W.src), W.P.led);
+    if (kTwo) store_radiance(out_b, B.pixel(W.src), WL.led);
   }
   count_work(work ? work + 2 : nullptr, active ? 1 : 0, n_vert);
 }
 
 // kMesh: the launch's scenes may hold a triangle mesh; the dynamic LDS then
 // holds `stack` traversal-stack entries per lane.
+// kShared: the launch may hold shared-path pair slices (the other launches
+// keep the smaller exchange buffer and register budget of single paths).
 // Mesh scenes: 96 VGPRs (5 waves per SIMD) measured 10% faster than the
-// 102 the compiler picks by itself.
-template <int TW, int TH, bool kMesh>
-__global__ void __launch_bounds__(TW * TH) __attribute__((amdgpu_waves_per_eu(kMesh ? 5 : 4)))
+// 102 the compiler picks by itself; the two-ledger path of shared pairs needs
+// more and keeps 4 waves (128 VGPRs), where it does not spill.
+template <int TW, int TH, bool kMesh, bool kShared>
+__global__ void __launch_bounds__(TW * TH)
+__attribute__((amdgpu_waves_per_eu(kMesh && !kShared ? 5 : 4)))
 k_forward(const FwdArgs* __restrict__ Units, int n_units, int stack, unsigned long long* work) {
   using SH = Shape<TW, TH>;
-  __shared__ uint32_t s_xchg[kFwdXchgWords * kXchg];
+  __shared__ uint32_t s_xchg[(kShared ? kFwd2XchgWords : kFwdXchgWords) * kXchg];
   __shared__ int s_cnt[SH::WAVES];
   extern __shared__ uint32_t s_dyn[];
   const FwdArgs& A = unit_of(Units, n_units);
   const uint32_t iter = iteration_of(A.key);
   if (A.h.max_iter && iter >= A.h.max_iter) return;  // finished problem
   const TravStack st{s_dyn + threadIdx.x, SH::N, stack};
-  forward_tile<SH, kMesh>(A, G(A.scene), iter, s_xchg, s_cnt, st, work);
+  const TileBlock tb = tile_block<SH>(A);
+  if (kShared && G(A.sl[tb.slice].params_b) != nullptr)  // uniform over the block
+    forward_tile<SH, kMesh, kShared>(A, G(A.scene), tb, iter, s_xchg, s_cnt, st, work);
+  else
+    forward_tile<SH, kMesh, false>(A, G(A.scene), tb, iter, s_xchg, s_cnt, st, work);
 }
 
 // ---------------------------------------------------------------------------
@@ -569,7 +610,15 @@ struct RepPairItem {
   int src, pad_;
 };
 
+struct RepSharedItem {  // a shared-path pair: one path, two ledgers
+  Path P;
+  Ledger2 L2;
+  float adj_a[3], adj_b[3];
+  int src, pad_;
+};
+
 constexpr int kRepXchgWords = (int)(sizeof(RepPairItem) / 4);
+static_assert(sizeof(RepSharedItem) <= sizeof(RepPairItem), "exchange buffer size");
 
 // Start the replay of a path: P.led = the radiance still to come.
 template <bool kMesh>
@@ -586,16 +635,18 @@ __device__ __forceinline__ void replay_begin(const DevScene& S, const TravStack&
 // (their gradients go to the block table, flushed right after), later ones on
 // the compacted lanes in a wave-uniform loop, so the later-vertex scatter can
 // use the whole wave.  The exchange buffer reuses the table's LDS.
-template <class SH, bool kMesh>
+// kPairs: the launch may hold replay-pair slices (kPairs = false compiles
+// their code out).
+template <class SH, bool kMesh, bool kPairs>
 __device__ __forceinline__ void adjoint_tile(const RepArgs& A, const DevScene* __restrict__ Sp,
-                                             uint32_t iter, uint32_t* s_dyn, int* s_cnt,
-                                             const TravStack& st, unsigned long long* work) {
+                                             const TileBlock& tb, uint32_t iter, uint32_t* s_dyn,
+                                             int* s_cnt, const TravStack& st,
+                                             unsigned long long* work) {
   const DevScene& S = *Sp;
   uint32_t* s_keys = s_dyn;
   float* s_vals = reinterpret_cast<float*>(s_dyn + kTableSize);
-  const TileBlock tb = tile_block<SH>(A);
   const RepSlice& sl = A.sl[tb.slice];
-  const bool pair = G(sl.params_b) != nullptr;  // uniform over the block
+  const bool pair = kPairs && G(sl.params_b) != nullptr;  // uniform over the block
   int px, py;
   const bool inside = tile_pixel<SH>(A.crop, tb, px, py);
   const uint32_t pix = (uint32_t)(py * S.width + px);
@@ -740,9 +791,103 @@ __device__ __forceinline__ void adjoint_tile(const RepArgs& A, const DevScene* _
   count_work(work, paths, n_vert);
 }
 
+// A shared-path pair slice (Eq. 5 as written): each path is drawn at A's
+// parameters and replayed once; the vertex carries both ledgers (B's material
+// evaluated over A's densities), and the difference of the two gradients is
+// formed in registers over the one footprint they share, so it is scattered
+// once.  The first vertices go to the block table as in adjoint_tile.
+template <class SH, bool kMesh>
+__device__ __forceinline__ void adjoint_tile_shared(const RepArgs& A,
+                                                    const DevScene* __restrict__ Sp,
+                                                    const TileBlock& tb, uint32_t iter,
+                                                    uint32_t* s_dyn, int* s_cnt,
+                                                    const TravStack& st,
+                                                    unsigned long long* work) {
+  const DevScene& S = *Sp;
+  uint32_t* s_keys = s_dyn;
+  float* s_vals = reinterpret_cast<float*>(s_dyn + kTableSize);
+  const RepSlice& sl = A.sl[tb.slice];
+  int px, py;
+  const bool inside = tile_pixel<SH>(A.crop, tb, px, py);
+  const uint32_t pix = (uint32_t)(py * S.width + px);
+  const bool active = inside && !(G(A.mask) && G(A.mask)[pix]);
+  for (int i = threadIdx.x; i < kTableSize; i += SH::N) s_keys[i] = kEmpty;
+  for (int i = threadIdx.x; i < kTableSize * S.n_ch; i += SH::N) s_vals[i] = 0.0f;
+  __syncthreads();
+  Sink sink;
+  sink.init(GradTable{s_keys, s_vals, G(sl.grad)});
+  const uint64_t key = stream_key(A.key.seed, iter, sl.tag);
+  const BlockPaths<SH> B = block_paths<SH>(tb, S, key, sl.sample, A.flags);
+  const Rng rng = B.rng((int)threadIdx.x);
+  const int tid = (int)threadIdx.x;
+  const float* pa = G(sl.params);
+  const float* pb = G(sl.params_b);
+  RepSharedItem mine;
+  mine.P.alive = false;
+  mine.src = tid;
+  int n_vert = 0;
+  {
+    VertexGrad v;
+    v.valid = false;
+    if (active) {
+#pragma unroll
+      for (int k = 0; k < 3; ++k) {
+        mine.adj_a[k] = G(sl.delta)[3 * (size_t)pix + k] * sl.adj_scale;
+        mine.adj_b[k] = G(sl.delta_b)[3 * (size_t)pix + k] * sl.adj_scale;
+      }
+      path_begin<kMesh>(S, st, rng, px, py, A.flags, mine.P);
+      const double* Ca = G(A.slots) + ((size_t)sl.slot_a * A.npix + pix) * 3;
+      const double* Cb = G(A.slots) + ((size_t)sl.slot_b * A.npix + pix) * 3;
+#pragma unroll
+      for (int k = 0; k < 3; ++k) {
+        mine.L2.led[k] = Cb[k] - mine.P.led[k];
+        mine.L2.beta[k] = 1.0f;
+        mine.P.led[k] = Ca[k] - mine.P.led[k];
+      }
+      if (mine.P.alive) {
+        ++n_vert;
+        path_vertex2<true, kMesh, true>(S, st, pa, pb, rng, A.flags, mine.P, mine.L2,
+                                        mine.adj_a, mine.adj_b, v);
+      }
+    }
+    sink.template add<kMesh>(S, v, 1.0f);  // first vertices (j = 1) go to the table
+  }
+  __syncthreads();
+  sink.flush_table(S, SH::N);
+  const bool live = mine.P.alive;
+  int n;
+  const int r = block_rank<SH>(live, n, s_cnt);  // its barriers also retire the table
+  RepSharedItem W;
+  if (n > compact_max<SH>()) {
+    W = mine;
+  } else {
+    W.P.alive = false;
+    W.src = tid;
+    if (n > 0) pack(s_dyn, live, r, n, mine, W);
+  }
+  // no barrier below: waves without a path leave
+  if (__ballot(W.P.alive) != 0) {
+    const Rng wr = B.rng(W.src);
+    while (__ballot(W.P.alive) != 0) {
+      VertexGrad v;
+      v.valid = false;
+      if (W.P.alive) {
+        ++n_vert;
+        path_vertex2<true, kMesh, true>(S, st, pa, pb, wr, A.flags, W.P, W.L2, W.adj_a, W.adj_b,
+                                        v);
+      }
+      const bool later = sink.template add<kMesh>(S, v, 1.0f);
+      scatter_wave<kMesh>(S, G(sl.grad), v, 1.0f, later);
+    }
+  }
+  sink.flush_acc(S);
+  count_work(work, active ? 1 : 0, n_vert);
+}
+
 // Dynamic LDS: with kMesh, `stack` traversal-stack entries per lane first
 // (the LDS part of the stack), then the gradient table / exchange buffer.
-template <int TW, int TH, bool kMesh>
+// kShared: the launch's pair slices are shared-path pairs (no replay pairs).
+template <int TW, int TH, bool kMesh, bool kShared>
 __global__ void __launch_bounds__(TW * TH) __attribute__((amdgpu_waves_per_eu(3)))
 k_adjoint(const RepArgs* __restrict__ Units, int n_units, int stack, unsigned long long* work) {
   using SH = Shape<TW, TH>;
@@ -752,8 +897,12 @@ k_adjoint(const RepArgs* __restrict__ Units, int n_units, int stack, unsigned lo
   const uint32_t iter = iteration_of(A.key);
   if (A.h.max_iter && iter >= A.h.max_iter) return;  // finished problem
   const TravStack st{s_dyn + threadIdx.x, SH::N, stack};
-  adjoint_tile<SH, kMesh>(A, G(A.scene), iter, s_dyn + (kMesh ? stack * SH::N : 0), s_cnt, st,
-                          work);
+  const TileBlock tb = tile_block<SH>(A);
+  uint32_t* lds = s_dyn + (kMesh ? stack * SH::N : 0);
+  if (kShared && G(A.sl[tb.slice].params_b) != nullptr)  // uniform over the block
+    adjoint_tile_shared<SH, kMesh>(A, G(A.scene), tb, iter, lds, s_cnt, st, work);
+  else
+    adjoint_tile<SH, kMesh, !kShared>(A, G(A.scene), tb, iter, lds, s_cnt, st, work);
 }
 
 // ---------------------------------------------------------------------------
@@ -1045,26 +1194,34 @@ hipError_t launch_philox(const uint32_t* ctr, size_t n, uint64_t key, uint32_t* 
 // needs `stack` entries (the rest spill to private memory).
 static int lds_stack(int stack) { return stack < kLdsStack ? stack : kLdsStack; }
 
-template <int TW, int TH>
+template <int TW, int TH, bool kShared>
 static void fwd_launch(const FwdArgs* U, int n, uint32_t blocks, int stack,
                        unsigned long long* work, hipStream_t st) {
   const int cap = lds_stack(stack);
   const size_t lds = (size_t)cap * TW * TH * 4;
   if (stack > 0)
-    hipLaunchKernelGGL((k_forward<TW, TH, true>), dim3(blocks), dim3(TW * TH), lds, st, U, n, cap,
-                       work);
+    hipLaunchKernelGGL((k_forward<TW, TH, true, kShared>), dim3(blocks), dim3(TW * TH), lds, st,
+                       U, n, cap, work);
   else
-    hipLaunchKernelGGL((k_forward<TW, TH, false>), dim3(blocks), dim3(TW * TH), 0, st, U, n, 0,
-                       work);
+    hipLaunchKernelGGL((k_forward<TW, TH, false, kShared>), dim3(blocks), dim3(TW * TH), 0, st,
+                       U, n, 0, work);
+}
+template <int TW, int TH>
+static void fwd_launch(const FwdArgs* U, int n, uint32_t blocks, int stack, bool shared,
+                       unsigned long long* work, hipStream_t st) {
+  if (shared)
+    fwd_launch<TW, TH, true>(U, n, blocks, stack, work, st);
+  else
+    fwd_launch<TW, TH, false>(U, n, blocks, stack, work, st);
 }
 hipError_t launch_forward(const FwdArgs* U, int n, uint32_t blocks, int shape, int stack,
-                          unsigned long long* work, hipStream_t st) {
+                          bool shared, unsigned long long* work, hipStream_t st) {
   if (n <= 0 || blocks == 0) return hipSuccess;
   if (stack < 0 || stack > kBvhMaxStack) return hipErrorInvalidValue;
   switch (shape) {
-    case 0: fwd_launch<16, 16>(U, n, blocks, stack, work, st); break;
-    case 1: fwd_launch<16, 8>(U, n, blocks, stack, work, st); break;
-    case 2: fwd_launch<8, 8>(U, n, blocks, stack, work, st); break;
+    case 0: fwd_launch<16, 16>(U, n, blocks, stack, shared, work, st); break;
+    case 1: fwd_launch<16, 8>(U, n, blocks, stack, shared, work, st); break;
+    case 2: fwd_launch<8, 8>(U, n, blocks, stack, shared, work, st); break;
     default: return hipErrorInvalidValue;
   }
   return hipGetLastError();
@@ -1082,27 +1239,35 @@ size_t adjoint_lds_bytes(int n_ch) {
   return table > xchg ? table : xchg;
 }
 
-template <int TW, int TH>
+template <int TW, int TH, bool kShared>
 static void adj_launch(const RepArgs* U, int n, uint32_t blocks, size_t lds, int stack,
                        unsigned long long* work, hipStream_t st) {
   const int cap = lds_stack(stack);
   if (stack > 0)
-    hipLaunchKernelGGL((k_adjoint<TW, TH, true>), dim3(blocks), dim3(TW * TH),
+    hipLaunchKernelGGL((k_adjoint<TW, TH, true, kShared>), dim3(blocks), dim3(TW * TH),
                        lds + (size_t)cap * TW * TH * 4, st, U, n, cap, work);
   else
-    hipLaunchKernelGGL((k_adjoint<TW, TH, false>), dim3(blocks), dim3(TW * TH), lds, st, U, n, 0,
-                       work);
+    hipLaunchKernelGGL((k_adjoint<TW, TH, false, kShared>), dim3(blocks), dim3(TW * TH), lds, st,
+                       U, n, 0, work);
+}
+template <int TW, int TH>
+static void adj_launch(const RepArgs* U, int n, uint32_t blocks, size_t lds, int stack,
+                       bool shared, unsigned long long* work, hipStream_t st) {
+  if (shared)
+    adj_launch<TW, TH, true>(U, n, blocks, lds, stack, work, st);
+  else
+    adj_launch<TW, TH, false>(U, n, blocks, lds, stack, work, st);
 }
 
 hipError_t launch_adjoint(const RepArgs* U, int n, uint32_t blocks, int shape, size_t lds,
-                          int stack, unsigned long long* work, hipStream_t st) {
+                          int stack, bool shared, unsigned long long* work, hipStream_t st) {
   if (n <= 0 || blocks == 0) return hipSuccess;
   if (lds < adjoint_lds_bytes(0) || lds > adjoint_lds_bytes(5)) return hipErrorInvalidValue;
   if (stack < 0 || stack > kBvhMaxStack) return hipErrorInvalidValue;
   switch (shape) {
-    case 0: adj_launch<16, 16>(U, n, blocks, lds, stack, work, st); break;
-    case 1: adj_launch<16, 8>(U, n, blocks, lds, stack, work, st); break;
-    case 2: adj_launch<8, 8>(U, n, blocks, lds, stack, work, st); break;
+    case 0: adj_launch<16, 16>(U, n, blocks, lds, stack, shared, work, st); break;
+    case 1: adj_launch<16, 8>(U, n, blocks, lds, stack, shared, work, st); break;
+    case 2: adj_launch<8, 8>(U, n, blocks, lds, stack, shared, work, st); break;
     default: return hipErrorInvalidValue;
   }
   return hipGetLastError();

@@ -123,11 +123,11 @@ class Problem:
     def estimate_gradients(self, seed: int, iteration: int, spp_prop: int = 2, spp_fd: int = 1,
                            flags: int = 0, crop=None, mask: Optional[torch.Tensor] = None,
                            with_fd: bool = True, want_img: bool = False,
-                           loss: int = L.JSO_LOSS_L2):
+                           loss: int = L.JSO_LOSS_L2, fd_mode: int = L.JSO_FD_REPLAY):
         F = torch.zeros(self.n_params, device=self.dev)
         dF = torch.zeros(self.n_params, device=self.dev) if with_fd else None
         img = torch.zeros(self.height, self.width, 3, device=self.dev) if want_img else None
-        o = L.render_opts(flags, crop, _dptr(mask), loss)
+        o = L.render_opts(flags, crop, _dptr(mask), loss, fd_mode)
         rc, loss = L.jso_estimate_gradients(self.ctx, self.sid, seed, iteration, spp_prop,
                                             spp_fd, o, F.data_ptr(), _dptr(dF), _dptr(img),
                                             want_loss=True)

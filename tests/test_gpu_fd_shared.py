@@ -1,0 +1,249 @@
+"""GPU parity of the shared-path finite-difference sample (Eq. 5 as written:
+one path drawn at pi_i, its integrand evaluated at pi_i and pi_{i-1} over the
+density of pi_i) against the oracle, element by element, with the tolerances
+of the other parity tests; its bitwise zero for equal parameters; its
+agreement with the replay pair where sampling does not depend on the
+parameters; whole iterations against the oracle loop; and the batched launch."""
+import sys
+
+import numpy as np
+import pytest
+
+import oracle as O
+from oracle import meta as OM
+from paper_2309_15676_amd import inputs as I
+from test_gpu_parity import TAU, _case, _check_grad, _set_pair
+from test_gpu_mesh import _mesh_texture, _mesh_vertex
+
+pytestmark = pytest.mark.gpu
+
+
+def _say(*a):
+    print("[case]", *a, flush=True)
+    sys.stdout.flush()
+
+
+@pytest.fixture(scope="module")
+def ctx():
+    torch = pytest.importorskip("torch")
+    if not torch.cuda.is_available():
+        pytest.skip("no GPU")
+    from paper_2309_15676_amd.problem import Context
+    c = Context(0)
+    yield c
+    c.close()
+
+
+def _problem(ctx, spec):
+    from paper_2309_15676_amd.problem import Problem
+    return Problem(spec, context=ctx)
+
+
+def _spec(name):
+    if name == "mesh_vertex":
+        spec, p, _ = _mesh_vertex()
+        return spec, p
+    if name == "mesh_texture":
+        spec, p, _ = _mesh_texture()
+        return spec, p
+    return _case(name)
+
+
+def _oracle_shared(spec, p, p_prev, T, seed, it, flags=0, mask=None):
+    pd, pp, Td = p.astype(np.float64), p_prev.astype(np.float64), T.astype(np.float64)
+    return O.rounding_sensitivity(
+        spec, lambda: O.gradient_pair(spec, pd, pp, Td, seed, it, flags=flags, mask=mask,
+                                      fd_shared=True))
+
+
+def _mask_shared(spec, p, p_prev, T, seed, it, flags=0, max_frac=0.03):
+    r0, f0 = _oracle_shared(spec, p, p_prev, T, seed, it, flags)
+    bad = (r0["margin"] <= TAU) | O.ill_conditioned(r0, f0)
+    frac = bad.mean()
+    print("masked: %.3f%% of pixels" % (100 * frac))
+    assert frac <= max_frac, frac
+    return bad.astype(np.uint8)
+
+
+def _pair(spec, p):
+    g = np.random.Generator(np.random.PCG64(8))
+    # a larger step than the replay-pair tests: roughness changes move the
+    # GGX lobe, which the shared path (pi_i's density) has to carry
+    return np.clip(p + g.normal(0, 0.05, p.shape).astype(np.float32), 0.06, 0.99)
+
+
+@pytest.mark.parametrize("name,flags", [("tiny", 0), ("textured", 0), ("ragged", 0),
+                                        ("textured", O.PARAM_INDEP), ("tiny", O.NO_NEE),
+                                        ("mesh_vertex", 0), ("mesh_texture", 0)])
+def test_shared_fd_parity(ctx, name, flags):
+    import torch
+    from paper_2309_15676_amd import _lib as L
+    _say("shared fd", name, flags)
+    spec, p = _spec(name)
+    p_prev = _pair(spec, p)
+    T = I.target_image_synthetic(spec, 5)
+    seed, it = 33, 6
+    mask = _mask_shared(spec, p, p_prev, T, seed, it, flags,
+                        max_frac=0.06 if name.startswith("mesh") else 0.03)
+    prob = _problem(ctx, spec)
+    prob.set_target(T)
+    _set_pair(prob, p, p_prev, it)
+    r = prob.estimate_gradients(seed, it, 2, 1, flags=flags,
+                                mask=torch.from_numpy(mask.reshape(-1)).to("cuda"),
+                                fd_mode=L.JSO_FD_SHARED)
+    ref, floor = _oracle_shared(spec, p, p_prev, T, seed, it, flags, mask)
+    _check_grad(r["F"].cpu().numpy().astype(np.float64), ref["F"], ref["F_abs"], floor["F"], "F",
+                spec)
+    _check_grad(r["dF"].cpu().numpy().astype(np.float64), ref["dF"], ref["dF_abs"], floor["dF"],
+                "dF", spec)
+    assert np.count_nonzero(ref["dF"]) > 0
+    # and it is not the replay pair's sample (which the oracle also gives)
+    if not flags & O.PARAM_INDEP:
+        rep = O.gradient_pair(spec, p.astype(np.float64), p_prev.astype(np.float64),
+                              T.astype(np.float64), seed, it, flags=flags, mask=mask)
+        assert np.max(np.abs(rep["dF"] - ref["dF"])) > 1e-3 * np.max(np.abs(ref["dF"]))
+
+
+@pytest.mark.parametrize("name", ["tiny", "textured", "mesh_vertex"])
+def test_shared_fd_bitwise_zero_for_equal_params(ctx, name):
+    from paper_2309_15676_amd import _lib as L
+    _say("shared fd zero", name)
+    spec, p = _spec(name)
+    prob = _problem(ctx, spec)
+    prob.set_target(I.target_image_synthetic(spec, 1))
+    _set_pair(prob, p, p, 9)
+    r = prob.estimate_gradients(seed=4, iteration=9, fd_mode=L.JSO_FD_SHARED)
+    assert np.all(r["dF"].cpu().numpy() == 0.0)
+    assert np.count_nonzero(r["F"].cpu().numpy()) > 0
+
+
+@pytest.mark.parametrize("name", ["textured", "mesh_texture"])
+def test_shared_equals_replay_when_sampling_is_parameter_independent(ctx, name):
+    # the two forms then trace the same paths with the same densities: equal
+    # up to the order of the FP32 sums (the replay pair differences two
+    # finished vertex gradients, the shared path two running ones; and the
+    # launches differ, so the atomics of <F_i> land in another order too)
+    from paper_2309_15676_amd import _lib as L
+    _say("shared vs replay", name)
+    spec, p = _spec(name)
+    p_prev = _pair(spec, p)
+    prob = _problem(ctx, spec)
+    prob.set_target(I.target_image_synthetic(spec, 5))
+    _set_pair(prob, p, p_prev, 6)
+    flags = O.PARAM_INDEP
+    a = prob.estimate_gradients(33, 6, 2, 1, flags=flags, fd_mode=L.JSO_FD_SHARED)
+    b = prob.estimate_gradients(33, 6, 2, 1, flags=flags, fd_mode=L.JSO_FD_REPLAY)
+    ref = O.gradient_pair(spec, p.astype(np.float64), p_prev.astype(np.float64),
+                          I.target_image_synthetic(spec, 5).astype(np.float64), 33, 6,
+                          flags=flags, fd_shared=True)
+    fa, fb = a["F"].cpu().numpy().astype(np.float64), b["F"].cpu().numpy().astype(np.float64)
+    assert np.all(np.abs(fa - fb) <= 1e-5 * ref["F_abs"] + 1e-12), np.max(np.abs(fa - fb))
+    da, db = a["dF"].cpu().numpy().astype(np.float64), b["dF"].cpu().numpy().astype(np.float64)
+    assert np.count_nonzero(db) > 0
+    assert np.all(np.abs(da - db) <= 1e-5 * ref["dF_abs"] + 1e-12), np.max(np.abs(da - db))
+
+
+@pytest.mark.parametrize("ablate", [0, 4])
+def test_shared_grad_step_matches_oracle_loop(ctx, ablate):
+    """Whole iterations with the shared-path finite-difference sample (and,
+    with ablate = 4, its uncorrelated variance samples) against the oracle
+    loop, which takes each gradient at the GPU's parameters."""
+    from paper_2309_15676_amd import _lib as L
+    _say("shared grad_step loop", ablate)
+    spec, gt, init = I.config_tiny()
+    spec.width = spec.height = 16
+    T = I.target_image_synthetic(spec, 2)
+    Td = T.astype(np.float64)
+    lo, hi = spec.param_bounds()
+    f32 = lambda v: float(np.float32(v))  # noqa: E731  (ABI values are float32)
+    eta = f32(0.01)
+    n_it = 3
+
+    def samples(ref, s, i):
+        p, pp = ref.params.astype(np.float64), ref.params_prev.astype(np.float64)
+        r = O.gradient_pair(spec, p, pp, Td, s, i, fd_shared=True)
+        out = dict(F=r["F"], dF=r["dF"], F_var=None, dF_var=None)
+        m = r["margin"].min()
+        if ablate:
+            fv, _, _, m1, _ = O.grad(spec, p, Td, s, i, L.JSO_TAG_VAR_PRIMAL_PROP,
+                                     L.JSO_TAG_VAR_ADJ_PROP, 2)
+            dv = np.zeros_like(fv)
+            m = min(m, m1.min())
+            if i >= 1:
+                g1, _, _, ma, _ = O.grad(spec, p, Td, s, i, L.JSO_TAG_VAR_PRIMAL_FD,
+                                         L.JSO_TAG_VAR_ADJ_FD, 1)
+                g0, _, _, mb, _ = O.grad(spec, pp, Td, s, i, L.JSO_TAG_VAR_PRIMAL_FD,
+                                         L.JSO_TAG_VAR_ADJ_FD, 1, sample_params=p)
+                dv = g1 - g0
+                m = min(m, ma.min(), mb.min())
+            out.update(F_var=fv, dF_var=dv)
+        return out, m, r
+
+    def make_ref():
+        return OM.MetaOptimizer(init, lo, hi, eta, f32(0.99), f32(0.9))
+
+    seed = None
+    for s in range(100, 400):
+        ref = make_ref()
+        ok = True
+        for i in range(n_it):
+            smp, m, _ = samples(ref, s, i)
+            if m <= 2 * TAU:
+                ok = False
+                break
+            ref.step(smp["F"], smp["dF"], smp["F_var"], smp["dF_var"])
+        if ok:
+            seed = s
+            break
+    assert seed is not None
+    prob = _problem(ctx, spec)
+    prob.set_target(T)
+    prob.set_params(init)
+    opts = L.step_opts(eta=eta, seed=seed, ablate=ablate, fd_mode=L.JSO_FD_SHARED)
+    ref = make_ref()
+    for i in range(n_it):
+        p_cur, p_prev = prob.get_params(), prob.get_params_prev()
+        st = prob.grad_step(opts, want_stats=True)
+        ref.params, ref.params_prev = p_cur.copy(), p_prev.copy()
+        smp, m, r = samples(ref, seed, i)
+        assert m > TAU
+        ref.step(smp["F"], smp["dF"], smp["F_var"], smp["dF_var"])
+        np.testing.assert_allclose(prob.get_params(), ref.params, rtol=0,
+                                   atol=2e-4 * eta + 1e-7, err_msg="iteration %d" % i)
+        np.testing.assert_allclose(st.loss, np.mean((r["I"] - Td) ** 2), rtol=2e-4)
+
+
+def test_shared_batch_matches_grad_step(ctx):
+    from paper_2309_15676_amd import _lib as L
+    from paper_2309_15676_amd.problem import Batch, grad_step_many
+    from test_gpu_batch import _close_states, _make
+    _say("shared batch")
+    opts = L.step_opts(optimizer=L.JSO_OPT_META, eta=0.02, seed=5, fd_mode=L.JSO_FD_SHARED)
+    batched, ref = _make(ctx), _make(ctx)
+    b = Batch(batched, opts, max_iters=[0, 0, 0], use_graph=True)
+    for it in range(3):
+        b.step(1)
+        grad_step_many(ref, opts)
+        for k, p in enumerate(batched):
+            _close_states(p.get_state(), ref[k].get_state(), "problem %d after %d" % (k, it + 1))
+    b.close()
+    # the replay form takes different steps from the first finite-difference sample on
+    rep = _make(ctx)
+    grad_step_many(rep, L.step_opts(optimizer=L.JSO_OPT_META, eta=0.02, seed=5))
+    grad_step_many(rep, L.step_opts(optimizer=L.JSO_OPT_META, eta=0.02, seed=5))
+    sh = _make(ctx)
+    grad_step_many(sh, opts)
+    grad_step_many(sh, opts)
+    assert any(np.any(a.get_params() != c.get_params()) for a, c in zip(rep, sh))
+
+
+def test_fd_mode_is_validated(ctx):
+    from paper_2309_15676_amd import _lib as L
+    _say("fd_mode validation")
+    spec, p = _case("tiny")
+    prob = _problem(ctx, spec)
+    prob.set_target(I.target_image_synthetic(spec, 1))
+    with pytest.raises(RuntimeError, match="fd_mode"):
+        prob.estimate_gradients(seed=1, iteration=1, fd_mode=7)
+    with pytest.raises(RuntimeError, match="fd_mode"):
+        prob.grad_step(L.step_opts(fd_mode=-1))
