@@ -185,14 +185,26 @@ def time_to_loss(prob, init, gt, target, args, iters: int, label: str, lam: floa
     m_eta = min(meta, key=lambda e: min(h[2] for h in meta[e]))
     hm = meta[m_eta]
     it_meta, t_meta = first(hm, target_loss)
+    # the same with the shared-path finite-difference sample (Eq. 5 as written)
+    shared = {}
+    for eta in grid:
+        o = L.step_opts(optimizer=L.JSO_OPT_META, eta=eta, beta_F=0.99, beta_D=0.9, spp_prop=2,
+                        spp_fd=1, seed=args.seed + 2, precond_lambda=lam,
+                        fd_mode=L.JSO_FD_SHARED)
+        shared[eta] = run(o, 10 ** 9, every * 4, seconds=budget_s)
+    s_eta = min(shared, key=lambda e: min(h[2] for h in shared[e]))
+    hs = shared[s_eta]
+    it_sh, t_sh = first(hs, target_loss)
     levels = {}
     for frac in (8, 4, 2):
         lv = next(h[2] for h in ha if h[0] >= iters // frac)
         ia, ta = first(ha, lv)
         im, tm = first(hm, lv)
+        i2, t2 = first(hs, lv)
         levels["adam_iters_%d" % (iters // frac)] = {
             "loss": lv, "adam_seconds": ta, "meta_seconds": tm, "meta_iterations": im,
-            "speedup": (ta / tm) if tm else None}
+            "speedup": (ta / tm) if tm else None,
+            "meta_fd_shared_seconds": t2, "speedup_fd_shared": (ta / t2) if t2 else None}
     return {
         "workload": label,
         "evaluation": "L2 of a %d-spp render (fixed evaluation stream) against the target, "
@@ -207,6 +219,11 @@ def time_to_loss(prob, init, gt, target, args, iters: int, label: str, lam: floa
                  "best_loss_by_eta": {str(e): min(h[2] for h in meta[e]) for e in grid},
                  "seconds_budget": budget_s},
         "speedup": (t_adam / t_meta) if t_meta else None,
+        "meta_fd_shared": {
+            "spp": "2 prop + 1 FD (shared path)", "eta": s_eta, "iterations": it_sh,
+            "seconds": t_sh, "best_loss": min(h[2] for h in hs), "iterations_run": hs[-1][0],
+            "best_loss_by_eta": {str(e): min(h[2] for h in shared[e]) for e in grid},
+            "speedup": (t_adam / t_sh) if t_sh else None},
         "speedup_by_level": levels,
         "precond_lambda": lam,
     }
@@ -445,6 +462,10 @@ def mesh_workloads(context, args):
                            args.mesh_steps)
     opts = L.step_opts(optimizer=L.JSO_OPT_META, eta=0.01, seed=args.seed)
     ms_step, kt_step = timed(lambda: prob.grad_step(opts), args.mesh_steps)
+    opts_sh = L.step_opts(optimizer=L.JSO_OPT_META, eta=0.01, seed=args.seed,
+                          fd_mode=L.JSO_FD_SHARED)
+    prob.set_params(init)
+    ms_sh, kt_sh = timed(lambda: prob.grad_step(opts_sh), args.mesh_steps)
     out["sphere_200k"] = {
         "workload": "1024x1024, displaced geodesic sphere of 200,000 triangles on a grey "
                     "plane, per-vertex RGB + roughness (400,008 params), depth 8, roulette "
@@ -454,6 +475,7 @@ def mesh_workloads(context, args):
                          "kernel_ms": kt_bwd},
         "meta_step": {"ms": ms_step, "diff_paths_per_s": 4 * npix / (ms_step / 1e3),
                       "kernel_ms": kt_step},
+        "meta_step_fd_shared": {"ms": ms_sh, "kernel_ms": kt_sh},
     }
     print("[bench] mesh sphere: %s" % json.dumps(out["sphere_200k"]), file=sys.stderr, flush=True)
     del prob
@@ -467,6 +489,8 @@ def mesh_workloads(context, args):
     prob.set_params(init)
     npix = spec.n_pixels
     ms_step, kt_step = timed(lambda: prob.grad_step(opts), max(2, args.mesh_steps // 2))
+    prob.set_params(init)
+    ms_sh, kt_sh = timed(lambda: prob.grad_step(opts_sh), max(2, args.mesh_steps // 2))
     out["terrain_1m"] = {
         "workload": "2048x2048, fractal terrain of 999,698 triangles + 32 spheres, 512x512 "
                     "texture of RGB + metalness + roughness (1,310,720 params), depth 12, "
@@ -474,6 +498,7 @@ def mesh_workloads(context, args):
         "scene_load_s": load_s,
         "meta_step": {"ms": ms_step, "diff_paths_per_s": 4 * npix / (ms_step / 1e3),
                       "kernel_ms": kt_step},
+        "meta_step_fd_shared": {"ms": ms_sh, "kernel_ms": kt_sh},
     }
     print("[bench] terrain: %s" % json.dumps(out["terrain_1m"]), file=sys.stderr, flush=True)
     del prob
@@ -567,6 +592,32 @@ def main():
     print("[bench] kernel ms per step: %s; loss %.5g; %.4f vertices per path" % (
         {k: round(v[0] / max(v[1], 1), 4) for k, v in ktimes.items()}, st.loss, vpp),
         file=sys.stderr, flush=True)
+    # the same step with the shared-path finite-difference sample (Eq. 5 as
+    # written: one finite-difference path per pixel instead of two), reported
+    # beside the headline figure
+    opts_sh = L.step_opts(optimizer=L.JSO_OPT_META, eta=0.01, beta_F=0.99, beta_D=0.9,
+                          spp_prop=2, spp_fd=1, seed=args.seed, fd_mode=L.JSO_FD_SHARED)
+    prob.set_params(init)
+    for _ in range(args.warmup):
+        prob.grad_step(opts_sh)
+    L.check(L.jso_set_timing(ctx, True), ctx)
+    for k in range(L.JSO_K_COUNT):
+        L.jso_get_kernel_time(ctx, k, reset=True)
+    torch.cuda.synchronize()
+    e0.record()
+    for _ in range(args.steps):
+        prob.grad_step(opts_sh)
+    e1.record()
+    torch.cuda.synchronize()
+    fd_shared = {"ms_per_step": e0.elapsed_time(e1) / args.steps,
+                 "kernel_ms_per_step": {name: (lambda v: v[0] / max(v[1], 1))(
+                     L.jso_get_kernel_time(ctx, k)) for k, name in
+                     ((L.JSO_K_FORWARD, "forward"), (L.JSO_K_FINALIZE, "finalize"),
+                      (L.JSO_K_ADJOINT, "adjoint"), (L.JSO_K_META, "meta"))},
+                 "paths_traced_per_step": 3 * spec.n_pixels}
+    L.check(L.jso_set_timing(ctx, False), ctx)
+    prob.set_params(init)
+    print("[bench] shared-path FD step: %s" % json.dumps(fd_shared), file=sys.stderr, flush=True)
     if args.copy_mib > 0:
         copy_calibration(args.copy_mib)
 
@@ -668,6 +719,7 @@ def main():
                      "vertices_per_path": k_vpp},
         "vertices_per_s": value * vpp,
         "kernel_ms_per_step": {k: v[0] / max(v[1], 1) for k, v in ktimes.items()},
+        "fd_shared_step": fd_shared,
         "cpu_baseline": cpu,
         "time_to_loss": ttl,
         "batched": bat,
