@@ -68,6 +68,8 @@ class _Scene(ctypes.Structure):
         ("n_verts", ctypes.c_int), ("n_tris", ctypes.c_int),
         ("verts", ctypes.POINTER(ctypes.c_double)), ("tris", ctypes.POINTER(ctypes.c_int)),
         ("mesh_mat", ctypes.c_int), ("param_layout", ctypes.c_int),
+        ("vol_res", ctypes.c_int), ("vol_views", ctypes.c_int),
+        ("vol_box", ctypes.c_double * 4), ("vol_sigma", ctypes.c_double),
     ]
 
 
@@ -154,6 +156,10 @@ class _Marshalled:
         s.tris = self.tris.ctypes.data_as(ctypes.POINTER(ctypes.c_int))
         s.mesh_mat = int(spec.mesh_mat)
         s.param_layout = int(getattr(spec, "param_layout", 0))
+        s.vol_res = int(getattr(spec, "vol_res", 0))
+        s.vol_views = int(getattr(spec, "vol_views", 1))
+        s.vol_box[:] = _f32(getattr(spec, "vol_box", (0.0, 0.0, 0.0, 1.0)))
+        s.vol_sigma = float(_f32(getattr(spec, "vol_sigma", 0.0)))
         self.s = s
 
     def ptr(self):

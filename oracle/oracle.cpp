@@ -124,6 +124,7 @@ struct Scene {
   double tan_half, aspect;
   int n_ch;
   int ch_slot[5];  // slot of channel bit b in a texel, -1 if not a parameter
+  int view_h;      // rows per view (volume scenes stack several views)
 
   explicit Scene(const orc_scene* sc) : s(sc) {
     eye = from(sc->cam_eye);
@@ -131,12 +132,30 @@ struct Scene {
     cu = normalize(cross(cw, from(sc->cam_up)));
     cv = cross(cu, cw);
     tan_half = std::tan(sc->vfov_deg * PI / 360.0);
-    aspect = (double)sc->width / (double)sc->height;
+    view_h = volume() ? sc->height / sc->vol_views : sc->height;
+    aspect = (double)sc->width / (double)view_h;
     n_ch = 0;
     for (int b = 0; b < 5; ++b) ch_slot[b] = (sc->ch_mask >> b & 1) ? n_ch++ : -1;
   }
 
+  bool volume() const { return s->param_layout == 2; }
+
   Ray camera_ray(int x, int y, double jx, double jy) const {
+    if (volume()) {
+      // view v: the eye turned by 2 pi v / V about the vertical line through
+      // the target
+      const int v = y / view_h;
+      const double ang = 2.0 * PI * v / s->vol_views;
+      const V3 tg = from(s->cam_target), r = eye - tg;
+      const V3 e{tg.x + r.x * std::cos(ang) + r.z * std::sin(ang), eye.y,
+                 tg.z - r.x * std::sin(ang) + r.z * std::cos(ang)};
+      const V3 w = normalize(tg - e);
+      const V3 u = normalize(cross(w, from(s->cam_up)));
+      const V3 vv = cross(u, w);
+      double sx = (2.0 * (x + jx) / s->width - 1.0) * tan_half * aspect;
+      double sy = (1.0 - 2.0 * (y - v * view_h + jy) / view_h) * tan_half;
+      return {e, normalize(w + u * sx + vv * sy)};
+    }
     double sx = (2.0 * (x + jx) / s->width - 1.0) * tan_half * aspect;
     double sy = (1.0 - 2.0 * (y + jy) / s->height) * tan_half;
     return {eye, normalize(cw + cu * sx + cv * sy)};
@@ -585,10 +604,22 @@ struct TapeVertex {
   double E[3] = {0, 0, 0};  // emission picked up by the continuation, per unit beta_j
 };
 
+// One sample of an emission-absorption ray march (volume scenes).
+struct VolSample {
+  double T;        // transmittance before the sample
+  double alpha;    // 1 - exp(-sigma dt)
+  double e[3];     // emission
+  double sigma;    // density per unit length (vol_sigma x the density parameter)
+  double dt;       // segment length
+  size_t vox[8];   // trilinear corners (voxel indices) and weights
+  double w[8];
+};
+
 struct PathResult {
   double L[3] = {0, 0, 0};
   double margin = INF;
   std::vector<TapeVertex> tape;
+  std::vector<VolSample> vtape;  // volume scenes
 };
 
 // Test hook: a fixed offset (in pixels) added to every primary sample
@@ -601,6 +632,125 @@ double g_jitter_dx = 0.0, g_jitter_dy = 0.0;
 // parameterised material.
 std::atomic<uint64_t> g_paths{0}, g_vertices{0}, g_param_vertices{0};
 
+// Emission-absorption volume (the volume experiment of the Experiments
+// section): the camera ray's chord through the cube is split into
+// N = ceil(chord / voxel) equal segments of length dt, sampled at
+// t0 + (k + u) dt with one jitter u per ray (0.5 under ORC_PIXEL_CENTER);
+// each sample reads the trilinearly interpolated voxel values (centres at
+// (i + 0.5) / R of the cube, clamp-to-edge) and the radiance is the
+// quadrature sum_k T_k alpha_k e_k + T_N env, alpha_k = 1 - exp(-sigma_k dt),
+// T_{k+1} = T_k (1 - alpha_k).  Margins: the hit/miss of the cube, the
+// rounding of chord / voxel to N, and each sample's cell (which corner gets
+// a vanishing weight), as for textures.
+void trace_volume(const Scene& sc, const double* params, const PathRng& rng, int px, int py,
+                  int flags, bool record, PathResult& out) {
+  const orc_scene* s = sc.s;
+  Margin mg;
+  double u[4];
+  g_paths.fetch_add(1, std::memory_order_relaxed);
+  rng.draw(0, 0, u);
+  const bool center = (flags & ORC_PIXEL_CENTER) != 0;
+  const double jx = center ? 0.5 : u[0], jy = center ? 0.5 : u[1], us = center ? 0.5 : u[2];
+  const Ray ray = sc.camera_ray(px, py, jx + g_jitter_dx, jy + g_jitter_dy);
+  const double R = s->vol_res, side = s->vol_box[3];
+  // slab test against the cube
+  double t0 = 0.0, t1 = INF;
+  const double o[3] = {ray.o.x, ray.o.y, ray.o.z}, d[3] = {ray.d.x, ray.d.y, ray.d.z};
+  for (int a = 0; a < 3; ++a) {
+    const double lo = s->vol_box[a], hi = s->vol_box[a] + side;
+    if (d[a] == 0.0) {
+      if (o[a] < lo || o[a] > hi) t1 = -INF;
+      continue;
+    }
+    double ta = (lo - o[a]) / d[a], tb = (hi - o[a]) / d[a];
+    if (ta > tb) std::swap(ta, tb);
+    t0 = std::max(t0, ta);
+    t1 = std::min(t1, tb);
+  }
+  double* L = out.L;
+  const double vox = side / R;
+  mg.add((t1 - t0) / vox);  // grazing the cube: hit or miss
+  if (!(t1 > t0)) {
+    for (int k = 0; k < 3; ++k) L[k] = s->env[k];
+    out.margin = mg.m;
+    return;
+  }
+  const double q = (t1 - t0) / vox;
+  const int N = std::max(1, (int)std::ceil(q));
+  mg.add((q - std::floor(q)) / std::max(q, 1.0));
+  mg.add((std::ceil(q) - q) / std::max(q, 1.0));
+  const double dt = (t1 - t0) / N;
+  double T = 1.0;
+  for (int k = 0; k < N; ++k) {
+    const double t = t0 + (k + us) * dt;
+    const double x[3] = {o[0] + t * d[0], o[1] + t * d[1], o[2] + t * d[2]};
+    int i0[3], i1[3];
+    double f[3];
+    for (int a = 0; a < 3; ++a) {
+      const double g = (x[a] - s->vol_box[a]) / vox - 0.5;
+      const double fl = std::floor(g);
+      mg.add(g - std::round(g));
+      f[a] = g - fl;
+      i0[a] = (int)std::min(std::max(fl, 0.0), R - 1);
+      i1[a] = (int)std::min(std::max(fl + 1.0, 0.0), R - 1);
+    }
+    VolSample vs;
+    double val[4] = {0, 0, 0, 0};
+    for (int c = 0; c < 8; ++c) {
+      const int ix = (c & 1) ? i1[0] : i0[0], iy = (c & 2) ? i1[1] : i0[1],
+                iz = (c & 4) ? i1[2] : i0[2];
+      const double w = ((c & 1) ? f[0] : 1 - f[0]) * ((c & 2) ? f[1] : 1 - f[1]) *
+                       ((c & 4) ? f[2] : 1 - f[2]);
+      vs.vox[c] = ((size_t)iz * s->vol_res + iy) * s->vol_res + ix;
+      vs.w[c] = w;
+      for (int ch = 0; ch < 4; ++ch) val[ch] += w * params[4 * vs.vox[c] + ch];
+    }
+    vs.T = T;
+    vs.sigma = s->vol_sigma * val[3];
+    vs.dt = dt;
+    vs.alpha = 1.0 - std::exp(-vs.sigma * dt);
+    for (int ch = 0; ch < 3; ++ch) {
+      vs.e[ch] = val[ch];
+      L[ch] += T * vs.alpha * val[ch];
+    }
+    T *= std::exp(-vs.sigma * dt);
+    if (record) out.vtape.push_back(vs);
+  }
+  g_vertices.fetch_add((uint64_t)N, std::memory_order_relaxed);
+  g_param_vertices.fetch_add((uint64_t)N, std::memory_order_relaxed);
+  for (int k = 0; k < 3; ++k) L[k] += T * s->env[k];
+  out.margin = mg.m;
+}
+
+// Reverse sweep over a volume tape.  D = radiance behind the sample per unit
+// transmittance in front of it: D_N = env, D_k = alpha_k e_k + (1 - alpha_k) D_{k+1},
+// C = D_0.  Hence dC/de_k = T_k alpha_k and
+// dC/dsigma_k = T_k dt exp(-sigma_k dt) (e_k - D_{k+1}); the density parameter
+// adds the factor vol_sigma, and trilinear weights spread both over 8 voxels.
+void backprop_volume(const Scene& sc, const std::vector<VolSample>& tape, const double adj[3],
+                     double* grad, double* gabs) {
+  double D[3] = {sc.s->env[0], sc.s->env[1], sc.s->env[2]};
+  for (int k = (int)tape.size() - 1; k >= 0; --k) {
+    const VolSample& v = tape[k];
+    double g[4] = {0, 0, 0, 0}, ga[4] = {0, 0, 0, 0};
+    const double et = std::exp(-v.sigma * v.dt);
+    for (int ch = 0; ch < 3; ++ch) {
+      const double ge = adj[ch] * v.T * v.alpha;
+      const double gs = adj[ch] * v.T * v.dt * et * (v.e[ch] - D[ch]) * sc.s->vol_sigma;
+      g[ch] += ge;
+      ga[ch] += std::fabs(ge);
+      g[3] += gs;
+      ga[3] += std::fabs(gs);
+    }
+    for (int c = 0; c < 8; ++c)
+      for (int ch = 0; ch < 4; ++ch) {
+        grad[4 * v.vox[c] + ch] += v.w[c] * g[ch];
+        gabs[4 * v.vox[c] + ch] += v.w[c] * ga[ch];
+      }
+    for (int ch = 0; ch < 3; ++ch) D[ch] = v.alpha * v.e[ch] + (1.0 - v.alpha) * D[ch];
+  }
+}
+
 // sample_params (nullable, else = params): the parameters whose BSDF
 // densities choose the directions.  The path is then drawn at sample_params
 // and weighted by f(x; params) / p(x; sample_params) -- every density (the
@@ -610,6 +760,12 @@ std::atomic<uint64_t> g_paths{0}, g_vertices{0}, g_param_vertices{0};
 // vectors over the density of the current ones.
 void trace(const Scene& sc, const double* params, const double* sample_params,
            const PathRng& rng, int px, int py, int flags, bool record, PathResult& out) {
+  if (sc.volume()) {
+    // the march does not sample anything from the parameters: the path is
+    // the same at every parameter vector
+    trace_volume(sc, params, rng, px, py, flags, record, out);
+    return;
+  }
   const orc_scene* s = sc.s;
   Margin mg;
   double u[4];
@@ -727,6 +883,7 @@ void trace(const Scene& sc, const double* params, const double* sample_params,
 // continuation term: adj beta_{j-1} (cos/(pdf q)) S_j df(w_i)/dtheta
 void backprop(const Scene& sc, const std::vector<TapeVertex>& tape, const double adj[3],
               double* grad, double* gabs) {
+  if (sc.volume()) return;  // volume tapes: backprop_volume
   const int nv = (int)tape.size();
   double T_next[3] = {0, 0, 0};
   for (int j = nv - 1; j >= 0; --j) {
@@ -786,6 +943,7 @@ PathRng make_rng(uint64_t key, uint32_t pixel, uint32_t sample) {
 }
 
 size_t n_params(const Scene& sc) {
+  if (sc.volume()) return 4 * (size_t)sc.s->vol_res * sc.s->vol_res * sc.s->vol_res;
   const size_t elems = sc.s->param_layout == 1 ? (size_t)sc.s->n_verts
                                                : (size_t)sc.s->tex_w * sc.s->tex_h;
   return elems * sc.n_ch;
@@ -820,6 +978,11 @@ int check(const orc_scene* s) {
     if (s->plane_enabled && s->plane_mat < 0) return -1;
     for (int k = 0; k < s->n_spheres; ++k)
       if (s->sphere_mat[k] < 0) return -1;
+  } else if (s->param_layout == 2) {
+    // a volume alone: no surfaces, no light
+    if (s->vol_res < 1 || s->vol_views < 1 || s->height % s->vol_views != 0) return -1;
+    if (!(s->vol_box[3] > 0) || !(s->vol_sigma >= 0) || s->ch_mask != 15) return -1;
+    if (s->plane_enabled || s->n_spheres > 0 || s->n_tris > 0 || s->light_enabled) return -1;
   } else if (s->param_layout != 0) {
     return -1;
   }
@@ -934,7 +1097,10 @@ static int grad_common(const orc_scene* s, const double* params, const double* s
       for (int smp = 0; smp < spp; ++smp) {
         PathResult r;
         trace(sc, params, sample_params, make_rng(key_adj, pix, smp), x, y, flags, true, r);
-        backprop(sc, r.tape, adj, g[t].data(), ga[t].data());
+        if (sc.volume())
+          backprop_volume(sc, r.vtape, adj, g[t].data(), ga[t].data());
+        else
+          backprop(sc, r.tape, adj, g[t].data(), ga[t].data());
         mg = std::min(mg, r.margin);
         for (int k = 0; k < 3; ++k) acc[k] += r.L[k];
       }

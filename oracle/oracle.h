@@ -53,7 +53,16 @@ typedef struct {
   const int* tris;                   /* [n_tris][3] vertex indices             */
   int mesh_mat;                      /* -1 = parameterised, else fixed k       */
   int param_layout;                  /* 0: texture (mesh: planar UV over the plane
-                                        extent); 1: per mesh vertex            */
+                                        extent); 1: per mesh vertex; 2: volume  */
+  /* emission-absorption volume (param_layout 2): vol_res^3 voxels filling the
+   * cube of side vol_box[3] with its low corner at vol_box[0..2]; per voxel
+   * (emission R, G, B, density) in [0, 1], density scaled by vol_sigma per
+   * unit length; ch_mask must be 15.  The image stacks vol_views views of
+   * height / vol_views rows, view v's eye turned by 2 pi v / vol_views about
+   * the vertical axis through cam_target.  No surfaces or lights. */
+  int vol_res, vol_views;
+  double vol_box[4];
+  double vol_sigma;
 } orc_scene;
 
 /* debug / test-mode flags */

@@ -42,7 +42,10 @@ CHANNEL_BOUNDS = {CH_R: (0.0, 1.0), CH_G: (0.0, 1.0), CH_B: (0.0, 1.0),
 
 MAT_PARAM = -1  # object uses the parameterised (textured / global) material
 
-LAYOUT_TEXTURE, LAYOUT_VERTEX = 0, 1
+LAYOUT_TEXTURE, LAYOUT_VERTEX, LAYOUT_VOLUME = 0, 1, 2
+# a volume's four channels per voxel: emission R, G, B and density (the bits of
+# R, G, B and metalness; all in [0, 1])
+CH_VOLUME = CH_R | CH_G | CH_B | CH_M
 
 
 @dataclasses.dataclass
@@ -78,6 +81,15 @@ class SceneSpec:
     tris: np.ndarray = dataclasses.field(default_factory=lambda: np.zeros((0, 3), np.int32))
     mesh_mat: int = MAT_PARAM
     param_layout: int = LAYOUT_TEXTURE
+    # emission-absorption volume (param_layout LAYOUT_VOLUME): vol_res^3 voxels
+    # in the cube of side vol_box[3] from corner vol_box[:3]; density scale
+    # vol_sigma per unit length; the image stacks vol_views views (rows
+    # height / vol_views each), view v's eye turned by 2 pi v / vol_views about
+    # the vertical axis through cam_target
+    vol_res: int = 0
+    vol_views: int = 1
+    vol_box: Tuple[float, float, float, float] = (-1.0, 0.0, -1.0, 2.0)
+    vol_sigma: float = 8.0
 
     @property
     def n_ch(self) -> int:
@@ -85,7 +97,9 @@ class SceneSpec:
 
     @property
     def n_elems(self) -> int:
-        """Texels, or mesh vertices in the per-vertex layout."""
+        """Texels, mesh vertices in the per-vertex layout, or voxels."""
+        if self.param_layout == LAYOUT_VOLUME:
+            return self.vol_res ** 3
         if self.param_layout == LAYOUT_VERTEX:
             return int(np.asarray(self.verts).reshape(-1, 3).shape[0])
         return self.tex_w * self.tex_h
@@ -398,3 +412,59 @@ def config_batched(n: int = 64, seed: int = 0):
             gt, init = fourier_params(s, sub + 1), uniform_params(s, sub + 2, 0.2, 0.8)
         out.append(dict(spec=s, gt=gt, init=init, max_iter=max_iter, seed=sub))
     return out
+
+
+# ----------------------------------------------------------------------------
+# emission-absorption volume (the volume experiment of the paper)
+# ----------------------------------------------------------------------------
+def scene_volume(res: int = 256, views: int = 8, view_w: int = 256, view_h: int = 256,
+                 sigma: float = 8.0) -> SceneSpec:
+    """A res^3 emission-absorption volume in the cube [-1, 1] x [0, 2] x [-1, 1]
+    seen by `views` cameras on a circle around it (eye 4.5 from the axis,
+    slightly above the centre, vFOV 40 degrees); environment radiance 0.2;
+    no surfaces or lights."""
+    return SceneSpec(width=view_w, height=view_h * views, cam_eye=(0.0, 1.9, 4.5),
+                     cam_target=(0.0, 1.0, 0.0), vfov_deg=40.0, plane_enabled=False,
+                     light_enabled=False, env=(0.2, 0.2, 0.2), depth=1, ch_mask=CH_VOLUME,
+                     param_layout=LAYOUT_VOLUME, vol_res=res, vol_views=views,
+                     vol_box=(-1.0, 0.0, -1.0, 2.0), vol_sigma=sigma)
+
+
+def volume_blobs(spec: SceneSpec, seed: int, n_blobs: int = 12) -> np.ndarray:
+    """Ground-truth volume: the sum of seeded Gaussian blobs (centres in the
+    inner 70% of the cube, radii 6-20% of its side) carrying the density and,
+    weighted by it, each blob's colour; clipped to [0, 1].  Layout
+    ((z R + y) R + x) * 4 + (R, G, B, density), float32."""
+    g = rng(seed)
+    R = spec.vol_res
+    c = (np.arange(R) + 0.5) / R
+    z, y, x = np.meshgrid(c, c, c, indexing="ij")
+    dens = np.zeros((R, R, R))
+    col = np.zeros((R, R, R, 3))
+    for _ in range(n_blobs):
+        ctr = g.uniform(0.15, 0.85, 3)
+        rad = g.uniform(0.06, 0.2)
+        amp = g.uniform(0.4, 1.0)
+        rgb = g.uniform(0.1, 1.0, 3)
+        b = amp * np.exp(-((x - ctr[0]) ** 2 + (y - ctr[1]) ** 2 + (z - ctr[2]) ** 2) /
+                         (2 * rad * rad))
+        dens += b
+        col += b[..., None] * rgb
+    col = col / np.maximum(dens[..., None], 1e-6)
+    out = np.concatenate([np.clip(col, 0, 1), np.clip(dens, 0, 1)[..., None]], axis=-1)
+    return out.reshape(-1).astype(np.float32)
+
+
+def volume_uniform(spec: SceneSpec, emission: float = 0.5, density: float = 0.05) -> np.ndarray:
+    """A constant volume (the usual starting point of a volume fit)."""
+    v = np.empty((spec.vol_res ** 3, 4), np.float32)
+    v[:, :3] = emission
+    v[:, 3] = density
+    return v.reshape(-1)
+
+
+def config_volume(res: int = 256, views: int = 8, view_w: int = 256, view_h: int = 256,
+                  seed_gt: int = 1):
+    """The volume workload: (spec, ground truth, initial parameters)."""
+    spec = scene_volume(res, views, view_w, view_h)
+    return spec, volume_blobs(spec, seed_gt), volume_uniform(spec)
