@@ -107,6 +107,11 @@ extern "C" {
 #define JSO_LAYOUT_VERTEX 1  /* mesh vertices: v * n_ch + c, interpolated with the
                                 barycentric weights of the hit point; only the
                                 mesh may then use JSO_MAT_PARAM                  */
+#define JSO_LAYOUT_VOLUME 2  /* emission-absorption volume: voxel
+                                ((z * R + y) * R + x) * 4 + c, c = emission R, G, B,
+                                density (ch_mask 15), trilinear interpolation  */
+#define JSO_MAX_VIEWS 16     /* cameras of a volume scene                         */
+#define JSO_MAX_VOL_RES 512  /* voxels per side                                   */
 
 typedef struct jso_ctx jso_ctx;
 
@@ -147,7 +152,23 @@ typedef struct {
   const float* verts;    /* [n_verts][3]: x, y, z                           */
   const int* tris;       /* [n_tris][3]: vertex indices                     */
   int mesh_mat;          /* JSO_MAT_PARAM or a fixed index                  */
-  int param_layout;      /* JSO_LAYOUT_TEXTURE or JSO_LAYOUT_VERTEX         */
+  int param_layout;      /* JSO_LAYOUT_TEXTURE, _VERTEX or _VOLUME          */
+  /* emission-absorption volume (param_layout = JSO_LAYOUT_VOLUME; the volume
+   * experiment of the Experiments section): vol_res^3 voxels filling the cube
+   * of side vol_box[3] whose low corner is vol_box[0..2], voxel centres at
+   * (i + 0.5) / vol_res of the side, clamp-to-edge trilinear interpolation;
+   * per voxel emission RGB and a density in [0, 1], the density scaled by
+   * vol_sigma per unit length.  A camera ray's chord through the cube is
+   * split into N = ceil(chord / voxel side) equal segments of length dt,
+   * sampled at t0 + (k + u) dt (one jitter u per ray, 0.5 with
+   * JSO_F_PIXEL_CENTER); radiance sum_k T_k (1 - exp(-sigma_k dt)) e_k +
+   * T_N env.  The image stacks vol_views views (height / vol_views rows
+   * each); view v's eye is cam_eye turned by 2 pi v / vol_views about the
+   * vertical axis through cam_target.  No plane, spheres, mesh or light;
+   * depth, roulette and texture fields are ignored. */
+  int vol_res, vol_views;
+  float vol_box[4];
+  float vol_sigma;
 } jso_scene_desc;
 
 typedef struct {

@@ -639,9 +639,11 @@ std::atomic<uint64_t> g_paths{0}, g_vertices{0}, g_param_vertices{0};
 // each sample reads the trilinearly interpolated voxel values (centres at
 // (i + 0.5) / R of the cube, clamp-to-edge) and the radiance is the
 // quadrature sum_k T_k alpha_k e_k + T_N env, alpha_k = 1 - exp(-sigma_k dt),
-// T_{k+1} = T_k (1 - alpha_k).  Margins: the hit/miss of the cube, the
-// rounding of chord / voxel to N, and each sample's cell (which corner gets
-// a vanishing weight), as for textures.
+// T_{k+1} = T_k (1 - alpha_k).  Margins: the hit/miss of the cube and the
+// rounding of chord / voxel to N.  A sample's cell is no decision for the
+// radiance (trilinear values are continuous across cells); only which corner
+// takes a vanishing weight changes there, which a gradient comparison must
+// allow for between neighbouring voxels.
 void trace_volume(const Scene& sc, const double* params, const PathRng& rng, int px, int py,
                   int flags, bool record, PathResult& out) {
   const orc_scene* s = sc.s;
@@ -689,7 +691,6 @@ void trace_volume(const Scene& sc, const double* params, const PathRng& rng, int
     for (int a = 0; a < 3; ++a) {
       const double g = (x[a] - s->vol_box[a]) / vox - 0.5;
       const double fl = std::floor(g);
-      mg.add(g - std::round(g));
       f[a] = g - fl;
       i0[a] = (int)std::min(std::max(fl, 0.0), R - 1);
       i1[a] = (int)std::min(std::max(fl + 1.0, 0.0), R - 1);

@@ -30,7 +30,8 @@ JSO_LOSS_L2, JSO_LOSS_RELATIVE = 0, 1
 JSO_ABLATE_CENTRED, JSO_ABLATE_NO_CLIP, JSO_ABLATE_UNCORRELATED = 1, 2, 4
 JSO_FD_REPLAY, JSO_FD_SHARED = 0, 1
 JSO_MAX_SPHERES, JSO_MAX_FIXED_MATS, JSO_MAX_TRIS = 32, 8, 4194304
-JSO_LAYOUT_TEXTURE, JSO_LAYOUT_VERTEX = 0, 1
+JSO_LAYOUT_TEXTURE, JSO_LAYOUT_VERTEX, JSO_LAYOUT_VOLUME = 0, 1, 2
+JSO_MAX_VIEWS, JSO_MAX_VOL_RES = 16, 512
 
 EXPORTED = [
     "jso_create", "jso_destroy", "jso_last_error", "jso_set_stream", "jso_synchronize",
@@ -71,6 +72,8 @@ class jso_scene_desc(ctypes.Structure):
         ("n_verts", ctypes.c_int), ("n_tris", ctypes.c_int),
         ("verts", ctypes.POINTER(ctypes.c_float)), ("tris", ctypes.POINTER(ctypes.c_int)),
         ("mesh_mat", ctypes.c_int), ("param_layout", ctypes.c_int),
+        ("vol_res", ctypes.c_int), ("vol_views", ctypes.c_int),
+        ("vol_box", ctypes.c_float * 4), ("vol_sigma", ctypes.c_float),
     ]
 
 
@@ -250,6 +253,10 @@ class SceneDesc:
         d.tris = self.tris.ctypes.data_as(ctypes.POINTER(ctypes.c_int))
         d.mesh_mat = int(getattr(spec, "mesh_mat", JSO_MAT_PARAM))
         d.param_layout = int(getattr(spec, "param_layout", JSO_LAYOUT_TEXTURE))
+        d.vol_res = int(getattr(spec, "vol_res", 0))
+        d.vol_views = int(getattr(spec, "vol_views", 1))
+        d.vol_box[:] = tuple(getattr(spec, "vol_box", (0.0, 0.0, 0.0, 1.0)))
+        d.vol_sigma = float(getattr(spec, "vol_sigma", 0.0))
         self.desc = d
 
 

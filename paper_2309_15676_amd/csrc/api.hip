@@ -172,7 +172,7 @@ struct DescRing {
 // flags); launch records keep their metadata, their units live on the device.
 struct CachedLaunch {
   int kind, timer, shape, n, stack;
-  bool shared;
+  bool shared, vol;
   uint32_t blocks;
   size_t lds, offset;
 };
@@ -320,6 +320,20 @@ int build_devscene(jso_ctx* c, const jso_scene_desc* d, SceneGPU* s) {
       other = other || (d->sphere_mat ? d->sphere_mat[k] : JSO_MAT_PARAM) == JSO_MAT_PARAM;
     if (other)
       return fail(c, JSO_E_INVALID, "with per-vertex parameters only the mesh may use them");
+  } else if (d->param_layout == JSO_LAYOUT_VOLUME) {
+    if (d->vol_res < 1 || d->vol_res > JSO_MAX_VOL_RES)
+      return fail(c, JSO_E_INVALID, "vol_res %d invalid (max %d)", d->vol_res, JSO_MAX_VOL_RES);
+    if (d->vol_views < 1 || d->vol_views > JSO_MAX_VIEWS || d->height % d->vol_views != 0)
+      return fail(c, JSO_E_INVALID, "vol_views %d invalid (max %d, must divide the height)",
+                  d->vol_views, JSO_MAX_VIEWS);
+    if (!(d->vol_box[3] > 0.0f) || !std::isfinite(d->vol_box[3]) || !(d->vol_sigma >= 0.0f) ||
+        !std::isfinite(d->vol_sigma))
+      return fail(c, JSO_E_INVALID, "volume box side and density scale must be finite, >0/>=0");
+    if (d->ch_mask != 15)
+      return fail(c, JSO_E_INVALID, "a volume has the 4 channels emission RGB + density "
+                                    "(ch_mask 15)");
+    if (d->plane_enabled || d->n_spheres > 0 || d->n_tris > 0 || d->light_enabled)
+      return fail(c, JSO_E_INVALID, "a volume scene has no plane, spheres, mesh or light");
   } else if (d->param_layout != JSO_LAYOUT_TEXTURE) {
     return fail(c, JSO_E_INVALID, "param_layout %d invalid", d->param_layout);
   }
@@ -401,6 +415,44 @@ int build_devscene(jso_ctx* c, const jso_scene_desc* d, SceneGPU* s) {
   s->npix = (size_t)d->width * d->height;
   s->P = (d->param_layout == JSO_LAYOUT_VERTEX ? (size_t)d->n_verts
                                                : (size_t)d->tex_w * d->tex_h) * nc;
+  if (d->param_layout == JSO_LAYOUT_VOLUME) {
+    const size_t R = (size_t)d->vol_res;
+    s->P = R * R * R * 4;
+    S.vol_res = d->vol_res;
+    S.vol_views = d->vol_views;
+    S.view_h = d->height / d->vol_views;
+    for (int k = 0; k < 3; ++k) S.vol_lo[k] = d->vol_box[k];
+    S.vol_side = d->vol_box[3];
+    S.vol_inv_vox = (float)((double)d->vol_res / (double)d->vol_box[3]);
+    S.vol_sigma = d->vol_sigma;
+    S.aspect = (float)((double)d->width / (double)S.view_h);
+    // view v: the eye turned by 2 pi v / V about the vertical axis through the
+    // target (bases in double, stored as float)
+    for (int v = 0; v < d->vol_views; ++v) {
+      const double ang = 2.0 * M_PI * v / d->vol_views, ca = std::cos(ang), sa = std::sin(ang);
+      const double r[3] = {(double)d->cam_eye[0] - d->cam_target[0], 0.0,
+                           (double)d->cam_eye[2] - d->cam_target[2]};
+      const double ev[3] = {d->cam_target[0] + r[0] * ca + r[2] * sa, (double)d->cam_eye[1],
+                            d->cam_target[2] - r[0] * sa + r[2] * ca};
+      double wv[3] = {d->cam_target[0] - ev[0], d->cam_target[1] - ev[1],
+                      d->cam_target[2] - ev[2]};
+      const double wn = std::sqrt(wv[0] * wv[0] + wv[1] * wv[1] + wv[2] * wv[2]);
+      for (double& x : wv) x /= wn;
+      double uv[3] = {wv[1] * up[2] - wv[2] * up[1], wv[2] * up[0] - wv[0] * up[2],
+                      wv[0] * up[1] - wv[1] * up[0]};
+      const double un = std::sqrt(uv[0] * uv[0] + uv[1] * uv[1] + uv[2] * uv[2]);
+      if (!(un > 0)) return fail(c, JSO_E_INVALID, "camera up parallel to view %d", v);
+      for (double& x : uv) x /= un;
+      const double vv[3] = {uv[1] * wv[2] - uv[2] * wv[1], uv[2] * wv[0] - uv[0] * wv[2],
+                            uv[0] * wv[1] - uv[1] * wv[0]};
+      for (int k = 0; k < 3; ++k) {
+        S.view_eye[v][k] = (float)ev[k];
+        S.view_cw[v][k] = (float)wv[k];
+        S.view_cu[v][k] = (float)uv[k];
+        S.view_cv[v][k] = (float)vv[k];
+      }
+    }
+  }
   return JSO_OK;
 }
 
@@ -576,6 +628,7 @@ struct LaunchRec {
   size_t lds = 0;
   int stack = 0;               // path kernels: BVH stack entries (deepest mesh of the units)
   bool shared = false;         // path kernels: units hold shared-path pair slices
+  bool vol = false;            // path kernels: the units' scenes are volumes
   size_t dev_offset = 0;       // batches: offset of the units in the device arena
 };
 
@@ -683,6 +736,7 @@ void plan_estimators(const std::vector<ProbPlan>& ps, Plan& plan, int shape = 0)
     fw.kind = Kern::Forward;
     fw.timer = JSO_K_FORWARD;
     fw.shape = shape;
+    fw.vol = p0.s->dev.layout == JSO_LAYOUT_VOLUME;
     for (const ProbPlan& p : ps) {
       if (crop_empty(p.crop)) continue;
       FwdArgs f{};
@@ -781,6 +835,7 @@ void plan_estimators(const std::vector<ProbPlan>& ps, Plan& plan, int shape = 0)
       ad.shape = shape;
       ad.lds = adjoint_lds_bytes(max_ch);
       ad.shared = shared_pairs;
+      ad.vol = p0.s->dev.layout == JSO_LAYOUT_VOLUME;
       for (int pass = 0; pass < 2; ++pass) {
         for (const ProbPlan& p : ps) {
           if (crop_empty(p.crop)) continue;
@@ -1048,6 +1103,24 @@ ProbPlan variance_problem(SceneGPU* s, const jso_step_opts& o, uint32_t flags,
   return p;
 }
 
+bool is_volume(const SceneGPU* s) { return s->dev.layout == JSO_LAYOUT_VOLUME; }
+
+// Problems stepped together must all be volumes or none (their launches use
+// different kernels).
+int check_same_kind(jso_ctx* c, const int* ids, int n) {
+  for (int k = 1; k < n; ++k)
+    if (is_volume(get_scene(c, ids[k])) != is_volume(get_scene(c, ids[0])))
+      return fail(c, JSO_E_INVALID, "volume and surface scenes cannot be stepped together");
+  return JSO_OK;
+}
+
+// The volume kernels read each voxel's 4 channels with one 16-byte load.
+int check_volume_params(jso_ctx* c, const SceneGPU* s, const float* params) {
+  if (is_volume(s) && (reinterpret_cast<uintptr_t>(params) & 15u) != 0)
+    return fail(c, JSO_E_INVALID, "volume parameters must be 16-byte aligned");
+  return JSO_OK;
+}
+
 bool uncorrelated(const jso_step_opts& o) {
   return o.optimizer == JSO_OPT_META && (o.ablate & JSO_ABLATE_UNCORRELATED) != 0;
 }
@@ -1088,11 +1161,17 @@ hipError_t launch_rec(const LaunchRec& r, const void* dev_units, unsigned long l
                       hipStream_t st) {
   switch (r.kind) {
     case Kern::Forward:
+      if (r.vol)
+        return launch_vol_forward(static_cast<const FwdArgs*>(dev_units), r.n, r.blocks, r.shape,
+                                  work, st);
       return launch_forward(static_cast<const FwdArgs*>(dev_units), r.n, r.blocks, r.shape,
                             r.stack, r.shared, work, st);
     case Kern::Finalize:
       return launch_finalize(static_cast<const FinArgs*>(dev_units), r.n, r.blocks, st);
     case Kern::Adjoint:
+      if (r.vol)
+        return launch_vol_adjoint(static_cast<const RepArgs*>(dev_units), r.n, r.blocks, r.shape,
+                                  work, st);
       return launch_adjoint(static_cast<const RepArgs*>(dev_units), r.n, r.blocks, r.shape, r.lds,
                             r.stack, r.shared, work, st);
     case Kern::Meta:
@@ -1201,8 +1280,8 @@ int exec_cached(jso_ctx* c, const std::vector<uint64_t>& sig, Build build) {
     for (size_t k = 0; k < plan.size(); ++k) {
       const LaunchRec& r = plan[k];
       np.launches.push_back(
-          CachedLaunch{(int)r.kind, r.timer, r.shape, r.n, r.stack, r.shared, r.blocks, r.lds,
-                       off[k]});
+          CachedLaunch{(int)r.kind, r.timer, r.shape, r.n, r.stack, r.shared, r.vol, r.blocks,
+                       r.lds, off[k]});
     }
     np.sig = sig;
     pc.plans.push_back(std::move(np));
@@ -1220,6 +1299,7 @@ int exec_cached(jso_ctx* c, const std::vector<uint64_t>& sig, Build build) {
     r.lds = l.lds;
     r.stack = l.stack;
     r.shared = l.shared;
+    r.vol = l.vol;
     TIMED_LAUNCH(c, l.timer, launch_rec(r, hit->dev + l.offset, work, c->stream));
   }
   return JSO_OK;
@@ -1449,6 +1529,7 @@ int jso_render(jso_ctx* c, int id, const float* params, uint64_t seed, uint32_t 
   if (!s) return c ? fail(c, JSO_E_INVALID, "bad scene id %d", id) : JSO_E_INVALID;
   if (!params || !img) return fail(c, JSO_E_INVALID, "null params/img");
   if (spp < 1) return fail(c, JSO_E_INVALID, "spp must be >= 1");
+  if (int rc = check_volume_params(c, s, params)) return rc;
   DeviceGuard g(c->device);
   ProbPlan p{};
   p.s = s;
@@ -1469,6 +1550,7 @@ int jso_render_bwd(jso_ctx* c, int id, const float* params, uint64_t seed, uint3
   if (!s) return c ? fail(c, JSO_E_INVALID, "bad scene id %d", id) : JSO_E_INVALID;
   if (!params || !dimg || !dparams) return fail(c, JSO_E_INVALID, "null argument");
   if (spp < 1) return fail(c, JSO_E_INVALID, "spp must be >= 1");
+  if (int rc = check_volume_params(c, s, params)) return rc;
   DeviceGuard g(c->device);
   ProbPlan p{};
   p.s = s;
@@ -1597,6 +1679,8 @@ int jso_grad_step(jso_ctx* c, const int* ids, int n, const jso_step_opts* o,
       if (ids[q] == ids[k]) return fail(c, JSO_E_INVALID, "scene %d listed twice", ids[k]);
   }
   int rc = check_step_opts(c, o);
+  if (rc) return rc;
+  rc = check_same_kind(c, ids, n);
   if (rc) return rc;
   DeviceGuard g(c->device);
   const uint32_t flags = c->debug_flags | o->flags;
@@ -1790,6 +1874,8 @@ int jso_batch_create(jso_ctx* c, const int* ids, int n, const jso_step_opts* o,
       if (ids[q] == ids[k]) return fail(c, JSO_E_INVALID, "scene %d listed twice", ids[k]);
   }
   int rc = check_step_opts(c, o);
+  if (rc) return rc;
+  rc = check_same_kind(c, ids, n);
   if (rc) return rc;
   DeviceGuard g(c->device);
   std::unique_ptr<jso_batch, void (*)(jso_batch*)> b(new (std::nothrow) jso_batch, batch_free);

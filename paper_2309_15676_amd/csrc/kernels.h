@@ -230,6 +230,12 @@ hipError_t launch_finalize(const FinArgs* U, int n, uint32_t blocks, hipStream_t
 // lds: dynamic LDS bytes (adjoint_lds_bytes of the largest channel count)
 hipError_t launch_adjoint(const RepArgs* U, int n, uint32_t blocks, int shape, size_t lds,
                           int stack, bool shared, unsigned long long* work, hipStream_t st);
+// The same for emission-absorption volume scenes (every unit's scene a volume;
+// parameter buffers 16-byte aligned)
+hipError_t launch_vol_forward(const FwdArgs* U, int n, uint32_t blocks, int shape,
+                              unsigned long long* work, hipStream_t st);
+hipError_t launch_vol_adjoint(const RepArgs* U, int n, uint32_t blocks, int shape,
+                              unsigned long long* work, hipStream_t st);
 hipError_t launch_meta(const MetaArgs* U, int n, uint32_t blocks, hipStream_t st);
 hipError_t launch_adam(const AdamArgs* U, int n, uint32_t blocks, hipStream_t st);
 hipError_t launch_fill_f64(double* p, size_t n, double v, hipStream_t st);

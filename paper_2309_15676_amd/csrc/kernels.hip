@@ -906,6 +906,281 @@ k_adjoint(const RepArgs* __restrict__ Units, int n_units, int stack, unsigned lo
 }
 
 // ---------------------------------------------------------------------------
+// emission-absorption volume (layout JSO_LAYOUT_VOLUME; the volume experiment
+// of the Experiments section).  Each lane marches its pixel's ray through the
+// cube: the chord is split into n = ceil(chord / voxel) equal segments of
+// length dt, sampled at t0 + (k + u) dt with one jitter u per ray; each
+// sample reads the clamp-to-edge trilinear interpolation of 8 voxels (one
+// 16-byte load each: emission RGB, density).  Radiance: sum_k T_k a_k e_k +
+// T_n env with a_k = 1 - exp(-sigma_k dt), T_{k+1} = T_k exp(-sigma_k dt),
+// summed in an FP64 ledger.  The march draws nothing from the parameters, so
+// a finite-difference pair is one march with two ledgers in either fd_mode.
+// ---------------------------------------------------------------------------
+struct VolRay {
+  V3 o, d;
+  float t0, dt, us;
+  int n;  // segments (0: the ray misses the cube)
+};
+
+__device__ __forceinline__ VolRay vol_ray(const DevScene& S, const Rng& rng, int px, int py,
+                                          uint32_t flags) {
+  float u[4];
+  rng.draw(0, 0, u);
+  const bool center = (flags & JSO_F_PIXEL_CENTER) != 0;
+  const float jx = center ? 0.5f : u[0], jy = center ? 0.5f : u[1];
+  VolRay r;
+  r.us = center ? 0.5f : u[2];
+  const int v = py / S.view_h;
+  const int row = py - v * S.view_h;
+  const float sx = (2.0f * ((float)px + jx) / (float)S.width - 1.0f) * S.tan_half * S.aspect;
+  const float sy = (1.0f - 2.0f * ((float)row + jy) / (float)S.view_h) * S.tan_half;
+  r.o = ld3(S.view_eye[v]);
+  r.d = normalize(ld3(S.view_cw[v]) + ld3(S.view_cu[v]) * sx + ld3(S.view_cv[v]) * sy);
+  const float o[3] = {r.o.x, r.o.y, r.o.z}, d[3] = {r.d.x, r.d.y, r.d.z};
+  float t0 = 0.0f, t1 = 3.0e38f;
+#pragma unroll
+  for (int a = 0; a < 3; ++a) {
+    const float inv = safe_inv(d[a]);
+    const float ta = (S.vol_lo[a] - o[a]) * inv, tb = (S.vol_lo[a] + S.vol_side - o[a]) * inv;
+    t0 = fmaxf(t0, fminf(ta, tb));
+    t1 = fminf(t1, fmaxf(ta, tb));
+  }
+  r.n = 0;
+  r.t0 = t0;
+  r.dt = 0.0f;
+  if (t1 > t0) {
+    r.n = max(1, (int)ceilf((t1 - t0) * S.vol_inv_vox));
+    r.dt = (t1 - t0) / (float)r.n;
+  }
+  return r;
+}
+
+// Trilinear corners of the sample at x: voxel indices (8) and the fractions.
+struct VolCell {
+  int idx[8];
+  float fx, fy, fz;
+  __device__ __forceinline__ float w(int c) const {
+    return ((c & 1) ? fx : 1.0f - fx) * ((c & 2) ? fy : 1.0f - fy) * ((c & 4) ? fz : 1.0f - fz);
+  }
+};
+
+__device__ __forceinline__ VolCell vol_cell(const DevScene& S, V3 x) {
+  const int R = S.vol_res;
+  const float g[3] = {(x.x - S.vol_lo[0]) * S.vol_inv_vox - 0.5f,
+                      (x.y - S.vol_lo[1]) * S.vol_inv_vox - 0.5f,
+                      (x.z - S.vol_lo[2]) * S.vol_inv_vox - 0.5f};
+  int i0[3], i1[3];
+  float f[3];
+#pragma unroll
+  for (int a = 0; a < 3; ++a) {
+    const float fl = floorf(g[a]);
+    f[a] = g[a] - fl;
+    i0[a] = min(max((int)fl, 0), R - 1);
+    i1[a] = min(max((int)fl + 1, 0), R - 1);
+  }
+  VolCell c;
+  c.fx = f[0];
+  c.fy = f[1];
+  c.fz = f[2];
+#pragma unroll
+  for (int k = 0; k < 8; ++k)
+    c.idx[k] = (((k & 4) ? i1[2] : i0[2]) * R + ((k & 2) ? i1[1] : i0[1])) * R +
+               ((k & 1) ? i1[0] : i0[0]);
+  return c;
+}
+
+__device__ __forceinline__ float4 vol_fetch(const float* __restrict__ params, const VolCell& c) {
+  const float4* p4 = reinterpret_cast<const float4*>(params);
+  float4 v = make_float4(0.0f, 0.0f, 0.0f, 0.0f);
+#pragma unroll
+  for (int k = 0; k < 8; ++k) {
+    const float4 q = p4[c.idx[k]];
+    const float w = c.w(k);
+    v.x += w * q.x;
+    v.y += w * q.y;
+    v.z += w * q.z;
+    v.w += w * q.w;
+  }
+  return v;
+}
+
+// One march; kTwo: also the ledger of params_b.  led / led_b: radiance (FP64).
+template <bool kTwo>
+__device__ __forceinline__ int vol_march(const DevScene& S, const VolRay& r,
+                                         const float* __restrict__ pa,
+                                         const float* __restrict__ pb, double led[3],
+                                         double led_b[3]) {
+  float T = 1.0f, Tb = 1.0f;
+#pragma unroll
+  for (int ch = 0; ch < 3; ++ch) led[ch] = led_b[ch] = 0.0;
+  for (int k = 0; k < r.n; ++k) {
+    const VolCell c = vol_cell(S, r.o + r.d * (r.t0 + ((float)k + r.us) * r.dt));
+    const float4 v = vol_fetch(pa, c);
+    const float od = S.vol_sigma * v.w * r.dt;
+    const float a = -expm1f(-od);
+    led[0] += (double)(T * a * v.x);
+    led[1] += (double)(T * a * v.y);
+    led[2] += (double)(T * a * v.z);
+    T *= expf(-od);
+    if (kTwo) {
+      const float4 vb = vol_fetch(pb, c);
+      const float odb = S.vol_sigma * vb.w * r.dt;
+      const float ab = -expm1f(-odb);
+      led_b[0] += (double)(Tb * ab * vb.x);
+      led_b[1] += (double)(Tb * ab * vb.y);
+      led_b[2] += (double)(Tb * ab * vb.z);
+      Tb *= expf(-odb);
+    }
+  }
+#pragma unroll
+  for (int ch = 0; ch < 3; ++ch) {
+    led[ch] += (double)(T * S.env[ch]);
+    if (kTwo) led_b[ch] += (double)(Tb * S.env[ch]);
+  }
+  return r.n;
+}
+
+template <int TW, int TH>
+__global__ void __launch_bounds__(TW * TH)
+k_vol_forward(const FwdArgs* __restrict__ Units, int n_units, unsigned long long* work) {
+  using SH = Shape<TW, TH>;
+  const FwdArgs& A = unit_of(Units, n_units);
+  const uint32_t iter = iteration_of(A.key);
+  if (A.h.max_iter && iter >= A.h.max_iter) return;  // finished problem
+  const DevScene& S = *G(A.scene);
+  const TileBlock tb = tile_block<SH>(A);
+  const FwdSlice& sl = A.sl[tb.slice];
+  int px, py;
+  const bool inside = tile_pixel<SH>(A.crop, tb, px, py);
+  const uint32_t pix = (uint32_t)(py * S.width + px);
+  const bool active = inside && !(G(A.mask) && G(A.mask)[pix]);
+  int n_samples = 0;
+  if (active) {
+    const Rng rng = make_rng(stream_key(A.key.seed, iter, sl.tag), pix, sl.sample);
+    const VolRay r = vol_ray(S, rng, px, py, A.flags);
+    double led[3], led_b[3];
+    double* out = G(A.slots) + (size_t)sl.slot * A.npix * 3;
+    if (G(sl.params_b) != nullptr) {
+      n_samples = vol_march<true>(S, r, G(sl.params), G(sl.params_b), led, led_b);
+      store_radiance(G(A.slots) + (size_t)sl.slot_b * A.npix * 3, pix, led_b);
+    } else {
+      n_samples = vol_march<false>(S, r, G(sl.params), nullptr, led, led_b);
+    }
+    store_radiance(out, pix, led);
+  }
+  count_work(work ? work + 2 : nullptr, active ? 1 : 0, n_samples);
+}
+
+// Replay: the remainder R = C - (radiance collected so far) gives, per sample,
+//   dC/de_k     = T_k a_k
+//   dC/dsigma_k = dt (T_{k+1} e_k - R_{k+1})
+// (R_{k+1}: the radiance behind the sample, environment included), times the
+// density scale, spread over the 8 voxels by the trilinear weights with
+// no-return FP32 atomics.  Pairs difference the two ledgers' gradients per
+// sample (same voxels) and scatter once.
+// One pixel's replay of a volume slice (see k_vol_adjoint).
+__device__ __forceinline__ void vol_replay(const DevScene& S, const RepArgs& A,
+                                           const RepSlice& sl, uint32_t pix, int px, int py,
+                                           uint32_t iter, int& n_samples) {
+  const bool pair = G(sl.params_b) != nullptr;
+  const float* pa = G(sl.params);
+  const float* pb = G(sl.params_b);
+  float* grad = G(sl.grad);
+  const Rng rng = make_rng(stream_key(A.key.seed, iter, sl.tag), pix, sl.sample);
+  const VolRay r = vol_ray(S, rng, px, py, A.flags);
+  float adj[3], adj_b[3];
+  double rem[3], rem_b[3];
+  const double* Ca = G(A.slots) + ((size_t)sl.slot_a * A.npix + pix) * 3;
+#pragma unroll
+  for (int ch = 0; ch < 3; ++ch) {
+    adj[ch] = G(sl.delta)[3 * (size_t)pix + ch] * sl.adj_scale;
+    rem[ch] = Ca[ch];
+    adj_b[ch] = 0.0f;
+    rem_b[ch] = 0.0;
+  }
+  if (pair) {
+    const double* Cb = G(A.slots) + ((size_t)sl.slot_b * A.npix + pix) * 3;
+#pragma unroll
+    for (int ch = 0; ch < 3; ++ch) {
+      adj_b[ch] = G(sl.delta_b)[3 * (size_t)pix + ch] * sl.adj_scale;
+      rem_b[ch] = Cb[ch];
+    }
+  }
+  const float sign = pair ? 1.0f : sl.sign;
+  float T = 1.0f, Tb = 1.0f;
+  for (int k = 0; k < r.n; ++k) {
+    const VolCell c = vol_cell(S, r.o + r.d * (r.t0 + ((float)k + r.us) * r.dt));
+    float g[4];
+    {
+      const float4 v = vol_fetch(pa, c);
+      const float od = S.vol_sigma * v.w * r.dt;
+      const float a = -expm1f(-od), et = expf(-od);
+      const float e[3] = {v.x, v.y, v.z};
+      const float Tn = T * et;
+      float gs = 0.0f;
+#pragma unroll
+      for (int ch = 0; ch < 3; ++ch) {
+        rem[ch] -= (double)(T * a * e[ch]);
+        g[ch] = adj[ch] * T * a;
+        gs += adj[ch] * (Tn * e[ch] - (float)rem[ch]);
+      }
+      g[3] = gs * r.dt * S.vol_sigma;
+      T = Tn;
+    }
+    if (pair) {
+      const float4 v = vol_fetch(pb, c);
+      const float od = S.vol_sigma * v.w * r.dt;
+      const float a = -expm1f(-od), et = expf(-od);
+      const float e[3] = {v.x, v.y, v.z};
+      const float Tn = Tb * et;
+      float gb[4], gs = 0.0f;
+#pragma unroll
+      for (int ch = 0; ch < 3; ++ch) {
+        rem_b[ch] -= (double)(Tb * a * e[ch]);
+        gb[ch] = adj_b[ch] * Tb * a;
+        gs += adj_b[ch] * (Tn * e[ch] - (float)rem_b[ch]);
+      }
+      gb[3] = gs * r.dt * S.vol_sigma;
+      Tb = Tn;
+#pragma unroll
+      for (int q = 0; q < 4; ++q) g[q] -= gb[q];
+    }
+#pragma unroll
+    for (int q = 0; q < 8; ++q) {
+      const float w = c.w(q) * sign;
+      float* gp = grad + 4 * (size_t)c.idx[q];
+#pragma unroll
+      for (int ch = 0; ch < 4; ++ch) {
+        const float val = w * g[ch];
+        if (val != 0.0f) unsafeAtomicAdd(gp + ch, val);
+      }
+    }
+  }
+  n_samples = r.n;
+}
+
+template <int TW, int TH>
+__global__ void __launch_bounds__(TW * TH)
+k_vol_adjoint(const RepArgs* __restrict__ Units, int n_units, unsigned long long* work) {
+  using SH = Shape<TW, TH>;
+  const RepArgs& A = unit_of(Units, n_units);
+  const uint32_t iter = iteration_of(A.key);
+  if (A.h.max_iter && iter >= A.h.max_iter) return;  // finished problem
+  const DevScene& S = *G(A.scene);
+  const TileBlock tb = tile_block<SH>(A);
+  const RepSlice& sl = A.sl[tb.slice];
+  int px, py;
+  const bool inside = tile_pixel<SH>(A.crop, tb, px, py);
+  const uint32_t pix = (uint32_t)(py * S.width + px);
+  const bool active = inside && !(G(A.mask) && G(A.mask)[pix]);
+  int n_samples = 0;
+  if (active) vol_replay(S, A, sl, pix, px, py, iter, n_samples);
+  count_work(work, active ? 1 : 0, n_samples);
+}
+
+
+
+// ---------------------------------------------------------------------------
 // fused meta-estimator + stabilised step
 // ---------------------------------------------------------------------------
 // Each thread takes kMetaK elements, one block-width apart, with every load
@@ -1268,6 +1543,30 @@ hipError_t launch_adjoint(const RepArgs* U, int n, uint32_t blocks, int shape, s
     case 0: adj_launch<16, 16>(U, n, blocks, lds, stack, shared, work, st); break;
     case 1: adj_launch<16, 8>(U, n, blocks, lds, stack, shared, work, st); break;
     case 2: adj_launch<8, 8>(U, n, blocks, lds, stack, shared, work, st); break;
+    default: return hipErrorInvalidValue;
+  }
+  return hipGetLastError();
+}
+
+hipError_t launch_vol_forward(const FwdArgs* U, int n, uint32_t blocks, int shape,
+                              unsigned long long* work, hipStream_t st) {
+  if (n <= 0 || blocks == 0) return hipSuccess;
+  switch (shape) {
+    case 0: hipLaunchKernelGGL((k_vol_forward<16, 16>), dim3(blocks), dim3(256), 0, st, U, n, work); break;
+    case 1: hipLaunchKernelGGL((k_vol_forward<16, 8>), dim3(blocks), dim3(128), 0, st, U, n, work); break;
+    case 2: hipLaunchKernelGGL((k_vol_forward<8, 8>), dim3(blocks), dim3(64), 0, st, U, n, work); break;
+    default: return hipErrorInvalidValue;
+  }
+  return hipGetLastError();
+}
+
+hipError_t launch_vol_adjoint(const RepArgs* U, int n, uint32_t blocks, int shape,
+                              unsigned long long* work, hipStream_t st) {
+  if (n <= 0 || blocks == 0) return hipSuccess;
+  switch (shape) {
+    case 0: hipLaunchKernelGGL((k_vol_adjoint<16, 16>), dim3(blocks), dim3(256), 0, st, U, n, work); break;
+    case 1: hipLaunchKernelGGL((k_vol_adjoint<16, 8>), dim3(blocks), dim3(128), 0, st, U, n, work); break;
+    case 2: hipLaunchKernelGGL((k_vol_adjoint<8, 8>), dim3(blocks), dim3(64), 0, st, U, n, work); break;
     default: return hipErrorInvalidValue;
   }
   return hipGetLastError();
