@@ -425,6 +425,122 @@ def batched_throughput(ctx_problem, args):
     }
 
 
+META_BYTES_PER_PARAM = 108  # k_meta: reads 52 B, writes 56 B per parameter
+
+
+def volume_workload(context, args):
+    """The volume experiment's workload: a 256^3 emission-absorption volume
+    (67.1M parameters: emission RGB + density per voxel) seen by 8 cameras of
+    256x256.  Meta-estimator step time (replay pair and shared path; the
+    march draws nothing from the parameters, so both trace the same rays),
+    Adam at 2 and 4 spp (the paper places the meta-estimator's cost between
+    them), k_meta against the HBM roofline at this parameter count, and the
+    loss each reaches in the same wall-clock."""
+    import torch
+    from paper_2309_15676_amd import _lib as L
+    from paper_2309_15676_amd import inputs as I
+    from paper_2309_15676_amd.problem import Problem
+    t0 = time.time()
+    spec, gt, init = I.config_volume()
+    prob = Problem(spec, context=context)
+    ctx = prob.ctx
+    target = prob.render(gt, seed=12345, iteration=0, tag=L.JSO_TAG_TARGET, spp=16)
+    prob.set_target(target)
+    prob.set_params(init)
+    load_s = time.time() - t0
+    names = ((L.JSO_K_FORWARD, "forward"), (L.JSO_K_FINALIZE, "finalize"),
+             (L.JSO_K_ADJOINT, "adjoint"), (L.JSO_K_META, "meta"), (L.JSO_K_ADAM, "adam"))
+
+    def timed(opts, n):
+        prob.set_params(init)
+        for _ in range(2):
+            prob.grad_step(opts)
+        torch.cuda.synchronize()
+        L.check(L.jso_set_timing(ctx, True), ctx)
+        for k in range(L.JSO_K_COUNT):
+            L.jso_get_kernel_time(ctx, k, reset=True)
+        e0, e1 = torch.cuda.Event(enable_timing=True), torch.cuda.Event(enable_timing=True)
+        e0.record()
+        for _ in range(n):
+            prob.grad_step(opts)
+        e1.record()
+        torch.cuda.synchronize()
+        kt = {}
+        for k, name in names:
+            ms, calls = L.jso_get_kernel_time(ctx, k)
+            if calls:
+                kt[name] = {"ms_per_step": ms / n, "ms_per_launch": ms / calls}
+        L.check(L.jso_set_timing(ctx, False), ctx)
+        return e0.elapsed_time(e1) / n, kt
+
+    n = args.volume_steps
+    npix = spec.n_pixels
+    out = {"workload": "256^3 emission-absorption volume (67,108,864 params: emission RGB + "
+                       "density), 8 views of 256x256 (524,288 pixels), density scale 8 per unit "
+                       "length, voxel-length segments (up to ~440 samples per ray)",
+           "scene_load_s": load_s}
+    meta = L.step_opts(optimizer=L.JSO_OPT_META, eta=0.01, seed=args.seed)
+    ms, kt = timed(meta, n)
+    out["meta_step"] = {"ms": ms, "diff_paths_per_s": 4 * npix / (ms / 1e3), "kernel": kt}
+    ms, kt = timed(L.step_opts(optimizer=L.JSO_OPT_META, eta=0.01, seed=args.seed,
+                               fd_mode=L.JSO_FD_SHARED), n)
+    out["meta_step_fd_shared"] = {"ms": ms, "kernel": kt}
+    for spp in (2, 4):
+        ms, kt = timed(L.step_opts(optimizer=L.JSO_OPT_ADAM, eta=0.01, adam_spp=spp,
+                                   seed=args.seed), n)
+        out["adam%d_step" % spp] = {"ms": ms, "kernel": kt}
+    km = out["meta_step"]["kernel"]["meta"]["ms_per_launch"]
+    bytes_meta = META_BYTES_PER_PARAM * spec.n_params
+    out["k_meta_roofline"] = {"bound": "hbm", "bytes_per_launch": bytes_meta, "ms": km,
+                              "achieved_GBs": bytes_meta / (km / 1e3) / 1e9,
+                              "peak_GBs": PEAK_HBM_GBS,
+                              "frac": bytes_meta / (km / 1e3) / 1e9 / PEAK_HBM_GBS}
+    # equal wall-clock: the loss of a 16-spp evaluation render (off the clock)
+    if args.volume_ttl_seconds > 0:
+        def eval_loss():
+            img = prob.render(prob.get_params(), seed=777, iteration=0, tag=L.JSO_TAG_EVAL,
+                              spp=16)
+            return float(((img - target) ** 2).mean())
+
+        def run(opts, seconds, every):
+            prob.set_params(init)
+            clock, it, hist = 0.0, 0, [(0, 0.0, eval_loss())]
+            e0, e1 = torch.cuda.Event(enable_timing=True), torch.cuda.Event(enable_timing=True)
+            while clock < seconds:
+                torch.cuda.synchronize()
+                e0.record()
+                for _ in range(every):
+                    prob.grad_step(opts)
+                e1.record()
+                torch.cuda.synchronize()
+                clock += e0.elapsed_time(e1) / 1e3
+                it += every
+                hist.append((it, clock, eval_loss()))
+            return hist
+
+        ttl = {"seconds": args.volume_ttl_seconds, "initial_loss": eval_loss(), "runs": {}}
+        for name, mk in (("meta", lambda e: L.step_opts(optimizer=L.JSO_OPT_META, eta=e,
+                                                         seed=args.seed + 2)),
+                         ("adam2", lambda e: L.step_opts(optimizer=L.JSO_OPT_ADAM, eta=e,
+                                                          adam_spp=2, seed=args.seed + 1)),
+                         ("adam4", lambda e: L.step_opts(optimizer=L.JSO_OPT_ADAM, eta=e,
+                                                          adam_spp=4, seed=args.seed + 1))):
+            best = None
+            for eta in (0.003, 0.01, 0.03):
+                h = run(mk(eta), args.volume_ttl_seconds, 10)
+                row = {"eta": eta, "iterations": h[-1][0], "final_loss": h[-1][2],
+                       "best_loss": min(x[2] for x in h),
+                       "loss_curve": [(x[0], round(x[1], 4), x[2]) for x in h[:: max(len(h) // 8, 1)]]}
+                if best is None or row["best_loss"] < best["best_loss"]:
+                    best = row
+            ttl["runs"][name] = best
+        out["equal_time"] = ttl
+    print("[bench] volume: %s" % json.dumps(out), file=sys.stderr, flush=True)
+    del prob
+    torch.cuda.empty_cache()
+    return out
+
+
 def mesh_workloads(context, args):
     """Throughput of the mesh workloads (BVH traversal): the 1024x1024,
     200,000-triangle displaced sphere with per-vertex RGB + roughness
@@ -544,6 +660,10 @@ def main():
     ap.add_argument("--large-ttl-seconds", type=float, default=0.0,
                     help="GPU-seconds per run of the terrain time-to-RMSE comparison "
                          "(meta-estimator vs Adam at 32 and 64 spp; 0: skip)")
+    ap.add_argument("--volume-steps", type=int, default=5,
+                    help="timed calls per volume configuration (0 = skip the volume workload)")
+    ap.add_argument("--volume-ttl-seconds", type=float, default=5.0,
+                    help="GPU-seconds per run of the volume equal-time comparison (0: skip)")
     ap.add_argument("--mesh-steps", type=int, default=10,
                     help="timed calls per mesh workload (0 = skip the mesh workloads)")
     args = ap.parse_args()
@@ -652,6 +772,10 @@ def main():
     if args.mesh_steps > 0:
         print("[bench] mesh workloads", file=sys.stderr, flush=True)
         mesh = mesh_workloads(prob.context, args)
+    vol = None
+    if args.volume_steps > 0:
+        print("[bench] volume workload", file=sys.stderr, flush=True)
+        vol = volume_workload(prob.context, args)
     large = None
     if args.large_ttl_seconds > 0:
         print("[bench] terrain time to RMSE", file=sys.stderr, flush=True)
@@ -735,6 +859,7 @@ def main():
         "time_to_loss": ttl,
         "batched": bat,
         "meshes": mesh,
+        "volume": vol,
         "ablations": abl,
         "large_time_to_rmse": large,
     }

@@ -14,6 +14,7 @@
 //   k_adam     - Adam baseline
 #include <hip/hip_runtime.h>
 
+#include <climits>
 #include <type_traits>
 
 #include "device.h"
@@ -955,9 +956,12 @@ __device__ __forceinline__ VolRay vol_ray(const DevScene& S, const Rng& rng, int
   return r;
 }
 
-// Trilinear corners of the sample at x: voxel indices (8) and the fractions.
+// Trilinear corners of the sample at x: voxel indices (8, clamped to the
+// grid), the cell's base (unclamped floor of the grid coordinate) and the
+// fractions.
 struct VolCell {
   int idx[8];
+  int bx, by, bz;
   float fx, fy, fz;
   __device__ __forceinline__ float w(int c) const {
     return ((c & 1) ? fx : 1.0f - fx) * ((c & 2) ? fy : 1.0f - fy) * ((c & 4) ? fz : 1.0f - fz);
@@ -982,6 +986,9 @@ __device__ __forceinline__ VolCell vol_cell(const DevScene& S, V3 x) {
   c.fx = f[0];
   c.fy = f[1];
   c.fz = f[2];
+  c.bx = (int)floorf(g[0]);
+  c.by = (int)floorf(g[1]);
+  c.bz = (int)floorf(g[2]);
 #pragma unroll
   for (int k = 0; k < 8; ++k)
     c.idx[k] = (((k & 4) ? i1[2] : i0[2]) * R + ((k & 2) ? i1[1] : i0[1])) * R +
@@ -1078,6 +1085,64 @@ k_vol_forward(const FwdArgs* __restrict__ Units, int n_units, unsigned long long
 // density scale, spread over the 8 voxels by the trilinear weights with
 // no-return FP32 atomics.  Pairs difference the two ledgers' gradients per
 // sample (same voxels) and scatter once.
+// Per-lane sums over the 8 corners of the current cell.  Consecutive samples
+// of a ray share the corners of the cell faces they stay between, so their
+// gradients are summed in registers and a corner is written out (4 atomics)
+// only when the ray leaves it: about half the atomics of writing every
+// sample's 8 corners.  A corner's slot is given by the parities of its voxel
+// coordinates (bit 0: x, bit 1: y, bit 2: z), so moving to a neighbouring
+// cell keeps the shared corners in place and only the slots whose
+// coordinate changes are written out; slot indices stay compile-time
+// constants (the sums stay in registers).
+struct CornerSums {
+  int x[2], y[2], z[2];  // voxel coordinate held by the slots of each parity
+  float4 acc[8];
+};
+
+template <int SL>
+__device__ __forceinline__ void corner_flush(const DevScene& S, float* grad, CornerSums& cs) {
+  const int R = S.vol_res;
+  const int x = min(max(cs.x[SL & 1], 0), R - 1);
+  const int y = min(max(cs.y[(SL >> 1) & 1], 0), R - 1);
+  const int z = min(max(cs.z[SL >> 2], 0), R - 1);
+  float* gp = grad + 4 * (size_t)((z * R + y) * R + x);
+  const float4 v = cs.acc[SL];
+  if (v.x != 0.0f) unsafeAtomicAdd(gp + 0, v.x);
+  if (v.y != 0.0f) unsafeAtomicAdd(gp + 1, v.y);
+  if (v.z != 0.0f) unsafeAtomicAdd(gp + 2, v.z);
+  if (v.w != 0.0f) unsafeAtomicAdd(gp + 3, v.w);
+  cs.acc[SL] = make_float4(0.0f, 0.0f, 0.0f, 0.0f);
+}
+
+// Write out the slots whose coordinate along axis AX (0, 1, 2) changes for a
+// cell with base b on that axis.
+template <int AX>
+__device__ __forceinline__ void corner_move(const DevScene& S, float* grad, CornerSums& cs,
+                                            int b) {
+  int* co = AX == 0 ? cs.x : (AX == 1 ? cs.y : cs.z);
+#pragma unroll
+  for (int p = 0; p < 2; ++p) {
+    const int need = ((b & 1) == p) ? b : b + 1;
+    if (co[p] != need) {
+#pragma unroll
+      for (int sl = 0; sl < 8; ++sl) {
+        if (((sl >> AX) & 1) != p) continue;
+        switch (sl) {
+          case 0: corner_flush<0>(S, grad, cs); break;
+          case 1: corner_flush<1>(S, grad, cs); break;
+          case 2: corner_flush<2>(S, grad, cs); break;
+          case 3: corner_flush<3>(S, grad, cs); break;
+          case 4: corner_flush<4>(S, grad, cs); break;
+          case 5: corner_flush<5>(S, grad, cs); break;
+          case 6: corner_flush<6>(S, grad, cs); break;
+          default: corner_flush<7>(S, grad, cs); break;
+        }
+      }
+      co[p] = need;
+    }
+  }
+}
+
 // One pixel's replay of a volume slice (see k_vol_adjoint).
 __device__ __forceinline__ void vol_replay(const DevScene& S, const RepArgs& A,
                                            const RepSlice& sl, uint32_t pix, int px, int py,
@@ -1108,8 +1173,16 @@ __device__ __forceinline__ void vol_replay(const DevScene& S, const RepArgs& A,
   }
   const float sign = pair ? 1.0f : sl.sign;
   float T = 1.0f, Tb = 1.0f;
+  CornerSums cs;
+#pragma unroll
+  for (int q = 0; q < 8; ++q) cs.acc[q] = make_float4(0.0f, 0.0f, 0.0f, 0.0f);
+#pragma unroll
+  for (int p = 0; p < 2; ++p) cs.x[p] = cs.y[p] = cs.z[p] = INT_MIN;
   for (int k = 0; k < r.n; ++k) {
     const VolCell c = vol_cell(S, r.o + r.d * (r.t0 + ((float)k + r.us) * r.dt));
+    corner_move<0>(S, grad, cs, c.bx);
+    corner_move<1>(S, grad, cs, c.by);
+    corner_move<2>(S, grad, cs, c.bz);
     float g[4];
     {
       const float4 v = vol_fetch(pa, c);
@@ -1145,17 +1218,29 @@ __device__ __forceinline__ void vol_replay(const DevScene& S, const RepArgs& A,
 #pragma unroll
       for (int q = 0; q < 4; ++q) g[q] -= gb[q];
     }
+    // slot sl holds the cell's low corner on an axis when its parity there is
+    // the base's
+    const float wx0 = ((c.bx & 1) == 0) ? 1.0f - c.fx : c.fx;
+    const float wy0 = ((c.by & 1) == 0) ? 1.0f - c.fy : c.fy;
+    const float wz0 = ((c.bz & 1) == 0) ? 1.0f - c.fz : c.fz;
 #pragma unroll
-    for (int q = 0; q < 8; ++q) {
-      const float w = c.w(q) * sign;
-      float* gp = grad + 4 * (size_t)c.idx[q];
-#pragma unroll
-      for (int ch = 0; ch < 4; ++ch) {
-        const float val = w * g[ch];
-        if (val != 0.0f) unsafeAtomicAdd(gp + ch, val);
-      }
+    for (int sl = 0; sl < 8; ++sl) {
+      const float w = ((sl & 1) ? 1.0f - wx0 : wx0) * ((sl & 2) ? 1.0f - wy0 : wy0) *
+                      ((sl & 4) ? 1.0f - wz0 : wz0) * sign;
+      cs.acc[sl].x += w * g[0];
+      cs.acc[sl].y += w * g[1];
+      cs.acc[sl].z += w * g[2];
+      cs.acc[sl].w += w * g[3];
     }
   }
+  corner_flush<0>(S, grad, cs);
+  corner_flush<1>(S, grad, cs);
+  corner_flush<2>(S, grad, cs);
+  corner_flush<3>(S, grad, cs);
+  corner_flush<4>(S, grad, cs);
+  corner_flush<5>(S, grad, cs);
+  corner_flush<6>(S, grad, cs);
+  corner_flush<7>(S, grad, cs);
   n_samples = r.n;
 }
 
