@@ -495,8 +495,18 @@ def volume_workload(context, args):
                               "achieved_GBs": bytes_meta / (km / 1e3) / 1e9,
                               "peak_GBs": PEAK_HBM_GBS,
                               "frac": bytes_meta / (km / 1e3) / 1e9 / PEAK_HBM_GBS}
-    # equal wall-clock: the loss of a 16-spp evaluation render (off the clock)
+    del prob
+    torch.cuda.empty_cache()
+    # equal wall-clock on a smaller grid (the 256^3 step is too slow for many
+    # iterations in a bench run): the loss of a 16-spp evaluation render (off
+    # the clock) after the same GPU time
     if args.volume_ttl_seconds > 0:
+        R = args.volume_ttl_res
+        spec, gt, init = I.config_volume(res=R, view_w=R, view_h=R)
+        prob = Problem(spec, context=context)
+        target = prob.render(gt, seed=12345, iteration=0, tag=L.JSO_TAG_TARGET, spp=64)
+        prob.set_target(target)
+
         def eval_loss():
             img = prob.render(prob.get_params(), seed=777, iteration=0, tag=L.JSO_TAG_EVAL,
                               spp=16)
@@ -518,7 +528,10 @@ def volume_workload(context, args):
                 hist.append((it, clock, eval_loss()))
             return hist
 
-        ttl = {"seconds": args.volume_ttl_seconds, "initial_loss": eval_loss(), "runs": {}}
+        prob.set_params(init)
+        ttl = {"workload": "%d^3 volume, 8 views of %dx%d, same scene and initial volume" % (
+                   R, R, R),
+               "seconds": args.volume_ttl_seconds, "initial_loss": eval_loss(), "runs": {}}
         for name, mk in (("meta", lambda e: L.step_opts(optimizer=L.JSO_OPT_META, eta=e,
                                                          seed=args.seed + 2)),
                          ("adam2", lambda e: L.step_opts(optimizer=L.JSO_OPT_ADAM, eta=e,
@@ -526,7 +539,7 @@ def volume_workload(context, args):
                          ("adam4", lambda e: L.step_opts(optimizer=L.JSO_OPT_ADAM, eta=e,
                                                           adam_spp=4, seed=args.seed + 1))):
             best = None
-            for eta in (0.003, 0.01, 0.03):
+            for eta in (0.003, 0.01, 0.03, 0.1):
                 h = run(mk(eta), args.volume_ttl_seconds, 10)
                 row = {"eta": eta, "iterations": h[-1][0], "final_loss": h[-1][2],
                        "best_loss": min(x[2] for x in h),
@@ -535,9 +548,9 @@ def volume_workload(context, args):
                     best = row
             ttl["runs"][name] = best
         out["equal_time"] = ttl
+        del prob
+        torch.cuda.empty_cache()
     print("[bench] volume: %s" % json.dumps(out), file=sys.stderr, flush=True)
-    del prob
-    torch.cuda.empty_cache()
     return out
 
 
@@ -662,8 +675,10 @@ def main():
                          "(meta-estimator vs Adam at 32 and 64 spp; 0: skip)")
     ap.add_argument("--volume-steps", type=int, default=5,
                     help="timed calls per volume configuration (0 = skip the volume workload)")
-    ap.add_argument("--volume-ttl-seconds", type=float, default=5.0,
+    ap.add_argument("--volume-ttl-seconds", type=float, default=8.0,
                     help="GPU-seconds per run of the volume equal-time comparison (0: skip)")
+    ap.add_argument("--volume-ttl-res", type=int, default=128,
+                    help="voxels per side (and view size) of the equal-time comparison")
     ap.add_argument("--mesh-steps", type=int, default=10,
                     help="timed calls per mesh workload (0 = skip the mesh workloads)")
     args = ap.parse_args()
