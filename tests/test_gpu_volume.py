@@ -222,6 +222,51 @@ def test_volume_full_size_sampled(ctx):
     _check_grad(g.astype(np.float64), ref, ga, floor[0], "render_bwd", spec)
 
 
+def test_volume_edge_cases(ctx):
+    """A transparent volume shows the environment exactly and has no
+    gradient; 16 views (the maximum) with a ragged crop and an empty
+    crop; a one-voxel grid is a homogeneous medium (closed form per ray)."""
+    import torch
+    from paper_2309_15676_amd import _lib as L
+    _say("volume edge cases")
+    # density scale 0: every pixel is the environment, bit for bit
+    spec = I.scene_volume(6, 2, 12, 10, sigma=0.0)
+    prob = _problem(ctx, spec)
+    p = I.volume_blobs(spec, 2)
+    img = prob.render(p, seed=3, iteration=0, tag=L.JSO_TAG_EVAL, spp=1).cpu().numpy()
+    assert np.all(img == np.float32(spec.env[0]))
+    g = prob.render_bwd(p, torch.ones(spec.height, spec.width, 3), seed=3, iteration=0,
+                        tag=L.JSO_TAG_EVAL, spp=1).cpu().numpy()
+    assert np.all(g == 0.0)  # opacity 0 everywhere, and the density scale multiplies its gradient
+    # 16 views, ragged and empty crops against the oracle
+    spec = I.scene_volume(7, L.JSO_MAX_VIEWS, 13, 9, sigma=5.0)
+    prob = _problem(ctx, spec)
+    p = I.volume_blobs(spec, 4)
+    crop = (3, 17, 12, 131)
+    img = prob.render(p, seed=8, iteration=2, tag=L.JSO_TAG_EVAL, spp=1, crop=crop).cpu().numpy()
+    pd = p.astype(np.float64)
+    (ref, mg), floor = O.rounding_sensitivity(
+        spec, lambda: O.render(spec, pd, 8, 2, O.TAG_EVAL, 1, crop=crop)[0:2])
+    sl = (slice(crop[1], crop[3]), slice(crop[0], crop[2]))
+    _check_radiance(img[sl], ref[sl], mg[sl], floor[0][sl], max_unstable=MAX_UNSTABLE)
+    outside = np.ones(img.shape[:2], bool)
+    outside[sl] = False
+    assert np.all(img[outside] == 0.0)
+    empty = prob.render(p, seed=8, iteration=2, tag=L.JSO_TAG_EVAL, spp=1,
+                        crop=(5, 5, 5, 40)).cpu().numpy()
+    assert np.all(empty == 0.0)
+    # one voxel: C = e (1 - exp(-sigma l)) + env exp(-sigma l) on every ray, as
+    # the oracle also gives
+    spec = I.scene_volume(1, 3, 10, 8, sigma=2.0)
+    prob = _problem(ctx, spec)
+    p = np.array([0.7, 0.2, 0.5, 0.6], np.float32)
+    img = prob.render(p, seed=1, iteration=0, tag=L.JSO_TAG_EVAL, spp=1).cpu().numpy()
+    ref, mg = O.render(spec, p.astype(np.float64), 1, 0, O.TAG_EVAL, 1)
+    ok = mg > TAU
+    assert ok.mean() > 0.95
+    np.testing.assert_allclose(img[ok], ref[ok], rtol=2e-5, atol=1e-6)
+
+
 def test_volume_errors(ctx):
     import torch
     from paper_2309_15676_amd import _lib as L
@@ -238,3 +283,12 @@ def test_volume_errors(ctx):
         vol.render(p, seed=1, iteration=0, tag=L.JSO_TAG_EVAL, spp=1)
     with pytest.raises(RuntimeError, match="precondition|texture"):
         vol.precondition(torch.zeros(spec.n_params, device="cuda"), 1.0)
+    for bad in (dict(vol_views=L.JSO_MAX_VIEWS + 1, height=20 * (L.JSO_MAX_VIEWS + 1)),
+                dict(vol_res=L.JSO_MAX_VOL_RES + 1), dict(vol_res=0), dict(height=61),
+                dict(ch_mask=I.CH_ALL), dict(light_enabled=True), dict(vol_sigma=-1.0),
+                dict(vol_box=(0.0, 0.0, 0.0, 0.0))):
+        b = I.scene_volume(4, 3, 8, 20)
+        for k, v in bad.items():
+            setattr(b, k, v)
+        with pytest.raises(RuntimeError):
+            _problem(ctx, b)
