@@ -59,3 +59,51 @@ def test_create_without_gpu_reports_unsupported():
     rc = L.load().jso_create(ctypes.byref(ctx), 0, None)
     assert rc in (L.JSO_E_UNSUPPORTED, L.JSO_E_INVALID)
     assert not ctx.value
+
+
+def test_header_constants_match_the_binding():
+    with open(os.path.join(ROOT, "include", "jso.h")) as f:
+        src = f.read()
+    defs = dict(re.findall(r"^#define (JSO_\w+)\s+(-?\d+)\b", src, re.M))
+    shared = [k for k in defs if hasattr(L, k)]
+    assert len(shared) >= 40
+    for k in shared:
+        assert getattr(L, k) == int(defs[k]), k
+
+
+def _c_layout(struct, fields):
+    """sizeof and field offsets of a header struct, from the C compiler."""
+    import tempfile
+    body = "\n".join('  printf("%%zu\\n", offsetof(%s, %s));' % (struct, f) for f in fields)
+    prog = ('#include <stddef.h>\n#include <stdio.h>\n#include "jso.h"\nint main(void) {\n'
+            '  printf("%%zu\\n", sizeof(%s));\n%s\n  return 0;\n}\n' % (struct, body))
+    with tempfile.TemporaryDirectory() as d:
+        c, exe = os.path.join(d, "l.c"), os.path.join(d, "l")
+        with open(c, "w") as f:
+            f.write(prog)
+        subprocess.run(["gcc", "-I", os.path.join(ROOT, "include"), c, "-o", exe], check=True)
+        out = subprocess.run([exe], capture_output=True, text=True, check=True).stdout.split()
+    return int(out[0]), [int(x) for x in out[1:]]
+
+
+@pytest.mark.parametrize("struct", ["jso_scene_desc", "jso_render_opts", "jso_step_opts",
+                                    "jso_step_stats"])
+def test_ctypes_structs_match_the_c_layout(struct):
+    cls = getattr(L, struct)
+    names = [f[0] for f in cls._fields_]
+    size, offs = _c_layout(struct, names)
+    assert ctypes_size(cls) == size, struct
+    for name, off in zip(names, offs):
+        assert getattr(cls, name).offset == off, (struct, name)
+
+
+def ctypes_size(cls):
+    import ctypes
+    return ctypes.sizeof(cls)
+
+
+def test_bench_refuses_more_than_one_gpu():
+    r = subprocess.run(["python", os.path.join(ROOT, "bench.py"), "--gpus", "2"],
+                       capture_output=True, text=True, timeout=120)
+    assert r.returncode == 2
+    assert "one GPU" in r.stderr
