@@ -247,3 +247,44 @@ def test_fd_mode_is_validated(ctx):
         prob.estimate_gradients(seed=1, iteration=1, fd_mode=7)
     with pytest.raises(RuntimeError, match="fd_mode"):
         prob.grad_step(L.step_opts(fd_mode=-1))
+
+
+def test_shared_fd_full_size_sampled(ctx):
+    """The 512x512 workload (262,144 texel parameters) in the benchmark's
+    launch configuration with the shared-path pairs: 256 sampled pixels
+    against the oracle, the rest masked; and, unmasked, a finite sample that
+    vanishes for equal parameters."""
+    import torch
+    from paper_2309_15676_amd import _lib as L
+    _say("shared fd full size sampled")
+    spec, gt, init = I.config_textured()
+    p = gt
+    g = np.random.Generator(np.random.PCG64(21))
+    sel = g.choice(spec.n_pixels, 256, replace=False)
+    T = I.target_image_synthetic(spec, 6)
+    pp = np.clip(p + g.normal(0, 0.02, p.shape).astype(np.float32), 0.06, 0.99)
+    seed, it = 77, 3
+    keep = np.zeros(spec.n_pixels, bool)
+    keep[sel] = True
+    outside = (~keep).reshape(spec.height, spec.width).astype(np.uint8)
+    r0, f0 = _oracle_shared(spec, p, pp, T, seed, it, 0, outside)
+    bad = (r0["margin"] <= TAU) | O.ill_conditioned(r0, f0)
+    frac = (bad & (outside == 0)).sum() / 256
+    print("masked %.3f%% of the sample" % (100 * frac))
+    assert frac <= 0.1
+    mask = (outside | bad).astype(np.uint8)
+    ref, floor = _oracle_shared(spec, p, pp, T, seed, it, 0, mask)
+    prob = _problem(ctx, spec)
+    prob.set_target(T)
+    _set_pair(prob, p, pp, it)
+    r = prob.estimate_gradients(seed, it, 2, 1, mask=torch.from_numpy(mask.reshape(-1)).cuda(),
+                                fd_mode=L.JSO_FD_SHARED)
+    _check_grad(r["F"].cpu().numpy().astype(np.float64), ref["F"], ref["F_abs"], floor["F"], "F",
+                spec)
+    _check_grad(r["dF"].cpu().numpy().astype(np.float64), ref["dF"], ref["dF_abs"], floor["dF"],
+                "dF", spec)
+    assert np.count_nonzero(ref["dF"]) > 0
+    _set_pair(prob, p, p, 3)
+    r2 = prob.estimate_gradients(77, 3, 2, 1, fd_mode=L.JSO_FD_SHARED)
+    assert torch.isfinite(r2["F"]).all() and torch.count_nonzero(r2["F"]) > 0
+    assert torch.count_nonzero(r2["dF"]) == 0
