@@ -100,9 +100,22 @@ def cpu_baseline(spec, params, target, seconds: float, seed: int):
         if dt >= seconds or iters >= 1000:
             break
     paths = 4 * spec.n_pixels * iters - 2 * spec.n_pixels  # no FD pair at iteration 0
-    return dict(value=paths / dt, unit="differentiable paths/s", cores=threads, kind="oracle",
-                sample="first %d iterations of the 512x512 workload from the same initial "
-                       "texture (iteration 0 has no FD pair), %.1f s" % (iters, dt))
+    out = dict(value=paths / dt, unit="differentiable paths/s", cores=threads, kind="oracle",
+               sample="first %d iterations of the 512x512 workload from the same initial "
+                      "texture (iteration 0 has no FD pair), %.1f s" % (iters, dt))
+    # one thread, on a 64x64 crop at the image centre (a few seconds)
+    crop = (224, 224, 288, 288)
+    n = 0
+    t0 = time.perf_counter()
+    while time.perf_counter() - t0 < seconds / 4 and n < 200:
+        O.gradient_pair(spec, params.astype(np.float64), params.astype(np.float64), target,
+                        seed, 1 + n, crop=crop, nthreads=1)
+        n += 1
+    dt1 = time.perf_counter() - t0
+    out["single_thread"] = dict(value=4 * 64 * 64 * n / dt1, unit="differentiable paths/s",
+                                sample="%d iterations' gradient samples (prop + FD pair) on the "
+                                       "central 64x64 crop, %.1f s" % (n, dt1))
+    return out
 
 
 def copy_calibration(mib: int):
