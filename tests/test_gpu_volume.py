@@ -267,6 +267,40 @@ def test_volume_edge_cases(ctx):
     np.testing.assert_allclose(img[ok], ref[ok], rtol=2e-5, atol=1e-6)
 
 
+def test_volume_batch_and_options_match_grad_step(ctx):
+    """Two volume problems of different sizes in one captured-graph batch take
+    the same steps as grad_step over both; the shared-path finite differences
+    and the uncorrelated-variance ablation run on volumes too."""
+    from paper_2309_15676_amd import _lib as L
+    from paper_2309_15676_amd.problem import Batch, grad_step_many
+    from test_gpu_batch import _close_states
+    _say("volume batch")
+
+    def make():
+        out = []
+        for res, views, w, h in ((6, 2, 12, 10), (9, 3, 14, 8)):
+            spec, gt, init = _small(res, views, w, h)
+            p = _problem(ctx, spec)
+            p.set_target(p.render(gt, seed=9, iteration=0, tag=L.JSO_TAG_TARGET, spp=8))
+            p.set_params(init)
+            out.append(p)
+        return out
+
+    for opts in (L.step_opts(eta=0.02, seed=5),
+                 L.step_opts(eta=0.02, seed=5, fd_mode=L.JSO_FD_SHARED),
+                 L.step_opts(eta=0.02, seed=5, ablate=L.JSO_ABLATE_UNCORRELATED)):
+        batched, ref = make(), make()
+        b = Batch(batched, opts, max_iters=[0, 0], use_graph=True)
+        for it in range(3):
+            b.step(1)
+            grad_step_many(ref, opts)
+            for k, p in enumerate(batched):
+                st = p.get_state()
+                assert np.all(np.isfinite(st["params"]))
+                _close_states(st, ref[k].get_state(), "problem %d after %d" % (k, it + 1))
+        b.close()
+
+
 def test_volume_errors(ctx):
     import torch
     from paper_2309_15676_amd import _lib as L
