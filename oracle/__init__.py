@@ -7,7 +7,9 @@ the GPU library and shares no code with it.
 
 Contents
   liboracle.so (oracle.cpp):  Philox4x32-10 / SplitMix64, FP64 path tracer,
-      proportional gradient sample <F_i> (Eq. 2) with a tape-based adjoint.
+      proportional gradient sample <F_i> (Eq. 2) with a tape-based adjoint,
+      the shared-path variant of Eq. 5 (paths drawn at other parameters) and
+      an emission-absorption voxel volume.
   meta.py:  Moment2 variance EMAs (Eq. 9, 13-14), the meta-estimator
       (Eq. 7-8, 15, 17), its stabilised step (Eq. 21) and plain Adam
       (Eq. 18-20), plus the exponential-rate toy of Figure 2.

@@ -17,6 +17,12 @@
  *     for an L2 image loss, with the derivative taken by recording each
  *     path's vertices on an explicit tape and sweeping it backward (reverse
  *     mode with detached sampling densities and MIS weights);
+ *   - the same estimators with the paths drawn at other parameters than the
+ *     integrand is evaluated at (the previous-parameter half of Eq. 5's
+ *     finite-difference sample);
+ *   - an emission-absorption voxel volume (the volume experiment of the
+ *     Experiments section): a ray-marched quadrature and its adjoint by a
+ *     backward sweep over the recorded samples;
  *   - per-pixel decision margins used to exclude paths whose discrete
  *     choices are too close to call for an FP32 vs FP64 comparison.
  * The meta-estimator and optimiser (Sections 4-5, supplement pseudocode) live
