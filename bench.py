@@ -189,6 +189,8 @@ def time_to_loss(prob, init, gt, target, args, iters: int, label: str, lam: floa
         o = L.step_opts(optimizer=L.JSO_OPT_ADAM, eta=eta, adam_spp=64, seed=args.seed + 1,
                         precond_lambda=lam)
         adam[eta] = run(o, iters, every)
+        print("[bench]   %s: adam eta %g best %.4g" % (label[:24], eta, min(h[2] for h in adam[eta])),
+              file=sys.stderr, flush=True)
     best_eta = min(adam, key=lambda e: min(h[2] for h in adam[e]))
     ha = adam[best_eta]
     target_loss = min(h[2] for h in ha)
@@ -201,6 +203,9 @@ def time_to_loss(prob, init, gt, target, args, iters: int, label: str, lam: floa
                             spp_prop=2, spp_fd=1, seed=args.seed + 2, precond_lambda=lam,
                             fd_mode=mode)
             runs[name][eta] = run(o, 10 ** 9, every * 4, seconds=META_BUDGET * budget_s)
+            print("[bench]   %s: %s eta %g best %.4g" % (
+                label[:24], name, eta, min(h[2] for h in runs[name][eta])), file=sys.stderr,
+                flush=True)
 
     def time_to(hists, level):
         """(seconds, iterations, eta) of the learning rate that reaches `level`
@@ -352,6 +357,9 @@ def large_time_to_rmse(context, args):
             clock += e0.elapsed_time(e1) / 1e3
             it += chunk
             hist.append((it, clock, rmse()))
+            if it % (50 * chunk) == 0:
+                print("[bench]   large problem %s: %d iterations, %.1f s, rmse %.4g" % (
+                    name, it, clock, hist[-1][2]), file=sys.stderr, flush=True)
         reach = {"%.4g" % lv: next((h[1] for h in hist if h[2] <= lv), None) for lv in levels}
         runs[name] = {"seconds_to_rmse": reach, "final_rmse": hist[-1][2],
                       "iterations": it, "seconds": clock,
@@ -554,6 +562,8 @@ def volume_workload(context, args):
             best = None
             for eta in (0.003, 0.01, 0.03, 0.1):
                 h = run(mk(eta), args.volume_ttl_seconds, 10)
+                print("[bench]   volume equal time: %s eta %g best %.4g after %d iterations" % (
+                    name, eta, min(x[2] for x in h), h[-1][0]), file=sys.stderr, flush=True)
                 row = {"eta": eta, "iterations": h[-1][0], "final_loss": h[-1][2],
                        "best_loss": min(x[2] for x in h),
                        "loss_curve": [(x[0], round(x[1], 4), x[2]) for x in h[:: max(len(h) // 8, 1)]]}
