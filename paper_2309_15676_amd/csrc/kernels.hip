@@ -888,12 +888,12 @@ __device__ __forceinline__ void adjoint_tile_shared(const RepArgs& A,
 // Dynamic LDS: with kMesh, `stack` traversal-stack entries per lane first
 // (the LDS part of the stack), then the gradient table / exchange buffer.
 // kShared: the launch's pair slices are shared-path pairs (no replay pairs).
-// Without replay pairs or traversal the kernel fits 128 VGPRs without
-// spilling, so it runs at 4 waves per SIMD; the others keep 3 (forcing 4
-// spills and is no faster).
+// Without replay pairs the kernel fits 128 VGPRs (no spill without traversal,
+// a few dwords with it), so it runs at 4 waves per SIMD; the replay-pair
+// kernels keep 3 (forcing 4 spills and is no faster overall).
 template <int TW, int TH, bool kMesh, bool kShared>
 __global__ void __launch_bounds__(TW * TH)
-__attribute__((amdgpu_waves_per_eu(kShared && !kMesh ? 4 : 3)))
+__attribute__((amdgpu_waves_per_eu(kShared ? 4 : 3)))
 k_adjoint(const RepArgs* __restrict__ Units, int n_units, int stack, unsigned long long* work) {
   using SH = Shape<TW, TH>;
   extern __shared__ uint32_t s_dyn[];
