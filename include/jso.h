@@ -242,7 +242,7 @@ int jso_synchronize(jso_ctx* ctx);
 /* Default test-mode flags OR-ed into every render of this context. */
 int jso_set_debug(jso_ctx* ctx, uint32_t flags);
 
-/* ---- counter-based random numbers (row a1) ------------------------------- */
+/* ---- counter-based random numbers ------------------------------- */
 
 /* 64-bit Philox key of a stream: splitmix64(seed ^ splitmix64((iteration << 8) | tag)),
  * with SplitMix64 of Steele, Lea and Flood (2014).  Pure function. */
@@ -253,17 +253,29 @@ int jso_philox(jso_ctx* ctx, uint64_t key, const uint32_t* ctr, size_t n, uint32
 
 /* ---- scenes / problems ---------------------------------------------------- */
 
-/* Upload a scene; allocates its parameter, target, gradient and optimiser
- * buffers on the device.  Parameters start at fixed_default / 0.5. */
+/* Upload a scene: everything of the inverse problem except its parameters
+ * (Introduction: inverse rendering estimates the scene parameters --
+ * materials, textures -- from a target image, with the rest of the scene
+ * given).  Builds the mesh's hierarchy on the host, allocates the problem's
+ * parameter, target, gradient and optimiser buffers on the device.
+ * Parameters start at fixed_default / 0.5.  desc and its arrays are host
+ * memory owned by the caller and copied before return.  Errors:
+ * JSO_E_INVALID (sizes out of range, null arrays), JSO_E_OOM, JSO_E_HIP. */
 int jso_load_scene(jso_ctx* ctx, const jso_scene_desc* desc, int* scene_id);
 int jso_free_scene(jso_ctx* ctx, int scene_id);
 int jso_scene_info(jso_ctx* ctx, int scene_id, size_t* n_params, int* width, int* height);
-/* Set pi (n = n_params).  Also sets pi_{i-1} = pi and resets the optimiser
- * state (iteration 0, Moment2 counts 0, alpha_{-1} = -inf, Adam moments 0). */
+/* Set the parameter vector pi (Section 3's notation: F_i integrates f(x, pi_i);
+ * n = n_params, float32, layout above; mem = JSO_MEM_HOST or _DEVICE).
+ * Starts the optimisation loop of Sections 4-5 afresh: pi_{i-1} = pi,
+ * iteration 0, both variance averages empty, alpha_{-1} = -inf (so alpha_0 = 0,
+ * Eq. 7's initialisation), Adam moments 0.  Errors: JSO_E_INVALID (bad id,
+ * null p, n != n_params), JSO_E_HIP. */
 int jso_set_params(jso_ctx* ctx, int scene_id, const float* p, size_t n, int mem);
 int jso_get_params(jso_ctx* ctx, int scene_id, float* p, size_t n, int mem);
 int jso_get_params_prev(jso_ctx* ctx, int scene_id, float* p, size_t n, int mem);
-/* Target image (n = H*W*3). */
+/* The target image the loss compares each rendering with (Introduction:
+ * the loss quantifies the disparity between the image rendered with the
+ * current parameters and the target).  n = H*W*3 float32; mem as above. */
 int jso_set_target(jso_ctx* ctx, int scene_id, const float* img, size_t n, int mem);
 
 /* Texture-gradient preconditioner (Large Steps; Nicolet, Jacobson, Jakob 2021,
@@ -275,15 +287,20 @@ int jso_set_target(jso_ctx* ctx, int scene_id, const float* img, size_t n, int m
  * Errors: JSO_E_INVALID (bad id, null g, lambda < 0, per-vertex layout). */
 int jso_precondition(jso_ctx* ctx, int scene_id, float* g, float lambda);
 
-/* ---- rendering and differentiation (rows a2-a6) ---------------------------- */
+/* ---- rendering and differentiation ---------------------------- */
 
-/* Primal render: img (dev, H*W*3) = mean of spp paths per pixel with the
+/* Forward rendering by path tracing (Introduction: the rendering equation
+ * estimated by Monte Carlo for given scene parameters; Related work, path
+ * tracing): img (dev, H*W*3) = mean of spp paths per pixel with the
  * parameters `params` (dev, n_params), stream (seed, iteration, tag).
  * Pixels outside the crop or masked are left untouched.  opts may be NULL. */
 int jso_render(jso_ctx* ctx, int scene_id, const float* params, uint64_t seed,
                uint32_t iteration, uint32_t tag, int spp, const jso_render_opts* opts,
                float* img);
-/* Replayed adjoint of jso_render: dparams (dev, n_params) += sum over pixels p
+/* Path replay backpropagation (Related work; Experiments, implementation):
+ * the derivative of jso_render's image with respect to the scene
+ * parameters, backpropagated from an adjoint image (Introduction: gradients
+ * w.r.t. the scene parameters from the loss).  dparams (dev, n_params) += sum over pixels p
  * of dimg_p . d(mean_s C_ps)/dparams, with C_ps re-traced from the same stream
  * (no tape).  The derivative treats sampling densities and MIS weights as
  * constants (detached sampling).  dparams is accumulated into, not cleared. */
@@ -291,7 +308,7 @@ int jso_render_bwd(jso_ctx* ctx, int scene_id, const float* params, uint64_t see
                    uint32_t iteration, uint32_t tag, int spp, const float* dimg,
                    const jso_render_opts* opts, float* dparams);
 
-/* ---- estimators (rows a5-a7) ------------------------------------------------ */
+/* ---- estimators ------------------------------------------------ */
 
 /* One iteration's gradient samples for the loss opts->loss (L2 by default,
  * sum (I - T)^2 / (3 W H)) against the scene's target, at the scene's pi_i
@@ -310,7 +327,7 @@ int jso_estimate_gradients(jso_ctx* ctx, int scene_id, uint64_t seed, uint32_t i
                            int spp_prop, int spp_fd, const jso_render_opts* opts, float* F,
                            float* dF, float* img, double* loss);
 
-/* ---- optimiser steps (rows a8, a9) ------------------------------------------- */
+/* ---- optimiser steps ------------------------------------------- */
 
 /* One meta-estimator step on given gradient samples (dev, n_params each):
  * Moment2 updates of Var[F] and Var[dF]_D (Eq. 9, 13; bias-corrected), the
@@ -325,12 +342,16 @@ int jso_meta_step(jso_ctx* ctx, int scene_id, const float* F, const float* dF, f
 int jso_adam_step(jso_ctx* ctx, int scene_id, const float* g, float eta, float beta1,
                   float beta2, float eps);
 
-/* One full iteration for each listed problem (the hot path): estimators into
- * the scene's own gradient buffers, then the fused optimiser step, which also
- * clears those buffers for the next iteration.  All listed problems share one
- * launch per kernel (Section 5's loop, run for many independent problems at
- * once); scene ids must be distinct.  stats (host array of n, nullable) waits
- * for the stream and reports each problem's loss and step. */
+/* One iteration of the optimisation loop (supplement, loop snippet;
+ * Sections 3-5): the proportional sample <F_i> (Eq. 2), the finite-difference
+ * sample <dF_i> (Eq. 5), then jso_meta_step's update, for each listed
+ * problem -- or Adam's step (Eq. 18-20) on one sample of opts->adam_spp.
+ * The samples go into the scene's own gradient buffers, then the fused
+ * optimiser step, which also clears those buffers for the next iteration.
+ * All listed problems share one launch per kernel (Section 5's loop, run for
+ * many independent problems at once); scene ids must be distinct.  stats
+ * (host array of n, nullable) waits for the stream and reports each
+ * problem's loss and step. */
 int jso_grad_step(jso_ctx* ctx, const int* scene_ids, int n, const jso_step_opts* opts,
                   jso_step_stats* stats);
 
@@ -408,6 +429,15 @@ int jso_set_work_counting(jso_ctx* ctx, int enable);
 int jso_get_work(jso_ctx* ctx, uint64_t out[4], int reset);
 
 /* ---- checkpoint ---------------------------------------------------------------- */
+/* The state the optimisation loop carries from iteration i to i + 1
+ * (Sections 4-5, supplement pseudocode): pi_i, pi_{i-1}, <F_{i-1}>_M and
+ * Var[F_{i-1}]_M (Eq. 7, 15), alpha_{i-1} (Eq. 17), the two variance
+ * averages (Eq. 9, 13) with their sample counts, ||dpi_i||^2 (Eq. 14), Adam's
+ * moments.  jso_get_state waits for the stream and copies every buffer of
+ * the view (host arrays of n_params each, caller-owned; none may be NULL) and
+ * the counters; jso_set_state uploads them, so that the next jso_grad_step
+ * continues exactly as the checkpointed run would have.  Errors:
+ * JSO_E_INVALID (bad id, null buffer), JSO_E_HIP. */
 int jso_get_state(jso_ctx* ctx, int scene_id, jso_state* st);
 int jso_set_state(jso_ctx* ctx, int scene_id, const jso_state* st);
 

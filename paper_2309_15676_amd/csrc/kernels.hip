@@ -1356,7 +1356,9 @@ __global__ void __launch_bounds__(kMetaBlock) k_meta(const MetaArgs* __restrict_
       // carry the previous estimate forward, weight (Eq. 8, 17), combine (Eq. 7, 15)
       double mu = mean[e] + df;
       double v = var[e] + varD;
-      double a = varF / (varF + v + 1e-30);
+      // Eq. 8; a parameter with every variance zero (untouched so far) gets alpha = 0
+      const double den = varF + v;
+      double a = den > 0.0 ? varF / den : 0.0;
       if (clip)
         a = fmin(a, 1.0 / (2.0 - ap[e]));
       else if (isinf(ap[e]))
@@ -1423,11 +1425,19 @@ __global__ void __launch_bounds__(kMetaBlock) k_meta(const MetaArgs* __restrict_
 // ---------------------------------------------------------------------------
 __global__ void __launch_bounds__(kMetaBlock) k_adam(const AdamArgs* __restrict__ Units,
                                                      int n_units) {
+  __shared__ uint32_t s_it, s_t;
   const AdamArgs& A = unit_of(Units, n_units);
   Ctl* ctl = G(A.ctl);
-  if (A.h.max_iter && ctl->iteration >= A.h.max_iter) return;  // finished problem
+  // one read of the iteration state per block: the last block advances it
+  // once every block has signalled, and every wave must have read it by then
+  if (threadIdx.x == 0) {
+    s_it = ctl->iteration;
+    s_t = ctl->adam_t;
+  }
+  __syncthreads();
+  if (A.h.max_iter && s_it >= A.h.max_iter) return;  // finished problem (block-uniform)
   const uint32_t lb = blockIdx.x - A.h.block0, nb = A.nblocks;
-  const uint32_t t = ctl->adam_t + 1u;
+  const uint32_t t = s_t + 1u;
   const float bc1 = (float)(1.0 - pow((double)A.beta1, (double)t));
   const float bc2 = (float)(1.0 - pow((double)A.beta2, (double)t));
   const size_t stride = (size_t)nb * kMetaBlock;
@@ -1445,14 +1455,15 @@ __global__ void __launch_bounds__(kMetaBlock) k_adam(const AdamArgs* __restrict_
     G(A.params)[i] = pn;
     if (A.zero_grads) G(A.g)[i] = 0.0f;
   }
+  __syncthreads();  // every wave of the block is done before it signals
   if (threadIdx.x == 0) {
     __threadfence();
     const uint32_t done = atomicAdd(&ctl->blocks_done, 1u);
     if (done == nb - 1u) {
       __threadfence();
       ctl->adam_t = t;
-      ctl->iteration = ctl->iteration + 1u;
-      ctl->loss[ctl->iteration & 1u] = 0.0;
+      ctl->iteration = s_it + 1u;
+      ctl->loss[(s_it + 1u) & 1u] = 0.0;
       ctl->blocks_done = 0u;
       __threadfence();
     }

@@ -322,9 +322,9 @@ def test_meta_step_parity(ctx):
         st = prob.get_state()
         ref.step(F.astype(np.float64), dF.astype(np.float64) if i >= 1 else None)
         assert st["iteration"] == i + 1
-        assert st["count_F"] == ref.var_F.count and st["count_D"] == ref.var_D.count
-        for k, r in (("mean", ref.meta.mean), ("var", ref.meta.var), ("m2_F", ref.var_F.m2),
-                     ("m2_D", ref.var_D.m2), ("alpha_prev", ref.meta.alpha_prev)):
+        assert st["count_F"] == ref.var_F.n and st["count_D"] == ref.var_D.n
+        for k, r in (("mean", ref.meta.F_M), ("var", ref.meta.V_M), ("m2_F", ref.var_F.estimate),
+                     ("m2_D", ref.var_D.estimate), ("alpha_prev", ref.meta.alpha_last)):
             np.testing.assert_allclose(st[k], r, rtol=1e-12, atol=1e-14 * np.abs(r).max(),
                                        err_msg="%s at iteration %d" % (k, i))
         np.testing.assert_array_max_ulp(st["params"], ref.params, maxulp=1)

@@ -47,46 +47,46 @@ def test_relative_loss_weights_each_pixel_by_its_target():
 
 
 def test_centred_moment_closed_forms():
-    m = OM.Moment2((2,), 0.9, centred=True)
-    m.step(np.array([3.0, -0.25]))
-    np.testing.assert_allclose(m.var, [0.0, 0.0], atol=1e-15)  # one sample: no spread
+    m = OM.DecayedMoment((2,), 0.9, centred=True)
+    m.push(np.array([3.0, -0.25]))
+    np.testing.assert_allclose(m.estimate, [0.0, 0.0], atol=1e-15)  # one sample: no spread
     for _ in range(5):
-        m.step(np.array([3.0, -0.25]))
-    np.testing.assert_allclose(m.var, [0.0, 0.0], atol=1e-12)  # constant samples
+        m.push(np.array([3.0, -0.25]))
+    np.testing.assert_allclose(m.estimate, [0.0, 0.0], atol=1e-12)  # constant samples
     # two samples +a, -a with start-up-corrected weights beta/(1+beta), 1/(1+beta)
     b, a = 0.8, 1.5
-    m = OM.Moment2((1,), b, centred=True)
-    m.step(np.array([a]))
-    m.step(np.array([-a]))
+    m = OM.DecayedMoment((1,), b, centred=True)
+    m.push(np.array([a]))
+    m.push(np.array([-a]))
     mean = (b * a - a) / (1 + b)
-    np.testing.assert_allclose(m.var, [a * a - mean * mean], rtol=1e-13)
-    z = OM.Moment2((1,), b)  # zero-centred: the plain second moment
-    z.step(np.array([a]))
-    z.step(np.array([-a]))
-    np.testing.assert_allclose(z.var, [a * a], rtol=1e-13)
+    np.testing.assert_allclose(m.estimate, [a * a - mean * mean], rtol=1e-13)
+    z = OM.DecayedMoment((1,), b)  # zero-centred: the plain second moment
+    z.push(np.array([a]))
+    z.push(np.array([-a]))
+    np.testing.assert_allclose(z.estimate, [a * a], rtol=1e-13)
 
 
 def test_no_alpha_clip_keeps_the_unclipped_weight():
     F = np.array([1.0, -2.0, 0.5])
-    clipped = OM.Meta((3,), 0.1)
-    free = OM.Meta((3,), 0.1, clip=False)
+    clipped = OM.MetaEstimate((3,))
+    free = OM.MetaEstimate((3,), clip=False)
     vF = F * F
     for m in (clipped, free):
-        m.step(F, np.zeros(3), vF, np.zeros(3))
+        m.update(F, np.zeros(3), vF, np.zeros(3))
         # Eq. 7's initialisation holds with or without the clip: alpha_0 = 0
-        np.testing.assert_array_equal(m.alpha, 0.0)
-        np.testing.assert_allclose(m.mean, F, rtol=1e-15)
+        np.testing.assert_array_equal(m.alpha_last, 0.0)
+        np.testing.assert_allclose(m.F_M, F, rtol=1e-15)
     # second step with a small carried variance: Eq. 8 gives
     # Var[F] / (Var[F] + Var_M + Var[dF]); the clip of Eq. 17 caps it at
     # 1 / (2 - alpha_0) = 1/2
     vF2 = 4.0 * vF
     dF, vdF = np.zeros(3), 0.01 * vF
-    clipped.step(F, dF, vF2, vdF)
-    free.step(F, dF, vF2, vdF)
+    clipped.update(F, dF, vF2, vdF)
+    free.update(F, dF, vF2, vdF)
     want = vF2 / (vF2 + vF + vdF)
-    np.testing.assert_allclose(free.alpha, want, rtol=1e-12)
-    np.testing.assert_allclose(clipped.alpha, np.minimum(want, 0.5), rtol=1e-12)
-    assert np.all(free.alpha > 0.5)
+    np.testing.assert_allclose(free.alpha_last, want, rtol=1e-12)
+    np.testing.assert_allclose(clipped.alpha_last, np.minimum(want, 0.5), rtol=1e-12)
+    assert np.all(free.alpha_last > 0.5)
 
 
 def test_sample_reuse_ablation_plumbing():
@@ -100,10 +100,10 @@ def test_sample_reuse_ablation_plumbing():
         a.step(F, dF)
         b.step(F, dF, F_var=F, dF_var=dF)  # the same samples: identical
     np.testing.assert_array_equal(a.params, b.params)
-    np.testing.assert_array_equal(a.meta.mean, b.meta.mean)
+    np.testing.assert_array_equal(a.meta.F_M, b.meta.F_M)
     # variance samples of zero: Var[F] = 0, so alpha = 0 and the estimate is <F_i>
     c = OM.MetaOptimizer(p0, lo, hi, 0.01)
     for _ in range(3):
         F, dF = g.normal(size=4), 0.1 * g.normal(size=4)
         c.step(F, dF, F_var=np.zeros(4), dF_var=np.zeros(4))
-        np.testing.assert_allclose(c.meta.mean, F, rtol=1e-12)
+        np.testing.assert_allclose(c.meta.F_M, F, rtol=1e-12)
