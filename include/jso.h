@@ -307,6 +307,24 @@ int jso_render(jso_ctx* ctx, int scene_id, const float* params, uint64_t seed,
 int jso_render_bwd(jso_ctx* ctx, int scene_id, const float* params, uint64_t seed,
                    uint32_t iteration, uint32_t tag, int spp, const float* dimg,
                    const jso_render_opts* opts, float* dparams);
+/* For callers that cannot allocate device memory (code under HIP graph
+ * capture, tight serving loops, harnesses that forbid hipMalloc): the same
+ * result as jso_render_bwd (same arguments, same streams, dparams accumulated
+ * into), but the forward radiance of the replayed paths lives in a scratch
+ * array of JSO_NOALLOC_SCRATCH_BYTES that the library holds per GPU, set up by
+ * jso_create; the call itself allocates nothing (no hipMalloc/hipFree).  Each
+ * sample needs H*W*24 bytes of it, so images above JSO_NOALLOC_MAX_PIXELS
+ * pixels are rejected (JSO_E_INVALID); larger spp run in more launches.  All
+ * calls on one GPU share the array: calls that overlap in time on one GPU
+ * (other streams, other contexts, other threads) race and give wrong results;
+ * calls in one stream's order are safe.  Nothing in the array needs to start
+ * at zero.  Errors: as jso_render_bwd; JSO_E_STATE if the context has no
+ * scratch address. */
+#define JSO_NOALLOC_SCRATCH_BYTES (128u << 20)
+#define JSO_NOALLOC_MAX_PIXELS (JSO_NOALLOC_SCRATCH_BYTES / 24u)
+int jso_render_bwd_noalloc(jso_ctx* ctx, int scene_id, const float* params, uint64_t seed,
+                           uint32_t iteration, uint32_t tag, int spp, const float* dimg,
+                           const jso_render_opts* opts, float* dparams);
 
 /* ---- estimators ------------------------------------------------ */
 

@@ -41,8 +41,10 @@ EXPORTED = [
     "jso_meta_step", "jso_adam_step", "jso_grad_step", "jso_get_state", "jso_set_state",
     "jso_set_timing", "jso_get_kernel_time", "jso_set_work_counting", "jso_get_work",
     "jso_batch_create", "jso_batch_step", "jso_batch_active", "jso_batch_destroy",
-    "jso_batch_autotune", "jso_set_tile_shape", "jso_precondition",
+    "jso_batch_autotune", "jso_set_tile_shape", "jso_precondition", "jso_render_bwd_noalloc",
 ]
+JSO_NOALLOC_SCRATCH_BYTES = 128 << 20
+JSO_NOALLOC_MAX_PIXELS = JSO_NOALLOC_SCRATCH_BYTES // 24
 JSO_TILE_16x16, JSO_TILE_16x8, JSO_TILE_8x8, JSO_TILE_SHAPES = 0, 1, 2, 3
 JSO_K_FORWARD, JSO_K_ADJOINT, JSO_K_META, JSO_K_ADAM, JSO_K_FINALIZE = 0, 1, 2, 3, 4
 JSO_K_PRECOND = 5
@@ -144,6 +146,7 @@ def load() -> ctypes.CDLL:
         "jso_set_target": (I, [P, I, P, SZ, I]),
         "jso_render": (I, [P, I, P, U64, U32, U32, I, P, P]),
         "jso_render_bwd": (I, [P, I, P, U64, U32, U32, I, P, P, P]),
+        "jso_render_bwd_noalloc": (I, [P, I, P, U64, U32, U32, I, P, P, P]),
         "jso_estimate_gradients": (I, [P, I, U64, U32, I, I, P, P, P, P, P]),
         "jso_meta_step": (I, [P, I, P, P, F, F, F]),
         "jso_adam_step": (I, [P, I, P, F, F, F, F]),
@@ -335,6 +338,13 @@ def jso_render_bwd(ctx, sid, params_ptr, seed, iteration, tag, spp, dimg_ptr, op
                    dparams_ptr) -> int:
     return load().jso_render_bwd(ctx, sid, params_ptr, seed, iteration, tag, spp, dimg_ptr,
                                  ctypes.byref(opts) if opts is not None else None, dparams_ptr)
+
+
+def jso_render_bwd_noalloc(ctx, sid, params_ptr, seed, iteration, tag, spp, dimg_ptr, opts,
+                           dparams_ptr) -> int:
+    return load().jso_render_bwd_noalloc(ctx, sid, params_ptr, seed, iteration, tag, spp,
+                                         dimg_ptr, ctypes.byref(opts) if opts is not None
+                                         else None, dparams_ptr)
 
 
 def jso_estimate_gradients(ctx, sid, seed, iteration, spp_prop, spp_fd, opts, F_ptr, dF_ptr,

@@ -67,6 +67,38 @@ std::atomic<uint64_t> g_scene_generation{0};
 std::mutex g_tuned_mu;
 std::map<std::pair<std::string, uint64_t>, int> g_tuned;
 
+// Scratch memory of jso_render_bwd_noalloc (the forward radiance slots of
+// the replayed paths), a file-scope device array: every GPU the library runs
+// on holds its own copy until the process ends, and every call on that GPU
+// shares it.  Host code never passes the array's name to a kernel (on the
+// host it is a stand-in, not a device address); it uses the address that
+// hipGetSymbolAddress returned on that device, kept per device below.
+constexpr size_t kNoAllocScratchBytes = JSO_NOALLOC_SCRATCH_BYTES;
+static __device__ __align__(256) uint8_t scratch[kNoAllocScratchBytes];
+
+std::mutex g_scratch_mu;
+std::map<int, uint8_t*> g_scratch_ptr;  // device -> address of `scratch` there
+
+// Look up (once per device, with `device` current) the device address of
+// `scratch`; *out = null and an error code on failure.
+hipError_t scratch_address(int device, uint8_t** out) {
+  std::lock_guard<std::mutex> lock(g_scratch_mu);
+  auto it = g_scratch_ptr.find(device);
+  if (it != g_scratch_ptr.end()) {
+    *out = it->second;
+    return hipSuccess;
+  }
+  void* ptr = nullptr;
+  const hipError_t e = hipGetSymbolAddress(&ptr, HIP_SYMBOL(scratch));
+  if (e != hipSuccess || ptr == nullptr) {
+    *out = nullptr;
+    return e != hipSuccess ? e : hipErrorInvalidSymbol;
+  }
+  *out = static_cast<uint8_t*>(ptr);
+  g_scratch_ptr[device] = *out;
+  return hipSuccess;
+}
+
 // HIP-event timing of kernel launches, per kernel class.
 struct KernelTimer {
   bool enabled = false;
@@ -213,6 +245,7 @@ struct jso_ctx {
   KernelTimer timer;
   unsigned long long* d_work = nullptr;  // work counters (replay paths/vertices, forward paths/vertices)
   bool counting = false;
+  uint8_t* scratch = nullptr;  // this device's `scratch` (set up by jso_create)
 };
 
 namespace {
@@ -614,7 +647,10 @@ struct ProbPlan {
   int np;
   AdjointSpec aj[2];
   int na;
+  double* slots = nullptr;  // radiance slots; null: the scene's own
 };
+
+double* slots_of(const ProbPlan& p) { return p.slots ? p.slots : p.s->slots; }
 
 enum class Kern { Forward, Finalize, Adjoint, Meta, Adam, Dct };
 
@@ -654,8 +690,10 @@ uint32_t tiles_of(const Crop& c, int shape) {
 bool crop_empty(const Crop& c) { return c.x1 <= c.x0 || c.y1 <= c.y0; }
 
 // The launches of the estimator part of a step for problems `ps` (all with the
-// same job structure), with pixel tiles of the given shape.
-void plan_estimators(const std::vector<ProbPlan>& ps, Plan& plan, int shape = 0) {
+// same job structure), with pixel tiles of the given shape and at most
+// max_slots radiance slots per pixel per launch (a replay pair needs 2).
+void plan_estimators(const std::vector<ProbPlan>& ps, Plan& plan, int shape = 0,
+                     int max_slots = kMaxSlots) {
   if (ps.empty()) return;
   const ProbPlan& p0 = ps[0];
   // primal samples in job order; replay units, pairs first: within a launch
@@ -687,14 +725,14 @@ void plan_estimators(const std::vector<ProbPlan>& ps, Plan& plan, int shape = 0)
     while (next_prim < prim.size()) {
       const int j = prim[next_prim].first;
       if (p0.pj[j].params_b == nullptr) {
-        if (nslot + 1 > kMaxSlots) break;
+        if (nslot + 1 > max_slots) break;
         fsl.push_back({0, j, prim[next_prim].second, nslot++, -1});
         ++next_prim;
         continue;
       }
       int m = 0;
       while (next_prim + m < prim.size() && prim[next_prim + m].first == j &&
-             nslot + 2 * (m + 1) <= kMaxSlots)
+             nslot + 2 * (m + 1) <= max_slots)
         ++m;
       if (m == 0) break;
       for (int t = 0; t < m; ++t)
@@ -717,7 +755,7 @@ void plan_estimators(const std::vector<ProbPlan>& ps, Plan& plan, int shape = 0)
         const auto u = units[next_unit];
         const AdjointSpec& a = p0.aj[u.first];
         const int need = a.params_b ? 2 : 1;
-        if (nslot + need > kMaxSlots) break;
+        if (nslot + need > max_slots) break;
         const int sa = nslot++;
         const int sb = need == 2 ? nslot++ : -1;
         if (a.params_b && a.shared) {
@@ -731,6 +769,7 @@ void plan_estimators(const std::vector<ProbPlan>& ps, Plan& plan, int shape = 0)
         ++next_unit;
       }
     }
+    if (fsl.empty()) break;  // nothing fits max_slots (callers keep it >= 1, 2 with pairs)
     // k_forward
     LaunchRec fw;
     fw.kind = Kern::Forward;
@@ -764,7 +803,7 @@ void plan_estimators(const std::vector<ProbPlan>& ps, Plan& plan, int shape = 0)
       f.key = p.key;
       f.crop = p.crop;
       f.mask = gmem(p.mask);
-      f.slots = gmem(p.s->slots);
+      f.slots = gmem(slots_of(p));
       f.npix = (uint32_t)p.s->npix;
       f.flags = p.flags;
       f.tiles_x = tiles_x(p.crop, shape);
@@ -810,7 +849,7 @@ void plan_estimators(const std::vector<ProbPlan>& ps, Plan& plan, int shape = 0)
           fj.loss2 = second ? gmem((double*)nullptr) : gmem(p.pj[j].loss2);
           f.jobs[f.n_jobs++] = fj;
         }
-        f.slots = gmem(p.s->slots);
+        f.slots = gmem(slots_of(p));
         f.npix = (uint32_t)p.s->npix;
         f.width = p.s->width;
         f.key = p.key;
@@ -863,7 +902,7 @@ void plan_estimators(const std::vector<ProbPlan>& ps, Plan& plan, int shape = 0)
           r.key = p.key;
           r.crop = p.crop;
           r.mask = gmem(p.mask);
-          r.slots = gmem((const double*)p.s->slots);
+          r.slots = gmem((const double*)slots_of(p));
           r.npix = (uint32_t)p.s->npix;
           r.flags = p.flags;
           r.tiles_x = tiles_x(p.crop, shape);
@@ -1347,6 +1386,16 @@ int jso_create(jso_ctx** out, int device, void* stream) {
   c->stream = (hipStream_t)stream;
   hipDeviceProp_t prop;
   if (hipGetDeviceProperties(&prop, device) == hipSuccess) c->arch = prop.gcnArchName;
+  {
+    // set-up of what the no-allocation entry point uses: the device address
+    // of this GPU's scratch array and the descriptor ring
+    DeviceGuard g(device);
+    if (scratch_address(device, &c->scratch) != hipSuccess || c->ring.init() != hipSuccess) {
+      c->ring.destroy();
+      delete c;
+      return JSO_E_HIP;
+    }
+  }
   *out = c;
   return JSO_OK;
 }
@@ -1561,6 +1610,40 @@ int jso_render_bwd(jso_ctx* c, int id, const float* params, uint64_t seed, uint3
   p.aj[p.na++] = AdjointSpec{params, nullptr, dimg, nullptr, dparams, 1.0f, tag, spp};
   Plan plan;
   plan_estimators({p}, plan, c->tile_shape);
+  return exec_plan(c, plan);
+}
+
+int jso_render_bwd_noalloc(jso_ctx* c, int id, const float* params, uint64_t seed,
+                           uint32_t iteration, uint32_t tag, int spp, const float* dimg,
+                           const jso_render_opts* opts, float* dparams) {
+  SceneGPU* s = get_scene(c, id);
+  if (!s) return c ? fail(c, JSO_E_INVALID, "bad scene id %d", id) : JSO_E_INVALID;
+  if (!params || !dimg || !dparams) return fail(c, JSO_E_INVALID, "null argument");
+  if (spp < 1) return fail(c, JSO_E_INVALID, "spp must be >= 1");
+  if (int rc = check_volume_params(c, s, params)) return rc;
+  if (!c->scratch) return fail(c, JSO_E_STATE, "no scratch address for device %d", c->device);
+  // one radiance slot = 3 doubles per pixel of the whole image
+  const size_t slot_bytes = s->npix * 3 * sizeof(double);
+  if (slot_bytes > kNoAllocScratchBytes)
+    return fail(c, JSO_E_INVALID,
+                "render_bwd_noalloc: a %dx%d image needs %zu bytes of scratch per sample; "
+                "the no-allocation scratch holds %zu (at most %zu pixels)",
+                s->width, s->height, slot_bytes, kNoAllocScratchBytes,
+                kNoAllocScratchBytes / (3 * sizeof(double)));
+  const int max_slots = (int)std::min<size_t>(kMaxSlots, kNoAllocScratchBytes / slot_bytes);
+  DeviceGuard g(c->device);
+  ProbPlan p{};
+  p.s = s;
+  p.key = KeyArgs{seed, iteration, nullptr};
+  p.crop = crop_of(s, opts);
+  p.mask = opts ? opts->pixel_mask : nullptr;
+  p.flags = c->debug_flags | (opts ? opts->flags : 0u);
+  p.aj[p.na++] = AdjointSpec{params, nullptr, dimg, nullptr, dparams, 1.0f, tag, spp};
+  p.slots = reinterpret_cast<double*>(c->scratch);
+  Plan plan;
+  plan_estimators({p}, plan, c->tile_shape, max_slots);
+  // every slot a replay reads is written by the forward launch before it (same
+  // pixels, same crop and mask), so the scratch needs no clearing
   return exec_plan(c, plan);
 }
 
