@@ -66,7 +66,17 @@ def _textured(w=64, h=48, tex=32, seed=0, depth=6):
     return spec, I.fourier_params(spec, 1), I.uniform_params(spec, 2, 0.2, 0.8)
 
 
-def _check_radiance(img, ref, margin, floor, max_unstable=MAX_UNSTABLE):
+# Share of elements that meet the bound only thanks to the measured rounding
+# floor (or, for gradients, the neighbour allowance), i.e. differ by more than
+# the plain 1e-4: asserted to stay below these limits.  Measured: up to 9.4%
+# of the parameters of the textured cases (white-noise roughness texels:
+# sharp lobes amplify FP32 rounding), all within the floor-based bound.
+MAX_STRICT_RADIANCE = 0.02
+MAX_STRICT_GRAD = 0.12
+
+
+def _check_radiance(img, ref, margin, floor, max_unstable=MAX_UNSTABLE,
+                    max_strict=MAX_STRICT_RADIANCE):
     ok = margin > TAU
     assert 1.0 - ok.mean() <= max_unstable, "unstable fraction %g" % (1.0 - ok.mean())
     scale = np.maximum(np.abs(ref), 1e-3 * np.abs(ref).mean())
@@ -79,6 +89,7 @@ def _check_radiance(img, ref, margin, floor, max_unstable=MAX_UNSTABLE):
     w = np.unravel_index(ratio.argmax(), ratio.shape)
     assert ratio.max() <= 1.0, "pixel %s off: gpu %s ref %s floor %s" % (
         w, img[w], ref[w], floor[w])
+    assert strict <= max_strict, "%.4f%% of stable pixels beyond plain 1e-4" % (100 * strict)
 
 
 def _neighbour_allowance(gabs, spec):
@@ -97,7 +108,7 @@ def _neighbour_allowance(gabs, spec):
     return np.where(gabs < 1e-3 * nbr, 1e-3 * nbr, 0.0)
 
 
-def _check_grad(g, ref, gabs, floor, what, spec=None):
+def _check_grad(g, ref, gabs, floor, what, spec=None, max_strict=MAX_STRICT_GRAD):
     tiny = 1e-12 * max(gabs.max(), 1e-30)
     tol = RTOL * gabs + 2 * floor + tiny + _neighbour_allowance(gabs, spec)
     ratio = np.abs(g - ref) / tol
@@ -107,6 +118,7 @@ def _check_grad(g, ref, gabs, floor, what, spec=None):
           flush=True)
     assert ratio[i] <= 1.0, "%s param %d: gpu %g ref %g gabs %g floor %g" % (
         what, i, g[i], ref[i], gabs[i], floor[i])
+    assert strict <= max_strict, "%s: %.4f%% of params beyond plain 1e-4" % (what, 100 * strict)
 
 
 # ---------------------------------------------------------------------------

@@ -102,3 +102,36 @@ def test_fd_sample_mean_is_gradient_change():
     assert np.all(np.abs(lhs - F1.mean(0)) <= 4.5 * se), (lhs, F1.mean(0), se)
     # and the finite-difference sample is far less noisy than the proportional one
     assert np.all(dF.std(0) < F1.std(0))
+
+
+@pytest.mark.parametrize("which", [0, 1])
+def test_adjoint_at_base_colour_zero_lambert_only(which):
+    """At a base colour of exactly 0 (the lower bound of its domain) the
+    Lambert-only BSDF value of that channel vanishes, but its derivative
+    (1/pi times the incident radiance) does not: the adjoint must equal the
+    one-sided derivative of J there.  In Lambert-only mode J is a polynomial
+    in each base-colour parameter, so the second-order one-sided difference
+    (-3 J(0) + 4 J(h) - J(2h)) / 2h is exact up to O(h^2)."""
+    name, spec, p = _scenes()[which]
+    p = p.copy()
+    n_ch = spec.n_ch
+    if name == "global":
+        zero = [0, 2]
+    else:
+        zero = list(range(0, len(p), n_ch))[::2]  # every other texel's red channel
+    p[zero] = 0.0
+    dimg = I.target_image_synthetic(spec, 11).astype(np.float64) - 0.7
+    flags = O.LAMBERT_ONLY
+    g, ga, _, _ = O.render_bwd(spec, p, dimg, 7, 3, O.TAG_ADJ_PROP, 2, flags)
+    checked = 0
+    h = 1e-5
+    for i in zero[:12]:
+        js = []
+        for k in (0, 1, 2):
+            q = p.copy()
+            q[i] = k * h
+            js.append(_J(spec, q, dimg, flags))
+        fd = (-3 * js[0] + 4 * js[1] - js[2]) / (2 * h)
+        assert abs(fd - g[i]) <= 1e-6 * ga[i] + 1e-12, (name, i, fd, g[i], ga[i])
+        checked += g[i] != 0.0
+    assert checked > 0  # the derivative at the bound is not zero
