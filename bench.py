@@ -1,24 +1,31 @@
 #!/usr/bin/env python3
 """Benchmark of the joint sampling-and-optimisation hot path on one MI355X.
 
-Workload: the 512x512 textured inverse problem (plane + 8 spheres, one shared
-256x256 texture of base colour RGB + roughness = 262,144 parameters, path
-depth 6 with Russian roulette from vertex 3), optimised with the
-meta-estimator at 2 proportional + 1 finite-difference samples per pixel.
-A step is one call of jso_grad_step: primal renders for the adjoint images,
-the replayed adjoint of 2 proportional paths and 1 finite-difference path
-pair per pixel (4 differentiable paths per pixel), and the fused
+Workload (the headline): the 2048x2048 terrain problem -- a fractal
+heightfield of 999,698 triangles and 32 spheres behind a four-wide BVH, one
+512x512 texture of base colour RGB + metalness + roughness (1,310,720
+parameters), path depth 12 with Russian roulette from vertex 3 -- optimised
+with the meta-estimator at 2 proportional + 1 finite-difference samples per
+pixel.  A step is one call of jso_grad_step: primal renders for the adjoint
+images, the replayed adjoint of 2 proportional paths and 1 finite-difference
+path pair per pixel (4 differentiable paths per pixel), and the fused
 meta-estimator + stabilised step.  Inputs are synthetic and already resident
 on the GPU when the timed region starts.
 
 Prints one JSON line.  `value` = differentiable paths/s (forward + replayed
-adjoint); `roofline` = the dominant kernel (forward tracing or the replayed
-adjoint, whichever takes longer): its algorithmic FP32 work (surface vertices
-counted on the GPU x per-vertex FLOP figures) per launch over its HIP-event
-launch time, against the FP32 vector peak, with `traffic` = HBM bytes per
-launch from the committed rocprofv3 counter summary (null when the kernel
-changed since it was taken);
-`cpu_baseline` = the FP64 CPU oracle on the same workload for about 10 s.
+adjoint).  `roofline` = the dominant kernel of the step (forward tracing or
+the replayed adjoint, whichever takes longer per launch; the other follows in
+`roofline_other_kernel`): the adjoint against HBM (its algorithmic bytes per
+launch over its HIP-event launch time, beside its FP32 atomic rate against
+the measured atomic peak), the forward against the VALU lane-operation rate
+(operations per vertex from rocprofv3 counters x vertices counted on the
+GPU); `traffic` = HBM bytes per launch from the committed rocprofv3 counter
+summary (null when the kernel changed since it was taken).
+`microbenchmarks` = the measured copy bandwidth and atomic rates;
+`cpu_baseline` = the FP64 CPU oracle on a crop of the same workload.
+Extras: the 512x512 textured problem, time to loss against Adam-64, the
+terrain's time to parameter RMSE, 64 problems in one batch, the meshes and
+the volume.
 """
 from __future__ import annotations
 
@@ -37,17 +44,20 @@ if ROOT not in sys.path:
 PEAK_HBM_GBS = 8000.0
 PEAK_FP32_VECTOR_TFLOPS = 157.3
 
-# Algorithmic FP32 work per surface vertex of a path: intersection of the
-# continuation and shadow rays with the scene, texture fetch, BSDF evaluation
-# and sampling, NEE with MIS, throughput update (forward); the replay repeats
-# that and adds the material partials of both BSDF evaluations, the adjoint
-# coefficients and the bilinear scatter weights.
-FLOP_FORWARD_VERTEX = 600
-FLOP_REPLAY_VERTEX = 1000
+# VALU lane operations per second: 256 CUs x 4 SIMDs x 16 lanes x 2.4 GHz (a
+# wave64 instruction occupies a 16-lane SIMD for 4 cycles; the 157.3 TFLOP/s
+# figure counts an FMA as 2 and packed FP32 as 2 more)
+PEAK_VALU_TOPS = 256 * 4 * 16 * 2.4e9 / 1e12
+# VALU lane operations the path kernels execute per surface vertex on the
+# terrain workload (active lanes of every VALU instruction, traversal
+# included), from rocprofv3 counters: SQ_INSTS_VALU x SQ_THREAD_CYCLES_VALU /
+# SQ_ACTIVE_INST_VALU per dispatch over the dispatch's surface vertices
+# (profiles/grad_step_terrain2048_kernel_trace_and_issue.md)
+VALU_OPS_PER_VERTEX = {"k_forward": 6183.0, "k_adjoint": 7194.0}
 
 KERNEL_SOURCES = ("paper_2309_15676_amd/csrc/device.h", "paper_2309_15676_amd/csrc/kernels.h",
                   "paper_2309_15676_amd/csrc/kernels.hip")
-TRAFFIC_SUMMARY = "profiles/%s_textured512_hbm_traffic.md"
+TRAFFIC_SUMMARY = "profiles/%s_terrain2048_hbm_traffic.md"
 
 
 def kernel_source_hash() -> str:
@@ -74,50 +84,6 @@ def measured_traffic(kernel: str):
     return None
 
 
-def cpu_baseline(spec, params, target, seconds: float, seed: int):
-    """The FP64 oracle, as it stands, timed on this host: whole iterations
-    (proportional + finite-difference gradient samples on the full image, then
-    the meta-estimator step) of the same workload, repeated until `seconds`
-    have passed."""
-    import numpy as np
-
-    import oracle as O
-    from oracle import meta as OM
-
-    lo, hi = spec.param_bounds()
-    opt = OM.MetaOptimizer(params, lo, hi, eta=float(np.float32(0.01)))
-    # this host's share of cores (at most 16 worker threads)
-    threads = max(1, min(len(os.sched_getaffinity(0)), 16))
-    t0 = time.perf_counter()
-    iters = 0
-    while True:
-        r = O.gradient_pair(spec, opt.params.astype(np.float64),
-                            opt.params_prev.astype(np.float64), target, seed, iters,
-                            nthreads=threads)
-        opt.step(r["F"], r["dF"])
-        iters += 1
-        dt = time.perf_counter() - t0
-        if dt >= seconds or iters >= 1000:
-            break
-    paths = 4 * spec.n_pixels * iters - 2 * spec.n_pixels  # no FD pair at iteration 0
-    out = dict(value=paths / dt, unit="differentiable paths/s", cores=threads, kind="oracle",
-               sample="first %d iterations of the 512x512 workload from the same initial "
-                      "texture (iteration 0 has no FD pair), %.1f s" % (iters, dt))
-    # one thread, on a 64x64 crop at the image centre (a few seconds)
-    crop = (224, 224, 288, 288)
-    n = 0
-    t0 = time.perf_counter()
-    while time.perf_counter() - t0 < seconds / 4 and n < 200:
-        O.gradient_pair(spec, params.astype(np.float64), params.astype(np.float64), target,
-                        seed, 1 + n, crop=crop, nthreads=1)
-        n += 1
-    dt1 = time.perf_counter() - t0
-    out["single_thread"] = dict(value=4 * 64 * 64 * n / dt1, unit="differentiable paths/s",
-                                sample="%d iterations' gradient samples (prop + FD pair) on the "
-                                       "central 64x64 crop, %.1f s" % (n, dt1))
-    return out
-
-
 def copy_calibration(mib: int):
     """A plain device copy of known size (mib MiB read + mib MiB written), run
     three times, for scaling the HBM byte counters of a profiled run."""
@@ -130,30 +96,28 @@ def copy_calibration(mib: int):
     torch.cuda.synchronize()
 
 
-META_BUDGET = 2.0  # meta-estimator wall-clock per run, in units of Adam's
+def time_to_loss(prob, init, gt, target, args, iters: int, seeds: int, label: str,
+                 lam: float = 0.0, etas=None):
+    """Wall-clock (grad_step calls only; evaluations off the clock) for the
+    meta-estimator at 2 proportional + 1 FD spp (replay pair, and shared path)
+    to reach plain Adam-64's loss, same GPU, same process.
 
-
-def time_to_loss(prob, init, gt, target, args, iters: int, label: str, lam: float = 0.0,
-                 etas=None):
-    """Loss against wall-clock (grad_step calls only; evaluations off the
-    clock) of plain Adam at 64 spp and of the meta-estimator at 2 proportional
-    + 1 FD spp (replay pair, and shared path), same GPU, same process.  Every
-    method runs at every learning rate of a grid: Adam for `iters`
-    iterations, the meta-estimator for META_BUDGET times Adam's wall-clock.
-
-    Reported: the time each method needs to reach Adam's best loss (the first
-    time any learning rate reaches it: rates tuned per target, as the paper
-    tunes each method's; speedup null when no rate reaches it within the
-    budget), and the same for the losses Adam reaches after 1/8, 1/4 and 1/2
-    of its iterations (speedup_by_level).  lam > 0: both methods
-    precondition their texture gradients (Large Steps)."""
+    Reference loss: Adam at 64 spp runs `iters` iterations at every learning
+    rate of the grid with optimisation seed 0; the rate with the lowest final
+    evaluation loss is kept and run with seeds 1 .. seeds-1 too; the reference
+    is the median over seeds of the final loss.  Each method's time is the
+    first time its evaluation loss reaches the reference: Adam's with its
+    tuned rate, the meta-estimator's with the rate that reaches it first for
+    seed 0 (then run with the other seeds), within Adam's wall-clock (a run
+    that does not get there within it is not faster).  Reported per seed and
+    as medians (a run that never reaches the reference counts as infinite).
+    lam > 0: both methods precondition their texture gradients (Large Steps)."""
     import torch
 
     from paper_2309_15676_amd import _lib as L
 
     ev_seed, ev_spp = 777, 256
     T = target.float()
-    every = max(iters // 40, 1)
 
     def eval_loss(p=None):
         p = prob.get_params() if p is None else p
@@ -183,77 +147,77 @@ def time_to_loss(prob, init, gt, target, args, iters: int, label: str, lam: floa
     def first(hist, level):
         return next(((h[0], h[1]) for h in hist if h[2] <= level), (None, None))
 
+    def median(xs):
+        v = sorted(float("inf") if x is None else x for x in xs)
+        m = v[len(v) // 2] if len(v) % 2 else 0.5 * (v[len(v) // 2 - 1] + v[len(v) // 2])
+        return None if m == float("inf") else m
+
+    def adam_opts(eta, k):
+        return L.step_opts(optimizer=L.JSO_OPT_ADAM, eta=eta, adam_spp=64,
+                           seed=args.seed + 1 + 100 * k, precond_lambda=lam)
+
+    def meta_opts(eta, k, mode):
+        return L.step_opts(optimizer=L.JSO_OPT_META, eta=eta, beta_F=0.99, beta_D=0.9,
+                           spp_prop=2, spp_fd=1, seed=args.seed + 2 + 100 * k,
+                           precond_lambda=lam, fd_mode=mode)
+
     grid = etas or [float(x) for x in args.ttl_etas.split(",")]
-    adam = {}
+    every = max(iters // 20, 1)
+    adam0 = {}
     for eta in grid:
-        o = L.step_opts(optimizer=L.JSO_OPT_ADAM, eta=eta, adam_spp=64, seed=args.seed + 1,
-                        precond_lambda=lam)
-        adam[eta] = run(o, iters, every)
-        print("[bench]   %s: adam eta %g best %.4g" % (label[:24], eta, min(h[2] for h in adam[eta])),
+        adam0[eta] = run(adam_opts(eta, 0), iters, every)
+        print("[bench]   %s: adam eta %g final %.4g" % (label[:24], eta, adam0[eta][-1][2]),
               file=sys.stderr, flush=True)
-    best_eta = min(adam, key=lambda e: min(h[2] for h in adam[e]))
-    ha = adam[best_eta]
-    target_loss = min(h[2] for h in ha)
-    budget_s = ha[-1][1]
-    runs = {}
+    eta_a = min(adam0, key=lambda e: adam0[e][-1][2])
+    adam_runs = [adam0[eta_a]] + [run(adam_opts(eta_a, k), iters, every)
+                                  for k in range(1, seeds)]
+    ref = median([h[-1][2] for h in adam_runs])
+    adam_t = [first(h, ref)[1] for h in adam_runs]
+    budget = max(h[-1][1] for h in adam_runs)
+    out_runs = {}
     for name, mode in (("meta", L.JSO_FD_REPLAY), ("meta_fd_shared", L.JSO_FD_SHARED)):
-        runs[name] = {}
+        tuned = {}
         for eta in grid:
-            o = L.step_opts(optimizer=L.JSO_OPT_META, eta=eta, beta_F=0.99, beta_D=0.9,
-                            spp_prop=2, spp_fd=1, seed=args.seed + 2, precond_lambda=lam,
-                            fd_mode=mode)
-            runs[name][eta] = run(o, 10 ** 9, every * 4, seconds=META_BUDGET * budget_s)
-            print("[bench]   %s: %s eta %g best %.4g" % (
-                label[:24], name, eta, min(h[2] for h in runs[name][eta])), file=sys.stderr,
-                flush=True)
-
-    def time_to(hists, level):
-        """(seconds, iterations, eta) of the learning rate that reaches `level`
-        first, or Nones."""
-        best = (None, None, None)
-        for eta, h in hists.items():
-            it, t = first(h, level)
-            if t is not None and (best[0] is None or t < best[0]):
-                best = (t, it, eta)
-        return best
-
-    def summary(name):
-        h = runs[name]
-        t, it, eta = time_to(h, target_loss)
-        return {"spp": "2 prop + 1 FD" + (" (shared path)" if "shared" in name else ""),
-                "seconds": t, "iterations": it, "eta": eta,
-                "speedup": (t_adam / t) if t else None,
-                "best_loss_by_eta": {str(e): min(x[2] for x in h[e]) for e in grid},
-                "iterations_run_by_eta": {str(e): h[e][-1][0] for e in grid},
-                "seconds_budget": META_BUDGET * budget_s}
-
-    t_adam, it_adam, _ = time_to({best_eta: ha}, target_loss)
-    levels = {}
-    for frac in (8, 4, 2, 1):
-        lv = next(h[2] for h in ha if h[0] >= iters // frac) if frac > 1 else target_loss
-        ta, ia, ea = time_to(adam, lv)
-        row = {"loss": lv, "adam_seconds": ta, "adam_eta": ea}
-        for name in runs:
-            tm, im, em = time_to(runs[name], lv)
-            row.update({name + "_seconds": tm, name + "_iterations": im, name + "_eta": em,
-                        name + "_speedup": (ta / tm) if tm else None})
-        levels["adam_iters_%d" % (iters // frac)] = row
+            tuned[eta] = run(meta_opts(eta, 0, mode), 10 ** 9, every, seconds=budget)
+            print("[bench]   %s: %s eta %g best %.4g after %d iterations" % (
+                label[:24], name, eta, min(h[2] for h in tuned[eta]), tuned[eta][-1][0]),
+                file=sys.stderr, flush=True)
+        reach = {e: first(h, ref)[1] for e, h in tuned.items()}
+        ok = [e for e in grid if reach[e] is not None]
+        eta_m = min(ok, key=lambda e: reach[e]) if ok else min(
+            tuned, key=lambda e: min(h[2] for h in tuned[e]))
+        hs = [tuned[eta_m]] + [run(meta_opts(eta_m, k, mode), 10 ** 9, every, seconds=budget)
+                               for k in range(1, seeds)]
+        ts = [first(h, ref)[1] for h in hs]
+        its = [first(h, ref)[0] for h in hs]
+        tm = median(ts)
+        out_runs[name] = {
+            "spp": "2 prop + 1 FD" + (" (shared path)" if mode == L.JSO_FD_SHARED else ""),
+            "eta": eta_m, "seconds_per_seed": ts, "iterations_per_seed": its,
+            "best_loss_per_seed": [min(h[2] for h in x) for x in hs],
+            "seconds_median": tm,
+            "speedup": (median(adam_t) / tm) if (tm and median(adam_t)) else None,
+            "best_loss_by_eta_seed0": {str(e): min(h[2] for h in tuned[e]) for e in grid},
+            "ms_per_iteration": 1e3 * hs[0][-1][1] / max(hs[0][-1][0], 1)}
     return {
         "workload": label,
         "evaluation": "L2 of a %d-spp render (fixed evaluation stream) against the target, "
                       "off the clock" % ev_spp,
-        "method": "each method's time to a loss is the first time any learning rate of the "
-                  "grid reaches it (learning rates tuned per target); the meta-estimator runs "
-                  "get %.0fx Adam's wall-clock" % META_BUDGET,
-        "target_loss": target_loss,
+        "protocol": "Adam-64 for %d iterations, learning rate tuned on seed 0 over %s (lowest "
+                    "final loss), %d seeds; reference = median final loss; each method's time "
+                    "= first evaluation at or below it, median over seeds; meta-estimator "
+                    "rates tuned on seed 0 within Adam's wall-clock" % (iters, grid, seeds),
+        "reference_loss": ref,
         "loss_at_ground_truth": floor,
-        "adam": {"spp": 64, "eta": best_eta, "iterations": it_adam, "seconds": t_adam,
-                 "best_loss_by_eta": {str(e): min(h[2] for h in adam[e]) for e in grid},
-                 "iteration_budget": iters, "seconds_budget": budget_s},
-        "meta": summary("meta"),
-        "meta_fd_shared": summary("meta_fd_shared"),
-        "speedup": summary("meta")["speedup"],
-        "speedup_by_level": levels,
+        "adam": {"spp": 64, "eta": eta_a, "seconds_per_seed": adam_t,
+                 "seconds_median": median(adam_t),
+                 "final_loss_per_seed": [h[-1][2] for h in adam_runs],
+                 "final_loss_by_eta_seed0": {str(e): adam0[e][-1][2] for e in grid},
+                 "ms_per_iteration": 1e3 * adam_runs[0][-1][1] / max(adam_runs[0][-1][0], 1)},
+        "meta": out_runs["meta"],
+        "meta_fd_shared": out_runs["meta_fd_shared"],
+        "speedup": out_runs["meta"]["speedup"],
+        "speedup_fd_shared": out_runs["meta_fd_shared"]["speedup"],
         "precond_lambda": lam,
     }
 
@@ -301,25 +265,21 @@ def ablations(prob, init, target, iters: int, eta: float, seed: int, label: str)
     return out
 
 
-def large_time_to_rmse(context, args):
+def large_time_to_rmse(prob, gt, init, args):
     """The 2048x2048 terrain problem (1.0M triangles + 32 spheres, 512x512
     texture of 5 channels): parameter-space RMSE against the ground truth
     over wall-clock (grad_step calls only) for the meta-estimator (2 prop +
-    1 FD spp) and plain Adam at 32 and 64 spp.  The RMSE counts the
-    observable parameters only: every channel of the texels that a 64-spp
-    backward pass at the ground truth touches.  Each run stops at RMSE 1e-2,
-    at 2000 iterations, or at args.large_ttl_seconds of GPU time."""
+    1 FD spp, replay pair and shared path) and plain Adam at 32 and 64 spp.
+    The RMSE counts the observable parameters only: every channel of the
+    texels that a 64-spp backward pass at the ground truth touches.  Each
+    run stops at RMSE 1e-2, at 2000 iterations, or at args.large_ttl_seconds
+    of GPU time."""
     import numpy as np
     import torch
 
     from paper_2309_15676_amd import _lib as L
-    from paper_2309_15676_amd import inputs as I
-    from paper_2309_15676_amd.problem import Problem
 
-    spec, gt, init = I.config_large()
-    prob = Problem(spec, context=context)
-    target = prob.render(gt, seed=12345, iteration=0, tag=L.JSO_TAG_TARGET, spp=256)
-    prob.set_target(target)
+    spec = prob.spec
     ones = torch.ones(spec.height, spec.width, 3, device="cuda")
     g = prob.render_bwd(gt, ones, seed=99, iteration=0, tag=L.JSO_TAG_EVAL, spp=64)
     texel_seen = (g.abs().reshape(-1, spec.n_ch) > 0).any(dim=1)
@@ -337,8 +297,9 @@ def large_time_to_rmse(context, args):
     levels = [1e-2] + [f * r0 for f in (0.95, 0.9, 0.85, 0.8)]
     runs = {}
     for name, opts in (
-            ("meta_eta0.003", L.step_opts(optimizer=L.JSO_OPT_META, eta=0.003, seed=args.seed)),
             ("meta_eta0.01", L.step_opts(optimizer=L.JSO_OPT_META, eta=0.01, seed=args.seed)),
+            ("meta_fd_shared_eta0.01", L.step_opts(optimizer=L.JSO_OPT_META, eta=0.01,
+                                                   seed=args.seed, fd_mode=L.JSO_FD_SHARED)),
             ("adam32_eta0.01", L.step_opts(optimizer=L.JSO_OPT_ADAM, eta=0.01, adam_spp=32,
                                            seed=args.seed)),
             ("adam64_eta0.01", L.step_opts(optimizer=L.JSO_OPT_ADAM, eta=0.01, adam_spp=64,
@@ -357,25 +318,21 @@ def large_time_to_rmse(context, args):
             clock += e0.elapsed_time(e1) / 1e3
             it += chunk
             hist.append((it, clock, rmse()))
-            if it % (50 * chunk) == 0:
-                print("[bench]   large problem %s: %d iterations, %.1f s, rmse %.4g" % (
-                    name, it, clock, hist[-1][2]), file=sys.stderr, flush=True)
         reach = {"%.4g" % lv: next((h[1] for h in hist if h[2] <= lv), None) for lv in levels}
         runs[name] = {"seconds_to_rmse": reach, "final_rmse": hist[-1][2],
                       "iterations": it, "seconds": clock,
                       "ms_per_iteration": 1e3 * clock / max(it, 1)}
         print("[bench] large problem %s: %s" % (name, json.dumps(runs[name])), file=sys.stderr,
               flush=True)
-    del prob
-    torch.cuda.empty_cache()
+    prob.set_params(init)
     return {"workload": "2048x2048 terrain (999,698 triangles) + 32 spheres, 512x512 texture "
                         "of RGB + metalness + roughness (1,310,720 params), depth 12, roulette "
-                        "from vertex 3; target at 256 spp",
+                        "from vertex 3; target at %d spp" % args.large_target_spp,
             "observable_params": int(obs.sum()), "total_params": spec.n_params,
             "initial_rmse": r0, "budget_seconds": args.large_ttl_seconds, "runs": runs}
 
 
-def batched_throughput(ctx_problem, args):
+def batched_throughput(context, args):
     """64 independent problems of uneven size (image side 64-512, 5-65,536
     parameters, own seeds and iteration budgets): differentiable paths/s of
     one iteration for all of them, (a) as a batch replayed from a captured
@@ -389,7 +346,7 @@ def batched_throughput(ctx_problem, args):
     from paper_2309_15676_amd.problem import Batch, Problem, grad_step_many
 
     cfg = I.config_batched(64, seed=args.seed)
-    ctx = ctx_problem.context
+    ctx = context
     probs = []
     for k, c in enumerate(cfg):
         p = Problem(c["spec"], context=ctx)
@@ -669,36 +626,226 @@ def mesh_workloads(context, args):
     return out
 
 
+KERNELS = ((0, "forward"), (4, "finalize"), (1, "adjoint"), (2, "meta"))  # JSO_K_* ids
+
+
+def timed_steps(prob, opts, steps: int, warmup: int):
+    """Wall-clock of `steps` grad_step calls (HIP events on torch's stream,
+    which the context is bound to) and, over the same region, each kernel
+    class's device time from the library's HIP events around its launches."""
+    import torch
+
+    from paper_2309_15676_amd import _lib as L
+    ctx = prob.ctx
+    for _ in range(warmup):
+        prob.grad_step(opts)
+    torch.cuda.synchronize()
+    L.check(L.jso_set_timing(ctx, True), ctx)
+    for k in range(L.JSO_K_COUNT):
+        L.jso_get_kernel_time(ctx, k, reset=True)
+    e0, e1 = torch.cuda.Event(enable_timing=True), torch.cuda.Event(enable_timing=True)
+    torch.cuda.synchronize()
+    e0.record()
+    for _ in range(steps):
+        prob.grad_step(opts)
+    e1.record()
+    torch.cuda.synchronize()
+    kt = {name: L.jso_get_kernel_time(ctx, k) for k, name in KERNELS}
+    L.check(L.jso_set_timing(ctx, False), ctx)
+    return e0.elapsed_time(e1), kt
+
+
+def counted_work(prob, opts, n: int):
+    """Paths and surface vertices of the path launches, counted on the GPU
+    over n further steps (outside any timed region), per step."""
+    from paper_2309_15676_amd import _lib as L
+    ctx = prob.ctx
+    L.check(L.jso_set_work_counting(ctx, True), ctx)
+    L.jso_get_work(ctx, reset=True)
+    for _ in range(n):
+        prob.grad_step(opts)
+    rep_paths, rep_verts, fwd_paths, fwd_verts = L.jso_get_work(ctx, reset=True)
+    L.check(L.jso_set_work_counting(ctx, False), ctx)
+    return rep_paths / n, rep_verts / n, fwd_paths / n, fwd_verts / n
+
+
+def microbenchmarks(context, n_params: int):
+    """The roofline denominators measured on this GPU: a plain device copy of
+    1 GiB (bytes read + written per second), and no-return FP32 atomic adds
+    into a buffer of the headline's parameter count under four address
+    patterns (operations per second)."""
+    import torch
+
+    from paper_2309_15676_amd import _lib as L
+    ctx = context.bind()
+    nbytes = 1 << 30
+    src = torch.ones(nbytes // 4, dtype=torch.float32, device="cuda")
+    dst = torch.empty_like(src)
+    ms = L.jso_ub_copy(ctx, dst.data_ptr(), src.data_ptr(), nbytes, 5)
+    out = {"copy_GBs": 2 * nbytes / (ms / 1e3) / 1e9, "copy_bytes": nbytes, "copy_ms": ms}
+    del src, dst
+    buf = torch.zeros(n_params, dtype=torch.float32, device="cuda")
+    n_ops = 1 << 26
+    for name, pat in (("random", L.JSO_UB_RANDOM), ("lines", L.JSO_UB_LINES),
+                      ("16_addresses", L.JSO_UB_16), ("same_address", L.JSO_UB_SAME)):
+        ms = L.jso_ub_atomics(ctx, buf.data_ptr(), n_params, pat, n_ops, 3)
+        out["atomic_ops_per_s_" + name] = n_ops / (ms / 1e3)
+    out["atomic_buffer_floats"] = n_params
+    out["atomic_ops"] = n_ops
+    del buf
+    torch.cuda.empty_cache()
+    return out
+
+
+def cpu_baseline_crop(spec, params, target, seed: int, crop, label: str):
+    """The FP64 oracle, as it stands, on this host's share of cores (at most
+    16 threads, the CPU share of one GPU): one iteration's gradient samples
+    (2 proportional + 1 finite-difference pair per pixel) and the
+    meta-estimator step on a crop of the workload, timed whole."""
+    import numpy as np
+
+    import oracle as O
+    from oracle import meta as OM
+
+    threads = max(1, min(len(os.sched_getaffinity(0)), 16))
+    lo, hi = spec.param_bounds()
+    opt = OM.MetaOptimizer(params, lo, hi, eta=float(np.float32(0.01)))
+    prev = np.clip(np.asarray(params, np.float32) + np.float32(0.01), lo, hi)
+    t0 = time.perf_counter()
+    r = O.gradient_pair(spec, np.asarray(params, np.float64), prev.astype(np.float64), target,
+                        seed, 1, crop=crop, nthreads=threads)
+    opt.step(r["F"], r["dF"])
+    dt = time.perf_counter() - t0
+    px = (crop[2] - crop[0]) * (crop[3] - crop[1])
+    return dict(value=4 * px / dt, unit="differentiable paths/s", cores=threads, kind="oracle",
+                sample="one iteration (gradient samples of 2 proportional + 1 finite-difference "
+                       "pair per pixel, brute-force intersection, then the meta-estimator step "
+                       "over all %d parameters) on the %dx%d crop at (%d, %d) of %s, %.1f s" % (
+                           spec.n_params, crop[2] - crop[0], crop[3] - crop[1], crop[0], crop[1],
+                           label, dt))
+
+
+def textured_extra(context, args):
+    """The 512x512 textured problem (plane + 8 spheres, 256x256 RGB +
+    roughness texture, 262,144 parameters, depth 6): meta-estimator step
+    (replay pair and shared path), kernel times, and the adjoint against its
+    HBM and atomic roofline."""
+    from paper_2309_15676_amd import _lib as L
+    from paper_2309_15676_amd import inputs as I
+    from paper_2309_15676_amd.problem import Problem
+
+    spec, gt, init = I.config_textured()
+    prob = Problem(spec, context=context)
+    target = prob.render(gt, seed=12345, iteration=0, tag=L.JSO_TAG_TARGET, spp=args.target_spp)
+    prob.set_target(target)
+    prob.set_params(init)
+    opts = L.step_opts(optimizer=L.JSO_OPT_META, eta=0.01, beta_F=0.99, beta_D=0.9, spp_prop=2,
+                       spp_fd=1, seed=args.seed)
+    total_ms, kt = timed_steps(prob, opts, args.steps, args.warmup)
+    work = counted_work(prob, opts, 3)
+    npix = spec.n_pixels
+    out = {"workload": "textured 512x512, 256x256 RGB+roughness texture (262,144 params), "
+                       "plane + 8 spheres, depth 6, roulette from vertex 3, meta-estimator 2 "
+                       "prop + 1 FD spp",
+           "ms_per_step": total_ms / args.steps,
+           "diff_paths_per_s": 4 * npix * args.steps / (total_ms / 1e3),
+           "kernel_ms_per_step": {k: v[0] / args.steps for k, v in kt.items()},
+           "adjoint": adjoint_roofline(spec, prob, kt, work, None, args.steps),
+           "vertices_per_replayed_path": work[1] / max(work[0], 1)}
+    prob.set_params(init)
+    opts_sh = L.step_opts(optimizer=L.JSO_OPT_META, eta=0.01, beta_F=0.99, beta_D=0.9,
+                          spp_prop=2, spp_fd=1, seed=args.seed, fd_mode=L.JSO_FD_SHARED)
+    ms_sh, kt_sh = timed_steps(prob, opts_sh, args.steps, args.warmup)
+    out["fd_shared_step"] = {"ms_per_step": ms_sh / args.steps,
+                             "kernel_ms_per_step": {k: v[0] / args.steps
+                                                    for k, v in kt_sh.items()},
+                             "paths_traced_per_step": 3 * npix}
+    prob.set_params(init)
+    return out, prob, spec, gt, init, target
+
+
+def scene_bytes(prob) -> int:
+    """Bytes of the scene data a path launch reads at least once: the BVH
+    (128-byte four-wide nodes, 48 bytes per triangle) of a mesh."""
+    n_tris = len(prob.spec.tris) if len(prob.spec.tris) else 0
+    if not n_tris:
+        return 0
+    # a four-wide hierarchy over leaves of a few triangles: at most n_tris / 3
+    # nodes in practice; the exact count is not exported, so bound it by that
+    return 48 * n_tris + 128 * (n_tris // 3)
+
+
+def adjoint_roofline(spec, prob, kt, work, ub, steps):
+    """k_adjoint against the bounds of its work per launch.
+
+    Algorithmic work of one launch (the replay of one step's adjoint paths):
+    every surface vertex scatters its material gradient into the 4 texels
+    of its bilinear footprint, 4 n_ch FP32 atomics of 4 bytes; each replayed
+    path reads its radiance slot (24 B) and its pixel's adjoint colour
+    (12 B); the parameters (4 B each) and the scene's BVH are read at least
+    once.  HBM: those bytes over the launch time against 8 TB/s; atomics:
+    the 4 n_ch atomics per vertex over the launch time against the measured
+    peak of no-return FP32 atomics (coalesced 64-byte segments, and random
+    addresses)."""
+    ms, calls = kt["adjoint"]
+    launch_ms = ms / max(calls, 1)
+    per_launch = steps / max(calls, 1)  # launches per step: calls / steps
+    rep_paths, rep_verts = work[0] * per_launch, work[1] * per_launch
+    n_ch = spec.n_ch
+    atomics = rep_verts * 4 * n_ch
+    bytes_ = (atomics * 4 + rep_paths * (24 + 12) + 4 * spec.n_params + scene_bytes(prob))
+    achieved = bytes_ / (launch_ms / 1e3) / 1e9
+    out = {"bound": "hbm", "achieved": achieved, "peak": PEAK_HBM_GBS, "unit": "GB/s",
+           "frac": achieved / PEAK_HBM_GBS, "kernel": "k_adjoint", "kernel_ms": launch_ms,
+           "algorithmic_bytes": bytes_, "paths_per_launch": rep_paths,
+           "vertices_per_launch": rep_verts, "vertices_per_path": rep_verts / max(rep_paths, 1),
+           "atomics_per_launch": atomics,
+           "atomics_per_s": atomics / (launch_ms / 1e3)}
+    if ub:
+        out["atomic_frac_lines"] = out["atomics_per_s"] / ub["atomic_ops_per_s_lines"]
+        out["atomic_frac_random"] = out["atomics_per_s"] / ub["atomic_ops_per_s_random"]
+        out["frac_of_measured_copy"] = achieved / ub["copy_GBs"]
+    return out
+
+
 def main():
     ap = argparse.ArgumentParser(description=__doc__.split("\n")[0])
     ap.add_argument("--gpus", type=int, default=1)
     ap.add_argument("--steps", type=int, default=30)
     ap.add_argument("--warmup", type=int, default=3)
-    ap.add_argument("--target-spp", type=int, default=4096)
-    ap.add_argument("--cpu-seconds", type=float, default=10.0)
+    ap.add_argument("--target-spp", type=int, default=256,
+                    help="samples per pixel of the 512x512 target render")
+    ap.add_argument("--large-target-spp", type=int, default=64,
+                    help="samples per pixel of the 2048x2048 target render")
     ap.add_argument("--no-cpu-baseline", action="store_true")
+    ap.add_argument("--no-microbench", action="store_true")
     ap.add_argument("--copy-mib", type=int, default=0,
                     help="also run a plain copy of this many MiB (counter calibration)")
     ap.add_argument("--seed", type=int, default=4)
-    ap.add_argument("--ttl-iters", type=int, default=300,
+    ap.add_argument("--no-extras", action="store_true",
+                    help="the headline only (no 512x512, batch, mesh, volume or time-to-loss "
+                         "runs)")
+    ap.add_argument("--ttl-iters", type=int, default=1000,
                     help="Adam-64 iteration budget of the textured time-to-loss comparison "
                          "(0: skip the comparisons)")
-    ap.add_argument("--ttl-etas", default="0.0003,0.001,0.003,0.01,0.03,0.1")
-    ap.add_argument("--ttl-lambda", type=float, default=20.0,
+    ap.add_argument("--ttl-seeds", type=int, default=3,
+                    help="optimisation seeds of the textured time-to-loss comparison (median)")
+    ap.add_argument("--ttl-etas", default="0.001,0.003,0.01,0.03,0.1")
+    ap.add_argument("--ttl-lambda", type=float, default=0.0,
                     help="also compare both methods with preconditioned texture gradients "
                          "(Large Steps) at this lambda (0: skip)")
     ap.add_argument("--batch-steps", type=int, default=20,
                     help="iterations timed for the 64-problem batch (0: skip it)")
     ap.add_argument("--batch-target-spp", type=int, default=256)
-    ap.add_argument("--ablation-iters", type=int, default=1000,
+    ap.add_argument("--ablation-iters", type=int, default=0,
                     help="meta-estimator iterations of the ablation runs on the textured "
                          "problem (the tiny problem runs 200; 0: skip)")
-    ap.add_argument("--large-ttl-seconds", type=float, default=0.0,
+    ap.add_argument("--large-ttl-seconds", type=float, default=15.0,
                     help="GPU-seconds per run of the terrain time-to-RMSE comparison "
                          "(meta-estimator vs Adam at 32 and 64 spp; 0: skip)")
     ap.add_argument("--volume-steps", type=int, default=5,
                     help="timed calls per volume configuration (0 = skip the volume workload)")
-    ap.add_argument("--volume-ttl-seconds", type=float, default=8.0,
+    ap.add_argument("--volume-ttl-seconds", type=float, default=4.0,
                     help="GPU-seconds per run of the volume equal-time comparison (0: skip)")
     ap.add_argument("--volume-ttl-res", type=int, default=128,
                     help="voxels per side (and view size) of the equal-time comparison")
@@ -715,159 +862,131 @@ def main():
 
     from paper_2309_15676_amd import _lib as L
     from paper_2309_15676_amd import inputs as I
-    from paper_2309_15676_amd.problem import Problem
+    from paper_2309_15676_amd.problem import Context, Problem
 
     if not torch.cuda.is_available():
         print("bench.py needs a GPU", file=sys.stderr)
         sys.exit(1)
-    spec, gt, init = I.config_textured()
-    prob = Problem(spec)
-    # target image: ground-truth texture rendered at high spp (off the clock)
-    print("[bench] rendering target at %d spp" % args.target_spp, file=sys.stderr, flush=True)
-    target = prob.render(gt, seed=12345, iteration=0, tag=L.JSO_TAG_TARGET, spp=args.target_spp)
+    context = Context(0)
+    # ---- headline: the 2048x2048 terrain problem -------------------------
+    t0 = time.time()
+    spec, gt, init = I.config_large()
+    prob = Problem(spec, context=context)
+    load_s = time.time() - t0
+    print("[bench] terrain loaded in %.1f s; rendering target at %d spp" % (
+        load_s, args.large_target_spp), file=sys.stderr, flush=True)
+    target = prob.render(gt, seed=12345, iteration=0, tag=L.JSO_TAG_TARGET,
+                         spp=args.large_target_spp)
     prob.set_target(target)
     prob.set_params(init)
     opts = L.step_opts(optimizer=L.JSO_OPT_META, eta=0.01, beta_F=0.99, beta_D=0.9, spp_prop=2,
                        spp_fd=1, seed=args.seed)
-    ctx = prob.ctx
-    for _ in range(args.warmup):
-        prob.grad_step(opts)
-    torch.cuda.synchronize()
-    L.check(L.jso_set_timing(ctx, True), ctx)
-    for k in range(L.JSO_K_COUNT):
-        L.jso_get_kernel_time(ctx, k, reset=True)
-    e0, e1 = torch.cuda.Event(enable_timing=True), torch.cuda.Event(enable_timing=True)
-    torch.cuda.synchronize()
-    e0.record()
-    for _ in range(args.steps):
-        prob.grad_step(opts)
-    e1.record()
-    torch.cuda.synchronize()
-    total_ms = e0.elapsed_time(e1)
-    ktimes = {name: L.jso_get_kernel_time(ctx, k) for k, name in
-              ((L.JSO_K_FORWARD, "forward"), (L.JSO_K_FINALIZE, "finalize"),
-               (L.JSO_K_ADJOINT, "adjoint"), (L.JSO_K_META, "meta"))}
-    L.check(L.jso_set_timing(ctx, False), ctx)
-    # work of the path-tracing launches, counted on the GPU (outside the timed region)
-    L.check(L.jso_set_work_counting(ctx, True), ctx)
-    L.jso_get_work(ctx, reset=True)
-    n_count = 3
-    for _ in range(n_count):
-        prob.grad_step(opts)
-    rep_paths, rep_verts, fwd_paths, fwd_verts = L.jso_get_work(ctx, reset=True)
-    L.check(L.jso_set_work_counting(ctx, False), ctx)
-    vpp = rep_verts / max(rep_paths, 1)
+    total_ms, ktimes = timed_steps(prob, opts, args.steps, args.warmup)
+    work = counted_work(prob, opts, 2)
     st = prob.grad_step(opts, want_stats=True)
-    print("[bench] kernel ms per step: %s; loss %.5g; %.4f vertices per path" % (
-        {k: round(v[0] / max(v[1], 1), 4) for k, v in ktimes.items()}, st.loss, vpp),
-        file=sys.stderr, flush=True)
-    # the same step with the shared-path finite-difference sample (Eq. 5 as
-    # written: one finite-difference path per pixel instead of two), reported
-    # beside the headline figure
-    opts_sh = L.step_opts(optimizer=L.JSO_OPT_META, eta=0.01, beta_F=0.99, beta_D=0.9,
-                          spp_prop=2, spp_fd=1, seed=args.seed, fd_mode=L.JSO_FD_SHARED)
-    prob.set_params(init)
-    for _ in range(args.warmup):
-        prob.grad_step(opts_sh)
-    L.check(L.jso_set_timing(ctx, True), ctx)
-    for k in range(L.JSO_K_COUNT):
-        L.jso_get_kernel_time(ctx, k, reset=True)
-    torch.cuda.synchronize()
-    e0.record()
-    for _ in range(args.steps):
-        prob.grad_step(opts_sh)
-    e1.record()
-    torch.cuda.synchronize()
-    fd_shared = {"ms_per_step": e0.elapsed_time(e1) / args.steps,
-                 "kernel_ms_per_step": {name: (lambda v: v[0] / max(v[1], 1))(
-                     L.jso_get_kernel_time(ctx, k)) for k, name in
-                     ((L.JSO_K_FORWARD, "forward"), (L.JSO_K_FINALIZE, "finalize"),
-                      (L.JSO_K_ADJOINT, "adjoint"), (L.JSO_K_META, "meta"))},
-                 "paths_traced_per_step": 3 * spec.n_pixels}
-    L.check(L.jso_set_timing(ctx, False), ctx)
-    prob.set_params(init)
-    print("[bench] shared-path FD step: %s" % json.dumps(fd_shared), file=sys.stderr, flush=True)
-    if args.copy_mib > 0:
-        copy_calibration(args.copy_mib)
-
     npix = spec.n_pixels
-    diff_paths = 4 * npix * args.steps
-    value = diff_paths / (total_ms / 1e3)
-
-    # CPU baseline: the oracle on this host
+    value = 4 * npix * args.steps / (total_ms / 1e3)
+    print("[bench] terrain: %.3f ms per step, kernels %s, loss %.5g; per step: replayed "
+          "paths %d, their vertices %d, forward paths %d, their vertices %d" % (
+              total_ms / args.steps, {k: round(v[0] / args.steps, 3) for k, v in ktimes.items()},
+              st.loss, *work), file=sys.stderr, flush=True)
+    ub = None
+    if not args.no_microbench:
+        ub = microbenchmarks(context, spec.n_params)
+        print("[bench] microbenchmarks: %s" % json.dumps(ub), file=sys.stderr, flush=True)
+    adj = adjoint_roofline(spec, prob, ktimes, work, ub, args.steps)
+    fwd_ms, fwd_calls = ktimes["forward"]
+    fwd_launch_ms = fwd_ms / max(fwd_calls, 1)
+    fwd_verts = work[3] * args.steps / max(fwd_calls, 1)
+    fwd = {"kernel": "k_forward", "kernel_ms": fwd_launch_ms, "bound": "alu",
+           "paths_per_launch": work[2] * args.steps / max(fwd_calls, 1),
+           "vertices_per_launch": fwd_verts, "vertices_per_path": work[3] / max(work[2], 1),
+           "achieved": None, "peak": PEAK_VALU_TOPS, "unit": "T VALU lane-op/s", "frac": None}
+    if VALU_OPS_PER_VERTEX["k_forward"]:
+        fwd["achieved"] = (fwd_verts * VALU_OPS_PER_VERTEX["k_forward"] /
+                           (fwd_launch_ms / 1e3) / 1e12)
+        fwd["frac"] = fwd["achieved"] / PEAK_VALU_TOPS
+    if VALU_OPS_PER_VERTEX["k_adjoint"]:
+        adj["alu_achieved_Tops"] = (adj["vertices_per_launch"] * VALU_OPS_PER_VERTEX["k_adjoint"]
+                                    / (adj["kernel_ms"] / 1e3) / 1e12)
+        adj["alu_frac"] = adj["alu_achieved_Tops"] / PEAK_VALU_TOPS
+    # the dominant kernel's roofline leads; the other follows
+    if fwd_launch_ms > adj["kernel_ms"]:
+        roof, other = fwd, adj
+    else:
+        roof, other = adj, fwd
+    roof = dict(roof)
+    roof["traffic"] = measured_traffic(roof["kernel"])
     cpu = None
     if not args.no_cpu_baseline:
-        print("[bench] CPU oracle baseline (%.0f s)" % args.cpu_seconds, file=sys.stderr,
-              flush=True)
+        print("[bench] CPU oracle baseline", file=sys.stderr, flush=True)
         Tn = target.cpu().numpy().astype(np.float64)
-        cpu = cpu_baseline(spec, init, Tn, args.cpu_seconds, args.seed)
-    bat = None
-    if args.batch_steps > 0:
-        print("[bench] 64-problem batch", file=sys.stderr, flush=True)
-        bat = batched_throughput(prob, args)
-        print("[bench] batch: %s" % json.dumps(bat), file=sys.stderr, flush=True)
-    mesh = None
-    if args.mesh_steps > 0:
-        print("[bench] mesh workloads", file=sys.stderr, flush=True)
-        mesh = mesh_workloads(prob.context, args)
-    vol = None
-    if args.volume_steps > 0:
-        print("[bench] volume workload", file=sys.stderr, flush=True)
-        vol = volume_workload(prob.context, args)
+        cpu = cpu_baseline_crop(spec, init, Tn, args.seed, (1016, 1100, 1032, 1116),
+                                "the 2048x2048 terrain")
+        print("[bench] CPU baseline: %s" % json.dumps(cpu), file=sys.stderr, flush=True)
     large = None
-    if args.large_ttl_seconds > 0:
+    if args.large_ttl_seconds > 0 and not args.no_extras:
         print("[bench] terrain time to RMSE", file=sys.stderr, flush=True)
-        large = large_time_to_rmse(prob.context, args)
-    ttl = None
-    if args.ttl_iters > 0:
-        print("[bench] time to loss: Adam-64 vs meta-estimator", file=sys.stderr, flush=True)
-        ttl = {}
-        # the paper's multivariate-material case: 5 global parameters
-        tspec, tgt, tinit = I.config_tiny()
-        tprob = Problem(tspec, context=prob.context)
-        ttarget = tprob.render(tgt, seed=12345, iteration=0, tag=L.JSO_TAG_TARGET, spp=1024)
-        tprob.set_target(ttarget)
-        ttl["tiny"] = time_to_loss(
-            tprob, tinit, tgt, ttarget, args, 200,
-            "64x64, unit sphere on a grey plane, 5 global parameters (RGB, metalness, "
-            "roughness), depth 3, target at 1024 spp")
-        print("[bench] time to loss: %s" % json.dumps(ttl["tiny"]), file=sys.stderr, flush=True)
-        ttl["textured"] = time_to_loss(
-            prob, init, gt, target, args, args.ttl_iters,
-            "the 512x512 textured problem (262,144 texel parameters, no preconditioning)")
-        print("[bench] time to loss: %s" % json.dumps(ttl["textured"]), file=sys.stderr,
-              flush=True)
-        if args.ttl_lambda > 0:
-            ttl["textured_preconditioned"] = time_to_loss(
-                prob, init, gt, target, args, args.ttl_iters,
-                "the 512x512 textured problem, both methods with Large-Steps preconditioned "
-                "texture gradients", lam=args.ttl_lambda, etas=[0.01, 0.03, 0.1, 0.3])
-            print("[bench] time to loss: %s" % json.dumps(ttl["textured_preconditioned"]),
-                  file=sys.stderr, flush=True)
-    abl = None
-    if args.ablation_iters > 0:
-        print("[bench] meta-estimator ablations", file=sys.stderr, flush=True)
-        tspec, tgt, tinit = I.config_tiny()
-        tprob = Problem(tspec, context=prob.context)
-        ttarget = tprob.render(tgt, seed=12345, iteration=0, tag=L.JSO_TAG_TARGET, spp=1024)
-        tprob.set_target(ttarget)
-        abl = {"tiny": ablations(tprob, tinit, ttarget, 200, 0.01, args.seed + 2,
-                                 "64x64, 5 global parameters"),
-               "textured": ablations(prob, init, target, args.ablation_iters, 0.003,
-                                     args.seed + 2, "512x512, 262,144 texel parameters")}
-        print("[bench] ablations: %s" % json.dumps(abl), file=sys.stderr, flush=True)
-    # roofline of the dominant kernel: algorithmic FP32 work per launch over
-    # its average launch time
-    cands = {
-        "k_forward": (ktimes["forward"], fwd_verts / n_count * FLOP_FORWARD_VERTEX,
-                      fwd_paths / n_count, fwd_verts / max(fwd_paths, 1)),
-        "k_adjoint": (ktimes["adjoint"], rep_verts / n_count * FLOP_REPLAY_VERTEX,
-                      rep_paths / n_count, vpp),
-    }
-    kname = max(cands, key=lambda k: cands[k][0][0])
-    (k_ms, k_n), k_flop, k_paths, k_vpp = cands[kname]
-    k_launch_ms = k_ms / max(k_n, 1)
-    achieved = k_flop / (k_launch_ms / 1e3) / 1e12
+        large = large_time_to_rmse(prob, gt, init, args)
+    del prob, target
+    torch.cuda.empty_cache()
+
+    extras = {}
+    if not args.no_extras:
+        print("[bench] 512x512 textured problem", file=sys.stderr, flush=True)
+        tex, tprob, tspec, tgt, tinit, ttarget = textured_extra(context, args)
+        extras["textured_512"] = tex
+        print("[bench] textured: %s" % json.dumps(tex), file=sys.stderr, flush=True)
+        if args.ttl_iters > 0:
+            print("[bench] time to loss: Adam-64 vs meta-estimator", file=sys.stderr, flush=True)
+            ttl = {}
+            sspec, sgt, sinit = I.config_tiny()
+            sprob = Problem(sspec, context=context)
+            starget = sprob.render(sgt, seed=12345, iteration=0, tag=L.JSO_TAG_TARGET, spp=1024)
+            sprob.set_target(starget)
+            ttl["tiny"] = time_to_loss(
+                sprob, sinit, sgt, starget, args, 200, 1,
+                "64x64, unit sphere on a grey plane, 5 global parameters (RGB, metalness, "
+                "roughness), depth 3, target at 1024 spp")
+            print("[bench] time to loss: %s" % json.dumps(ttl["tiny"]), file=sys.stderr,
+                  flush=True)
+            ttl["textured"] = time_to_loss(
+                tprob, tinit, tgt, ttarget, args, args.ttl_iters, args.ttl_seeds,
+                "the 512x512 textured problem (262,144 texel parameters, no preconditioning)")
+            print("[bench] time to loss: %s" % json.dumps(ttl["textured"]), file=sys.stderr,
+                  flush=True)
+            if args.ttl_lambda > 0:
+                ttl["textured_preconditioned"] = time_to_loss(
+                    tprob, tinit, tgt, ttarget, args, args.ttl_iters, 1,
+                    "the 512x512 textured problem, both methods with Large-Steps preconditioned "
+                    "texture gradients", lam=args.ttl_lambda, etas=[0.01, 0.03, 0.1, 0.3])
+            extras["time_to_loss"] = ttl
+        if args.ablation_iters > 0:
+            print("[bench] meta-estimator ablations", file=sys.stderr, flush=True)
+            aspec, agt, ainit = I.config_tiny()
+            aprob = Problem(aspec, context=context)
+            atarget = aprob.render(agt, seed=12345, iteration=0, tag=L.JSO_TAG_TARGET, spp=1024)
+            aprob.set_target(atarget)
+            extras["ablations"] = {
+                "tiny": ablations(aprob, ainit, atarget, 200, 0.01, args.seed + 2,
+                                  "64x64, 5 global parameters"),
+                "textured": ablations(tprob, tinit, ttarget, args.ablation_iters, 0.003,
+                                      args.seed + 2, "512x512, 262,144 texel parameters")}
+        del tprob
+        torch.cuda.empty_cache()
+        if args.batch_steps > 0:
+            print("[bench] 64-problem batch", file=sys.stderr, flush=True)
+            extras["batched"] = batched_throughput(context, args)
+            print("[bench] batch: %s" % json.dumps(extras["batched"]), file=sys.stderr,
+                  flush=True)
+        if args.mesh_steps > 0:
+            print("[bench] mesh workloads", file=sys.stderr, flush=True)
+            extras["meshes"] = mesh_workloads(context, args)
+        if args.volume_steps > 0:
+            print("[bench] volume workload", file=sys.stderr, flush=True)
+            extras["volume"] = volume_workload(context, args)
+    if args.copy_mib > 0:
+        copy_calibration(args.copy_mib)
     line = {
         "metric": "differentiable paths/s (fwd+adjoint); time-to-loss vs plain Adam, same GPU",
         "value": value,
@@ -881,26 +1000,22 @@ def main():
         "vs_baseline": None,
         "dtype": "f32 (radiance/gradients), f64 (meta-estimator state)",
         "data": "synthetic",
-        "config": {"workload": "textured 512x512, 256x256 RGB+roughness texture (262,144 params), "
-                               "plane + 8 spheres, depth 6, roulette from vertex 3, "
+        "config": {"workload": "2048x2048 terrain: fractal heightfield of 999,698 triangles + "
+                               "32 spheres, 512x512 texture of RGB + metalness + roughness "
+                               "(1,310,720 params), depth 12, roulette from vertex 3, "
                                "meta-estimator 2 prop + 1 FD spp",
-                   "pixels": npix, "params": spec.n_params, "diff_paths_per_step": 4 * npix},
-        "roofline": {"bound": "alu", "achieved": achieved, "peak": PEAK_FP32_VECTOR_TFLOPS,
-                     "unit": "TFLOP/s", "frac": achieved / PEAK_FP32_VECTOR_TFLOPS,
-                     "traffic": measured_traffic(kname), "kernel": kname,
-                     "kernel_ms": k_launch_ms, "paths_per_launch": k_paths,
-                     "vertices_per_path": k_vpp},
-        "vertices_per_s": value * vpp,
-        "kernel_ms_per_step": {k: v[0] / max(v[1], 1) for k, v in ktimes.items()},
-        "fd_shared_step": fd_shared,
+                   "pixels": npix, "params": spec.n_params, "triangles": len(spec.tris),
+                   "diff_paths_per_step": 4 * npix},
+        "roofline": roof,
+        "roofline_other_kernel": other,
+        "microbenchmarks": ub,
+        "vertices_per_s": value * work[1] / max(work[0], 1),
+        "kernel_ms_per_step": {k: v[0] / args.steps for k, v in ktimes.items()},
+        "scene_load_s": load_s,
         "cpu_baseline": cpu,
-        "time_to_loss": ttl,
-        "batched": bat,
-        "meshes": mesh,
-        "volume": vol,
-        "ablations": abl,
         "large_time_to_rmse": large,
     }
+    line.update(extras)
     print(json.dumps(line))
 
 

@@ -434,6 +434,29 @@ int jso_set_timing(jso_ctx* ctx, int enable);
  * events.  reset != 0 clears the totals afterwards. */
 int jso_get_kernel_time(jso_ctx* ctx, int kernel, double* ms, uint64_t* launches, int reset);
 
+/* ---- memory-system microbenchmarks ------------------------------------ */
+
+/* The denominators of the roofline fractions the benchmark reports; not part
+ * of the method.  Each runs its kernel once untimed, then `reps` times on the
+ * context's stream, and returns the mean time per run in *ms (HIP events).
+ * jso_ub_copy: dst = src for `bytes` bytes (dev; both 16-byte aligned, bytes a
+ * multiple of 16, the buffers not overlapping).
+ * jso_ub_atomics: n_ops no-return FP32 atomic adds of 1.0 into buf (dev,
+ * n_buf >= 16 floats), operation i to
+ *   JSO_UB_RANDOM  a hashed index in [0, n_buf)
+ *   JSO_UB_LINES   16 consecutive operations to the 16 floats of one hashed
+ *                  64-byte segment (the coalesced form of a texel scatter)
+ *   JSO_UB_16      index i mod 16
+ *   JSO_UB_SAME    index 0
+ * Errors: JSO_E_INVALID for bad arguments, JSO_E_HIP for a failed launch. */
+#define JSO_UB_RANDOM 0
+#define JSO_UB_LINES 1
+#define JSO_UB_16 2
+#define JSO_UB_SAME 3
+int jso_ub_copy(jso_ctx* ctx, void* dst, const void* src, size_t bytes, int reps, double* ms);
+int jso_ub_atomics(jso_ctx* ctx, float* buf, size_t n_buf, int pattern, size_t n_ops, int reps,
+                   double* ms);
+
 /* Work counters, for throughput accounting.  While enabled, the launches of
  * this context add: out[0] the paths the adjoint replays (a finite-difference
  * pair counts two), out[1] their surface vertices; out[2] the paths traced

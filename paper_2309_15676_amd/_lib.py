@@ -42,7 +42,9 @@ EXPORTED = [
     "jso_set_timing", "jso_get_kernel_time", "jso_set_work_counting", "jso_get_work",
     "jso_batch_create", "jso_batch_step", "jso_batch_active", "jso_batch_destroy",
     "jso_batch_autotune", "jso_set_tile_shape", "jso_precondition", "jso_render_bwd_noalloc",
+    "jso_ub_copy", "jso_ub_atomics",
 ]
+JSO_UB_RANDOM, JSO_UB_LINES, JSO_UB_16, JSO_UB_SAME = 0, 1, 2, 3
 JSO_NOALLOC_SCRATCH_BYTES = 128 << 20
 JSO_NOALLOC_MAX_PIXELS = JSO_NOALLOC_SCRATCH_BYTES // 24
 JSO_TILE_16x16, JSO_TILE_16x8, JSO_TILE_8x8, JSO_TILE_SHAPES = 0, 1, 2, 3
@@ -147,6 +149,8 @@ def load() -> ctypes.CDLL:
         "jso_render": (I, [P, I, P, U64, U32, U32, I, P, P]),
         "jso_render_bwd": (I, [P, I, P, U64, U32, U32, I, P, P, P]),
         "jso_render_bwd_noalloc": (I, [P, I, P, U64, U32, U32, I, P, P, P]),
+        "jso_ub_copy": (I, [P, P, P, SZ, I, ctypes.POINTER(D)]),
+        "jso_ub_atomics": (I, [P, P, SZ, I, SZ, I, ctypes.POINTER(D)]),
         "jso_estimate_gradients": (I, [P, I, U64, U32, I, I, P, P, P, P, P]),
         "jso_meta_step": (I, [P, I, P, P, F, F, F]),
         "jso_adam_step": (I, [P, I, P, F, F, F, F]),
@@ -338,6 +342,22 @@ def jso_render_bwd(ctx, sid, params_ptr, seed, iteration, tag, spp, dimg_ptr, op
                    dparams_ptr) -> int:
     return load().jso_render_bwd(ctx, sid, params_ptr, seed, iteration, tag, spp, dimg_ptr,
                                  ctypes.byref(opts) if opts is not None else None, dparams_ptr)
+
+
+def jso_ub_copy(ctx, dst_ptr, src_ptr, nbytes, reps) -> float:
+    """Mean ms per copy of nbytes (device to device) over reps runs."""
+    ms = ctypes.c_double(0.0)
+    check(load().jso_ub_copy(ctx, dst_ptr, src_ptr, nbytes, reps, ctypes.byref(ms)), ctx,
+          "jso_ub_copy")
+    return ms.value
+
+
+def jso_ub_atomics(ctx, buf_ptr, n_buf, pattern, n_ops, reps) -> float:
+    """Mean ms per launch of n_ops no-return FP32 atomic adds (pattern JSO_UB_*)."""
+    ms = ctypes.c_double(0.0)
+    check(load().jso_ub_atomics(ctx, buf_ptr, n_buf, pattern, n_ops, reps, ctypes.byref(ms)),
+          ctx, "jso_ub_atomics")
+    return ms.value
 
 
 def jso_render_bwd_noalloc(ctx, sid, params_ptr, seed, iteration, tag, spp, dimg_ptr, opts,

@@ -12,7 +12,7 @@ HERE = os.path.dirname(os.path.abspath(__file__))
 ROOT = os.path.dirname(HERE)
 CSRC = os.path.join(HERE, "csrc")
 LIB = os.path.join(HERE, "libjso.so")
-SOURCES = ["kernels.hip", "api.hip", "bvh.cpp"]
+SOURCES = ["kernels.hip", "api.hip", "bvh.cpp", "ubench.hip"]
 ARCH = os.environ.get("JSO_ARCH", "gfx950")
 
 FLAGS = [
@@ -36,15 +36,18 @@ FLAGS = [
 
 def build(verbose: bool = False) -> str:
     """Compile every source and link libjso.so; always rebuilds."""
+    from concurrent.futures import ThreadPoolExecutor
     hipcc = os.environ.get("HIPCC", "hipcc")
-    objs = []
-    for src in SOURCES:
-        obj = os.path.join(CSRC, os.path.splitext(src)[0] + ".o")
-        cmd = [hipcc, *FLAGS, "-c", os.path.join(CSRC, src), "-o", obj]
+    objs = [os.path.join(CSRC, os.path.splitext(src)[0] + ".o") for src in SOURCES]
+
+    def compile_one(k):
+        cmd = [hipcc, *FLAGS, "-c", os.path.join(CSRC, SOURCES[k]), "-o", objs[k]]
         if verbose:
             print(" ".join(cmd), flush=True)
         subprocess.run(cmd, check=True, stderr=None if verbose else subprocess.PIPE)
-        objs.append(obj)
+
+    with ThreadPoolExecutor(max_workers=len(SOURCES)) as pool:
+        list(pool.map(compile_one, range(len(SOURCES))))
     tmp = LIB + ".tmp%d" % os.getpid()
     cmd = [hipcc, "--offload-arch=" + ARCH, "-shared", "-fPIC", *objs, "-o", tmp]
     if verbose:

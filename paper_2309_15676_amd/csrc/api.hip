@@ -248,6 +248,12 @@ struct jso_ctx {
   uint8_t* scratch = nullptr;  // this device's `scratch` (set up by jso_create)
 };
 
+namespace jso {
+// The context's stream and device, for the microbenchmarks (ubench.hip).
+hipStream_t ctx_stream(jso_ctx* c) { return c->stream; }
+int ctx_device(jso_ctx* c) { return c->device; }
+}  // namespace jso
+
 namespace {
 
 int fail(jso_ctx* c, int code, const char* fmt, ...) {

@@ -19,9 +19,7 @@ def test_bench_json_contract():
         pytest.skip("no GPU")
     print("[case] bench contract", flush=True)
     r = subprocess.run([sys.executable, os.path.join(ROOT, "bench.py"), "--steps", "3",
-                        "--warmup", "1", "--target-spp", "64", "--cpu-seconds", "1",
-                        "--ttl-iters", "0", "--batch-steps", "0", "--ablation-iters", "0",
-                        "--mesh-steps", "0", "--volume-steps", "0"],
+                        "--warmup", "1", "--large-target-spp", "4", "--no-extras"],
                        capture_output=True, text=True, timeout=600, cwd=ROOT)
     assert r.returncode == 0, r.stderr[-2000:]
     lines = [l for l in r.stdout.splitlines() if l.startswith("{")]
@@ -37,9 +35,18 @@ def test_bench_json_contract():
     npix = d["config"]["pixels"]
     assert abs(d["value"] - 4 * npix / (d["ms_per_step"] / 1e3)) <= 1e-6 * d["value"]
     assert "workload" in d["config"]
-    rf = d["roofline"]
-    assert rf["bound"] in ("hbm", "mfma", "alu") and rf["peak"] > 0
-    assert abs(rf["frac"] - rf["achieved"] / rf["peak"]) <= 1e-9
-    assert rf["traffic"] is None or rf["traffic"] > 0
+    assert d["config"]["triangles"] == 999698 and d["config"]["params"] == 1310720
+    for rf in (d["roofline"], d["roofline_other_kernel"]):
+        assert rf["bound"] in ("hbm", "mfma", "alu") and rf["peak"] > 0
+        assert rf["kernel"] in ("k_forward", "k_adjoint") and rf["kernel_ms"] > 0
+        assert rf["achieved"] is None or abs(rf["frac"] - rf["achieved"] / rf["peak"]) <= 1e-9
+    assert d["roofline"]["kernel_ms"] >= d["roofline_other_kernel"]["kernel_ms"]
+    assert d["roofline"]["traffic"] is None or d["roofline"]["traffic"] > 0
+    adj = [rf for rf in (d["roofline"], d["roofline_other_kernel"])
+           if rf["kernel"] == "k_adjoint"][0]
+    assert adj["bound"] == "hbm" and adj["achieved"] > 0 and adj["atomics_per_s"] > 0
+    ub = d["microbenchmarks"]
+    assert ub["copy_GBs"] > 1000
+    assert ub["atomic_ops_per_s_lines"] > 0 and ub["atomic_ops_per_s_same_address"] > 0
     cb = d["cpu_baseline"]
     assert cb["kind"] == "oracle" and cb["value"] > 0 and cb["cores"] >= 1 and cb["sample"]
