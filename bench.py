@@ -336,8 +336,9 @@ def batched_throughput(context, args):
     """64 independent problems of uneven size (image side 64-512, 5-65,536
     parameters, own seeds and iteration budgets): differentiable paths/s of
     one iteration for all of them, (a) as a batch replayed from a captured
-    HIP graph with the tile shape picked by the autotuner, (b) as one
-    jso_grad_step over all problems (one launch per kernel, tuned shape),
+    HIP graph with the launch configuration (tile shape, persistent grid)
+    picked by the autotuner, and the same launches issued directly, (b) as one
+    jso_grad_step over all problems (one launch per kernel, tuned configuration),
     (c) as one jso_grad_step per problem."""
     import torch
 
@@ -370,9 +371,13 @@ def batched_throughput(context, args):
         return e0.elapsed_time(e1) / steps
 
     b = Batch(probs, opts, max_iters=[c["max_iter"] for c in cfg], use_graph=True)
-    shape, shape_ms = b.autotune(3)  # state is restored after each trial
+    best, config_ms = b.autotune(3)  # state is restored after each trial
     ms_graph = timed(lambda n: b.step(n))
     b.close()
+    # direct launches of the batch (no graph), tuned configuration
+    b1 = Batch(probs, opts, max_iters=[c["max_iter"] for c in cfg], use_graph=False)
+    ms_direct = timed(lambda n: b1.step(n))
+    b1.close()
 
     def together(n):
         for _ in range(n):
@@ -393,9 +398,11 @@ def batched_throughput(context, args):
         "pixels": pixels,
         "params": sum(c["spec"].n_params for c in cfg),
         "steps": steps,
-        "autotune": {"tile": ["16x16", "16x8", "8x8"][shape],
-                     "ms_per_iteration": {t: m for t, m in zip(["16x16", "16x8", "8x8"], shape_ms)}},
-        "graph": {"ms_per_iteration": ms_graph, "paths_per_s": paths / (ms_graph / 1e3)},
+        "autotune": {"best": L.config_name(best),
+                     "ms_per_iteration": {L.config_name(c): m for c, m in enumerate(config_ms)}},
+        "graph": {"ms_per_iteration": ms_graph, "paths_per_s": paths / (ms_graph / 1e3),
+                  "config": L.config_name(best)},
+        "batch_direct_launches": {"ms_per_iteration": ms_direct, "config": L.config_name(best)},
         "one_launch_per_kernel": {"ms_per_iteration": ms_together,
                                   "paths_per_s": paths / (ms_together / 1e3)},
         "one_grad_step_per_problem": {"ms_per_iteration": ms_each,
@@ -813,7 +820,7 @@ def main():
     ap.add_argument("--gpus", type=int, default=1)
     ap.add_argument("--steps", type=int, default=30)
     ap.add_argument("--warmup", type=int, default=3)
-    ap.add_argument("--target-spp", type=int, default=256,
+    ap.add_argument("--target-spp", type=int, default=4096,
                     help="samples per pixel of the 512x512 target render")
     ap.add_argument("--large-target-spp", type=int, default=64,
                     help="samples per pixel of the 2048x2048 target render")

@@ -397,23 +397,31 @@ int jso_batch_step(jso_batch* b, int iterations);
 int jso_batch_active(jso_batch* b, int* active);
 int jso_batch_destroy(jso_batch* b);
 
-/* Pixel tiles of the path kernels: one workgroup traces one tile. */
+/* Launch configurations of the path kernels (forward tracing and replay):
+ * a pixel tile shape, one workgroup per tile ... */
 #define JSO_TILE_16x16 0 /* 256 lanes */
 #define JSO_TILE_16x8 1  /* 128 lanes */
 #define JSO_TILE_8x8 2   /* 64 lanes  */
 #define JSO_TILE_SHAPES 3
-/* Time `iterations` real iterations of the batch with each tile shape (the
- * problems' optimiser state is restored after each trial), keep the fastest
- * for this batch and remember it, for this GPU architecture and
- * configuration (image sizes, parameter layouts, sample counts), for every
- * later batch or jso_grad_step of the process with the same configuration.
- * best_shape (nullable) receives JSO_TILE_*; ms (nullable host array of
- * JSO_TILE_SHAPES) the milliseconds per iteration of each shape.  Waits for
- * the stream.  Errors: JSO_E_INVALID, JSO_E_OOM, JSO_E_HIP. */
-int jso_batch_autotune(jso_batch* b, int iterations, int* best_shape, double* ms);
-/* Tile shape used when the tuner has no entry for a configuration
- * (JSO_TILE_*, default JSO_TILE_16x16). */
-int jso_set_tile_shape(jso_ctx* ctx, int shape);
+/* ... and a grid: configuration c uses tile shape c % JSO_TILE_SHAPES and,
+ * for c >= JSO_TILE_SHAPES, a persistent grid of {1, 2, 4, 8}[c / 3 - 1]
+ * workgroups per compute unit that pull tiles from a work queue (in steps
+ * and batches; single renders always launch one workgroup per tile).
+ * Configurations 0-2 are the plain grids of the three tile shapes. */
+#define JSO_LAUNCH_CONFIGS 15
+/* Time `iterations` real iterations of the batch with each launch
+ * configuration (the problems' optimiser state is restored after each
+ * trial), keep the fastest for this batch and remember it, for this GPU
+ * architecture and configuration (image sizes, parameter layouts, sample
+ * counts), for every later batch or jso_grad_step of the process with the
+ * same configuration.  best_config (nullable) receives the configuration; ms
+ * (nullable host array of JSO_LAUNCH_CONFIGS) the milliseconds per iteration
+ * of each.  Waits for the stream.  Errors: JSO_E_INVALID, JSO_E_OOM,
+ * JSO_E_HIP. */
+int jso_batch_autotune(jso_batch* b, int iterations, int* best_config, double* ms);
+/* Launch configuration used when the tuner has no entry for a configuration
+ * (0 .. JSO_LAUNCH_CONFIGS - 1, default 0: 16x16 tiles, one per workgroup). */
+int jso_set_launch_config(jso_ctx* ctx, int config);
 
 /* ---- kernel timing --------------------------------------------------------------- */
 

@@ -41,13 +41,22 @@ EXPORTED = [
     "jso_meta_step", "jso_adam_step", "jso_grad_step", "jso_get_state", "jso_set_state",
     "jso_set_timing", "jso_get_kernel_time", "jso_set_work_counting", "jso_get_work",
     "jso_batch_create", "jso_batch_step", "jso_batch_active", "jso_batch_destroy",
-    "jso_batch_autotune", "jso_set_tile_shape", "jso_precondition", "jso_render_bwd_noalloc",
+    "jso_batch_autotune", "jso_set_launch_config", "jso_precondition", "jso_render_bwd_noalloc",
     "jso_ub_copy", "jso_ub_atomics",
 ]
 JSO_UB_RANDOM, JSO_UB_LINES, JSO_UB_16, JSO_UB_SAME = 0, 1, 2, 3
 JSO_NOALLOC_SCRATCH_BYTES = 128 << 20
 JSO_NOALLOC_MAX_PIXELS = JSO_NOALLOC_SCRATCH_BYTES // 24
 JSO_TILE_16x16, JSO_TILE_16x8, JSO_TILE_8x8, JSO_TILE_SHAPES = 0, 1, 2, 3
+JSO_LAUNCH_CONFIGS = 15
+PERSIST_PER_CU = (0, 1, 2, 4, 8)
+
+
+def config_name(c: int) -> str:
+    """Tile shape and grid of launch configuration c."""
+    tile = ("16x16", "16x8", "8x8")[c % JSO_TILE_SHAPES]
+    p = PERSIST_PER_CU[c // JSO_TILE_SHAPES]
+    return tile + (" persistent x%d" % p if p else "")
 JSO_K_FORWARD, JSO_K_ADJOINT, JSO_K_META, JSO_K_ADAM, JSO_K_FINALIZE = 0, 1, 2, 3, 4
 JSO_K_PRECOND = 5
 JSO_K_COUNT = 6
@@ -167,7 +176,7 @@ def load() -> ctypes.CDLL:
         "jso_batch_active": (I, [P, ctypes.POINTER(I)]),
         "jso_batch_destroy": (I, [P]),
         "jso_batch_autotune": (I, [P, I, ctypes.POINTER(I), ctypes.POINTER(D)]),
-        "jso_set_tile_shape": (I, [P, I]),
+        "jso_set_launch_config": (I, [P, I]),
         "jso_precondition": (I, [P, I, P, F]),
     }
     for name, (res, args) in sig.items():
@@ -474,16 +483,16 @@ def jso_batch_active(ctx, batch) -> int:
 
 
 def jso_batch_autotune(ctx, batch, iterations: int = 3):
-    """(best tile shape, ms per iteration of each shape)."""
+    """Returns (best launch configuration, [ms per iteration of each])."""
     best = ctypes.c_int(0)
-    ms = (ctypes.c_double * JSO_TILE_SHAPES)()
+    ms = (ctypes.c_double * JSO_LAUNCH_CONFIGS)()
     check(load().jso_batch_autotune(batch, iterations, ctypes.byref(best), ms), ctx,
           "jso_batch_autotune")
     return best.value, list(ms)
 
 
-def jso_set_tile_shape(ctx, shape: int) -> None:
-    check(load().jso_set_tile_shape(ctx, shape), ctx, "jso_set_tile_shape")
+def jso_set_launch_config(ctx, config: int) -> None:
+    check(load().jso_set_launch_config(ctx, config), ctx, "jso_set_launch_config")
 
 
 def jso_batch_destroy(batch) -> int:

@@ -207,6 +207,7 @@ struct CachedLaunch {
   bool shared, vol;
   uint32_t blocks;
   size_t lds, offset;
+  int persist;
 };
 
 struct CachedPlan {
@@ -214,6 +215,7 @@ struct CachedPlan {
   std::vector<CachedLaunch> launches;
   uint8_t* dev = nullptr;   // unit arrays
   uint8_t* host = nullptr;  // pinned staging copy (source of the upload)
+  uint32_t* queues = nullptr;  // two work-queue counters per launch (persistent launches)
   uint64_t last_use = 0;
 };
 
@@ -224,7 +226,9 @@ struct PlanCache {
   static void release(CachedPlan& p) {
     if (p.dev) (void)hipFree(p.dev);
     if (p.host) (void)hipHostFree(p.host);
+    if (p.queues) (void)hipFree(p.queues);
     p.dev = p.host = nullptr;
+    p.queues = nullptr;
   }
   void destroy() {
     for (CachedPlan& p : plans) release(p);
@@ -236,7 +240,8 @@ struct jso_ctx {
   DescRing ring;
   PlanCache plan_cache;
   std::string arch;     // gcnArchName of the device
-  int tile_shape = 0;   // default tile shape when the tuner has no entry
+  int launch_config = 0;  // default launch configuration when the tuner has no entry
+  int n_cu = 0;           // compute units of the device
   int device = 0;
   hipStream_t stream = nullptr;  // nullptr = the device's null (default) stream
   uint32_t debug_flags = 0;
@@ -615,6 +620,15 @@ hipMemcpyKind kind_from_dev(int mem) {
 // the same estimator configuration: each launch carries one unit per problem
 // (or per slice group), so a single launch serves all of them.
 // ---------------------------------------------------------------------------
+// A launch configuration of the path kernels: a tile shape (kShapeW/kShapeH)
+// and a persistent grid of kPersistPerCU[...] blocks per compute unit pulling
+// tiles from a work queue (0: one block per tile).
+constexpr int kPersistPerCU[] = {0, 1, 2, 4, 8};
+constexpr int kConfigs = kShapes * (int)(sizeof(kPersistPerCU) / sizeof(int));
+static_assert(kConfigs == JSO_LAUNCH_CONFIGS, "launch configurations");
+int shape_of(int config) { return config % kShapes; }
+int persist_of(int config) { return kPersistPerCU[config / kShapes]; }
+
 struct PrimalSpec {
   const float* params;
   uint32_t tag;
@@ -671,6 +685,7 @@ struct LaunchRec {
   int stack = 0;               // path kernels: BVH stack entries (deepest mesh of the units)
   bool shared = false;         // path kernels: units hold shared-path pair slices
   bool vol = false;            // path kernels: the units' scenes are volumes
+  int persist = 0;             // path kernels: persistent blocks per CU (0: none)
   size_t dev_offset = 0;       // batches: offset of the units in the device arena
 };
 
@@ -698,8 +713,9 @@ bool crop_empty(const Crop& c) { return c.x1 <= c.x0 || c.y1 <= c.y0; }
 // The launches of the estimator part of a step for problems `ps` (all with the
 // same job structure), with pixel tiles of the given shape and at most
 // max_slots radiance slots per pixel per launch (a replay pair needs 2).
-void plan_estimators(const std::vector<ProbPlan>& ps, Plan& plan, int shape = 0,
+void plan_estimators(const std::vector<ProbPlan>& ps, Plan& plan, int config = 0,
                      int max_slots = kMaxSlots) {
+  const int shape = shape_of(config);
   if (ps.empty()) return;
   const ProbPlan& p0 = ps[0];
   // primal samples in job order; replay units, pairs first: within a launch
@@ -782,6 +798,7 @@ void plan_estimators(const std::vector<ProbPlan>& ps, Plan& plan, int shape = 0,
     fw.timer = JSO_K_FORWARD;
     fw.shape = shape;
     fw.vol = p0.s->dev.layout == JSO_LAYOUT_VOLUME;
+    fw.persist = fw.vol ? 0 : persist_of(config);
     for (const ProbPlan& p : ps) {
       if (crop_empty(p.crop)) continue;
       FwdArgs f{};
@@ -881,6 +898,7 @@ void plan_estimators(const std::vector<ProbPlan>& ps, Plan& plan, int shape = 0,
       ad.lds = adjoint_lds_bytes(max_ch);
       ad.shared = shared_pairs;
       ad.vol = p0.s->dev.layout == JSO_LAYOUT_VOLUME;
+      ad.persist = ad.vol ? 0 : persist_of(config);
       for (int pass = 0; pass < 2; ++pass) {
         for (const ProbPlan& p : ps) {
           if (crop_empty(p.crop)) continue;
@@ -1202,15 +1220,20 @@ int check_precond_layout(jso_ctx* c, const std::vector<SceneGPU*>& ss, const jso
   return JSO_OK;
 }
 
+// queue: the launch's two work-queue counters when its configuration is
+// persistent (null: one block per tile whatever the configuration)
 hipError_t launch_rec(const LaunchRec& r, const void* dev_units, unsigned long long* work,
-                      hipStream_t st) {
+                      hipStream_t st, uint32_t* queue = nullptr, int n_cu = 0) {
+  const bool persistent = queue && r.persist > 0 && n_cu > 0;
+  uint32_t* q = persistent ? queue : nullptr;
+  const uint32_t grid = persistent ? (uint32_t)(r.persist * n_cu) : 0u;
   switch (r.kind) {
     case Kern::Forward:
       if (r.vol)
         return launch_vol_forward(static_cast<const FwdArgs*>(dev_units), r.n, r.blocks, r.shape,
                                   work, st);
       return launch_forward(static_cast<const FwdArgs*>(dev_units), r.n, r.blocks, r.shape,
-                            r.stack, r.shared, work, st);
+                            r.stack, r.shared, work, st, q, grid);
     case Kern::Finalize:
       return launch_finalize(static_cast<const FinArgs*>(dev_units), r.n, r.blocks, st);
     case Kern::Adjoint:
@@ -1218,7 +1241,7 @@ hipError_t launch_rec(const LaunchRec& r, const void* dev_units, unsigned long l
         return launch_vol_adjoint(static_cast<const RepArgs*>(dev_units), r.n, r.blocks, r.shape,
                                   work, st);
       return launch_adjoint(static_cast<const RepArgs*>(dev_units), r.n, r.blocks, r.shape, r.lds,
-                            r.stack, r.shared, work, st);
+                            r.stack, r.shared, work, st, q, grid);
     case Kern::Meta:
       return launch_meta(static_cast<const MetaArgs*>(dev_units), r.n, r.blocks, st);
     case Kern::Adam:
@@ -1257,10 +1280,10 @@ uint64_t config_hash(const std::vector<SceneGPU*>& ss, const jso_step_opts& o) {
   return h;
 }
 
-int chosen_shape(jso_ctx* c, uint64_t hash) {
+int chosen_config(jso_ctx* c, uint64_t hash) {
   std::lock_guard<std::mutex> lock(g_tuned_mu);
   auto it = g_tuned.find({c->arch, hash});
-  return it != g_tuned.end() ? it->second : c->tile_shape;
+  return it != g_tuned.end() ? it->second : c->launch_config;
 }
 
 // Run a plan now: each launch's units are staged through the context's ring.
@@ -1310,11 +1333,15 @@ int exec_cached(jso_ctx* c, const std::vector<uint64_t>& sig, Build build) {
       pc.plans.erase(pc.plans.begin() + (long)lru);
     }
     CachedPlan np;
+    const size_t nq = 2 * plan.size();
     if (hipHostMalloc(reinterpret_cast<void**>(&np.host), all.size(), 0) != hipSuccess ||
-        hipMalloc(reinterpret_cast<void**>(&np.dev), all.size()) != hipSuccess) {
+        hipMalloc(reinterpret_cast<void**>(&np.dev), all.size()) != hipSuccess ||
+        hipMalloc(reinterpret_cast<void**>(&np.queues), nq * sizeof(uint32_t)) != hipSuccess) {
       PlanCache::release(np);
       return fail(c, JSO_E_OOM, "launch descriptors");
     }
+    // zeroed by a kernel (not a memset node, should a caller capture the step)
+    HIP_TRY(c, launch_fill_f32(reinterpret_cast<float*>(np.queues), nq, 0.0f, c->stream));
     std::memcpy(np.host, all.data(), all.size());
     const hipError_t e =
         hipMemcpyAsync(np.dev, np.host, all.size(), hipMemcpyHostToDevice, c->stream);
@@ -1326,7 +1353,7 @@ int exec_cached(jso_ctx* c, const std::vector<uint64_t>& sig, Build build) {
       const LaunchRec& r = plan[k];
       np.launches.push_back(
           CachedLaunch{(int)r.kind, r.timer, r.shape, r.n, r.stack, r.shared, r.vol, r.blocks,
-                       r.lds, off[k]});
+                       r.lds, off[k], r.persist});
     }
     np.sig = sig;
     pc.plans.push_back(std::move(np));
@@ -1334,7 +1361,8 @@ int exec_cached(jso_ctx* c, const std::vector<uint64_t>& sig, Build build) {
   }
   hit->last_use = ++pc.clock;
   unsigned long long* work = c->counting ? c->d_work : nullptr;
-  for (const CachedLaunch& l : hit->launches) {
+  for (size_t k = 0; k < hit->launches.size(); ++k) {
+    const CachedLaunch& l = hit->launches[k];
     if (l.n == 0) continue;
     LaunchRec r;
     r.kind = (Kern)l.kind;
@@ -1345,7 +1373,9 @@ int exec_cached(jso_ctx* c, const std::vector<uint64_t>& sig, Build build) {
     r.stack = l.stack;
     r.shared = l.shared;
     r.vol = l.vol;
-    TIMED_LAUNCH(c, l.timer, launch_rec(r, hit->dev + l.offset, work, c->stream));
+    r.persist = l.persist;
+    TIMED_LAUNCH(c, l.timer, launch_rec(r, hit->dev + l.offset, work, c->stream,
+                                        hit->queues + 2 * k, c->n_cu));
   }
   return JSO_OK;
 }
@@ -1391,7 +1421,10 @@ int jso_create(jso_ctx** out, int device, void* stream) {
   c->device = device;
   c->stream = (hipStream_t)stream;
   hipDeviceProp_t prop;
-  if (hipGetDeviceProperties(&prop, device) == hipSuccess) c->arch = prop.gcnArchName;
+  if (hipGetDeviceProperties(&prop, device) == hipSuccess) {
+    c->arch = prop.gcnArchName;
+    c->n_cu = prop.multiProcessorCount;
+  }
   {
     // set-up of what the no-allocation entry point uses: the device address
     // of this GPU's scratch array and the descriptor ring
@@ -1594,7 +1627,7 @@ int jso_render(jso_ctx* c, int id, const float* params, uint64_t seed, uint32_t 
   p.flags = c->debug_flags | (opts ? opts->flags : 0u);
   p.pj[p.np++] = PrimalSpec{params, tag, spp, img, nullptr, nullptr};
   Plan plan;
-  plan_estimators({p}, plan, c->tile_shape);
+  plan_estimators({p}, plan, c->launch_config);
   return exec_plan(c, plan);
 }
 
@@ -1615,7 +1648,7 @@ int jso_render_bwd(jso_ctx* c, int id, const float* params, uint64_t seed, uint3
   p.flags = c->debug_flags | (opts ? opts->flags : 0u);
   p.aj[p.na++] = AdjointSpec{params, nullptr, dimg, nullptr, dparams, 1.0f, tag, spp};
   Plan plan;
-  plan_estimators({p}, plan, c->tile_shape);
+  plan_estimators({p}, plan, c->launch_config);
   return exec_plan(c, plan);
 }
 
@@ -1647,7 +1680,7 @@ int jso_render_bwd_noalloc(jso_ctx* c, int id, const float* params, uint64_t see
   p.aj[p.na++] = AdjointSpec{params, nullptr, dimg, nullptr, dparams, 1.0f, tag, spp};
   p.slots = reinterpret_cast<double*>(c->scratch);
   Plan plan;
-  plan_estimators({p}, plan, c->tile_shape, max_slots);
+  plan_estimators({p}, plan, c->launch_config, max_slots);
   // every slot a replay reads is written by the forward launch before it (same
   // pixels, same crop and mask), so the scratch needs no clearing
   return exec_plan(c, plan);
@@ -1675,7 +1708,7 @@ int jso_estimate_gradients(jso_ctx* c, int id, uint64_t seed, uint32_t iteration
                                     opts ? opts->pixel_mask : nullptr,
                                     c->debug_flags | (opts ? opts->flags : 0u), lossk,
                                     fd_mode)},
-                  plan, c->tile_shape);
+                  plan, c->launch_config);
   int rc = exec_plan(c, plan);
   if (rc) return rc;
   if (loss) {
@@ -1787,8 +1820,8 @@ int jso_grad_step(jso_ctx* c, const int* ids, int n, const jso_step_opts* o,
   }
   rc = check_precond_layout(c, ss, *o);
   if (rc) return rc;
-  const int shape = chosen_shape(c, config_hash(ss, *o));
-  sig.push_back((uint64_t)shape);
+  const int config = chosen_config(c, config_hash(ss, *o));
+  sig.push_back((uint64_t)config);
   for (uint64_t v : {(uint64_t)o->optimizer, bits(o->eta), bits(o->beta_F), bits(o->beta_D),
                      (uint64_t)o->spp_prop, (uint64_t)o->spp_fd, bits(o->adam_beta1),
                      bits(o->adam_beta2), bits(o->adam_eps), (uint64_t)o->adam_spp, o->seed,
@@ -1801,8 +1834,8 @@ int jso_grad_step(jso_ctx* c, const int* ids, int n, const jso_step_opts* o,
       ps.push_back(step_problem(get_scene(c, ids[k]), *o, flags, 0));
       if (uncorrelated(*o)) pv.push_back(variance_problem(get_scene(c, ids[k]), *o, flags, 0));
     }
-    plan_estimators(ps, plan, shape);
-    if (!pv.empty()) plan_estimators(pv, plan, shape);
+    plan_estimators(ps, plan, config);
+    if (!pv.empty()) plan_estimators(pv, plan, config);
     plan_precond(ps, *o, plan);
     plan_optimizer(ps, *o, plan);
   });
@@ -1824,10 +1857,11 @@ struct jso_batch {
   jso_step_opts opts{};
   uint32_t flags = 0;
   bool use_graph = false;
-  int shape = 0;
+  int config = 0;
   uint64_t hash = 0;
   Plan plan;
   uint8_t* dev = nullptr;  // unit arrays of the plan
+  uint32_t* queues = nullptr;  // two work-queue counters per launch
   std::vector<size_t> off;
   hipStream_t capture = nullptr;
   hipGraph_t graph = nullptr;
@@ -1840,9 +1874,11 @@ void batch_release(jso_batch* b) {
   if (b->exec) (void)hipGraphExecDestroy(b->exec);
   if (b->graph) (void)hipGraphDestroy(b->graph);
   if (b->dev) (void)hipFree(b->dev);
+  if (b->queues) (void)hipFree(b->queues);
   b->exec = nullptr;
   b->graph = nullptr;
   b->dev = nullptr;
+  b->queues = nullptr;
   b->plan.clear();
   b->off.clear();
 }
@@ -1857,18 +1893,18 @@ int batch_launch_all(jso_batch* b, hipStream_t st) {
   for (size_t k = 0; k < b->plan.size(); ++k) {
     const LaunchRec& r = b->plan[k];
     if (r.n == 0) continue;
-    HIP_TRY(b->c, launch_rec(r, b->dev + b->off[k], nullptr, st));
+    HIP_TRY(b->c, launch_rec(r, b->dev + b->off[k], nullptr, st, b->queues + 2 * k, b->c->n_cu));
   }
   return JSO_OK;
 }
 
 // (Re)build the batch's plan for a tile shape: descriptors uploaded once, the
 // iteration captured in a graph when requested.
-int batch_build(jso_batch* b, int shape) {
+int batch_build(jso_batch* b, int config) {
   jso_ctx* c = b->c;
   HIP_TRY(c, hipStreamSynchronize(c->stream));  // the old descriptors may be in use
   batch_release(b);
-  b->shape = shape;
+  b->config = config;
   std::vector<ProbPlan> ps, pv;
   for (size_t k = 0; k < b->ids.size(); ++k) {
     SceneGPU* s = get_scene(c, b->ids[k]);
@@ -1876,13 +1912,15 @@ int batch_build(jso_batch* b, int shape) {
     ps.push_back(step_problem(s, b->opts, b->flags, b->max_iters[k]));
     if (uncorrelated(b->opts)) pv.push_back(variance_problem(s, b->opts, b->flags, b->max_iters[k]));
   }
-  plan_estimators(ps, b->plan, shape);
-  if (!pv.empty()) plan_estimators(pv, b->plan, shape);
+  plan_estimators(ps, b->plan, config);
+  if (!pv.empty()) plan_estimators(pv, b->plan, config);
   plan_precond(ps, b->opts, b->plan);
   plan_optimizer(ps, b->opts, b->plan);
   const std::vector<uint8_t> all = pack_plan(b->plan, b->off);
   HIP_TRY(c, hipMalloc(reinterpret_cast<void**>(&b->dev), all.size()));
   HIP_TRY(c, hipMemcpy(b->dev, all.data(), all.size(), hipMemcpyHostToDevice));
+  HIP_TRY(c, hipMalloc(reinterpret_cast<void**>(&b->queues), 2 * b->plan.size() * sizeof(uint32_t)));
+  HIP_TRY(c, hipMemset(b->queues, 0, 2 * b->plan.size() * sizeof(uint32_t)));  // before any capture
   if (b->use_graph) {
     // capture on a private stream; replays run on the context's stream
     if (!b->capture) HIP_TRY(c, hipStreamCreateWithFlags(&b->capture, hipStreamNonBlocking));
@@ -1981,7 +2019,7 @@ int jso_batch_create(jso_ctx* c, const int* ids, int n, const jso_step_opts* o,
   rc = check_precond_layout(c, ss, *o);
   if (rc) return rc;
   b->hash = config_hash(ss, *o);
-  rc = batch_build(b.get(), chosen_shape(c, b->hash));
+  rc = batch_build(b.get(), chosen_config(c, b->hash));
   if (rc) return rc;
   *out = b.release();
   return JSO_OK;
@@ -1995,7 +2033,7 @@ int jso_batch_step(jso_batch* b, int iterations) {
   return batch_run(b, iterations);
 }
 
-int jso_batch_autotune(jso_batch* b, int iterations, int* best_shape, double* ms) {
+int jso_batch_autotune(jso_batch* b, int iterations, int* best_config, double* ms) {
   if (!b) return JSO_E_INVALID;
   jso_ctx* c = b->c;
   if (iterations < 1) return fail(c, JSO_E_INVALID, "iterations < 1");
@@ -2008,12 +2046,12 @@ int jso_batch_autotune(jso_batch* b, int iterations, int* best_shape, double* ms
   std::unique_ptr<void, void (*)(void*)> g0(e0, [](void* e) { (void)hipEventDestroy((hipEvent_t)e); });
   HIP_TRY(c, hipEventCreate(&e1));
   std::unique_ptr<void, void (*)(void*)> g1(e1, [](void* e) { (void)hipEventDestroy((hipEvent_t)e); });
-  int best = b->shape;
+  int best = b->config;
   float best_ms = 0.0f;
-  for (int shape = 0; shape < kShapes; ++shape) {
-    rc = batch_build(b, shape);
+  for (int config = 0; config < kConfigs; ++config) {
+    rc = batch_build(b, config);
     if (rc) return rc;
-    rc = batch_run(b, 1);  // warm-up (first launches of this shape)
+    rc = batch_run(b, 1);  // warm-up (first launches of this configuration)
     if (rc) return rc;
     HIP_TRY(c, hipEventRecord(e0, c->stream));
     rc = batch_run(b, iterations);
@@ -2022,9 +2060,9 @@ int jso_batch_autotune(jso_batch* b, int iterations, int* best_shape, double* ms
     HIP_TRY(c, hipEventSynchronize(e1));
     float t = 0.0f;
     HIP_TRY(c, hipEventElapsedTime(&t, e0, e1));
-    if (ms) ms[shape] = t / (float)iterations;
-    if (shape == 0 || t < best_ms) {
-      best = shape;
+    if (ms) ms[config] = t / (float)iterations;
+    if (config == 0 || t < best_ms) {
+      best = config;
       best_ms = t;
     }
     rc = restore(c, sc);
@@ -2037,14 +2075,15 @@ int jso_batch_autotune(jso_batch* b, int iterations, int* best_shape, double* ms
   rc = batch_build(b, best);
   if (rc) return rc;
   HIP_TRY(c, hipStreamSynchronize(c->stream));
-  if (best_shape) *best_shape = best;
+  if (best_config) *best_config = best;
   return JSO_OK;
 }
 
-int jso_set_tile_shape(jso_ctx* c, int shape) {
+int jso_set_launch_config(jso_ctx* c, int config) {
   if (!c) return JSO_E_INVALID;
-  if (shape < 0 || shape >= kShapes) return fail(c, JSO_E_INVALID, "tile shape %d", shape);
-  c->tile_shape = shape;
+  if (config < 0 || config >= kConfigs)
+    return fail(c, JSO_E_INVALID, "launch configuration %d", config);
+  c->launch_config = config;
   return JSO_OK;
 }
 

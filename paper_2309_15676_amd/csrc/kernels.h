@@ -224,12 +224,16 @@ hipError_t launch_dct(const DctArgs* U, int n, uint32_t blocks, hipStream_t st);
 // units' scenes; 0 = no scene of the launch has a mesh), at most kBvhMaxStack
 // shared: the units may hold shared-path pair slices (forward: params_b set;
 // adjoint: pair slices are then all shared-path pairs, none a replay pair)
+// queue (nullable): a persistent launch of min(blocks, persist) blocks that
+// pull the `blocks` tiles from queue[0..1] (two zeroed counters, left zeroed)
 hipError_t launch_forward(const FwdArgs* U, int n, uint32_t blocks, int shape, int stack,
-                          bool shared, unsigned long long* work, hipStream_t st);
+                          bool shared, unsigned long long* work, hipStream_t st,
+                          uint32_t* queue = nullptr, uint32_t persist = 0);
 hipError_t launch_finalize(const FinArgs* U, int n, uint32_t blocks, hipStream_t st);
 // lds: dynamic LDS bytes (adjoint_lds_bytes of the largest channel count)
 hipError_t launch_adjoint(const RepArgs* U, int n, uint32_t blocks, int shape, size_t lds,
-                          int stack, bool shared, unsigned long long* work, hipStream_t st);
+                          int stack, bool shared, unsigned long long* work, hipStream_t st,
+                          uint32_t* queue = nullptr, uint32_t persist = 0);
 // The same for emission-absorption volume scenes (every unit's scene a volume;
 // parameter buffers 16-byte aligned)
 hipError_t launch_vol_forward(const FwdArgs* U, int n, uint32_t blocks, int shape,

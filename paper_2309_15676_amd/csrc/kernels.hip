@@ -80,10 +80,9 @@ struct Shape {
   static_assert(N % 64 == 0 && (TW & (TW - 1)) == 0, "tile shape");
 };
 
-// The unit owning this block: the last one whose block0 <= blockIdx.x.
+// The unit owning grid block b: the last one whose block0 <= b.
 template <class U>
-__device__ __forceinline__ const U& unit_of(const U* __restrict__ u, int n) {
-  const uint32_t b = blockIdx.x;
+__device__ __forceinline__ const U& unit_of(const U* __restrict__ u, int n, uint32_t b) {
   int lo = 0, hi = n - 1;
   while (lo < hi) {
     const int mid = (lo + hi + 1) >> 1;
@@ -92,6 +91,10 @@ __device__ __forceinline__ const U& unit_of(const U* __restrict__ u, int n) {
   }
   return u[lo];
 }
+template <class U>
+__device__ __forceinline__ const U& unit_of(const U* __restrict__ u, int n) {
+  return unit_of(u, n, blockIdx.x);
+}
 
 // A path unit's block: its slice and its tile's pixel origin.
 struct TileBlock {
@@ -99,8 +102,8 @@ struct TileBlock {
 };
 
 template <class SH, class U>
-__device__ __forceinline__ TileBlock tile_block(const U& u) {
-  const uint32_t local = blockIdx.x - u.h.block0;
+__device__ __forceinline__ TileBlock tile_block(const U& u, uint32_t b) {
+  const uint32_t local = b - u.h.block0;
   const uint32_t t = local % u.tiles;
   return TileBlock{(int)(local / u.tiles), u.crop.x0 + (int)(t % u.tiles_x) * SH::W,
                    u.crop.y0 + (int)(t / u.tiles_x) * SH::H};
@@ -126,7 +129,7 @@ __device__ __forceinline__ bool tile_pixel(const Crop& c, const TileBlock& tb, i
 // identity of the lane it came from (src), so it draws the same random
 // numbers and writes to the same pixel.
 // ---------------------------------------------------------------------------
-constexpr int kXchg = 64;  // paths per exchange round
+constexpr int kXchg = 32;  // paths per exchange round
 // Survivors are packed only when that frees at least one wave (a one-wave
 // block never packs).
 template <class SH>
@@ -322,6 +325,39 @@ __device__ __forceinline__ void forward_tile(const FwdArgs& A, const DevScene* _
   count_work(work ? work + 2 : nullptr, active ? 1 : 0, n_vert);
 }
 
+// ---------------------------------------------------------------------------
+// persistent launches
+//
+// With a work queue (queue != null) a path kernel runs a fixed grid whose
+// blocks pull grid-block indices (tiles of units) from queue[0] until `total`
+// are taken; the last block to finish resets queue[0] and queue[1] (the count
+// of finished blocks) to zero for the next launch.  Without one, block b is
+// blockIdx.x as usual.  The barriers of the pull also separate one tile's use
+// of the block's LDS from the next tile's: waves that leave a tile early wait
+// there for the others.
+// ---------------------------------------------------------------------------
+__device__ __forceinline__ bool next_block(uint32_t* queue, uint32_t total, uint32_t* s_vb,
+                                           bool first, uint32_t& vb) {
+  if (!queue) {
+    vb = blockIdx.x;
+    return first;
+  }
+  if (threadIdx.x == 0) *s_vb = atomicAdd(queue, 1u);
+  __syncthreads();
+  vb = *s_vb;
+  __syncthreads();  // every lane has read it before lane 0 takes the next
+  return vb < total;
+}
+
+__device__ __forceinline__ void queue_done(uint32_t* queue) {
+  if (!queue || threadIdx.x != 0) return;
+  __threadfence();
+  if (atomicAdd(queue + 1, 1u) == gridDim.x - 1) {
+    atomicExch(queue, 0u);
+    atomicExch(queue + 1, 0u);
+  }
+}
+
 // kMesh: the launch's scenes may hold a triangle mesh; the dynamic LDS then
 // holds `stack` traversal-stack entries per lane.
 // kShared: the launch may hold shared-path pair slices (the other launches
@@ -332,20 +368,26 @@ __device__ __forceinline__ void forward_tile(const FwdArgs& A, const DevScene* _
 template <int TW, int TH, bool kMesh, bool kShared>
 __global__ void __launch_bounds__(TW * TH)
 __attribute__((amdgpu_waves_per_eu(kMesh && !kShared ? 5 : 4)))
-k_forward(const FwdArgs* __restrict__ Units, int n_units, int stack, unsigned long long* work) {
+k_forward(const FwdArgs* __restrict__ Units, int n_units, int stack, unsigned long long* work,
+          uint32_t* queue, uint32_t total) {
   using SH = Shape<TW, TH>;
   __shared__ uint32_t s_xchg[(kShared ? kFwd2XchgWords : kFwdXchgWords) * kXchg];
   __shared__ int s_cnt[SH::WAVES];
+  __shared__ uint32_t s_vb;
   extern __shared__ uint32_t s_dyn[];
-  const FwdArgs& A = unit_of(Units, n_units);
-  const uint32_t iter = iteration_of(A.key);
-  if (A.h.max_iter && iter >= A.h.max_iter) return;  // finished problem
   const TravStack st{s_dyn + threadIdx.x, SH::N, stack};
-  const TileBlock tb = tile_block<SH>(A);
-  if (kShared && G(A.sl[tb.slice].params_b) != nullptr)  // uniform over the block
-    forward_tile<SH, kMesh, kShared>(A, G(A.scene), tb, iter, s_xchg, s_cnt, st, work);
-  else
-    forward_tile<SH, kMesh, false>(A, G(A.scene), tb, iter, s_xchg, s_cnt, st, work);
+  uint32_t b;
+  for (bool first = true; next_block(queue, total, &s_vb, first, b); first = false) {
+    const FwdArgs& A = unit_of(Units, n_units, b);
+    const uint32_t iter = iteration_of(A.key);
+    if (A.h.max_iter && iter >= A.h.max_iter) continue;  // finished problem
+    const TileBlock tb = tile_block<SH>(A, b);
+    if (kShared && G(A.sl[tb.slice].params_b) != nullptr)  // uniform over the block
+      forward_tile<SH, kMesh, kShared>(A, G(A.scene), tb, iter, s_xchg, s_cnt, st, work);
+    else
+      forward_tile<SH, kMesh, false>(A, G(A.scene), tb, iter, s_xchg, s_cnt, st, work);
+  }
+  queue_done(queue);
 }
 
 // ---------------------------------------------------------------------------
@@ -423,12 +465,17 @@ __global__ void __launch_bounds__(kFinBlock) k_finalize(const FinArgs* __restric
 // atomic at the end.  A congested probe sequence falls back to a direct
 // global atomic, so the table can never lose a contribution.
 // ---------------------------------------------------------------------------
-constexpr int kTableBits = 10;
+constexpr int kTableBits = 8;
 constexpr int kTableSize = 1 << kTableBits;  // texels per block table
 constexpr int kMaxProbe = 32;
 constexpr uint32_t kEmpty = 0xFFFFFFFFu;
-// LDS per block (dynamic): kTableSize * 4 * (1 + n_ch) bytes, 20 KiB for
-// RGB + roughness.  Only first vertices (one tile's footprint) enter it.
+// LDS per block (dynamic): kTableSize * 4 * (1 + n_ch) bytes, 5 KiB for
+// RGB + roughness.  Only first vertices (one tile's footprint: some 25-100
+// texels in the workloads here) enter it.  A block keeps its LDS until its
+// last wave ends, so after the compaction leaves most blocks with one or two
+// waves, LDS bounds the blocks a CU holds: 256 slots instead of 1024 made the
+// terrain replay 15% faster (31% with shared-path pairs); past 256 the table
+// has no use.
 
 struct GradTable {
   uint32_t* keys;  // LDS: texel index of each slot
@@ -894,20 +941,26 @@ __device__ __forceinline__ void adjoint_tile_shared(const RepArgs& A,
 template <int TW, int TH, bool kMesh, bool kShared>
 __global__ void __launch_bounds__(TW * TH)
 __attribute__((amdgpu_waves_per_eu(kShared ? 4 : 3)))
-k_adjoint(const RepArgs* __restrict__ Units, int n_units, int stack, unsigned long long* work) {
+k_adjoint(const RepArgs* __restrict__ Units, int n_units, int stack, unsigned long long* work,
+          uint32_t* queue, uint32_t total) {
   using SH = Shape<TW, TH>;
   extern __shared__ uint32_t s_dyn[];
   __shared__ int s_cnt[SH::WAVES];
-  const RepArgs& A = unit_of(Units, n_units);
-  const uint32_t iter = iteration_of(A.key);
-  if (A.h.max_iter && iter >= A.h.max_iter) return;  // finished problem
+  __shared__ uint32_t s_vb;
   const TravStack st{s_dyn + threadIdx.x, SH::N, stack};
-  const TileBlock tb = tile_block<SH>(A);
   uint32_t* lds = s_dyn + (kMesh ? stack * SH::N : 0);
-  if (kShared && G(A.sl[tb.slice].params_b) != nullptr)  // uniform over the block
-    adjoint_tile_shared<SH, kMesh>(A, G(A.scene), tb, iter, lds, s_cnt, st, work);
-  else
-    adjoint_tile<SH, kMesh, !kShared>(A, G(A.scene), tb, iter, lds, s_cnt, st, work);
+  uint32_t b;
+  for (bool first = true; next_block(queue, total, &s_vb, first, b); first = false) {
+    const RepArgs& A = unit_of(Units, n_units, b);
+    const uint32_t iter = iteration_of(A.key);
+    if (A.h.max_iter && iter >= A.h.max_iter) continue;  // finished problem
+    const TileBlock tb = tile_block<SH>(A, b);
+    if (kShared && G(A.sl[tb.slice].params_b) != nullptr)  // uniform over the block
+      adjoint_tile_shared<SH, kMesh>(A, G(A.scene), tb, iter, lds, s_cnt, st, work);
+    else
+      adjoint_tile<SH, kMesh, !kShared>(A, G(A.scene), tb, iter, lds, s_cnt, st, work);
+  }
+  queue_done(queue);
 }
 
 // ---------------------------------------------------------------------------
@@ -1059,7 +1112,7 @@ k_vol_forward(const FwdArgs* __restrict__ Units, int n_units, unsigned long long
   const uint32_t iter = iteration_of(A.key);
   if (A.h.max_iter && iter >= A.h.max_iter) return;  // finished problem
   const DevScene& S = *G(A.scene);
-  const TileBlock tb = tile_block<SH>(A);
+  const TileBlock tb = tile_block<SH>(A, blockIdx.x);
   const FwdSlice& sl = A.sl[tb.slice];
   int px, py;
   const bool inside = tile_pixel<SH>(A.crop, tb, px, py);
@@ -1256,7 +1309,7 @@ k_vol_adjoint(const RepArgs* __restrict__ Units, int n_units, unsigned long long
   const uint32_t iter = iteration_of(A.key);
   if (A.h.max_iter && iter >= A.h.max_iter) return;  // finished problem
   const DevScene& S = *G(A.scene);
-  const TileBlock tb = tile_block<SH>(A);
+  const TileBlock tb = tile_block<SH>(A, blockIdx.x);
   const RepSlice& sl = A.sl[tb.slice];
   int px, py;
   const bool inside = tile_pixel<SH>(A.crop, tb, px, py);
@@ -1569,34 +1622,45 @@ hipError_t launch_philox(const uint32_t* ctr, size_t n, uint64_t key, uint32_t* 
 // needs `stack` entries (the rest spill to private memory).
 static int lds_stack(int stack) { return stack < kLdsStack ? stack : kLdsStack; }
 
+// Grid of a launch of `blocks` tiles: all of them, or with a work queue a
+// persistent grid of at most `persist` blocks.
+static uint32_t grid_of(uint32_t blocks, const uint32_t* queue, uint32_t persist) {
+  return queue && persist < blocks ? persist : blocks;
+}
+
 template <int TW, int TH, bool kShared>
 static void fwd_launch(const FwdArgs* U, int n, uint32_t blocks, int stack,
-                       unsigned long long* work, hipStream_t st) {
+                       unsigned long long* work, uint32_t* queue, uint32_t persist,
+                       hipStream_t st) {
   const int cap = lds_stack(stack);
   const size_t lds = (size_t)cap * TW * TH * 4;
+  const dim3 grid(grid_of(blocks, queue, persist));
   if (stack > 0)
-    hipLaunchKernelGGL((k_forward<TW, TH, true, kShared>), dim3(blocks), dim3(TW * TH), lds, st,
-                       U, n, cap, work);
+    hipLaunchKernelGGL((k_forward<TW, TH, true, kShared>), grid, dim3(TW * TH), lds, st,
+                       U, n, cap, work, queue, blocks);
   else
-    hipLaunchKernelGGL((k_forward<TW, TH, false, kShared>), dim3(blocks), dim3(TW * TH), 0, st,
-                       U, n, 0, work);
+    hipLaunchKernelGGL((k_forward<TW, TH, false, kShared>), grid, dim3(TW * TH), 0, st,
+                       U, n, 0, work, queue, blocks);
 }
 template <int TW, int TH>
 static void fwd_launch(const FwdArgs* U, int n, uint32_t blocks, int stack, bool shared,
-                       unsigned long long* work, hipStream_t st) {
+                       unsigned long long* work, uint32_t* queue, uint32_t persist,
+                       hipStream_t st) {
   if (shared)
-    fwd_launch<TW, TH, true>(U, n, blocks, stack, work, st);
+    fwd_launch<TW, TH, true>(U, n, blocks, stack, work, queue, persist, st);
   else
-    fwd_launch<TW, TH, false>(U, n, blocks, stack, work, st);
+    fwd_launch<TW, TH, false>(U, n, blocks, stack, work, queue, persist, st);
 }
 hipError_t launch_forward(const FwdArgs* U, int n, uint32_t blocks, int shape, int stack,
-                          bool shared, unsigned long long* work, hipStream_t st) {
+                          bool shared, unsigned long long* work, hipStream_t st,
+                          uint32_t* queue, uint32_t persist) {
   if (n <= 0 || blocks == 0) return hipSuccess;
   if (stack < 0 || stack > kBvhMaxStack) return hipErrorInvalidValue;
+  if (queue && persist == 0) return hipErrorInvalidValue;
   switch (shape) {
-    case 0: fwd_launch<16, 16>(U, n, blocks, stack, shared, work, st); break;
-    case 1: fwd_launch<16, 8>(U, n, blocks, stack, shared, work, st); break;
-    case 2: fwd_launch<8, 8>(U, n, blocks, stack, shared, work, st); break;
+    case 0: fwd_launch<16, 16>(U, n, blocks, stack, shared, work, queue, persist, st); break;
+    case 1: fwd_launch<16, 8>(U, n, blocks, stack, shared, work, queue, persist, st); break;
+    case 2: fwd_launch<8, 8>(U, n, blocks, stack, shared, work, queue, persist, st); break;
     default: return hipErrorInvalidValue;
   }
   return hipGetLastError();
@@ -1616,33 +1680,38 @@ size_t adjoint_lds_bytes(int n_ch) {
 
 template <int TW, int TH, bool kShared>
 static void adj_launch(const RepArgs* U, int n, uint32_t blocks, size_t lds, int stack,
-                       unsigned long long* work, hipStream_t st) {
+                       unsigned long long* work, uint32_t* queue, uint32_t persist,
+                       hipStream_t st) {
   const int cap = lds_stack(stack);
+  const dim3 grid(grid_of(blocks, queue, persist));
   if (stack > 0)
-    hipLaunchKernelGGL((k_adjoint<TW, TH, true, kShared>), dim3(blocks), dim3(TW * TH),
-                       lds + (size_t)cap * TW * TH * 4, st, U, n, cap, work);
+    hipLaunchKernelGGL((k_adjoint<TW, TH, true, kShared>), grid, dim3(TW * TH),
+                       lds + (size_t)cap * TW * TH * 4, st, U, n, cap, work, queue, blocks);
   else
-    hipLaunchKernelGGL((k_adjoint<TW, TH, false, kShared>), dim3(blocks), dim3(TW * TH), lds, st,
-                       U, n, 0, work);
+    hipLaunchKernelGGL((k_adjoint<TW, TH, false, kShared>), grid, dim3(TW * TH), lds, st,
+                       U, n, 0, work, queue, blocks);
 }
 template <int TW, int TH>
 static void adj_launch(const RepArgs* U, int n, uint32_t blocks, size_t lds, int stack,
-                       bool shared, unsigned long long* work, hipStream_t st) {
+                       bool shared, unsigned long long* work, uint32_t* queue, uint32_t persist,
+                       hipStream_t st) {
   if (shared)
-    adj_launch<TW, TH, true>(U, n, blocks, lds, stack, work, st);
+    adj_launch<TW, TH, true>(U, n, blocks, lds, stack, work, queue, persist, st);
   else
-    adj_launch<TW, TH, false>(U, n, blocks, lds, stack, work, st);
+    adj_launch<TW, TH, false>(U, n, blocks, lds, stack, work, queue, persist, st);
 }
 
 hipError_t launch_adjoint(const RepArgs* U, int n, uint32_t blocks, int shape, size_t lds,
-                          int stack, bool shared, unsigned long long* work, hipStream_t st) {
+                          int stack, bool shared, unsigned long long* work, hipStream_t st,
+                          uint32_t* queue, uint32_t persist) {
   if (n <= 0 || blocks == 0) return hipSuccess;
   if (lds < adjoint_lds_bytes(0) || lds > adjoint_lds_bytes(5)) return hipErrorInvalidValue;
   if (stack < 0 || stack > kBvhMaxStack) return hipErrorInvalidValue;
+  if (queue && persist == 0) return hipErrorInvalidValue;
   switch (shape) {
-    case 0: adj_launch<16, 16>(U, n, blocks, lds, stack, shared, work, st); break;
-    case 1: adj_launch<16, 8>(U, n, blocks, lds, stack, shared, work, st); break;
-    case 2: adj_launch<8, 8>(U, n, blocks, lds, stack, shared, work, st); break;
+    case 0: adj_launch<16, 16>(U, n, blocks, lds, stack, shared, work, queue, persist, st); break;
+    case 1: adj_launch<16, 8>(U, n, blocks, lds, stack, shared, work, queue, persist, st); break;
+    case 2: adj_launch<8, 8>(U, n, blocks, lds, stack, shared, work, queue, persist, st); break;
     default: return hipErrorInvalidValue;
   }
   return hipGetLastError();
