@@ -783,9 +783,9 @@ def scene_bytes(prob) -> int:
 
 
 def adjoint_roofline(spec, prob, kt, work, ub, steps):
-    """k_adjoint against the bounds of its work per launch.
+    """k_adjoint against the bounds of its work per step.
 
-    Algorithmic work of one launch (the replay of one step's adjoint paths):
+    Algorithmic work of a step's replay (its one or two adjoint launches):
     every surface vertex scatters its material gradient into the 4 texels
     of its bilinear footprint, 4 n_ch FP32 atomics of 4 bytes; each replayed
     path reads its radiance slot (24 B) and its pixel's adjoint colour
@@ -794,10 +794,12 @@ def adjoint_roofline(spec, prob, kt, work, ub, steps):
     the 4 n_ch atomics per vertex over the launch time against the measured
     peak of no-return FP32 atomics (coalesced 64-byte segments, and random
     addresses)."""
+    # a step's replay is one launch, or two when it holds both replay pairs and
+    # single paths (the pair kernel and the single-path kernel): the figures
+    # below are per step, over the step's adjoint launches together
     ms, calls = kt["adjoint"]
-    launch_ms = ms / max(calls, 1)
-    per_launch = steps / max(calls, 1)  # launches per step: calls / steps
-    rep_paths, rep_verts = work[0] * per_launch, work[1] * per_launch
+    launch_ms = ms / max(steps, 1)
+    rep_paths, rep_verts = work[0], work[1]
     n_ch = spec.n_ch
     atomics = rep_verts * 4 * n_ch
     bytes_ = (atomics * 4 + rep_paths * (24 + 12) + 4 * spec.n_params + scene_bytes(prob))
@@ -807,7 +809,8 @@ def adjoint_roofline(spec, prob, kt, work, ub, steps):
            "algorithmic_bytes": bytes_, "paths_per_launch": rep_paths,
            "vertices_per_launch": rep_verts, "vertices_per_path": rep_verts / max(rep_paths, 1),
            "atomics_per_launch": atomics,
-           "atomics_per_s": atomics / (launch_ms / 1e3)}
+           "atomics_per_s": atomics / (launch_ms / 1e3),
+           "launches_per_step": calls / max(steps, 1)}
     if ub:
         out["atomic_frac_lines"] = out["atomics_per_s"] / ub["atomic_ops_per_s_lines"]
         out["atomic_frac_random"] = out["atomics_per_s"] / ub["atomic_ops_per_s_random"]

@@ -362,12 +362,14 @@ __device__ __forceinline__ void queue_done(uint32_t* queue) {
 // holds `stack` traversal-stack entries per lane.
 // kShared: the launch may hold shared-path pair slices (the other launches
 // keep the smaller exchange buffer and register budget of single paths).
-// Mesh scenes: 96 VGPRs (5 waves per SIMD) measured 10% faster than the
-// 102 the compiler picks by itself; the two-ledger path of shared pairs needs
-// more and keeps 4 waves (128 VGPRs), where it does not spill.
+// Register budgets (waves per SIMD), each the fastest measured on the
+// 2048x2048 terrain and the 512x512 textured step: analytic scenes 7 (72
+// VGPRs); mesh scenes 6 (80 VGPRs, some private-memory spills: 6% faster than
+// 5, 7 is slower again); the two-ledger path of shared pairs 5 (96 VGPRs:
+// 14% faster than 4 on the terrain).
 template <int TW, int TH, bool kMesh, bool kShared>
 __global__ void __launch_bounds__(TW * TH)
-__attribute__((amdgpu_waves_per_eu(kMesh && !kShared ? 5 : 4)))
+__attribute__((amdgpu_waves_per_eu(kShared ? 5 : (kMesh ? 6 : 7))))
 k_forward(const FwdArgs* __restrict__ Units, int n_units, int stack, unsigned long long* work,
           uint32_t* queue, uint32_t total) {
   using SH = Shape<TW, TH>;
@@ -935,12 +937,12 @@ __device__ __forceinline__ void adjoint_tile_shared(const RepArgs& A,
 // Dynamic LDS: with kMesh, `stack` traversal-stack entries per lane first
 // (the LDS part of the stack), then the gradient table / exchange buffer.
 // kShared: the launch's pair slices are shared-path pairs (no replay pairs).
-// Without replay pairs the kernel fits 128 VGPRs (no spill without traversal,
-// a few dwords with it), so it runs at 4 waves per SIMD; the replay-pair
-// kernels keep 3 (forcing 4 spills and is no faster overall).
+// Without replay pairs the kernel runs at 5 waves per SIMD (96 VGPRs; a few
+// spills: 4-10% faster than 4 waves at 128, 6 waves is slower again); the
+// replay-pair kernels keep 3 (forcing 4 spills and is no faster overall).
 template <int TW, int TH, bool kMesh, bool kShared>
 __global__ void __launch_bounds__(TW * TH)
-__attribute__((amdgpu_waves_per_eu(kShared ? 4 : 3)))
+__attribute__((amdgpu_waves_per_eu(kShared ? 5 : 3)))
 k_adjoint(const RepArgs* __restrict__ Units, int n_units, int stack, unsigned long long* work,
           uint32_t* queue, uint32_t total) {
   using SH = Shape<TW, TH>;
