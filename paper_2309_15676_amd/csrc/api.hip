@@ -625,9 +625,6 @@ hipMemcpyKind kind_from_dev(int mem) {
 // tiles from a work queue (0: one block per tile).
 constexpr int kPersistPerCU[] = {0, 1, 2, 4, 8};
 constexpr int kConfigs = kShapes * (int)(sizeof(kPersistPerCU) / sizeof(int));
-// Replay-pair tiles from which a step's replay runs as two launches (the pair
-// kernel and the single-path kernel); see plan_estimators.
-constexpr size_t kSplitMinBlocks = 4096;
 static_assert(kConfigs == JSO_LAUNCH_CONFIGS, "launch configurations");
 int shape_of(int config) { return config % kShapes; }
 int persist_of(int config) { return kPersistPerCU[config / kShapes]; }
@@ -709,6 +706,12 @@ uint32_t tiles_x(const Crop& c, int shape) {
 }
 uint32_t tiles_of(const Crop& c, int shape) {
   return tiles_x(c, shape) * (uint32_t)((c.y1 - c.y0 + kShapeH[shape] - 1) / kShapeH[shape]);
+}
+
+// Tiles of half the shape's height (replay pairs on lane pairs).
+uint32_t pair_tiles_of(const Crop& c, int shape) {
+  const int h = kShapeH[shape] / 2;
+  return tiles_x(c, shape) * (uint32_t)((c.y1 - c.y0 + h - 1) / h);
 }
 
 bool crop_empty(const Crop& c) { return c.x1 <= c.x0 || c.y1 <= c.y0; }
@@ -893,43 +896,20 @@ void plan_estimators(const std::vector<ProbPlan>& ps, Plan& plan, int config = 0
       plan.push_back(std::move(fr));
     }
     // k_adjoint: pair units of every problem first, then single-path units.
-    // Replay pairs need the pair kernel (two paths per lane, 3 waves per
-    // SIMD); single paths alone fit the shared-path kernel (4 waves), so
-    // when both kinds are present and the pairs alone fill the GPU
-    // (kSplitMinBlocks tiles) they go to two launches.  Below that, the
-    // launches' tails would not overlap: measured on the 512x512 problem
-    // (1024 pair tiles) the split replay is 35% slower, on the 2048x2048
-    // terrain (16384) 9% faster.
+    // Replay pairs (not shared) run on lane pairs: their units take tiles of
+    // half the shape's height, so a pair tile has as many lanes as a single
+    // one.
     if (!reps.empty()) {
       const bool vol = p0.s->dev.layout == JSO_LAYOUT_VOLUME;
-      bool has_pair = false, has_single = false;
-      size_t pair_blocks = 0;
-      for (const auto& u : reps) {
-        const bool pair = p0.aj[u.first].params_b != nullptr;
-        (pair ? has_pair : has_single) = true;
-        if (pair)
-          for (const ProbPlan& p : ps)
-            if (!crop_empty(p.crop)) pair_blocks += tiles_of(p.crop, shape);
-      }
-      const bool split = !vol && !shared_pairs && has_pair && has_single &&
-                         pair_blocks >= kSplitMinBlocks;
       LaunchRec ad;
       ad.kind = Kern::Adjoint;
       ad.timer = JSO_K_ADJOINT;
       ad.shape = shape;
       ad.lds = adjoint_lds_bytes(max_ch);
-      ad.shared = shared_pairs || !has_pair;  // no replay pairs: the smaller kernel
+      ad.shared = shared_pairs;
       ad.vol = vol;
       ad.persist = vol ? 0 : persist_of(config);
       for (int pass = 0; pass < 2; ++pass) {
-        if (pass == 1 && split) {
-          plan.push_back(ad);
-          ad.units.clear();
-          ad.n = 0;
-          ad.blocks = 0;
-          ad.stack = 0;
-          ad.shared = true;  // single paths only: the kernel without replay pairs
-        }
         for (const ProbPlan& p : ps) {
           if (crop_empty(p.crop)) continue;
           RepArgs r{};
@@ -959,8 +939,9 @@ void plan_estimators(const std::vector<ProbPlan>& ps, Plan& plan, int config = 0
           r.slots = gmem((const double*)slots_of(p));
           r.npix = (uint32_t)p.s->npix;
           r.flags = p.flags;
+          r.pair_lanes = pass == 0 && !shared_pairs && !vol;
           r.tiles_x = tiles_x(p.crop, shape);
-          r.tiles = tiles_of(p.crop, shape);
+          r.tiles = r.pair_lanes ? pair_tiles_of(p.crop, shape) : tiles_of(p.crop, shape);
           ad.stack = std::max(ad.stack, p.s->stack);
           push_unit(ad, r, r.tiles * (uint32_t)r.n_slices);
         }

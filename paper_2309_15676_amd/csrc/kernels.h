@@ -153,6 +153,10 @@ struct RepArgs {
   uint32_t npix;
   uint32_t flags;
   uint32_t tiles_x, tiles;
+  // nonzero: every slice is a replay pair (params_b set, not shared), traced on
+  // lane pairs over tiles of half the tile shape's height (tiles_x, tiles
+  // count those)
+  int pair_lanes;
 };
 
 struct MetaArgs {

@@ -101,12 +101,13 @@ struct TileBlock {
   int slice, x0, y0;
 };
 
+// th: the tile height in pixels (SH::H, or SH::H / 2 for lane-pair tiles)
 template <class SH, class U>
-__device__ __forceinline__ TileBlock tile_block(const U& u, uint32_t b) {
+__device__ __forceinline__ TileBlock tile_block(const U& u, uint32_t b, int th = SH::H) {
   const uint32_t local = b - u.h.block0;
   const uint32_t t = local % u.tiles;
   return TileBlock{(int)(local / u.tiles), u.crop.x0 + (int)(t % u.tiles_x) * SH::W,
-                   u.crop.y0 + (int)(t / u.tiles_x) * SH::H};
+                   u.crop.y0 + (int)(t / u.tiles_x) * th};
 }
 
 template <class SH>
@@ -654,11 +655,6 @@ struct RepItem {
   int src;
 };
 
-struct RepPairItem {
-  Path Pa, Pb;
-  float adj_a[3], adj_b[3];
-  int src, pad_;
-};
 
 struct RepSharedItem {  // a shared-path pair: one path, two ledgers
   Path P;
@@ -667,8 +663,8 @@ struct RepSharedItem {  // a shared-path pair: one path, two ledgers
   int src, pad_;
 };
 
-constexpr int kRepXchgWords = (int)(sizeof(RepPairItem) / 4);
-static_assert(sizeof(RepSharedItem) <= sizeof(RepPairItem), "exchange buffer size");
+constexpr int kRepXchgWords = (int)(sizeof(RepSharedItem) / 4);
+static_assert(sizeof(RepItem) <= sizeof(RepSharedItem), "exchange buffer size");
 
 // Start the replay of a path: P.led = the radiance still to come.
 template <bool kMesh>
@@ -680,14 +676,12 @@ __device__ __forceinline__ void replay_begin(const DevScene& S, const TravStack&
   for (int k = 0; k < 3; ++k) P.led[k] = C[k] - P.led[k];
 }
 
-// One block = one pixel tile of one slice.  Each path is
+// One block = one pixel tile of one slice of single paths.  Each path is
 // replayed vertex by vertex from its forward radiance: first vertices in place
 // (their gradients go to the block table, flushed right after), later ones on
 // the compacted lanes in a wave-uniform loop, so the later-vertex scatter can
 // use the whole wave.  The exchange buffer reuses the table's LDS.
-// kPairs: the launch may hold replay-pair slices (kPairs = false compiles
-// their code out).
-template <class SH, bool kMesh, bool kPairs>
+template <class SH, bool kMesh>
 __device__ __forceinline__ void adjoint_tile(const RepArgs& A, const DevScene* __restrict__ Sp,
                                              const TileBlock& tb, uint32_t iter, uint32_t* s_dyn,
                                              int* s_cnt, const TravStack& st,
@@ -696,7 +690,6 @@ __device__ __forceinline__ void adjoint_tile(const RepArgs& A, const DevScene* _
   uint32_t* s_keys = s_dyn;
   float* s_vals = reinterpret_cast<float*>(s_dyn + kTableSize);
   const RepSlice& sl = A.sl[tb.slice];
-  const bool pair = kPairs && G(sl.params_b) != nullptr;  // uniform over the block
   int px, py;
   const bool inside = tile_pixel<SH>(A.crop, tb, px, py);
   const uint32_t pix = (uint32_t)(py * S.width + px);
@@ -710,135 +703,189 @@ __device__ __forceinline__ void adjoint_tile(const RepArgs& A, const DevScene* _
   const BlockPaths<SH> B = block_paths<SH>(tb, S, key, sl.sample, A.flags);
   const Rng rng = B.rng((int)threadIdx.x);
   const int tid = (int)threadIdx.x;
-  float adj_a[3] = {0.0f, 0.0f, 0.0f}, adj_b[3] = {0.0f, 0.0f, 0.0f};
-  Path Pa, Pb;
-  Pa.alive = Pb.alive = false;
+  RepItem mine;
+  mine.P.alive = false;
+  mine.src = tid;
   int n_vert = 0;
   {
-    VertexGrad va, vb;
-    va.valid = vb.valid = false;
+    VertexGrad v;
+    v.valid = false;
     if (active) {
 #pragma unroll
-      for (int k = 0; k < 3; ++k) {
-        adj_a[k] = G(sl.delta)[3 * (size_t)pix + k] * sl.adj_scale;
-        if (pair) adj_b[k] = G(sl.delta_b)[3 * (size_t)pix + k] * sl.adj_scale;
-      }
+      for (int k = 0; k < 3; ++k) mine.adj[k] = G(sl.delta)[3 * (size_t)pix + k] * sl.adj_scale;
       replay_begin<kMesh>(S, st, rng, px, py, A.flags,
-                          G(A.slots) + ((size_t)sl.slot_a * A.npix + pix) * 3, Pa);
-      if (Pa.alive) {
+                          G(A.slots) + ((size_t)sl.slot_a * A.npix + pix) * 3, mine.P);
+      if (mine.P.alive) {
         ++n_vert;
-        path_vertex<true, kMesh>(S, st, G(sl.params), rng, A.flags, Pa, adj_a, va);
-      }
-      if (pair) {
-        replay_begin<kMesh>(S, st, rng, px, py, A.flags,
-                            G(A.slots) + ((size_t)sl.slot_b * A.npix + pix) * 3, Pb);
-        if (Pb.alive) {
-          ++n_vert;
-          path_vertex<true, kMesh>(S, st, G(sl.params_b), rng, A.flags, Pb, adj_b, vb);
-        }
-        if (va.valid && vb.valid && same_footprint(va.fp, vb.fp)) {
-#pragma unroll
-          for (int q = 0; q < 5; ++q) va.g[q] -= vb.g[q];
-          vb.valid = false;
-        }
+        path_vertex<true, kMesh>(S, st, G(sl.params), rng, A.flags, mine.P, mine.adj, v);
       }
     }
-    // first vertices (j = 1) go to the table
-    sink.template add<kMesh>(S, va, pair ? 1.0f : sl.sign);
-    sink.template add<kMesh>(S, vb, -1.0f);
+    sink.template add<kMesh>(S, v, sl.sign);  // first vertices (j = 1) go to the table
   }
   __syncthreads();
   sink.flush_table(S, SH::N);
-  const int paths = active ? (pair ? 2 : 1) : 0;
-  const bool live = Pa.alive || Pb.alive;
+  const bool live = mine.P.alive;
   int n;
   const int r = block_rank<SH>(live, n, s_cnt);  // its barriers also retire the table
-  uint32_t* xbuf = s_dyn;
-  if (!pair) {
-    RepItem W;
-    if (n > compact_max<SH>()) {
-      W.P = Pa;
-      W.src = tid;
-#pragma unroll
-      for (int k = 0; k < 3; ++k) W.adj[k] = adj_a[k];
-    } else {
-      RepItem mine;
-      mine.P = Pa;
-      mine.src = tid;
-#pragma unroll
-      for (int k = 0; k < 3; ++k) mine.adj[k] = adj_a[k];
-      W.P.alive = false;
-      W.src = tid;
-      if (n > 0) pack(xbuf, live, r, n, mine, W);
-    }
-    // no barrier below: waves without a path leave
-    if (__ballot(W.P.alive) != 0) {
-      const Rng wr = B.rng(W.src);
-      while (__ballot(W.P.alive) != 0) {
-        VertexGrad v;
-        v.valid = false;
-        if (W.P.alive) {
-          ++n_vert;
-          path_vertex<true, kMesh>(S, st, G(sl.params), wr, A.flags, W.P, W.adj, v);
-        }
-        const bool later = sink.template add<kMesh>(S, v, sl.sign);
-        scatter_wave<kMesh>(S, G(sl.grad), v, sl.sign, later);
-      }
-    }
+  RepItem W;
+  if (n > compact_max<SH>()) {
+    W = mine;
   } else {
-    RepPairItem W;
-    if (n > compact_max<SH>()) {
-      W.Pa = Pa;
-      W.Pb = Pb;
-      W.src = tid;
-#pragma unroll
-      for (int k = 0; k < 3; ++k) {
-        W.adj_a[k] = adj_a[k];
-        W.adj_b[k] = adj_b[k];
+    W.P.alive = false;
+    W.src = tid;
+    if (n > 0) pack(s_dyn, live, r, n, mine, W);
+  }
+  // no barrier below: waves without a path leave
+  if (__ballot(W.P.alive) != 0) {
+    const Rng wr = B.rng(W.src);
+    while (__ballot(W.P.alive) != 0) {
+      VertexGrad v;
+      v.valid = false;
+      if (W.P.alive) {
+        ++n_vert;
+        path_vertex<true, kMesh>(S, st, G(sl.params), wr, A.flags, W.P, W.adj, v);
       }
-    } else {
-      RepPairItem mine;
-      mine.Pa = Pa;
-      mine.Pb = Pb;
-      mine.src = tid;
-#pragma unroll
-      for (int k = 0; k < 3; ++k) {
-        mine.adj_a[k] = adj_a[k];
-        mine.adj_b[k] = adj_b[k];
-      }
-      W.Pa.alive = W.Pb.alive = false;
-      W.src = tid;
-      if (n > 0) pack(xbuf, live, r, n, mine, W);
-    }
-    // no barrier below: waves without a path leave; the pair is replayed in
-    // lockstep and coinciding vertices are differenced in registers
-    if (__ballot(W.Pa.alive || W.Pb.alive) != 0) {
-      const Rng wr = B.rng(W.src);
-      while (__ballot(W.Pa.alive || W.Pb.alive) != 0) {
-        VertexGrad va, vb;
-        va.valid = vb.valid = false;
-        if (W.Pa.alive) {
-          ++n_vert;
-          path_vertex<true, kMesh>(S, st, G(sl.params), wr, A.flags, W.Pa, W.adj_a, va);
-        }
-        if (W.Pb.alive) {
-          ++n_vert;
-          path_vertex<true, kMesh>(S, st, G(sl.params_b), wr, A.flags, W.Pb, W.adj_b, vb);
-        }
-        if (va.valid && vb.valid && same_footprint(va.fp, vb.fp)) {
-#pragma unroll
-          for (int q = 0; q < 5; ++q) va.g[q] -= vb.g[q];
-          vb.valid = false;
-        }
-        const bool later_a = sink.template add<kMesh>(S, va, 1.0f);
-        const bool later_b = sink.template add<kMesh>(S, vb, -1.0f);
-        scatter_wave<kMesh>(S, G(sl.grad), va, 1.0f, later_a);
-        scatter_wave<kMesh>(S, G(sl.grad), vb, -1.0f, later_b);
-      }
+      const bool later = sink.template add<kMesh>(S, v, sl.sign);
+      scatter_wave<kMesh>(S, G(sl.grad), v, sl.sign, later);
     }
   }
   sink.flush_acc(S);
-  count_work(work, paths, n_vert);
+  count_work(work, active ? 1 : 0, n_vert);
+}
+
+// The gradient of the partner lane's vertex (lane ^ 1); every lane of the wave
+// must call it.  Where both vertices are valid and share their footprint
+// bitwise, the first lane of the pair keeps the difference of the two
+// gradients and the second drops its vertex, so equal parameter vectors give
+// an exactly zero difference before any atomic.  The second lane's gradient
+// is then negated, so both lanes scatter with sign +1 (the wave-cooperative
+// scatter applies one sign to every lane's vertex).
+template <bool kMesh>
+__device__ __forceinline__ void pair_difference(VertexGrad& v, int half) {
+  Footprint o;
+  const int ov = __shfl_xor(v.valid ? 1 : 0, 1, 64);
+  o.global = __shfl_xor(v.fp.global, 1, 64);
+  o.tri = kMesh ? __shfl_xor(v.fp.tri, 1, 64) : 0;
+  o.t00 = __shfl_xor(v.fp.t00, 1, 64);
+  o.t01 = __shfl_xor(v.fp.t01, 1, 64);
+  o.t10 = __shfl_xor(v.fp.t10, 1, 64);
+  o.fx = __shfl_xor(v.fp.fx, 1, 64);
+  o.fy = __shfl_xor(v.fp.fy, 1, 64);
+  float og[5];
+#pragma unroll
+  for (int b = 0; b < 5; ++b) og[b] = __shfl_xor(v.g[b], 1, 64);
+  Footprint mine = v.fp;
+  if (!kMesh) mine.tri = 0;
+  if (v.valid && ov && same_footprint(mine, o)) {
+    if (half == 0) {
+#pragma unroll
+      for (int b = 0; b < 5; ++b) v.g[b] -= og[b];
+    } else {
+      v.valid = false;
+    }
+  }
+  if (half) {
+#pragma unroll
+    for (int b = 0; b < 5; ++b) v.g[b] = -v.g[b];
+  }
+}
+
+// A replay-pair slice (Eq. 5 by primary-sample-space replay): one block = a
+// tile of TW x TH/2 pixels, lanes 2k and 2k + 1 replaying pixel k's path at
+// A's parameters (+) and at B's (-) from the same random numbers, vertex by
+// vertex in lockstep; coinciding vertices are differenced across the lane pair
+// (pair_difference).  A pair occupies two lanes of one path each, so the
+// kernel keeps the register budget of single paths.  The first vertices go to
+// the block table; then the live pairs are compacted, each onto two
+// neighbouring lanes.
+template <class SH, bool kMesh>
+__device__ __forceinline__ void adjoint_tile_pairs(const RepArgs& A,
+                                                   const DevScene* __restrict__ Sp,
+                                                   const TileBlock& tb, uint32_t iter,
+                                                   uint32_t* s_dyn, int* s_cnt,
+                                                   const TravStack& st,
+                                                   unsigned long long* work) {
+  const DevScene& S = *Sp;
+  uint32_t* s_keys = s_dyn;
+  float* s_vals = reinterpret_cast<float*>(s_dyn + kTableSize);
+  const RepSlice& sl = A.sl[tb.slice];
+  const int tid = (int)threadIdx.x;
+  const int half = tid & 1;
+  auto pixel_of = [&](int t, int& x, int& y) {
+    const int k = t >> 1;
+    x = tb.x0 + k % SH::W;
+    y = tb.y0 + k / SH::W;
+  };
+  int px, py;
+  pixel_of(tid, px, py);
+  const bool inside = px < A.crop.x1 && py < A.crop.y1;
+  const uint32_t pix = (uint32_t)(py * S.width + px);
+  const bool active = inside && !(G(A.mask) && G(A.mask)[pix]);
+  for (int i = threadIdx.x; i < kTableSize; i += SH::N) s_keys[i] = kEmpty;
+  for (int i = threadIdx.x; i < kTableSize * S.n_ch; i += SH::N) s_vals[i] = 0.0f;
+  __syncthreads();
+  Sink sink;
+  sink.init(GradTable{s_keys, s_vals, G(sl.grad)});
+  const uint64_t key = stream_key(A.key.seed, iter, sl.tag);
+  const float* params = half ? G(sl.params_b) : G(sl.params);
+  RepItem mine;
+  mine.P.alive = false;
+  mine.src = tid;
+  int n_vert = 0;
+  {
+    VertexGrad v;
+    v.valid = false;
+    if (active) {
+      const float* delta = half ? G(sl.delta_b) : G(sl.delta);
+#pragma unroll
+      for (int k = 0; k < 3; ++k) mine.adj[k] = delta[3 * (size_t)pix + k] * sl.adj_scale;
+      const Rng rng = make_rng(key, pix, sl.sample);
+      replay_begin<kMesh>(S, st, rng, px, py, A.flags,
+                          G(A.slots) + ((size_t)(half ? sl.slot_b : sl.slot_a) * A.npix + pix) * 3,
+                          mine.P);
+      if (mine.P.alive) {
+        ++n_vert;
+        path_vertex<true, kMesh>(S, st, params, rng, A.flags, mine.P, mine.adj, v);
+      }
+    }
+    pair_difference<kMesh>(v, half);
+    sink.template add<kMesh>(S, v, 1.0f);  // first vertices (j = 1) go to the table
+  }
+  __syncthreads();
+  sink.flush_table(S, SH::N);
+  // pairs with a live path, counted on their first lanes; both lanes of such
+  // a pair move (to lanes 2 r and 2 r + 1), a finished path keeps its lane
+  const int pair_live = (mine.P.alive ? 1 : 0) | __shfl_xor(mine.P.alive ? 1 : 0, 1, 64);
+  int n;
+  const int r0 = block_rank<SH>(pair_live && half == 0, n, s_cnt);
+  const int r = 2 * __shfl(r0, tid & ~1 & 63, 64) + half;
+  RepItem W;
+  if (2 * n > compact_max<SH>()) {
+    W = mine;
+  } else {
+    W.P.alive = false;
+    W.src = tid;
+    if (n > 0) pack(s_dyn, pair_live != 0, r, 2 * n, mine, W);
+  }
+  // no barrier below: waves without a live pair leave
+  if (__ballot(W.P.alive) != 0) {
+    int wx, wy;
+    pixel_of(W.src, wx, wy);
+    const Rng wr = make_rng(key, (uint32_t)(wy * S.width + wx), sl.sample);
+    while (__ballot(W.P.alive) != 0) {
+      VertexGrad v;
+      v.valid = false;
+      if (W.P.alive) {
+        ++n_vert;
+        path_vertex<true, kMesh>(S, st, params, wr, A.flags, W.P, W.adj, v);
+      }
+      pair_difference<kMesh>(v, half);
+      const bool later = sink.template add<kMesh>(S, v, 1.0f);
+      scatter_wave<kMesh>(S, G(sl.grad), v, 1.0f, later);
+    }
+  }
+  sink.flush_acc(S);
+  count_work(work, active ? 1 : 0, n_vert);
 }
 
 // A shared-path pair slice (Eq. 5 as written): each path is drawn at A's
@@ -936,13 +983,14 @@ __device__ __forceinline__ void adjoint_tile_shared(const RepArgs& A,
 
 // Dynamic LDS: with kMesh, `stack` traversal-stack entries per lane first
 // (the LDS part of the stack), then the gradient table / exchange buffer.
-// kShared: the launch's pair slices are shared-path pairs (no replay pairs).
-// Without replay pairs the kernel runs at 5 waves per SIMD (96 VGPRs; a few
-// spills: 4-10% faster than 4 waves at 128, 6 waves is slower again); the
-// replay-pair kernels keep 3 (forcing 4 spills and is no faster overall).
+// kShared: the launch's pair slices are shared-path pairs; otherwise they are
+// replay pairs on lane pairs (units with pair_lanes).  Single paths, lane
+// pairs and shared-path pairs each keep one path per lane, so the kernel runs
+// at 5 waves per SIMD (96 VGPRs; a few spills: 4-10% faster than 4 waves at
+// 128, 6 waves is slower again).
 template <int TW, int TH, bool kMesh, bool kShared>
 __global__ void __launch_bounds__(TW * TH)
-__attribute__((amdgpu_waves_per_eu(kShared ? 5 : 3)))
+__attribute__((amdgpu_waves_per_eu(5)))
 k_adjoint(const RepArgs* __restrict__ Units, int n_units, int stack, unsigned long long* work,
           uint32_t* queue, uint32_t total) {
   using SH = Shape<TW, TH>;
@@ -956,11 +1004,16 @@ k_adjoint(const RepArgs* __restrict__ Units, int n_units, int stack, unsigned lo
     const RepArgs& A = unit_of(Units, n_units, b);
     const uint32_t iter = iteration_of(A.key);
     if (A.h.max_iter && iter >= A.h.max_iter) continue;  // finished problem
+    if (!kShared && A.pair_lanes) {  // uniform over the block, as is everything below
+      const TileBlock tb = tile_block<SH>(A, b, SH::H / 2);
+      adjoint_tile_pairs<SH, kMesh>(A, G(A.scene), tb, iter, lds, s_cnt, st, work);
+      continue;
+    }
     const TileBlock tb = tile_block<SH>(A, b);
-    if (kShared && G(A.sl[tb.slice].params_b) != nullptr)  // uniform over the block
+    if (kShared && G(A.sl[tb.slice].params_b) != nullptr)
       adjoint_tile_shared<SH, kMesh>(A, G(A.scene), tb, iter, lds, s_cnt, st, work);
     else
-      adjoint_tile<SH, kMesh, !kShared>(A, G(A.scene), tb, iter, lds, s_cnt, st, work);
+      adjoint_tile<SH, kMesh>(A, G(A.scene), tb, iter, lds, s_cnt, st, work);
   }
   queue_done(queue);
 }
