@@ -97,6 +97,16 @@ extern "C" {
 #define JSO_F_LAMBERT_ONLY 2 /* f = c/pi with cosine sampling                      */
 #define JSO_F_PARAM_INDEP 4  /* both lobes sampled with the cosine density         */
 #define JSO_F_PIXEL_CENTER 8 /* no pixel jitter                                    */
+/* Deterministic gradient sums: each replayed contribution is rounded to a
+ * multiple of 2^-k and summed in 64-bit fixed point with integer atomics
+ * (associative, so the result is bitwise the same whatever the order of the
+ * atomics, the launch configuration or the batching), then folded into the
+ * FP32 gradient.  k = 32 + ceil(log2(1.5 W H)) for the estimators (their
+ * adjoint images carry 1 / (1.5 W H)), 32 for jso_render_bwd; a gradient
+ * element must stay below 2^(63-k) in magnitude.  Slower (no block table,
+ * one integer atomic per contribution); not for volume scenes or
+ * jso_render_bwd_noalloc (JSO_E_UNSUPPORTED). */
+#define JSO_F_DETERMINISTIC 16
 
 #define JSO_MAX_SPHERES 32
 #define JSO_MAX_FIXED_MATS 8

@@ -53,6 +53,7 @@ struct SceneGPU {
   // the separate variance samples of the uncorrelated ablation
   double *m1F = nullptr, *m1D = nullptr;
   float *Fv = nullptr, *dFv = nullptr;
+  unsigned long long* fx = nullptr;  // deterministic mode: 2 x P fixed-point accumulators
   uint32_t host_iter = 0;          // mirror of ctl->iteration
   uint64_t generation = 0;         // unique per loaded scene (plan cache key)
 };
@@ -208,6 +209,7 @@ struct CachedLaunch {
   uint32_t blocks;
   size_t lds, offset;
   int persist;
+  bool det;
 };
 
 struct CachedPlan {
@@ -317,7 +319,7 @@ void free_scene_buffers(SceneGPU* s) {
                   s->m2D,    s->adam_m,      s->adam_v, s->ctl,    s->scratch_loss,
                   s->partials, s->slots,     s->accum,  s->d_scene, s->bvh_nodes,
                   s->bvh_tris, s->bvh_tri_id, s->pc, s->pc_tmp, s->m1F,
-                  s->m1D,    s->Fv,          s->dFv};
+                  s->m1D,    s->Fv,          s->dFv,    s->fx};
   for (void* b : bufs)
     if (b) (void)hipFree(b);
 }
@@ -668,11 +670,20 @@ struct ProbPlan {
   AdjointSpec aj[2];
   int na;
   double* slots = nullptr;  // radiance slots; null: the scene's own
+  double fx_scale = 0.0;    // deterministic mode: fixed-point scale (see fx_scale_of)
 };
 
 double* slots_of(const ProbPlan& p) { return p.slots ? p.slots : p.s->slots; }
 
-enum class Kern { Forward, Finalize, Adjoint, Meta, Adam, Dct };
+// Fixed-point scale of the deterministic mode: 2^32 for adjoint images of the
+// caller's (jso_render_bwd), 2^(32 + ceil(log2(1.5 W H))) for the estimators,
+// whose adjoint images carry the loss's 1 / (1.5 W H).
+double fx_scale_of(const SceneGPU* s, bool estimator) {
+  if (!estimator) return std::ldexp(1.0, 32);
+  return std::ldexp(1.0, 32 + (int)std::ceil(std::log2(1.5 * (double)s->npix)));
+}
+
+enum class Kern { Forward, Finalize, Adjoint, Meta, Adam, Dct, FxFlush };
 
 struct LaunchRec {
   Kern kind;
@@ -686,6 +697,7 @@ struct LaunchRec {
   bool shared = false;         // path kernels: units hold shared-path pair slices
   bool vol = false;            // path kernels: the units' scenes are volumes
   int persist = 0;             // path kernels: persistent blocks per CU (0: none)
+  bool det = false;            // adjoint: deterministic mode (fixed-point sums)
   size_t dev_offset = 0;       // batches: offset of the units in the device arena
 };
 
@@ -909,6 +921,7 @@ void plan_estimators(const std::vector<ProbPlan>& ps, Plan& plan, int config = 0
       ad.shared = shared_pairs;
       ad.vol = vol;
       ad.persist = vol ? 0 : persist_of(config);
+      ad.det = (p0.flags & JSO_F_DETERMINISTIC) != 0;
       for (int pass = 0; pass < 2; ++pass) {
         for (const ProbPlan& p : ps) {
           if (crop_empty(p.crop)) continue;
@@ -930,6 +943,10 @@ void plan_estimators(const std::vector<ProbPlan>& ps, Plan& plan, int config = 0
             rs.sample = (uint32_t)reps[i].second;
             rs.slot_a = rep_slot[i].first;
             rs.slot_b = rep_slot[i].second;
+            if (p.flags & JSO_F_DETERMINISTIC) {  // accumulator k of job k
+              rs.fx = gmem(p.s->fx + (size_t)reps[i].first * p.s->P);
+              rs.fx_scale = p.fx_scale;
+            }
             r.sl[r.n_slices++] = rs;
           }
           if (r.n_slices == 0) continue;
@@ -948,6 +965,25 @@ void plan_estimators(const std::vector<ProbPlan>& ps, Plan& plan, int config = 0
       }
       plan.push_back(std::move(ad));
     }
+  }
+  // deterministic mode: fold each job's fixed-point sums into its gradient
+  if (p0.flags & JSO_F_DETERMINISTIC) {
+    LaunchRec fl;
+    fl.kind = Kern::FxFlush;
+    fl.timer = JSO_K_ADJOINT;
+    for (const ProbPlan& p : ps) {
+      for (int j = 0; j < p.na; ++j) {
+        FxArgs f{};
+        f.h.max_iter = p.max_iter;
+        f.fx = gmem(p.s->fx + (size_t)j * p.s->P);
+        f.grad = gmem(p.aj[j].grad);
+        f.n = p.s->P;
+        f.inv_scale = 1.0 / p.fx_scale;
+        f.nblocks = (uint32_t)std::min<size_t>((p.s->P + kFxBlock - 1) / kFxBlock, 1024);
+        push_unit(fl, f, f.nblocks);
+      }
+    }
+    plan.push_back(std::move(fl));
   }
 }
 
@@ -1132,6 +1168,7 @@ void add_fd_jobs(ProbPlan& p, SceneGPU* s, int fd_mode, uint32_t tag_primal, uin
 ProbPlan step_problem(SceneGPU* s, const jso_step_opts& o, uint32_t flags, uint32_t max_iter) {
   ProbPlan p{};
   p.s = s;
+  p.fx_scale = fx_scale_of(s, true);
   p.relative = o.loss == JSO_LOSS_RELATIVE;
   p.key = KeyArgs{o.seed, 0u, gmem((const uint32_t*)&s->ctl->iteration)};  // the kernels read the device counter
   p.crop = Crop{0, 0, s->width, s->height};
@@ -1231,6 +1268,18 @@ int check_precond_layout(jso_ctx* c, const std::vector<SceneGPU*>& ss, const jso
   return JSO_OK;
 }
 
+// Deterministic mode (JSO_F_DETERMINISTIC in flags): the scene's fixed-point
+// accumulators (allocated zeroed on first use; the flush leaves them zeroed).
+int ensure_fx(jso_ctx* c, SceneGPU* s, uint32_t flags) {
+  if (!(flags & JSO_F_DETERMINISTIC)) return JSO_OK;
+  if (s->dev.layout == JSO_LAYOUT_VOLUME)
+    return fail(c, JSO_E_UNSUPPORTED, "deterministic mode: not for volume scenes");
+  if (s->fx) return JSO_OK;
+  HIP_TRY(c, hipMalloc(reinterpret_cast<void**>(&s->fx), 2 * s->P * sizeof(unsigned long long)));
+  HIP_TRY(c, hipMemset(s->fx, 0, 2 * s->P * sizeof(unsigned long long)));
+  return JSO_OK;
+}
+
 // queue: the launch's two work-queue counters when its configuration is
 // persistent (null: one block per tile whatever the configuration)
 hipError_t launch_rec(const LaunchRec& r, const void* dev_units, unsigned long long* work,
@@ -1252,13 +1301,15 @@ hipError_t launch_rec(const LaunchRec& r, const void* dev_units, unsigned long l
         return launch_vol_adjoint(static_cast<const RepArgs*>(dev_units), r.n, r.blocks, r.shape,
                                   work, st);
       return launch_adjoint(static_cast<const RepArgs*>(dev_units), r.n, r.blocks, r.shape, r.lds,
-                            r.stack, r.shared, work, st, q, grid);
+                            r.stack, r.shared, work, st, q, grid, r.det);
     case Kern::Meta:
       return launch_meta(static_cast<const MetaArgs*>(dev_units), r.n, r.blocks, st);
     case Kern::Adam:
       return launch_adam(static_cast<const AdamArgs*>(dev_units), r.n, r.blocks, st);
     case Kern::Dct:
       return launch_dct(static_cast<const DctArgs*>(dev_units), r.n, r.blocks, st);
+    case Kern::FxFlush:
+      return launch_fx_flush(static_cast<const FxArgs*>(dev_units), r.n, r.blocks, st);
   }
   return hipErrorInvalidValue;
 }
@@ -1364,7 +1415,7 @@ int exec_cached(jso_ctx* c, const std::vector<uint64_t>& sig, Build build) {
       const LaunchRec& r = plan[k];
       np.launches.push_back(
           CachedLaunch{(int)r.kind, r.timer, r.shape, r.n, r.stack, r.shared, r.vol, r.blocks,
-                       r.lds, off[k], r.persist});
+                       r.lds, off[k], r.persist, r.det});
     }
     np.sig = sig;
     pc.plans.push_back(std::move(np));
@@ -1385,6 +1436,7 @@ int exec_cached(jso_ctx* c, const std::vector<uint64_t>& sig, Build build) {
     r.shared = l.shared;
     r.vol = l.vol;
     r.persist = l.persist;
+    r.det = l.det;
     TIMED_LAUNCH(c, l.timer, launch_rec(r, hit->dev + l.offset, work, c->stream,
                                         hit->queues + 2 * k, c->n_cu));
   }
@@ -1398,6 +1450,8 @@ ProbPlan estimate_problem(SceneGPU* s, uint64_t seed, uint32_t iteration, int sp
                           int fd_mode) {
   ProbPlan p{};
   p.s = s;
+  p.fx_scale = fx_scale_of(s, true);
+  p.fx_scale = fx_scale_of(s, true);
   p.relative = loss == JSO_LOSS_RELATIVE;
   p.key = KeyArgs{seed, iteration, nullptr};
   p.crop = crop;
@@ -1481,7 +1535,7 @@ int jso_synchronize(jso_ctx* c) {
 
 int jso_set_debug(jso_ctx* c, uint32_t flags) {
   if (!c) return JSO_E_INVALID;
-  if (flags & ~15u) return fail(c, JSO_E_INVALID, "unknown debug flags 0x%x", flags);
+  if (flags & ~31u) return fail(c, JSO_E_INVALID, "unknown debug flags 0x%x", flags);
   c->debug_flags = flags;
   return JSO_OK;
 }
@@ -1658,6 +1712,8 @@ int jso_render_bwd(jso_ctx* c, int id, const float* params, uint64_t seed, uint3
   p.mask = opts ? opts->pixel_mask : nullptr;
   p.flags = c->debug_flags | (opts ? opts->flags : 0u);
   p.aj[p.na++] = AdjointSpec{params, nullptr, dimg, nullptr, dparams, 1.0f, tag, spp};
+  p.fx_scale = fx_scale_of(s, false);
+  if (int rc = ensure_fx(c, s, p.flags)) return rc;
   Plan plan;
   plan_estimators({p}, plan, c->launch_config);
   return exec_plan(c, plan);
@@ -1689,6 +1745,9 @@ int jso_render_bwd_noalloc(jso_ctx* c, int id, const float* params, uint64_t see
   p.mask = opts ? opts->pixel_mask : nullptr;
   p.flags = c->debug_flags | (opts ? opts->flags : 0u);
   p.aj[p.na++] = AdjointSpec{params, nullptr, dimg, nullptr, dparams, 1.0f, tag, spp};
+  if (p.flags & JSO_F_DETERMINISTIC)
+    return fail(c, JSO_E_UNSUPPORTED, "render_bwd_noalloc: no deterministic mode (its "
+                                      "fixed-point sums need memory of the scene's)");
   p.slots = reinterpret_cast<double*>(c->scratch);
   Plan plan;
   plan_estimators({p}, plan, c->launch_config, max_slots);
@@ -1712,6 +1771,7 @@ int jso_estimate_gradients(jso_ctx* c, int id, uint64_t seed, uint32_t iteration
   if (fd_mode != JSO_FD_REPLAY && fd_mode != JSO_FD_SHARED)
     return fail(c, JSO_E_INVALID, "unknown fd_mode %d", fd_mode);
   DeviceGuard g(c->device);
+  if (int rc = ensure_fx(c, s, c->debug_flags | (opts ? opts->flags : 0u))) return rc;
   HIP_TRY(c, hipMemsetAsync(s->scratch_loss, 0, 2 * sizeof(double), c->stream));
   Plan plan;
   plan_estimators({estimate_problem(s, seed, iteration, spp_prop, spp_fd, F, dF, img,
@@ -1817,6 +1877,8 @@ int jso_grad_step(jso_ctx* c, const int* ids, int n, const jso_step_opts* o,
   if (rc) return rc;
   DeviceGuard g(c->device);
   const uint32_t flags = c->debug_flags | o->flags;
+  for (int k = 0; k < n; ++k)
+    if (int rc2 = ensure_fx(c, get_scene(c, ids[k]), flags)) return rc2;
   std::vector<uint64_t> sig;
   auto bits = [](float f) {
     uint32_t u;
@@ -1920,6 +1982,7 @@ int batch_build(jso_batch* b, int config) {
   for (size_t k = 0; k < b->ids.size(); ++k) {
     SceneGPU* s = get_scene(c, b->ids[k]);
     if (!s) return fail(c, JSO_E_STATE, "scene %d of the batch was freed", b->ids[k]);
+    if (int rc = ensure_fx(c, s, b->flags)) return rc;
     ps.push_back(step_problem(s, b->opts, b->flags, b->max_iters[k]));
     if (uncorrelated(b->opts)) pv.push_back(variance_problem(s, b->opts, b->flags, b->max_iters[k]));
   }

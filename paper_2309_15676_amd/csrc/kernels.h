@@ -139,6 +139,11 @@ struct RepSlice {
   uint32_t tag;
   uint32_t sample;
   int slot_a, slot_b;    // forward radiance slots
+  // deterministic mode: 64-bit fixed-point accumulators of grad (contributions
+  // in units of 1 / fx_scale), folded into grad by k_fx_flush; null: FP32
+  // atomics into grad
+  JSO_GMEM unsigned long long* fx;
+  double fx_scale;
 };
 
 struct RepArgs {
@@ -158,6 +163,18 @@ struct RepArgs {
   // count those)
   int pair_lanes;
 };
+
+// One fixed-point gradient accumulator of the deterministic mode: grad[i] +=
+// fx[i] / fx_scale, then fx[i] = 0 (ready for the next step).
+struct FxArgs {
+  UnitHead h;
+  JSO_GMEM unsigned long long* fx;
+  JSO_GMEM float* grad;
+  size_t n;
+  double inv_scale;
+  uint32_t nblocks;
+};
+constexpr int kFxBlock = 256;
 
 struct MetaArgs {
   UnitHead h;
@@ -235,9 +252,10 @@ hipError_t launch_forward(const FwdArgs* U, int n, uint32_t blocks, int shape, i
                           uint32_t* queue = nullptr, uint32_t persist = 0);
 hipError_t launch_finalize(const FinArgs* U, int n, uint32_t blocks, hipStream_t st);
 // lds: dynamic LDS bytes (adjoint_lds_bytes of the largest channel count)
+// det: the units' slices carry fixed-point accumulators (deterministic mode)
 hipError_t launch_adjoint(const RepArgs* U, int n, uint32_t blocks, int shape, size_t lds,
                           int stack, bool shared, unsigned long long* work, hipStream_t st,
-                          uint32_t* queue = nullptr, uint32_t persist = 0);
+                          uint32_t* queue = nullptr, uint32_t persist = 0, bool det = false);
 // The same for emission-absorption volume scenes (every unit's scene a volume;
 // parameter buffers 16-byte aligned)
 hipError_t launch_vol_forward(const FwdArgs* U, int n, uint32_t blocks, int shape,
@@ -245,6 +263,7 @@ hipError_t launch_vol_forward(const FwdArgs* U, int n, uint32_t blocks, int shap
 hipError_t launch_vol_adjoint(const RepArgs* U, int n, uint32_t blocks, int shape,
                               unsigned long long* work, hipStream_t st);
 hipError_t launch_meta(const MetaArgs* U, int n, uint32_t blocks, hipStream_t st);
+hipError_t launch_fx_flush(const FxArgs* U, int n, uint32_t blocks, hipStream_t st);
 hipError_t launch_adam(const AdamArgs* U, int n, uint32_t blocks, hipStream_t st);
 hipError_t launch_fill_f64(double* p, size_t n, double v, hipStream_t st);
 hipError_t launch_fill_f32(float* p, size_t n, float v, hipStream_t st);

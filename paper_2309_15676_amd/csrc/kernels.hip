@@ -484,7 +484,25 @@ struct GradTable {
   uint32_t* keys;  // LDS: texel index of each slot
   float* vals;     // LDS: n_ch gradient values per slot
   float* grad;     // global gradient buffer of this block's job
+  // deterministic mode (fx set): every contribution goes, rounded to a
+  // multiple of 1 / fx_scale, into a 64-bit fixed-point accumulator with an
+  // integer atomic; integer sums do not depend on the order the atomics
+  // arrive in, so the result is bitwise reproducible across launches, tile
+  // shapes and batches.  The block table (LDS float atomics) is bypassed.
+  unsigned long long* fx;
+  double fx_scale;
 };
+
+// Add v to gradient element i: an FP32 atomic, or (kDet) fixed point (see
+// GradTable).  The deterministic mode has kernel instances of its own, so the
+// default ones carry none of its code.
+template <bool kDet>
+__device__ __forceinline__ void grad_add(const GradTable& T, size_t i, float v) {
+  if constexpr (kDet)
+    atomicAdd(T.fx + i, (unsigned long long)__double2ll_rn((double)v * T.fx_scale));
+  else
+    unsafeAtomicAdd(T.grad + i, v);
+}
 
 // Slot of `texel` in the table (claimed if new), or -1 when the probe
 // sequence is congested.
@@ -516,7 +534,7 @@ __device__ __forceinline__ void footprint_texel(const Footprint& fp, int q, int&
 // Add one first-hit vertex's material gradient g (R, G, B, metal, rough) to
 // its four texels in the block table (global atomics when a probe sequence is
 // congested).
-template <bool kMesh>
+template <bool kMesh, bool kDet>
 __device__ __forceinline__ void scatter_texels(const DevScene& S, const GradTable& T,
                                                const Footprint& fp, const float g[5],
                                                float sign) {
@@ -527,7 +545,7 @@ __device__ __forceinline__ void scatter_texels(const DevScene& S, const GradTabl
     float w;
     footprint_texel<kMesh>(fp, q, texel, w);
     if (w == 0.0f) continue;
-    const int h = table_slot(T, (uint32_t)texel);
+    const int h = kDet ? -1 : table_slot(T, (uint32_t)texel);
 #pragma unroll
     for (int b = 0; b < 5; ++b) {
       const int s = S.slot[b];
@@ -538,7 +556,7 @@ __device__ __forceinline__ void scatter_texels(const DevScene& S, const GradTabl
         __hip_atomic_fetch_add(&T.vals[h * nc + s], v, __ATOMIC_RELAXED,
                                __HIP_MEMORY_SCOPE_WORKGROUP);
       else
-        unsafeAtomicAdd(T.grad + (size_t)texel * nc + s, v);
+        grad_add<kDet>(T, (size_t)texel * nc + s, v);
     }
   }
 }
@@ -548,8 +566,8 @@ __device__ __forceinline__ void scatter_texels(const DevScene& S, const GradTabl
 // spreads each vertex over 4 * n_ch lanes, neighbouring lanes taking the
 // neighbouring channels of one texel: a texel then costs one transaction
 // instead of n_ch.  Must be reached by all 64 lanes of the wave.
-template <bool kMesh>
-__device__ __forceinline__ void scatter_wave(const DevScene& S, float* __restrict__ grad,
+template <bool kMesh, bool kDet>
+__device__ __forceinline__ void scatter_wave(const DevScene& S, const GradTable& T,
                                              const VertexGrad& v, float sign, bool has) {
   uint64_t m = __ballot(has);
   if (m == 0) return;
@@ -585,7 +603,7 @@ __device__ __forceinline__ void scatter_wave(const DevScene& S, float* __restric
       float w;
       footprint_texel<kMesh>(fp, q, texel, w);
       const float val = w * (sign * gc);
-      if (w != 0.0f && val != 0.0f) unsafeAtomicAdd(grad + (size_t)texel * nc + c, val);
+      if (w != 0.0f && val != 0.0f) grad_add<kDet>(T, (size_t)texel * nc + c, val);
     }
     for (int k = 0; k < nv && m != 0; ++k) m &= m - 1;
   }
@@ -602,6 +620,7 @@ __device__ __forceinline__ bool same_footprint(const Footprint& a, const Footpri
 // (reduced over the wave when it leaves), first-hit texels into the block's
 // table; later textured vertices are handed back for the wave-cooperative
 // scatter.
+template <bool kDet>
 struct Sink {
   float acc[5];
   GradTable T;
@@ -615,12 +634,20 @@ struct Sink {
   __device__ __forceinline__ bool add(const DevScene& S, const VertexGrad& v, float sign) {
     if (!v.valid) return false;
     if (v.fp.global) {
+      if constexpr (kDet) {  // each contribution on its own: fixed point is order-free
+#pragma unroll
+        for (int b = 0; b < 5; ++b) {
+          const float x = sign * v.g[b];
+          if (S.slot[b] >= 0 && x != 0.0f) grad_add<kDet>(T, (size_t)S.slot[b], x);
+        }
+        return false;
+      }
 #pragma unroll
       for (int b = 0; b < 5; ++b) acc[b] += sign * v.g[b];
       return false;
     }
     if (v.j > 1) return true;
-    scatter_texels<kMesh>(S, T, v.fp, v.g, sign);
+    scatter_texels<kMesh, kDet>(S, T, v.fp, v.g, sign);
     return false;
   }
   // every lane of the block (nthreads), after a barrier; neighbouring lanes
@@ -633,7 +660,7 @@ struct Sink {
       const uint32_t k = T.keys[slot];
       if (k == kEmpty) continue;
       const float v = T.vals[i];
-      if (v != 0.0f) unsafeAtomicAdd(T.grad + (size_t)k * nc + c, v);
+      if (v != 0.0f) grad_add<kDet>(T, (size_t)k * nc + c, v);
     }
   }
   // every lane of the wave
@@ -642,7 +669,7 @@ struct Sink {
     for (int b = 0; b < 5; ++b) {
       const int s = S.slot[b];
       const float v = wave_sum(acc[b]);
-      if (s >= 0 && (threadIdx.x & 63) == 0 && v != 0.0f) unsafeAtomicAdd(T.grad + s, v);
+      if (s >= 0 && (threadIdx.x & 63) == 0 && v != 0.0f) grad_add<kDet>(T, (size_t)s, v);
     }
   }
 };
@@ -681,7 +708,7 @@ __device__ __forceinline__ void replay_begin(const DevScene& S, const TravStack&
 // (their gradients go to the block table, flushed right after), later ones on
 // the compacted lanes in a wave-uniform loop, so the later-vertex scatter can
 // use the whole wave.  The exchange buffer reuses the table's LDS.
-template <class SH, bool kMesh>
+template <class SH, bool kMesh, bool kDet>
 __device__ __forceinline__ void adjoint_tile(const RepArgs& A, const DevScene* __restrict__ Sp,
                                              const TileBlock& tb, uint32_t iter, uint32_t* s_dyn,
                                              int* s_cnt, const TravStack& st,
@@ -697,8 +724,8 @@ __device__ __forceinline__ void adjoint_tile(const RepArgs& A, const DevScene* _
   for (int i = threadIdx.x; i < kTableSize; i += SH::N) s_keys[i] = kEmpty;
   for (int i = threadIdx.x; i < kTableSize * S.n_ch; i += SH::N) s_vals[i] = 0.0f;
   __syncthreads();
-  Sink sink;
-  sink.init(GradTable{s_keys, s_vals, G(sl.grad)});
+  Sink<kDet> sink;
+  sink.init(GradTable{s_keys, s_vals, G(sl.grad), G(sl.fx), sl.fx_scale});
   const uint64_t key = stream_key(A.key.seed, iter, sl.tag);
   const BlockPaths<SH> B = block_paths<SH>(tb, S, key, sl.sample, A.flags);
   const Rng rng = B.rng((int)threadIdx.x);
@@ -746,7 +773,7 @@ __device__ __forceinline__ void adjoint_tile(const RepArgs& A, const DevScene* _
         path_vertex<true, kMesh>(S, st, G(sl.params), wr, A.flags, W.P, W.adj, v);
       }
       const bool later = sink.template add<kMesh>(S, v, sl.sign);
-      scatter_wave<kMesh>(S, G(sl.grad), v, sl.sign, later);
+      scatter_wave<kMesh, kDet>(S, sink.T, v, sl.sign, later);
     }
   }
   sink.flush_acc(S);
@@ -798,7 +825,7 @@ __device__ __forceinline__ void pair_difference(VertexGrad& v, int half) {
 // kernel keeps the register budget of single paths.  The first vertices go to
 // the block table; then the live pairs are compacted, each onto two
 // neighbouring lanes.
-template <class SH, bool kMesh>
+template <class SH, bool kMesh, bool kDet>
 __device__ __forceinline__ void adjoint_tile_pairs(const RepArgs& A,
                                                    const DevScene* __restrict__ Sp,
                                                    const TileBlock& tb, uint32_t iter,
@@ -824,8 +851,8 @@ __device__ __forceinline__ void adjoint_tile_pairs(const RepArgs& A,
   for (int i = threadIdx.x; i < kTableSize; i += SH::N) s_keys[i] = kEmpty;
   for (int i = threadIdx.x; i < kTableSize * S.n_ch; i += SH::N) s_vals[i] = 0.0f;
   __syncthreads();
-  Sink sink;
-  sink.init(GradTable{s_keys, s_vals, G(sl.grad)});
+  Sink<kDet> sink;
+  sink.init(GradTable{s_keys, s_vals, G(sl.grad), G(sl.fx), sl.fx_scale});
   const uint64_t key = stream_key(A.key.seed, iter, sl.tag);
   const float* params = half ? G(sl.params_b) : G(sl.params);
   RepItem mine;
@@ -881,7 +908,7 @@ __device__ __forceinline__ void adjoint_tile_pairs(const RepArgs& A,
       }
       pair_difference<kMesh>(v, half);
       const bool later = sink.template add<kMesh>(S, v, 1.0f);
-      scatter_wave<kMesh>(S, G(sl.grad), v, 1.0f, later);
+      scatter_wave<kMesh, kDet>(S, sink.T, v, 1.0f, later);
     }
   }
   sink.flush_acc(S);
@@ -893,7 +920,7 @@ __device__ __forceinline__ void adjoint_tile_pairs(const RepArgs& A,
 // evaluated over A's densities), and the difference of the two gradients is
 // formed in registers over the one footprint they share, so it is scattered
 // once.  The first vertices go to the block table as in adjoint_tile.
-template <class SH, bool kMesh>
+template <class SH, bool kMesh, bool kDet>
 __device__ __forceinline__ void adjoint_tile_shared(const RepArgs& A,
                                                     const DevScene* __restrict__ Sp,
                                                     const TileBlock& tb, uint32_t iter,
@@ -911,8 +938,8 @@ __device__ __forceinline__ void adjoint_tile_shared(const RepArgs& A,
   for (int i = threadIdx.x; i < kTableSize; i += SH::N) s_keys[i] = kEmpty;
   for (int i = threadIdx.x; i < kTableSize * S.n_ch; i += SH::N) s_vals[i] = 0.0f;
   __syncthreads();
-  Sink sink;
-  sink.init(GradTable{s_keys, s_vals, G(sl.grad)});
+  Sink<kDet> sink;
+  sink.init(GradTable{s_keys, s_vals, G(sl.grad), G(sl.fx), sl.fx_scale});
   const uint64_t key = stream_key(A.key.seed, iter, sl.tag);
   const BlockPaths<SH> B = block_paths<SH>(tb, S, key, sl.sample, A.flags);
   const Rng rng = B.rng((int)threadIdx.x);
@@ -974,7 +1001,7 @@ __device__ __forceinline__ void adjoint_tile_shared(const RepArgs& A,
                                         v);
       }
       const bool later = sink.template add<kMesh>(S, v, 1.0f);
-      scatter_wave<kMesh>(S, G(sl.grad), v, 1.0f, later);
+      scatter_wave<kMesh, kDet>(S, sink.T, v, 1.0f, later);
     }
   }
   sink.flush_acc(S);
@@ -988,7 +1015,9 @@ __device__ __forceinline__ void adjoint_tile_shared(const RepArgs& A,
 // pairs and shared-path pairs each keep one path per lane, so the kernel runs
 // at 5 waves per SIMD (96 VGPRs; a few spills: 4-10% faster than 4 waves at
 // 128, 6 waves is slower again).
-template <int TW, int TH, bool kMesh, bool kShared>
+// kDet: the deterministic mode (fixed-point sums); its instances take every
+// kind of slice (single paths, lane pairs, shared-path pairs).
+template <int TW, int TH, bool kMesh, bool kShared, bool kDet = false>
 __global__ void __launch_bounds__(TW * TH)
 __attribute__((amdgpu_waves_per_eu(5)))
 k_adjoint(const RepArgs* __restrict__ Units, int n_units, int stack, unsigned long long* work,
@@ -1004,16 +1033,16 @@ k_adjoint(const RepArgs* __restrict__ Units, int n_units, int stack, unsigned lo
     const RepArgs& A = unit_of(Units, n_units, b);
     const uint32_t iter = iteration_of(A.key);
     if (A.h.max_iter && iter >= A.h.max_iter) continue;  // finished problem
-    if (!kShared && A.pair_lanes) {  // uniform over the block, as is everything below
+    if ((!kShared || kDet) && A.pair_lanes) {  // uniform over the block, as below
       const TileBlock tb = tile_block<SH>(A, b, SH::H / 2);
-      adjoint_tile_pairs<SH, kMesh>(A, G(A.scene), tb, iter, lds, s_cnt, st, work);
+      adjoint_tile_pairs<SH, kMesh, kDet>(A, G(A.scene), tb, iter, lds, s_cnt, st, work);
       continue;
     }
     const TileBlock tb = tile_block<SH>(A, b);
     if (kShared && G(A.sl[tb.slice].params_b) != nullptr)
-      adjoint_tile_shared<SH, kMesh>(A, G(A.scene), tb, iter, lds, s_cnt, st, work);
+      adjoint_tile_shared<SH, kMesh, kDet>(A, G(A.scene), tb, iter, lds, s_cnt, st, work);
     else
-      adjoint_tile<SH, kMesh>(A, G(A.scene), tb, iter, lds, s_cnt, st, work);
+      adjoint_tile<SH, kMesh, kDet>(A, G(A.scene), tb, iter, lds, s_cnt, st, work);
   }
   queue_done(queue);
 }
@@ -1649,6 +1678,23 @@ __global__ void __launch_bounds__(kDctBlock) k_dct(const DctArgs* __restrict__ U
   }
 }
 
+// ---------------------------------------------------------------------------
+// deterministic mode: fold the fixed-point accumulators into their gradients
+// ---------------------------------------------------------------------------
+__global__ void __launch_bounds__(kFxBlock) k_fx_flush(const FxArgs* __restrict__ Units,
+                                                        int n_units) {
+  const FxArgs& A = unit_of(Units, n_units);
+  const uint32_t lb = blockIdx.x - A.h.block0;
+  for (size_t i = (size_t)lb * kFxBlock + threadIdx.x; i < A.n;
+       i += (size_t)A.nblocks * kFxBlock) {
+    const long long v = (long long)G(A.fx)[i];
+    if (v != 0) {
+      G(A.grad)[i] += (float)((double)v * A.inv_scale);
+      G(A.fx)[i] = 0ull;
+    }
+  }
+}
+
 __global__ void k_fill_f64(double* p, size_t n, double v) {
   const size_t i = (size_t)blockIdx.x * blockDim.x + threadIdx.x;
   if (i < n) p[i] = v;
@@ -1733,40 +1779,42 @@ size_t adjoint_lds_bytes(int n_ch) {
   return table > xchg ? table : xchg;
 }
 
-template <int TW, int TH, bool kShared>
+template <int TW, int TH, bool kShared, bool kDet>
 static void adj_launch(const RepArgs* U, int n, uint32_t blocks, size_t lds, int stack,
                        unsigned long long* work, uint32_t* queue, uint32_t persist,
                        hipStream_t st) {
   const int cap = lds_stack(stack);
   const dim3 grid(grid_of(blocks, queue, persist));
   if (stack > 0)
-    hipLaunchKernelGGL((k_adjoint<TW, TH, true, kShared>), grid, dim3(TW * TH),
+    hipLaunchKernelGGL((k_adjoint<TW, TH, true, kShared, kDet>), grid, dim3(TW * TH),
                        lds + (size_t)cap * TW * TH * 4, st, U, n, cap, work, queue, blocks);
   else
-    hipLaunchKernelGGL((k_adjoint<TW, TH, false, kShared>), grid, dim3(TW * TH), lds, st,
+    hipLaunchKernelGGL((k_adjoint<TW, TH, false, kShared, kDet>), grid, dim3(TW * TH), lds, st,
                        U, n, 0, work, queue, blocks);
 }
 template <int TW, int TH>
 static void adj_launch(const RepArgs* U, int n, uint32_t blocks, size_t lds, int stack,
-                       bool shared, unsigned long long* work, uint32_t* queue, uint32_t persist,
-                       hipStream_t st) {
-  if (shared)
-    adj_launch<TW, TH, true>(U, n, blocks, lds, stack, work, queue, persist, st);
+                       bool shared, bool det, unsigned long long* work, uint32_t* queue,
+                       uint32_t persist, hipStream_t st) {
+  if (det)  // one instance takes every kind of slice
+    adj_launch<TW, TH, true, true>(U, n, blocks, lds, stack, work, queue, persist, st);
+  else if (shared)
+    adj_launch<TW, TH, true, false>(U, n, blocks, lds, stack, work, queue, persist, st);
   else
-    adj_launch<TW, TH, false>(U, n, blocks, lds, stack, work, queue, persist, st);
+    adj_launch<TW, TH, false, false>(U, n, blocks, lds, stack, work, queue, persist, st);
 }
 
 hipError_t launch_adjoint(const RepArgs* U, int n, uint32_t blocks, int shape, size_t lds,
                           int stack, bool shared, unsigned long long* work, hipStream_t st,
-                          uint32_t* queue, uint32_t persist) {
+                          uint32_t* queue, uint32_t persist, bool det) {
   if (n <= 0 || blocks == 0) return hipSuccess;
   if (lds < adjoint_lds_bytes(0) || lds > adjoint_lds_bytes(5)) return hipErrorInvalidValue;
   if (stack < 0 || stack > kBvhMaxStack) return hipErrorInvalidValue;
   if (queue && persist == 0) return hipErrorInvalidValue;
   switch (shape) {
-    case 0: adj_launch<16, 16>(U, n, blocks, lds, stack, shared, work, queue, persist, st); break;
-    case 1: adj_launch<16, 8>(U, n, blocks, lds, stack, shared, work, queue, persist, st); break;
-    case 2: adj_launch<8, 8>(U, n, blocks, lds, stack, shared, work, queue, persist, st); break;
+    case 0: adj_launch<16, 16>(U, n, blocks, lds, stack, shared, det, work, queue, persist, st); break;
+    case 1: adj_launch<16, 8>(U, n, blocks, lds, stack, shared, det, work, queue, persist, st); break;
+    case 2: adj_launch<8, 8>(U, n, blocks, lds, stack, shared, det, work, queue, persist, st); break;
     default: return hipErrorInvalidValue;
   }
   return hipGetLastError();
@@ -1805,6 +1853,12 @@ hipError_t launch_dct(const DctArgs* U, int n, uint32_t blocks, hipStream_t st) 
 hipError_t launch_meta(const MetaArgs* U, int n, uint32_t blocks, hipStream_t st) {
   if (n <= 0 || blocks == 0) return hipSuccess;
   hipLaunchKernelGGL(k_meta, dim3(blocks), dim3(kMetaBlock), 0, st, U, n);
+  return hipGetLastError();
+}
+
+hipError_t launch_fx_flush(const FxArgs* U, int n, uint32_t blocks, hipStream_t st) {
+  if (n <= 0 || blocks == 0) return hipSuccess;
+  hipLaunchKernelGGL(k_fx_flush, dim3(blocks), dim3(kFxBlock), 0, st, U, n);
   return hipGetLastError();
 }
 
