@@ -7,6 +7,7 @@
 #include <cmath>
 #include <cstdarg>
 #include <cstdio>
+#include <cstdlib>
 #include <cstring>
 #include <map>
 #include <memory>
@@ -54,6 +55,10 @@ struct SceneGPU {
   double *m1F = nullptr, *m1D = nullptr;
   float *Fv = nullptr, *dFv = nullptr;
   unsigned long long* fx = nullptr;  // deterministic mode: 2 x P fixed-point accumulators
+  // volumes: the bricked copies of up to 2 parameter vectors that the volume
+  // kernels read (BrickArgs), made at the start of each plan; brick_n floats each
+  float* vbrick = nullptr;
+  size_t brick_n = 0;
   uint32_t host_iter = 0;          // mirror of ctl->iteration
   uint64_t generation = 0;         // unique per loaded scene (plan cache key)
 };
@@ -210,6 +215,7 @@ struct CachedLaunch {
   size_t lds, offset;
   int persist;
   bool det;
+  int waves;
 };
 
 struct CachedPlan {
@@ -319,7 +325,7 @@ void free_scene_buffers(SceneGPU* s) {
                   s->m2D,    s->adam_m,      s->adam_v, s->ctl,    s->scratch_loss,
                   s->partials, s->slots,     s->accum,  s->d_scene, s->bvh_nodes,
                   s->bvh_tris, s->bvh_tri_id, s->pc, s->pc_tmp, s->m1F,
-                  s->m1D,    s->Fv,          s->dFv,    s->fx};
+                  s->m1D,    s->Fv,          s->dFv,    s->fx,     s->vbrick};
   for (void* b : bufs)
     if (b) (void)hipFree(b);
 }
@@ -465,6 +471,8 @@ int build_devscene(jso_ctx* c, const jso_scene_desc* d, SceneGPU* s) {
     const size_t R = (size_t)d->vol_res;
     s->P = R * R * R * 4;
     S.vol_res = d->vol_res;
+    S.vol_rb = (d->vol_res + 3) / 4;
+    s->brick_n = (size_t)S.vol_rb * S.vol_rb * S.vol_rb * 64 * 4;
     S.vol_views = d->vol_views;
     S.view_h = d->height / d->vol_views;
     for (int k = 0; k < 3; ++k) S.vol_lo[k] = d->vol_box[k];
@@ -683,7 +691,7 @@ double fx_scale_of(const SceneGPU* s, bool estimator) {
   return std::ldexp(1.0, 32 + (int)std::ceil(std::log2(1.5 * (double)s->npix)));
 }
 
-enum class Kern { Forward, Finalize, Adjoint, Meta, Adam, Dct, FxFlush };
+enum class Kern { Forward, Finalize, Adjoint, Meta, Adam, Dct, FxFlush, Brick };
 
 struct LaunchRec {
   Kern kind;
@@ -698,6 +706,7 @@ struct LaunchRec {
   bool vol = false;            // path kernels: the units' scenes are volumes
   int persist = 0;             // path kernels: persistent blocks per CU (0: none)
   bool det = false;            // adjoint: deterministic mode (fixed-point sums)
+  int waves = 0;               // volume forward: slices (waves) per block
   size_t dev_offset = 0;       // batches: offset of the units in the device arena
 };
 
@@ -753,6 +762,51 @@ void plan_estimators(const std::vector<ProbPlan>& ps, Plan& plan, int config = 0
   size_t next_prim = 0, next_unit = 0;
   int max_ch = 0;
   for (const ProbPlan& p : ps) max_ch = std::max(max_ch, p.s->n_ch);
+  // volumes: the kernels read bricked copies of the parameter vectors, made
+  // here first (each problem references at most 2 vectors)
+  std::vector<std::vector<std::pair<const float*, const float*>>> bricks(ps.size());
+  if (p0.s->dev.layout == JSO_LAYOUT_VOLUME) {
+    LaunchRec br;
+    br.kind = Kern::Brick;
+    br.timer = JSO_K_FORWARD;
+    for (size_t q = 0; q < ps.size(); ++q) {
+      const ProbPlan& p = ps[q];
+      auto add = [&](const float* src) {
+        if (!src) return;
+        for (const auto& x : bricks[q])
+          if (x.first == src) return;
+        if (bricks[q].size() == 2) {  // no entry point builds such a plan
+          std::fprintf(stderr, "jso: a volume plan references 3 parameter vectors\n");
+          std::abort();
+        }
+        const float* dst = p.s->vbrick + bricks[q].size() * p.s->brick_n;
+        bricks[q].push_back({src, dst});
+        BrickArgs b{};
+        b.src = gmem(reinterpret_cast<const float4*>(src));
+        b.dst = gmem(reinterpret_cast<float4*>(const_cast<float*>(dst)));
+        b.R = p.s->dev.vol_res;
+        b.Rb = p.s->dev.vol_rb;
+        const size_t vox = p.s->brick_n / 4;
+        b.nblocks = (uint32_t)std::min<size_t>((vox + kBrickBlock - 1) / kBrickBlock, 8192);
+        push_unit(br, b, b.nblocks);
+      };
+      for (int j = 0; j < p.np; ++j) {
+        add(p.pj[j].params);
+        add(p.pj[j].params_b);
+      }
+      for (int j = 0; j < p.na; ++j) {
+        add(p.aj[j].params);
+        add(p.aj[j].params_b);
+      }
+    }
+    plan.push_back(std::move(br));
+  }
+  // the pointer a kernel of problem q reads for parameter vector src
+  auto kparams = [&](size_t q, const float* src) -> const float* {
+    for (const auto& x : bricks[q])
+      if (x.first == src) return x.second;
+    return src;
+  };
   while (next_prim < prim.size() || next_unit < units.size()) {
     // slice layout of this launch (shared by all problems).  kind 0 primal,
     // 1 adjoint A, 2 adjoint B (replay pair), 3 adjoint shared pair; a slice
@@ -817,7 +871,9 @@ void plan_estimators(const std::vector<ProbPlan>& ps, Plan& plan, int config = 0
     fw.shape = shape;
     fw.vol = p0.s->dev.layout == JSO_LAYOUT_VOLUME;
     fw.persist = fw.vol ? 0 : persist_of(config);
-    for (const ProbPlan& p : ps) {
+    fw.waves = std::min((int)fsl.size(), kVolMaxSliceWaves);
+    for (size_t q = 0; q < ps.size(); ++q) {
+      const ProbPlan& p = ps[q];
       if (crop_empty(p.crop)) continue;
       FwdArgs f{};
       f.h.max_iter = p.max_iter;
@@ -829,13 +885,14 @@ void plan_estimators(const std::vector<ProbPlan>& ps, Plan& plan, int config = 0
         fs.slot = x.slot;
         fs.slot_b = x.slot_b;
         if (x.kind == 0) {
-          fs.params = gmem(p.pj[x.job].params);
-          fs.params_b = x.slot_b >= 0 ? gmem(p.pj[x.job].params_b) : gmem((const float*)nullptr);
+          fs.params = gmem(kparams(q, p.pj[x.job].params));
+          fs.params_b = x.slot_b >= 0 ? gmem(kparams(q, p.pj[x.job].params_b))
+                                      : gmem((const float*)nullptr);
           fs.tag = p.pj[x.job].tag;
         } else {
           const AdjointSpec& a = p.aj[x.job];
-          fs.params = gmem(x.kind == 2 ? a.params_b : a.params);
-          fs.params_b = x.kind == 3 ? gmem(a.params_b) : gmem((const float*)nullptr);
+          fs.params = gmem(kparams(q, x.kind == 2 ? a.params_b : a.params));
+          fs.params_b = x.kind == 3 ? gmem(kparams(q, a.params_b)) : gmem((const float*)nullptr);
           fs.tag = a.tag;
         }
         if (x.slot_b >= 0) fw.shared = true;
@@ -847,10 +904,19 @@ void plan_estimators(const std::vector<ProbPlan>& ps, Plan& plan, int config = 0
       f.slots = gmem(slots_of(p));
       f.npix = (uint32_t)p.s->npix;
       f.flags = p.flags;
-      f.tiles_x = tiles_x(p.crop, shape);
-      f.tiles = tiles_of(p.crop, shape);
       fw.stack = std::max(fw.stack, p.s->stack);
-      push_unit(fw, f, f.tiles * (uint32_t)f.n_slices);
+      if (fw.vol) {  // 8x8 tiles, fw.waves slices per block
+        constexpr int kVolShape = 2;
+        static_assert(kShapeW[kVolShape] == 8 && kShapeH[kVolShape] == 8, "volume tiles");
+        f.tiles_x = tiles_x(p.crop, kVolShape);
+        f.tiles = tiles_of(p.crop, kVolShape);
+        const uint32_t groups = (uint32_t)((f.n_slices + fw.waves - 1) / fw.waves);
+        push_unit(fw, f, f.tiles * groups);
+      } else {
+        f.tiles_x = tiles_x(p.crop, shape);
+        f.tiles = tiles_of(p.crop, shape);
+        push_unit(fw, f, f.tiles * (uint32_t)f.n_slices);
+      }
     }
     plan.push_back(std::move(fw));
     // k_finalize of the primal jobs with samples in this launch
@@ -923,7 +989,8 @@ void plan_estimators(const std::vector<ProbPlan>& ps, Plan& plan, int config = 0
       ad.persist = vol ? 0 : persist_of(config);
       ad.det = (p0.flags & JSO_F_DETERMINISTIC) != 0;
       for (int pass = 0; pass < 2; ++pass) {
-        for (const ProbPlan& p : ps) {
+        for (size_t q = 0; q < ps.size(); ++q) {
+          const ProbPlan& p = ps[q];
           if (crop_empty(p.crop)) continue;
           RepArgs r{};
           r.h.max_iter = p.max_iter;
@@ -932,8 +999,8 @@ void plan_estimators(const std::vector<ProbPlan>& ps, Plan& plan, int config = 0
             const AdjointSpec& a = p.aj[reps[i].first];
             if ((a.params_b != nullptr) != (pass == 0)) continue;
             RepSlice rs{};
-            rs.params = gmem(a.params);
-            rs.params_b = gmem(a.params_b);
+            rs.params = gmem(kparams(q, a.params));
+            rs.params_b = gmem(a.params_b ? kparams(q, a.params_b) : nullptr);
             rs.delta = gmem(a.delta);
             rs.delta_b = gmem(a.delta_b);
             rs.grad = gmem(a.grad);
@@ -1290,7 +1357,7 @@ hipError_t launch_rec(const LaunchRec& r, const void* dev_units, unsigned long l
   switch (r.kind) {
     case Kern::Forward:
       if (r.vol)
-        return launch_vol_forward(static_cast<const FwdArgs*>(dev_units), r.n, r.blocks, r.shape,
+        return launch_vol_forward(static_cast<const FwdArgs*>(dev_units), r.n, r.blocks, r.waves,
                                   work, st);
       return launch_forward(static_cast<const FwdArgs*>(dev_units), r.n, r.blocks, r.shape,
                             r.stack, r.shared, work, st, q, grid);
@@ -1310,6 +1377,8 @@ hipError_t launch_rec(const LaunchRec& r, const void* dev_units, unsigned long l
       return launch_dct(static_cast<const DctArgs*>(dev_units), r.n, r.blocks, st);
     case Kern::FxFlush:
       return launch_fx_flush(static_cast<const FxArgs*>(dev_units), r.n, r.blocks, st);
+    case Kern::Brick:
+      return launch_vol_brick(static_cast<const BrickArgs*>(dev_units), r.n, r.blocks, st);
   }
   return hipErrorInvalidValue;
 }
@@ -1415,7 +1484,7 @@ int exec_cached(jso_ctx* c, const std::vector<uint64_t>& sig, Build build) {
       const LaunchRec& r = plan[k];
       np.launches.push_back(
           CachedLaunch{(int)r.kind, r.timer, r.shape, r.n, r.stack, r.shared, r.vol, r.blocks,
-                       r.lds, off[k], r.persist, r.det});
+                       r.lds, off[k], r.persist, r.det, r.waves});
     }
     np.sig = sig;
     pc.plans.push_back(std::move(np));
@@ -1437,6 +1506,7 @@ int exec_cached(jso_ctx* c, const std::vector<uint64_t>& sig, Build build) {
     r.vol = l.vol;
     r.persist = l.persist;
     r.det = l.det;
+    r.waves = l.waves;
     TIMED_LAUNCH(c, l.timer, launch_rec(r, hit->dev + l.offset, work, c->stream,
                                         hit->queues + 2 * k, c->n_cu));
   }
@@ -1589,6 +1659,7 @@ int jso_load_scene(jso_ctx* c, const jso_scene_desc* d, int* scene_id) {
   A(dalloc(&s->slots, (size_t)kMaxSlots * n3));
   A(dalloc(&s->accum, 3 * n3));
   A(dalloc(&s->d_scene, 1));
+  if (s->brick_n) A(dalloc(&s->vbrick, 2 * s->brick_n));
   if (e != hipSuccess) {
     free_scene_buffers(s.get());
     return fail(c, e == hipErrorOutOfMemory ? JSO_E_OOM : JSO_E_HIP, "scene allocation: %s",

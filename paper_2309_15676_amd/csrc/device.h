@@ -51,8 +51,9 @@ struct DevScene {
   JSO_GMEM const float4* bvh_nodes;  // four-wide nodes, 8 words each
   JSO_GMEM const float4* bvh_tris;   // 3 words per triangle, leaf order
   JSO_GMEM const int* bvh_tri_id;    // original index of each reordered triangle
-  // emission-absorption volume (layout JSO_LAYOUT_VOLUME)
-  int vol_res, vol_views, view_h;
+  // emission-absorption volume (layout JSO_LAYOUT_VOLUME); vol_rb: bricks of
+  // 4x4x4 voxels per side of the kernels' bricked copy of the parameters
+  int vol_res, vol_rb, vol_views, view_h;
   float vol_lo[3], vol_side, vol_inv_vox, vol_sigma;
   float view_eye[JSO_MAX_VIEWS][3], view_cw[JSO_MAX_VIEWS][3], view_cu[JSO_MAX_VIEWS][3],
       view_cv[JSO_MAX_VIEWS][3];

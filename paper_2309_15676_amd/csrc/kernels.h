@@ -176,6 +176,21 @@ struct FxArgs {
 };
 constexpr int kFxBlock = 256;
 
+// The bricked copy of one volume parameter vector that the volume kernels
+// read: dst holds vol_rb^3 bricks of 4x4x4 voxels in (z, y, x) brick order,
+// the 64 voxels of a brick in Morton order (bit 0 x, bit 1 y, bit 2 z, then
+// the second bits), so each 128-byte line is a 2x2x2 block of voxels; voxels
+// past the grid's edge are zero.  src: the parameters in the interface's
+// layout ((z R + y) R + x) * 4 + channel.
+struct BrickArgs {
+  UnitHead h;
+  JSO_GMEM const float4* src;
+  JSO_GMEM float4* dst;
+  int R, Rb;
+  uint32_t nblocks;
+};
+constexpr int kBrickBlock = 256;
+
 struct MetaArgs {
   UnitHead h;
   uint32_t nblocks;
@@ -257,11 +272,17 @@ hipError_t launch_adjoint(const RepArgs* U, int n, uint32_t blocks, int shape, s
                           int stack, bool shared, unsigned long long* work, hipStream_t st,
                           uint32_t* queue = nullptr, uint32_t persist = 0, bool det = false);
 // The same for emission-absorption volume scenes (every unit's scene a volume;
-// parameter buffers 16-byte aligned)
-hipError_t launch_vol_forward(const FwdArgs* U, int n, uint32_t blocks, int shape,
+// the slices' parameter pointers are bricked copies made by launch_vol_brick;
+// the gradients are in the interface's layout)
+// The volume forward takes 8x8 pixel tiles and `waves` slices per block, one
+// wave each (1 <= waves <= kVolMaxSliceWaves; blocks of a unit: tiles x
+// ceil(n_slices / waves)), whatever the configuration's tile shape.
+constexpr int kVolMaxSliceWaves = 8;
+hipError_t launch_vol_forward(const FwdArgs* U, int n, uint32_t blocks, int waves,
                               unsigned long long* work, hipStream_t st);
 hipError_t launch_vol_adjoint(const RepArgs* U, int n, uint32_t blocks, int shape,
                               unsigned long long* work, hipStream_t st);
+hipError_t launch_vol_brick(const BrickArgs* U, int n, uint32_t blocks, hipStream_t st);
 hipError_t launch_meta(const MetaArgs* U, int n, uint32_t blocks, hipStream_t st);
 hipError_t launch_fx_flush(const FxArgs* U, int n, uint32_t blocks, hipStream_t st);
 hipError_t launch_adam(const AdamArgs* U, int n, uint32_t blocks, hipStream_t st);

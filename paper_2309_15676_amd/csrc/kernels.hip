@@ -1097,9 +1097,23 @@ __device__ __forceinline__ VolRay vol_ray(const DevScene& S, const Rng& rng, int
   return r;
 }
 
-// Trilinear corners of the sample at x: voxel indices (8, clamped to the
-// grid), the cell's base (unclamped floor of the grid coordinate) and the
-// fractions.
+// Offsets of voxel coordinate i along each axis in the bricked copy (see
+// BrickArgs): the brick's offset (multiples of 64 voxels) plus the axis's two
+// Morton bits, so a voxel's index is the sum of its three axis offsets.
+__device__ __forceinline__ int brick_x(int i, int Rb) {
+  (void)Rb;
+  return ((i >> 2) << 6) | (i & 1) | ((i & 2) << 2);
+}
+__device__ __forceinline__ int brick_y(int i, int Rb) {
+  return (((i >> 2) * Rb) << 6) | ((i & 1) << 1) | ((i & 2) << 3);
+}
+__device__ __forceinline__ int brick_z(int i, int Rb) {
+  return (((i >> 2) * Rb * Rb) << 6) | ((i & 1) << 2) | ((i & 2) << 4);
+}
+
+// Trilinear corners of the sample at x: voxel indices in the bricked copy (8,
+// clamped to the grid), the cell's base (unclamped floor of the grid
+// coordinate) and the fractions.
 struct VolCell {
   int idx[8];
   int bx, by, bz;
@@ -1110,7 +1124,7 @@ struct VolCell {
 };
 
 __device__ __forceinline__ VolCell vol_cell(const DevScene& S, V3 x) {
-  const int R = S.vol_res;
+  const int R = S.vol_res, Rb = S.vol_rb;
   const float g[3] = {(x.x - S.vol_lo[0]) * S.vol_inv_vox - 0.5f,
                       (x.y - S.vol_lo[1]) * S.vol_inv_vox - 0.5f,
                       (x.z - S.vol_lo[2]) * S.vol_inv_vox - 0.5f};
@@ -1130,10 +1144,11 @@ __device__ __forceinline__ VolCell vol_cell(const DevScene& S, V3 x) {
   c.bx = (int)floorf(g[0]);
   c.by = (int)floorf(g[1]);
   c.bz = (int)floorf(g[2]);
+  const int ox[2] = {brick_x(i0[0], Rb), brick_x(i1[0], Rb)};
+  const int oy[2] = {brick_y(i0[1], Rb), brick_y(i1[1], Rb)};
+  const int oz[2] = {brick_z(i0[2], Rb), brick_z(i1[2], Rb)};
 #pragma unroll
-  for (int k = 0; k < 8; ++k)
-    c.idx[k] = (((k & 4) ? i1[2] : i0[2]) * R + ((k & 2) ? i1[1] : i0[1])) * R +
-               ((k & 1) ? i1[0] : i0[0]);
+  for (int k = 0; k < 8; ++k) c.idx[k] = oz[k >> 2] + oy[(k >> 1) & 1] + ox[k & 1];
   return c;
 }
 
@@ -1188,18 +1203,52 @@ __device__ __forceinline__ int vol_march(const DevScene& S, const VolRay& r,
   return r.n;
 }
 
-template <int TW, int TH>
-__global__ void __launch_bounds__(TW * TH)
+// The hardware deals a grid's blocks out to the 8 XCDs in turn (block i to
+// XCD i mod 8), and each XCD has an L2 of its own.  The volume kernels
+// renumber their blocks so that XCD j takes the j-th contiguous eighth of
+// the tiles, in order: the blocks resident on one XCD at a time are then
+// neighbouring tiles of one view, whose rays cross the same voxels at about
+// the same time and share that XCD's L2.  A bijection of [0, n).
+__device__ __forceinline__ uint32_t xcd_block(uint32_t i, uint32_t n) {
+  const uint32_t q = n >> 3, r = n & 7u, x = i & 7u;
+  return x * q + min(x, r) + (i >> 3);
+}
+
+// A volume replay unit's block: its tiles in order, each tile's slices
+// together (the slices of a tile march nearly the same rays, so running them
+// side by side lets them share the voxels in L2).
+template <class SH, class U>
+__device__ __forceinline__ TileBlock vol_tile_block(const U& u, uint32_t b) {
+  const uint32_t local = b - u.h.block0;
+  const uint32_t ns = (uint32_t)u.n_slices;
+  const uint32_t t = local / ns;
+  return TileBlock{(int)(local - t * ns), u.crop.x0 + (int)(t % u.tiles_x) * SH::W,
+                   u.crop.y0 + (int)(t / u.tiles_x) * SH::H};
+}
+
+// The volume forward: a block takes one 8x8 pixel tile and blockDim.x / 64 of
+// the unit's slices, one wave each (block b of a unit: tile b / groups, slice
+// group b % groups).  The waves march nearly the same rays in step, so each
+// voxel line one of them brings into the CU's L1 and the XCD's L2 serves the
+// others too.
+__global__ void __launch_bounds__(64 * kVolMaxSliceWaves)
 k_vol_forward(const FwdArgs* __restrict__ Units, int n_units, unsigned long long* work) {
-  using SH = Shape<TW, TH>;
-  const FwdArgs& A = unit_of(Units, n_units);
+  const uint32_t b = xcd_block(blockIdx.x, gridDim.x);
+  const FwdArgs& A = unit_of(Units, n_units, b);
   const uint32_t iter = iteration_of(A.key);
   if (A.h.max_iter && iter >= A.h.max_iter) return;  // finished problem
   const DevScene& S = *G(A.scene);
-  const TileBlock tb = tile_block<SH>(A, blockIdx.x);
-  const FwdSlice& sl = A.sl[tb.slice];
-  int px, py;
-  const bool inside = tile_pixel<SH>(A.crop, tb, px, py);
+  const int waves = (int)(blockDim.x / 64);
+  const uint32_t groups = (uint32_t)((A.n_slices + waves - 1) / waves);
+  const uint32_t local = b - A.h.block0;
+  const uint32_t t = local / groups;
+  const int slice = (int)(local - t * groups) * waves + (int)(threadIdx.x / 64);
+  if (slice >= A.n_slices) return;  // a whole wave: the group's last slices
+  const FwdSlice& sl = A.sl[slice];
+  const int lane = (int)(threadIdx.x % 64);
+  const int px = A.crop.x0 + (int)(t % A.tiles_x) * 8 + (lane & 7);
+  const int py = A.crop.y0 + (int)(t / A.tiles_x) * 8 + (lane >> 3);
+  const bool inside = px < A.crop.x1 && py < A.crop.y1;
   const uint32_t pix = (uint32_t)(py * S.width + px);
   const bool active = inside && !(G(A.mask) && G(A.mask)[pix]);
   int n_samples = 0;
@@ -1223,93 +1272,141 @@ k_vol_forward(const FwdArgs* __restrict__ Units, int n_units, unsigned long long
 //   dC/de_k     = T_k a_k
 //   dC/dsigma_k = dt (T_{k+1} e_k - R_{k+1})
 // (R_{k+1}: the radiance behind the sample, environment included), times the
-// density scale, spread over the 8 voxels by the trilinear weights with
-// no-return FP32 atomics.  Pairs difference the two ledgers' gradients per
-// sample (same voxels) and scatter once.
+// density scale, spread over the 8 voxels by the trilinear weights and added
+// to the gradient with no-return FP32 atomics.  Pairs difference the two
+// ledgers' gradients per sample (same voxels) and scatter once.
+//
 // Per-lane sums over the 8 corners of the current cell.  Consecutive samples
 // of a ray share the corners of the cell faces they stay between, so their
-// gradients are summed in registers and a corner is written out (4 atomics)
-// only when the ray leaves it: about half the atomics of writing every
-// sample's 8 corners.  A corner's slot is given by the parities of its voxel
-// coordinates (bit 0: x, bit 1: y, bit 2: z), so moving to a neighbouring
-// cell keeps the shared corners in place and only the slots whose
-// coordinate changes are written out; slot indices stay compile-time
-// constants (the sums stay in registers).
+// gradients are summed in registers and a corner is written out only when the
+// ray leaves it.  A corner's slot is given by the parities of its voxel
+// coordinates (bit 0: x, bit 1: y, bit 2: z), so moving to a neighbouring cell
+// keeps the shared corners in place and only the slots whose coordinate
+// changes are written out; slot indices stay compile-time constants (the sums
+// stay in registers).
+//
+// The write-out is wave-cooperative: the lanes leaving a slot put its voxel
+// and 4 sums into the wave's LDS staging area, and the wave adds them with 4
+// lanes per voxel, so that one atomic instruction carries 16 voxels' 16-byte
+// rows.  The L2 takes atomics at a rate per distinct line segment an
+// instruction touches, not per lane, so this needs a quarter of the requests
+// of adding each channel from its own lane.  Every lane of the wave runs the
+// march to the wave's longest ray, those past their own end idle.
 struct CornerSums {
   int x[2], y[2], z[2];  // voxel coordinate held by the slots of each parity
   float4 acc[8];
 };
 
-template <int SL>
-__device__ __forceinline__ void corner_flush(const DevScene& S, float* grad, CornerSums& cs) {
+// A wave's staging area: the voxel (linear index) and sums of up to 8 slots
+// per lane.
+constexpr int kVolStage = 8 * 64;
+struct VolStage {
+  float4 v[kVolStage];
+  int voxel[kVolStage];
+};
+
+// Write out the slots in each lane's mask f (bit sl: slot sl) and clear those
+// sums.  Every lane of the wave calls this.  A lane's slots are staged
+// together, in slot order (x-neighbouring voxels next to each other), lanes
+// in order (neighbouring pixels): the voxels an atomic instruction carries
+// then often share 64-byte segments of the gradient, which the L2 takes as
+// one request.
+__device__ __forceinline__ void corner_write(const DevScene& S, float* grad, CornerSums& cs,
+                                             VolStage& st, uint32_t f) {
+  if (__ballot(f != 0u) == 0) return;
   const int R = S.vol_res;
-  const int x = min(max(cs.x[SL & 1], 0), R - 1);
-  const int y = min(max(cs.y[(SL >> 1) & 1], 0), R - 1);
-  const int z = min(max(cs.z[SL >> 2], 0), R - 1);
-  float* gp = grad + 4 * (size_t)((z * R + y) * R + x);
-  const float4 v = cs.acc[SL];
-  if (v.x != 0.0f) unsafeAtomicAdd(gp + 0, v.x);
-  if (v.y != 0.0f) unsafeAtomicAdd(gp + 1, v.y);
-  if (v.z != 0.0f) unsafeAtomicAdd(gp + 2, v.z);
-  if (v.w != 0.0f) unsafeAtomicAdd(gp + 3, v.w);
-  cs.acc[SL] = make_float4(0.0f, 0.0f, 0.0f, 0.0f);
-}
-
-// Write out the slots whose coordinate along axis AX (0, 1, 2) changes for a
-// cell with base b on that axis.
-template <int AX>
-__device__ __forceinline__ void corner_move(const DevScene& S, float* grad, CornerSums& cs,
-                                            int b) {
-  int* co = AX == 0 ? cs.x : (AX == 1 ? cs.y : cs.z);
+  const int lane = (int)__lane_id();
+  // this lane's first entry: the exclusive prefix sum of the slot counts
+  const int cnt = __popc(f);
+  int incl = cnt;
 #pragma unroll
-  for (int p = 0; p < 2; ++p) {
-    const int need = ((b & 1) == p) ? b : b + 1;
-    if (co[p] != need) {
-#pragma unroll
-      for (int sl = 0; sl < 8; ++sl) {
-        if (((sl >> AX) & 1) != p) continue;
-        switch (sl) {
-          case 0: corner_flush<0>(S, grad, cs); break;
-          case 1: corner_flush<1>(S, grad, cs); break;
-          case 2: corner_flush<2>(S, grad, cs); break;
-          case 3: corner_flush<3>(S, grad, cs); break;
-          case 4: corner_flush<4>(S, grad, cs); break;
-          case 5: corner_flush<5>(S, grad, cs); break;
-          case 6: corner_flush<6>(S, grad, cs); break;
-          default: corner_flush<7>(S, grad, cs); break;
-        }
-      }
-      co[p] = need;
-    }
+  for (int o = 1; o < 64; o <<= 1) {
+    const int t = __shfl_up(incl, (unsigned)o, 64);
+    if (lane >= o) incl += t;
   }
+  const int n = __builtin_amdgcn_readfirstlane(__shfl(incl, 63, 64));  // entries in all
+  int e = incl - cnt;
+#pragma unroll
+  for (int sl = 0; sl < 8; ++sl) {
+    if (!((f >> sl) & 1u)) continue;
+    const int x = min(max(cs.x[sl & 1], 0), R - 1);
+    const int y = min(max(cs.y[(sl >> 1) & 1], 0), R - 1);
+    const int z = min(max(cs.z[sl >> 2], 0), R - 1);
+    st.v[e] = cs.acc[sl];
+    st.voxel[e] = (z * R + y) * R + x;
+    cs.acc[sl] = make_float4(0.0f, 0.0f, 0.0f, 0.0f);
+    ++e;
+  }
+  // the staged entries of the other lanes are read below: LDS operations of
+  // one wave complete in order; the fences keep the compiler from moving the
+  // reads above the writes
+  __builtin_amdgcn_fence(__ATOMIC_RELEASE, "wavefront");
+  __builtin_amdgcn_wave_barrier();
+  __builtin_amdgcn_fence(__ATOMIC_ACQUIRE, "wavefront");
+  const int ch = lane & 3;
+  for (int k = lane >> 2; k < n; k += 16) {
+    const float val = reinterpret_cast<const float*>(&st.v[k])[ch];
+    if (val != 0.0f) unsafeAtomicAdd(grad + 4 * (size_t)st.voxel[k] + ch, val);
+  }
+  // the next write-out reuses the area
+  __builtin_amdgcn_fence(__ATOMIC_RELEASE, "wavefront");
+  __builtin_amdgcn_wave_barrier();
+  __builtin_amdgcn_fence(__ATOMIC_ACQUIRE, "wavefront");
 }
 
-// One pixel's replay of a volume slice (see k_vol_adjoint).
+// Move the slots of axis AX (0, 1, 2; coordinates co) to a cell with base b
+// on that axis: returns the slots to write out first, those whose coordinate
+// changes (the slots of parity p on axis AX: bit AX of the index equal to p),
+// and sets the new coordinates in `next`.
+template <int AX>
+__device__ __forceinline__ uint32_t corner_move(const int co[2], int b, int next[2]) {
+  constexpr uint32_t kLow = AX == 0 ? 0x55u : (AX == 1 ? 0x33u : 0x0Fu);
+  next[0] = (b & 1) == 0 ? b : b + 1;
+  next[1] = (b & 1) == 1 ? b : b + 1;
+  return (co[0] != next[0] ? kLow : 0u) | (co[1] != next[1] ? (kLow ^ 0xFFu) : 0u);
+}
+
+// The cell base (floor of the grid coordinate) of the sample at x.
+__device__ __forceinline__ void vol_base(const DevScene& S, V3 x, int& bx, int& by, int& bz) {
+  bx = (int)floorf((x.x - S.vol_lo[0]) * S.vol_inv_vox - 0.5f);
+  by = (int)floorf((x.y - S.vol_lo[1]) * S.vol_inv_vox - 0.5f);
+  bz = (int)floorf((x.z - S.vol_lo[2]) * S.vol_inv_vox - 0.5f);
+}
+
+// One pixel's replay of a volume slice (see above); every lane of the wave
+// calls it, those with active unset trace nothing.
 __device__ __forceinline__ void vol_replay(const DevScene& S, const RepArgs& A,
-                                           const RepSlice& sl, uint32_t pix, int px, int py,
-                                           uint32_t iter, int& n_samples) {
+                                           const RepSlice& sl, VolStage& st, bool active,
+                                           uint32_t pix, int px, int py, uint32_t iter,
+                                           int& n_samples) {
   const bool pair = G(sl.params_b) != nullptr;
   const float* pa = G(sl.params);
   const float* pb = G(sl.params_b);
   float* grad = G(sl.grad);
-  const Rng rng = make_rng(stream_key(A.key.seed, iter, sl.tag), pix, sl.sample);
-  const VolRay r = vol_ray(S, rng, px, py, A.flags);
+  VolRay r{};
   float adj[3], adj_b[3];
   double rem[3], rem_b[3];
-  const double* Ca = G(A.slots) + ((size_t)sl.slot_a * A.npix + pix) * 3;
 #pragma unroll
   for (int ch = 0; ch < 3; ++ch) {
-    adj[ch] = G(sl.delta)[3 * (size_t)pix + ch] * sl.adj_scale;
-    rem[ch] = Ca[ch];
-    adj_b[ch] = 0.0f;
-    rem_b[ch] = 0.0;
+    adj[ch] = adj_b[ch] = 0.0f;
+    rem[ch] = rem_b[ch] = 0.0;
   }
-  if (pair) {
-    const double* Cb = G(A.slots) + ((size_t)sl.slot_b * A.npix + pix) * 3;
+  if (active) {
+    const Rng rng = make_rng(stream_key(A.key.seed, iter, sl.tag), pix, sl.sample);
+    r = vol_ray(S, rng, px, py, A.flags);
+    const double* Ca = G(A.slots) + ((size_t)sl.slot_a * A.npix + pix) * 3;
 #pragma unroll
     for (int ch = 0; ch < 3; ++ch) {
-      adj_b[ch] = G(sl.delta_b)[3 * (size_t)pix + ch] * sl.adj_scale;
-      rem_b[ch] = Cb[ch];
+      adj[ch] = G(sl.delta)[3 * (size_t)pix + ch] * sl.adj_scale;
+      rem[ch] = Ca[ch];
+    }
+    if (pair) {
+      const double* Cb = G(A.slots) + ((size_t)sl.slot_b * A.npix + pix) * 3;
+#pragma unroll
+      for (int ch = 0; ch < 3; ++ch) {
+        adj_b[ch] = G(sl.delta_b)[3 * (size_t)pix + ch] * sl.adj_scale;
+        rem_b[ch] = Cb[ch];
+      }
     }
   }
   const float sign = pair ? 1.0f : sl.sign;
@@ -1319,11 +1416,36 @@ __device__ __forceinline__ void vol_replay(const DevScene& S, const RepArgs& A,
   for (int q = 0; q < 8; ++q) cs.acc[q] = make_float4(0.0f, 0.0f, 0.0f, 0.0f);
 #pragma unroll
   for (int p = 0; p < 2; ++p) cs.x[p] = cs.y[p] = cs.z[p] = INT_MIN;
-  for (int k = 0; k < r.n; ++k) {
-    const VolCell c = vol_cell(S, r.o + r.d * (r.t0 + ((float)k + r.us) * r.dt));
-    corner_move<0>(S, grad, cs, c.bx);
-    corner_move<1>(S, grad, cs, c.by);
-    corner_move<2>(S, grad, cs, c.bz);
+  // the wave's longest march (a scalar bound keeps the loop's registers as
+  // few as a per-lane bound would)
+  int n_wave = r.n;
+  for (int o = 32; o > 0; o >>= 1) n_wave = max(n_wave, __shfl_xor(n_wave, o, 64));
+  n_wave = __builtin_amdgcn_readfirstlane(n_wave);
+  for (int k = 0; k < n_wave; ++k) {
+    const bool live = k < r.n;
+    const V3 xs = r.o + r.d * (r.t0 + ((float)k + r.us) * r.dt);
+    int bx = 0, by = 0, bz = 0;
+    if (live) vol_base(S, xs, bx, by, bz);
+    if (k == 0) {  // the slots start at the first cell's corners (sums zero)
+#pragma unroll
+      for (int p = 0; p < 2; ++p) {
+        cs.x[p] = ((bx & 1) == p) ? bx : bx + 1;
+        cs.y[p] = ((by & 1) == p) ? by : by + 1;
+        cs.z[p] = ((bz & 1) == p) ? bz : bz + 1;
+      }
+    }
+    int nx[2], ny[2], nz[2];
+    uint32_t f = corner_move<0>(cs.x, bx, nx) | corner_move<1>(cs.y, by, ny) |
+                 corner_move<2>(cs.z, bz, nz);
+    corner_write(S, grad, cs, st, live ? f : 0u);
+    if (!live) continue;
+#pragma unroll
+    for (int p = 0; p < 2; ++p) {
+      cs.x[p] = nx[p];
+      cs.y[p] = ny[p];
+      cs.z[p] = nz[p];
+    }
+    const VolCell c = vol_cell(S, xs);
     float g[4];
     {
       const float4 v = vol_fetch(pa, c);
@@ -1374,14 +1496,7 @@ __device__ __forceinline__ void vol_replay(const DevScene& S, const RepArgs& A,
       cs.acc[sl].w += w * g[3];
     }
   }
-  corner_flush<0>(S, grad, cs);
-  corner_flush<1>(S, grad, cs);
-  corner_flush<2>(S, grad, cs);
-  corner_flush<3>(S, grad, cs);
-  corner_flush<4>(S, grad, cs);
-  corner_flush<5>(S, grad, cs);
-  corner_flush<6>(S, grad, cs);
-  corner_flush<7>(S, grad, cs);
+  corner_write(S, grad, cs, st, r.n > 0 ? 0xFFu : 0u);
   n_samples = r.n;
 }
 
@@ -1389,22 +1504,44 @@ template <int TW, int TH>
 __global__ void __launch_bounds__(TW * TH)
 k_vol_adjoint(const RepArgs* __restrict__ Units, int n_units, unsigned long long* work) {
   using SH = Shape<TW, TH>;
-  const RepArgs& A = unit_of(Units, n_units);
+  __shared__ VolStage s_stage[SH::N / 64];
+  const uint32_t b = xcd_block(blockIdx.x, gridDim.x);
+  const RepArgs& A = unit_of(Units, n_units, b);
   const uint32_t iter = iteration_of(A.key);
   if (A.h.max_iter && iter >= A.h.max_iter) return;  // finished problem
   const DevScene& S = *G(A.scene);
-  const TileBlock tb = tile_block<SH>(A, blockIdx.x);
+  const TileBlock tb = vol_tile_block<SH>(A, b);
   const RepSlice& sl = A.sl[tb.slice];
   int px, py;
   const bool inside = tile_pixel<SH>(A.crop, tb, px, py);
   const uint32_t pix = (uint32_t)(py * S.width + px);
   const bool active = inside && !(G(A.mask) && G(A.mask)[pix]);
   int n_samples = 0;
-  if (active) vol_replay(S, A, sl, pix, px, py, iter, n_samples);
+  vol_replay(S, A, sl, s_stage[threadIdx.x / 64], active, pix, px, py, iter, n_samples);
   count_work(work, active ? 1 : 0, n_samples);
 }
 
-
+// The bricked copy of a volume parameter vector (BrickArgs), one destination
+// voxel per thread (the writes are contiguous).
+__global__ void __launch_bounds__(kBrickBlock) k_vol_brick(const BrickArgs* __restrict__ Units,
+                                                           int n_units) {
+  const BrickArgs& A = unit_of(Units, n_units);
+  const uint32_t lb = blockIdx.x - A.h.block0;
+  const int R = A.R, Rb = A.Rb;
+  const size_t n = (size_t)Rb * Rb * Rb * 64;
+  for (size_t d = (size_t)lb * kBrickBlock + threadIdx.x; d < n;
+       d += (size_t)A.nblocks * kBrickBlock) {
+    const uint32_t brick = (uint32_t)(d >> 6), m = (uint32_t)d & 63u;
+    const int x = (int)(brick % (uint32_t)Rb) * 4 + (int)((m & 1u) | ((m >> 2) & 2u));
+    const int y = (int)((brick / (uint32_t)Rb) % (uint32_t)Rb) * 4 +
+                  (int)(((m >> 1) & 1u) | ((m >> 3) & 2u));
+    const int z = (int)(brick / ((uint32_t)Rb * (uint32_t)Rb)) * 4 +
+                  (int)(((m >> 2) & 1u) | ((m >> 4) & 2u));
+    float4 v = make_float4(0.0f, 0.0f, 0.0f, 0.0f);
+    if (x < R && y < R && z < R) v = G(A.src)[((size_t)z * R + y) * R + x];
+    G(A.dst)[d] = v;
+  }
+}
 
 // ---------------------------------------------------------------------------
 // fused meta-estimator + stabilised step
@@ -1820,15 +1957,11 @@ hipError_t launch_adjoint(const RepArgs* U, int n, uint32_t blocks, int shape, s
   return hipGetLastError();
 }
 
-hipError_t launch_vol_forward(const FwdArgs* U, int n, uint32_t blocks, int shape,
+hipError_t launch_vol_forward(const FwdArgs* U, int n, uint32_t blocks, int waves,
                               unsigned long long* work, hipStream_t st) {
   if (n <= 0 || blocks == 0) return hipSuccess;
-  switch (shape) {
-    case 0: hipLaunchKernelGGL((k_vol_forward<16, 16>), dim3(blocks), dim3(256), 0, st, U, n, work); break;
-    case 1: hipLaunchKernelGGL((k_vol_forward<16, 8>), dim3(blocks), dim3(128), 0, st, U, n, work); break;
-    case 2: hipLaunchKernelGGL((k_vol_forward<8, 8>), dim3(blocks), dim3(64), 0, st, U, n, work); break;
-    default: return hipErrorInvalidValue;
-  }
+  if (waves < 1 || waves > kVolMaxSliceWaves) return hipErrorInvalidValue;
+  hipLaunchKernelGGL(k_vol_forward, dim3(blocks), dim3(64 * waves), 0, st, U, n, work);
   return hipGetLastError();
 }
 
@@ -1841,6 +1974,12 @@ hipError_t launch_vol_adjoint(const RepArgs* U, int n, uint32_t blocks, int shap
     case 2: hipLaunchKernelGGL((k_vol_adjoint<8, 8>), dim3(blocks), dim3(64), 0, st, U, n, work); break;
     default: return hipErrorInvalidValue;
   }
+  return hipGetLastError();
+}
+
+hipError_t launch_vol_brick(const BrickArgs* U, int n, uint32_t blocks, hipStream_t st) {
+  if (n <= 0 || blocks == 0) return hipSuccess;
+  hipLaunchKernelGGL(k_vol_brick, dim3(blocks), dim3(kBrickBlock), 0, st, U, n);
   return hipGetLastError();
 }
 

@@ -96,11 +96,15 @@ def _oracle(spec, p, pp, T, seed, it, fd_shared, mask=None):
                                       fd_shared=fd_shared))
 
 
+# (res, view_w, view_h): a grid of whole 4^3 bricks, and a ragged one (7 = 4 + 3
+# voxels per side) seen on an image whose tile count is not a multiple of 8
 @pytest.mark.parametrize("fd_mode", [0, 1])
-def test_volume_gradient_parity(ctx, fd_mode):
+@pytest.mark.parametrize("size", [(12, 24, 20), (7, 40, 22)])
+def test_volume_gradient_parity(ctx, fd_mode, size):
     import torch
-    _say("volume gradient", fd_mode)
-    spec, gt, init = _small()
+    _say("volume gradient", fd_mode, size)
+    res, w, h = size
+    spec, gt, init = _small(res=res, w=w, h=h)
     g = np.random.Generator(np.random.PCG64(8))
     p = np.clip(gt + g.normal(0, 0.05, gt.shape).astype(np.float32), 0.0, 1.0)
     pp = np.clip(p + g.normal(0, 0.02, p.shape).astype(np.float32), 0.0, 1.0)
