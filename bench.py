@@ -58,6 +58,7 @@ VALU_OPS_PER_VERTEX = {"k_forward": 6217.0, "k_adjoint": 7016.0}
 KERNEL_SOURCES = ("paper_2309_15676_amd/csrc/device.h", "paper_2309_15676_amd/csrc/kernels.h",
                   "paper_2309_15676_amd/csrc/kernels.hip")
 TRAFFIC_SUMMARY = "profiles/%s_terrain2048_hbm_traffic.md"
+VOLUME_SUMMARY = "profiles/volume256_kernel_trace_traffic.md"
 
 
 def kernel_source_hash() -> str:
@@ -69,19 +70,27 @@ def kernel_source_hash() -> str:
     return h.hexdigest()
 
 
-def measured_traffic(kernel: str):
-    """HBM bytes per launch of `kernel` from the committed rocprofv3 counter
-    summary, or None when the kernel sources changed since it was taken."""
-    path = os.path.join(ROOT, TRAFFIC_SUMMARY % kernel)
+def profile_record(path: str, prefix: str):
+    """The JSON record on the line starting with `prefix` of a committed
+    rocprofv3 counter summary, or None when the kernel sources changed since
+    the counters were taken (or there is no such summary)."""
+    path = os.path.join(ROOT, path)
     if not os.path.exists(path):
         return None
     with open(path) as fh:
         for line in fh:
-            if line.startswith("traffic-json: "):
-                rec = json.loads(line[len("traffic-json: "):])
+            if line.startswith(prefix):
+                rec = json.loads(line[len(prefix):])
                 if rec.get("source_sha256") == kernel_source_hash():
-                    return rec["bytes_per_launch"]
+                    return rec
     return None
+
+
+def measured_traffic(kernel: str):
+    """HBM bytes per launch of `kernel` from the committed rocprofv3 counter
+    summary, or None when the kernel sources changed since it was taken."""
+    rec = profile_record(TRAFFIC_SUMMARY % kernel, "traffic-json: ")
+    return rec["bytes_per_launch"] if rec else None
 
 
 def copy_calibration(mib: int):
@@ -413,7 +422,7 @@ def batched_throughput(context, args):
 META_BYTES_PER_PARAM = 108  # k_meta: reads 52 B, writes 56 B per parameter
 
 
-def volume_workload(context, args):
+def volume_workload(context, args, ub=None):
     """The volume experiment's workload: a 256^3 emission-absorption volume
     (67.1M parameters: emission RGB + density per voxel) seen by 8 cameras of
     256x256.  Meta-estimator step time (replay pair and shared path; the
@@ -474,6 +483,19 @@ def volume_workload(context, args):
         ms, kt = timed(L.step_opts(optimizer=L.JSO_OPT_ADAM, eta=0.01, adam_spp=spp,
                                    seed=args.seed), n)
         out["adam%d_step" % spp] = {"ms": ms, "kernel": kt}
+    # the replay is bound by the L2's atomic requests (one per 16-byte voxel row
+    # and distinct 64-byte segment of an instruction): requests per launch from
+    # the committed counter summary, against the rate of random 16-byte-row
+    # atomics measured above
+    ka = out["meta_step"]["kernel"]["adjoint"]["ms_per_launch"]
+    rec = profile_record(VOLUME_SUMMARY, "atomics-json: ")
+    req = rec["meta_adjoint_requests_per_launch"] if rec else None
+    peak = ub["atomic_ops_per_s_rows"] / 4 if ub else None
+    out["k_vol_adjoint_roofline"] = {
+        "bound": "atomic", "ms": ka, "requests_per_launch": req,
+        "achieved_requests_per_s": req / (ka / 1e3) if req else None,
+        "peak_requests_per_s": peak,
+        "frac": req / (ka / 1e3) / peak if req and peak else None}
     km = out["meta_step"]["kernel"]["meta"]["ms_per_launch"]
     bytes_meta = META_BYTES_PER_PARAM * spec.n_params
     out["k_meta_roofline"] = {"bound": "hbm", "bytes_per_launch": bytes_meta, "ms": km,
@@ -679,7 +701,7 @@ def counted_work(prob, opts, n: int):
 def microbenchmarks(context, n_params: int):
     """The roofline denominators measured on this GPU: a plain device copy of
     1 GiB (bytes read + written per second), and no-return FP32 atomic adds
-    into a buffer of the headline's parameter count under four address
+    into a buffer of the headline's parameter count under five address
     patterns (operations per second)."""
     import torch
 
@@ -694,7 +716,8 @@ def microbenchmarks(context, n_params: int):
     buf = torch.zeros(n_params, dtype=torch.float32, device="cuda")
     n_ops = 1 << 26
     for name, pat in (("random", L.JSO_UB_RANDOM), ("lines", L.JSO_UB_LINES),
-                      ("16_addresses", L.JSO_UB_16), ("same_address", L.JSO_UB_SAME)):
+                      ("rows", L.JSO_UB_ROWS), ("16_addresses", L.JSO_UB_16),
+                      ("same_address", L.JSO_UB_SAME)):
         ms = L.jso_ub_atomics(ctx, buf.data_ptr(), n_params, pat, n_ops, 3)
         out["atomic_ops_per_s_" + name] = n_ops / (ms / 1e3)
     out["atomic_buffer_floats"] = n_params
@@ -994,7 +1017,7 @@ def main():
             extras["meshes"] = mesh_workloads(context, args)
         if args.volume_steps > 0:
             print("[bench] volume workload", file=sys.stderr, flush=True)
-            extras["volume"] = volume_workload(context, args)
+            extras["volume"] = volume_workload(context, args, ub)
     if args.copy_mib > 0:
         copy_calibration(args.copy_mib)
     line = {

@@ -466,11 +466,14 @@ int jso_get_kernel_time(jso_ctx* ctx, int kernel, double* ms, uint64_t* launches
  *                  64-byte segment (the coalesced form of a texel scatter)
  *   JSO_UB_16      index i mod 16
  *   JSO_UB_SAME    index 0
+ *   JSO_UB_ROWS    4 consecutive operations to the 4 floats of one hashed
+ *                  16-byte row (the form of a volume replay's voxel write-out)
  * Errors: JSO_E_INVALID for bad arguments, JSO_E_HIP for a failed launch. */
 #define JSO_UB_RANDOM 0
 #define JSO_UB_LINES 1
 #define JSO_UB_16 2
 #define JSO_UB_SAME 3
+#define JSO_UB_ROWS 4
 int jso_ub_copy(jso_ctx* ctx, void* dst, const void* src, size_t bytes, int reps, double* ms);
 int jso_ub_atomics(jso_ctx* ctx, float* buf, size_t n_buf, int pattern, size_t n_ops, int reps,
                    double* ms);

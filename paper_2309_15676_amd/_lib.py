@@ -45,7 +45,7 @@ EXPORTED = [
     "jso_batch_autotune", "jso_set_launch_config", "jso_precondition", "jso_render_bwd_noalloc",
     "jso_ub_copy", "jso_ub_atomics",
 ]
-JSO_UB_RANDOM, JSO_UB_LINES, JSO_UB_16, JSO_UB_SAME = 0, 1, 2, 3
+JSO_UB_RANDOM, JSO_UB_LINES, JSO_UB_16, JSO_UB_SAME, JSO_UB_ROWS = 0, 1, 2, 3, 4
 JSO_NOALLOC_SCRATCH_BYTES = 128 << 20
 JSO_NOALLOC_MAX_PIXELS = JSO_NOALLOC_SCRATCH_BYTES // 24
 JSO_TILE_16x16, JSO_TILE_16x8, JSO_TILE_8x8, JSO_TILE_SHAPES = 0, 1, 2, 3

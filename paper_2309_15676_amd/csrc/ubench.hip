@@ -54,6 +54,9 @@ __global__ void __launch_bounds__(kBlock) k_ub_atomics(float* __restrict__ buf, 
       case JSO_UB_16:
         idx = (uint32_t)(i & 15u);
         break;
+      case JSO_UB_ROWS:  // 4 neighbouring lanes share one 16-byte row
+        idx = (mix32(i >> 2) % (n_buf / 4u)) * 4u + (uint32_t)(i & 3u);
+        break;
       default:  // JSO_UB_SAME
         idx = 0;
         break;
@@ -121,7 +124,7 @@ int jso_ub_copy(jso_ctx* c, void* dst, const void* src, size_t bytes, int reps, 
 int jso_ub_atomics(jso_ctx* c, float* buf, size_t n_buf, int pattern, size_t n_ops, int reps,
                    double* ms) {
   if (!buf || n_buf < 16 || n_buf > 0xFFFFFFFFull || n_ops == 0) return JSO_E_INVALID;
-  if (pattern < JSO_UB_RANDOM || pattern > JSO_UB_SAME) return JSO_E_INVALID;
+  if (pattern < JSO_UB_RANDOM || pattern > JSO_UB_ROWS) return JSO_E_INVALID;
   const size_t threads = (n_ops + kPer - 1) / kPer;
   const size_t nb = (threads + kBlock - 1) / kBlock;  // covers n_ops: nb * kBlock * kPer >= n_ops
   if (nb > 0x7FFFFFFFu) return JSO_E_INVALID;
