@@ -349,6 +349,7 @@ def batched_throughput(context, args):
     picked by the autotuner, and the same launches issued directly, (b) as one
     jso_grad_step over all problems (one launch per kernel, tuned configuration),
     (c) as one jso_grad_step per problem."""
+    import numpy as np
     import torch
 
     from paper_2309_15676_amd import _lib as L
@@ -381,11 +382,27 @@ def batched_throughput(context, args):
 
     b = Batch(probs, opts, max_iters=[c["max_iter"] for c in cfg], use_graph=True)
     best, config_ms = b.autotune(3)  # state is restored after each trial
-    ms_graph = timed(lambda n: b.step(n))
-    b.close()
-    # direct launches of the batch (no graph), tuned configuration
+    # the same launches issued directly (no graph), tuned configuration; the
+    # two batches step the same problems in turn, so both see the same
+    # optimisation states, each iteration timed on its own
     b1 = Batch(probs, opts, max_iters=[c["max_iter"] for c in cfg], use_graph=False)
-    ms_direct = timed(lambda n: b1.step(n))
+    b.step(2)
+    b1.step(2)
+    torch.cuda.synchronize()
+    t_graph, t_direct = [], []
+    for _ in range(steps):
+        for bb, out_t in ((b, t_graph), (b1, t_direct)):
+            e0, e1 = torch.cuda.Event(enable_timing=True), torch.cuda.Event(enable_timing=True)
+            e0.record()
+            bb.step(1)
+            e1.record()
+            torch.cuda.synchronize()
+            out_t.append(e0.elapsed_time(e1))
+    ms_graph = float(np.median(t_graph))
+    ms_direct = float(np.median(t_direct))
+    # several iterations per replay call: consecutive graph launches
+    ms_graph_run = timed(lambda n: b.step(n))
+    b.close()
     b1.close()
 
     def together(n):
@@ -410,8 +427,11 @@ def batched_throughput(context, args):
         "autotune": {"best": L.config_name(best),
                      "ms_per_iteration": {L.config_name(c): m for c, m in enumerate(config_ms)}},
         "graph": {"ms_per_iteration": ms_graph, "paths_per_s": paths / (ms_graph / 1e3),
-                  "config": L.config_name(best)},
-        "batch_direct_launches": {"ms_per_iteration": ms_direct, "config": L.config_name(best)},
+                  "config": L.config_name(best),
+                  "ms_per_iteration_in_runs": ms_graph_run},
+        "batch_direct_launches": {"ms_per_iteration": ms_direct, "config": L.config_name(best),
+                                  "note": "median over iterations alternating with the graph's, "
+                                          "on the same problems"},
         "one_launch_per_kernel": {"ms_per_iteration": ms_together,
                                   "paths_per_s": paths / (ms_together / 1e3)},
         "one_grad_step_per_problem": {"ms_per_iteration": ms_each,
@@ -702,7 +722,8 @@ def microbenchmarks(context, n_params: int):
     """The roofline denominators measured on this GPU: a plain device copy of
     1 GiB (bytes read + written per second), and no-return FP32 atomic adds
     into a buffer of the headline's parameter count under five address
-    patterns (operations per second)."""
+    patterns (operations per second), and the gap between dependent launches
+    issued on a stream and replayed from a captured graph."""
     import torch
 
     from paper_2309_15676_amd import _lib as L
@@ -723,6 +744,15 @@ def microbenchmarks(context, n_params: int):
     out["atomic_buffer_floats"] = n_params
     out["atomic_ops"] = n_ops
     del buf
+    # gap between dependent launches: 64 one-block kernels issued on the
+    # stream, and the same chain replayed from a captured graph
+    ctr = torch.zeros(1, dtype=torch.int32, device="cuda")
+    for name, graph in (("stream", False), ("graph", True)):
+        ms = L.jso_ub_launch(ctx, ctr.data_ptr(), 64, graph, 20)
+        out["launch_gap_us_" + name] = ms * 1e3 / 64
+    expect = 64 * 21 * 2
+    out["launch_chain_count_ok"] = int(ctr.item()) == expect
+    del ctr
     torch.cuda.empty_cache()
     return out
 

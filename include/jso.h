@@ -475,6 +475,14 @@ int jso_get_kernel_time(jso_ctx* ctx, int kernel, double* ms, uint64_t* launches
 #define JSO_UB_SAME 3
 #define JSO_UB_ROWS 4
 int jso_ub_copy(jso_ctx* ctx, void* dst, const void* src, size_t bytes, int reps, double* ms);
+/* jso_ub_launch: a chain of n_kernels (1..4096) dependent one-block launches,
+ * each adding 1 to counter[0] (dev, one uint32; it ends up raised by
+ * n_kernels x (reps + 1)), issued on the context's stream one by one
+ * (use_graph = 0) or replayed from a graph of the same launches captured
+ * once (use_graph != 0); *ms is per chain, so *ms / n_kernels is the gap
+ * between dependent launches. */
+int jso_ub_launch(jso_ctx* ctx, uint32_t* counter, int n_kernels, int use_graph, int reps,
+                  double* ms);
 int jso_ub_atomics(jso_ctx* ctx, float* buf, size_t n_buf, int pattern, size_t n_ops, int reps,
                    double* ms);
 

@@ -43,7 +43,7 @@ EXPORTED = [
     "jso_set_timing", "jso_get_kernel_time", "jso_set_work_counting", "jso_get_work",
     "jso_batch_create", "jso_batch_step", "jso_batch_active", "jso_batch_destroy",
     "jso_batch_autotune", "jso_set_launch_config", "jso_precondition", "jso_render_bwd_noalloc",
-    "jso_ub_copy", "jso_ub_atomics",
+    "jso_ub_copy", "jso_ub_atomics", "jso_ub_launch",
 ]
 JSO_UB_RANDOM, JSO_UB_LINES, JSO_UB_16, JSO_UB_SAME, JSO_UB_ROWS = 0, 1, 2, 3, 4
 JSO_NOALLOC_SCRATCH_BYTES = 128 << 20
@@ -161,6 +161,7 @@ def load() -> ctypes.CDLL:
         "jso_render_bwd_noalloc": (I, [P, I, P, U64, U32, U32, I, P, P, P]),
         "jso_ub_copy": (I, [P, P, P, SZ, I, ctypes.POINTER(D)]),
         "jso_ub_atomics": (I, [P, P, SZ, I, SZ, I, ctypes.POINTER(D)]),
+        "jso_ub_launch": (I, [P, P, I, I, I, ctypes.POINTER(D)]),
         "jso_estimate_gradients": (I, [P, I, U64, U32, I, I, P, P, P, P, P]),
         "jso_meta_step": (I, [P, I, P, P, F, F, F]),
         "jso_adam_step": (I, [P, I, P, F, F, F, F]),
@@ -359,6 +360,15 @@ def jso_ub_copy(ctx, dst_ptr, src_ptr, nbytes, reps) -> float:
     ms = ctypes.c_double(0.0)
     check(load().jso_ub_copy(ctx, dst_ptr, src_ptr, nbytes, reps, ctypes.byref(ms)), ctx,
           "jso_ub_copy")
+    return ms.value
+
+
+def jso_ub_launch(ctx, counter_ptr, n_kernels, use_graph, reps) -> float:
+    """Mean ms per chain of n_kernels dependent one-block launches, issued one
+    by one or replayed from a captured graph."""
+    ms = ctypes.c_double(0.0)
+    check(load().jso_ub_launch(ctx, counter_ptr, n_kernels, 1 if use_graph else 0, reps,
+                               ctypes.byref(ms)), ctx, "jso_ub_launch")
     return ms.value
 
 

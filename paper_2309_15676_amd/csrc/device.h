@@ -314,43 +314,64 @@ __device__ __forceinline__ void bvh_closest(const DevScene& S, const TravStack& 
 }
 
 // Whether any triangle lies at a distance in (0, tmax).  Children in slot
-// order, the first hit one visited next.
+// order, the first hit one visited next.  Each lane may hold one postponed
+// leaf (speculative traversal, Aila and Laine, "Understanding the efficiency
+// of ray traversal on GPUs", HPG 2009): a lane that reaches a leaf sets it
+// aside and goes on down inner nodes, and the wave tests triangles once every
+// lane holds a leaf or is finished, so node visits and triangle tests each run
+// on more lanes at once.  Postponing changes only when a hit is found, not
+// whether.  (The closest-hit traversal measured slower this way: a postponed
+// leaf's hit would have culled the nodes visited meanwhile.)
 __device__ __forceinline__ bool bvh_any(const DevScene& S, const TravStack& st, V3 o, V3 d,
                                         float tmax) {
   const RayQ r = make_rayq(o, d);
   StackSpill sv;
   int sp = 0;
   int32_t link = 0;
+  bool go = true, hit = false;
+  int32_t leaf = 0;
+  bool has = false;
   for (;;) {
-    if (link >= 0) {
-      const Node4 n = load_node4(S, r, link, tmax);
-      int32_t next = 0;
-      bool any = false;
+    while (!__all(has || !go)) {
+      if (!go || (has && link < 0)) continue;
+      if (link >= 0) {
+        const Node4 n = load_node4(S, r, link, tmax);
+        int32_t next = 0;
+        bool any = false;
 #pragma unroll
-      for (int k = 0; k < 4; ++k) {
-        if (n.t[k] == kInf) continue;
-        if (any) push(st, sv, sp, n.l[k]);
-        else next = n.l[k];
-        any = true;
+        for (int k = 0; k < 4; ++k) {
+          if (n.t[k] == kInf) continue;
+          if (any) push(st, sv, sp, n.l[k]);
+          else next = n.l[k];
+          any = true;
+        }
+        if (any) link = next;
+        else if (sp == 0) go = false;
+        else link = pop(st, sv, sp);
+      } else {
+        leaf = link;
+        has = true;
+        if (sp == 0) go = false;
+        else link = pop(st, sv, sp);
       }
-      if (any) {
-        link = next;
-        continue;
-      }
-    } else {
-      const uint32_t v = ~(uint32_t)link;
+    }
+    if (has) {
+      const uint32_t v = ~(uint32_t)leaf;
       const int first = (int)(v >> kLeafBits), end = first + (int)(v & (uint32_t)kLeafMax);
       for (int i = first; i < end; ++i) {
         JSO_GMEM const float4* tp = S.bvh_tris + 3 * (size_t)i;
         const float4 a = ldg4(tp), b = ldg4(tp + 1), c = ldg4(tp + 2);
-        if (tri_hit(r, mk(a.x, a.y, a.z), mk(b.x, b.y, b.z), mk(c.x, c.y, c.z), tmax) < tmax)
-          return true;
+        if (tri_hit(r, mk(a.x, a.y, a.z), mk(b.x, b.y, b.z), mk(c.x, c.y, c.z), tmax) < tmax) {
+          hit = true;
+          break;
+        }
       }
+      has = false;
+      if (hit) go = false;
     }
-    if (sp == 0) break;
-    link = pop(st, sv, sp);
+    if (!__any(go)) break;
   }
-  return false;
+  return hit;
 }
 
 // Closest hit; candidates in the order plane < spheres < mesh < light, each

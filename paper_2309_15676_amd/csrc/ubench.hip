@@ -65,6 +65,13 @@ __global__ void __launch_bounds__(kBlock) k_ub_atomics(float* __restrict__ buf, 
   }
 }
 
+// One single-thread block per launch, each adding 1 to the counter the last
+// one wrote: a chain of dependent launches whose length in time is the
+// launch-to-launch gap.
+__global__ void k_ub_tick(uint32_t* counter) {
+  if (threadIdx.x == 0) counter[0] += 1u;
+}
+
 }  // namespace
 
 namespace jso {
@@ -133,6 +140,47 @@ int jso_ub_atomics(jso_ctx* c, float* buf, size_t n_buf, int pattern, size_t n_o
     hipLaunchKernelGGL(k_ub_atomics, dim3(blocks), dim3(kBlock), 0, st, buf, (uint32_t)n_buf,
                        pattern, (uint64_t)n_ops);
   });
+}
+
+int jso_ub_launch(jso_ctx* c, uint32_t* counter, int n_kernels, int use_graph, int reps,
+                  double* ms) {
+  if (!c || !counter || n_kernels < 1 || n_kernels > 4096) return JSO_E_INVALID;
+  int prev = -1;
+  (void)hipGetDevice(&prev);
+  (void)hipSetDevice(jso::ctx_device(c));
+  const hipStream_t st = jso::ctx_stream(c);
+  auto chain = [&](hipStream_t s) {
+    for (int k = 0; k < n_kernels; ++k)
+      hipLaunchKernelGGL(k_ub_tick, dim3(1), dim3(64), 0, s, counter);
+  };
+  int rc = JSO_OK;
+  hipGraph_t g = nullptr;
+  hipGraphExec_t ge = nullptr;
+  if (use_graph) {
+    hipStream_t cs = nullptr;
+    if (hipStreamCreateWithFlags(&cs, hipStreamNonBlocking) != hipSuccess) {
+      rc = JSO_E_HIP;
+    } else {
+      if (hipStreamBeginCapture(cs, hipStreamCaptureModeThreadLocal) != hipSuccess) {
+        rc = JSO_E_HIP;
+      } else {
+        chain(cs);
+        if (hipStreamEndCapture(cs, &g) != hipSuccess ||
+            hipGraphInstantiate(&ge, g, nullptr, nullptr, 0) != hipSuccess)
+          rc = JSO_E_HIP;
+      }
+      (void)hipStreamDestroy(cs);
+    }
+  }
+  if (prev >= 0) (void)hipSetDevice(prev);
+  if (rc == JSO_OK)
+    rc = timed(c, reps, ms, [&](hipStream_t s) {
+      if (use_graph) (void)hipGraphLaunch(ge, s);
+      else chain(s);
+    });
+  if (ge) (void)hipGraphExecDestroy(ge);
+  if (g) (void)hipGraphDestroy(g);
+  return rc;
 }
 
 }  // extern "C"
