@@ -313,6 +313,128 @@ __device__ __forceinline__ void bvh_closest(const DevScene& S, const TravStack& 
   }
 }
 
+// Closest hit for the rays of one wave's neighbouring pixels (camera rays),
+// traversed by the wave together: one node sequence for the wave, each lane
+// testing the node's children against its own ray and nearest hit so far.  A
+// child is visited when any lane meets it, by the lanes that meet it (their
+// mask travels with it on the wave's stack), nearest first by the distances of
+// the first such lane.  Node and triangle words are wave-uniform, read through
+// the scalar cache.  The stack (link and 64-bit lane mask per entry, 3 words)
+// lives in the wave's per-lane LDS stack words, which hold it: it defers the
+// same children per node as bvh_closest, and 3 x the tree's stack bound fits
+// in 64 lanes x min(bound, kLdsStack) words.  The hit is bvh_closest's: every
+// lane tests every leaf whose box it meets within its nearest hit so far.
+__device__ __forceinline__ bool dist_less(float a, float b) {
+  // both >= 0 or +inf: the IEEE bit patterns order as unsigned integers
+  return __float_as_uint(a) < __float_as_uint(b);
+}
+
+// A 16-byte word of read-only data at a wave-uniform address, through the
+// scalar cache.
+__device__ __forceinline__ float4 ldc4(const JSO_CMEM float* p) {
+  return make_float4(p[0], p[1], p[2], p[3]);
+}
+
+__device__ __forceinline__ void bvh_closest_wave(const DevScene& S, const TravStack& st, V3 o,
+                                                 V3 d, float& best_t, int& best_tri) {
+  const RayQ r = make_rayq(o, d);
+  const int lane = (int)__lane_id();
+  uint32_t* wbase = st.base - lane;  // stack word 0 of the wave's first lane
+  auto word = [&](int q) -> uint32_t* { return wbase + (q & 63) + (q >> 6) * st.stride; };
+  const JSO_CMEM float* nodes = (const JSO_CMEM float*)S.bvh_nodes;
+  const JSO_CMEM float* tris = (const JSO_CMEM float*)S.bvh_tris;
+  uint64_t m = __ballot(1);  // lanes of the current node
+  int32_t link = 0;
+  int sp = 0;
+  for (;;) {
+    const bool me = (m >> lane) & 1ull;
+    bool pop_next = true;
+    if (link >= 0) {
+      const JSO_CMEM float* nd = nodes + 32 * (size_t)link;
+      const float4 lx = ldc4(nd), hx = ldc4(nd + 4), ly = ldc4(nd + 8), hy = ldc4(nd + 12);
+      const float4 lz = ldc4(nd + 16), hz = ldc4(nd + 20), ln = ldc4(nd + 24);
+      float t[4] = {kInf, kInf, kInf, kInf};
+      if (me) {
+        t[0] = box_entry(r, lx.x, ly.x, lz.x, hx.x, hy.x, hz.x, best_t);
+        t[1] = box_entry(r, lx.y, ly.y, lz.y, hx.y, hy.y, hz.y, best_t);
+        t[2] = box_entry(r, lx.z, ly.z, lz.z, hx.z, hy.z, hz.z, best_t);
+        t[3] = box_entry(r, lx.w, ly.w, lz.w, hx.w, hy.w, hz.w, best_t);
+      }
+      uint64_t hk[4];
+#pragma unroll
+      for (int k = 0; k < 4; ++k) hk[k] = __ballot(t[k] != kInf);
+      const uint64_t any = hk[0] | hk[1] | hk[2] | hk[3];
+      if (any != 0) {
+        const int lead = __ffsll((unsigned long long)any) - 1;
+        float lt[4];
+        int32_t ll[4] = {__float_as_int(ln.x), __float_as_int(ln.y), __float_as_int(ln.z),
+                         __float_as_int(ln.w)};
+#pragma unroll
+        for (int k = 0; k < 4; ++k)
+          lt[k] = __int_as_float(__builtin_amdgcn_readlane(__float_as_int(t[k]), lead));
+        // sort the 4 children by the first lane's entry distance
+        auto cswap = [&](int a, int b) {
+          if (dist_less(lt[b], lt[a])) {
+            const float tf = lt[a];
+            lt[a] = lt[b];
+            lt[b] = tf;
+            const int32_t tl = ll[a];
+            ll[a] = ll[b];
+            ll[b] = tl;
+            const uint64_t tm = hk[a];
+            hk[a] = hk[b];
+            hk[b] = tm;
+          }
+        };
+        cswap(0, 1);
+        cswap(2, 3);
+        cswap(0, 2);
+        cswap(1, 3);
+        cswap(1, 2);
+        int f = 3;
+#pragma unroll
+        for (int k = 3; k >= 0; --k)
+          if (hk[k] != 0) f = k;
+#pragma unroll
+        for (int k = 3; k >= 1; --k) {
+          if (k <= f || hk[k] == 0) continue;
+          *word(3 * sp) = (uint32_t)ll[k];
+          *word(3 * sp + 1) = (uint32_t)hk[k];
+          *word(3 * sp + 2) = (uint32_t)(hk[k] >> 32);
+          ++sp;
+        }
+        link = ll[f];
+        m = hk[f];
+        pop_next = false;
+      }
+    } else {
+      const uint32_t v = ~(uint32_t)link;
+      const int first = (int)(v >> kLeafBits), end = first + (int)(v & (uint32_t)kLeafMax);
+      for (int i = first; i < end; ++i) {
+        const JSO_CMEM float* tp = tris + 12 * (size_t)i;
+        const float4 a = ldc4(tp), b = ldc4(tp + 4), c = ldc4(tp + 8);
+        if (me) {
+          const float t = tri_hit(r, mk(a.x, a.y, a.z), mk(b.x, b.y, b.z), mk(c.x, c.y, c.z),
+                                  best_t);
+          if (t < best_t ||
+              (t == best_t && best_tri >= 0 && S.bvh_tri_id[i] < S.bvh_tri_id[best_tri])) {
+            best_t = t;
+            best_tri = i;
+          }
+        }
+      }
+    }
+    if (pop_next) {
+      if (sp == 0) break;
+      --sp;
+      link = (int32_t)__builtin_amdgcn_readfirstlane(*word(3 * sp));
+      const uint32_t lo = __builtin_amdgcn_readfirstlane(*word(3 * sp + 1));
+      const uint32_t hi = __builtin_amdgcn_readfirstlane(*word(3 * sp + 2));
+      m = (uint64_t)lo | ((uint64_t)hi << 32);
+    }
+  }
+}
+
 // Whether any triangle lies at a distance in (0, tmax).  Children in slot
 // order, the first hit one visited next.  Each lane may hold one postponed
 // leaf (speculative traversal, Aila and Laine, "Understanding the efficiency
@@ -377,7 +499,9 @@ __device__ __forceinline__ bool bvh_any(const DevScene& S, const TravStack& st, 
 // Closest hit; candidates in the order plane < spheres < mesh < light, each
 // replacing the current one only at a strictly smaller distance, so equal
 // distances keep the earlier kind.
-template <bool kMesh>
+// kCoherent: the rays of the calling lanes come from neighbouring pixels of
+// one wave (bvh_closest_wave); the hit is the same either way.
+template <bool kMesh, bool kCoherent = false>
 __device__ __forceinline__ Hit intersect(const DevScene& S, const TravStack& st, V3 o, V3 d) {
   Hit h{kInf, HIT_NONE, -1};
   if (S.plane_enabled && d.y < 0.0f && o.y > 0.0f) {
@@ -396,7 +520,8 @@ __device__ __forceinline__ Hit intersect(const DevScene& S, const TravStack& st,
   if (kMesh && S.n_tris > 0) {
     int tri = -1;
     float t = h.t;
-    bvh_closest(S, st, o, d, t, tri);
+    if (kCoherent) bvh_closest_wave(S, st, o, d, t, tri);
+    else bvh_closest(S, st, o, d, t, tri);
     if (tri >= 0) {
       h.t = t;
       h.kind = HIT_MESH;
@@ -723,7 +848,7 @@ __device__ __forceinline__ void path_begin(const DevScene& S, const TravStack& s
   P.d = normalize(ld3(S.cw) + ld3(S.cu) * sx + ld3(S.cv) * sy);
   P.beta[0] = P.beta[1] = P.beta[2] = 1.0f;
   P.led[0] = P.led[1] = P.led[2] = 0.0;
-  const Hit h = intersect<kMesh>(S, st, eye, P.d);
+  const Hit h = intersect<kMesh, true>(S, st, eye, P.d);
   P.o = eye + P.d * h.t;
   P.set_hit(h.kind, h.obj, 1);
   P.alive = false;
