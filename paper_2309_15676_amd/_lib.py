@@ -28,6 +28,7 @@ JSO_OPT_META, JSO_OPT_ADAM = 0, 1
 JSO_TAG_VAR_PRIMAL_PROP, JSO_TAG_VAR_ADJ_PROP, JSO_TAG_VAR_PRIMAL_FD, JSO_TAG_VAR_ADJ_FD = 9, 10, 11, 12
 JSO_LOSS_L2, JSO_LOSS_RELATIVE = 0, 1
 JSO_F_DETERMINISTIC = 16
+JSO_F_NO_HIT_RECORDS = 32
 JSO_ABLATE_CENTRED, JSO_ABLATE_NO_CLIP, JSO_ABLATE_UNCORRELATED = 1, 2, 4
 JSO_FD_REPLAY, JSO_FD_SHARED = 0, 1
 JSO_MAX_SPHERES, JSO_MAX_FIXED_MATS, JSO_MAX_TRIS = 32, 8, 4194304

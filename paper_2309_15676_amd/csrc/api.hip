@@ -59,6 +59,9 @@ struct SceneGPU {
   // kernels read (BrickArgs), made at the start of each plan; brick_n floats each
   float* vbrick = nullptr;
   size_t brick_n = 0;
+  // surfaces: hit records of replayed paths (kHitRecs x kRecWords words per
+  // slot and pixel), written by the forward pass of a plan, read by its replay
+  uint32_t* recs = nullptr;
   uint32_t host_iter = 0;          // mirror of ctl->iteration
   uint64_t generation = 0;         // unique per loaded scene (plan cache key)
 };
@@ -67,6 +70,8 @@ struct SceneGPU {
 
 // Source of SceneGPU::generation.
 std::atomic<uint64_t> g_scene_generation{0};
+// Hit-record epoch: one value per estimator plan, mixed into its records' tags.
+std::atomic<uint32_t> g_rec_epoch{0};
 
 // Tile shapes picked by the autotuner, by (GPU architecture, configuration
 // hash); shared by every context of the process.
@@ -325,7 +330,7 @@ void free_scene_buffers(SceneGPU* s) {
                   s->m2D,    s->adam_m,      s->adam_v, s->ctl,    s->scratch_loss,
                   s->partials, s->slots,     s->accum,  s->d_scene, s->bvh_nodes,
                   s->bvh_tris, s->bvh_tri_id, s->pc, s->pc_tmp, s->m1F,
-                  s->m1D,    s->Fv,          s->dFv,    s->fx,     s->vbrick};
+                  s->m1D,    s->Fv,          s->dFv,    s->fx,     s->vbrick, s->recs};
   for (void* b : bufs)
     if (b) (void)hipFree(b);
 }
@@ -682,6 +687,8 @@ struct ProbPlan {
 };
 
 double* slots_of(const ProbPlan& p) { return p.slots ? p.slots : p.s->slots; }
+// The hit records go with the scene's own slots (none with a caller's slots).
+uint32_t* recs_of(const ProbPlan& p) { return p.slots ? nullptr : p.s->recs; }
 
 // Fixed-point scale of the deterministic mode: 2^32 for adjoint images of the
 // caller's (jso_render_bwd), 2^(32 + ceil(log2(1.5 W H))) for the estimators,
@@ -754,6 +761,12 @@ void plan_estimators(const std::vector<ProbPlan>& ps, Plan& plan, int config = 0
   const bool shared_pairs = std::any_of(p0.aj, p0.aj + p0.na, [](const AdjointSpec& a) {
     return a.params_b != nullptr && a.shared;
   });
+  // hit records: for replays of single paths and replay pairs (the kernel
+  // instances of shared-path pairs and of the deterministic mode have none)
+  const bool use_recs = !shared_pairs &&
+                        !(p0.flags & (JSO_F_DETERMINISTIC | JSO_F_NO_HIT_RECORDS)) &&
+                        p0.s->dev.layout != JSO_LAYOUT_VOLUME;
+  const uint32_t rec_epoch = ++g_rec_epoch;
   std::vector<std::pair<int, int>> units;
   for (int pass = 0; pass < 2; ++pass)
     for (int j = 0; j < p0.na; ++j)
@@ -878,9 +891,13 @@ void plan_estimators(const std::vector<ProbPlan>& ps, Plan& plan, int config = 0
       FwdArgs f{};
       f.h.max_iter = p.max_iter;
       f.scene = cmem((const DevScene*)p.s->d_scene);
+      uint32_t* recs = use_recs ? recs_of(p) : nullptr;
+      f.recs = gmem(recs);
+      f.rec_epoch = rec_epoch;
       for (size_t i = 0; i < fsl.size(); ++i) {
         const FSl& x = fsl[i];
         FwdSlice& fs = f.sl[i];
+        if (recs && x.kind != 0) f.rec_mask |= 1u << i;  // paths this plan replays
         fs.sample = (uint32_t)x.sample;
         fs.slot = x.slot;
         fs.slot_b = x.slot_b;
@@ -1024,6 +1041,8 @@ void plan_estimators(const std::vector<ProbPlan>& ps, Plan& plan, int config = 0
           r.npix = (uint32_t)p.s->npix;
           r.flags = p.flags;
           r.pair_lanes = pass == 0 && !shared_pairs && !vol;
+          r.recs = gmem(use_recs ? recs_of(p) : nullptr);
+          r.rec_epoch = rec_epoch;
           r.tiles_x = tiles_x(p.crop, shape);
           r.tiles = r.pair_lanes ? pair_tiles_of(p.crop, shape) : tiles_of(p.crop, shape);
           ad.stack = std::max(ad.stack, p.s->stack);
@@ -1605,7 +1624,7 @@ int jso_synchronize(jso_ctx* c) {
 
 int jso_set_debug(jso_ctx* c, uint32_t flags) {
   if (!c) return JSO_E_INVALID;
-  if (flags & ~31u) return fail(c, JSO_E_INVALID, "unknown debug flags 0x%x", flags);
+  if (flags & ~63u) return fail(c, JSO_E_INVALID, "unknown debug flags 0x%x", flags);
   c->debug_flags = flags;
   return JSO_OK;
 }
@@ -1660,6 +1679,7 @@ int jso_load_scene(jso_ctx* c, const jso_scene_desc* d, int* scene_id) {
   A(dalloc(&s->accum, 3 * n3));
   A(dalloc(&s->d_scene, 1));
   if (s->brick_n) A(dalloc(&s->vbrick, 2 * s->brick_n));
+  else A(dalloc(&s->recs, (size_t)kMaxSlots * kHitRecs * kRecWords * s->npix));
   if (e != hipSuccess) {
     free_scene_buffers(s.get());
     return fail(c, e == hipErrorOutOfMemory ? JSO_E_OOM : JSO_E_HIP, "scene allocation: %s",

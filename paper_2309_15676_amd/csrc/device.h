@@ -551,6 +551,111 @@ __device__ __forceinline__ bool occluded(const DevScene& S, const TravStack& st,
 }
 
 // ---------------------------------------------------------------------------
+// hit records
+//
+// The forward pass of a path that a replay will read back writes, for its
+// first kHitRecs rays (the camera ray, then the continuation rays), what the
+// ray hit and whether the shadow ray of the vertex it reached is blocked, so
+// the replay need not trace those rays again.  Record k, kRecWords words:
+//   w0: hit kind | blocked << 3 | object << 10 (the object bits of the path's
+//       hit word),
+//   w1: the hit distance's bits,
+//   w2: the ray's tag: a hash of its origin and direction bits, its index k,
+//       the path's random stream (key, pixel, sample) and the plan's epoch.
+// The replay takes a record only when its tag equals the tag of the replay's
+// own ray and its object index is in range, and only while it took every
+// earlier record of the path; otherwise it traces.  A record left by another
+// launch or another plan, or one of a path the replay does not reproduce bit
+// for bit, is never used, so the replay finds exactly the hits the forward
+// pass found for the same rays.
+// kRec: REC_NONE (no records: the plain tracing code), REC_WRITE (forward
+// pass), REC_READ (replay); with a null base the calls trace.
+// ---------------------------------------------------------------------------
+enum : int { REC_NONE = 0, REC_WRITE = 1, REC_READ = 2 };
+
+struct HitRecs {
+  JSO_GMEM uint32_t* base;  // record 0 of the path, or null
+  uint32_t stride;          // words from record k to record k + 1
+  uint32_t epoch;
+};
+
+// One step of the tag hash: a bijection of h for each word w (xor, a
+// multiplication by an odd constant, an xor-shift), so two inputs that differ
+// in a single word always hash apart.
+__device__ __forceinline__ uint32_t tag_step(uint32_t h, uint32_t w) {
+  h = (h ^ w) * 0x9E3779B1u;
+  return h ^ (h >> 16);
+}
+
+__device__ __forceinline__ uint32_t ray_tag(const Rng& rng, uint32_t epoch, int k, V3 o, V3 d) {
+  uint32_t h = tag_step(epoch, rng.k0);
+  h = tag_step(h, rng.k1);
+  h = tag_step(h, rng.pixel);
+  h = tag_step(h, rng.sample ^ ((uint32_t)k << 24));
+  h = tag_step(h, __float_as_uint(o.x));
+  h = tag_step(h, __float_as_uint(o.y));
+  h = tag_step(h, __float_as_uint(o.z));
+  h = tag_step(h, __float_as_uint(d.x));
+  h = tag_step(h, __float_as_uint(d.y));
+  return tag_step(h, __float_as_uint(d.z));
+}
+
+// The closest hit of ray k of the path (k = 0: the camera ray).
+template <bool kMesh, bool kCoherent, int kRec>
+__device__ __forceinline__ Hit traced_hit(const DevScene& S, const TravStack& st, V3 o, V3 d,
+                                          const HitRecs& hr, const Rng& rng, int k,
+                                          bool& rec_ok) {
+  if constexpr (kRec != REC_NONE) {
+    if (hr.base != nullptr && k < kHitRecs) {
+      JSO_GMEM uint32_t* r = hr.base + (size_t)k * hr.stride;
+      const uint32_t tag = ray_tag(rng, hr.epoch, k, o, d);
+      if constexpr (kRec == REC_READ) {
+        if (rec_ok) {
+          const uint32_t w0 = r[0], w1 = r[1], w2 = r[2];
+          const int kind = (int)(w0 & 7u);
+          const int obj = (int)(w0 >> 10);
+          const bool in_range = kind <= HIT_MESH &&
+                                (kind != HIT_SPHERE || obj < S.n_spheres) &&
+                                (kind != HIT_MESH || (kMesh && obj < S.n_tris));
+          if (w2 == tag && in_range) return Hit{__uint_as_float(w1), kind, obj};
+          rec_ok = false;
+        }
+      } else {
+        const Hit h = intersect<kMesh, kCoherent>(S, st, o, d);
+        r[0] = (uint32_t)h.kind | ((uint32_t)h.obj << 10);
+        r[1] = __float_as_uint(h.t);
+        r[2] = tag;
+        return h;
+      }
+    }
+  }
+  return intersect<kMesh, kCoherent>(S, st, o, d);
+}
+
+// Whether the shadow ray of the vertex that ray k reached is blocked; hit is
+// that vertex's hit word.  The replay reads the bit only while rec_ok, that
+// is when it took record k, so the vertex and the shadow ray are the forward
+// pass's.
+template <bool kMesh, int kRec>
+__device__ __forceinline__ bool traced_occluded(const DevScene& S, const TravStack& st, V3 o,
+                                                V3 d, float tmax, const HitRecs& hr, int k,
+                                                uint32_t hit, const bool& rec_ok) {
+  if constexpr (kRec != REC_NONE) {
+    if (hr.base != nullptr && k < kHitRecs) {
+      JSO_GMEM uint32_t* r = hr.base + (size_t)k * hr.stride;
+      if constexpr (kRec == REC_READ) {
+        if (rec_ok) return (r[0] & 8u) != 0u;
+      } else {
+        const bool occ = occluded<kMesh>(S, st, o, d, tmax);
+        if (occ) r[0] = (hit & ~(127u << 3)) | 8u;  // w0 as written, with the bit
+        return occ;
+      }
+    }
+  }
+  return occluded<kMesh>(S, st, o, d, tmax);
+}
+
+// ---------------------------------------------------------------------------
 // materials
 // ---------------------------------------------------------------------------
 struct Mat {
@@ -805,6 +910,7 @@ struct Path {
   float beta[3];
   uint32_t hit;   // pending hit: kind | vertex index j << 3 | object << 10
   bool alive;
+  bool rec_ok;    // replay with hit records: every record of the path so far was taken
   __device__ __forceinline__ int kind() const { return (int)(hit & 7u); }
   __device__ __forceinline__ int j() const { return (int)((hit >> 3) & 127u); }
   __device__ __forceinline__ int obj() const { return (int)(hit >> 10); }
@@ -832,9 +938,10 @@ struct Ledger2 {
   float beta[3];
 };
 
-template <bool kMesh>
+template <bool kMesh, int kRec = REC_NONE>
 __device__ __forceinline__ void path_begin(const DevScene& S, const TravStack& st, const Rng& rng,
-                                           int px, int py, uint32_t flags, Path& P) {
+                                           int px, int py, uint32_t flags, Path& P,
+                                           const HitRecs& hr = HitRecs{nullptr, 0, 0}) {
   float jx = 0.5f, jy = 0.5f;
   if (!(flags & JSO_F_PIXEL_CENTER)) {
     float u[4];
@@ -848,7 +955,8 @@ __device__ __forceinline__ void path_begin(const DevScene& S, const TravStack& s
   P.d = normalize(ld3(S.cw) + ld3(S.cu) * sx + ld3(S.cv) * sy);
   P.beta[0] = P.beta[1] = P.beta[2] = 1.0f;
   P.led[0] = P.led[1] = P.led[2] = 0.0;
-  const Hit h = intersect<kMesh, true>(S, st, eye, P.d);
+  if constexpr (kRec == REC_READ) P.rec_ok = true;
+  const Hit h = traced_hit<kMesh, true, kRec>(S, st, eye, P.d, hr, rng, 0, P.rec_ok);
   P.o = eye + P.d * h.t;
   P.set_hit(h.kind, h.obj, 1);
   P.alive = false;
@@ -876,13 +984,16 @@ __device__ __forceinline__ void path_begin(const DevScene& S, const TravStack& s
 // with the material of params_b at the same point and directions; with kGrad
 // vg.g is then (gradient of ledger 1) - (gradient of ledger 2, adjoint adj_b)
 // over the one footprint both share.
-template <bool kGrad, bool kMesh, bool kTwo>
+// kRec, hr: the path's hit records (written by the forward pass, read by the
+// replay) for the shadow ray of this vertex and the continuation ray.
+template <bool kGrad, bool kMesh, bool kTwo, int kRec = REC_NONE>
 __device__ __forceinline__ void path_vertex2(const DevScene& S, const TravStack& st,
                                              const float* __restrict__ params,
                                              const float* __restrict__ params_b, const Rng& rng,
                                              uint32_t flags, Path& P, Ledger2& L2,
                                              const float adj[3], const float adj_b[3],
-                                             VertexGrad& vg) {
+                                             VertexGrad& vg,
+                                             const HitRecs& hr = HitRecs{nullptr, 0, 0}) {
   Surf x;
   x.p = P.o;
   x.kind = P.kind();
@@ -949,7 +1060,9 @@ __device__ __forceinline__ void path_vertex2(const DevScene& S, const TravStack&
     const float dist2 = dot(dl, dl), dist = sqrtf(dist2);
     const V3 wl = dl * (1.0f / dist);
     const float cos_l = wl.y, cos_s = dot(n, wl);
-    if (cos_l > 0.0f && cos_s > 0.0f && !occluded<kMesh>(S, st, po, wl, dist - kShadowEps)) {
+    if (cos_l > 0.0f && cos_s > 0.0f &&
+        !traced_occluded<kMesh, kRec>(S, st, po, wl, dist - kShadowEps, hr, j - 1, P.hit,
+                                      P.rec_ok)) {
       Bsdf nb;
       eval_bsdf<kGrad>(M, n, wo, wl, flags, nb);
       const float pl = dist2 / (cos_l * S.larea);
@@ -1038,7 +1151,7 @@ __device__ __forceinline__ void path_vertex2(const DevScene& S, const TravStack&
     if constexpr (kTwo) L2.beta[k] *= cbb.f[k] * cw;
   }
   P.d = wi;
-  const Hit h = intersect<kMesh>(S, st, po, wi);
+  const Hit h = traced_hit<kMesh, false, kRec>(S, st, po, wi, hr, rng, j, P.rec_ok);
   P.o = po + wi * h.t;
   if (h.kind == HIT_NONE) {
 #pragma unroll
@@ -1070,14 +1183,15 @@ __device__ __forceinline__ void path_vertex2(const DevScene& S, const TravStack&
   }
 }
 
-template <bool kGrad, bool kMesh>
+template <bool kGrad, bool kMesh, int kRec = REC_NONE>
 __device__ __forceinline__ void path_vertex(const DevScene& S, const TravStack& st,
                                             const float* __restrict__ params, const Rng& rng,
                                             uint32_t flags, Path& P, const float adj[3],
-                                            VertexGrad& vg) {
+                                            VertexGrad& vg,
+                                            const HitRecs& hr = HitRecs{nullptr, 0, 0}) {
   Ledger2 unused;
-  path_vertex2<kGrad, kMesh, false>(S, st, params, nullptr, rng, flags, P, unused, adj, nullptr,
-                                    vg);
+  path_vertex2<kGrad, kMesh, false, kRec>(S, st, params, nullptr, rng, flags, P, unused, adj,
+                                          nullptr, vg, hr);
 }
 
 }  // namespace jso

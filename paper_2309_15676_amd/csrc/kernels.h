@@ -67,6 +67,12 @@ struct UnitHead {
 // per-path slots: slot k of pixel p holds 3 doubles at ((k * npix) + p) * 3.
 constexpr int kMaxSlots = 8;  // path slots per pixel per launch
 
+// Hit records of replayed paths (device.h describes them): kHitRecs records of
+// kRecWords words per path, record k of slot s and pixel p at
+// ((s * kHitRecs + k) * npix + p) * kRecWords.
+constexpr int kHitRecs = 3;
+constexpr int kRecWords = 3;
+
 // One grid slice of k_forward: the paths of one sample of one parameter set.
 struct FwdSlice {
   JSO_GMEM const float* params;
@@ -91,6 +97,12 @@ struct FwdArgs {
   uint32_t npix;
   uint32_t flags;
   uint32_t tiles_x, tiles;  // tiles of the crop (launch's tile shape): per row, per slice
+  // hit records: slices with bit i of rec_mask set write them for their paths
+  // (the forward pass of paths that a replay in the same plan reads back);
+  // rec_epoch is the plan's, mixed into every record's tag
+  JSO_GMEM uint32_t* recs;
+  uint32_t rec_mask;
+  uint32_t rec_epoch;
 };
 
 // One primal image of k_finalize: n slots of this launch summed per pixel,
@@ -162,6 +174,10 @@ struct RepArgs {
   // lane pairs over tiles of half the tile shape's height (tiles_x, tiles
   // count those)
   int pair_lanes;
+  // the forward pass's hit records of these slices' paths (FwdArgs), or null:
+  // trace every ray again
+  JSO_GMEM uint32_t* recs;
+  uint32_t rec_epoch;
 };
 
 // One fixed-point gradient accumulator of the deterministic mode: grad[i] +=

@@ -138,6 +138,13 @@ constexpr int compact_max() {
   return SH::N - 64;
 }
 
+// The hit records of the path of pixel `pix` in slot `slot` (recs null: none).
+__device__ __forceinline__ HitRecs hit_recs(JSO_GMEM uint32_t* recs, int slot, uint32_t npix,
+                                            uint32_t pix, uint32_t epoch) {
+  return HitRecs{recs ? recs + ((size_t)slot * kHitRecs * npix + pix) * kRecWords : nullptr,
+                 npix * (uint32_t)kRecWords, epoch};
+}
+
 // Identity of the paths of one block: tile origin and random stream.
 template <class SH>
 struct BlockPaths {
@@ -254,7 +261,8 @@ __device__ __forceinline__ Ledger2& ledger2(FwdItem&, Ledger2& none) { return no
 // nothing the kernels write aliases it, so its fields stay in registers.
 // kTwo: the slice is a shared-path pair (params_b set): each path also
 // carries the ledger of params_b, stored to slot_b.
-template <class SH, bool kMesh, bool kTwo>
+// kRec: REC_WRITE where the slice's bit of rec_mask asks for hit records.
+template <class SH, bool kMesh, bool kTwo, int kRec = REC_NONE>
 __device__ __forceinline__ void forward_tile(const FwdArgs& A, const DevScene* __restrict__ Sp,
                                              const TileBlock& tb, uint32_t iter,
                                              uint32_t* s_xchg, int* s_cnt, const TravStack& st,
@@ -279,9 +287,12 @@ __device__ __forceinline__ void forward_tile(const FwdArgs& A, const DevScene* _
   Path& P = mine.P;
   Ledger2& L2 = ledger2(mine, none);
   P.alive = false;
+  JSO_GMEM uint32_t* recs = nullptr;
+  if constexpr (kRec != REC_NONE) recs = ((A.rec_mask >> tb.slice) & 1u) ? A.recs : nullptr;
   if (active) {
     const Rng rng = B.rng((int)threadIdx.x);
-    path_begin<kMesh>(S, st, rng, px, py, A.flags, P);
+    const HitRecs hr = hit_recs(recs, sl.slot, A.npix, pix, A.rec_epoch);
+    path_begin<kMesh, kRec>(S, st, rng, px, py, A.flags, P, hr);
     if (kTwo) {
 #pragma unroll
       for (int k = 0; k < 3; ++k) {
@@ -291,8 +302,8 @@ __device__ __forceinline__ void forward_tile(const FwdArgs& A, const DevScene* _
     }
     if (P.alive) {
       ++n_vert;
-      path_vertex2<false, kMesh, kTwo>(S, st, G(sl.params), params_b, rng, A.flags, P, L2, zero,
-                                       zero, vg);
+      path_vertex2<false, kMesh, kTwo, kRec>(S, st, G(sl.params), params_b, rng, A.flags, P, L2,
+                                             zero, zero, vg, hr);
     }
     if (!P.alive) {
       store_radiance(out, pix, P.led);
@@ -315,10 +326,11 @@ __device__ __forceinline__ void forward_tile(const FwdArgs& A, const DevScene* _
   if (W.P.alive) {
     const Rng rng = B.rng(W.src);
     Ledger2& WL = ledger2(W, none);
+    const HitRecs hr = hit_recs(recs, sl.slot, A.npix, B.pixel(W.src), A.rec_epoch);
     while (W.P.alive) {
       ++n_vert;
-      path_vertex2<false, kMesh, kTwo>(S, st, G(sl.params), params_b, rng, A.flags, W.P, WL, zero,
-                                       zero, vg);
+      path_vertex2<false, kMesh, kTwo, kRec>(S, st, G(sl.params), params_b, rng, A.flags, W.P,
+                                             WL, zero, zero, vg, hr);
     }
     store_radiance(out, B.pixel(W.src), W.P.led);
     if (kTwo) store_radiance(out_b, B.pixel(W.src), WL.led);
@@ -388,7 +400,8 @@ k_forward(const FwdArgs* __restrict__ Units, int n_units, int stack, unsigned lo
     if (kShared && G(A.sl[tb.slice].params_b) != nullptr)  // uniform over the block
       forward_tile<SH, kMesh, kShared>(A, G(A.scene), tb, iter, s_xchg, s_cnt, st, work);
     else
-      forward_tile<SH, kMesh, false>(A, G(A.scene), tb, iter, s_xchg, s_cnt, st, work);
+      forward_tile<SH, kMesh, false, kShared ? REC_NONE : REC_WRITE>(A, G(A.scene), tb, iter,
+                                                                     s_xchg, s_cnt, st, work);
   }
   queue_done(queue);
 }
@@ -694,11 +707,12 @@ constexpr int kRepXchgWords = (int)(sizeof(RepSharedItem) / 4);
 static_assert(sizeof(RepItem) <= sizeof(RepSharedItem), "exchange buffer size");
 
 // Start the replay of a path: P.led = the radiance still to come.
-template <bool kMesh>
+template <bool kMesh, int kRec>
 __device__ __forceinline__ void replay_begin(const DevScene& S, const TravStack& st,
                                              const Rng& rng, int px, int py, uint32_t flags,
-                                             const double* __restrict__ C, Path& P) {
-  path_begin<kMesh>(S, st, rng, px, py, flags, P);
+                                             const double* __restrict__ C, Path& P,
+                                             const HitRecs& hr) {
+  path_begin<kMesh, kRec>(S, st, rng, px, py, flags, P, hr);
 #pragma unroll
   for (int k = 0; k < 3; ++k) P.led[k] = C[k] - P.led[k];
 }
@@ -708,7 +722,7 @@ __device__ __forceinline__ void replay_begin(const DevScene& S, const TravStack&
 // (their gradients go to the block table, flushed right after), later ones on
 // the compacted lanes in a wave-uniform loop, so the later-vertex scatter can
 // use the whole wave.  The exchange buffer reuses the table's LDS.
-template <class SH, bool kMesh, bool kDet>
+template <class SH, bool kMesh, bool kDet, int kRec = REC_NONE>
 __device__ __forceinline__ void adjoint_tile(const RepArgs& A, const DevScene* __restrict__ Sp,
                                              const TileBlock& tb, uint32_t iter, uint32_t* s_dyn,
                                              int* s_cnt, const TravStack& st,
@@ -740,11 +754,14 @@ __device__ __forceinline__ void adjoint_tile(const RepArgs& A, const DevScene* _
     if (active) {
 #pragma unroll
       for (int k = 0; k < 3; ++k) mine.adj[k] = G(sl.delta)[3 * (size_t)pix + k] * sl.adj_scale;
-      replay_begin<kMesh>(S, st, rng, px, py, A.flags,
-                          G(A.slots) + ((size_t)sl.slot_a * A.npix + pix) * 3, mine.P);
+      const HitRecs hr = hit_recs(kRec != REC_NONE ? A.recs : nullptr, sl.slot_a, A.npix, pix,
+                                  A.rec_epoch);
+      replay_begin<kMesh, kRec>(S, st, rng, px, py, A.flags,
+                                G(A.slots) + ((size_t)sl.slot_a * A.npix + pix) * 3, mine.P, hr);
       if (mine.P.alive) {
         ++n_vert;
-        path_vertex<true, kMesh>(S, st, G(sl.params), rng, A.flags, mine.P, mine.adj, v);
+        path_vertex<true, kMesh, kRec>(S, st, G(sl.params), rng, A.flags, mine.P, mine.adj, v,
+                                       hr);
       }
     }
     sink.template add<kMesh>(S, v, sl.sign);  // first vertices (j = 1) go to the table
@@ -765,12 +782,14 @@ __device__ __forceinline__ void adjoint_tile(const RepArgs& A, const DevScene* _
   // no barrier below: waves without a path leave
   if (__ballot(W.P.alive) != 0) {
     const Rng wr = B.rng(W.src);
+    const HitRecs whr = hit_recs(kRec != REC_NONE ? A.recs : nullptr, sl.slot_a, A.npix,
+                                 B.pixel(W.src), A.rec_epoch);
     while (__ballot(W.P.alive) != 0) {
       VertexGrad v;
       v.valid = false;
       if (W.P.alive) {
         ++n_vert;
-        path_vertex<true, kMesh>(S, st, G(sl.params), wr, A.flags, W.P, W.adj, v);
+        path_vertex<true, kMesh, kRec>(S, st, G(sl.params), wr, A.flags, W.P, W.adj, v, whr);
       }
       const bool later = sink.template add<kMesh>(S, v, sl.sign);
       scatter_wave<kMesh, kDet>(S, sink.T, v, sl.sign, later);
@@ -825,7 +844,7 @@ __device__ __forceinline__ void pair_difference(VertexGrad& v, int half) {
 // kernel keeps the register budget of single paths.  The first vertices go to
 // the block table; then the live pairs are compacted, each onto two
 // neighbouring lanes.
-template <class SH, bool kMesh, bool kDet>
+template <class SH, bool kMesh, bool kDet, int kRec = REC_NONE>
 __device__ __forceinline__ void adjoint_tile_pairs(const RepArgs& A,
                                                    const DevScene* __restrict__ Sp,
                                                    const TileBlock& tb, uint32_t iter,
@@ -867,12 +886,14 @@ __device__ __forceinline__ void adjoint_tile_pairs(const RepArgs& A,
 #pragma unroll
       for (int k = 0; k < 3; ++k) mine.adj[k] = delta[3 * (size_t)pix + k] * sl.adj_scale;
       const Rng rng = make_rng(key, pix, sl.sample);
-      replay_begin<kMesh>(S, st, rng, px, py, A.flags,
-                          G(A.slots) + ((size_t)(half ? sl.slot_b : sl.slot_a) * A.npix + pix) * 3,
-                          mine.P);
+      const int slot = half ? sl.slot_b : sl.slot_a;
+      const HitRecs hr = hit_recs(kRec != REC_NONE ? A.recs : nullptr, slot, A.npix, pix,
+                                  A.rec_epoch);
+      replay_begin<kMesh, kRec>(S, st, rng, px, py, A.flags,
+                                G(A.slots) + ((size_t)slot * A.npix + pix) * 3, mine.P, hr);
       if (mine.P.alive) {
         ++n_vert;
-        path_vertex<true, kMesh>(S, st, params, rng, A.flags, mine.P, mine.adj, v);
+        path_vertex<true, kMesh, kRec>(S, st, params, rng, A.flags, mine.P, mine.adj, v, hr);
       }
     }
     pair_difference<kMesh>(v, half);
@@ -898,13 +919,16 @@ __device__ __forceinline__ void adjoint_tile_pairs(const RepArgs& A,
   if (__ballot(W.P.alive) != 0) {
     int wx, wy;
     pixel_of(W.src, wx, wy);
-    const Rng wr = make_rng(key, (uint32_t)(wy * S.width + wx), sl.sample);
+    const uint32_t wpix = (uint32_t)(wy * S.width + wx);
+    const Rng wr = make_rng(key, wpix, sl.sample);
+    const HitRecs whr = hit_recs(kRec != REC_NONE ? A.recs : nullptr,
+                                 half ? sl.slot_b : sl.slot_a, A.npix, wpix, A.rec_epoch);
     while (__ballot(W.P.alive) != 0) {
       VertexGrad v;
       v.valid = false;
       if (W.P.alive) {
         ++n_vert;
-        path_vertex<true, kMesh>(S, st, params, wr, A.flags, W.P, W.adj, v);
+        path_vertex<true, kMesh, kRec>(S, st, params, wr, A.flags, W.P, W.adj, v, whr);
       }
       pair_difference<kMesh>(v, half);
       const bool later = sink.template add<kMesh>(S, v, 1.0f);
@@ -1023,6 +1047,9 @@ __attribute__((amdgpu_waves_per_eu(5)))
 k_adjoint(const RepArgs* __restrict__ Units, int n_units, int stack, unsigned long long* work,
           uint32_t* queue, uint32_t total) {
   using SH = Shape<TW, TH>;
+  // hit records: read by the replays of single paths and replay pairs; the
+  // shared-path and deterministic instances trace every ray
+  constexpr int kRec = (kShared || kDet) ? REC_NONE : REC_READ;
   extern __shared__ uint32_t s_dyn[];
   __shared__ int s_cnt[SH::WAVES];
   __shared__ uint32_t s_vb;
@@ -1035,14 +1062,14 @@ k_adjoint(const RepArgs* __restrict__ Units, int n_units, int stack, unsigned lo
     if (A.h.max_iter && iter >= A.h.max_iter) continue;  // finished problem
     if ((!kShared || kDet) && A.pair_lanes) {  // uniform over the block, as below
       const TileBlock tb = tile_block<SH>(A, b, SH::H / 2);
-      adjoint_tile_pairs<SH, kMesh, kDet>(A, G(A.scene), tb, iter, lds, s_cnt, st, work);
+      adjoint_tile_pairs<SH, kMesh, kDet, kRec>(A, G(A.scene), tb, iter, lds, s_cnt, st, work);
       continue;
     }
     const TileBlock tb = tile_block<SH>(A, b);
     if (kShared && G(A.sl[tb.slice].params_b) != nullptr)
       adjoint_tile_shared<SH, kMesh, kDet>(A, G(A.scene), tb, iter, lds, s_cnt, st, work);
     else
-      adjoint_tile<SH, kMesh, kDet>(A, G(A.scene), tb, iter, lds, s_cnt, st, work);
+      adjoint_tile<SH, kMesh, kDet, kRec>(A, G(A.scene), tb, iter, lds, s_cnt, st, work);
   }
   queue_done(queue);
 }
