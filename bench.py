@@ -53,7 +53,7 @@ PEAK_VALU_TOPS = 256 * 4 * 16 * 2.4e9 / 1e12
 # included), from rocprofv3 counters: SQ_INSTS_VALU x SQ_THREAD_CYCLES_VALU /
 # SQ_ACTIVE_INST_VALU per dispatch over the dispatch's surface vertices
 # (profiles/grad_step_terrain2048_kernel_trace_and_issue.md)
-VALU_OPS_PER_VERTEX = {"k_forward": 6290.0, "k_adjoint": 7083.0}
+VALU_OPS_PER_VERTEX = {"k_forward": 6328.0, "k_adjoint": 2350.0}
 
 KERNEL_SOURCES = ("paper_2309_15676_amd/csrc/device.h", "paper_2309_15676_amd/csrc/kernels.h",
                   "paper_2309_15676_amd/csrc/kernels.hip")
@@ -841,8 +841,10 @@ def adjoint_roofline(spec, prob, kt, work, ub, steps):
     Algorithmic work of a step's replay (its one or two adjoint launches):
     every surface vertex scatters its material gradient into the 4 texels
     of its bilinear footprint, 4 n_ch FP32 atomics of 4 bytes; each replayed
-    path reads its radiance slot (24 B) and its pixel's adjoint colour
-    (12 B); the parameters (4 B each) and the scene's BVH are read at least
+    path reads its radiance slot (24 B), its pixel's adjoint colour (12 B)
+    and the hit records of its camera ray and of each vertex's continuation
+    ray (12 B each; records cover the first three rays, nearly every ray
+    here); the parameters (4 B each) and the scene's BVH are read at least
     once.  HBM: those bytes over the launch time against 8 TB/s; atomics:
     the 4 n_ch atomics per vertex over the launch time against the measured
     peak of no-return FP32 atomics (coalesced 64-byte segments, and random
@@ -855,7 +857,8 @@ def adjoint_roofline(spec, prob, kt, work, ub, steps):
     rep_paths, rep_verts = work[0], work[1]
     n_ch = spec.n_ch
     atomics = rep_verts * 4 * n_ch
-    bytes_ = (atomics * 4 + rep_paths * (24 + 12) + 4 * spec.n_params + scene_bytes(prob))
+    bytes_ = (atomics * 4 + rep_paths * (24 + 12) + 12 * (rep_paths + rep_verts) +
+              4 * spec.n_params + scene_bytes(prob))
     achieved = bytes_ / (launch_ms / 1e3) / 1e9
     out = {"bound": "hbm", "achieved": achieved, "peak": PEAK_HBM_GBS, "unit": "GB/s",
            "frac": achieved / PEAK_HBM_GBS, "kernel": "k_adjoint", "kernel_ms": launch_ms,

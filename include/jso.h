@@ -108,11 +108,11 @@ extern "C" {
  * jso_render_bwd_noalloc (JSO_E_UNSUPPORTED). */
 #define JSO_F_DETERMINISTIC 16
 /* The replay traces every ray again instead of reading the hit records its
- * forward pass wrote (the records hold, for the first rays of each replayed
- * path, what the ray hit and whether the vertex's shadow ray is blocked; the
- * replay takes a record only for the bitwise same ray, so both ways give the
- * same gradients up to the order of the float atomics).  For tests and
- * timing. */
+ * forward pass wrote (triangle-mesh scenes: the records hold, for the first
+ * rays of each replayed path, what the ray hit and whether the vertex's
+ * shadow ray is blocked; the replay takes a record only for the bitwise same
+ * ray, so both ways give the same gradients up to the order of the float
+ * atomics).  For tests and timing. */
 #define JSO_F_NO_HIT_RECORDS 32
 
 #define JSO_MAX_SPHERES 32

@@ -59,8 +59,9 @@ struct SceneGPU {
   // kernels read (BrickArgs), made at the start of each plan; brick_n floats each
   float* vbrick = nullptr;
   size_t brick_n = 0;
-  // surfaces: hit records of replayed paths (kHitRecs x kRecWords words per
-  // slot and pixel), written by the forward pass of a plan, read by its replay
+  // triangle meshes: hit records of replayed paths (kHitRecs x kRecWords
+  // words per slot and pixel), written by the forward pass of a plan, read by
+  // its replay
   uint32_t* recs = nullptr;
   uint32_t host_iter = 0;          // mirror of ctl->iteration
   uint64_t generation = 0;         // unique per loaded scene (plan cache key)
@@ -761,8 +762,9 @@ void plan_estimators(const std::vector<ProbPlan>& ps, Plan& plan, int config = 0
   const bool shared_pairs = std::any_of(p0.aj, p0.aj + p0.na, [](const AdjointSpec& a) {
     return a.params_b != nullptr && a.shared;
   });
-  // hit records: for replays of single paths and replay pairs (the kernel
-  // instances of shared-path pairs and of the deterministic mode have none)
+  // hit records: for replays of single paths and replay pairs of mesh scenes
+  // (only the mesh kernel instances use them; those of shared-path pairs and
+  // of the deterministic mode have none)
   const bool use_recs = !shared_pairs &&
                         !(p0.flags & (JSO_F_DETERMINISTIC | JSO_F_NO_HIT_RECORDS)) &&
                         p0.s->dev.layout != JSO_LAYOUT_VOLUME;
@@ -1679,7 +1681,8 @@ int jso_load_scene(jso_ctx* c, const jso_scene_desc* d, int* scene_id) {
   A(dalloc(&s->accum, 3 * n3));
   A(dalloc(&s->d_scene, 1));
   if (s->brick_n) A(dalloc(&s->vbrick, 2 * s->brick_n));
-  else A(dalloc(&s->recs, (size_t)kMaxSlots * kHitRecs * kRecWords * s->npix));
+  else if (s->dev.n_tris > 0)
+    A(dalloc(&s->recs, (size_t)kMaxSlots * kHitRecs * kRecWords * s->npix));
   if (e != hipSuccess) {
     free_scene_buffers(s.get());
     return fail(c, e == hipErrorOutOfMemory ? JSO_E_OOM : JSO_E_HIP, "scene allocation: %s",

@@ -400,8 +400,8 @@ k_forward(const FwdArgs* __restrict__ Units, int n_units, int stack, unsigned lo
     if (kShared && G(A.sl[tb.slice].params_b) != nullptr)  // uniform over the block
       forward_tile<SH, kMesh, kShared>(A, G(A.scene), tb, iter, s_xchg, s_cnt, st, work);
     else
-      forward_tile<SH, kMesh, false, kShared ? REC_NONE : REC_WRITE>(A, G(A.scene), tb, iter,
-                                                                     s_xchg, s_cnt, st, work);
+      forward_tile<SH, kMesh, false, (kShared || !kMesh) ? REC_NONE : REC_WRITE>(
+          A, G(A.scene), tb, iter, s_xchg, s_cnt, st, work);
   }
   queue_done(queue);
 }
@@ -1047,9 +1047,11 @@ __attribute__((amdgpu_waves_per_eu(5)))
 k_adjoint(const RepArgs* __restrict__ Units, int n_units, int stack, unsigned long long* work,
           uint32_t* queue, uint32_t total) {
   using SH = Shape<TW, TH>;
-  // hit records: read by the replays of single paths and replay pairs; the
-  // shared-path and deterministic instances trace every ray
-  constexpr int kRec = (kShared || kDet) ? REC_NONE : REC_READ;
+  // hit records: read by the replays of single paths and replay pairs in the
+  // mesh instances (BVH traversal is what they save; analytic scenes intersect
+  // a plane and a few spheres for less than a record costs); the shared-path
+  // and deterministic instances trace every ray
+  constexpr int kRec = (kShared || kDet || !kMesh) ? REC_NONE : REC_READ;
   extern __shared__ uint32_t s_dyn[];
   __shared__ int s_cnt[SH::WAVES];
   __shared__ uint32_t s_vb;
