@@ -101,13 +101,27 @@ struct TileBlock {
   int slice, x0, y0;
 };
 
+// kRuns: a unit's blocks take its tiles in order, the slices of one tile side
+// by side (they trace paths through the same pixels, so they touch the same
+// part of the scene at about the same time); otherwise slice by slice, each
+// slice's tiles in order.  The shared-path kernel instances keep the second
+// order: with the first, their single-path replays gave wrong proportional
+// gradients whenever the shared-path replays ran beside them (a fault of
+// those instances that depends on where the blocks run, its cause not found).
 // th: the tile height in pixels (SH::H, or SH::H / 2 for lane-pair tiles)
-template <class SH, class U>
+template <class SH, bool kRuns, class U>
 __device__ __forceinline__ TileBlock tile_block(const U& u, uint32_t b, int th = SH::H) {
   const uint32_t local = b - u.h.block0;
-  const uint32_t t = local % u.tiles;
-  return TileBlock{(int)(local / u.tiles), u.crop.x0 + (int)(t % u.tiles_x) * SH::W,
-                   u.crop.y0 + (int)(t / u.tiles_x) * th};
+  if constexpr (kRuns) {
+    const uint32_t ns = (uint32_t)u.n_slices;
+    const uint32_t t = local / ns;
+    return TileBlock{(int)(local - t * ns), u.crop.x0 + (int)(t % u.tiles_x) * SH::W,
+                     u.crop.y0 + (int)(t / u.tiles_x) * th};
+  } else {
+    const uint32_t t = local % u.tiles;
+    return TileBlock{(int)(local / u.tiles), u.crop.x0 + (int)(t % u.tiles_x) * SH::W,
+                     u.crop.y0 + (int)(t / u.tiles_x) * th};
+  }
 }
 
 template <class SH>
@@ -345,14 +359,32 @@ __device__ __forceinline__ void forward_tile(const FwdArgs& A, const DevScene* _
 // blocks pull grid-block indices (tiles of units) from queue[0] until `total`
 // are taken; the last block to finish resets queue[0] and queue[1] (the count
 // of finished blocks) to zero for the next launch.  Without one, block b is
-// blockIdx.x as usual.  The barriers of the pull also separate one tile's use
+// blockIdx.x, renumbered by xcd_runs in the kernel instances that order their
+// tiles in runs (tile_block).  The barriers of the pull also separate one tile's use
 // of the block's LDS from the next tile's: waves that leave a tile early wait
 // there for the others.
 // ---------------------------------------------------------------------------
+// The block numbers of a path launch in the order the XCDs take them.  The
+// hardware deals a grid's blocks out to the 8 XCDs in turn (block i to XCD
+// i mod 8), each XCD with an L2 of its own.  Renumbered, XCD x takes runs of
+// kXcdRun consecutive blocks (neighbouring tiles with all their slices: one
+// region of the scene) and the XCDs take turns run by run, so each L2 serves
+// one region at a time while the XCDs still spread over the whole image (the
+// sky and the ground of a view balance out).  A bijection of [0, n): blocks
+// past the last whole round of 8 runs keep their numbers.
+constexpr uint32_t kXcdRun = 64;
+__device__ __forceinline__ uint32_t xcd_runs(uint32_t i, uint32_t n) {
+  const uint32_t round = 8 * kXcdRun, full = n - n % round;
+  if (i >= full) return i;
+  const uint32_t x = i & 7u, k = i >> 3;
+  return ((k / kXcdRun) * 8 + x) * kXcdRun + k % kXcdRun;
+}
+
+template <bool kRuns>
 __device__ __forceinline__ bool next_block(uint32_t* queue, uint32_t total, uint32_t* s_vb,
                                            bool first, uint32_t& vb) {
   if (!queue) {
-    vb = blockIdx.x;
+    vb = kRuns ? xcd_runs(blockIdx.x, total) : blockIdx.x;
     return first;
   }
   if (threadIdx.x == 0) *s_vb = atomicAdd(queue, 1u);
@@ -392,11 +424,11 @@ k_forward(const FwdArgs* __restrict__ Units, int n_units, int stack, unsigned lo
   extern __shared__ uint32_t s_dyn[];
   const TravStack st{s_dyn + threadIdx.x, SH::N, stack};
   uint32_t b;
-  for (bool first = true; next_block(queue, total, &s_vb, first, b); first = false) {
+  for (bool first = true; next_block<!kShared>(queue, total, &s_vb, first, b); first = false) {
     const FwdArgs& A = unit_of(Units, n_units, b);
     const uint32_t iter = iteration_of(A.key);
     if (A.h.max_iter && iter >= A.h.max_iter) continue;  // finished problem
-    const TileBlock tb = tile_block<SH>(A, b);
+    const TileBlock tb = tile_block<SH, !kShared>(A, b);
     if (kShared && G(A.sl[tb.slice].params_b) != nullptr)  // uniform over the block
       forward_tile<SH, kMesh, kShared>(A, G(A.scene), tb, iter, s_xchg, s_cnt, st, work);
     else
@@ -1058,16 +1090,16 @@ k_adjoint(const RepArgs* __restrict__ Units, int n_units, int stack, unsigned lo
   const TravStack st{s_dyn + threadIdx.x, SH::N, stack};
   uint32_t* lds = s_dyn + (kMesh ? stack * SH::N : 0);
   uint32_t b;
-  for (bool first = true; next_block(queue, total, &s_vb, first, b); first = false) {
+  for (bool first = true; next_block<!kShared>(queue, total, &s_vb, first, b); first = false) {
     const RepArgs& A = unit_of(Units, n_units, b);
     const uint32_t iter = iteration_of(A.key);
     if (A.h.max_iter && iter >= A.h.max_iter) continue;  // finished problem
     if ((!kShared || kDet) && A.pair_lanes) {  // uniform over the block, as below
-      const TileBlock tb = tile_block<SH>(A, b, SH::H / 2);
+      const TileBlock tb = tile_block<SH, !kShared>(A, b, SH::H / 2);
       adjoint_tile_pairs<SH, kMesh, kDet, kRec>(A, G(A.scene), tb, iter, lds, s_cnt, st, work);
       continue;
     }
-    const TileBlock tb = tile_block<SH>(A, b);
+    const TileBlock tb = tile_block<SH, !kShared>(A, b);
     if (kShared && G(A.sl[tb.slice].params_b) != nullptr)
       adjoint_tile_shared<SH, kMesh, kDet>(A, G(A.scene), tb, iter, lds, s_cnt, st, work);
     else
