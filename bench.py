@@ -53,7 +53,7 @@ PEAK_VALU_TOPS = 256 * 4 * 16 * 2.4e9 / 1e12
 # included), from rocprofv3 counters: SQ_INSTS_VALU x SQ_THREAD_CYCLES_VALU /
 # SQ_ACTIVE_INST_VALU per dispatch over the dispatch's surface vertices
 # (profiles/grad_step_terrain2048_kernel_trace_and_issue.md)
-VALU_OPS_PER_VERTEX = {"k_forward": 6327.0, "k_adjoint": 2349.0}
+VALU_OPS_PER_VERTEX = {"k_forward": 6328.0, "k_adjoint": 2352.0}
 
 KERNEL_SOURCES = ("paper_2309_15676_amd/csrc/device.h", "paper_2309_15676_amd/csrc/kernels.h",
                   "paper_2309_15676_amd/csrc/kernels.hip")

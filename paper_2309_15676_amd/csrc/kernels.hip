@@ -374,19 +374,31 @@ __device__ __forceinline__ void forward_tile(const FwdArgs& A, const DevScene* _
 // bijection of [0, n): blocks past the last whole round of 8 runs keep their
 // numbers.  Runs of 8 measured best: against 64 (8 tiles) the 200k-triangle
 // sphere step took 5.2 instead of 7.4 ms, the terrain 23.4 instead of 23.6.
+// A launch whose units hold one slice each (a one-sample replayed adjoint)
+// has no slices to keep together and takes runs of 1: plain turns, tile by
+// tile (runs of 8 tiles there load the XCDs unevenly).
 constexpr uint32_t kXcdRun = 8;
-__device__ __forceinline__ uint32_t xcd_runs(uint32_t i, uint32_t n) {
-  const uint32_t round = 8 * kXcdRun, full = n - n % round;
+__device__ __forceinline__ uint32_t xcd_runs(uint32_t i, uint32_t n, uint32_t run) {
+  const uint32_t round = 8 * run, full = n - n % round;
   if (i >= full) return i;
   const uint32_t x = i & 7u, k = i >> 3;
-  return ((k / kXcdRun) * 8 + x) * kXcdRun + k % kXcdRun;
+  return ((k / run) * 8 + x) * run + k % run;
+}
+
+// The run length of a launch: kXcdRun when its first or last unit holds more
+// than one slice (the units of a launch share their slice layout, except
+// that a replay launch puts its pair units, one slice, before its single
+// units), else 1.
+template <class U>
+__device__ __forceinline__ uint32_t xcd_run_of(const U* __restrict__ u, int n) {
+  return (u[0].n_slices > 1 || u[n - 1].n_slices > 1) ? kXcdRun : 1u;
 }
 
 template <bool kRuns>
 __device__ __forceinline__ bool next_block(uint32_t* queue, uint32_t total, uint32_t* s_vb,
-                                           bool first, uint32_t& vb) {
+                                           bool first, uint32_t& vb, uint32_t run) {
   if (!queue) {
-    vb = kRuns ? xcd_runs(blockIdx.x, total) : blockIdx.x;
+    vb = kRuns ? xcd_runs(blockIdx.x, total, run) : blockIdx.x;
     return first;
   }
   if (threadIdx.x == 0) *s_vb = atomicAdd(queue, 1u);
@@ -426,7 +438,9 @@ k_forward(const FwdArgs* __restrict__ Units, int n_units, int stack, unsigned lo
   extern __shared__ uint32_t s_dyn[];
   const TravStack st{s_dyn + threadIdx.x, SH::N, stack};
   uint32_t b;
-  for (bool first = true; next_block<!kShared>(queue, total, &s_vb, first, b); first = false) {
+  const uint32_t run = kShared || queue ? 1u : xcd_run_of(Units, n_units);
+  for (bool first = true; next_block<!kShared>(queue, total, &s_vb, first, b, run);
+       first = false) {
     const FwdArgs& A = unit_of(Units, n_units, b);
     const uint32_t iter = iteration_of(A.key);
     if (A.h.max_iter && iter >= A.h.max_iter) continue;  // finished problem
@@ -1092,7 +1106,9 @@ k_adjoint(const RepArgs* __restrict__ Units, int n_units, int stack, unsigned lo
   const TravStack st{s_dyn + threadIdx.x, SH::N, stack};
   uint32_t* lds = s_dyn + (kMesh ? stack * SH::N : 0);
   uint32_t b;
-  for (bool first = true; next_block<!kShared>(queue, total, &s_vb, first, b); first = false) {
+  const uint32_t run = kShared || queue ? 1u : xcd_run_of(Units, n_units);
+  for (bool first = true; next_block<!kShared>(queue, total, &s_vb, first, b, run);
+       first = false) {
     const RepArgs& A = unit_of(Units, n_units, b);
     const uint32_t iter = iteration_of(A.key);
     if (A.h.max_iter && iter >= A.h.max_iter) continue;  // finished problem
