@@ -237,6 +237,34 @@ def test_shared_batch_matches_grad_step(ctx):
     assert any(np.any(a.get_params() != c.get_params()) for a, c in zip(rep, sh))
 
 
+@pytest.mark.parametrize("name", ["five_channel", "mesh_texture"])
+def test_shared_plan_proportional_gradient_equals_replay_plans(ctx, name):
+    """The proportional job (its primal samples, its adjoint paths, their
+    streams) is the same in both finite-difference modes, so the shared-path
+    plan's F equals the replay-pair plan's F up to the order of the float
+    atomics, in every call.  Guards the shared-path kernel instances: with
+    another block order their single-path replays once gave a wrong F (a few
+    texels off by up to 0.1) whenever the shared-path replays ran beside
+    them."""
+    from paper_2309_15676_amd import _lib as L
+    from test_gpu_configs import _five_channel
+    _say("shared plan F == replay plan F", name)
+    spec, gt, init = _five_channel() if name == "five_channel" else _mesh_texture()
+    g = np.random.Generator(np.random.PCG64(8))
+    lo, hi = spec.param_bounds()
+    pp = np.clip(gt + g.normal(0, 0.02, gt.shape).astype(np.float32), lo, hi)
+    prob = _problem(ctx, spec)
+    prob.set_target(I.target_image_synthetic(spec, 5))
+    _set_pair(prob, gt, pp, 6)
+    ref = prob.estimate_gradients(33, 6, 2, 1, fd_mode=L.JSO_FD_REPLAY)["F"].cpu().numpy()
+    scale = np.abs(ref).max()
+    assert scale > 0
+    for k in range(6):
+        F = prob.estimate_gradients(33, 6, 2, 1, fd_mode=L.JSO_FD_SHARED)["F"].cpu().numpy()
+        err = np.abs(F.astype(np.float64) - ref).max()
+        assert err <= 1e-5 * scale, "call %d: max |F - F_replay| %.3g of %.3g" % (k, err, scale)
+
+
 def test_fd_mode_is_validated(ctx):
     from paper_2309_15676_amd import _lib as L
     _say("fd_mode validation")
