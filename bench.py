@@ -919,7 +919,7 @@ def main():
                     help="timed calls per mesh workload (0 = skip the mesh workloads)")
     args = ap.parse_args()
     if args.gpus != 1:
-        print("bench.py: this build runs on one GPU; --gpus %d is not supported "
+        print("bench.py: the benchmark runs on one GPU; --gpus %d is not supported "
               "(the multi-GPU sharding is a design note, not built)" % args.gpus, file=sys.stderr)
         sys.exit(2)
 

@@ -40,7 +40,7 @@ extern "C" {
 #define JSO_E_OOM (-2)         /* device allocation failed                    */
 #define JSO_E_HIP (-3)         /* a HIP runtime call failed                   */
 #define JSO_E_STATE (-4)       /* call not valid in the current state         */
-#define JSO_E_UNSUPPORTED (-5) /* feature not supported by this build / device */
+#define JSO_E_UNSUPPORTED (-5) /* feature not supported by the library or the device */
 
 /* memory space of a pointer argument */
 #define JSO_MEM_HOST 0
